@@ -1,0 +1,1072 @@
+/*
+ * CPU ORACLE: test infrastructure only.  Nothing in the simulator library may
+ * include, link or call this file; only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg use it (through oracle/__init__.py).
+ *
+ * A plain, slow FP64 reference of the paper's Algorithm 1 (Section II): the
+ * state vector of 2^n complex amplitudes is cut into slices, every slice is
+ * kept compressed, and for each gate every slice goes through
+ *     Decompress -> Normalize -> GateComputation -> Compress.
+ * The compressor is an SZ-style error-bounded lossy codec (Section I names SZ;
+ * Section II lets the user set the per-amplitude error bound):
+ *     prequantise p = rint(a / step)  (error-bounded quantisation)
+ *     Lorenzo difference d = p_i - p_{i-1} inside chunks of B values
+ *     symbols d + R for |d| < R, else an escape carrying d exactly
+ *     length-limited Huffman code (package-merge, Larmore & Hirschberg 1990)
+ *     canonical codes (as in RFC 1951), MSB-first 32-bit words.
+ * Everything here follows the stream definition directly, one value at a time;
+ * no blocking or fusion.  Compiled with -ffp-contract=off: every FP64
+ * operation is rounded on its own.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ format */
+
+#define ORC_MAGIC 0x31535143u /* "CQS1" little-endian */
+#define ORC_HDR 64
+#define ORC_R 512             /* quantisation radius: symbols 1..1023 hold d + R */
+#define ORC_NSYM 1024         /* alphabet size; symbol 0 is the escape */
+#define ORC_LMAX 12           /* longest Huffman code */
+#define ORC_ESC_LEN_BITS 6    /* escape payload: 6-bit length, then the zigzag value */
+#define ORC_PMAX ((int64_t)1 << 48) /* |p| must stay below this */
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EBOUND = -3, ORC_ECORRUPT = -4 };
+
+enum { ORC_DENSE = 1, ORC_PHASE = 2 };
+
+typedef struct {
+  uint32_t kind;
+  uint32_t n_targets;
+  uint32_t targets[5];
+  uint32_t pad;
+  uint64_t ctrl_mask;
+  uint64_t ctrl_vals;
+  double phase_re, phase_im;
+  const double *matrix; /* row-major 2^k x 2^k, interleaved (re, im) */
+} orc_gate;
+
+/* ------------------------------------------------------- complex arithmetic */
+
+/* c += u * a, in the fixed order used by every gate:
+   pr = ur*ar, pi = ui*ai, qr = ur*ai, qi = ui*ar; cr += (pr - pi); ci += (qr + qi). */
+static void cmac(double ur, double ui, double ar, double ai, double *cr, double *ci) {
+  double pr = ur * ar;
+  double pi = ui * ai;
+  double qr = ur * ai;
+  double qi = ui * ar;
+  *cr = *cr + (pr - pi);
+  *ci = *ci + (qr + qi);
+}
+
+/* ------------------------------------------------------------ gate on a group
+ * A group is a set of M = 2^m slices whose indices differ only in the slice
+ * bits of the gate's targets.  amp_re[u] / amp_im[u] hold slice slices[u],
+ * L = 2^slice_log2 amplitudes each.  The gate is applied to every tuple of
+ * amplitudes it couples inside the group. */
+
+static double *locate(int nmem, const uint64_t *slices, double **planes, int slice_log2, uint64_t gi) {
+  uint64_t j = gi >> slice_log2;
+  uint64_t o = gi & (((uint64_t)1 << slice_log2) - 1);
+  for (int u = 0; u < nmem; u++)
+    if (slices[u] == j) return planes[u] + o;
+  return NULL;
+}
+
+static int apply_gate_group(const orc_gate *g, int slice_log2, int nmem, const uint64_t *slices,
+                            double **re, double **im) {
+  uint64_t L = (uint64_t)1 << slice_log2;
+  if (g->kind == ORC_PHASE) {
+    for (int u = 0; u < nmem; u++) {
+      for (uint64_t o = 0; o < L; o++) {
+        uint64_t gi = (slices[u] << slice_log2) | o;
+        if ((gi & g->ctrl_mask) != g->ctrl_vals) continue;
+        double cr = 0.0, ci = 0.0;
+        cmac(g->phase_re, g->phase_im, re[u][o], im[u][o], &cr, &ci);
+        re[u][o] = cr;
+        im[u][o] = ci;
+      }
+    }
+    return ORC_OK;
+  }
+  if (g->kind != ORC_DENSE || g->n_targets < 1 || g->n_targets > 5) return ORC_EINVAL;
+  int k = (int)g->n_targets;
+  int dim = 1 << k;
+  uint64_t tmask = 0;
+  for (int t = 0; t < k; t++) tmask |= (uint64_t)1 << g->targets[t];
+  double in_r[32], in_i[32], out_r[32], out_i[32];
+  double *pr_[32], *pi_[32];
+  /* every amplitude of the group whose target bits are all zero is a base */
+  for (int u = 0; u < nmem; u++) {
+    for (uint64_t o = 0; o < L; o++) {
+      uint64_t base = (slices[u] << slice_log2) | o;
+      if (base & tmask) continue;
+      if ((base & g->ctrl_mask) != g->ctrl_vals) continue;
+      for (int m = 0; m < dim; m++) {
+        uint64_t gi = base;
+        for (int t = 0; t < k; t++)
+          if ((m >> t) & 1) gi |= (uint64_t)1 << g->targets[t];
+        pr_[m] = locate(nmem, slices, re, slice_log2, gi);
+        pi_[m] = locate(nmem, slices, im, slice_log2, gi);
+        if (!pr_[m]) return ORC_EINVAL;
+        in_r[m] = *pr_[m];
+        in_i[m] = *pi_[m];
+      }
+      for (int r = 0; r < dim; r++) {
+        double cr = 0.0, ci = 0.0;
+        for (int c = 0; c < dim; c++) {
+          const double *u2 = g->matrix + 2 * (r * dim + c);
+          cmac(u2[0], u2[1], in_r[c], in_i[c], &cr, &ci);
+        }
+        out_r[r] = cr;
+        out_i[r] = ci;
+      }
+      for (int m = 0; m < dim; m++) {
+        *pr_[m] = out_r[m];
+        *pi_[m] = out_i[m];
+      }
+    }
+  }
+  return ORC_OK;
+}
+
+/* The gate on one group of slices given as raw planes (no compression). */
+int orc_group_apply(const orc_gate *g, int slice_log2, int nmem, const uint64_t *slices, double **re, double **im) {
+  return apply_gate_group(g, slice_log2, nmem, slices, re, im);
+}
+
+/* Uncompressed state vector: the whole state is one slice of 2^n amplitudes. */
+int orc_sv_apply(int n, double *re, double *im, const orc_gate *g) {
+  uint64_t zero = 0;
+  return apply_gate_group(g, n, 1, &zero, &re, &im);
+}
+
+/* -------------------------------------------------------------- quantiser */
+
+/* Absolute bound eb: step = 2*eb*(1 - 2^-20), r = 1/step. */
+void orc_abs_step(double eb, double *step, double *recip) {
+  double s = (2.0 * eb) * (1.0 - 0x1p-20);
+  *step = s;
+  *recip = 1.0 / s;
+}
+
+/* Relative bound rel over one slice's 2L values (value-range based): the
+ * bound is eb_j = rel * max(max - min, 2^-24 * max|a|) -- the floor keeps
+ * nearly constant slices codable -- and the step is the largest power of two
+ * not above 2*eb_j (1 if eb_j is zero), so that a*r, rint and p*step are all
+ * exact. */
+void orc_rel_step(double rel, const double *v, uint64_t count, double *step, double *recip, double *ebj) {
+  double lo = v[0], hi = v[0];
+  for (uint64_t i = 1; i < count; i++) {
+    if (v[i] < lo) lo = v[i];
+    if (v[i] > hi) hi = v[i];
+  }
+  double range = hi - lo;
+  double m = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
+  double fl = m * 0x1p-24;
+  double e = rel * (range > fl ? range : fl);
+  *ebj = e;
+  if (!(e > 0.0)) {
+    *step = 1.0;
+    *recip = 1.0;
+    return;
+  }
+  int ex;
+  frexp(2.0 * e, &ex); /* 2e = f * 2^ex, f in [0.5, 1) */
+  *step = ldexp(1.0, ex - 1);
+  *recip = ldexp(1.0, 1 - ex);
+}
+
+/* ----------------------------------------------------------- package-merge */
+
+typedef struct {
+  uint64_t w;
+  int leaf; /* >= 0: leaf rank; -1: package of items a and b of the next deeper level */
+  int a, b;
+} pm_item;
+
+static void pm_count(pm_item **lev, int l, int lmax, int idx, int *len) {
+  pm_item *it = &lev[l][idx];
+  if (it->leaf >= 0) {
+    len[it->leaf]++;
+    return;
+  }
+  pm_count(lev, l + 1, lmax, it->a, len);
+  pm_count(lev, l + 1, lmax, it->b, len);
+}
+
+/* Optimal code lengths bounded by lmax for n weights sorted ascending.
+ * Coin-collector form: level lmax holds the leaves; each shallower level is
+ * the merge of the leaves with the pairwise packages of the level below (a
+ * leaf goes first when weights tie); the 2n-2 cheapest items of level 1 are
+ * selected and a leaf's code length is the number of times it occurs in them.
+ * One leaf gets length 0 (no bits are needed to name the only symbol). */
+static int package_merge(const uint64_t *w, int n, int lmax, int *len) {
+  for (int i = 0; i < n; i++) len[i] = 0;
+  if (n <= 1) return ORC_OK;
+  if (lmax < 1 || lmax > 30 || (uint64_t)n > ((uint64_t)1 << lmax)) return ORC_EINVAL;
+  pm_item *lev[33];
+  int cnt[33];
+  for (int l = 0; l <= lmax; l++) lev[l] = NULL;
+  int rc = ORC_OK;
+  lev[lmax] = (pm_item *)malloc(sizeof(pm_item) * (size_t)n);
+  if (!lev[lmax]) return ORC_ENOMEM;
+  for (int i = 0; i < n; i++) {
+    lev[lmax][i].w = w[i];
+    lev[lmax][i].leaf = i;
+    lev[lmax][i].a = lev[lmax][i].b = -1;
+  }
+  cnt[lmax] = n;
+  for (int l = lmax - 1; l >= 1; l--) {
+    int np = cnt[l + 1] / 2;
+    lev[l] = (pm_item *)malloc(sizeof(pm_item) * (size_t)(n + np));
+    if (!lev[l]) {
+      rc = ORC_ENOMEM;
+      goto done;
+    }
+    int i = 0, p = 0, o = 0;
+    while (i < n || p < np) {
+      uint64_t pw = 0;
+      if (p < np) pw = lev[l + 1][2 * p].w + lev[l + 1][2 * p + 1].w;
+      if (i < n && (p >= np || w[i] <= pw)) {
+        lev[l][o].w = w[i];
+        lev[l][o].leaf = i;
+        lev[l][o].a = lev[l][o].b = -1;
+        i++;
+      } else {
+        lev[l][o].w = pw;
+        lev[l][o].leaf = -1;
+        lev[l][o].a = 2 * p;
+        lev[l][o].b = 2 * p + 1;
+        p++;
+      }
+      o++;
+    }
+    cnt[l] = o;
+  }
+  for (int s = 0; s < 2 * n - 2; s++) pm_count(lev, 1, lmax, s, len);
+done:
+  for (int l = 1; l <= lmax; l++) free(lev[l]);
+  return rc;
+}
+
+typedef struct {
+  uint64_t count;
+  int sym;
+} sym_count;
+
+static int cmp_sym_count(const void *x, const void *y) {
+  const sym_count *a = (const sym_count *)x, *b = (const sym_count *)y;
+  if (a->count != b->count) return a->count < b->count ? -1 : 1;
+  return a->sym < b->sym ? -1 : (a->sym > b->sym ? 1 : 0);
+}
+
+/* Code lengths per symbol from a histogram: leaves ordered by (count, symbol). */
+int orc_huffman_lengths(const uint64_t *hist, int nsym, int lmax, uint8_t *lens) {
+  sym_count *sc = (sym_count *)malloc(sizeof(sym_count) * (size_t)nsym);
+  uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nsym);
+  int *len = (int *)malloc(sizeof(int) * (size_t)nsym);
+  if (!sc || !w || !len) {
+    free(sc); free(w); free(len);
+    return ORC_ENOMEM;
+  }
+  int n = 0;
+  for (int s = 0; s < nsym; s++) {
+    lens[s] = 0;
+    if (hist[s]) {
+      sc[n].count = hist[s];
+      sc[n].sym = s;
+      n++;
+    }
+  }
+  qsort(sc, (size_t)n, sizeof(sym_count), cmp_sym_count);
+  for (int i = 0; i < n; i++) w[i] = sc[i].count;
+  int rc = package_merge(w, n, lmax, len);
+  if (rc == ORC_OK)
+    for (int i = 0; i < n; i++) lens[sc[i].sym] = (uint8_t)len[i];
+  free(sc); free(w); free(len);
+  return rc;
+}
+
+/* Canonical codes: for each length, consecutive values in symbol order,
+ * shorter codes first (RFC 1951, section 3.2.2). */
+void orc_canonical_codes(const uint8_t *lens, int nsym, int lmax, uint32_t *codes) {
+  uint32_t bl_count[33] = {0}, next_code[33] = {0};
+  for (int s = 0; s < nsym; s++)
+    if (lens[s]) bl_count[lens[s]]++;
+  uint32_t code = 0;
+  bl_count[0] = 0;
+  for (int b = 1; b <= lmax; b++) {
+    code = (code + bl_count[b - 1]) << 1;
+    next_code[b] = code;
+  }
+  for (int s = 0; s < nsym; s++) {
+    codes[s] = 0;
+    if (lens[s]) codes[s] = next_code[lens[s]]++;
+  }
+}
+
+/* -------------------------------------------------------------- bit writer */
+
+typedef struct {
+  uint32_t *words;
+  uint64_t pos; /* bits written */
+} bitw;
+
+static void put_bits(bitw *bw, uint64_t v, int nbits) {
+  for (int k = nbits - 1; k >= 0; k--) {
+    uint64_t bit = (v >> k) & 1;
+    if (bit) bw->words[bw->pos >> 5] |= 0x80000000u >> (bw->pos & 31);
+    bw->pos++;
+  }
+}
+
+static uint64_t zigzag(int64_t d) { return ((uint64_t)d << 1) ^ (uint64_t)(d >> 63); }
+static int64_t unzigzag(uint64_t z) { return (int64_t)(z >> 1) ^ -(int64_t)(z & 1); }
+static int bitlen(uint64_t z) {
+  int b = 0;
+  while (z) {
+    b++;
+    z >>= 1;
+  }
+  return b;
+}
+
+static uint32_t rd32(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
+static uint64_t rd64(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
+static double rdf64(const uint8_t *p) { double v; memcpy(&v, p, 8); return v; }
+static void wr32(uint8_t *p, uint32_t v) { memcpy(p, &v, 4); }
+static void wr64(uint8_t *p, uint64_t v) { memcpy(p, &v, 8); }
+static void wrf64(uint8_t *p, double v) { memcpy(p, &v, 8); }
+
+/* ------------------------------------------------------------- compressor */
+
+typedef struct {
+  double max_err;        /* max |a - p*step| over the slice */
+  uint64_t n_escapes;
+  uint64_t sumsq_lo, sumsq_hi;
+  double step;
+} orc_cstats;
+
+/* Compress one slice (Re plane then Im plane, L values each).
+ * mode bit 0: 0 = absolute bound eb, 1 = relative bound eb.
+ * On success *out is a malloc'ed record of *out_len bytes. */
+int orc_compress_slice(const double *re, const double *im, int slice_log2, int chunk_log2, double eb,
+                       uint32_t mode, uint8_t **out, uint64_t *out_len, orc_cstats *st) {
+  if (slice_log2 < 0 || slice_log2 > 26 || chunk_log2 < 0) return ORC_EINVAL;
+  if (chunk_log2 > slice_log2) chunk_log2 = slice_log2;
+  uint64_t L = (uint64_t)1 << slice_log2;
+  uint64_t nv = 2 * L;
+  uint64_t B = (uint64_t)1 << chunk_log2;
+  uint64_t nchunks = nv / B;
+  double *v = (double *)malloc(sizeof(double) * nv);
+  int64_t *p = (int64_t *)malloc(sizeof(int64_t) * nv);
+  int64_t *d = (int64_t *)malloc(sizeof(int64_t) * nv);
+  uint32_t *sym = (uint32_t *)malloc(sizeof(uint32_t) * nv);
+  if (!v || !p || !d || !sym) {
+    free(v); free(p); free(d); free(sym);
+    return ORC_ENOMEM;
+  }
+  memcpy(v, re, sizeof(double) * L);
+  memcpy(v + L, im, sizeof(double) * L);
+
+  double step, r, ebj;
+  if (mode & 1) {
+    orc_rel_step(eb, v, nv, &step, &r, &ebj);
+  } else {
+    orc_abs_step(eb, &step, &r);
+    ebj = eb;
+  }
+  int rc = ORC_OK;
+  double max_err = 0.0;
+  unsigned __int128 sumsq = 0;
+  /* error-bounded quantisation */
+  for (uint64_t i = 0; i < nv; i++) {
+    double t = v[i] * r;
+    double q = rint(t);
+    if (!(fabs(q) < (double)ORC_PMAX)) {
+      rc = ORC_EBOUND;
+      break;
+    }
+    p[i] = (int64_t)q;
+    double back = (double)p[i] * step;
+    double err = fabs(v[i] - back);
+    if (err > ebj) {
+      rc = ORC_EBOUND;
+      break;
+    }
+    if (err > max_err) max_err = err;
+    unsigned __int128 sq = (unsigned __int128)((__int128)p[i] * (__int128)p[i]);
+    sumsq += sq;
+  }
+  if (rc != ORC_OK) {
+    free(v); free(p); free(d); free(sym);
+    return rc;
+  }
+  /* Lorenzo difference inside each chunk, predictor 0 at the chunk head */
+  uint64_t hist[ORC_NSYM];
+  memset(hist, 0, sizeof(hist));
+  uint64_t nesc = 0;
+  for (uint64_t c = 0; c < nchunks; c++) {
+    int64_t prev = 0;
+    for (uint64_t j = 0; j < B; j++) {
+      uint64_t i = c * B + j;
+      d[i] = p[i] - prev;
+      prev = p[i];
+      if (d[i] > -ORC_R && d[i] < ORC_R) {
+        sym[i] = (uint32_t)(d[i] + ORC_R);
+      } else {
+        sym[i] = 0;
+        nesc++;
+      }
+      hist[sym[i]]++;
+    }
+  }
+  uint8_t lens[ORC_NSYM];
+  uint32_t codes[ORC_NSYM];
+  rc = orc_huffman_lengths(hist, ORC_NSYM, ORC_LMAX, lens);
+  if (rc != ORC_OK) {
+    free(v); free(p); free(d); free(sym);
+    return rc;
+  }
+  orc_canonical_codes(lens, ORC_NSYM, ORC_LMAX, codes);
+  uint32_t n_used = 0;
+  for (int s = 0; s < ORC_NSYM; s++)
+    if (hist[s]) n_used++;
+  /* bits per chunk, then the stream */
+  uint64_t *cbits = (uint64_t *)calloc(nchunks, sizeof(uint64_t));
+  uint64_t *coff = (uint64_t *)calloc(nchunks + 1, sizeof(uint64_t));
+  if (!cbits || !coff) {
+    free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+    return ORC_ENOMEM;
+  }
+  for (uint64_t c = 0; c < nchunks; c++) {
+    uint64_t bits = 0;
+    for (uint64_t j = 0; j < B; j++) {
+      uint64_t i = c * B + j;
+      bits += lens[sym[i]];
+      if (sym[i] == 0) bits += ORC_ESC_LEN_BITS + (uint64_t)bitlen(zigzag(d[i]));
+    }
+    cbits[c] = bits;
+    coff[c + 1] = coff[c] + (bits + 31) / 32;
+  }
+  uint64_t n_words = coff[nchunks];
+  uint64_t symtab_bytes = ((2 * (uint64_t)n_used) + 3) & ~(uint64_t)3;
+  uint64_t total = ORC_HDR + symtab_bytes + 4 * (nchunks + 1) + 4 * n_words;
+  if (total > 0xFFFFFFFFull) {
+    free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+    return ORC_EINVAL;
+  }
+  uint8_t *rec = (uint8_t *)calloc(total, 1);
+  if (!rec) {
+    free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+    return ORC_ENOMEM;
+  }
+  wr32(rec + 0, ORC_MAGIC);
+  wr32(rec + 4, (uint32_t)slice_log2);
+  wr32(rec + 8, (uint32_t)chunk_log2);
+  wr32(rec + 12, n_used);
+  wr32(rec + 16, (uint32_t)nchunks);
+  wr32(rec + 20, (uint32_t)n_words);
+  wr32(rec + 24, (uint32_t)nesc);
+  wr32(rec + 28, (uint32_t)total);
+  wrf64(rec + 32, step);
+  wr64(rec + 40, (uint64_t)sumsq);
+  wr64(rec + 48, (uint64_t)(sumsq >> 64));
+  wr32(rec + 56, 0);
+  wr32(rec + 60, 0);
+  uint8_t *tab = rec + ORC_HDR;
+  uint32_t k = 0;
+  for (int s = 0; s < ORC_NSYM; s++) {
+    if (!hist[s]) continue;
+    uint16_t e = (uint16_t)((unsigned)s | ((unsigned)lens[s] << 10));
+    memcpy(tab + 2 * k, &e, 2);
+    k++;
+  }
+  uint8_t *offs = tab + symtab_bytes;
+  for (uint64_t c = 0; c <= nchunks; c++) wr32(offs + 4 * c, (uint32_t)coff[c]);
+  uint32_t *words = (uint32_t *)calloc(n_words ? n_words : 1, sizeof(uint32_t));
+  if (!words) {
+    free(rec); free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+    return ORC_ENOMEM;
+  }
+  for (uint64_t c = 0; c < nchunks; c++) {
+    bitw bw;
+    bw.words = words + coff[c];
+    bw.pos = 0;
+    for (uint64_t j = 0; j < B; j++) {
+      uint64_t i = c * B + j;
+      put_bits(&bw, codes[sym[i]], lens[sym[i]]);
+      if (sym[i] == 0) {
+        uint64_t z = zigzag(d[i]);
+        int nb = bitlen(z);
+        put_bits(&bw, (uint64_t)nb, ORC_ESC_LEN_BITS);
+        put_bits(&bw, z, nb);
+      }
+    }
+  }
+  memcpy(offs + 4 * (nchunks + 1), words, 4 * n_words);
+  free(words);
+  if (st) {
+    st->max_err = max_err;
+    st->n_escapes = nesc;
+    st->sumsq_lo = (uint64_t)sumsq;
+    st->sumsq_hi = (uint64_t)(sumsq >> 64);
+    st->step = step;
+  }
+  *out = rec;
+  *out_len = total;
+  free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+  return ORC_OK;
+}
+
+/* ----------------------------------------------------------- decompressor */
+
+typedef struct {
+  uint32_t slice_log2, chunk_log2, n_used, n_chunks, n_words, n_escapes, total;
+  double step;
+  uint64_t sumsq_lo, sumsq_hi;
+  const uint8_t *symtab;
+  const uint8_t *offs;
+  const uint8_t *words;
+} orc_rec;
+
+int orc_parse(const uint8_t *rec, uint64_t len, orc_rec *h) {
+  if (len < ORC_HDR || rd32(rec) != ORC_MAGIC) return ORC_ECORRUPT;
+  h->slice_log2 = rd32(rec + 4);
+  h->chunk_log2 = rd32(rec + 8);
+  h->n_used = rd32(rec + 12);
+  h->n_chunks = rd32(rec + 16);
+  h->n_words = rd32(rec + 20);
+  h->n_escapes = rd32(rec + 24);
+  h->total = rd32(rec + 28);
+  h->step = rdf64(rec + 32);
+  h->sumsq_lo = rd64(rec + 40);
+  h->sumsq_hi = rd64(rec + 48);
+  if (h->slice_log2 > 26 || h->chunk_log2 > h->slice_log2) return ORC_ECORRUPT;
+  if (h->n_chunks != (uint32_t)((2ull << h->slice_log2) >> h->chunk_log2)) return ORC_ECORRUPT;
+  if (h->n_used < 1 || h->n_used > ORC_NSYM) return ORC_ECORRUPT;
+  uint64_t symtab_bytes = ((2 * (uint64_t)h->n_used) + 3) & ~(uint64_t)3;
+  uint64_t total = ORC_HDR + symtab_bytes + 4 * ((uint64_t)h->n_chunks + 1) + 4 * (uint64_t)h->n_words;
+  if (total != h->total || total > len) return ORC_ECORRUPT;
+  h->symtab = rec + ORC_HDR;
+  h->offs = h->symtab + symtab_bytes;
+  h->words = h->offs + 4 * ((uint64_t)h->n_chunks + 1);
+  return ORC_OK;
+}
+
+typedef struct {
+  const uint32_t *w; /* chunk words, read as little-endian u32 */
+  uint64_t nw;
+  uint64_t pos;
+} bitr;
+
+static int get_bit(bitr *br, int *bit) {
+  uint64_t wi = br->pos >> 5;
+  if (wi >= br->nw) return ORC_ECORRUPT;
+  uint32_t word;
+  memcpy(&word, (const uint8_t *)br->w + 4 * wi, 4);
+  *bit = (int)((word >> (31 - (br->pos & 31))) & 1);
+  br->pos++;
+  return ORC_OK;
+}
+
+static int get_bits(bitr *br, int n, uint64_t *v) {
+  uint64_t x = 0;
+  for (int k = 0; k < n; k++) {
+    int b;
+    if (get_bit(br, &b)) return ORC_ECORRUPT;
+    x = (x << 1) | (uint64_t)b;
+  }
+  *v = x;
+  return ORC_OK;
+}
+
+/* Decode a record into integer codes p (2L values, Re plane then Im plane).
+ * Canonical decoding one bit at a time: a code of length l with value c is
+ * symbol number c - first[l] among the symbols of length l in symbol order. */
+int orc_decode_p(const uint8_t *rec, uint64_t len, int64_t *p) {
+  orc_rec h;
+  int rc = orc_parse(rec, len, &h);
+  if (rc) return rc;
+  uint32_t lens_count[ORC_LMAX + 1] = {0};
+  uint16_t syms[ORC_NSYM];
+  uint8_t lens[ORC_NSYM];
+  int prev_sym = -1;
+  for (uint32_t k = 0; k < h.n_used; k++) {
+    uint16_t e;
+    memcpy(&e, h.symtab + 2 * k, 2);
+    int s = e & 1023, l = e >> 10;
+    if (s <= prev_sym || l > ORC_LMAX) return ORC_ECORRUPT;
+    if (h.n_used > 1 && l == 0) return ORC_ECORRUPT;
+    if (h.n_used == 1 && l != 0) return ORC_ECORRUPT;
+    prev_sym = s;
+    syms[k] = (uint16_t)s;
+    lens[k] = (uint8_t)l;
+    lens_count[l]++;
+  }
+  if (h.n_used > 1) { /* a complete prefix code: sum of 2^-l equals 1 */
+    uint64_t kraft = 0;
+    for (int l = 1; l <= ORC_LMAX; l++) kraft += (uint64_t)lens_count[l] << (ORC_LMAX - l);
+    if (kraft != ((uint64_t)1 << ORC_LMAX)) return ORC_ECORRUPT;
+  }
+  /* symbols sorted by (length, symbol), and the first code of each length */
+  uint16_t by_len[ORC_NSYM];
+  uint32_t first[ORC_LMAX + 2] = {0}, start[ORC_LMAX + 2] = {0};
+  {
+    uint32_t o = 0;
+    for (int l = 1; l <= ORC_LMAX; l++) {
+      start[l] = o;
+      for (uint32_t k = 0; k < h.n_used; k++)
+        if (lens[k] == l) by_len[o++] = syms[k];
+    }
+    uint32_t code = 0;
+    for (int l = 1; l <= ORC_LMAX; l++) {
+      code = (code + (l > 1 ? lens_count[l - 1] : 0)) << 1;
+      first[l] = code;
+    }
+  }
+  uint64_t B = (uint64_t)1 << h.chunk_log2;
+  for (uint64_t c = 0; c < h.n_chunks; c++) {
+    uint32_t w0 = rd32(h.offs + 4 * c), w1 = rd32(h.offs + 4 * (c + 1));
+    if (w1 < w0 || w1 > h.n_words) return ORC_ECORRUPT;
+    bitr br;
+    br.w = (const uint32_t *)(h.words + 4 * (uint64_t)w0);
+    br.nw = w1 - w0;
+    br.pos = 0;
+    int64_t prev = 0;
+    for (uint64_t j = 0; j < B; j++) {
+      int sym;
+      if (h.n_used == 1) {
+        sym = syms[0];
+      } else {
+        uint32_t code = 0;
+        int l = 0;
+        sym = -1;
+        while (l < ORC_LMAX) {
+          int b;
+          if (get_bit(&br, &b)) return ORC_ECORRUPT;
+          code = (code << 1) | (uint32_t)b;
+          l++;
+          if (code - first[l] < lens_count[l]) {
+            sym = by_len[start[l] + (code - first[l])];
+            break;
+          }
+        }
+        if (sym < 0) return ORC_ECORRUPT;
+      }
+      int64_t dv;
+      if (sym == 0) {
+        uint64_t nb, z;
+        if (get_bits(&br, ORC_ESC_LEN_BITS, &nb)) return ORC_ECORRUPT;
+        if (get_bits(&br, (int)nb, &z)) return ORC_ECORRUPT;
+        dv = unzigzag(z);
+      } else {
+        dv = (int64_t)sym - ORC_R;
+      }
+      prev = prev + dv;
+      p[c * B + j] = prev;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Decompress into planes, a = p * kscale (kscale = step * normalisation). */
+int orc_decompress_slice(const uint8_t *rec, uint64_t len, double kscale, double *re, double *im) {
+  orc_rec h;
+  int rc = orc_parse(rec, len, &h);
+  if (rc) return rc;
+  uint64_t L = (uint64_t)1 << h.slice_log2;
+  int64_t *p = (int64_t *)malloc(sizeof(int64_t) * 2 * L);
+  if (!p) return ORC_ENOMEM;
+  rc = orc_decode_p(rec, len, p);
+  if (rc == ORC_OK) {
+    for (uint64_t i = 0; i < L; i++) {
+      re[i] = (double)p[i] * kscale;
+      im[i] = (double)p[L + i] * kscale;
+    }
+  }
+  free(p);
+  return rc;
+}
+
+/* ----------------------------------------------------------- normalisation */
+
+/* sum of p^2 as FP64: hi * 2^64 + lo, each half converted with one rounding */
+static double sumsq_to_double(uint64_t lo, uint64_t hi) { return (double)hi * 0x1p64 + (double)lo; }
+
+/* N = sum_j step_j^2 * P_j over the stored state, added as a pairwise tree over
+ * slice indices (x_i <- x_2i + x_2i+1 level by level; count a power of two). */
+double orc_norm(int nslices, const double *step, const uint64_t *lo, const uint64_t *hi) {
+  double *x = (double *)malloc(sizeof(double) * (size_t)nslices);
+  for (int j = 0; j < nslices; j++) x[j] = (step[j] * step[j]) * sumsq_to_double(lo[j], hi[j]);
+  int m = nslices;
+  while (m > 1) {
+    for (int i = 0; i < m / 2; i++) x[i] = x[2 * i] + x[2 * i + 1];
+    m /= 2;
+  }
+  double N = x[0];
+  free(x);
+  return N;
+}
+
+/* 1/sqrt(N) by ten Newton steps y <- y * (1.5 - (0.5 N y) y) from y = 1
+ * (converged to the last bit for 0.25 <= N <= 2.5). */
+double orc_rsqrt(double N) {
+  double h = 0.5 * N;
+  double y = 1.0;
+  for (int k = 0; k < 10; k++) {
+    double t = h * y;
+    t = t * y;
+    t = 1.5 - t;
+    y = y * t;
+  }
+  return y;
+}
+
+/* ------------------------------------------------------ compressed simulator */
+
+typedef struct {
+  int n, slice_log2, chunk_log2;
+  double eb;
+  uint32_t mode;
+  uint64_t nslices;
+  uint8_t **rec;
+  uint64_t *rec_len;
+  double *step;
+  uint64_t *sq_lo, *sq_hi;
+  double max_err;
+  uint64_t passes;
+  uint64_t min_total_inv; /* largest total compressed bytes seen after any pass */
+} orc_sim;
+
+static uint64_t total_bytes(const orc_sim *s) {
+  uint64_t t = 0;
+  for (uint64_t j = 0; j < s->nslices; j++) t += s->rec_len[j];
+  return t;
+}
+
+orc_sim *orc_sim_create(int n, int slice_log2, int chunk_log2, double eb, uint32_t mode) {
+  if (n < 1 || n > 40 || slice_log2 < 1 || slice_log2 > n || slice_log2 > 26) return NULL;
+  orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+  if (!s) return NULL;
+  s->n = n;
+  s->slice_log2 = slice_log2;
+  s->chunk_log2 = chunk_log2 > slice_log2 ? slice_log2 : chunk_log2;
+  s->eb = eb;
+  s->mode = mode;
+  s->nslices = (uint64_t)1 << (n - slice_log2);
+  s->rec = (uint8_t **)calloc(s->nslices, sizeof(uint8_t *));
+  s->rec_len = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+  s->step = (double *)calloc(s->nslices, sizeof(double));
+  s->sq_lo = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+  s->sq_hi = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+  return s;
+}
+
+void orc_sim_destroy(orc_sim *s) {
+  if (!s) return;
+  for (uint64_t j = 0; j < s->nslices; j++) free(s->rec[j]);
+  free(s->rec); free(s->rec_len); free(s->step); free(s->sq_lo); free(s->sq_hi);
+  free(s);
+}
+
+static void note_total(orc_sim *s) {
+  uint64_t t = total_bytes(s);
+  if (t > s->min_total_inv) s->min_total_inv = t;
+}
+
+/* Initial state: kind 0 = |0..0>, 1 = basis |x>, 2 = product state with
+ * per-qubit factors f[q] = (f0re, f0im, f1re, f1im): psi_i = prod_q f_q(b_q),
+ * multiplied from (1, 0) with qubit 0 first. */
+int orc_sim_init(orc_sim *s, int kind, uint64_t x, const double *f) {
+  uint64_t L = (uint64_t)1 << s->slice_log2;
+  int rc_all = ORC_OK;
+  uint8_t **nrec = (uint8_t **)calloc(s->nslices, sizeof(uint8_t *));
+  uint64_t *nlen = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+  orc_cstats *st = (orc_cstats *)calloc(s->nslices, sizeof(orc_cstats));
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t j = 0; j < (int64_t)s->nslices; j++) {
+    double *re = (double *)calloc(L, sizeof(double));
+    double *im = (double *)calloc(L, sizeof(double));
+    for (uint64_t o = 0; o < L; o++) {
+      uint64_t gi = ((uint64_t)j << s->slice_log2) | o;
+      if (kind == 0) {
+        re[o] = gi == 0 ? 1.0 : 0.0;
+      } else if (kind == 1) {
+        re[o] = gi == x ? 1.0 : 0.0;
+      } else {
+        double ar = 1.0, ai = 0.0;
+        for (int q = 0; q < s->n; q++) {
+          int b = (int)((gi >> q) & 1);
+          double cr = 0.0, ci = 0.0;
+          cmac(f[4 * q + 2 * b], f[4 * q + 2 * b + 1], ar, ai, &cr, &ci);
+          ar = cr;
+          ai = ci;
+        }
+        re[o] = ar;
+        im[o] = ai;
+      }
+    }
+    int rc = orc_compress_slice(re, im, s->slice_log2, s->chunk_log2, s->eb, s->mode, &nrec[j], &nlen[j], &st[j]);
+    if (rc) {
+#pragma omp critical
+      rc_all = rc;
+    }
+    free(re);
+    free(im);
+  }
+  if (rc_all == ORC_OK) {
+    for (uint64_t j = 0; j < s->nslices; j++) {
+      free(s->rec[j]);
+      s->rec[j] = nrec[j];
+      s->rec_len[j] = nlen[j];
+      s->step[j] = st[j].step;
+      s->sq_lo[j] = st[j].sumsq_lo;
+      s->sq_hi[j] = st[j].sumsq_hi;
+      if (st[j].max_err > s->max_err) s->max_err = st[j].max_err;
+    }
+    note_total(s);
+  } else {
+    for (uint64_t j = 0; j < s->nslices; j++) free(nrec[j]);
+  }
+  free(nrec); free(nlen); free(st);
+  return rc_all;
+}
+
+double orc_sim_scale(const orc_sim *s) {
+  return orc_rsqrt(orc_norm((int)s->nslices, s->step, s->sq_lo, s->sq_hi));
+}
+
+/* Slices whose index bits coincide except at the gate's target slice bits
+ * form one group; return the members of the group led by j0 (ascending in
+ * the local index of those bits). */
+static int group_of(const orc_sim *s, const orc_gate *g, uint64_t j0, uint64_t *mem) {
+  int m = 0;
+  int bits[5];
+  if (g->kind == ORC_DENSE)
+    for (uint32_t t = 0; t < g->n_targets; t++)
+      if ((int)g->targets[t] >= s->slice_log2) bits[m++] = (int)g->targets[t] - s->slice_log2;
+  for (int u = 0; u < (1 << m); u++) {
+    uint64_t j = j0;
+    for (int b = 0; b < m; b++)
+      if ((u >> b) & 1) j |= (uint64_t)1 << bits[b];
+    mem[u] = j;
+  }
+  return 1 << m;
+}
+
+static uint64_t group_mask(const orc_sim *s, const orc_gate *g) {
+  uint64_t mk = 0;
+  if (g->kind == ORC_DENSE)
+    for (uint32_t t = 0; t < g->n_targets; t++)
+      if ((int)g->targets[t] >= s->slice_log2) mk |= (uint64_t)1 << (g->targets[t] - s->slice_log2);
+  return mk;
+}
+
+static int check_gate(const orc_sim *s, const orc_gate *g) {
+  uint64_t top = s->n >= 64 ? ~0ull : (((uint64_t)1 << s->n) - 1);
+  if (g->ctrl_mask & ~top) return ORC_EINVAL;
+  if (g->ctrl_vals & ~g->ctrl_mask) return ORC_EINVAL;
+  if (g->kind == ORC_PHASE) return ORC_OK;
+  if (g->kind != ORC_DENSE || g->n_targets < 1 || g->n_targets > 5 || !g->matrix) return ORC_EINVAL;
+  uint64_t tm = 0;
+  for (uint32_t t = 0; t < g->n_targets; t++) {
+    if ((int)g->targets[t] >= s->n) return ORC_EINVAL;
+    if (tm & ((uint64_t)1 << g->targets[t])) return ORC_EINVAL;
+    tm |= (uint64_t)1 << g->targets[t];
+  }
+  if (tm & g->ctrl_mask) return ORC_EINVAL;
+  return ORC_OK;
+}
+
+/* One pass of Algorithm 1 for one group: decompress each member, normalise
+ * with the global scale, apply the gate, compress each member. */
+static int process_group(const orc_sim *s, const orc_gate *g, double scale, int nmem, const uint64_t *mem,
+                         uint8_t **orec, uint64_t *olen, orc_cstats *ost) {
+  uint64_t L = (uint64_t)1 << s->slice_log2;
+  double *re[32], *im[32];
+  int rc = ORC_OK;
+  for (int u = 0; u < nmem; u++) {
+    re[u] = (double *)malloc(sizeof(double) * L);
+    im[u] = (double *)malloc(sizeof(double) * L);
+  }
+  for (int u = 0; u < nmem && rc == ORC_OK; u++) {
+    uint64_t j = mem[u];
+    double k = s->step[j] * scale;                                          /* Normalize */
+    rc = orc_decompress_slice(s->rec[j], s->rec_len[j], k, re[u], im[u]);   /* Decompress */
+  }
+  if (rc == ORC_OK) rc = apply_gate_group(g, s->slice_log2, nmem, mem, re, im); /* GateComputation */
+  for (int u = 0; u < nmem && rc == ORC_OK; u++)                              /* Compress */
+    rc = orc_compress_slice(re[u], im[u], s->slice_log2, s->chunk_log2, s->eb, s->mode, &orec[u], &olen[u], &ost[u]);
+  for (int u = 0; u < nmem; u++) {
+    free(re[u]);
+    free(im[u]);
+  }
+  return rc;
+}
+
+/* Apply gates one by one (one pass each).  A pass that fails leaves the state
+ * as it was before that pass; *applied counts the completed passes. */
+int orc_sim_apply(orc_sim *s, const orc_gate *gates, uint64_t ngates, uint64_t *applied) {
+  *applied = 0;
+  for (uint64_t gi = 0; gi < ngates; gi++) {
+    const orc_gate *g = &gates[gi];
+    int rc = check_gate(s, g);
+    if (rc) return rc;
+    double scale = orc_sim_scale(s);
+    uint64_t gm = group_mask(s, g);
+    uint8_t **nrec = (uint8_t **)calloc(s->nslices, sizeof(uint8_t *));
+    uint64_t *nlen = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+    orc_cstats *st = (orc_cstats *)calloc(s->nslices, sizeof(orc_cstats));
+    int rc_all = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t j0 = 0; j0 < (int64_t)s->nslices; j0++) {
+      if ((uint64_t)j0 & gm) continue; /* not a group leader */
+      uint64_t mem[32];
+      uint8_t *orec[32];
+      uint64_t olen[32];
+      orc_cstats ost[32];
+      memset(orec, 0, sizeof(orec));
+      int nmem = group_of(s, g, (uint64_t)j0, mem);
+      int rc2 = process_group(s, g, scale, nmem, mem, orec, olen, ost);
+      if (rc2) {
+#pragma omp critical
+        rc_all = rc2;
+        for (int u = 0; u < nmem; u++) free(orec[u]);
+        continue;
+      }
+      for (int u = 0; u < nmem; u++) {
+        nrec[mem[u]] = orec[u];
+        nlen[mem[u]] = olen[u];
+        st[mem[u]] = ost[u];
+      }
+    }
+    if (rc_all) {
+      for (uint64_t j = 0; j < s->nslices; j++) free(nrec[j]);
+      free(nrec); free(nlen); free(st);
+      return rc_all;
+    }
+    for (uint64_t j = 0; j < s->nslices; j++) {
+      free(s->rec[j]);
+      s->rec[j] = nrec[j];
+      s->rec_len[j] = nlen[j];
+      s->step[j] = st[j].step;
+      s->sq_lo[j] = st[j].sumsq_lo;
+      s->sq_hi[j] = st[j].sumsq_hi;
+      if (st[j].max_err > s->max_err) s->max_err = st[j].max_err;
+    }
+    free(nrec); free(nlen); free(st);
+    s->passes++;
+    note_total(s);
+    *applied = gi + 1;
+  }
+  return ORC_OK;
+}
+
+/* Recompute one group's pass from given input records (used to check single
+ * slices of a large state).  in_rec[u] belongs to slice mem[u]; scale is the
+ * normalisation of the whole input state. */
+int orc_pass_group(int n, int slice_log2, int chunk_log2, double eb, uint32_t mode, const orc_gate *g, double scale,
+                   int nmem, const uint64_t *mem, const uint8_t *const *in_rec, const uint64_t *in_len,
+                   uint8_t **out_rec, uint64_t *out_len) {
+  orc_sim s;
+  memset(&s, 0, sizeof(s));
+  s.n = n;
+  s.slice_log2 = slice_log2;
+  s.chunk_log2 = chunk_log2 > slice_log2 ? slice_log2 : chunk_log2;
+  s.eb = eb;
+  s.mode = mode;
+  s.nslices = (uint64_t)1 << (n - slice_log2);
+  int rc = check_gate(&s, g);
+  if (rc) return rc;
+  /* a private view holding only the group's records, indexed by slice */
+  uint8_t *recs[32];
+  uint64_t lens[32];
+  double steps[32];
+  for (int u = 0; u < nmem; u++) {
+    orc_rec h;
+    rc = orc_parse(in_rec[u], in_len[u], &h);
+    if (rc) return rc;
+    recs[u] = (uint8_t *)in_rec[u];
+    lens[u] = in_len[u];
+    steps[u] = h.step;
+  }
+  uint64_t L = (uint64_t)1 << slice_log2;
+  double *re[32], *im[32];
+  for (int u = 0; u < nmem; u++) {
+    re[u] = (double *)malloc(sizeof(double) * L);
+    im[u] = (double *)malloc(sizeof(double) * L);
+  }
+  for (int u = 0; u < nmem && rc == ORC_OK; u++)
+    rc = orc_decompress_slice(recs[u], lens[u], steps[u] * scale, re[u], im[u]);
+  if (rc == ORC_OK) rc = apply_gate_group(g, slice_log2, nmem, mem, re, im);
+  for (int u = 0; u < nmem && rc == ORC_OK; u++) {
+    orc_cstats st;
+    rc = orc_compress_slice(re[u], im[u], slice_log2, s.chunk_log2, eb, mode, &out_rec[u], &out_len[u], &st);
+  }
+  for (int u = 0; u < nmem; u++) {
+    free(re[u]);
+    free(im[u]);
+  }
+  return rc;
+}
+
+uint64_t orc_sim_nslices(const orc_sim *s) { return s->nslices; }
+uint64_t orc_sim_record_len(const orc_sim *s, uint64_t j) { return j < s->nslices ? s->rec_len[j] : 0; }
+int orc_sim_record(const orc_sim *s, uint64_t j, uint8_t *buf, uint64_t cap) {
+  if (j >= s->nslices || cap < s->rec_len[j]) return ORC_EINVAL;
+  memcpy(buf, s->rec[j], s->rec_len[j]);
+  return ORC_OK;
+}
+uint64_t orc_sim_total_bytes(const orc_sim *s) { return total_bytes(s); }
+uint64_t orc_sim_peak_bytes(const orc_sim *s) { return s->min_total_inv; }
+double orc_sim_max_err(const orc_sim *s) { return s->max_err; }
+
+/* Normalised amplitudes [begin, begin + count), interleaved (re, im). */
+int orc_sim_amplitudes(const orc_sim *s, uint64_t begin, uint64_t count, double *out) {
+  uint64_t N = (uint64_t)1 << s->n;
+  if (begin > N || count > N - begin) return ORC_EINVAL;
+  double scale = orc_sim_scale(s);
+  uint64_t L = (uint64_t)1 << s->slice_log2;
+  double *re = (double *)malloc(sizeof(double) * L);
+  double *im = (double *)malloc(sizeof(double) * L);
+  int rc = ORC_OK;
+  uint64_t i = begin;
+  while (i < begin + count && rc == ORC_OK) {
+    uint64_t j = i >> s->slice_log2;
+    rc = orc_decompress_slice(s->rec[j], s->rec_len[j], s->step[j] * scale, re, im);
+    uint64_t end = (j + 1) << s->slice_log2;
+    if (end > begin + count) end = begin + count;
+    for (; i < end && rc == ORC_OK; i++) {
+      uint64_t o = i & (L - 1);
+      out[2 * (i - begin)] = re[o];
+      out[2 * (i - begin) + 1] = im[o];
+    }
+  }
+  free(re);
+  free(im);
+  return rc;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
