@@ -1,0 +1,190 @@
+/*
+ * cqsim -- compressed full-amplitude quantum circuit simulation on one MI355X.
+ *
+ * C ABI of the library libcqsim.so.  It implements the per-gate, per-slice
+ * loop of Algorithm 1 of Wu, Di, Cappello, Finkel, Alexeev and Chong,
+ * "Memory-Efficient Quantum Circuit Simulation by Using Lossy Data
+ * Compression" (Section II): the state vector of 2^n complex amplitudes
+ * (Section I: 2^(n+4) bytes in FP64) is cut into slices; every slice stays
+ * compressed in device memory (HBM) with an error-bounded lossy codec, and
+ * each gate is applied as
+ *     for each slice: Decompress -> Normalize -> GateComputation -> Compress.
+ *
+ * Conventions shared by all entry points
+ *   - Return value: 0 on success, a negative SIM_E* code on failure.  The text
+ *     of the last failure on the calling thread is sim_last_error().
+ *   - Amplitude index i = sum_q b_q 2^q (qubit 0 is the least significant bit).
+ *   - Pointers named "host" are ordinary CPU memory owned by the caller; the
+ *     library never keeps them after the call returns.  All device memory is
+ *     owned by the handle (or obtained through sim_set_allocator).
+ *   - One handle must not be used from two threads at once.  Work is ordered
+ *     on the handle's HIP stream; calls that return data synchronise it.
+ *   - No CPU fallback exists: without a usable gfx950 device sim_create fails
+ *     with SIM_EDEVICE.
+ */
+#ifndef CQSIM_H
+#define CQSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes */
+#define SIM_OK 0
+#define SIM_EINVAL (-1)   /* invalid argument or gate */
+#define SIM_ENOMEM (-2)   /* device memory could not be obtained */
+#define SIM_EBOUND (-3)   /* a value cannot be coded within the error bound */
+#define SIM_ECORRUPT (-4) /* a slice record failed its consistency checks */
+#define SIM_EDEVICE (-5)  /* HIP runtime or device failure */
+
+/* ---- mode bits of sim_create (Section II: the user sets the error bound) */
+#define SIM_EB_ABS 0x0u  /* |a - a'| <= error_bound for every real and imaginary part */
+#define SIM_EB_REL 0x1u  /* per slice: error_bound * max(max - min, 2^-24 max|a|) over its 2L values */
+#define SIM_FP64 0x0u    /* amplitudes and gate arithmetic in FP64 */
+#define SIM_PLAIN 0x0u   /* one pass per gate, exactly as in Algorithm 1 */
+
+/* ---- gate kinds */
+#define SIM_GATE_DENSE 1u /* 2^k x 2^k complex matrix on k = 1..5 targets, optional controls */
+#define SIM_GATE_PHASE 2u /* multiply amplitude i by phase where (i & ctrl_mask) == ctrl_vals */
+
+typedef struct sim_s sim_t;
+
+/* One gate of the program (Section II: the program is processed gate by gate).
+ * DENSE: local index m = sum_k bit(i, targets[k]) << k selects the row and
+ *   column of `matrix` (row-major, 2^k x 2^k complex, interleaved re, im; host
+ *   memory, copied by sim_apply).  The gate acts only where
+ *   (i & ctrl_mask) == ctrl_vals; controls must not overlap targets.
+ * PHASE: n_targets = 0; amplitude i is multiplied by (phase_re + i phase_im)
+ *   where (i & ctrl_mask) == ctrl_vals (Z, CZ, controlled phases, oracles).
+ * Layout is fixed: 72 bytes, naturally aligned. */
+typedef struct sim_gate {
+  uint32_t kind;
+  uint32_t n_targets;
+  uint32_t targets[5];
+  uint32_t reserved;
+  uint64_t ctrl_mask;
+  uint64_t ctrl_vals;
+  double phase_re;
+  double phase_im;
+  const double *matrix;
+} sim_gate;
+
+/* Extended creation parameters; zero fields take the defaults. */
+typedef struct sim_config {
+  int n_qubits;             /* 1..40 */
+  int slice_log2;           /* L = 2^slice_log2 amplitudes per slice, 1..26, <= n_qubits */
+  int chunk_log2;           /* B = 2^chunk_log2 values per coded chunk (0: 10), clipped to slice_log2 */
+  double error_bound;       /* > 0 */
+  uint32_t mode;            /* SIM_EB_* | SIM_FP64 | SIM_PLAIN */
+  uint64_t workspace_bytes; /* budget for decompressed slices in flight (0: up to 16 GiB) */
+  /* optional device-memory hooks used for every allocation of the handle
+   * (e.g. a framework's caching allocator); both NULL: hipMalloc / hipFree */
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free_fn)(void *ptr, void *ctx);
+  void *alloc_ctx;
+  void *stream;             /* hipStream_t to enqueue on (NULL: a stream of the handle) */
+  uint64_t arena_bytes;     /* initial capacity of each of the two record arenas (0: sized
+                               from the slice count); arenas grow by doubling when a pass
+                               overflows, and the pass is run again */
+} sim_config;
+
+/* Statistics (Section III measures compression ratio, fidelity and time). */
+typedef struct sim_stats_t {
+  uint64_t raw_bytes;           /* 16 * 2^n: the uncompressed FP64 state */
+  uint64_t compressed_bytes;    /* sum of the slice records now stored */
+  uint64_t peak_compressed;     /* largest total after any pass (sets the minimum ratio) */
+  double ratio;                 /* raw_bytes / compressed_bytes */
+  double min_ratio;             /* raw_bytes / peak_compressed */
+  uint64_t passes;              /* gates applied since creation */
+  uint64_t escapes;             /* escape symbols coded since creation */
+  double last_norm;             /* squared norm of the stored state before the last pass */
+  double max_abs_codec_err;     /* largest |a - p*step| seen by the quantiser */
+  double elapsed_s;             /* device time spent in sim_apply */
+  uint64_t arena_bytes;         /* device bytes held for compressed records (both buffers) */
+  uint64_t workspace_slots;     /* slices decompressed at once */
+} sim_stats_t;
+
+/* Create a simulator holding |0...0>, compressed (Algorithm 1 starts from a
+ * compressed state).  Arguments as in sim_config; error_bound is absolute or
+ * relative according to `mode`.  *out receives the handle.  Errors: SIM_EINVAL
+ * (range), SIM_ENOMEM, SIM_EDEVICE, SIM_EBOUND (the bound is too fine for the
+ * codes to stay below 2^48 in magnitude). */
+int sim_create(int n_qubits, int slice_log2, double error_bound, uint32_t mode, sim_t **out);
+int sim_create_ex(const sim_config *cfg, sim_t **out);
+
+/* Release all device memory of the handle.  NULL is ignored. */
+void sim_destroy(sim_t *sim);
+
+/* Text of the last failure on this thread (never NULL). */
+const char *sim_last_error(void);
+
+/* Replace the state by the basis state |x> (x < 2^n) and compress it. */
+int sim_init_basis(sim_t *sim, uint64_t x);
+
+/* Replace the state by the product state prod_q f_q(b_q) with
+ * f_q(0) = cos(theta_q / 2), f_q(1) = e^{i phi_q} sin(theta_q / 2); `factors`
+ * is host memory of n_qubits * 4 doubles (f_q(0).re, f_q(0).im, f_q(1).re,
+ * f_q(1).im), computed by the caller.  The product is formed from (1, 0) with
+ * qubit 0 first. */
+int sim_init_product(sim_t *sim, const double *factors);
+
+/* Use caller-provided device memory for allocations made from now on (arena
+ * growth, staging buffers).  alloc(bytes, ctx) returns device memory or NULL;
+ * free(ptr, ctx) releases it.  Memory already held is released through the
+ * functions that allocated it.  To cover the initial allocations as well,
+ * pass the hooks in sim_config. */
+int sim_set_allocator(sim_t *sim, void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *), void *ctx);
+
+/* Enqueue all work of the handle on `hip_stream` (a hipStream_t) from now on. */
+int sim_set_stream(sim_t *sim, void *hip_stream);
+
+/* Apply gates[0..n) in order, one pass of Algorithm 1 per gate (Section II):
+ * for every slice group, decompress, normalise by the norm of the stored
+ * state, apply the gate, recompress.  Gates whose targets are slice-index
+ * qubits couple 2^m slices, which are processed together.  The gate array
+ * and matrices are host memory read during the call.  Passes are
+ * transactional: on failure the state is the one after the last completed
+ * pass, and *n_applied (may be NULL) counts completed passes.  Errors:
+ * SIM_EINVAL (bad gate; nothing after it runs), SIM_EBOUND, SIM_ENOMEM,
+ * SIM_EDEVICE. */
+int sim_apply(sim_t *sim, const sim_gate *gates, size_t n, size_t *n_applied);
+
+/* Normalised amplitudes [begin, begin + count) into host memory `out`
+ * (2 * count doubles, interleaved re, im): the stored state decompressed and
+ * scaled by the same normalisation a pass would use. */
+int sim_amplitudes(sim_t *sim, uint64_t begin, uint64_t count, double *out);
+
+/* |a_i|^2 of the same normalised amplitudes into host memory (count doubles). */
+int sim_probabilities(sim_t *sim, uint64_t begin, uint64_t count, double *out);
+
+/* Fill *out (host memory).  Synchronises the stream. */
+int sim_stats(sim_t *sim, sim_stats_t *out);
+
+/* Size in bytes of the stored record of slice j (0 if j is out of range). */
+uint64_t sim_record_size(sim_t *sim, uint64_t j);
+
+/* Copy the stored record of slice j (its exact bytes) into host memory `buf`
+ * of `cap` bytes; *len receives the size.  The record format is fixed and
+ * self-describing: header, symbol table, chunk word offsets, bit stream. */
+int sim_export_slice(sim_t *sim, uint64_t j, void *buf, uint64_t cap, uint64_t *len);
+
+/* Replace the stored record of slice j by `len` bytes from host memory
+ * (checkpoint restore).  The record is checked for consistency (SIM_ECORRUPT)
+ * and must have the handle's slice and chunk sizes. */
+int sim_import_slice(sim_t *sim, uint64_t j, const void *buf, uint64_t len);
+
+/* Device time (milliseconds, summed since the last reset) spent in each of
+ * the library's kernel classes, measured with HIP events on the handle's
+ * stream when enabled.  `names` receives a static comma-separated list of the
+ * class names in order; out has room for `cap` values; returns the number of
+ * classes.  enable != 0 turns the per-kernel events on and resets the sums. */
+int sim_kernel_times(sim_t *sim, int enable, double *out, int cap, const char **names);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CQSIM_H */

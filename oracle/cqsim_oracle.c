@@ -481,13 +481,16 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
   wr64(rec + 48, (uint64_t)(sumsq >> 64));
   wr32(rec + 56, 0);
   wr32(rec + 60, 0);
+  /* symbol table in canonical order: by code length, then by symbol */
   uint8_t *tab = rec + ORC_HDR;
   uint32_t k = 0;
-  for (int s = 0; s < ORC_NSYM; s++) {
-    if (!hist[s]) continue;
-    uint16_t e = (uint16_t)((unsigned)s | ((unsigned)lens[s] << 10));
-    memcpy(tab + 2 * k, &e, 2);
-    k++;
+  for (int l = 0; l <= ORC_LMAX; l++) {
+    for (int s = 0; s < ORC_NSYM; s++) {
+      if (!hist[s] || lens[s] != l) continue;
+      uint16_t e = (uint16_t)((unsigned)s | ((unsigned)lens[s] << 10));
+      memcpy(tab + 2 * k, &e, 2);
+      k++;
+    }
   }
   uint8_t *offs = tab + symtab_bytes;
   for (uint64_t c = 0; c <= nchunks; c++) wr32(offs + 4 * c, (uint32_t)coff[c]);
@@ -598,15 +601,16 @@ int orc_decode_p(const uint8_t *rec, uint64_t len, int64_t *p) {
   uint32_t lens_count[ORC_LMAX + 1] = {0};
   uint16_t syms[ORC_NSYM];
   uint8_t lens[ORC_NSYM];
-  int prev_sym = -1;
+  int prev_key = -1;
   for (uint32_t k = 0; k < h.n_used; k++) {
     uint16_t e;
     memcpy(&e, h.symtab + 2 * k, 2);
     int s = e & 1023, l = e >> 10;
-    if (s <= prev_sym || l > ORC_LMAX) return ORC_ECORRUPT;
+    int key = (l << 10) | s; /* entries are ordered by (length, symbol) */
+    if (key <= prev_key || l > ORC_LMAX) return ORC_ECORRUPT;
+    prev_key = key;
     if (h.n_used > 1 && l == 0) return ORC_ECORRUPT;
     if (h.n_used == 1 && l != 0) return ORC_ECORRUPT;
-    prev_sym = s;
     syms[k] = (uint16_t)s;
     lens[k] = (uint8_t)l;
     lens_count[l]++;

@@ -1,0 +1,294 @@
+"""cqsim: compressed full-amplitude quantum circuit simulation on one MI355X.
+
+Python binding of ``libcqsim.so`` (the C ABI of ``include/cqsim.h``).  This
+module only marshals arguments: every step of the per-gate, per-slice loop --
+Decompress, Normalize, GateComputation, Compress (Algorithm 1, Section II of
+Wu et al., "Memory-Efficient Quantum Circuit Simulation by Using Lossy Data
+Compression") -- runs in the library's HIP kernels on gfx950.  PyTorch, when
+present, provides the device memory (its caching allocator) and the stream.
+
+There is no CPU fallback: if the library is missing or no gfx950 device is
+usable, the constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcqsim.so")
+
+SIM_EB_ABS = 0x0
+SIM_EB_REL = 0x1
+GATE_DENSE = 1
+GATE_PHASE = 2
+
+ERRORS = {-1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EBOUND", -4: "SIM_ECORRUPT", -5: "SIM_EDEVICE"}
+
+# every entry point declared in include/cqsim.h
+EXPORTS = ("sim_create", "sim_create_ex", "sim_destroy", "sim_last_error", "sim_init_basis", "sim_init_product",
+           "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_amplitudes", "sim_probabilities", "sim_stats",
+           "sim_record_size", "sim_export_slice", "sim_import_slice", "sim_kernel_times")
+
+
+class SimError(RuntimeError):
+    def __init__(self, rc: int, msg: str):
+        super().__init__(f"{ERRORS.get(rc, rc)}: {msg}")
+        self.rc = rc
+
+
+class GateStruct(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("n_targets", C.c_uint32), ("targets", C.c_uint32 * 5),
+                ("reserved", C.c_uint32), ("ctrl_mask", C.c_uint64), ("ctrl_vals", C.c_uint64),
+                ("phase_re", C.c_double), ("phase_im", C.c_double), ("matrix", C.POINTER(C.c_double))]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class ConfigStruct(C.Structure):
+    _fields_ = [("n_qubits", C.c_int), ("slice_log2", C.c_int), ("chunk_log2", C.c_int),
+                ("error_bound", C.c_double), ("mode", C.c_uint32), ("workspace_bytes", C.c_uint64),
+                ("alloc", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_ctx", C.c_void_p), ("stream", C.c_void_p),
+                ("arena_bytes", C.c_uint64)]
+
+
+class StatsStruct(C.Structure):
+    _fields_ = [("raw_bytes", C.c_uint64), ("compressed_bytes", C.c_uint64), ("peak_compressed", C.c_uint64),
+                ("ratio", C.c_double), ("min_ratio", C.c_double), ("passes", C.c_uint64),
+                ("escapes", C.c_uint64), ("last_norm", C.c_double), ("max_abs_codec_err", C.c_double),
+                ("elapsed_s", C.c_double), ("arena_bytes", C.c_uint64), ("workspace_slots", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcqsim.so (built in-tree by build.py); raises if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python {HERE}/build.py`")
+        # A process can drive the GPU through one HIP runtime only.  PyTorch
+        # ships its own libamdhip64.so.7; loading it first makes the library
+        # bind to that same copy (same soname) instead of a second runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.sim_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_uint32, C.POINTER(P)]
+        L.sim_create_ex.argtypes = [C.POINTER(ConfigStruct), C.POINTER(P)]
+        L.sim_destroy.argtypes = [P]
+        L.sim_destroy.restype = None
+        L.sim_last_error.restype = C.c_char_p
+        L.sim_init_basis.argtypes = [P, C.c_uint64]
+        L.sim_init_product.argtypes = [P, P]
+        L.sim_set_allocator.argtypes = [P, ALLOC_FN, FREE_FN, P]
+        L.sim_set_stream.argtypes = [P, P]
+        L.sim_apply.argtypes = [P, C.POINTER(GateStruct), C.c_size_t, C.POINTER(C.c_size_t)]
+        L.sim_amplitudes.argtypes = [P, C.c_uint64, C.c_uint64, P]
+        L.sim_probabilities.argtypes = [P, C.c_uint64, C.c_uint64, P]
+        L.sim_stats.argtypes = [P, C.POINTER(StatsStruct)]
+        L.sim_record_size.argtypes = [P, C.c_uint64]
+        L.sim_record_size.restype = C.c_uint64
+        L.sim_export_slice.argtypes = [P, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64)]
+        L.sim_import_slice.argtypes = [P, C.c_uint64, P, C.c_uint64]
+        L.sim_kernel_times.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_char_p)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SimError(rc, f"{what}: {lib().sim_last_error().decode()}")
+
+
+def gate_struct(g) -> Tuple[GateStruct, Optional[np.ndarray]]:
+    """sim_gate from any object with kind, targets, ctrl_mask, ctrl_vals, matrix, phase."""
+    s = GateStruct()
+    s.kind = int(g.kind)
+    tg = tuple(g.targets) if g.kind == GATE_DENSE else ()
+    s.n_targets = len(tg)
+    for i, t in enumerate(tg):
+        s.targets[i] = int(t)
+    s.ctrl_mask = int(g.ctrl_mask)
+    s.ctrl_vals = int(g.ctrl_vals)
+    ph = complex(getattr(g, "phase", 1.0))
+    s.phase_re, s.phase_im = ph.real, ph.imag
+    keep = None
+    if g.kind == GATE_DENSE:
+        keep = np.ascontiguousarray(np.asarray(g.matrix, dtype=np.complex128)).view(np.float64).copy()
+        s.matrix = keep.ctypes.data_as(C.POINTER(C.c_double))
+    return s, keep
+
+
+def gate_array(gates: Sequence):
+    arr = (GateStruct * max(1, len(gates)))()
+    keep = []
+    for i, g in enumerate(gates):
+        s, k = gate_struct(g)
+        arr[i] = s
+        keep.append(k)
+    return arr, keep
+
+
+class _TorchMemory:
+    """Device memory and stream from PyTorch (its caching allocator)."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            except Exception:
+                return None
+            p = t.data_ptr()
+            self.live[p] = t
+            return p
+
+        def _free(ptr, ctx):
+            self.live.pop(ptr, None)
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+    def stream(self):
+        return self.torch.cuda.current_stream().cuda_stream
+
+
+def _torch_ready() -> bool:
+    try:
+        import torch
+        return bool(torch.cuda.is_available())
+    except Exception:
+        return False
+
+
+class Sim:
+    """A compressed state of n qubits on the GPU (see include/cqsim.h)."""
+
+    def __init__(self, n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False,
+                 chunk_log2: int = 0, workspace_bytes: int = 0, use_torch: Optional[bool] = None,
+                 arena_bytes: int = 0):
+        L = lib()
+        cfg = ConfigStruct()
+        cfg.n_qubits = n_qubits
+        cfg.slice_log2 = slice_log2
+        cfg.chunk_log2 = chunk_log2
+        cfg.error_bound = error_bound
+        cfg.mode = SIM_EB_REL if relative else SIM_EB_ABS
+        cfg.workspace_bytes = workspace_bytes
+        cfg.arena_bytes = arena_bytes
+        self._mem = None
+        if use_torch is None:
+            use_torch = _torch_ready()
+        if use_torch:
+            self._mem = _TorchMemory()
+            cfg.alloc = self._mem.alloc
+            cfg.free_fn = self._mem.free
+            cfg.stream = self._mem.stream()
+        h = C.c_void_p()
+        self._h = None
+        _check(L.sim_create_ex(C.byref(cfg), C.byref(h)), "sim_create")
+        self._h = h
+        self.n, self.slice_log2, self.error_bound, self.relative = n_qubits, slice_log2, error_bound, relative
+        self.chunk_log2 = min(chunk_log2 or 10, slice_log2)
+
+    def close(self):
+        if self._h:
+            lib().sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def nslices(self) -> int:
+        return 1 << (self.n - self.slice_log2)
+
+    def init_basis(self, x: int):
+        _check(lib().sim_init_basis(self._h, x), "sim_init_basis")
+
+    def init_product(self, factors: np.ndarray):
+        f = np.ascontiguousarray(np.asarray(factors, dtype=np.complex128)).view(np.float64).copy()
+        assert f.size == 4 * self.n
+        _check(lib().sim_init_product(self._h, f.ctypes.data_as(C.c_void_p)), "sim_init_product")
+
+    def apply(self, gates: Sequence) -> int:
+        arr, keep = gate_array(gates)
+        n = C.c_size_t()
+        rc = lib().sim_apply(self._h, arr, len(gates), C.byref(n))
+        if rc:
+            raise SimError(rc, f"sim_apply after {n.value} gates: {lib().sim_last_error().decode()}")
+        return n.value
+
+    def apply_partial(self, gates: Sequence) -> Tuple[int, int]:
+        """Like apply, but returns (status, gates applied) instead of raising."""
+        arr, keep = gate_array(gates)
+        n = C.c_size_t()
+        rc = lib().sim_apply(self._h, arr, len(gates), C.byref(n))
+        return rc, n.value
+
+    def amplitudes(self, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = (1 << self.n) - begin
+        out = np.zeros(2 * count)
+        _check(lib().sim_amplitudes(self._h, begin, count, out.ctypes.data_as(C.c_void_p)), "sim_amplitudes")
+        return out[0::2] + 1j * out[1::2]
+
+    def probabilities(self, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = (1 << self.n) - begin
+        out = np.zeros(count)
+        _check(lib().sim_probabilities(self._h, begin, count, out.ctypes.data_as(C.c_void_p)),
+               "sim_probabilities")
+        return out
+
+    def stats(self) -> dict:
+        st = StatsStruct()
+        _check(lib().sim_stats(self._h, C.byref(st)), "sim_stats")
+        return {k: getattr(st, k) for k, _ in StatsStruct._fields_}
+
+    def record(self, j: int) -> bytes:
+        n = int(lib().sim_record_size(self._h, j))
+        buf = np.zeros(max(n, 1), dtype=np.uint8)
+        ln = C.c_uint64()
+        _check(lib().sim_export_slice(self._h, j, buf.ctypes.data_as(C.c_void_p), n, C.byref(ln)),
+               "sim_export_slice")
+        return buf[:ln.value].tobytes()
+
+    def records(self, which: Optional[Iterable[int]] = None) -> List[bytes]:
+        return [self.record(j) for j in (range(self.nslices) if which is None else which)]
+
+    def import_record(self, j: int, rec: bytes):
+        b = np.frombuffer(rec, dtype=np.uint8).copy()
+        _check(lib().sim_import_slice(self._h, j, b.ctypes.data_as(C.c_void_p), len(rec)), "sim_import_slice")
+
+    def kernel_times(self, enable: Optional[bool] = None) -> dict:
+        """Per-kernel-class device milliseconds since the last reset; enable=True/False
+        switches the event timing on/off (and resets the sums)."""
+        out = (C.c_double * 32)()
+        names = C.c_char_p()
+        k = lib().sim_kernel_times(self._h, -1 if enable is None else int(bool(enable)), out, 32,
+                                   C.byref(names))
+        if k < 0:
+            _check(k, "sim_kernel_times")
+        return dict(zip(names.value.decode().split(","), list(out)[:k]))

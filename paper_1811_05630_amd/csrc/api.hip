@@ -1,0 +1,845 @@
+// Host side of libcqsim: the C ABI declared in include/cqsim.h.
+//
+// The handle owns the compressed state: two arenas of slice records (the
+// input and output of a pass, swapped after every pass), per-slice metadata
+// for each arena, and a workspace of W slots into which slices are
+// decompressed.  A pass enqueues, for every batch of whole slice groups that
+// fits the workspace, the kernel chain of kernels.hip; nothing returns to the
+// host between passes.  Failures raise a flag in device memory that turns all
+// later kernels into no-ops; the host reads it once per sim_apply call, rolls
+// back to the input arena of the failed pass and, when the output arena was
+// too small, grows it and runs the remaining passes again.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "cqsim.h"
+#include "cqsim_impl.h"
+
+using namespace cq;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int set_err(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int set_err(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_err(SIM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+enum KClass { K_BEGIN, K_RESET, K_INIT, K_DECODE, K_MINMAX, K_RELSTEP, K_GATEQ, K_CODEBOOK, K_CHUNKBITS,
+              K_LAYOUT, K_HEADER, K_ENCODE, K_END, K_READOUT, K_COUNT };
+const char *kClassNames =
+    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,chunkbits,layout,header,encode,"
+    "end_pass,readout";
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+uint64_t rec_bytes_host(uint32_t n_used, uint32_t nchunks, uint64_t words) {
+  return (uint64_t)kHdr + ((2ull * n_used + 3) & ~3ull) + 4ull * (nchunks + 1) + 4ull * words;
+}
+
+}  // namespace
+
+struct sim_s {
+  Geo geo{};
+  double eb = 0;
+  uint32_t mode = 0;
+  uint64_t nslices = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void *(*al_fn)(size_t, void *) = nullptr;
+  void (*al_free)(void *, void *) = nullptr;
+  void *al_ctx = nullptr;
+  struct Owner {
+    void (*free_fn)(void *, void *);  // NULL: hipFree
+    void *ctx;
+  };
+  std::map<void *, Owner> owned;
+
+  Ctl *ctl = nullptr;
+  Ctl *h_ctl = nullptr;  // pinned host copy
+  uint8_t *arena[2] = {nullptr, nullptr};
+  uint64_t arena_cap[2] = {0, 0};
+  StateMeta meta[2]{};
+  int cur = 0;
+  double *kscale = nullptr;
+  Slots slots{};
+  int W = 0;
+  std::map<uint64_t, uint64_t *> tables;  // group mask -> slot order of all slices
+  double *dmat = nullptr;
+  size_t dmat_cap = 0;  // doubles
+  double *dfactors = nullptr;
+  double *dstage = nullptr;
+  size_t dstage_cap = 0;  // doubles
+  uint32_t pass_counter = 0;
+  uint64_t passes = 0;
+  double elapsed = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  bool kt_on = false;
+  std::vector<hipEvent_t> kt_pool;
+  std::vector<int> kt_cls;
+  size_t kt_used = 0;
+  double kt_ms[K_COUNT] = {0};
+
+  int dalloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (al_fn) {
+      *p = al_fn(bytes, al_ctx);
+      if (!*p) return set_err(SIM_ENOMEM, "allocator hook returned NULL for %zu bytes", bytes);
+      owned[*p] = Owner{al_free, al_ctx};
+      return SIM_OK;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return set_err(SIM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    owned[*p] = Owner{nullptr, nullptr};
+    return SIM_OK;
+  }
+  void dfree(void *p) {
+    if (!p) return;
+    auto it = owned.find(p);
+    if (it == owned.end()) return;
+    if (it->second.free_fn)
+      it->second.free_fn(p, it->second.ctx);
+    else
+      hipFree(p);
+    owned.erase(it);
+  }
+
+  // per-kernel-class event timing (off unless requested)
+  void kt_flush() {
+    if (!kt_used) return;
+    hipStreamSynchronize(stream);
+    for (size_t i = 0; i + 1 < kt_used; i += 2) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, kt_pool[i], kt_pool[i + 1]) == hipSuccess) kt_ms[kt_cls[i / 2]] += ms;
+    }
+    kt_used = 0;
+  }
+  void kt_begin(int cls) {
+    if (!kt_on) return;
+    if (kt_used + 2 > kt_pool.size()) kt_flush();
+    kt_cls[kt_used / 2] = cls;
+    hipEventRecord(kt_pool[kt_used++], stream);
+  }
+  void kt_end() {
+    if (!kt_on) return;
+    hipEventRecord(kt_pool[kt_used++], stream);
+  }
+};
+
+namespace {
+
+int check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(SIM_EDEVICE, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int alloc_meta(sim_t *s, StateMeta &m) {
+  int rc;
+  if ((rc = s->dalloc((void **)&m.rec_off, 8 * s->nslices))) return rc;
+  if ((rc = s->dalloc((void **)&m.rec_len, 4 * s->nslices))) return rc;
+  if ((rc = s->dalloc((void **)&m.step, 8 * s->nslices))) return rc;
+  if ((rc = s->dalloc((void **)&m.sq, 16 * s->nslices))) return rc;
+  return SIM_OK;
+}
+
+int alloc_slots(sim_t *s) {
+  const uint64_t W = (uint64_t)s->W, L2 = 2 * s->geo.L;
+  Slots &sl = s->slots;
+  int rc;
+  if ((rc = s->dalloc((void **)&sl.ws, 8 * W * L2))) return rc;
+  if ((rc = s->dalloc((void **)&sl.sym, 2 * W * L2))) return rc;
+  if ((rc = s->dalloc((void **)&sl.esc, 8 * W * L2))) return rc;
+  if ((rc = s->dalloc((void **)&sl.hist, 4 * W * kNSym))) return rc;
+  if ((rc = s->dalloc((void **)&sl.codes, 4 * W * kNSym))) return rc;
+  if ((rc = s->dalloc((void **)&sl.symtab, 2 * W * kNSym))) return rc;
+  if ((rc = s->dalloc((void **)&sl.nused, 4 * W))) return rc;
+  if ((rc = s->dalloc((void **)&sl.chunk_words, 4 * W * s->geo.nchunks))) return rc;
+  if ((rc = s->dalloc((void **)&sl.words, 4 * W))) return rc;
+  if ((rc = s->dalloc((void **)&sl.sq, 16 * W))) return rc;
+  if ((rc = s->dalloc((void **)&sl.nesc, 4 * W))) return rc;
+  if ((rc = s->dalloc((void **)&sl.minmax, 16 * W))) return rc;
+  if ((rc = s->dalloc((void **)&sl.qstep, 24 * W))) return rc;
+  return SIM_OK;
+}
+
+uint64_t per_slot_bytes(const Geo &g) {
+  return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 4 + 2) + 4ull * g.nchunks + 128;
+}
+
+// Slot order of every slice for gates whose slice-index targets form `gm`:
+// groups (slices equal outside gm) are contiguous, members ordered by the
+// bits of gm in ascending order.
+int slot_table(sim_t *s, uint64_t gm, const uint64_t **out) {
+  auto it = s->tables.find(gm);
+  if (it != s->tables.end()) {
+    *out = it->second;
+    return SIM_OK;
+  }
+  std::vector<int> bits;
+  for (int b = 0; b < 64; b++)
+    if ((gm >> b) & 1) bits.push_back(b);
+  std::vector<uint64_t> h;
+  h.reserve(s->nslices);
+  for (uint64_t j0 = 0; j0 < s->nslices; j0++) {
+    if (j0 & gm) continue;
+    for (uint64_t r = 0; r < (1ull << bits.size()); r++) {
+      uint64_t j = j0;
+      for (size_t b = 0; b < bits.size(); b++)
+        if ((r >> b) & 1) j |= 1ull << bits[b];
+      h.push_back(j);
+    }
+  }
+  uint64_t *d;
+  int rc = s->dalloc((void **)&d, 8 * s->nslices);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(d, h.data(), 8 * s->nslices, hipMemcpyHostToDevice));
+  s->tables[gm] = d;
+  *out = d;
+  return SIM_OK;
+}
+
+int validate_gate(const sim_t *s, const sim_gate &g, size_t idx) {
+  const int n = s->geo.n;
+  const uint64_t top = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  if (g.ctrl_mask & ~top) return set_err(SIM_EINVAL, "gate %zu: control mask beyond %d qubits", idx, n);
+  if (g.ctrl_vals & ~g.ctrl_mask) return set_err(SIM_EINVAL, "gate %zu: control values outside the mask", idx);
+  if (g.kind == SIM_GATE_PHASE) return SIM_OK;
+  if (g.kind != SIM_GATE_DENSE) return set_err(SIM_EINVAL, "gate %zu: unknown kind %u", idx, g.kind);
+  if (g.n_targets < 1 || g.n_targets > 5) return set_err(SIM_EINVAL, "gate %zu: %u targets", idx, g.n_targets);
+  if (!g.matrix) return set_err(SIM_EINVAL, "gate %zu: no matrix", idx);
+  uint64_t tm = 0;
+  int m = 0;
+  for (uint32_t k = 0; k < g.n_targets; k++) {
+    if ((int)g.targets[k] >= n) return set_err(SIM_EINVAL, "gate %zu: target %u beyond %d qubits", idx, g.targets[k], n);
+    if (tm & (1ull << g.targets[k])) return set_err(SIM_EINVAL, "gate %zu: repeated target", idx);
+    tm |= 1ull << g.targets[k];
+    if ((int)g.targets[k] >= s->geo.slice_log2) m++;
+  }
+  if (tm & g.ctrl_mask) return set_err(SIM_EINVAL, "gate %zu: controls overlap targets", idx);
+  if ((1 << m) > s->W) return set_err(SIM_ENOMEM, "gate %zu: group of %d slices exceeds the workspace", idx, 1 << m);
+  return SIM_OK;
+}
+
+GateDesc make_desc(const sim_t *s, const sim_gate &g, const double *dmat, uint64_t *gm_out) {
+  GateDesc d;
+  memset(&d, 0, sizeof(d));
+  d.ctrl_mask = g.ctrl_mask;
+  d.ctrl_vals = g.ctrl_vals;
+  *gm_out = 0;
+  if (g.kind == SIM_GATE_PHASE) {
+    d.kind = 2;
+    d.ph_re = g.phase_re;
+    d.ph_im = g.phase_im;
+    return d;
+  }
+  const int sl2 = s->geo.slice_log2;
+  d.kind = 1;
+  d.k = (int)g.n_targets;
+  uint64_t gm = 0;
+  for (int k = 0; k < d.k; k++)
+    if ((int)g.targets[k] >= sl2) gm |= 1ull << (g.targets[k] - sl2);
+  for (int k = 0; k < d.k; k++) {
+    int t = (int)g.targets[k];
+    if (t < sl2) {
+      d.tloc[k] = t;
+    } else {
+      int rank = __builtin_popcountll(gm & ((1ull << (t - sl2)) - 1));
+      d.tloc[k] = sl2 + rank;
+    }
+    d.tmask_loc |= 1ull << d.tloc[k];
+  }
+  d.m = __builtin_popcountll(gm);
+  for (int c = 0; c < (1 << d.k); c++) {
+    uint64_t off = 0;
+    for (int k = 0; k < d.k; k++)
+      if ((c >> k) & 1) off |= 1ull << d.tloc[k];
+    d.dep[c] = off;
+  }
+  d.mat = dmat;
+  *gm_out = gm;
+  return d;
+}
+
+QuantParams quant_params(const sim_t *s) {
+  QuantParams q;
+  q.rel = (s->mode & SIM_EB_REL) ? 1 : 0;
+  q.eb = s->eb;
+  double step = (2.0 * s->eb) * (1.0 - 0x1p-20);
+  q.step = step;
+  q.recip = 1.0 / step;
+  return q;
+}
+
+// Enqueue one pass.  init_kind >= 0: build that initial state instead of
+// decompressing (no normalisation, identity gate).
+int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint64_t x) {
+  const int c = s->cur;
+  const StateMeta &cur = s->meta[c];
+  const StateMeta &nxt = s->meta[1 - c];
+  const uint32_t pass = s->pass_counter++;
+  hipStream_t st = s->stream;
+  const QuantParams qp = quant_params(s);
+  const uint64_t *table;
+  int rc = slot_table(s, init_kind >= 0 ? 0 : gm, &table);
+  if (rc) return rc;
+  s->kt_begin(K_BEGIN);
+  launch_begin_pass(st, s->ctl, cur, s->nslices, nullptr, s->kscale, init_kind >= 0 ? 0 : 1);
+  s->kt_end();
+  for (uint64_t b0 = 0; b0 < s->nslices; b0 += (uint64_t)s->W) {
+    const int ns = (int)std::min<uint64_t>((uint64_t)s->W, s->nslices - b0);
+    const uint64_t *ss = table + b0;
+    s->kt_begin(K_RESET);
+    launch_reset_slots(st, s->slots, s->geo, ns);
+    s->kt_end();
+    if (init_kind >= 0) {
+      s->kt_begin(K_INIT);
+      launch_init(st, s->slots, s->geo, ss, ns, init_kind, x, s->dfactors, s->ctl);
+      s->kt_end();
+    } else {
+      s->kt_begin(K_DECODE);
+      launch_decode(st, s->slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass);
+      s->kt_end();
+    }
+    if (qp.rel) {
+      s->kt_begin(K_MINMAX);
+      launch_gate_minmax(st, s->slots, s->geo, ss, ns, gd, s->ctl);
+      s->kt_end();
+      s->kt_begin(K_RELSTEP);
+      launch_rel_step(st, s->slots, ns, qp.eb, s->ctl);
+      s->kt_end();
+    }
+    s->kt_begin(K_GATEQ);
+    launch_gate_quant(st, s->slots, s->geo, ss, ns, gd, qp, s->ctl, pass);
+    s->kt_end();
+    s->kt_begin(K_CODEBOOK);
+    launch_codebook(st, s->slots, ns, s->ctl);
+    s->kt_end();
+    s->kt_begin(K_CHUNKBITS);
+    launch_chunkbits(st, s->slots, s->geo, ns, s->ctl);
+    s->kt_end();
+    s->kt_begin(K_LAYOUT);
+    launch_layout(st, s->slots, s->geo, ss, ns, nxt, s->arena_cap[1 - c], s->ctl, pass);
+    s->kt_end();
+    s->kt_begin(K_HEADER);
+    launch_header(st, s->slots, s->geo, ss, ns, qp, s->arena[1 - c], nxt, s->ctl);
+    s->kt_end();
+    s->kt_begin(K_ENCODE);
+    launch_encode(st, s->slots, s->geo, ss, ns, s->arena[1 - c], nxt, s->ctl);
+    s->kt_end();
+  }
+  s->kt_begin(K_END);
+  launch_end_pass(st, s->ctl);
+  s->kt_end();
+  s->cur = 1 - c;
+  return check_launch("pass");
+}
+
+int read_ctl(sim_t *s) {
+  HIP_TRY(hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return SIM_OK;
+}
+
+int clear_flags(sim_t *s) {
+  s->h_ctl->flags = 0;
+  s->h_ctl->fail_pass = 0;
+  HIP_TRY(hipMemcpyAsync(&s->ctl->flags, &s->h_ctl->flags, 8, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return SIM_OK;
+}
+
+int grow_arena(sim_t *s, int which, uint64_t min_cap) {
+  uint64_t cap = std::max<uint64_t>(2 * s->arena_cap[which], min_cap);
+  s->dfree(s->arena[which]);
+  s->arena[which] = nullptr;
+  s->arena_cap[which] = 0;
+  int rc = s->dalloc((void **)&s->arena[which], cap);
+  if (rc) return rc;
+  s->arena_cap[which] = cap;
+  return SIM_OK;
+}
+
+// Run gates (or an init pass when gates == nullptr) with failure handling.
+int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, int init_kind, uint64_t x,
+               size_t *applied_out) {
+  size_t applied = 0;
+  int rc = SIM_OK;
+  size_t total = descs ? n : 1;
+  for (int attempt = 0; applied < total && attempt < 64; attempt++) {
+    const uint32_t start_pass = s->pass_counter;
+    const int cur_start = s->cur;
+    for (size_t i = applied; i < total; i++) {
+      if (descs)
+        rc = enqueue_pass(s, descs[i], gms[i], -1, 0);
+      else
+        rc = enqueue_pass(s, GateDesc{}, 0, init_kind, x);
+      if (rc) return rc;
+    }
+    if ((rc = read_ctl(s))) return rc;
+    const uint32_t flags = s->h_ctl->flags;
+    if (!flags) {
+      applied = total;
+      break;
+    }
+    const uint32_t done = s->h_ctl->fail_pass - start_pass;  // passes that completed
+    s->cur = cur_start ^ (int)(done & 1);
+    s->pass_counter = start_pass + done;
+    applied += done;
+    if ((rc = clear_flags(s))) return rc;
+    if (flags & kFlagOverflow) {
+      if ((rc = grow_arena(s, 1 - s->cur, 0))) return rc;
+      continue;
+    }
+    if (flags & kFlagCorrupt) {
+      rc = set_err(SIM_ECORRUPT, "a stored slice record failed its consistency checks");
+    } else {
+      rc = set_err(SIM_EBOUND, "a value could not be coded within the error bound (|p| >= 2^48 or bound check)");
+    }
+    break;
+  }
+  if (applied_out) *applied_out = applied;
+  return rc;
+}
+
+uint64_t min_record_total(const sim_t *s) {
+  return s->nslices * align_up(rec_bytes_host(1, s->geo.nchunks, 0), kRecAlign);
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char *sim_last_error(void) { return g_last_error.c_str(); }
+
+int sim_create(int n_qubits, int slice_log2, double error_bound, uint32_t mode, sim_t **out) {
+  sim_config c;
+  memset(&c, 0, sizeof(c));
+  c.n_qubits = n_qubits;
+  c.slice_log2 = slice_log2;
+  c.error_bound = error_bound;
+  c.mode = mode;
+  return sim_create_ex(&c, out);
+}
+
+int sim_create_ex(const sim_config *cfg, sim_t **out) {
+  if (!cfg || !out) return set_err(SIM_EINVAL, "null argument");
+  *out = nullptr;
+  const int n = cfg->n_qubits, sl2 = cfg->slice_log2;
+  if (n < 1 || n > 40) return set_err(SIM_EINVAL, "n_qubits %d outside 1..40", n);
+  if (sl2 < 1 || sl2 > n || sl2 > 26) return set_err(SIM_EINVAL, "slice_log2 %d outside 1..min(26, n)", sl2);
+  if (!(cfg->error_bound > 0.0) || !std::isfinite(cfg->error_bound))
+    return set_err(SIM_EINVAL, "error bound must be positive and finite");
+  if (cfg->mode & ~(SIM_EB_REL)) return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
+  int cl2 = cfg->chunk_log2 > 0 ? cfg->chunk_log2 : 10;
+  if (cl2 > sl2) cl2 = sl2;
+  if (cl2 > 12) return set_err(SIM_EINVAL, "chunk_log2 %d above 12", cl2);
+
+  int ndev = 0;
+  hipError_t de = hipGetDeviceCount(&ndev);
+  if (de != hipSuccess || ndev < 1)
+    return set_err(SIM_EDEVICE, "no HIP device (hipGetDeviceCount: %d %s, count %d)", (int)de, hipGetErrorString(de),
+                   ndev);
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return set_err(SIM_EDEVICE, "no device properties");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_err(SIM_EDEVICE, "device %s is not gfx950", prop.gcnArchName);
+
+  sim_t *s = new sim_t();
+  s->geo.n = n;
+  s->geo.slice_log2 = sl2;
+  s->geo.chunk_log2 = cl2;
+  s->geo.L = 1ull << sl2;
+  s->geo.nchunks = (uint32_t)((2ull << sl2) >> cl2);
+  s->eb = cfg->error_bound;
+  s->mode = cfg->mode;
+  s->nslices = 1ull << (n - sl2);
+  if ((cfg->alloc == nullptr) != (cfg->free_fn == nullptr)) {
+    delete s;
+    return set_err(SIM_EINVAL, "allocator needs both functions");
+  }
+  s->al_fn = cfg->alloc;
+  s->al_free = cfg->free_fn;
+  s->al_ctx = cfg->alloc_ctx;
+  if (cfg->stream) {
+    s->stream = (hipStream_t)cfg->stream;
+    s->own_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete s;
+      return set_err(SIM_EDEVICE, "stream creation failed");
+    }
+    s->own_stream = true;
+  }
+  hipEventCreate(&s->ev0);
+  hipEventCreate(&s->ev1);
+  // workspace: a power of two number of slots within the budget; the default
+  // budget always holds one full 32-slice group (a dense gate on five
+  // slice-index qubits); an explicit budget is honoured and gates whose group
+  // does not fit are refused with SIM_ENOMEM
+  const uint64_t budget = cfg->workspace_bytes ? cfg->workspace_bytes : (16ull << 30);
+  uint64_t W = 1;
+  while (W * 2 <= s->nslices && W * 2 * per_slot_bytes(s->geo) <= budget) W *= 2;
+  if (!cfg->workspace_bytes) W = std::max<uint64_t>(W, std::min<uint64_t>(s->nslices, 32));
+  s->W = (int)W;
+  int rc;
+  if ((rc = s->dalloc((void **)&s->ctl, sizeof(Ctl))) || (rc = alloc_meta(s, s->meta[0])) ||
+      (rc = alloc_meta(s, s->meta[1])) || (rc = s->dalloc((void **)&s->kscale, 8 * s->nslices)) ||
+      (rc = alloc_slots(s)) || (rc = s->dalloc((void **)&s->dfactors, 32 * (size_t)n))) {
+    sim_destroy(s);
+    return rc;
+  }
+  if (hipHostMalloc((void **)&s->h_ctl, sizeof(Ctl), 0) != hipSuccess) {
+    sim_destroy(s);
+    return set_err(SIM_ENOMEM, "pinned host allocation failed");
+  }
+  memset(s->h_ctl, 0, sizeof(Ctl));
+  if (hipMemcpy(s->ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice) != hipSuccess) {
+    sim_destroy(s);
+    return set_err(SIM_EDEVICE, "control block upload failed");
+  }
+  const uint64_t cap =
+      cfg->arena_bytes ? std::max<uint64_t>(cfg->arena_bytes, 4096) : std::max<uint64_t>(4 * min_record_total(s), 16ull << 20);
+  for (int a = 0; a < 2; a++) {
+    if ((rc = s->dalloc((void **)&s->arena[a], cap))) {
+      sim_destroy(s);
+      return rc;
+    }
+    s->arena_cap[a] = cap;
+  }
+  rc = run_passes(s, nullptr, nullptr, 0, 0, 0, nullptr);
+  if (rc) {
+    sim_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return SIM_OK;
+}
+
+void sim_destroy(sim_t *s) {
+  if (!s) return;
+  if (s->stream) hipStreamSynchronize(s->stream);
+  std::vector<void *> ptrs;
+  for (auto &kv : s->owned) ptrs.push_back(kv.first);
+  for (void *p : ptrs) s->dfree(p);
+  if (s->h_ctl) hipHostFree(s->h_ctl);
+  for (hipEvent_t e : s->kt_pool) hipEventDestroy(e);
+  if (s->ev0) hipEventDestroy(s->ev0);
+  if (s->ev1) hipEventDestroy(s->ev1);
+  if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+  delete s;
+}
+
+int sim_set_allocator(sim_t *s, void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *), void *ctx) {
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  if ((alloc == nullptr) != (free_fn == nullptr)) return set_err(SIM_EINVAL, "allocator needs both functions");
+  s->al_fn = alloc;
+  s->al_free = free_fn;
+  s->al_ctx = ctx;
+  return SIM_OK;
+}
+
+int sim_set_stream(sim_t *s, void *hip_stream) {
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (s->own_stream) hipStreamDestroy(s->stream);
+  s->own_stream = false;
+  s->stream = (hipStream_t)hip_stream;
+  return SIM_OK;
+}
+
+int sim_init_basis(sim_t *s, uint64_t x) {
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  if (s->geo.n < 64 && x >= (1ull << s->geo.n)) return set_err(SIM_EINVAL, "basis index out of range");
+  return run_passes(s, nullptr, nullptr, 0, 1, x, nullptr);
+}
+
+int sim_init_product(sim_t *s, const double *factors) {
+  if (!s || !factors) return set_err(SIM_EINVAL, "null argument");
+  HIP_TRY(hipMemcpy(s->dfactors, factors, 32 * (size_t)s->geo.n, hipMemcpyHostToDevice));
+  return run_passes(s, nullptr, nullptr, 0, 2, 0, nullptr);
+}
+
+int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
+  if (n_applied) *n_applied = 0;
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
+  size_t n_valid = 0;
+  int vrc = SIM_OK;
+  size_t ndoubles = 0;
+  for (; n_valid < n; n_valid++) {
+    vrc = validate_gate(s, gates[n_valid], n_valid);
+    if (vrc) break;
+    if (gates[n_valid].kind == SIM_GATE_DENSE) ndoubles += 2ull << (2 * gates[n_valid].n_targets);
+  }
+  std::string verr = vrc ? g_last_error : std::string();
+  if (ndoubles > s->dmat_cap) {
+    s->dfree(s->dmat);
+    s->dmat = nullptr;
+    s->dmat_cap = 0;
+    int rc = s->dalloc((void **)&s->dmat, 8 * ndoubles);
+    if (rc) return rc;
+    s->dmat_cap = ndoubles;
+  }
+  std::vector<double> hm(ndoubles);
+  std::vector<GateDesc> descs(n_valid);
+  std::vector<uint64_t> gms(n_valid);
+  size_t off = 0;
+  for (size_t i = 0; i < n_valid; i++) {
+    const sim_gate &g = gates[i];
+    const double *dm = nullptr;
+    if (g.kind == SIM_GATE_DENSE) {
+      size_t cnt = 2ull << (2 * g.n_targets);
+      memcpy(hm.data() + off, g.matrix, 8 * cnt);
+      dm = s->dmat + off;
+      off += cnt;
+    }
+    descs[i] = make_desc(s, g, dm, &gms[i]);
+  }
+  if (ndoubles) HIP_TRY(hipMemcpy(s->dmat, hm.data(), 8 * ndoubles, hipMemcpyHostToDevice));
+  size_t applied = 0;
+  HIP_TRY(hipEventRecord(s->ev0, s->stream));
+  int rc = n_valid ? run_passes(s, descs.data(), gms.data(), n_valid, -1, 0, &applied) : SIM_OK;
+  HIP_TRY(hipEventRecord(s->ev1, s->stream));
+  HIP_TRY(hipEventSynchronize(s->ev1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, s->ev0, s->ev1);
+  s->elapsed += ms * 1e-3;
+  s->passes += applied;
+  if (s->kt_on) s->kt_flush();
+  if (n_applied) *n_applied = applied;
+  if (rc) return rc;
+  if (vrc) {
+    g_last_error = verr;
+    return vrc;
+  }
+  return SIM_OK;
+}
+
+static int readout(sim_t *s, uint64_t begin, uint64_t count, double *out, int probs) {
+  if (!s || (!out && count)) return set_err(SIM_EINVAL, "null argument");
+  const uint64_t N = 1ull << s->geo.n;
+  if (begin > N || count > N - begin) return set_err(SIM_EINVAL, "amplitude range out of bounds");
+  if (!count) return SIM_OK;
+  int rc;
+  const uint64_t *table;
+  if ((rc = slot_table(s, 0, &table))) return rc;
+  launch_begin_pass(s->stream, s->ctl, s->meta[s->cur], s->nslices, nullptr, s->kscale, 2);
+  const uint64_t L = s->geo.L;
+  const uint64_t per = probs ? 1 : 2;
+  const uint64_t stage_amps = std::min<uint64_t>(count, std::max<uint64_t>(L, 1ull << 24));
+  if (stage_amps * per > s->dstage_cap) {
+    s->dfree(s->dstage);
+    s->dstage = nullptr;
+    s->dstage_cap = 0;
+    if ((rc = s->dalloc((void **)&s->dstage, 8 * stage_amps * per))) return rc;
+    s->dstage_cap = stage_amps * per;
+  }
+  uint64_t i = begin;
+  const uint64_t end = begin + count;
+  while (i < end) {
+    const uint64_t j0 = i / L;
+    const uint64_t j1 = std::min<uint64_t>((end + L - 1) / L, j0 + (uint64_t)s->W);
+    const int ns = (int)(j1 - j0);
+    launch_decode(s->stream, s->slots, s->geo, table + j0, ns, s->arena[s->cur], s->meta[s->cur], s->kscale, s->ctl,
+                  s->pass_counter);
+    const uint64_t bend = std::min<uint64_t>(end, j1 * L);
+    uint64_t k = i;
+    while (k < bend) {
+      const uint64_t cnt = std::min<uint64_t>(bend - k, stage_amps);
+      launch_readout(s->stream, s->slots, s->geo, ns, k - j0 * L, cnt, probs, s->dstage);
+      HIP_TRY(hipMemcpyAsync(out + (k - begin) * per, s->dstage, 8 * cnt * per, hipMemcpyDeviceToHost, s->stream));
+      HIP_TRY(hipStreamSynchronize(s->stream));
+      k += cnt;
+    }
+    i = bend;
+  }
+  if ((rc = check_launch("readout"))) return rc;
+  if ((rc = read_ctl(s))) return rc;
+  if (s->h_ctl->flags) {
+    clear_flags(s);
+    return set_err(SIM_ECORRUPT, "a stored slice record failed its consistency checks");
+  }
+  return SIM_OK;
+}
+
+int sim_amplitudes(sim_t *s, uint64_t begin, uint64_t count, double *out) { return readout(s, begin, count, out, 0); }
+
+int sim_probabilities(sim_t *s, uint64_t begin, uint64_t count, double *out) {
+  return readout(s, begin, count, out, 1);
+}
+
+int sim_stats(sim_t *s, sim_stats_t *out) {
+  if (!s || !out) return set_err(SIM_EINVAL, "null argument");
+  int rc = read_ctl(s);
+  if (rc) return rc;
+  const Ctl &c = *s->h_ctl;
+  memset(out, 0, sizeof(*out));
+  out->raw_bytes = 16ull << s->geo.n;
+  out->compressed_bytes = c.cur_bytes;
+  out->peak_compressed = std::max(c.peak_bytes, c.cur_bytes);
+  out->ratio = c.cur_bytes ? (double)out->raw_bytes / (double)c.cur_bytes : 0.0;
+  out->min_ratio = out->peak_compressed ? (double)out->raw_bytes / (double)out->peak_compressed : 0.0;
+  out->passes = s->passes;
+  out->escapes = c.escapes;
+  out->last_norm = c.N;
+  double me;
+  memcpy(&me, &c.max_err_bits, 8);
+  out->max_abs_codec_err = me;
+  out->elapsed_s = s->elapsed;
+  out->arena_bytes = s->arena_cap[0] + s->arena_cap[1];
+  out->workspace_slots = (uint64_t)s->W;
+  return SIM_OK;
+}
+
+static int record_loc(sim_t *s, uint64_t j, uint64_t *off, uint32_t *len) {
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpy(off, s->meta[s->cur].rec_off + j, 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(len, s->meta[s->cur].rec_len + j, 4, hipMemcpyDeviceToHost));
+  return SIM_OK;
+}
+
+uint64_t sim_record_size(sim_t *s, uint64_t j) {
+  if (!s || j >= s->nslices) return 0;
+  uint64_t off;
+  uint32_t len;
+  if (record_loc(s, j, &off, &len)) return 0;
+  return len;
+}
+
+int sim_export_slice(sim_t *s, uint64_t j, void *buf, uint64_t cap, uint64_t *len_out) {
+  if (!s || !buf) return set_err(SIM_EINVAL, "null argument");
+  if (j >= s->nslices) return set_err(SIM_EINVAL, "slice %llu out of range", (unsigned long long)j);
+  uint64_t off;
+  uint32_t len;
+  int rc = record_loc(s, j, &off, &len);
+  if (rc) return rc;
+  if (len_out) *len_out = len;
+  if (cap < len) return set_err(SIM_EINVAL, "buffer of %llu bytes is smaller than the record (%u)",
+                                (unsigned long long)cap, len);
+  HIP_TRY(hipMemcpy(buf, s->arena[s->cur] + off, len, hipMemcpyDeviceToHost));
+  return SIM_OK;
+}
+
+// Host check of a record's structure (everything a decoder relies on).
+static int check_record(const sim_t *s, const uint8_t *r, uint64_t len, double *step, uint64_t sq[2]) {
+  auto rd32 = [&](uint64_t o) { uint32_t v; memcpy(&v, r + o, 4); return v; };
+  if (len < (uint64_t)kHdr || rd32(0) != kMagic) return set_err(SIM_ECORRUPT, "bad magic or short record");
+  const uint32_t sl2 = rd32(4), cl2 = rd32(8), n_used = rd32(12), nch = rd32(16), nw = rd32(20), tot = rd32(28);
+  if ((int)sl2 != s->geo.slice_log2 || (int)cl2 != s->geo.chunk_log2 || nch != s->geo.nchunks)
+    return set_err(SIM_ECORRUPT, "record geometry does not match the simulator");
+  if (n_used < 1 || n_used > (uint32_t)kNSym) return set_err(SIM_ECORRUPT, "bad symbol count");
+  if (rec_bytes_host(n_used, nch, nw) != tot || tot != len) return set_err(SIM_ECORRUPT, "inconsistent size");
+  uint64_t kraft = 0;
+  int prev = -1;
+  for (uint32_t k = 0; k < n_used; k++) {
+    uint16_t e;
+    memcpy(&e, r + kHdr + 2 * k, 2);
+    uint32_t l = e >> 10;
+    int key = (int)e;
+    if (l > (uint32_t)kLMax || key <= prev) return set_err(SIM_ECORRUPT, "bad symbol table");
+    prev = key;
+    kraft += 1ull << (kLMax - l);
+  }
+  if (kraft != (1ull << kLMax)) return set_err(SIM_ECORRUPT, "symbol table is not a complete prefix code");
+  const uint64_t ooff = kHdr + ((2ull * n_used + 3) & ~3ull);
+  uint32_t prevw = 0;
+  for (uint32_t c = 0; c <= nch; c++) {
+    uint32_t w = rd32(ooff + 4ull * c);
+    if (w < prevw || w > nw || (c == 0 && w != 0) || (c == nch && w != nw))
+      return set_err(SIM_ECORRUPT, "bad chunk offsets");
+    prevw = w;
+  }
+  memcpy(step, r + 32, 8);
+  memcpy(sq, r + 40, 16);
+  if (!(*step > 0.0) || !std::isfinite(*step)) return set_err(SIM_ECORRUPT, "bad step");
+  return SIM_OK;
+}
+
+int sim_import_slice(sim_t *s, uint64_t j, const void *buf, uint64_t len) {
+  if (!s || !buf) return set_err(SIM_EINVAL, "null argument");
+  if (j >= s->nslices) return set_err(SIM_EINVAL, "slice out of range");
+  double step;
+  uint64_t sq[2];
+  int rc = check_record(s, (const uint8_t *)buf, len, &step, sq);
+  if (rc) return rc;
+  if ((rc = read_ctl(s))) return rc;
+  const int a = s->cur;
+  uint64_t off = align_up(s->h_ctl->bump, kRecAlign);
+  if (off + len > s->arena_cap[a]) {
+    // move the arena into a larger buffer (records keep their offsets)
+    uint64_t cap = std::max<uint64_t>(2 * s->arena_cap[a], off + len + (16ull << 20));
+    uint8_t *na;
+    if ((rc = s->dalloc((void **)&na, cap))) return rc;
+    HIP_TRY(hipMemcpy(na, s->arena[a], s->h_ctl->bump, hipMemcpyDeviceToDevice));
+    s->dfree(s->arena[a]);
+    s->arena[a] = na;
+    s->arena_cap[a] = cap;
+  }
+  uint64_t old_off;
+  uint32_t old_len;
+  if ((rc = record_loc(s, j, &old_off, &old_len))) return rc;
+  const uint32_t len32 = (uint32_t)len;
+  HIP_TRY(hipMemcpy(s->arena[a] + off, buf, len, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->meta[a].rec_off + j, &off, 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->meta[a].rec_len + j, &len32, 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->meta[a].step + j, &step, 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->meta[a].sq + 2 * j, sq, 16, hipMemcpyHostToDevice));
+  s->h_ctl->bump = off + align_up(len, kRecAlign);
+  s->h_ctl->cur_bytes = s->h_ctl->cur_bytes - old_len + len;
+  HIP_TRY(hipMemcpy(&s->ctl->bump, &s->h_ctl->bump, 16, hipMemcpyHostToDevice));
+  return SIM_OK;
+}
+
+int sim_kernel_times(sim_t *s, int enable, double *out, int cap, const char **names) {
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  if (names) *names = kClassNames;
+  if (s->kt_on) s->kt_flush();
+  if (out)
+    for (int k = 0; k < K_COUNT && k < cap; k++) out[k] = s->kt_ms[k];
+  if (enable >= 0) {
+    const bool on = enable != 0;
+    if (on && s->kt_pool.empty()) {
+      s->kt_pool.resize(8192);
+      s->kt_cls.resize(4096);
+      for (auto &e : s->kt_pool) hipEventCreate(&e);
+    }
+    s->kt_on = on;
+    for (double &v : s->kt_ms) v = 0;
+    s->kt_used = 0;
+  }
+  return K_COUNT;
+}
+
+}  // extern "C"

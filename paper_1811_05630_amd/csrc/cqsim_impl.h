@@ -1,0 +1,137 @@
+// Internal declarations of libcqsim: the slice-record format constants, the
+// device control block, kernel parameter blocks and the launch wrappers that
+// the host scheduler (api.hip) calls.  Everything runs on gfx950; there is no
+// CPU path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cq {
+
+// ---------------------------------------------------------------- record format
+// A slice of L = 2^slice_log2 amplitudes is coded as one stream of 2L values
+// (the real plane, then the imaginary plane), cut into chunks of
+// B = 2^chunk_log2 values.  Record layout (little-endian, 4-byte fields):
+//   0  u32 magic 0x31535143         32 f64 step (quantisation step)
+//   4  u32 slice_log2                40 u64 sum p^2, low 64 bits
+//   8  u32 chunk_log2                48 u64 sum p^2, high 64 bits
+//  12  u32 n_used (coded symbols)    56 u32 0, 60 u32 0
+//  16  u32 n_chunks = 2L/B
+//  20  u32 n_words (bit stream)
+//  24  u32 n_escapes
+//  28  u32 total bytes of the record
+//  64  n_used x u16 (symbol | length << 10) ordered by (length, symbol), padded to 4 bytes
+//      (n_chunks + 1) x u32 word offset of each chunk in the bit stream
+//      n_words x u32 bit stream, most significant bit first, chunks word-aligned
+constexpr uint32_t kMagic = 0x31535143u;
+constexpr int kHdr = 64;
+constexpr int kR = 512;       // quantisation radius: symbol d + R for |d| < R
+constexpr int kNSym = 1024;   // alphabet; symbol 0 is the escape
+constexpr int kLMax = 12;     // longest code; also the decoder's lookup width
+constexpr int kEscBits = 6;   // escape payload: 6-bit length, then zigzag(d)
+constexpr double kPMax = 281474976710656.0;  // 2^48: |p| must stay below
+constexpr uint64_t kRecAlign = 256;          // records start on 256-byte boundaries
+
+// ------------------------------------------------------------- control block
+enum : uint32_t { kFlagBound = 1u, kFlagOverflow = 2u, kFlagCorrupt = 4u };
+
+struct Ctl {
+  uint64_t bump;          // aligned bytes used in the output arena by this pass
+  uint64_t cur_bytes;     // exact record bytes written by this pass
+  uint64_t peak_bytes;    // largest cur_bytes at the end of any pass
+  uint64_t max_err_bits;  // largest |a - p step| (non-negative FP64 bits)
+  uint64_t escapes;       // escape symbols coded
+  uint32_t flags;         // kFlag* bits; any set bit turns later kernels into no-ops
+  uint32_t fail_pass;     // pass counter value of the first failure
+  double N;               // norm of the stored state at the start of this pass
+  double s;               // 1 / sqrt(N)
+  uint64_t pad[6];
+};
+
+// ---------------------------------------------------------------- gate block
+// A gate acting on a group of 2^m slices (m = targets at slice-index qubits).
+// Inside a group the local index is gl = (member << slice_log2) | offset;
+// target k sits at local bit tloc[k] (targets below slice_log2 keep their bit,
+// slice-bit targets are renumbered slice_log2, slice_log2 + 1, ... in order).
+struct GateDesc {
+  int kind;               // 0: identity, 1: dense, 2: phase
+  int k;                  // number of targets
+  int m;                  // slice-bit targets
+  int pad0;
+  int tloc[5];
+  int pad1;
+  uint64_t tmask_loc;     // OR of 1 << tloc[k]
+  uint64_t ctrl_mask, ctrl_vals;
+  double ph_re, ph_im;
+  const double *mat;      // device, 2^k x 2^k complex, row-major, interleaved
+  uint64_t dep[32];       // local offset of column c: bits of c deposited at tloc
+};
+
+struct QuantParams {
+  int rel;                // 0: absolute bound, 1: value-range-relative bound
+  double eb;              // absolute bound, or the relative factor
+  double step, recip;     // absolute mode: step = 2 eb (1 - 2^-20), recip = 1/step
+};
+
+struct Geo {
+  int n;
+  int slice_log2;
+  int chunk_log2;
+  uint32_t nchunks;       // 2L / B
+  uint64_t L;
+};
+
+// Per-slot scratch of one batch of decompressed slices.
+struct Slots {
+  double *ws;             // [W][2L] decompressed values (re plane, im plane)
+  uint16_t *sym;          // [W][2L] symbols
+  int64_t *esc;           // [W][2L] exact differences of escaped values
+  uint32_t *hist;         // [W][1024]
+  uint32_t *codes;        // [W][1024] code << 8 | length
+  uint16_t *symtab;       // [W][1024] canonical symbol table
+  uint32_t *nused;        // [W]
+  uint32_t *chunk_words;  // [W][nchunks]
+  uint32_t *words;        // [W] total words
+  uint64_t *sq;           // [W][2] sum p^2 (lo, hi)
+  uint32_t *nesc;         // [W]
+  uint64_t *minmax;       // [W][2] ordered keys of min and max (relative bound)
+  double *qstep;          // [W][3] step, recip, bound (relative bound)
+};
+
+// Per-slice stored-state metadata (one copy per arena).
+struct StateMeta {
+  uint64_t *rec_off;      // [S] byte offset of the record in the arena
+  uint32_t *rec_len;      // [S] exact record bytes
+  double *step;           // [S]
+  uint64_t *sq;           // [S][2]
+};
+
+// -------------------------------------------------------------- launchers
+// All launches go to `st`; `pass` is the global pass counter (for failure
+// reporting); `slot_slice` lists the slice held by every slot of the batch.
+void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *tmp,
+                       double *kscale, int with_norm);
+void launch_reset_slots(hipStream_t st, const Slots &sl, const Geo &g, int nslots);
+void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots, int kind,
+                 uint64_t x, const double *factors, const Ctl *ctl);
+void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                   const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl, uint32_t pass);
+void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                        const GateDesc &gd, const Ctl *ctl);
+void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl);
+void launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                       const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass);
+void launch_codebook(hipStream_t st, const Slots &sl, int nslots, const Ctl *ctl);
+void launch_chunkbits(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
+void launch_layout(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                   const StateMeta &nxt, uint64_t arena_cap, Ctl *ctl, uint32_t pass);
+void launch_header(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                   const QuantParams &qp, uint8_t *arena, const StateMeta &nxt, const Ctl *ctl);
+void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                   uint8_t *arena, const StateMeta &nxt, const Ctl *ctl);
+void launch_end_pass(hipStream_t st, Ctl *ctl);
+void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, int nslots, uint64_t first_amp, uint64_t count,
+                    int probabilities, double *out);
+
+}  // namespace cq

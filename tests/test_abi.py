@@ -1,0 +1,104 @@
+"""Host-only checks of the C ABI boundary: the library loads, exports every
+entry point include/cqsim.h declares, and the binding's structure layouts
+match the header as a C compiler sees it.  No kernel is launched."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+import paper_1811_05630_amd as cq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cqsim.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(cq.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(cq.LIB_PATH):
+        pytest.skip("libcqsim.so not built (run __graft_entry__.build())")
+    L = C.CDLL(cq.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", cq.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (sim_[a-z_]+)\b", out))
+    assert set(declared_functions()) <= exported
+
+
+LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "cqsim.h"
+#define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("sim_gate %zu\n", sizeof(sim_gate));
+  printf("sim_config %zu\n", sizeof(sim_config));
+  printf("sim_stats_t %zu\n", sizeof(sim_stats_t));
+  F(sim_gate, targets); F(sim_gate, ctrl_mask); F(sim_gate, phase_re); F(sim_gate, matrix);
+  F(sim_config, error_bound); F(sim_config, workspace_bytes); F(sim_config, alloc); F(sim_config, stream);
+  F(sim_config, arena_bytes);
+  F(sim_stats_t, ratio); F(sim_stats_t, max_abs_codec_err); F(sim_stats_t, workspace_slots);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header():
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(src, "w").write(LAYOUT_C)
+        subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), "-o", exe, src], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(line.split() for line in out.strip().splitlines())
+    py = {
+        "sim_gate": C.sizeof(cq.GateStruct), "sim_config": C.sizeof(cq.ConfigStruct),
+        "sim_stats_t": C.sizeof(cq.StatsStruct),
+        "sim_gate.targets": cq.GateStruct.targets.offset, "sim_gate.ctrl_mask": cq.GateStruct.ctrl_mask.offset,
+        "sim_gate.phase_re": cq.GateStruct.phase_re.offset, "sim_gate.matrix": cq.GateStruct.matrix.offset,
+        "sim_config.error_bound": cq.ConfigStruct.error_bound.offset,
+        "sim_config.workspace_bytes": cq.ConfigStruct.workspace_bytes.offset,
+        "sim_config.alloc": cq.ConfigStruct.alloc.offset, "sim_config.stream": cq.ConfigStruct.stream.offset,
+        "sim_config.arena_bytes": cq.ConfigStruct.arena_bytes.offset,
+        "sim_stats_t.ratio": cq.StatsStruct.ratio.offset,
+        "sim_stats_t.max_abs_codec_err": cq.StatsStruct.max_abs_codec_err.offset,
+        "sim_stats_t.workspace_slots": cq.StatsStruct.workspace_slots.offset,
+    }
+    assert {k: int(v) for k, v in got.items()} == py
+    assert py["sim_gate"] == 72
+
+
+def test_binding_converts_gates_without_the_device():
+    import numpy as np
+    import qcircuits as qc
+    arr, keep = cq.gate_array([qc.H(3), qc.CP(1, 4, 0.25), qc.SWAP(0, 7)])
+    assert arr[0].kind == cq.GATE_DENSE and arr[0].n_targets == 1 and arr[0].targets[0] == 3
+    assert arr[1].kind == cq.GATE_PHASE and arr[1].ctrl_mask == 0b10010
+    m = np.ctypeslib.as_array(arr[2].matrix, shape=(32,))
+    assert m[2 * (1 * 4 + 2)] == 1.0  # SWAP row 1, column 2
+
+
+def test_no_device_means_a_loud_failure():
+    """Without a GPU the library refuses to run (no CPU fallback)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    if not os.path.exists(cq.LIB_PATH):
+        pytest.skip("libcqsim.so not built")
+    with pytest.raises(cq.SimError) as e:
+        cq.Sim(4, 2, 1e-6, use_torch=False)
+    assert e.value.rc == -5
