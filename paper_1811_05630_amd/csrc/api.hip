@@ -47,11 +47,10 @@ int set_err(int code, const char *fmt, ...) {
       return set_err(SIM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
   } while (0)
 
-enum KClass { K_BEGIN, K_RESET, K_INIT, K_DECODE, K_MINMAX, K_RELSTEP, K_GATEQ, K_CODEBOOK, K_CHUNKBITS,
-              K_LAYOUT, K_HEADER, K_ENCODE, K_END, K_READOUT, K_COUNT };
+enum KClass { K_BEGIN, K_RESET, K_INIT, K_DECODE, K_MINMAX, K_RELSTEP, K_GATEQ, K_CODEBOOK, K_ENCODE, K_HEADER,
+              K_COMPACT, K_READOUT, K_COUNT };
 const char *kClassNames =
-    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,chunkbits,layout,header,encode,"
-    "end_pass,readout";
+    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,encode,header,compact,readout";
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -167,6 +166,7 @@ int alloc_meta(sim_t *s, StateMeta &m) {
   if ((rc = s->dalloc((void **)&m.rec_len, 4 * s->nslices))) return rc;
   if ((rc = s->dalloc((void **)&m.step, 8 * s->nslices))) return rc;
   if ((rc = s->dalloc((void **)&m.sq, 16 * s->nslices))) return rc;
+  if ((rc = s->dalloc((void **)&m.dtab, 2ull * (1u << kLMax) * s->nslices))) return rc;
   return SIM_OK;
 }
 
@@ -177,7 +177,6 @@ int alloc_slots(sim_t *s) {
   if ((rc = s->dalloc((void **)&sl.ws, 8 * W * L2))) return rc;
   if ((rc = s->dalloc((void **)&sl.sym, 2 * W * L2))) return rc;
   if ((rc = s->dalloc((void **)&sl.esc, 8 * W * L2))) return rc;
-  if ((rc = s->dalloc((void **)&sl.hist, 4 * W * kNSym))) return rc;
   if ((rc = s->dalloc((void **)&sl.codes, 4 * W * kNSym))) return rc;
   if ((rc = s->dalloc((void **)&sl.symtab, 2 * W * kNSym))) return rc;
   if ((rc = s->dalloc((void **)&sl.nused, 4 * W))) return rc;
@@ -187,11 +186,16 @@ int alloc_slots(sim_t *s) {
   if ((rc = s->dalloc((void **)&sl.nesc, 4 * W))) return rc;
   if ((rc = s->dalloc((void **)&sl.minmax, 16 * W))) return rc;
   if ((rc = s->dalloc((void **)&sl.qstep, 24 * W))) return rc;
+  if ((rc = s->dalloc((void **)&sl.part, 32ull * W * kGqParts))) return rc;
+  if ((rc = s->dalloc((void **)&sl.hpart, 4ull * W * kGqParts * kNSym))) return rc;
+  sl.stage_words = stage_words_for(s->geo.chunk_log2);
+  if ((rc = s->dalloc((void **)&sl.stage, 4ull * W * s->geo.nchunks * sl.stage_words))) return rc;
   return SIM_OK;
 }
 
 uint64_t per_slot_bytes(const Geo &g) {
-  return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 4 + 2) + 4ull * g.nchunks + 128;
+  return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 2) + 4ull * kGqParts * (kNSym + 8) + 4ull * g.nchunks +
+         4ull * g.nchunks * stage_words_for(g.chunk_log2) + 128;
 }
 
 // Slot order of every slice for gates whose slice-index targets form `gm`:
@@ -277,6 +281,8 @@ GateDesc make_desc(const sim_t *s, const sim_gate &g, const double *dmat, uint64
     d.tmask_loc |= 1ull << d.tloc[k];
   }
   d.m = __builtin_popcountll(gm);
+  if (d.k == 1)
+    for (int i = 0; i < 8; i++) d.m2[i] = g.matrix[i];
   for (int c = 0; c < (1 << d.k); c++) {
     uint64_t off = 0;
     for (int k = 0; k < d.k; k++)
@@ -311,14 +317,11 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
   int rc = slot_table(s, init_kind >= 0 ? 0 : gm, &table);
   if (rc) return rc;
   s->kt_begin(K_BEGIN);
-  launch_begin_pass(st, s->ctl, cur, s->nslices, nullptr, s->kscale, init_kind >= 0 ? 0 : 1);
+  launch_begin_pass(st, s->ctl, cur, s->nslices, s->kscale, init_kind >= 0 ? 0 : 1);
   s->kt_end();
   for (uint64_t b0 = 0; b0 < s->nslices; b0 += (uint64_t)s->W) {
     const int ns = (int)std::min<uint64_t>((uint64_t)s->W, s->nslices - b0);
     const uint64_t *ss = table + b0;
-    s->kt_begin(K_RESET);
-    launch_reset_slots(st, s->slots, s->geo, ns);
-    s->kt_end();
     if (init_kind >= 0) {
       s->kt_begin(K_INIT);
       launch_init(st, s->slots, s->geo, ss, ns, init_kind, x, s->dfactors, s->ctl);
@@ -340,24 +343,18 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
     launch_gate_quant(st, s->slots, s->geo, ss, ns, gd, qp, s->ctl, pass);
     s->kt_end();
     s->kt_begin(K_CODEBOOK);
-    launch_codebook(st, s->slots, ns, s->ctl);
-    s->kt_end();
-    s->kt_begin(K_CHUNKBITS);
-    launch_chunkbits(st, s->slots, s->geo, ns, s->ctl);
-    s->kt_end();
-    s->kt_begin(K_LAYOUT);
-    launch_layout(st, s->slots, s->geo, ss, ns, nxt, s->arena_cap[1 - c], s->ctl, pass);
-    s->kt_end();
-    s->kt_begin(K_HEADER);
-    launch_header(st, s->slots, s->geo, ss, ns, qp, s->arena[1 - c], nxt, s->ctl);
+    launch_codebook(st, s->slots, ss, ns, nxt, s->ctl);
     s->kt_end();
     s->kt_begin(K_ENCODE);
-    launch_encode(st, s->slots, s->geo, ss, ns, s->arena[1 - c], nxt, s->ctl);
+    launch_encode(st, s->slots, s->geo, ns, s->ctl);
+    s->kt_end();
+    s->kt_begin(K_HEADER);
+    launch_header(st, s->slots, s->geo, ss, ns, qp, s->arena[1 - c], s->arena_cap[1 - c], nxt, s->ctl, pass);
+    s->kt_end();
+    s->kt_begin(K_COMPACT);
+    launch_compact(st, s->slots, s->geo, ss, ns, s->arena[1 - c], nxt, s->ctl);
     s->kt_end();
   }
-  s->kt_begin(K_END);
-  launch_end_pass(st, s->ctl);
-  s->kt_end();
   s->cur = 1 - c;
   return check_launch("pass");
 }
@@ -368,12 +365,15 @@ int read_ctl(sim_t *s) {
   return SIM_OK;
 }
 
+// After a failure the per-slot accumulators may hold partial sums: clear
+// them together with the flags.
 int clear_flags(sim_t *s) {
   s->h_ctl->flags = 0;
   s->h_ctl->fail_pass = 0;
   HIP_TRY(hipMemcpyAsync(&s->ctl->flags, &s->h_ctl->flags, 8, hipMemcpyHostToDevice, s->stream));
+  launch_reset_slots(s->stream, s->slots, s->W);
   HIP_TRY(hipStreamSynchronize(s->stream));
-  return SIM_OK;
+  return check_launch("reset_slots");
 }
 
 int grow_arena(sim_t *s, int which, uint64_t min_cap) {
@@ -462,7 +462,7 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
   if (cfg->mode & ~(SIM_EB_REL)) return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
   int cl2 = cfg->chunk_log2 > 0 ? cfg->chunk_log2 : 10;
   if (cl2 > sl2) cl2 = sl2;
-  if (cl2 > 12) return set_err(SIM_EINVAL, "chunk_log2 %d above 12", cl2);
+  if (cl2 > 10) return set_err(SIM_EINVAL, "chunk_log2 %d above 10", cl2);
 
   int ndev = 0;
   hipError_t de = hipGetDeviceCount(&ndev);
@@ -529,6 +529,7 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
     sim_destroy(s);
     return set_err(SIM_EDEVICE, "control block upload failed");
   }
+  launch_reset_slots(s->stream, s->slots, s->W);
   const uint64_t cap =
       cfg->arena_bytes ? std::max<uint64_t>(cfg->arena_bytes, 4096) : std::max<uint64_t>(4 * min_record_total(s), 16ull << 20);
   for (int a = 0; a < 2; a++) {
@@ -655,7 +656,7 @@ static int readout(sim_t *s, uint64_t begin, uint64_t count, double *out, int pr
   int rc;
   const uint64_t *table;
   if ((rc = slot_table(s, 0, &table))) return rc;
-  launch_begin_pass(s->stream, s->ctl, s->meta[s->cur], s->nslices, nullptr, s->kscale, 2);
+  launch_begin_pass(s->stream, s->ctl, s->meta[s->cur], s->nslices, s->kscale, 2);
   const uint64_t L = s->geo.L;
   const uint64_t per = probs ? 1 : 2;
   const uint64_t stage_amps = std::min<uint64_t>(count, std::max<uint64_t>(L, 1ull << 24));
@@ -678,7 +679,7 @@ static int readout(sim_t *s, uint64_t begin, uint64_t count, double *out, int pr
     uint64_t k = i;
     while (k < bend) {
       const uint64_t cnt = std::min<uint64_t>(bend - k, stage_amps);
-      launch_readout(s->stream, s->slots, s->geo, ns, k - j0 * L, cnt, probs, s->dstage);
+      launch_readout(s->stream, s->slots, s->geo, k - j0 * L, cnt, probs, s->dstage);
       HIP_TRY(hipMemcpyAsync(out + (k - begin) * per, s->dstage, 8 * cnt * per, hipMemcpyDeviceToHost, s->stream));
       HIP_TRY(hipStreamSynchronize(s->stream));
       k += cnt;
@@ -816,6 +817,21 @@ int sim_import_slice(sim_t *s, uint64_t j, const void *buf, uint64_t len) {
   HIP_TRY(hipMemcpy(s->meta[a].rec_len + j, &len32, 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(s->meta[a].step + j, &step, 8, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(s->meta[a].sq + 2 * j, sq, 16, hipMemcpyHostToDevice));
+  {  // decoder table: code intervals of size 2^(12 - len) in table order tile [0, 4096)
+    const uint8_t *r = (const uint8_t *)buf;
+    uint32_t n_used;
+    memcpy(&n_used, r + 12, 4);
+    std::vector<uint16_t> dt(1u << kLMax);
+    uint32_t at = 0;
+    for (uint32_t k = 0; k < n_used; k++) {
+      uint16_t e;
+      memcpy(&e, r + kHdr + 2 * k, 2);
+      const uint32_t size = 1u << (kLMax - (e >> 10));
+      for (uint32_t i = 0; i < size; i++) dt[at + i] = e;
+      at += size;
+    }
+    HIP_TRY(hipMemcpy(s->meta[a].dtab + j * (1u << kLMax), dt.data(), 2u << kLMax, hipMemcpyHostToDevice));
+  }
   s->h_ctl->bump = off + align_up(len, kRecAlign);
   s->h_ctl->cur_bytes = s->h_ctl->cur_bytes - old_len + len;
   HIP_TRY(hipMemcpy(&s->ctl->bump, &s->h_ctl->bump, 16, hipMemcpyHostToDevice));

@@ -38,7 +38,7 @@ enum : uint32_t { kFlagBound = 1u, kFlagOverflow = 2u, kFlagCorrupt = 4u };
 
 struct Ctl {
   uint64_t bump;          // aligned bytes used in the output arena by this pass
-  uint64_t cur_bytes;     // exact record bytes written by this pass
+  uint64_t cur_bytes;     // exact record bytes of the stored state
   uint64_t peak_bytes;    // largest cur_bytes at the end of any pass
   uint64_t max_err_bits;  // largest |a - p step| (non-negative FP64 bits)
   uint64_t escapes;       // escape symbols coded
@@ -46,7 +46,9 @@ struct Ctl {
   uint32_t fail_pass;     // pass counter value of the first failure
   double N;               // norm of the stored state at the start of this pass
   double s;               // 1 / sqrt(N)
-  uint64_t pad[6];
+  uint64_t pending_bump;  // aligned bytes of the batch being written (header -> compact)
+  uint64_t pending_bytes; // exact bytes of that batch
+  uint64_t pad[4];
 };
 
 // ---------------------------------------------------------------- gate block
@@ -65,6 +67,7 @@ struct GateDesc {
   uint64_t ctrl_mask, ctrl_vals;
   double ph_re, ph_im;
   const double *mat;      // device, 2^k x 2^k complex, row-major, interleaved
+  double m2[8];           // one-target gates: the 2x2 matrix itself
   uint64_t dep[32];       // local offset of column c: bits of c deposited at tloc
 };
 
@@ -83,11 +86,14 @@ struct Geo {
 };
 
 // Per-slot scratch of one batch of decompressed slices.
+// Accumulators are zero between uses: hpart and part are cleared by the
+// codebook kernel, sq and nesc by the header kernel, words by the compact
+// kernel and minmax by the relative-step kernel, each right after its last
+// reader.
 struct Slots {
   double *ws;             // [W][2L] decompressed values (re plane, im plane)
   uint16_t *sym;          // [W][2L] symbols
   int64_t *esc;           // [W][2L] exact differences of escaped values
-  uint32_t *hist;         // [W][1024]
   uint32_t *codes;        // [W][1024] code << 8 | length
   uint16_t *symtab;       // [W][1024] canonical symbol table
   uint32_t *nused;        // [W]
@@ -97,6 +103,13 @@ struct Slots {
   uint32_t *nesc;         // [W]
   uint64_t *minmax;       // [W][2] ordered keys of min and max (relative bound)
   double *qstep;          // [W][3] step, recip, bound (relative bound)
+  uint32_t *stage;        // [W][nchunks][stage_words] encoded chunks before compaction
+  uint32_t stage_words;   // capacity of one chunk: ceil(B * 68 / 32) words
+  // gate_quant writes, per slot, up to kGqParts partial results (one per
+  // workgroup and tile role) without atomics; the codebook kernel adds and
+  // clears them
+  uint32_t *hpart;        // [W][kGqParts][1024] partial histograms
+  uint64_t *part;         // [W][kGqParts][4] sum p^2 lo, hi, escapes, max error bits
 };
 
 // Per-slice stored-state metadata (one copy per arena).
@@ -105,14 +118,17 @@ struct StateMeta {
   uint32_t *rec_len;      // [S] exact record bytes
   double *step;           // [S]
   uint64_t *sq;           // [S][2]
+  uint16_t *dtab;         // [S][4096] decoder lookup table derived from the record's symbol table
 };
 
 // -------------------------------------------------------------- launchers
 // All launches go to `st`; `pass` is the global pass counter (for failure
 // reporting); `slot_slice` lists the slice held by every slot of the batch.
-void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *tmp,
-                       double *kscale, int with_norm);
-void launch_reset_slots(hipStream_t st, const Slots &sl, const Geo &g, int nslots);
+// with_norm: 0 = a pass that builds an initial state, 1 = a gate pass,
+// 2 = read-out only (scales without touching the pass counters).
+void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *kscale,
+                       int with_norm);
+void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots);
 void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots, int kind,
                  uint64_t x, const double *factors, const Ctl *ctl);
 void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
@@ -122,16 +138,26 @@ void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uin
 void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl);
 void launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                        const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass);
-void launch_codebook(hipStream_t st, const Slots &sl, int nslots, const Ctl *ctl);
-void launch_chunkbits(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
-void launch_layout(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   const StateMeta &nxt, uint64_t arena_cap, Ctl *ctl, uint32_t pass);
+void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
+                     Ctl *ctl);
+void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
 void launch_header(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   const QuantParams &qp, uint8_t *arena, const StateMeta &nxt, const Ctl *ctl);
-void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   uint8_t *arena, const StateMeta &nxt, const Ctl *ctl);
-void launch_end_pass(hipStream_t st, Ctl *ctl);
-void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, int nslots, uint64_t first_amp, uint64_t count,
+                   const QuantParams &qp, uint8_t *arena, uint64_t arena_cap, const StateMeta &nxt, Ctl *ctl,
+                   uint32_t pass);
+void launch_compact(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                    uint8_t *arena, const StateMeta &nxt, Ctl *ctl);
+void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,
                     int probabilities, double *out);
+
+// amplitudes per gate_quant tile (a power of two, at most L, a multiple of
+// the chunk length); workgroups per slot and partial results per slot
+inline uint64_t gq_tile(uint64_t L) { return L < 1024 ? L : 1024; }
+constexpr uint32_t kGqWgs = 16;
+constexpr uint32_t kGqParts = 2 * kGqWgs;
+
+// words of one chunk's staging slot
+inline uint32_t stage_words_for(int chunk_log2) {
+  return (uint32_t)((((uint64_t)1 << chunk_log2) * (kLMax + kEscBits + 50) + 31) / 32 + 1);
+}
 
 }  // namespace cq

@@ -1,18 +1,23 @@
 // Device kernels of libcqsim for gfx950 (CDNA4, 64-wide wavefronts).
 //
-// One pass of Algorithm 1 (Section II of the paper) over a batch of slices is
-//   decode      Decompress(S): canonical-Huffman decode, exact escapes, prefix
-//               sum inside each chunk, a = p * (step * s)  -- Normalize(S) folded in
+// One pass of Algorithm 1 (Section II of the paper) over a batch of slices:
+//   begin_pass  norm of the stored state -> normalisation scale per slice
+//   decode      Decompress(S) + Normalize(S): canonical-Huffman decode with a
+//               4096-entry LDS table, exact escapes, prefix sum inside each
+//               chunk, a = p * (step * s); stores staged through LDS so that
+//               every wavefront writes whole 128-byte lines
 //   gate_quant  GateComputation(G, S) and the first half of Compress(S):
-//               error-bounded quantisation, chunked Lorenzo difference, symbols,
-//               escapes, histogram, exact sum of p^2
-//   codebook    package-merge code lengths (limit 12), canonical codes
-//   chunkbits   coded size of every chunk
-//   layout      record sizes -> offsets in the output arena
-//   header      record header, symbol table, chunk word offsets
-//   encode      bit packing, most significant bit first, one wavefront per chunk
-// FP64 arithmetic is never contracted into FMAs (the pragma below), so that
-// every rounding happens exactly as in the stream definition.
+//               error-bounded quantisation, chunked Lorenzo difference,
+//               symbols, escapes, histogram, exact sum of p^2
+//   codebook    package-merge code lengths (limit 12), canonical codes, the
+//               decoder table of the new record
+//   encode      bit packing, most significant bit first, one wavefront per
+//               chunk, into a fixed-size staging slot per chunk
+//   header      record sizes -> offsets in the output arena; record header,
+//               symbol table and chunk word offsets
+//   compact     copy each chunk's words from staging into its record
+// FP64 arithmetic is never contracted into FMAs (the pragma below), so every
+// rounding happens exactly as in the stream definition.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -32,6 +37,17 @@ __device__ __forceinline__ void cmac(double ur, double ui, double ar, double ai,
   double qi = ui * ar;
   cr = cr + (pr - pi);
   ci = ci + (qr + qi);
+}
+
+// u * a as the first term of a sum: equal to cmac from c = 0 except for the
+// sign of an exact zero, which no quantisation code can see
+__device__ __forceinline__ void cmul(double ur, double ui, double ar, double ai, double &cr, double &ci) {
+  double pr = ur * ar;
+  double pi = ui * ai;
+  double qr = ur * ai;
+  double qi = ui * ar;
+  cr = pr - pi;
+  ci = qr + qi;
 }
 
 __device__ __forceinline__ uint64_t zigzag(int64_t d) { return ((uint64_t)d << 1) ^ (uint64_t)(d >> 63); }
@@ -54,6 +70,17 @@ __device__ __forceinline__ void fail(Ctl *ctl, uint32_t bit, uint32_t pass) {
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
+// Workgroup barrier for phases that share only LDS: waits for this
+// wavefront's LDS operations (s_waitcnt lgkmcnt(0)), not for its global loads
+// and stores, so prefetched loads and earlier stores stay in flight.  The
+// asm clobbers keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_sync() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt and expcnt at their maximum, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
 // inclusive scan of a u32 over one wavefront
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   const uint32_t lane = lane_id();
@@ -65,13 +92,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
-// exclusive scan of one u32 per thread over a block of up to 1024 threads;
-// returns the prefix, *total gets the block sum.  Uses `scratch` (>= 16 u32).
+// exclusive scan of one u32 per thread over a block of up to 1024 threads
+// (whole wavefronts); returns the prefix, *total gets the block sum.
 __device__ uint32_t block_excl_scan(uint32_t x, uint32_t *scratch, uint32_t *total) {
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
   const uint32_t nw = (blockDim.x + 63) >> 6;
   uint32_t inc = wave_incl_scan(x);
-  if (lane == 63 || threadIdx.x == blockDim.x - 1) scratch[wave] = inc;
+  if (lane == 63) scratch[wave] = inc;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
@@ -89,7 +116,24 @@ __device__ uint32_t block_excl_scan(uint32_t x, uint32_t *scratch, uint32_t *tot
   return r;
 }
 
-// ----------------------------------------------------------- begin / end pass
+// block-wide sum of a u64 (whole wavefronts, up to 16 of them)
+__device__ uint64_t block_sum64(uint64_t x, uint64_t *scratch) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  if (lane_id() == 0) scratch[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint64_t t = 0;
+  for (uint32_t w = 0; w < blockDim.x / 64; w++) t += scratch[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ uint64_t rec_bytes(uint32_t n_used, uint32_t nchunks, uint32_t words) {
+  return (uint64_t)kHdr + ((2ull * n_used + 3) & ~3ull) + 4ull * (nchunks + 1) + 4ull * words;
+}
+
+__device__ __forceinline__ uint32_t ld32(const uint8_t *p) { return *(const uint32_t *)p; }
+
+// ----------------------------------------------------------- begin pass
 
 __device__ __forceinline__ double norm_leaf(const double *step, const uint64_t *sq, uint64_t j) {
   double s = step[j];
@@ -114,20 +158,18 @@ __device__ double pairwise_block(const double *step, const uint64_t *sq, uint64_
   return stk[0];
 }
 
-// with_norm: 0 = initial state (no norm), 1 = a pass, 2 = read-out only
 __global__ void __launch_bounds__(1024) k_begin_pass(Ctl *ctl, const double *step, const uint64_t *sq, uint64_t S,
                                                      double *kscale, int with_norm) {
   if (ctl->flags) return;
   __shared__ double part[1024];
   __shared__ double s_sh;
   const uint32_t tid = threadIdx.x, T = blockDim.x;
-  if (!with_norm) {
-    if (tid == 0) {
-      ctl->bump = 0;
-      ctl->cur_bytes = 0;
-    }
-    return;
+  if (with_norm != 2 && tid == 0) {  // a pass starts writing the other arena
+    if (ctl->cur_bytes > ctl->peak_bytes) ctl->peak_bytes = ctl->cur_bytes;
+    ctl->bump = 0;
+    ctl->cur_bytes = 0;
   }
+  if (with_norm == 0) return;
   uint64_t active;
   if (S <= T) {
     part[tid] = tid < S ? norm_leaf(step, sq, tid) : 0.0;
@@ -155,11 +197,9 @@ __global__ void __launch_bounds__(1024) k_begin_pass(Ctl *ctl, const double *ste
       t = 1.5 - t;
       y = y * t;
     }
-    if (with_norm == 1) {  // a pass starts writing the other arena
+    if (with_norm == 1) {
       ctl->N = N;
       ctl->s = y;
-      ctl->bump = 0;
-      ctl->cur_bytes = 0;
     }
     s_sh = y;
   }
@@ -167,14 +207,11 @@ __global__ void __launch_bounds__(1024) k_begin_pass(Ctl *ctl, const double *ste
   for (uint64_t j = tid; j < S; j += T) kscale[j] = step[j] * s_sh;
 }
 
-__global__ void k_end_pass(Ctl *ctl) {
-  if (ctl->flags) return;
-  if (ctl->cur_bytes > ctl->peak_bytes) ctl->peak_bytes = ctl->cur_bytes;
-}
-
-__global__ void k_reset_slots(Slots sl, uint32_t nchunks, int nslots) {
+// zero every per-slot accumulator (creation and recovery after a failure)
+__global__ void k_reset_slots(Slots sl, int nslots) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < (uint64_t)nslots * kNSym) sl.hist[i] = 0;
+  if (i < (uint64_t)nslots * kGqParts * kNSym) sl.hpart[i] = 0;
+  if (i < (uint64_t)nslots * kGqParts * 4) sl.part[i] = 0;
   if (i < (uint64_t)nslots) {
     sl.sq[2 * i] = 0;
     sl.sq[2 * i + 1] = 0;
@@ -217,23 +254,31 @@ __global__ void k_init(Slots sl, Geo g, const uint64_t *slot_slice, uint64_t tot
 }
 
 // ------------------------------------------------------------------ decode
-// One lane decodes one chunk serially; the workgroup first expands the
-// record's canonical symbol table into a 4096-entry lookup table in LDS
-// (entry = symbol | length << 10, indexed by the next 12 stream bits).
-
-__device__ __forceinline__ uint32_t ld32(const uint8_t *p) { return *(const uint32_t *)p; }
+// One wavefront per workgroup, one lane per chunk: the lane walks its chunk's
+// bit stream serially (12-bit peek into the decoder table, escapes carry the
+// exact difference), keeps the running sum p and writes a = p * k.  Every 16
+// values per lane go through an LDS tile and leave as whole 128-byte lines.
 
 struct BitReader {
   const uint32_t *w;
   uint32_t nw, wi;
+  uint32_t nxt;  // next stream word, loaded one refill ahead
   uint64_t buf;
   int nbits;
+  __device__ __forceinline__ void start(const uint32_t *words, uint32_t n) {
+    w = words;
+    nw = n;
+    wi = 0;
+    buf = 0;
+    nbits = 0;
+    nxt = n ? w[0] : 0u;
+  }
   __device__ __forceinline__ void refill() {
     while (nbits <= 32) {
-      uint32_t x = wi < nw ? w[wi] : 0u;
-      wi++;
-      buf |= (uint64_t)x << (32 - nbits);
+      buf |= (uint64_t)nxt << (32 - nbits);
       nbits += 32;
+      wi++;
+      nxt = wi < nw ? w[wi] : 0u;
     }
   }
   __device__ __forceinline__ uint64_t take(int n) {  // 0 <= n <= 32, needs nbits >= n
@@ -245,129 +290,106 @@ struct BitReader {
   }
 };
 
-__global__ void __launch_bounds__(256) k_decode(Slots sl, Geo g, const uint64_t *slot_slice, const uint8_t *arena,
-                                                StateMeta cur, const double *kscale, Ctl *ctl, uint32_t pass) {
+constexpr int kDecLanes = 64;
+constexpr int kDecRow = 16;    // values per lane per LDS round
+constexpr int kDecPitch = 17;  // LDS row pitch in doubles (breaks bank conflicts)
+
+__global__ void __launch_bounds__(kDecLanes) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
+                                                      const uint8_t *arena, StateMeta cur, const double *kscale,
+                                                      Ctl *ctl, uint32_t pass) {
   if (ctl->flags) return;
   __shared__ uint16_t dtab[1 << kLMax];
-  __shared__ uint16_t ent[kNSym];
-  __shared__ uint32_t lav[kNSym];
-  __shared__ uint32_t scratch[20];
-  __shared__ int bad;
-  const uint32_t u = blockIdx.y;
+  __shared__ double stg[kDecLanes * kDecPitch];
+  const uint32_t u = blockIdx.y, lane = threadIdx.x;
   const uint64_t slice = slot_slice[u];
   const uint8_t *rec = arena + cur.rec_off[slice];
-  const uint32_t tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  __syncthreads();
   const uint32_t n_used = ld32(rec + 12);
   const uint32_t nchunks = ld32(rec + 16);
   const uint32_t n_words = ld32(rec + 20);
-  if (tid == 0) {
-    if (ld32(rec) != kMagic || n_used < 1 || n_used > (uint32_t)kNSym || nchunks != g.nchunks ||
-        ld32(rec + 8) != (uint32_t)g.chunk_log2)
-      bad = 1;
-  }
-  __syncthreads();
-  if (bad) {
-    if (tid == 0) fail(ctl, kFlagCorrupt, pass);
+  if (ld32(rec) != kMagic || n_used < 1 || n_used > (uint32_t)kNSym || nchunks != g.nchunks ||
+      ld32(rec + 8) != (uint32_t)g.chunk_log2) {
+    if (lane == 0) fail(ctl, kFlagCorrupt, pass);
     return;
   }
-  // canonical table: code intervals of size 2^(12 - len) tile [0, 4096) in order
-  const uint16_t *st = (const uint16_t *)(rec + kHdr);
-  uint32_t sz[4], loc = 0;
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    uint32_t i = tid * 4 + k;
-    uint32_t s = 0;
-    if (i < n_used) {
-      uint16_t e = st[i];
-      ent[i] = e;
-      uint32_t len = e >> 10;
-      s = len <= (uint32_t)kLMax ? (1u << (kLMax - len)) : 0x10000u;
-    }
-    sz[k] = s;
-    loc += s;
+  {
+    const uint4 *src = (const uint4 *)(cur.dtab + slice * (1u << kLMax));
+    uint4 *dst = (uint4 *)dtab;
+    for (uint32_t i = lane; i < (1u << kLMax) / 8; i += kDecLanes) dst[i] = src[i];
   }
-  uint32_t tot;
-  uint32_t pre = block_excl_scan(loc, scratch, &tot);
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    uint32_t i = tid * 4 + k;
-    if (i < n_used) lav[i] = pre;
-    pre += sz[k];
-  }
-  if (tot != (1u << kLMax)) {
-    if (tid == 0) fail(ctl, kFlagCorrupt, pass);
-    return;
-  }
-  __syncthreads();
-  for (uint32_t e = tid; e < (1u << kLMax); e += blockDim.x) {
-    uint32_t lo = 0, hi = n_used;  // last k with lav[k] <= e
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (lav[mid] <= e) lo = mid; else hi = mid;
-    }
-    dtab[e] = ent[lo];
-  }
-  __syncthreads();
-
-  const uint32_t c = blockIdx.x * blockDim.x + tid;
-  if (c >= nchunks) return;
+  const uint32_t c0 = blockIdx.x * kDecLanes;
+  const uint32_t c = c0 + lane;
+  const bool active = c < nchunks;
   const uint32_t sym_bytes = (2 * n_used + 3) & ~3u;
   const uint32_t *offs = (const uint32_t *)(rec + kHdr + sym_bytes);
-  const uint32_t w0 = offs[c], w1 = offs[c + 1];
-  if (w1 < w0 || w1 > n_words) {
-    fail(ctl, kFlagCorrupt, pass);
-    return;
-  }
   BitReader br;
-  br.w = offs + (nchunks + 1) + w0;
-  br.nw = w1 - w0;
-  br.wi = 0;
-  br.buf = 0;
-  br.nbits = 0;
-  br.refill();
-  const uint64_t B = 1ull << g.chunk_log2;
-  const double k = kscale[slice];
-  double *out = sl.ws + (uint64_t)u * 2 * g.L + (uint64_t)c * B;
-  int64_t p = 0;
-  for (uint64_t j = 0; j < B; j++) {
-    if (br.nbits < kLMax) br.refill();
-    uint32_t e = dtab[(uint32_t)(br.buf >> (64 - kLMax))];
-    uint32_t sym = e & 1023u, len = e >> 10;
-    br.buf <<= len;
-    br.nbits -= (int)len;
-    int64_t d;
-    if (sym == 0) {
-      if (br.nbits < kEscBits) br.refill();
-      int nb = (int)br.take(kEscBits);
-      uint64_t z;
-      if (nb > 32) {
-        if (br.nbits < 32) br.refill();
-        uint64_t hi = br.take(nb - 32);
-        if (br.nbits < 32) br.refill();
-        z = (hi << 32) | br.take(32);
-      } else {
-        if (br.nbits < nb) br.refill();
-        z = br.take(nb);
-      }
-      d = unzigzag(z);
+  uint32_t w0 = 0, nw = 0;
+  if (active) {
+    w0 = offs[c];
+    const uint32_t w1 = offs[c + 1];
+    if (w1 < w0 || w1 > n_words) {
+      fail(ctl, kFlagCorrupt, pass);
+      w0 = 0;
     } else {
-      d = (int64_t)sym - kR;
+      nw = w1 - w0;
     }
-    p += d;
-    out[j] = (double)p * k;
+  }
+  br.start(offs + (nchunks + 1) + w0, nw);
+  br.refill();
+  __syncthreads();
+  const uint64_t B = 1ull << g.chunk_log2;
+  const uint32_t R = B < (uint64_t)kDecRow ? (uint32_t)B : (uint32_t)kDecRow;
+  const double k = kscale[slice];
+  double *out = sl.ws + (uint64_t)u * 2 * g.L;
+  double p = 0.0;  // running integer sum, exact in FP64 below 2^53
+  for (uint64_t j0 = 0; j0 < B; j0 += R) {
+    if (active) {
+      for (uint32_t q = 0; q < R; q++) {
+        if (br.nbits < kLMax) br.refill();
+        uint32_t e = dtab[(uint32_t)(br.buf >> (64 - kLMax))];
+        uint32_t sym = e & 1023u, len = e >> 10;
+        br.buf <<= len;
+        br.nbits -= (int)len;
+        double d;
+        if (sym == 0) {
+          if (br.nbits < kEscBits) br.refill();
+          int nb = (int)br.take(kEscBits);
+          uint64_t z;
+          if (nb > 32) {
+            if (br.nbits < 32) br.refill();
+            uint64_t hi = br.take(nb - 32);
+            if (br.nbits < 32) br.refill();
+            z = (hi << 32) | br.take(32);
+          } else {
+            if (br.nbits < nb) br.refill();
+            z = br.take(nb);
+          }
+          d = (double)unzigzag(z);
+        } else {
+          d = (double)((int)sym - kR);
+        }
+        p += d;
+        stg[lane * kDecPitch + q] = p * k;
+      }
+    }
+    lds_sync();
+    for (uint32_t idx = lane; idx < kDecLanes * R; idx += kDecLanes) {
+      const uint32_t row = idx / R, col = idx % R;
+      if (c0 + row < nchunks) out[(uint64_t)(c0 + row) * B + j0 + col] = stg[row * kDecPitch + col];
+    }
+    lds_sync();
   }
 }
 
 // ------------------------------------------------------------ gate + quantise
 
 // Output amplitude (re, im) of the gate at slot u, offset o.
+// KIND: 0 identity, 1 dense on one target, 2 phase, 3 dense on 2..5 targets.
+template <int KIND>
 __device__ __forceinline__ void eval_amp(const double *__restrict__ ws, const Geo &g, const uint64_t *slot_slice,
                                          const GateDesc &gd, uint32_t u, uint64_t o, double &re, double &im) {
   const uint64_t twoL = 2 * g.L;
   const double *w = ws + (uint64_t)u * twoL;
-  if (gd.kind == 0) {
+  if (KIND == 0) {
     re = w[o];
     im = w[g.L + o];
     return;
@@ -378,7 +400,7 @@ __device__ __forceinline__ void eval_amp(const double *__restrict__ ws, const Ge
     im = w[g.L + o];
     return;
   }
-  if (gd.kind == 2) {
+  if (KIND == 2) {
     double cr = 0.0, ci = 0.0;
     cmac(gd.ph_re, gd.ph_im, w[o], w[g.L + o], cr, ci);
     re = cr;
@@ -388,6 +410,22 @@ __device__ __forceinline__ void eval_amp(const double *__restrict__ ws, const Ge
   const uint32_t mm = (1u << gd.m) - 1u;
   const uint32_t gbase = u & ~mm;
   const uint64_t gl = ((uint64_t)(u & mm) << g.slice_log2) | o;
+  if (KIND == 1) {
+    const int t = gd.tloc[0];
+    const uint64_t g0 = gl & ~(1ull << t), g1 = g0 | (1ull << t);
+    const double *w0 = ws + (uint64_t)(gbase + (uint32_t)(g0 >> g.slice_log2)) * twoL;
+    const double *w1 = ws + (uint64_t)(gbase + (uint32_t)(g1 >> g.slice_log2)) * twoL;
+    const uint64_t o0 = g0 & (g.L - 1), o1 = g1 & (g.L - 1);
+    const bool row = (gl >> t) & 1;
+    const double u0r = row ? gd.m2[4] : gd.m2[0], u0i = row ? gd.m2[5] : gd.m2[1];
+    const double u1r = row ? gd.m2[6] : gd.m2[2], u1i = row ? gd.m2[7] : gd.m2[3];
+    double cr = 0.0, ci = 0.0;
+    cmac(u0r, u0i, w0[o0], w0[g.L + o0], cr, ci);
+    cmac(u1r, u1i, w1[o1], w1[g.L + o1], cr, ci);
+    re = cr;
+    im = ci;
+    return;
+  }
   int row = 0;
   for (int t = 0; t < gd.k; t++) row |= (int)((gl >> gd.tloc[t]) & 1) << t;
   const uint64_t bl = gl & ~gd.tmask_loc;
@@ -404,16 +442,17 @@ __device__ __forceinline__ void eval_amp(const double *__restrict__ ws, const Ge
   im = ci;
 }
 
-__device__ __forceinline__ bool quantise(double v, double step, double recip, double ebj, int64_t &p, double &err) {
+// q = rint(v / step) as an integer-valued double; false if |q| >= 2^48 or
+// the reconstruction q * step misses v by more than the bound.
+__device__ __forceinline__ bool quantise(double v, double step, double recip, double ebj, double &q, double &err) {
   double t = v * recip;
-  double q = rint(t);
+  q = rint(t);
   if (!(fabs(q) < kPMax)) {
-    p = 0;
+    q = 0.0;
     err = 0.0;
     return false;
   }
-  p = (int64_t)q;
-  double back = (double)p * step;
+  double back = q * step;
   err = fabs(v - back);
   return err <= ebj;
 }
@@ -421,6 +460,7 @@ __device__ __forceinline__ bool quantise(double v, double step, double recip, do
 // relative bound: min/max of the gate's output over every slot.  Workgroups
 // are whole wavefronts; a workgroup covers C = min(blockDim, L) amplitudes of
 // one slot and threads past C only take part in the reductions.
+template <int KIND>
 __global__ void __launch_bounds__(256) k_gate_minmax(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
                                                      const Ctl *ctl) {
   if (ctl->flags) return;
@@ -430,7 +470,7 @@ __global__ void __launch_bounds__(256) k_gate_minmax(Slots sl, Geo g, const uint
   uint64_t kmin = ~0ull, kmax = 0ull;
   if (threadIdx.x < C) {
     double re, im;
-    eval_amp(sl.ws, g, slot_slice, gd, u, i & (g.L - 1), re, im);
+    eval_amp<KIND>(sl.ws, g, slot_slice, gd, u, i & (g.L - 1), re, im);
     kmin = dkey(re) < dkey(im) ? dkey(re) : dkey(im);
     kmax = dkey(re) < dkey(im) ? dkey(im) : dkey(re);
   }
@@ -462,6 +502,8 @@ __global__ void k_rel_step(Slots sl, int nslots, double rel, const Ctl *ctl) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= nslots) return;
   double lo = dkey_inv(sl.minmax[2 * u]), hi = dkey_inv(sl.minmax[2 * u + 1]);
+  sl.minmax[2 * u] = ~0ull;  // consumed
+  sl.minmax[2 * u + 1] = 0ull;
   double range = hi - lo;
   double m = fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi);
   double fl = m * 0x1p-24;
@@ -478,170 +520,381 @@ __global__ void k_rel_step(Slots sl, int nslots, double rel, const Ctl *ctl) {
   sl.qstep[3 * u + 2] = e;
 }
 
+// Sum of q^2 over a thread's integer-valued doubles |q| < 2^48, added to a
+// 128-bit (lo, hi) sum.  When every value of the wavefront is below 2^31 the
+// squares come from 32-bit multiplies; otherwise from 64-bit ones.
 template <int V>
-__global__ void __launch_bounds__(256) k_gate_quant(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
-                                                    QuantParams qp, Ctl *ctl, uint32_t pass) {
-  if (ctl->flags) return;
-  __shared__ uint32_t h[kNSym];
-  __shared__ int64_t last[2][256];
-  __shared__ uint64_t wsq[4][2];
-  __shared__ uint64_t werr[4];
-  __shared__ uint32_t nesc_sh;
-  __shared__ uint32_t bad_sh;
-  const uint32_t tid = threadIdx.x;
-  for (uint32_t s = tid; s < (uint32_t)kNSym; s += blockDim.x) h[s] = 0;
-  if (tid == 0) {
-    nesc_sh = 0;
-    bad_sh = 0;
-  }
-  // the workgroup (whole wavefronts) covers C = min(blockDim * V, L)
-  // consecutive amplitudes of one slot; threads past C only take part in
-  // the reductions
-  const uint64_t C = (uint64_t)blockDim.x * V < g.L ? (uint64_t)blockDim.x * V : g.L;
-  const uint64_t flat0 = (uint64_t)blockIdx.x * C;
-  const uint32_t u = (uint32_t)(flat0 >> g.slice_log2);
-  const bool active = (uint64_t)tid * V < C;
-  const uint64_t o0 = (flat0 & (g.L - 1)) + (active ? (uint64_t)tid * V : 0);
-  const uint64_t Bm = (1ull << g.chunk_log2) - 1;
-  double step = qp.step, recip = qp.recip, ebj = qp.eb;
-  if (qp.rel) {
-    step = sl.qstep[3 * u];
-    recip = sl.qstep[3 * u + 1];
-    ebj = sl.qstep[3 * u + 2];
-  }
-  int64_t pr[V], pim[V];
-  double emax = 0.0;
-  bool ok = true;
+__device__ __forceinline__ void add_squares(const double (&qr)[V], const double (&qi)[V], uint64_t &lo,
+                                            uint64_t &hi) {
+  bool small = true;
 #pragma unroll
-  for (int v = 0; v < V; v++) {
-    pr[v] = 0;
-    pim[v] = 0;
-    if (active) {
-      double re, im, e1, e2;
-      eval_amp(sl.ws, g, slot_slice, gd, u, o0 + v, re, im);
-      ok &= quantise(re, step, recip, ebj, pr[v], e1);
-      ok &= quantise(im, step, recip, ebj, pim[v], e2);
-      emax = fmax(emax, fmax(e1, e2));
-    }
-  }
-  last[0][tid] = pr[V - 1];
-  last[1][tid] = pim[V - 1];
-  __syncthreads();
-  int64_t prev_r = 0, prev_i = 0;
-  if (active && (o0 & Bm) != 0) {
-    if (tid > 0) {
-      prev_r = last[0][tid - 1];
-      prev_i = last[1][tid - 1];
-    } else {
-      double re, im, e1, e2;
-      eval_amp(sl.ws, g, slot_slice, gd, u, o0 - 1, re, im);
-      quantise(re, step, recip, ebj, prev_r, e1);
-      quantise(im, step, recip, ebj, prev_i, e2);
-    }
-  }
-  uint16_t *sym_r = sl.sym + (uint64_t)u * 2 * g.L;
-  uint16_t *sym_i = sym_r + g.L;
-  int64_t *esc_r = sl.esc + (uint64_t)u * 2 * g.L;
-  int64_t *esc_i = esc_r + g.L;
-  uint32_t sr[V], si[V];
-  uint32_t nesc = 0;
-  uint64_t sq_lo = 0, sq_hi = 0;
-#pragma unroll
-  for (int v = 0; v < V; v++) {
-    sr[v] = si[v] = 0;
-    if (!active) continue;
-    const uint64_t o = o0 + v;
-    if ((o & Bm) == 0) {
-      prev_r = 0;
-      prev_i = 0;
-    }
-    int64_t dr = pr[v] - prev_r, di = pim[v] - prev_i;
-    prev_r = pr[v];
-    prev_i = pim[v];
-    bool er = !(dr > -kR && dr < kR), ei = !(di > -kR && di < kR);
-    sr[v] = er ? 0u : (uint32_t)(dr + kR);
-    si[v] = ei ? 0u : (uint32_t)(di + kR);
-    if (er) esc_r[o] = dr;
-    if (ei) esc_i[o] = di;
-    nesc += (uint32_t)er + (uint32_t)ei;
-    uint64_t a = (uint64_t)(pr[v] < 0 ? -pr[v] : pr[v]);
-    uint64_t b = (uint64_t)(pim[v] < 0 ? -pim[v] : pim[v]);
-    uint64_t l1 = a * a, h1 = __umul64hi(a, a), l2 = b * b, h2 = __umul64hi(b, b);
-    uint64_t t = sq_lo + l1;
-    sq_hi += h1 + (t < sq_lo);
-    sq_lo = t;
-    t = sq_lo + l2;
-    sq_hi += h2 + (t < sq_lo);
-    sq_lo = t;
-  }
-  // symbols out: V consecutive u16 per plane
-  if (active) {
+  for (int v = 0; v < V; v++) small &= (fabs(qr[v]) < 2147483648.0) & (fabs(qi[v]) < 2147483648.0);
+  if (__ballot(!small) == 0) {
 #pragma unroll
     for (int v = 0; v < V; v++) {
-      sym_r[o0 + v] = (uint16_t)sr[v];
-      sym_i[o0 + v] = (uint16_t)si[v];
+      const uint32_t a = (uint32_t)abs((int)qr[v]), b = (uint32_t)abs((int)qi[v]);
+      const uint64_t s = (uint64_t)a * a, t = (uint64_t)b * b;
+      uint64_t x = lo + s;
+      hi += x < lo;
+      lo = x + t;
+      hi += lo < x;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      const uint64_t a = (uint64_t)fabs(qr[v]), b = (uint64_t)fabs(qi[v]);
+      uint64_t x = lo + a * a;
+      hi += __umul64hi(a, a) + (x < lo);
+      lo = x + b * b;
+      hi += __umul64hi(b, b) + (lo < x);
     }
   }
-  // histogram: a wavefront whose values all share one symbol adds once
+}
+
+// Per-slot output pointers of gate_quant.
+struct SlotOut {
+  uint16_t *symr, *symi;
+  int64_t *escr, *esci;
+};
+
+__device__ __forceinline__ SlotOut slot_out(const Slots &sl, const Geo &g, uint32_t u) {
+  SlotOut t;
+  t.symr = sl.sym + (uint64_t)u * 2 * g.L;
+  t.symi = t.symr + g.L;
+  t.escr = sl.esc + (uint64_t)u * 2 * g.L;
+  t.esci = t.escr + g.L;
+  return t;
+}
+
+// Running sums of one thread over the tiles it handles.
+struct Acc {
+  uint64_t lo, hi;  // sum p^2
+  uint32_t nesc;
+  double emax;
+  bool ok;
+  __device__ __forceinline__ void zero() {
+    lo = hi = 0;
+    nesc = 0;
+    emax = 0.0;
+    ok = true;
+  }
+};
+
+// Symbols of one tile of C consecutive amplitudes from offset ob (a chunk
+// head: C is a multiple of the chunk length): Lorenzo differences inside
+// chunks -- the predecessor of tile element e = v * blockDim + tid comes
+// from the lane below, or across a wavefront boundary through LDS --,
+// symbols, escapes, the LDS histogram h and the running sums.
+template <int V, bool FULL>
+__device__ __forceinline__ void tile_symbols(const double (&qr)[V], const double (&qi)[V], uint32_t *h,
+                                             double (*bnd)[V][4], const Geo &g, const SlotOut &so, uint32_t ob,
+                                             uint32_t C, Acc &acc) {
+  const uint32_t tid = threadIdx.x, T = blockDim.x, lane = lane_id(), wave = tid >> 6, nwv = T >> 6;
+  const uint32_t Bm = (1u << g.chunk_log2) - 1;
+  if (lane == 63) {
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      bnd[0][v][wave] = qr[v];
+      bnd[1][v][wave] = qi[v];
+    }
+  }
+  lds_sync();
+  uint32_t sr[V], si[V];
+  uint32_t nval = 0;
   bool uni = true;
 #pragma unroll
-  for (int v = 0; v < V; v++) uni &= (sr[v] == sr[0]) & (si[v] == sr[0]);
+  for (int v = 0; v < V; v++) {
+    const uint32_t e = v * T + tid;
+    const double up_r = __shfl_up(qr[v], 1, 64), up_i = __shfl_up(qi[v], 1, 64);
+    sr[v] = si[v] = 0;
+    if (!FULL && e >= C) continue;
+    const uint32_t o = ob + e;
+    double pr = 0.0, pi = 0.0;  // predecessor in the chunk (0 at a chunk head)
+    if ((o & Bm) != 0) {
+      if (lane > 0) {
+        pr = up_r;
+        pi = up_i;
+      } else if (wave > 0) {
+        pr = bnd[0][v][wave - 1];
+        pi = bnd[1][v][wave - 1];
+      } else {  // e > 0 here: the tile starts at a chunk head
+        pr = bnd[0][v - 1][nwv - 1];
+        pi = bnd[1][v - 1][nwv - 1];
+      }
+    }
+    const double dr = qr[v] - pr, di = qi[v] - pi;  // exact: integers below 2^49
+    const bool er = !(fabs(dr) < (double)kR), ei = !(fabs(di) < (double)kR);
+    sr[v] = er ? 0u : (uint32_t)((int)dr + kR);
+    si[v] = ei ? 0u : (uint32_t)((int)di + kR);
+    if (er) so.escr[o] = (int64_t)dr;
+    if (ei) so.esci[o] = (int64_t)di;
+    acc.nesc += (uint32_t)er + (uint32_t)ei;
+    so.symr[o] = (uint16_t)sr[v];
+    so.symi[o] = (uint16_t)si[v];
+    uni &= (sr[v] == sr[0]) & (si[v] == sr[0]);
+    nval += 2;
+  }
+  add_squares<V>(qr, qi, acc.lo, acc.hi);  // values past C are zero
+  // histogram: a wavefront whose values all share one symbol adds once
+  const bool any = nval != 0;
   const uint32_t s0 = (uint32_t)__shfl((int)sr[0], 0, 64);
-  const uint64_t act = __ballot(active);
-  const bool wave_uni = __ballot(active && uni && sr[0] == s0) == act;
+  const uint64_t act = __ballot(any);
+  const bool wave_uni = __ballot(any && uni && sr[0] == s0) == act;
   if (wave_uni) {
-    if (lane_id() == 0 && act) atomicAdd(&h[s0], (uint32_t)(2 * V * __popcll(act)));
-  } else if (active) {
+    uint32_t cnt;
+    if (FULL) {
+      cnt = 2u * V * (uint32_t)__popcll(act);
+    } else {
+      cnt = nval;
+      for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    }
+    if (lane == 0 && cnt) atomicAdd(&h[s0], cnt);
+  } else if (any) {
     uint32_t cs = sr[0], cn = 0;
 #pragma unroll
     for (int v = 0; v < V; v++) {
+      if (!FULL && v * T + tid >= C) break;
       if (sr[v] != cs) { atomicAdd(&h[cs], cn); cs = sr[v]; cn = 0; }
       cn++;
-    }
-#pragma unroll
-    for (int v = 0; v < V; v++) {
       if (si[v] != cs) { atomicAdd(&h[cs], cn); cs = si[v]; cn = 0; }
       cn++;
     }
     atomicAdd(&h[cs], cn);
   }
-  // wavefront reductions of sum p^2, max error, escapes
+  lds_sync();  // bnd is reused by the next tile
+}
+
+// Reduce the workgroup's sums and write them, with the LDS histogram h (then
+// cleared), to partial result `pidx` of slot u.
+__device__ __forceinline__ void write_partial(Acc &acc, uint32_t *h, uint64_t (*wred)[4], const Slots &sl,
+                                              uint32_t u, uint32_t pidx, Ctl *ctl, uint32_t pass) {
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nwv = blockDim.x >> 6;
+  uint64_t lo = acc.lo, hi = acc.hi, ne = acc.nesc;
+  double em = acc.emax;
   for (int off = 32; off > 0; off >>= 1) {
-    uint64_t ol = __shfl_xor(sq_lo, off, 64), oh = __shfl_xor(sq_hi, off, 64);
-    uint64_t t = sq_lo + ol;
-    sq_hi += oh + (t < sq_lo);
-    sq_lo = t;
-    emax = fmax(emax, __shfl_xor(emax, off, 64));
+    uint64_t ol = __shfl_xor(lo, off, 64), oh = __shfl_xor(hi, off, 64);
+    uint64_t t = lo + ol;
+    hi += oh + (t < lo);
+    lo = t;
+    em = fmax(em, __shfl_xor(em, off, 64));
+    ne += __shfl_xor(ne, off, 64);
   }
-  if (nesc) atomicAdd(&nesc_sh, nesc);
-  if (!ok) atomicOr(&bad_sh, 1u);
-  const uint32_t wave = tid >> 6;
-  if (lane_id() == 0) {
-    wsq[wave][0] = sq_lo;
-    wsq[wave][1] = sq_hi;
-    werr[wave] = (uint64_t)__double_as_longlong(emax);
+  if (lane == 0) {
+    wred[wave][0] = lo;
+    wred[wave][1] = hi;
+    wred[wave][2] = ne;
+    wred[wave][3] = (uint64_t)__double_as_longlong(em);
+  }
+  if (__ballot(!acc.ok) && lane == 0) fail(ctl, kFlagBound, pass);
+  __syncthreads();
+  if (pidx >= kGqParts) return;  // launches never exceed the partial count
+  uint32_t *hp = sl.hpart + ((uint64_t)u * kGqParts + pidx) * kNSym;
+  for (uint32_t s = tid; s < (uint32_t)kNSym; s += blockDim.x) {
+    hp[s] = h[s];
+    h[s] = 0;
+  }
+  if (tid == 0) {
+    uint64_t l2 = wred[0][0], h2 = wred[0][1], n2 = wred[0][2], eb = wred[0][3];
+    for (uint32_t w = 1; w < nwv; w++) {
+      uint64_t t = l2 + wred[w][0];
+      h2 += wred[w][1] + (t < l2);
+      l2 = t;
+      n2 += wred[w][2];
+      eb = wred[w][3] > eb ? wred[w][3] : eb;
+    }
+    uint64_t *pp = sl.part + ((uint64_t)u * kGqParts + pidx) * 4;
+    pp[0] = l2;
+    pp[1] = h2;
+    pp[2] = n2;
+    pp[3] = eb;
   }
   __syncthreads();
-  for (uint32_t s = tid; s < (uint32_t)kNSym; s += blockDim.x)
-    if (h[s]) atomicAdd(&sl.hist[(uint64_t)u * kNSym + s], h[s]);
-  if (tid == 0) {
-    uint64_t lo = wsq[0][0], hi = wsq[0][1], eb = werr[0];
-    for (uint32_t w = 1; w < blockDim.x / 64; w++) {
-      uint64_t t = lo + wsq[w][0];
-      hi += wsq[w][1] + (t < lo);
-      lo = t;
-      eb = werr[w] > eb ? werr[w] : eb;
-    }
-    unsigned long long old = atomicAdd((unsigned long long *)&sl.sq[2 * u], (unsigned long long)lo);
-    if (old + lo < old) hi += 1;
-    atomicAdd((unsigned long long *)&sl.sq[2 * u + 1], (unsigned long long)hi);
-    atomicMax((unsigned long long *)&ctl->max_err_bits, (unsigned long long)eb);
-    if (nesc_sh) {
-      atomicAdd(&sl.nesc[u], nesc_sh);
-      atomicAdd((unsigned long long *)&ctl->escapes, (unsigned long long)nesc_sh);
-    }
-    if (bad_sh) fail(ctl, kFlagBound, pass);
+}
+
+__device__ __forceinline__ void slot_quant(const Slots &sl, const QuantParams &qp, uint32_t u, double &step,
+                                           double &recip, double &ebj) {
+  step = qp.step;
+  recip = qp.recip;
+  ebj = qp.eb;
+  if (qp.rel) {
+    step = sl.qstep[3 * u];
+    recip = sl.qstep[3 * u + 1];
+    ebj = sl.qstep[3 * u + 2];
   }
+}
+
+// gate_quant: workgroup (x, u) takes tiles x, x + G, ... of slot u, each of C
+// = min(256 V, L) consecutive amplitudes; tile element e = v * blockDim + tid
+// belongs to thread tid, so every load and store instruction is contiguous
+// across the wavefront.  The LDS histogram and the sums run over all the
+// workgroup's tiles and leave once, as partial result x of the slot.
+// KIND 0: identity; 1: one target inside the tile (partner through the
+// cache); 2: phase; 3: dense on several targets (general indexing).
+template <int KIND, int V, bool FULL>
+__global__ void __launch_bounds__(256, 2) k_gate_quant(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
+                                                       QuantParams qp, Ctl *ctl, uint32_t pass) {
+  if (ctl->flags) return;
+  __shared__ uint32_t h[kNSym];
+  __shared__ double bnd[2][V][4];
+  __shared__ uint64_t wred[4][4];
+  const uint32_t tid = threadIdx.x, T = FULL ? 256u : blockDim.x;
+  for (uint32_t s = tid; s < (uint32_t)kNSym; s += T) h[s] = 0;
+  const uint32_t C = FULL ? 256u * V : (uint32_t)((uint64_t)T * V < g.L ? (uint64_t)T * V : g.L);
+  const uint32_t u = blockIdx.y, G = gridDim.x;
+  const uint32_t ntiles = (uint32_t)(g.L / C);
+  const double *wre = sl.ws + (uint64_t)u * 2 * g.L, *wim = wre + g.L;
+  const SlotOut so = slot_out(sl, g, u);
+  // controls: slice-index bits are uniform, offset bits are checked per lane
+  const uint64_t gi_hi = slot_slice[u] << g.slice_log2;
+  const uint64_t mask_hi = gd.ctrl_mask & ~(g.L - 1);
+  const bool hi_ok = (gi_hi & mask_hi) == (gd.ctrl_vals & mask_hi);
+  const uint32_t mask_lo = (uint32_t)(gd.ctrl_mask & (g.L - 1)), vals_lo = (uint32_t)(gd.ctrl_vals & (g.L - 1));
+  const uint32_t bit = KIND == 1 ? 1u << gd.tloc[0] : 0u;
+  double step, recip, ebj;
+  slot_quant(sl, qp, u, step, recip, ebj);
+  Acc acc;
+  acc.zero();
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += G) {
+    const uint32_t ob = tile * C;
+    double ar[V], ai[V], br[V], bi[V];  // own amplitude; partner (one-target gates)
+    // all loads first (whole tiles need no bounds checks), then arithmetic
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      const uint32_t e = v * T + tid;
+      ar[v] = ai[v] = br[v] = bi[v] = 0.0;
+      if (KIND != 3 && (FULL || e < C)) {
+        ar[v] = wre[ob + e];
+        ai[v] = wim[ob + e];
+        if (KIND == 1) {
+          br[v] = wre[(ob + e) ^ bit];
+          bi[v] = wim[(ob + e) ^ bit];
+        }
+      }
+    }
+    double qr[V], qi[V];
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      const uint32_t e = v * T + tid;
+      qr[v] = qi[v] = 0.0;
+      if (!FULL && e >= C) continue;
+      const uint32_t o = ob + e;
+      double re = ar[v], im = ai[v];
+      if (KIND == 3) {
+        eval_amp<3>(sl.ws, g, slot_slice, gd, u, o, re, im);
+      } else {
+        const bool on = hi_ok && (o & mask_lo) == vals_lo;
+        if (KIND == 2 && on) {
+          cmul(gd.ph_re, gd.ph_im, ar[v], ai[v], re, im);
+        } else if (KIND == 1 && on) {
+          // column 0 is the amplitude with the target bit clear
+          const bool row = (o & bit) != 0;
+          const double a0r = row ? br[v] : ar[v], a0i = row ? bi[v] : ai[v];
+          const double a1r = row ? ar[v] : br[v], a1i = row ? ai[v] : bi[v];
+          const double u0r = row ? gd.m2[4] : gd.m2[0], u0i = row ? gd.m2[5] : gd.m2[1];
+          const double u1r = row ? gd.m2[6] : gd.m2[2], u1i = row ? gd.m2[7] : gd.m2[3];
+          double cr, ci;
+          cmul(u0r, u0i, a0r, a0i, cr, ci);
+          cmac(u1r, u1i, a1r, a1i, cr, ci);
+          re = cr;
+          im = ci;
+        }
+      }
+      double e1, e2;
+      acc.ok &= quantise(re, step, recip, ebj, qr[v], e1);
+      acc.ok &= quantise(im, step, recip, ebj, qi[v], e2);
+      acc.emax = fmax(acc.emax, fmax(e1, e2));
+    }
+    tile_symbols<V, FULL>(qr, qi, h, bnd, g, so, ob, C, acc);
+  }
+  write_partial(acc, h, wred, sl, u, blockIdx.x, ctl, pass);
+}
+
+// A one-target gate whose partner lies in another tile (target bit t at or
+// above the tile size): a workgroup takes both tiles of a pair, so every
+// amplitude is read once.  In the batch's flat index (slot * L + offset) the
+// partner of amplitude f is f ^ 2^t.  Slice-index targets pair slot uA (bit
+// clear) with uB = uA + 2^(t - slice_log2), tile for tile; in-slice targets
+// pair tiles of one slot.  Results go to partials x (tile A) and G + x (tile B).
+template <int V>
+__global__ void __launch_bounds__(256, 2) k_gate_quant_pair(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
+                                                            QuantParams qp, Ctl *ctl, uint32_t pass) {
+  if (ctl->flags) return;
+  __shared__ uint32_t hA[kNSym], hB[kNSym];
+  __shared__ double bnd[2][V][4];
+  __shared__ uint64_t wred[4][4];
+  const uint32_t tid = threadIdx.x, T = 256;
+  for (uint32_t s = tid; s < (uint32_t)kNSym; s += T) hA[s] = hB[s] = 0;
+  const uint32_t C = T * V;  // pairs are only formed when L >= C
+  const uint32_t ntiles = (uint32_t)(g.L / C);
+  const int t = gd.tloc[0];
+  const bool cross = t >= g.slice_log2;
+  uint32_t uA, uB, npairs;
+  int b = 0;
+  if (cross) {
+    const uint32_t sb = t - g.slice_log2, y = blockIdx.y;
+    uA = ((y >> sb) << (sb + 1)) | (y & ((1u << sb) - 1));
+    uB = uA | (1u << sb);
+    npairs = ntiles;
+  } else {
+    uA = uB = blockIdx.y;
+    b = t - (31 - __clz((int)C));
+    npairs = ntiles / 2;
+  }
+  const double *aRe = sl.ws + (uint64_t)uA * 2 * g.L, *aIm = aRe + g.L;
+  const double *bRe = sl.ws + (uint64_t)uB * 2 * g.L, *bIm = bRe + g.L;
+  const SlotOut soA = slot_out(sl, g, uA), soB = slot_out(sl, g, uB);
+  // controls never include the target bit: A's index decides for the pair
+  const uint64_t gi_hi = slot_slice[uA] << g.slice_log2;
+  const uint64_t mask_hi = gd.ctrl_mask & ~(g.L - 1);
+  const bool hi_ok = (gi_hi & mask_hi) == (gd.ctrl_vals & mask_hi);
+  const uint32_t mask_lo = (uint32_t)(gd.ctrl_mask & (g.L - 1)), vals_lo = (uint32_t)(gd.ctrl_vals & (g.L - 1));
+  double sa, ra, ba, sb2, rb, bb;
+  slot_quant(sl, qp, uA, sa, ra, ba);
+  slot_quant(sl, qp, uB, sb2, rb, bb);
+  Acc accA, accB;
+  accA.zero();
+  accB.zero();
+  for (uint32_t w = blockIdx.x; w < npairs; w += gridDim.x) {
+    uint32_t tA = w, tB = w;
+    if (!cross) {
+      tA = ((w >> b) << (b + 1)) | (w & ((1u << b) - 1));
+      tB = tA | (1u << b);
+    }
+    const uint32_t obA = tA * C, obB = tB * C;
+    double x0r[V], x0i[V], x1r[V], x1i[V];
+#pragma unroll
+    for (int v = 0; v < V; v++) {  // all loads first
+      const uint32_t e = v * T + tid;
+      x0r[v] = aRe[obA + e];
+      x0i[v] = aIm[obA + e];
+      x1r[v] = bRe[obB + e];
+      x1i[v] = bIm[obB + e];
+    }
+    double qar[V], qai[V], qbr[V], qbi[V];
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      const uint32_t e = v * T + tid;
+      const double a0r = x0r[v], a0i = x0i[v], a1r = x1r[v], a1i = x1i[v];
+      double outAr = a0r, outAi = a0i, outBr = a1r, outBi = a1i;
+      if (hi_ok && ((obA + e) & mask_lo) == vals_lo) {
+        cmul(gd.m2[0], gd.m2[1], a0r, a0i, outAr, outAi);
+        cmac(gd.m2[2], gd.m2[3], a1r, a1i, outAr, outAi);
+        cmul(gd.m2[4], gd.m2[5], a0r, a0i, outBr, outBi);
+        cmac(gd.m2[6], gd.m2[7], a1r, a1i, outBr, outBi);
+      }
+      double e1, e2;
+      accA.ok &= quantise(outAr, sa, ra, ba, qar[v], e1);
+      accA.ok &= quantise(outAi, sa, ra, ba, qai[v], e2);
+      accA.emax = fmax(accA.emax, fmax(e1, e2));
+      accB.ok &= quantise(outBr, sb2, rb, bb, qbr[v], e1);
+      accB.ok &= quantise(outBi, sb2, rb, bb, qbi[v], e2);
+      accB.emax = fmax(accB.emax, fmax(e1, e2));
+    }
+    tile_symbols<V, true>(qar, qai, hA, bnd, g, soA, obA, C, accA);
+    tile_symbols<V, true>(qbr, qbi, hB, bnd, g, soB, obB, C, accB);
+  }
+  write_partial(accA, hA, wred, sl, uA, blockIdx.x, ctl, pass);
+  write_partial(accB, hB, wred, sl, uB, gridDim.x + blockIdx.x, ctl, pass);
 }
 
 // ---------------------------------------------------------------- codebook
@@ -651,12 +904,15 @@ __global__ void __launch_bounds__(256) k_gate_quant(Slots sl, Geo g, const uint6
 // level l+1, a leaf first on equal weights.  The 2n-2 cheapest items of
 // level 1 are selected.  A selected prefix of m items at level l holds the
 // q_l lightest leaves and m - q_l packages, i.e. the first 2(m - q_l) items of
-// level l+1; a leaf of rank i gets the length #{l : i < q_l}.
+// level l+1; a leaf of rank i gets the length #{l : i < q_l}.  Canonical codes
+// are the left-aligned starts of intervals of size 2^(12 - len) that tile
+// [0, 4096) in (length, symbol) order; the same intervals fill the decoder
+// table of the new record.
 
-__device__ void bitonic_sort_1024(uint64_t *key) {
-  for (uint32_t k = 2; k <= 1024; k <<= 1) {
+__device__ void bitonic_sort(uint64_t *key, uint32_t P) {
+  for (uint32_t k = 2; k <= P; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t p = threadIdx.x; p < 512; p += blockDim.x) {
+      for (uint32_t p = threadIdx.x; p < P / 2; p += blockDim.x) {
         uint32_t i = (p / j) * 2 * j + (p % j);
         uint32_t ixj = i + j;
         bool asc = (i & k) == 0;
@@ -671,31 +927,102 @@ __device__ void bitonic_sort_1024(uint64_t *key) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_codebook(Slots sl, const Ctl *ctl) {
+__global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot_slice, StateMeta nxt,
+                                                  Ctl *ctl) {
   if (ctl->flags) return;
   __shared__ uint64_t key[kNSym];
   __shared__ uint32_t wgt[kNSym];
   __shared__ uint32_t LA[2 * kNSym], LB[2 * kNSym];
   __shared__ uint16_t LP[kLMax][kNSym];
   __shared__ uint8_t lens[kNSym];
+  __shared__ uint32_t lav[kNSym];
+  __shared__ uint16_t ent[kNSym];
   __shared__ uint32_t q[kLMax + 1];
   __shared__ uint32_t scratch[20];
+  __shared__ uint64_t s64[16];
   const uint32_t u = blockIdx.x, tid = threadIdx.x;
-  const uint32_t *hist = sl.hist + (uint64_t)u * kNSym;
-  uint32_t cnt = 0;
-  for (uint32_t s = tid; s < (uint32_t)kNSym; s += blockDim.x) {
-    uint32_t hv = hist[s];
-    key[s] = hv ? (((uint64_t)hv << 10) | s) : ~0ull;
-    lens[s] = 0;
-    cnt += hv ? 1u : 0u;
+  {  // sums of the gate_quant workgroups of this slot
+    uint64_t lo = 0, hi = 0, ne = 0, eb = 0;
+    uint64_t *pp = sl.part + (uint64_t)u * kGqParts * 4;
+    for (uint32_t i = tid; i < kGqParts; i += blockDim.x) {
+      uint64_t t = lo + pp[4 * i];
+      hi += pp[4 * i + 1] + (t < lo);
+      lo = t;
+      ne += pp[4 * i + 2];
+      eb = pp[4 * i + 3] > eb ? pp[4 * i + 3] : eb;
+      pp[4 * i] = pp[4 * i + 1] = pp[4 * i + 2] = pp[4 * i + 3] = 0;  // consumed
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      uint64_t ol = __shfl_xor(lo, off, 64), oh = __shfl_xor(hi, off, 64);
+      uint64_t t = lo + ol;
+      hi += oh + (t < lo);
+      lo = t;
+      ne += __shfl_xor(ne, off, 64);
+      uint64_t oe = __shfl_xor(eb, off, 64);
+      eb = oe > eb ? oe : eb;
+    }
+    if (lane_id() == 0) {
+      s64[4 * (tid >> 6)] = lo;
+      s64[4 * (tid >> 6) + 1] = hi;
+      s64[4 * (tid >> 6) + 2] = ne;
+      s64[4 * (tid >> 6) + 3] = eb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (uint32_t w = 1; w < blockDim.x / 64; w++) {
+        uint64_t t = lo + s64[4 * w];
+        hi += s64[4 * w + 1] + (t < lo);
+        lo = t;
+        ne += s64[4 * w + 2];
+        eb = s64[4 * w + 3] > eb ? s64[4 * w + 3] : eb;
+      }
+      sl.sq[2 * u] = lo;
+      sl.sq[2 * u + 1] = hi;
+      sl.nesc[u] = (uint32_t)ne;
+      atomicMax((unsigned long long *)&ctl->max_err_bits, (unsigned long long)eb);
+      if (ne) atomicAdd((unsigned long long *)&ctl->escapes, (unsigned long long)ne);
+    }
+  }
+  // used symbols, compacted in symbol order (4 consecutive symbols per thread)
+  uint32_t hv[4], cnt = 0;
+  {  // histogram = sum of the partial histograms (cleared after reading)
+    uint4 acc4 = make_uint4(0, 0, 0, 0);
+    uint32_t *hp = sl.hpart + (uint64_t)u * kGqParts * kNSym;
+    for (uint32_t pi = 0; pi < kGqParts; pi++) {
+      uint4 *q4 = (uint4 *)(hp + (uint64_t)pi * kNSym) + tid;
+      const uint4 x = *q4;
+      acc4.x += x.x;
+      acc4.y += x.y;
+      acc4.z += x.z;
+      acc4.w += x.w;
+      if (x.x | x.y | x.z | x.w) *q4 = make_uint4(0, 0, 0, 0);
+    }
+    hv[0] = acc4.x;
+    hv[1] = acc4.y;
+    hv[2] = acc4.z;
+    hv[3] = acc4.w;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    cnt += hv[k] ? 1u : 0u;
+    lens[tid * 4 + k] = 0;
   }
   uint32_t n;
-  block_excl_scan(cnt, scratch, &n);
-  bitonic_sort_1024(key);
+  uint32_t pos = block_excl_scan(cnt, scratch, &n);
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const uint32_t s = tid * 4 + k;
+    if (hv[k]) key[pos++] = ((uint64_t)hv[k] << 10) | s;
+  }
+  uint32_t P = 1;
+  while (P < n) P <<= 1;
+  for (uint32_t i = n + tid; i < P; i += blockDim.x) key[i] = ~0ull;
+  __syncthreads();
+  bitonic_sort(key, P);
   for (uint32_t i = tid; i < n; i += blockDim.x) wgt[i] = (uint32_t)(key[i] >> 10);
   __syncthreads();
   if (n >= 2) {
-    uint32_t *cur = LA, *nxt = LB;
+    uint32_t *cur = LA, *nx = LB;
     for (uint32_t i = tid; i < n; i += blockDim.x) cur[i] = wgt[i];
     uint32_t len_cur = n;
     __syncthreads();
@@ -708,7 +1035,7 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const Ctl *ctl) {
           uint32_t mid = (lo + hi) >> 1;
           if (cur[2 * mid] + cur[2 * mid + 1] < wi) lo = mid + 1; else hi = mid;
         }
-        nxt[i + lo] = wi;
+        nx[i + lo] = wi;
         LP[l][i] = (uint16_t)(i + lo);
       }
       for (uint32_t k = tid; k < np; k += blockDim.x) {
@@ -718,12 +1045,12 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const Ctl *ctl) {
           uint32_t mid = (lo + hi) >> 1;
           if (wgt[mid] <= pv) lo = mid + 1; else hi = mid;
         }
-        nxt[k + lo] = pv;
+        nx[k + lo] = pv;
       }
       __syncthreads();
       uint32_t *t = cur;
-      cur = nxt;
-      nxt = t;
+      cur = nx;
+      nx = t;
       len_cur = n + np;
     }
     if (tid == 0) {
@@ -747,11 +1074,13 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const Ctl *ctl) {
     }
   }
   __syncthreads();
-  // canonical order (length, symbol); codes are the left-aligned interval
-  // starts shifted back: intervals of size 2^(12 - len) tile [0, 4096)
-  for (uint32_t s = tid; s < (uint32_t)kNSym; s += blockDim.x)
-    key[s] = hist[s] ? (((uint64_t)lens[s] << 10) | s) : ~0ull;
-  bitonic_sort_1024(key);
+  // canonical order (length, symbol)
+  for (uint32_t i = tid; i < n; i += blockDim.x) {
+    const uint32_t s = (uint32_t)(key[i] & 1023);
+    key[i] = ((uint64_t)lens[s] << 10) | s;
+  }
+  __syncthreads();
+  bitonic_sort(key, P);
   uint32_t sz[4], loc = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
@@ -772,162 +1101,31 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const Ctl *ctl) {
       uint32_t len = (uint32_t)(key[i] >> 10), sym = (uint32_t)(key[i] & 1023);
       uint32_t code = pre >> (kLMax - len);
       codes[sym] = (code << 8) | len;
-      tab[i] = (uint16_t)(sym | (len << 10));
+      const uint16_t e = (uint16_t)(sym | (len << 10));
+      tab[i] = e;
+      ent[i] = e;
+      lav[i] = pre;
     }
     pre += sz[k];
+  }
+  __syncthreads();
+  uint16_t *dt = nxt.dtab + slot_slice[u] * (1u << kLMax);
+  for (uint32_t e = tid; e < (1u << kLMax); e += blockDim.x) {
+    uint32_t lo = 0, hi = n;  // last entry whose interval starts at or before e
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (lav[mid] <= e) lo = mid; else hi = mid;
+    }
+    dt[e] = ent[lo];
   }
   if (tid == 0) sl.nused[u] = n;
 }
 
-// --------------------------------------------------------------- chunk bits
-
-__global__ void __launch_bounds__(256) k_chunkbits(Slots sl, Geo g, uint64_t total_chunks, const Ctl *ctl) {
-  if (ctl->flags) return;
-  const uint64_t cg = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (cg >= total_chunks) return;
-  const uint32_t u = (uint32_t)(cg / g.nchunks), c = (uint32_t)(cg % g.nchunks);
-  const uint64_t B = 1ull << g.chunk_log2;
-  const uint64_t base = (uint64_t)u * 2 * g.L + (uint64_t)c * B;
-  const uint32_t *codes = sl.codes + (uint64_t)u * kNSym;
-  uint64_t bits = 0;
-  for (uint64_t j = lane_id(); j < B; j += 64) {
-    uint32_t s = sl.sym[base + j];
-    bits += codes[s] & 0xffu;
-    if (s == 0) bits += kEscBits + bitlen64(zigzag(sl.esc[base + j]));
-  }
-  for (int off = 32; off > 0; off >>= 1) bits += __shfl_xor(bits, off, 64);
-  if (lane_id() == 0) {
-    uint32_t w = (uint32_t)((bits + 31) >> 5);
-    sl.chunk_words[(uint64_t)u * g.nchunks + c] = w;
-    atomicAdd(&sl.words[u], w);
-  }
-}
-
-// ------------------------------------------------------------------ layout
-
-__device__ __forceinline__ uint64_t rec_bytes(uint32_t n_used, uint32_t nchunks, uint32_t words) {
-  return (uint64_t)kHdr + ((2ull * n_used + 3) & ~3ull) + 4ull * (nchunks + 1) + 4ull * words;
-}
-
-__global__ void __launch_bounds__(1024) k_layout(Slots sl, Geo g, const uint64_t *slot_slice, int nslots,
-                                                 StateMeta nxt, uint64_t cap, Ctl *ctl, uint32_t pass) {
-  if (ctl->flags) return;
-  __shared__ unsigned long long tot_al, tot_ex;
-  __shared__ unsigned long long carry;
-  __shared__ unsigned long long wpart[16];
-  const uint32_t tid = threadIdx.x;
-  if (tid == 0) {
-    tot_al = 0;
-    tot_ex = 0;
-    carry = 0;
-  }
-  __syncthreads();
-  unsigned long long a = 0, e = 0;
-  for (int u = tid; u < nslots; u += blockDim.x) {
-    uint64_t b = rec_bytes(sl.nused[u], g.nchunks, sl.words[u]);
-    e += b;
-    a += (b + kRecAlign - 1) & ~(kRecAlign - 1);
-  }
-  atomicAdd(&tot_al, a);
-  atomicAdd(&tot_ex, e);
-  __syncthreads();
-  const uint64_t base = ctl->bump;
-  if (base + tot_al > cap) {
-    if (tid == 0) fail(ctl, kFlagOverflow, pass);
-    return;
-  }
-  // exclusive scan of aligned sizes in slot order, tile by tile
-  for (int t0 = 0; t0 < nslots; t0 += blockDim.x) {
-    const int u = t0 + (int)tid;
-    uint64_t b = 0, ba = 0;
-    if (u < nslots) {
-      b = rec_bytes(sl.nused[u], g.nchunks, sl.words[u]);
-      ba = (b + kRecAlign - 1) & ~(kRecAlign - 1);
-    }
-    uint64_t x = ba;
-    const uint32_t lane = lane_id(), wave = tid >> 6;
-    for (int off = 1; off < 64; off <<= 1) {
-      uint64_t y = __shfl_up(x, off, 64);
-      if (lane >= (uint32_t)off) x += y;
-    }
-    if (lane == 63) wpart[wave] = x;
-    __syncthreads();
-    uint64_t wpre = 0;
-    for (uint32_t w = 0; w < wave; w++) wpre += wpart[w];
-    const uint64_t excl = carry + wpre + x - ba;
-    if (u < nslots) {
-      const uint64_t slice = slot_slice[u];
-      nxt.rec_off[slice] = base + excl;
-      nxt.rec_len[slice] = (uint32_t)b;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      uint64_t s = 0;
-      for (uint32_t w = 0; w < (blockDim.x >> 6); w++) s += wpart[w];
-      carry += s;
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    ctl->bump = base + tot_al;
-    ctl->cur_bytes += tot_ex;
-  }
-}
-
-// ------------------------------------------------------------------ header
-
-__global__ void __launch_bounds__(256) k_header(Slots sl, Geo g, const uint64_t *slot_slice, QuantParams qp,
-                                                uint8_t *arena, StateMeta nxt, const Ctl *ctl) {
-  if (ctl->flags) return;
-  __shared__ uint32_t scratch[20];
-  __shared__ uint32_t carry;
-  const uint32_t u = blockIdx.x, tid = threadIdx.x;
-  const uint64_t slice = slot_slice[u];
-  uint8_t *rec = arena + nxt.rec_off[slice];
-  const uint32_t n_used = sl.nused[u], words = sl.words[u], nch = g.nchunks;
-  const double step = qp.rel ? sl.qstep[3 * u] : qp.step;
-  if (tid == 0) {
-    uint32_t *h32 = (uint32_t *)rec;
-    h32[0] = kMagic;
-    h32[1] = (uint32_t)g.slice_log2;
-    h32[2] = (uint32_t)g.chunk_log2;
-    h32[3] = n_used;
-    h32[4] = nch;
-    h32[5] = words;
-    h32[6] = sl.nesc[u];
-    h32[7] = (uint32_t)rec_bytes(n_used, nch, words);
-    *(double *)(rec + 32) = step;
-    *(uint64_t *)(rec + 40) = sl.sq[2 * u];
-    *(uint64_t *)(rec + 48) = sl.sq[2 * u + 1];
-    h32[14] = 0;
-    h32[15] = 0;
-    nxt.step[slice] = step;
-    nxt.sq[2 * slice] = sl.sq[2 * u];
-    nxt.sq[2 * slice + 1] = sl.sq[2 * u + 1];
-    carry = 0;
-  }
-  uint16_t *tab = (uint16_t *)(rec + kHdr);
-  for (uint32_t i = tid; i < n_used; i += blockDim.x) tab[i] = sl.symtab[(uint64_t)u * kNSym + i];
-  if (tid == 0 && (n_used & 1)) tab[n_used] = 0;
-  uint32_t *offs = (uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
-  const uint32_t *cw = sl.chunk_words + (uint64_t)u * nch;
-  __syncthreads();
-  for (uint32_t t0 = 0; t0 < nch; t0 += blockDim.x) {
-    uint32_t c = t0 + tid;
-    uint32_t x = c < nch ? cw[c] : 0u, tot;
-    uint32_t pre = block_excl_scan(x, scratch, &tot);
-    if (c < nch) offs[c] = carry + pre;
-    __syncthreads();
-    if (tid == 0) carry += tot;
-    __syncthreads();
-  }
-  if (tid == 0) offs[nch] = words;
-}
-
 // ------------------------------------------------------------------ encode
-// One wavefront per chunk: code lengths -> wavefront prefix sum -> bit
-// positions; codes are OR-ed into the chunk's words staged in LDS, which are
-// then written out with coalesced stores.
+// One wavefront per chunk, four consecutive symbols per lane per step: code
+// lengths -> wavefront prefix sum -> bit positions; a lane's codes are joined
+// into one 64-bit field and OR-ed into the chunk's words staged in LDS, which
+// then go to the chunk's fixed-size staging slot.
 
 __device__ __forceinline__ void put_bits(uint32_t *lw, uint64_t v, int n, uint64_t pos) {
   while (n > 0) {
@@ -941,59 +1139,223 @@ __device__ __forceinline__ void put_bits(uint32_t *lw, uint64_t v, int n, uint64
   }
 }
 
-__global__ void __launch_bounds__(256) k_encode(Slots sl, Geo g, const uint64_t *slot_slice, uint64_t total_chunks,
-                                                uint32_t lds_words, uint8_t *arena, StateMeta nxt, const Ctl *ctl) {
+constexpr int kEncWaves = 4;
+
+// Chunks [cb, ce) of slot blockIdx.y; wavefront w takes chunks cb + w, cb + w + 4,
+// ...; every wavefront runs the same number of rounds so barriers line up.
+__global__ void __launch_bounds__(256) k_encode(Slots sl, Geo g, uint32_t chunks_per_block, const Ctl *ctl) {
   if (ctl->flags) return;
   extern __shared__ uint32_t lw_all[];
+  __shared__ uint32_t codes[kNSym];
+  __shared__ uint32_t wsum[kEncWaves];
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
-  const uint64_t cg = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-  const bool active = cg < total_chunks;  // inactive wavefronts still meet the barriers
-  uint32_t *lw = lw_all + (uint64_t)wave * lds_words;
-  const uint32_t u = active ? (uint32_t)(cg / g.nchunks) : 0u;
-  const uint32_t c = active ? (uint32_t)(cg % g.nchunks) : 0u;
-  const uint64_t slice = slot_slice[u];
-  uint8_t *rec = arena + nxt.rec_off[slice];
-  const uint32_t n_used = sl.nused[u];
-  const uint32_t *offs = (const uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
-  const uint32_t w0 = active ? offs[c] : 0u;
-  const uint32_t nw = active ? offs[c + 1] - w0 : 0u;
-  uint32_t *out = (uint32_t *)(offs + g.nchunks + 1) + w0;
-  for (uint32_t i = lane; i < nw && i < lds_words; i += 64) lw[i] = 0;
+  const uint32_t u = blockIdx.y;
+  const uint32_t cb = blockIdx.x * chunks_per_block;
+  const uint32_t ce = cb + chunks_per_block < g.nchunks ? cb + chunks_per_block : g.nchunks;
+  const uint32_t W = sl.stage_words;
+  uint32_t *lw = lw_all + (uint64_t)wave * W;
+  for (uint32_t s = threadIdx.x; s < (uint32_t)kNSym; s += blockDim.x) codes[s] = sl.codes[(uint64_t)u * kNSym + s];
   __syncthreads();
-  const uint64_t B = active ? (1ull << g.chunk_log2) : 0;
-  const uint64_t base = (uint64_t)u * 2 * g.L + (uint64_t)c * (1ull << g.chunk_log2);
-  const uint32_t *codes = sl.codes + (uint64_t)u * kNSym;
-  uint64_t run = 0;
-  for (uint64_t j0 = 0; j0 < B; j0 += 64) {
-    const uint64_t j = j0 + lane;
-    uint32_t bl = 0, code = 0, len = 0, s = 1;
-    int nb = 0;
-    uint64_t z = 0;
-    if (j < B) {
-      s = sl.sym[base + j];
-      uint32_t cwv = codes[s];
-      len = cwv & 0xffu;
-      code = cwv >> 8;
-      bl = len;
-      if (s == 0) {
-        z = zigzag(sl.esc[base + j]);
-        nb = bitlen64(z);
-        bl += kEscBits + (uint32_t)nb;
+  const uint64_t Bc = 1ull << g.chunk_log2;
+  uint32_t words_here = 0;
+  const uint32_t rounds = (chunks_per_block + kEncWaves - 1) / kEncWaves;
+  for (uint32_t r = 0; r < rounds; r++) {  // the same count in every wavefront
+    const uint32_t c = cb + r * kEncWaves + wave;
+    const bool active = c < ce;
+    const uint64_t B = active ? Bc : 0;
+    const uint64_t base = (uint64_t)u * 2 * g.L + (uint64_t)(active ? c : 0) * Bc;
+    const uint16_t *sym = sl.sym + base;
+    const int64_t *esc = sl.esc + base;
+    uint64_t run = 0;
+    uint32_t zeroed = 0;  // words [0, zeroed) of lw are cleared for this chunk
+    for (uint64_t j0 = 0; j0 < B; j0 += 256) {
+      const uint64_t j = j0 + 4 * (uint64_t)lane;
+      uint32_t s[4], cw[4], bl = 0;
+      bool has_esc = false;
+      if (j + 3 < B) {  // four aligned symbols in one load
+        const uint2 v4 = *(const uint2 *)(sym + j);
+        s[0] = v4.x & 0xffffu;
+        s[1] = v4.x >> 16;
+        s[2] = v4.y & 0xffffu;
+        s[3] = v4.y >> 16;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) s[k] = j + k < B ? sym[j + k] : 1u;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        cw[k] = 0;
+        if (j + k < B) {
+          cw[k] = codes[s[k]];
+          bl += cw[k] & 0xffu;
+          if (s[k] == 0) {
+            has_esc = true;
+            bl += kEscBits + (uint32_t)bitlen64(zigzag(esc[j + k]));
+          }
+        }
+      }
+      const uint32_t inc = wave_incl_scan(bl);
+      const uint32_t tot = (uint32_t)__shfl((int)inc, 63, 64);
+      uint64_t pos = run + inc - bl;
+      uint32_t end = (uint32_t)((run + tot + 31) >> 5);
+      if (end > W) end = W;
+      for (uint32_t w = zeroed + lane; w < end; w += 64) lw[w] = 0;
+      zeroed = end > zeroed ? end : zeroed;
+      // LDS operations of one wavefront execute in issue order: a compiler
+      // barrier keeps the clearing stores ahead of the OR-ing below
+      __asm__ __volatile__("" ::: "memory");
+      run += tot;
+      if (pos + bl > 32ull * W) continue;  // cannot happen for a consistent codebook
+      if (!has_esc) {
+        uint64_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc = (acc << (cw[k] & 0xffu)) | (cw[k] >> 8);
+        put_bits(lw, acc, (int)bl, pos);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          if (j + k >= B) break;
+          const uint32_t len = cw[k] & 0xffu;
+          put_bits(lw, cw[k] >> 8, (int)len, pos);
+          pos += len;
+          if (s[k] == 0) {
+            const uint64_t z = zigzag(esc[j + k]);
+            const int nb = bitlen64(z);
+            put_bits(lw, (uint64_t)nb, kEscBits, pos);
+            put_bits(lw, z, nb, pos + kEscBits);
+            pos += kEscBits + nb;
+          }
+        }
       }
     }
-    const uint32_t inc = wave_incl_scan(bl);
-    const uint64_t pos = run + inc - bl;
-    run += (uint32_t)__shfl((int)inc, 63, 64);
-    if (j < B && pos + bl <= 32ull * (nw < lds_words ? nw : lds_words)) {
-      put_bits(lw, code, (int)len, pos);
-      if (s == 0) {
-        put_bits(lw, (uint64_t)nb, kEscBits, pos + len);
-        put_bits(lw, z, nb, pos + len + kEscBits);
-      }
+    lds_sync();
+    if (active) {
+      const uint32_t nw = (uint32_t)((run + 31) >> 5);
+      uint32_t *dst = sl.stage + ((uint64_t)u * g.nchunks + c) * W;
+      for (uint32_t i = lane; i < nw; i += 64) dst[i] = lw[i];
+      if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = nw;
+      words_here += nw;
+    }
+    lds_sync();
+  }
+  if (lane == 0) wsum[wave] = words_here;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kEncWaves; w++) t += wsum[w];
+    if (t) atomicAdd(&sl.words[u], t);
+  }
+}
+
+// ------------------------------------------------------------------ header
+// One workgroup per slot.  Every workgroup sizes all records of the batch
+// (slot order), so it knows its record's offset and the batch total; the
+// total must fit the arena or the pass fails with an overflow flag.
+
+__global__ void __launch_bounds__(256) k_header(Slots sl, Geo g, const uint64_t *slot_slice, int nslots,
+                                                QuantParams qp, uint8_t *arena, uint64_t cap, StateMeta nxt, Ctl *ctl,
+                                                uint32_t pass) {
+  if (ctl->flags) return;
+  __shared__ uint32_t scratch[20];
+  __shared__ uint64_t s64[16];
+  __shared__ uint32_t carry;
+  const uint32_t u = blockIdx.x, tid = threadIdx.x;
+  const uint32_t nch = g.nchunks;
+  uint64_t pre = 0, tot = 0, ex = 0;
+  for (int v = tid; v < nslots; v += blockDim.x) {
+    const uint64_t b = rec_bytes(sl.nused[v], nch, sl.words[v]);
+    const uint64_t ba = (b + kRecAlign - 1) & ~(kRecAlign - 1);
+    tot += ba;
+    ex += b;
+    if ((uint32_t)v < u) pre += ba;
+  }
+  pre = block_sum64(pre, s64);
+  tot = block_sum64(tot, s64);
+  ex = block_sum64(ex, s64);
+  const uint64_t base = ctl->bump;
+  if (base + tot > cap) {
+    if (tid == 0) fail(ctl, kFlagOverflow, pass);
+    return;
+  }
+  const uint64_t slice = slot_slice[u];
+  const uint64_t off = base + pre;
+  uint8_t *rec = arena + off;
+  const uint32_t n_used = sl.nused[u], words = sl.words[u];
+  const double step = qp.rel ? sl.qstep[3 * u] : qp.step;
+  if (tid == 0) {
+    const uint64_t sq_lo = sl.sq[2 * u], sq_hi = sl.sq[2 * u + 1];
+    uint32_t *h32 = (uint32_t *)rec;
+    h32[0] = kMagic;
+    h32[1] = (uint32_t)g.slice_log2;
+    h32[2] = (uint32_t)g.chunk_log2;
+    h32[3] = n_used;
+    h32[4] = nch;
+    h32[5] = words;
+    h32[6] = sl.nesc[u];
+    h32[7] = (uint32_t)rec_bytes(n_used, nch, words);
+    *(double *)(rec + 32) = step;
+    *(uint64_t *)(rec + 40) = sq_lo;
+    *(uint64_t *)(rec + 48) = sq_hi;
+    h32[14] = 0;
+    h32[15] = 0;
+    nxt.rec_off[slice] = off;
+    nxt.rec_len[slice] = h32[7];
+    nxt.step[slice] = step;
+    nxt.sq[2 * slice] = sq_lo;
+    nxt.sq[2 * slice + 1] = sq_hi;
+    sl.sq[2 * u] = 0;  // consumed
+    sl.sq[2 * u + 1] = 0;
+    sl.nesc[u] = 0;
+    if (u == 0) {
+      ctl->pending_bump = tot;
+      ctl->pending_bytes = ex;
+    }
+    carry = 0;
+  }
+  uint16_t *tab = (uint16_t *)(rec + kHdr);
+  for (uint32_t i = tid; i < n_used; i += blockDim.x) tab[i] = sl.symtab[(uint64_t)u * kNSym + i];
+  if (tid == 0 && (n_used & 1)) tab[n_used] = 0;
+  uint32_t *offs = (uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
+  const uint32_t *cw = sl.chunk_words + (uint64_t)u * nch;
+  __syncthreads();
+  for (uint32_t t0 = 0; t0 < nch; t0 += blockDim.x) {
+    uint32_t c = t0 + tid;
+    uint32_t x = c < nch ? cw[c] : 0u, t;
+    uint32_t p = block_excl_scan(x, scratch, &t);
+    if (c < nch) offs[c] = carry + p;
+    __syncthreads();
+    if (tid == 0) carry += t;
+    __syncthreads();
+  }
+  if (tid == 0) offs[nch] = words;
+}
+
+// ----------------------------------------------------------------- compact
+
+__global__ void __launch_bounds__(256) k_compact(Slots sl, Geo g, const uint64_t *slot_slice, uint8_t *arena,
+                                                 StateMeta nxt, uint32_t chunks_per_block, Ctl *ctl) {
+  if (ctl->flags) return;
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  const uint32_t u = blockIdx.y;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sl.words[u] = 0;  // consumed
+    if (u == 0) {
+      ctl->bump += ctl->pending_bump;
+      ctl->cur_bytes += ctl->pending_bytes;
     }
   }
-  __syncthreads();
-  for (uint32_t i = lane; i < nw && i < lds_words; i += 64) out[i] = lw[i];
+  const uint64_t slice = slot_slice[u];
+  uint8_t *rec = arena + nxt.rec_off[slice];
+  const uint32_t n_used = ld32(rec + 12);
+  const uint32_t *offs = (const uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
+  uint32_t *words = (uint32_t *)(offs + g.nchunks + 1);
+  const uint32_t cb = blockIdx.x * chunks_per_block;
+  const uint32_t ce = cb + chunks_per_block < g.nchunks ? cb + chunks_per_block : g.nchunks;
+  for (uint32_t c = cb + wave; c < ce; c += 4) {
+    const uint32_t w0 = offs[c], nw = offs[c + 1] - w0;
+    const uint32_t *src = sl.stage + ((uint64_t)u * g.nchunks + c) * sl.stage_words;
+    for (uint32_t i = lane; i < nw; i += 64) words[w0 + i] = src[i];
+  }
 }
 
 // ----------------------------------------------------------------- readout
@@ -1018,17 +1380,14 @@ __global__ void k_readout(Slots sl, Geo g, uint64_t first, uint64_t count, int p
 
 static inline unsigned grid1(uint64_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
-void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *tmp,
-                       double *kscale, int with_norm) {
-  (void)tmp;
+void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *kscale,
+                       int with_norm) {
   hipLaunchKernelGGL(k_begin_pass, dim3(1), dim3(1024), 0, st, ctl, cur.step, cur.sq, nslices, kscale, with_norm);
 }
 
-void launch_end_pass(hipStream_t st, Ctl *ctl) { hipLaunchKernelGGL(k_end_pass, dim3(1), dim3(1), 0, st, ctl); }
-
-void launch_reset_slots(hipStream_t st, const Slots &sl, const Geo &g, int nslots) {
-  uint64_t n = (uint64_t)nslots * kNSym;
-  hipLaunchKernelGGL(k_reset_slots, dim3(grid1(n, 256)), dim3(256), 0, st, sl, g.nchunks, nslots);
+void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots) {
+  uint64_t n = (uint64_t)nslots * kGqParts * kNSym;
+  hipLaunchKernelGGL(k_reset_slots, dim3(grid1(n, 256)), dim3(256), 0, st, sl, nslots);
 }
 
 void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots, int kind,
@@ -1040,72 +1399,113 @@ void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *
 
 void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                    const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl, uint32_t pass) {
-  dim3 grid(grid1(g.nchunks, 256), (unsigned)nslots);
-  hipLaunchKernelGGL(k_decode, grid, dim3(256), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
+  dim3 grid(grid1(g.nchunks, kDecLanes), (unsigned)nslots);
+  hipLaunchKernelGGL(k_decode, grid, dim3(kDecLanes), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
 }
 
-// Gate kernels: workgroups of whole wavefronts, each covering
-// C = min(threads * V, L) amplitudes of one slot.
-void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                        const GateDesc &gd, const Ctl *ctl) {
+static int gate_kind(const GateDesc &gd) {
+  if (gd.kind == 0) return 0;
+  if (gd.kind == 2) return 2;
+  return gd.k == 1 ? 1 : 3;
+}
+
+template <int KIND>
+static void launch_minmax_k(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
+                            const GateDesc &gd, const Ctl *ctl) {
   const int threads = g.L >= 256 ? 256 : 64;
   const uint64_t C = (uint64_t)threads < g.L ? (uint64_t)threads : g.L;
   const uint64_t total = (uint64_t)nslots * g.L;
-  hipLaunchKernelGGL(k_gate_minmax, dim3((unsigned)(total / C)), dim3(threads), 0, st, sl, g, slot_slice, gd, ctl);
+  hipLaunchKernelGGL(k_gate_minmax<KIND>, dim3((unsigned)(total / C)), dim3(threads), 0, st, sl, g, ss, gd, ctl);
+}
+
+void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                        const GateDesc &gd, const Ctl *ctl) {
+  switch (gate_kind(gd)) {
+    case 0: launch_minmax_k<0>(st, sl, g, slot_slice, nslots, gd, ctl); break;
+    case 1: launch_minmax_k<1>(st, sl, g, slot_slice, nslots, gd, ctl); break;
+    case 2: launch_minmax_k<2>(st, sl, g, slot_slice, nslots, gd, ctl); break;
+    default: launch_minmax_k<3>(st, sl, g, slot_slice, nslots, gd, ctl); break;
+  }
 }
 
 void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl) {
   hipLaunchKernelGGL(k_rel_step, dim3(grid1((uint64_t)nslots, 256)), dim3(256), 0, st, sl, nslots, rel, ctl);
 }
 
+template <int KIND>
+static void launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
+                        const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
+  const uint64_t C = gq_tile(g.L);
+  const uint32_t ntiles = (uint32_t)(g.L / C);
+  const dim3 grid(ntiles < kGqWgs ? ntiles : kGqWgs, (unsigned)nslots);
+  if (C == 1024) {  // whole tiles of 256 threads x 4 amplitudes
+    hipLaunchKernelGGL((k_gate_quant<KIND, 4, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass);
+    return;
+  }
+  const int threads = g.L >= 256 ? 256 : 64;
+  hipLaunchKernelGGL((k_gate_quant<KIND, 4, false>), grid, dim3(threads), 0, st, sl, g, ss, gd, qp, ctl, pass);
+}
+
 void launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                        const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
-  const uint64_t total = (uint64_t)nslots * g.L;
-  if (g.L >= 1024) {
-    hipLaunchKernelGGL(k_gate_quant<4>, dim3((unsigned)(total / 1024)), dim3(256), 0, st, sl, g, slot_slice, gd, qp,
-                       ctl, pass);
-  } else {
-    const int threads = g.L >= 256 ? 256 : (g.L >= 64 ? (int)g.L : 64);
-    const uint64_t C = (uint64_t)threads < g.L ? (uint64_t)threads : g.L;
-    hipLaunchKernelGGL(k_gate_quant<1>, dim3((unsigned)(total / C)), dim3(threads), 0, st, sl, g, slot_slice, gd, qp,
-                       ctl, pass);
+  const int kind = gate_kind(gd);
+  if (kind == 1) {
+    const uint64_t C = gq_tile(g.L);
+    if ((1ull << gd.tloc[0]) < C) {  // partner inside the tile
+      launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+    } else if (g.L >= 1024) {       // partner in the paired tile
+      const bool cross = gd.tloc[0] >= g.slice_log2;
+      const uint32_t ntiles = (uint32_t)(g.L / C);
+      const uint32_t npairs = cross ? ntiles : ntiles / 2;
+      const dim3 grid(npairs < kGqWgs ? npairs : kGqWgs, (unsigned)(cross ? nslots / 2 : nslots));
+      hipLaunchKernelGGL(k_gate_quant_pair<4>, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
+    } else {                        // short slices: general indexing
+      launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+    }
+    return;
+  }
+  switch (kind) {
+    case 0: launch_gq_k<0>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass); break;
+    case 2: launch_gq_k<2>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass); break;
+    default: launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass); break;
   }
 }
 
-void launch_codebook(hipStream_t st, const Slots &sl, int nslots, const Ctl *ctl) {
-  hipLaunchKernelGGL(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, ctl);
+void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
+                     Ctl *ctl) {
+  hipLaunchKernelGGL(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, ctl);
 }
 
-void launch_chunkbits(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
-  uint64_t tc = (uint64_t)nslots * g.nchunks;
-  hipLaunchKernelGGL(k_chunkbits, dim3(grid1(tc, 4)), dim3(256), 0, st, sl, g, tc, ctl);
-}
-
-void launch_layout(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   const StateMeta &nxt, uint64_t arena_cap, Ctl *ctl, uint32_t pass) {
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, st, sl, g, slot_slice, nslots, nxt, arena_cap, ctl, pass);
+void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
+  // about four workgroups per CU over the batch, at least one chunk per wavefront
+  const uint64_t total = (uint64_t)nslots * g.nchunks;
+  uint64_t cpb = total / 1024;
+  if (cpb < kEncWaves) cpb = kEncWaves;
+  if (cpb > g.nchunks) cpb = g.nchunks;
+  dim3 grid(grid1(g.nchunks, (unsigned)cpb), (unsigned)nslots);
+  const size_t shm = (size_t)kEncWaves * sl.stage_words * 4;
+  hipLaunchKernelGGL(k_encode, grid, dim3(64 * kEncWaves), shm, st, sl, g, (uint32_t)cpb, ctl);
 }
 
 void launch_header(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   const QuantParams &qp, uint8_t *arena, const StateMeta &nxt, const Ctl *ctl) {
-  hipLaunchKernelGGL(k_header, dim3((unsigned)nslots), dim3(256), 0, st, sl, g, slot_slice, qp, arena, nxt, ctl);
+                   const QuantParams &qp, uint8_t *arena, uint64_t arena_cap, const StateMeta &nxt, Ctl *ctl,
+                   uint32_t pass) {
+  hipLaunchKernelGGL(k_header, dim3((unsigned)nslots), dim3(256), 0, st, sl, g, slot_slice, nslots, qp, arena,
+                     arena_cap, nxt, ctl, pass);
 }
 
-void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   uint8_t *arena, const StateMeta &nxt, const Ctl *ctl) {
-  const uint64_t B = 1ull << g.chunk_log2;
-  const uint32_t lds_words = (uint32_t)((B * (kLMax + kEscBits + 50) + 31) / 32 + 1);
-  int waves = 4;
-  while (waves > 1 && (uint64_t)waves * lds_words * 4 > 64 * 1024) waves >>= 1;
-  uint64_t tc = (uint64_t)nslots * g.nchunks;
-  size_t shm = (size_t)waves * lds_words * 4;
-  hipLaunchKernelGGL(k_encode, dim3(grid1(tc, (unsigned)waves)), dim3(64 * waves), shm, st, sl, g, slot_slice, tc,
-                     lds_words, arena, nxt, ctl);
+void launch_compact(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                    uint8_t *arena, const StateMeta &nxt, Ctl *ctl) {
+  const uint64_t total = (uint64_t)nslots * g.nchunks;
+  uint64_t cpb = total / 2048;
+  if (cpb < 4) cpb = 4;
+  if (cpb > g.nchunks) cpb = g.nchunks;
+  dim3 grid(grid1(g.nchunks, (unsigned)cpb), (unsigned)nslots);
+  hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, st, sl, g, slot_slice, arena, nxt, (uint32_t)cpb, ctl);
 }
 
-void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, int nslots, uint64_t first_amp, uint64_t count,
+void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,
                     int probabilities, double *out) {
-  (void)nslots;
   hipLaunchKernelGGL(k_readout, dim3(grid1(count, 256)), dim3(256), 0, st, sl, g, first_amp, count, probabilities,
                      out);
 }
