@@ -179,8 +179,11 @@ int sim_import_slice(sim_t *sim, uint64_t j, const void *buf, uint64_t len);
 /* Device time (milliseconds, summed since the last reset) spent in each of
  * the library's kernel classes, measured with HIP events on the handle's
  * stream when enabled.  `names` receives a static comma-separated list of the
- * class names in order; out has room for `cap` values; returns the number of
- * classes.  enable != 0 turns the per-kernel events on and resets the sums. */
+ * class names in order; out has room for `cap` values: out[k] is class k's
+ * milliseconds and, when cap >= 2 * classes, out[classes + k] the number of
+ * its launches that were timed.  Returns the number of classes.  enable != 0
+ * turns the per-kernel events on and resets the sums, enable == 0 turns them
+ * off, enable < 0 only reads. */
 int sim_kernel_times(sim_t *sim, int enable, double *out, int cap, const char **names);
 
 #ifdef __cplusplus

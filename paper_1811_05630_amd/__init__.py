@@ -283,12 +283,14 @@ class Sim:
         _check(lib().sim_import_slice(self._h, j, b.ctypes.data_as(C.c_void_p), len(rec)), "sim_import_slice")
 
     def kernel_times(self, enable: Optional[bool] = None) -> dict:
-        """Per-kernel-class device milliseconds since the last reset; enable=True/False
-        switches the event timing on/off (and resets the sums)."""
-        out = (C.c_double * 32)()
+        """Per-kernel-class device time since the last reset, as
+        {class: (milliseconds, launches)}; enable=True/False switches the event
+        timing on/off (and resets the sums)."""
+        out = (C.c_double * 64)()
         names = C.c_char_p()
-        k = lib().sim_kernel_times(self._h, -1 if enable is None else int(bool(enable)), out, 32,
+        k = lib().sim_kernel_times(self._h, -1 if enable is None else int(bool(enable)), out, 64,
                                    C.byref(names))
         if k < 0:
             _check(k, "sim_kernel_times")
-        return dict(zip(names.value.decode().split(","), list(out)[:k]))
+        cls = names.value.decode().split(",")
+        return {cls[i]: (out[i], int(out[k + i])) for i in range(k)}

@@ -101,6 +101,7 @@ struct sim_s {
   std::vector<int> kt_cls;
   size_t kt_used = 0;
   double kt_ms[K_COUNT] = {0};
+  double kt_n[K_COUNT] = {0};  // launches timed per class
 
   int dalloc(void **p, size_t bytes) {
     *p = nullptr;
@@ -136,7 +137,10 @@ struct sim_s {
     hipStreamSynchronize(stream);
     for (size_t i = 0; i + 1 < kt_used; i += 2) {
       float ms = 0;
-      if (hipEventElapsedTime(&ms, kt_pool[i], kt_pool[i + 1]) == hipSuccess) kt_ms[kt_cls[i / 2]] += ms;
+      if (hipEventElapsedTime(&ms, kt_pool[i], kt_pool[i + 1]) == hipSuccess) {
+        kt_ms[kt_cls[i / 2]] += ms;
+        kt_n[kt_cls[i / 2]] += 1;
+      }
     }
     kt_used = 0;
   }
@@ -842,17 +846,22 @@ int sim_kernel_times(sim_t *s, int enable, double *out, int cap, const char **na
   if (!s) return set_err(SIM_EINVAL, "null handle");
   if (names) *names = kClassNames;
   if (s->kt_on) s->kt_flush();
-  if (out)
+  if (out) {
     for (int k = 0; k < K_COUNT && k < cap; k++) out[k] = s->kt_ms[k];
+    for (int k = 0; k < K_COUNT && K_COUNT + k < cap; k++) out[K_COUNT + k] = s->kt_n[k];
+  }
   if (enable >= 0) {
     const bool on = enable != 0;
     if (on && s->kt_pool.empty()) {
       s->kt_pool.resize(8192);
       s->kt_cls.resize(4096);
-      for (auto &e : s->kt_pool) hipEventCreate(&e);
+      // timing-only events: no system-scope fence (and no cache writeback)
+      // between the kernels they bracket
+      for (auto &e : s->kt_pool) hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     }
     s->kt_on = on;
     for (double &v : s->kt_ms) v = 0;
+    for (double &v : s->kt_n) v = 0;
     s->kt_used = 0;
   }
   return K_COUNT;
