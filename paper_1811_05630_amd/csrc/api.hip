@@ -344,10 +344,10 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
       s->kt_end();
     }
     s->kt_begin(K_GATEQ);
-    launch_gate_quant(st, s->slots, s->geo, ss, ns, gd, qp, s->ctl, pass);
+    const uint32_t nparts = launch_gate_quant(st, s->slots, s->geo, ss, ns, gd, qp, s->ctl, pass);
     s->kt_end();
     s->kt_begin(K_CODEBOOK);
-    launch_codebook(st, s->slots, ss, ns, nxt, s->ctl);
+    launch_codebook(st, s->slots, ss, ns, nxt, nparts, s->ctl);
     s->kt_end();
     s->kt_begin(K_ENCODE);
     launch_encode(st, s->slots, s->geo, ns, s->ctl);

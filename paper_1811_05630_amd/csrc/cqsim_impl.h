@@ -86,10 +86,11 @@ struct Geo {
 };
 
 // Per-slot scratch of one batch of decompressed slices.
-// Accumulators are zero between uses: hpart and part are cleared by the
-// codebook kernel, sq and nesc by the header kernel, words by the compact
-// kernel and minmax by the relative-step kernel, each right after its last
-// reader.
+// Every gate_quant workgroup overwrites its partial results (hpart, part)
+// whole, and the codebook kernel reads only those of the current launch.
+// Accumulators are zero between uses: sq and nesc are cleared by the header
+// kernel, words by the compact kernel and minmax by the relative-step kernel,
+// each right after its last reader.
 struct Slots {
   double *ws;             // [W][2L] decompressed values (re plane, im plane)
   uint16_t *sym;          // [W][2L] symbols
@@ -106,8 +107,7 @@ struct Slots {
   uint32_t *stage;        // [W][nchunks][stage_words] encoded chunks before compaction
   uint32_t stage_words;   // capacity of one chunk: ceil(B * 68 / 32) words
   // gate_quant writes, per slot, up to kGqParts partial results (one per
-  // workgroup and tile role) without atomics; the codebook kernel adds and
-  // clears them
+  // workgroup and tile role) without atomics; the codebook kernel adds them
   uint32_t *hpart;        // [W][kGqParts][1024] partial histograms
   uint64_t *part;         // [W][kGqParts][4] sum p^2 lo, hi, escapes, max error bits
 };
@@ -136,10 +136,12 @@ void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
 void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                         const GateDesc &gd, const Ctl *ctl);
 void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl);
-void launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                       const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass);
+// returns the number of partial results per slot that the launch writes
+uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                           const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass);
+// nparts: partial results per slot written by the preceding gate_quant launch
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
-                     Ctl *ctl);
+                     uint32_t nparts, Ctl *ctl);
 void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
 void launch_header(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                    const QuantParams &qp, uint8_t *arena, uint64_t arena_cap, const StateMeta &nxt, Ctl *ctl,

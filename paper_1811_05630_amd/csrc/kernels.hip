@@ -254,31 +254,45 @@ __global__ void k_init(Slots sl, Geo g, const uint64_t *slot_slice, uint64_t tot
 }
 
 // ------------------------------------------------------------------ decode
-// One wavefront per workgroup, one lane per chunk: the lane walks its chunk's
-// bit stream serially (12-bit peek into the decoder table, escapes carry the
-// exact difference), keeps the running sum p and writes a = p * k.  Every 16
-// values per lane go through an LDS tile and leave as whole 128-byte lines.
+// One lane per chunk: the lane walks its chunk's bit stream serially (12-bit
+// peek into the decoder table, escapes carry the exact difference), keeps the
+// running sum p and writes a = p * k.  Four wavefronts share one decoder
+// table.  Values go out in rounds of 16 per lane through an LDS tile, so that
+// every store instruction writes whole 128-byte lines.
+// Stream words come from a per-lane LDS slot that holds the next kDecPf words
+// of the chunk, loaded while the previous round's values were being stored:
+// the loads are issued before those stores, so waiting for them never waits
+// for the stores (one in-order counter covers both on CDNA).  A round that
+// needs more words than the slot holds reads them from global memory.
+
+constexpr int kDecWaves = 4;   // wavefronts per workgroup
+constexpr int kDecRow = 16;    // values per lane per round
+constexpr int kDecPitch = 17;  // LDS row pitch in doubles (breaks bank conflicts)
+constexpr int kDecPf = 8;      // stream words prefetched per lane per round
 
 struct BitReader {
-  const uint32_t *w;
-  uint32_t nw, wi;
-  uint32_t nxt;  // next stream word, loaded one refill ahead
-  uint64_t buf;
+  const uint32_t *w;  // the chunk's words (global)
+  uint32_t nw;        // number of words
+  uint32_t wi;        // next word to enter buf
+  uint32_t wbase;     // first word held in the LDS slot
+  uint64_t buf;       // bits not yet consumed, most significant first
   int nbits;
-  __device__ __forceinline__ void start(const uint32_t *words, uint32_t n) {
-    w = words;
-    nw = n;
-    wi = 0;
-    buf = 0;
-    nbits = 0;
-    nxt = n ? w[0] : 0u;
-  }
-  __device__ __forceinline__ void refill() {
+  __device__ __forceinline__ void refill(const uint32_t (*pf)[64 * kDecWaves], uint32_t tid) {
     while (nbits <= 32) {
-      buf |= (uint64_t)nxt << (32 - nbits);
+      uint32_t word = 0;
+      const uint32_t d = wi - wbase;
+      if (wi < nw) {
+        if (d < (uint32_t)kDecPf) {
+          word = pf[d][tid];
+        } else {  // past the prefetched words: wait for this load here, so
+                  // that the common path after the join waits for LDS only
+          word = w[wi];
+          __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        }
+      }
+      buf |= (uint64_t)word << (32 - nbits);
       nbits += 32;
       wi++;
-      nxt = wi < nw ? w[wi] : 0u;
     }
   }
   __device__ __forceinline__ uint64_t take(int n) {  // 0 <= n <= 32, needs nbits >= n
@@ -290,17 +304,17 @@ struct BitReader {
   }
 };
 
-constexpr int kDecLanes = 64;
-constexpr int kDecRow = 16;    // values per lane per LDS round
-constexpr int kDecPitch = 17;  // LDS row pitch in doubles (breaks bank conflicts)
-
-__global__ void __launch_bounds__(kDecLanes) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
-                                                      const uint8_t *arena, StateMeta cur, const double *kscale,
-                                                      Ctl *ctl, uint32_t pass) {
+// FULL: chunks of at least 16 values and a whole number of workgroups of
+// chunks per slot (every lane active, 16 values per round).
+template <bool FULL>
+__global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
+                                                           const uint8_t *arena, StateMeta cur, const double *kscale,
+                                                           Ctl *ctl, uint32_t pass) {
   if (ctl->flags) return;
   __shared__ uint16_t dtab[1 << kLMax];
-  __shared__ double stg[kDecLanes * kDecPitch];
-  const uint32_t u = blockIdx.y, lane = threadIdx.x;
+  __shared__ double stg[kDecWaves][64 * kDecPitch];
+  __shared__ uint32_t pf[kDecPf][64 * kDecWaves];
+  const uint32_t u = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
   const uint64_t slice = slot_slice[u];
   const uint8_t *rec = arena + cur.rec_off[slice];
   const uint32_t n_used = ld32(rec + 12);
@@ -308,21 +322,17 @@ __global__ void __launch_bounds__(kDecLanes) k_decode(Slots sl, Geo g, const uin
   const uint32_t n_words = ld32(rec + 20);
   if (ld32(rec) != kMagic || n_used < 1 || n_used > (uint32_t)kNSym || nchunks != g.nchunks ||
       ld32(rec + 8) != (uint32_t)g.chunk_log2) {
-    if (lane == 0) fail(ctl, kFlagCorrupt, pass);
+    if (tid == 0) fail(ctl, kFlagCorrupt, pass);
     return;
   }
-  {
-    const uint4 *src = (const uint4 *)(cur.dtab + slice * (1u << kLMax));
-    uint4 *dst = (uint4 *)dtab;
-    for (uint32_t i = lane; i < (1u << kLMax) / 8; i += kDecLanes) dst[i] = src[i];
-  }
-  const uint32_t c0 = blockIdx.x * kDecLanes;
+  const uint32_t c0 = (blockIdx.x * kDecWaves + wave) * 64u;  // first chunk of this wavefront
   const uint32_t c = c0 + lane;
-  const bool active = c < nchunks;
+  const bool active = FULL || c < nchunks;
   const uint32_t sym_bytes = (2 * n_used + 3) & ~3u;
   const uint32_t *offs = (const uint32_t *)(rec + kHdr + sym_bytes);
   BitReader br;
-  uint32_t w0 = 0, nw = 0;
+  uint32_t w0 = 0;
+  br.nw = 0;
   if (active) {
     w0 = offs[c];
     const uint32_t w1 = offs[c + 1];
@@ -330,37 +340,62 @@ __global__ void __launch_bounds__(kDecLanes) k_decode(Slots sl, Geo g, const uin
       fail(ctl, kFlagCorrupt, pass);
       w0 = 0;
     } else {
-      nw = w1 - w0;
+      br.nw = w1 - w0;
     }
   }
-  br.start(offs + (nchunks + 1) + w0, nw);
-  br.refill();
-  __syncthreads();
+  br.w = offs + (nchunks + 1) + w0;
+  br.wi = 0;
+  br.buf = 0;
+  br.nbits = 0;
+  {
+    const uint4 *src = (const uint4 *)(cur.dtab + slice * (1u << kLMax));
+    uint4 *dst = (uint4 *)dtab;
+    for (uint32_t i = tid; i < (1u << kLMax) / 8; i += 64 * kDecWaves) dst[i] = src[i];
+  }
+  // words [from, from + kDecPf) of the chunk; the address of a word past the
+  // end is replaced by a valid one (the load is always issued)
+  uint32_t nx[kDecPf];
+  auto prefetch = [&](uint32_t from) {
+#pragma unroll
+    for (int i = 0; i < kDecPf; i++) nx[i] = *(from + i < br.nw ? br.w + from + i : offs);
+  };
+  auto to_slot = [&]() {
+    br.wbase = br.wi;
+#pragma unroll
+    for (int i = 0; i < kDecPf; i++) pf[i][tid] = nx[i];  // words past the chunk's end are never read
+  };
+  prefetch(0);
+  __syncthreads();  // decoder table in LDS
+  to_slot();
   const uint64_t B = 1ull << g.chunk_log2;
-  const uint32_t R = B < (uint64_t)kDecRow ? (uint32_t)B : (uint32_t)kDecRow;
+  const uint32_t R = FULL ? (uint32_t)kDecRow : (B < (uint64_t)kDecRow ? (uint32_t)B : (uint32_t)kDecRow);
   const double k = kscale[slice];
   double *out = sl.ws + (uint64_t)u * 2 * g.L;
+  double *st = stg[wave];
   double p = 0.0;  // running integer sum, exact in FP64 below 2^53
+  // nothing is in flight when the rounds start, so no load issued here is
+  // waited for inside them (where a wait would also wait for the stores)
+  __builtin_amdgcn_s_waitcnt(0);
   for (uint64_t j0 = 0; j0 < B; j0 += R) {
     if (active) {
       for (uint32_t q = 0; q < R; q++) {
-        if (br.nbits < kLMax) br.refill();
-        uint32_t e = dtab[(uint32_t)(br.buf >> (64 - kLMax))];
-        uint32_t sym = e & 1023u, len = e >> 10;
+        if (br.nbits < kLMax) br.refill(pf, tid);
+        const uint32_t e = dtab[(uint32_t)(br.buf >> (64 - kLMax))];
+        const uint32_t sym = e & 1023u, len = e >> 10;
         br.buf <<= len;
         br.nbits -= (int)len;
         double d;
         if (sym == 0) {
-          if (br.nbits < kEscBits) br.refill();
-          int nb = (int)br.take(kEscBits);
+          if (br.nbits < kEscBits) br.refill(pf, tid);
+          const int nb = (int)br.take(kEscBits);
           uint64_t z;
           if (nb > 32) {
-            if (br.nbits < 32) br.refill();
-            uint64_t hi = br.take(nb - 32);
-            if (br.nbits < 32) br.refill();
+            if (br.nbits < 32) br.refill(pf, tid);
+            const uint64_t hi = br.take(nb - 32);
+            if (br.nbits < 32) br.refill(pf, tid);
             z = (hi << 32) | br.take(32);
           } else {
-            if (br.nbits < nb) br.refill();
+            if (br.nbits < nb) br.refill(pf, tid);
             z = br.take(nb);
           }
           d = (double)unzigzag(z);
@@ -368,15 +403,29 @@ __global__ void __launch_bounds__(kDecLanes) k_decode(Slots sl, Geo g, const uin
           d = (double)((int)sym - kR);
         }
         p += d;
-        stg[lane * kDecPitch + q] = p * k;
+        st[lane * kDecPitch + q] = p * k;
       }
     }
-    lds_sync();
-    for (uint32_t idx = lane; idx < kDecLanes * R; idx += kDecLanes) {
-      const uint32_t row = idx / R, col = idx % R;
-      if (c0 + row < nchunks) out[(uint64_t)(c0 + row) * B + j0 + col] = stg[row * kDecPitch + col];
+    prefetch(br.wi);  // the next round's words, ahead of this round's stores
+    // the tile is private to the wavefront: its LDS operations complete in
+    // order, so waiting for them is enough before other lanes read
+    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (FULL) {
+#pragma unroll
+      for (int i = 0; i < kDecRow; i++) {
+        const uint32_t idx = (uint32_t)i * 64u + lane, row = idx >> 4, col = idx & 15u;
+        out[(uint64_t)(c0 + row) * B + j0 + col] = st[row * kDecPitch + col];
+      }
+    } else {
+      for (uint32_t idx = lane; idx < 64u * R; idx += 64u) {
+        const uint32_t row = idx / R, col = idx % R;
+        if (c0 + row < nchunks) out[(uint64_t)(c0 + row) * B + j0 + col] = st[row * kDecPitch + col];
+      }
     }
-    lds_sync();
+    // the next round's slot; its words were loaded before the stores above,
+    // so the wait for them leaves the stores in flight
+    to_slot();
+    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");  // tile read before the next round writes it
   }
 }
 
@@ -664,6 +713,193 @@ __device__ __forceinline__ void tile_symbols(const double (&qr)[V], const double
   lds_sync();  // bnd is reused by the next tile
 }
 
+// LDS histogram update of one thread's 2V symbols of a whole tile: a
+// wavefront whose symbols are all equal adds once, otherwise every thread
+// adds its runs of equal symbols.
+template <int V>
+__device__ __forceinline__ void hist_full(const uint32_t (&sr)[V], const uint32_t (&si)[V], uint32_t *h) {
+  bool uni = true;
+#pragma unroll
+  for (int v = 0; v < V; v++) uni &= (sr[v] == sr[0]) & (si[v] == sr[0]);
+  const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sr[0]);
+  if (__ballot(!(uni && sr[0] == s0)) == 0) {
+    if (lane_id() == 0) atomicAdd(&h[s0], 2u * V * 64u);
+  } else {
+    uint32_t cs = sr[0], cn = 0;
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      if (sr[v] != cs) { atomicAdd(&h[cs], cn); cs = sr[v]; cn = 0; }
+      cn++;
+      if (si[v] != cs) { atomicAdd(&h[cs], cn); cs = si[v]; cn = 0; }
+      cn++;
+    }
+    atomicAdd(&h[cs], cn);
+  }
+}
+
+// ------------------------------------------------ buffer memory operations
+// The whole-tile kernels address slot memory through buffer resources: a
+// descriptor in scalar registers plus a 32-bit offset per lane, so that no
+// 64-bit address arithmetic runs per lane, and an access past the
+// descriptor's size is dropped by the hardware (reads return zero).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufWord3 = 0x00020000;  // descriptor word 3 for untyped 32-bit access on gfx9-family chips
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufWord3);
+}
+__device__ __forceinline__ double buf_ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __longlong_as_double((long long)(((uint64_t)x.y << 32) | x.x));
+}
+__device__ __forceinline__ void buf_st_u16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_i64(__amdgpu_buffer_rsrc_t r, uint32_t off, int64_t v) {
+  u32x2 x;
+  x.x = (uint32_t)(uint64_t)v;
+  x.y = (uint32_t)((uint64_t)v >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
+}
+
+// the value of the lane below (0 in lane 0): a DPP shift of the wavefront
+__device__ __forceinline__ int lane_below(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
+
+// Output of a slot's gate_quant over whole tiles: symbols and escapes.
+struct SlotBuf {
+  __amdgpu_buffer_rsrc_t sym, esc;  // [2L] u16, [2L] i64 (re plane, then im plane)
+  uint32_t L;
+};
+
+__device__ __forceinline__ SlotBuf slot_buf(const Slots &sl, const Geo &g, uint32_t u) {
+  SlotBuf b;
+  b.sym = buf_rsrc(sl.sym + (uint64_t)u * 2 * g.L, (uint32_t)(4 * g.L));
+  b.esc = buf_rsrc(sl.esc + (uint64_t)u * 2 * g.L, (uint32_t)(16 * g.L));
+  b.L = (uint32_t)g.L;
+  return b;
+}
+
+// tile_symbols for whole tiles of 256 V amplitudes (256 threads), with an
+// integer path: when every |q| of the tile is below 2^24 -- decided for the
+// whole workgroup at the first barrier, so that all wavefronts take the same
+// barriers and exchange boundary values in one form -- differences, symbols
+// and squares are computed in 32/64-bit integers (q^2 < 2^48, and a tile adds
+// at most 2V of them per thread before they join the 128-bit sum).
+// Otherwise the FP64 path runs, which also refuses |q| >= 2^48.  Results are
+// identical on both paths.
+template <int V>
+__device__ __forceinline__ void tile_symbols_full(const double (&qr)[V], const double (&qi)[V], uint32_t *h,
+                                                  double (*bnd)[V][4], uint32_t *bigw, const Geo &g,
+                                                  const SlotBuf &sb, uint32_t ob, Acc &acc) {
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  constexpr uint32_t T = 256, nwv = 4;
+  const uint32_t Bm = (1u << g.chunk_log2) - 1;
+  bool small = true;
+#pragma unroll
+  for (int v = 0; v < V; v++) small &= (fabs(qr[v]) < 0x1p24) & (fabs(qi[v]) < 0x1p24);
+  const bool wbig = __ballot(!small) != 0;
+  if (lane == 63) {
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      bnd[0][v][wave] = qr[v];
+      bnd[1][v][wave] = qi[v];
+    }
+  }
+  if (lane == 0) bigw[wave] = wbig ? 1u : 0u;
+  lds_sync();
+  const bool big = (bigw[0] | bigw[1] | bigw[2] | bigw[3]) != 0;
+  uint32_t sr[V], si[V];
+  if (big) {
+    bool any_esc = false;
+    double dr[V], di[V];
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      acc.ok &= (fabs(qr[v]) < kPMax) & (fabs(qi[v]) < kPMax);
+      const uint32_t o = ob + v * T + tid;
+      const double up_r = __shfl_up(qr[v], 1, 64), up_i = __shfl_up(qi[v], 1, 64);
+      double pr = 0.0, pi = 0.0;  // predecessor in the chunk (0 at a chunk head)
+      if ((o & Bm) != 0) {
+        if (lane > 0) {
+          pr = up_r;
+          pi = up_i;
+        } else if (wave > 0) {
+          pr = bnd[0][v][wave - 1];
+          pi = bnd[1][v][wave - 1];
+        } else {  // the tile starts at a chunk head, so v > 0 here
+          pr = bnd[0][v - 1][nwv - 1];
+          pi = bnd[1][v - 1][nwv - 1];
+        }
+      }
+      dr[v] = qr[v] - pr;  // exact: integers below 2^49
+      di[v] = qi[v] - pi;
+      const bool er = !(fabs(dr[v]) < (double)kR), ei = !(fabs(di[v]) < (double)kR);
+      sr[v] = er ? 0u : (uint32_t)((int)dr[v] + kR);
+      si[v] = ei ? 0u : (uint32_t)((int)di[v] + kR);
+      any_esc |= er | ei;
+      acc.nesc += (uint32_t)er + (uint32_t)ei;
+      buf_st_u16(sb.sym, 2 * o, sr[v]);
+      buf_st_u16(sb.sym, 2 * (sb.L + o), si[v]);
+    }
+    if (__ballot(any_esc)) {
+#pragma unroll
+      for (int v = 0; v < V; v++) {
+        const uint32_t o = ob + v * T + tid;
+        if (sr[v] == 0) buf_st_i64(sb.esc, 8 * o, (int64_t)dr[v]);
+        if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + o), (int64_t)di[v]);
+      }
+    }
+    add_squares<V>(qr, qi, acc.lo, acc.hi);
+  } else {
+    int ir[V], ii[V], dr[V], di[V];
+    bool any_esc = false;
+    int64_t t = 0;  // sum of q^2 over the tile's 2V values of this thread, below 2^52
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      ir[v] = (int)qr[v];  // exact: |q| < 2^24
+      ii[v] = (int)qi[v];
+      const uint32_t o = ob + v * T + tid;
+      int pr = lane_below(ir[v]), pi = lane_below(ii[v]);
+      if (lane == 0) {
+        if (wave > 0) {
+          pr = (int)bnd[0][v][wave - 1];
+          pi = (int)bnd[1][v][wave - 1];
+        } else if (v > 0) {
+          pr = (int)bnd[0][v - 1][nwv - 1];
+          pi = (int)bnd[1][v - 1][nwv - 1];
+        }
+      }
+      if ((o & Bm) == 0) pr = pi = 0;  // chunk head: predictor 0
+      dr[v] = ir[v] - pr;  // |d| < 2^25
+      di[v] = ii[v] - pi;
+      const bool er = (uint32_t)(dr[v] + (kR - 1)) > (uint32_t)(2 * kR - 2);  // !(|d| < R)
+      const bool ei = (uint32_t)(di[v] + (kR - 1)) > (uint32_t)(2 * kR - 2);
+      sr[v] = er ? 0u : (uint32_t)(dr[v] + kR);
+      si[v] = ei ? 0u : (uint32_t)(di[v] + kR);
+      any_esc |= er | ei;
+      acc.nesc += (uint32_t)er + (uint32_t)ei;
+      buf_st_u16(sb.sym, 2 * o, sr[v]);
+      buf_st_u16(sb.sym, 2 * (sb.L + o), si[v]);
+      t += (int64_t)ir[v] * ir[v];
+      t += (int64_t)ii[v] * ii[v];
+    }
+    if (__ballot(any_esc)) {
+#pragma unroll
+      for (int v = 0; v < V; v++) {
+        const uint32_t o = ob + v * T + tid;
+        if (sr[v] == 0) buf_st_i64(sb.esc, 8 * o, (int64_t)dr[v]);
+        if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + o), (int64_t)di[v]);
+      }
+    }
+    const uint64_t x = acc.lo + (uint64_t)t;
+    acc.hi += x < acc.lo;
+    acc.lo = x;
+  }
+  hist_full<V>(sr, si, h);
+  lds_sync();  // bnd and bigw are reused by the next tile
+}
+
 // Reduce the workgroup's sums and write them, with the LDS histogram h (then
 // cleared), to partial result `pidx` of slot u.
 __device__ __forceinline__ void write_partial(Acc &acc, uint32_t *h, uint64_t (*wred)[4], const Slots &sl,
@@ -809,12 +1045,272 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant(Slots sl, Geo g, const ui
   write_partial(acc, h, wred, sl, u, blockIdx.x, ctl, pass);
 }
 
+// ------------------------------------------- gate + quantise, whole tiles
+// Slices of at least 1024 amplitudes run through software-pipelined variants
+// of the kernels above.  Vector memory operations of a wavefront complete in
+// issue order on CDNA (one counter for loads and stores), so a wait for a
+// tile's loads also waits for every store issued before them.  The pipelines
+// below keep, at the top of every tile step, the pending operations in the
+// order [loads of this tile] [stores of the previous tile] [loads of the next
+// tile]: waiting for this tile never waits for the previous tile's stores.
+// Every load is issued unconditionally (past the last tile a valid tile is
+// loaded again and ignored), so the count of operations in flight is the
+// same on every path into a step.  The number of tiles per workgroup is 1 or
+// even (slice and tile sizes are powers of two).
+
+constexpr int kGqV = 4;                      // amplitudes per thread per tile
+constexpr uint32_t kGqTile = 256 * kGqV;     // amplitudes per tile
+constexpr int kGpV = 2;                      // the same for the paired kernel (two tiles per step)
+constexpr uint32_t kGpTile = 256 * kGpV;
+
+template <int V>
+struct GqTile {  // one tile of one slot, in registers
+  double r[V], i[V];
+};
+
+// tile at offset ob of a slot whose planes are addressed by `ws` (re plane,
+// then im plane, L values each)
+template <int V>
+__device__ __forceinline__ void gq_load(GqTile<V> &x, __amdgpu_buffer_rsrc_t ws, uint32_t L, uint32_t ob) {
+#pragma unroll
+  for (int v = 0; v < V; v++) {
+    x.r[v] = buf_ld_f64(ws, 8 * (ob + v * 256 + threadIdx.x));
+    x.i[v] = buf_ld_f64(ws, 8 * (L + ob + v * 256 + threadIdx.x));
+  }
+}
+
+// Per-workgroup constants of gate_quant for one slot.
+struct GqSlot {
+  __amdgpu_buffer_rsrc_t ws;  // decompressed planes of the slot
+  SlotBuf out;
+  uint32_t mask_lo, vals_lo;  // control bits inside the slice
+  bool hi_ok;                 // control bits of the slice index hold
+  double step, recip, ebj;
+};
+
+__device__ __forceinline__ GqSlot gq_slot(const Slots &sl, const Geo &g, const uint64_t *slot_slice,
+                                          const GateDesc &gd, const QuantParams &qp, uint32_t u) {
+  GqSlot s;
+  s.ws = buf_rsrc(sl.ws + (uint64_t)u * 2 * g.L, (uint32_t)(16 * g.L));
+  s.out = slot_buf(sl, g, u);
+  const uint64_t gi_hi = slot_slice[u] << g.slice_log2;
+  const uint64_t mask_hi = gd.ctrl_mask & ~(g.L - 1);
+  s.hi_ok = (gi_hi & mask_hi) == (gd.ctrl_vals & mask_hi);
+  s.mask_lo = (uint32_t)(gd.ctrl_mask & (g.L - 1));
+  s.vals_lo = (uint32_t)(gd.ctrl_vals & (g.L - 1));
+  slot_quant(sl, qp, u, s.step, s.recip, s.ebj);
+  return s;
+}
+
+// q = rint(v / step) as an integer-valued double and the check of the bound;
+// the range of q is checked by the tile's symbol step
+__device__ __forceinline__ void quant_tile(double v, const GqSlot &s, double &q, Acc &acc) {
+  q = rint(v * s.recip);
+  const double err = fabs(v - q * s.step);
+  acc.ok &= err <= s.ebj;
+  acc.emax = fmax(acc.emax, err);
+}
+
+// Gate, quantisation and symbols of one tile at offset ob.  KIND 0:
+// identity; 1: one target t inside the tile (partner amplitude from the same
+// thread when 2^t >= 256, else through the LDS exchange buffer xch); 2: phase.
+template <int KIND>
+__device__ __forceinline__ void gq_tile_step(const GqTile<kGqV> &x, uint32_t ob, const GqSlot &s, const GateDesc &gd,
+                                             const Geo &g, double (*xch)[kGqTile], uint32_t *h,
+                                             double (*bnd)[kGqV][4], uint32_t *bigw, Acc &acc) {
+  const uint32_t tid = threadIdx.x;
+  double qr[kGqV], qi[kGqV];
+  double pr[kGqV], pi[kGqV];  // partner amplitudes (KIND 1)
+  uint32_t bit = 0;
+  if (KIND == 1) {
+    const int tb = gd.tloc[0];
+    bit = 1u << tb;
+    if (tb >= 8) {  // partner element (v ^ 2^(t-8)) * 256 + tid: same thread
+#pragma unroll
+      for (int v = 0; v < kGqV; v++) {
+        pr[v] = tb == 8 ? x.r[v ^ 1] : x.r[v ^ 2];
+        pi[v] = tb == 8 ? x.i[v ^ 1] : x.i[v ^ 2];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < kGqV; v++) {
+        xch[0][v * 256 + tid] = x.r[v];
+        xch[1][v * 256 + tid] = x.i[v];
+      }
+      lds_sync();
+#pragma unroll
+      for (int v = 0; v < kGqV; v++) {
+        pr[v] = xch[0][(v * 256 + tid) ^ bit];
+        pi[v] = xch[1][(v * 256 + tid) ^ bit];
+      }
+      // the tile's symbols start with a barrier; xch is written again only
+      // after the barrier that ends them
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < kGqV; v++) {
+    const uint32_t o = ob + v * 256 + tid;
+    double re = x.r[v], im = x.i[v];
+    const bool on = s.hi_ok && (o & s.mask_lo) == s.vals_lo;
+    if (KIND == 2 && on) {
+      cmul(gd.ph_re, gd.ph_im, x.r[v], x.i[v], re, im);
+    } else if (KIND == 1 && on) {
+      const bool row = (o & bit) != 0;  // column 0: the amplitude with the target bit clear
+      const double a0r = row ? pr[v] : x.r[v], a0i = row ? pi[v] : x.i[v];
+      const double a1r = row ? x.r[v] : pr[v], a1i = row ? x.i[v] : pi[v];
+      const double u0r = row ? gd.m2[4] : gd.m2[0], u0i = row ? gd.m2[5] : gd.m2[1];
+      const double u1r = row ? gd.m2[6] : gd.m2[2], u1i = row ? gd.m2[7] : gd.m2[3];
+      double cr, ci;
+      cmul(u0r, u0i, a0r, a0i, cr, ci);
+      cmac(u1r, u1i, a1r, a1i, cr, ci);
+      re = cr;
+      im = ci;
+    }
+    quant_tile(re, s, qr[v], acc);
+    quant_tile(im, s, qi[v], acc);
+  }
+  tile_symbols_full<kGqV>(qr, qi, h, bnd, bigw, g, s.out, ob, acc);
+}
+
+// gate_quant over whole tiles: workgroup (x, u) takes tiles x, x + G, ... of
+// slot u (n = ntiles / G of them), two tiles in flight.
+template <int KIND>
+__global__ void __launch_bounds__(256, 2) k_gate_quant_pipe(Slots sl, Geo g, const uint64_t *slot_slice,
+                                                            GateDesc gd, QuantParams qp, Ctl *ctl, uint32_t pass) {
+  if (ctl->flags) return;
+  __shared__ uint32_t h[kNSym];
+  __shared__ double bnd[2][kGqV][4];
+  __shared__ uint64_t wred[4][4];
+  __shared__ double xch[KIND == 1 ? 2 : 1][kGqTile];
+  __shared__ uint32_t bigw[4];
+  for (uint32_t s = threadIdx.x; s < (uint32_t)kNSym; s += 256) h[s] = 0;
+  const uint32_t u = blockIdx.y, G = gridDim.x, t0 = blockIdx.x;
+  const uint32_t ntiles = (uint32_t)(g.L / kGqTile), n = ntiles / G, L = (uint32_t)g.L;
+  const GqSlot s = gq_slot(sl, g, slot_slice, gd, qp, u);
+  Acc acc;
+  acc.zero();
+  auto tile_of = [&](uint32_t k) { return k < n ? t0 + k * G : t0; };  // past the end: tile t0 again
+  GqTile<kGqV> A, B;
+  gq_load(A, s.ws, L, t0 * kGqTile);
+  if (n == 1) {
+    gq_tile_step<KIND>(A, t0 * kGqTile, s, gd, g, xch, h, bnd, bigw, acc);
+  } else {
+    gq_load(B, s.ws, L, tile_of(1) * kGqTile);
+    gq_tile_step<KIND>(A, t0 * kGqTile, s, gd, g, xch, h, bnd, bigw, acc);
+    gq_load(A, s.ws, L, tile_of(2) * kGqTile);
+    for (uint32_t k = 1; k + 1 < n; k += 2) {
+      gq_tile_step<KIND>(B, tile_of(k) * kGqTile, s, gd, g, xch, h, bnd, bigw, acc);
+      gq_load(B, s.ws, L, tile_of(k + 2) * kGqTile);
+      gq_tile_step<KIND>(A, tile_of(k + 1) * kGqTile, s, gd, g, xch, h, bnd, bigw, acc);
+      gq_load(A, s.ws, L, tile_of(k + 3) * kGqTile);
+    }
+    gq_tile_step<KIND>(B, tile_of(n - 1) * kGqTile, s, gd, g, xch, h, bnd, bigw, acc);
+  }
+  write_partial(acc, h, wred, sl, u, blockIdx.x, ctl, pass);
+}
+
+// One tile pair of a one-target gate whose partner lies in another tile.
+struct GqPair {
+  GqTile<kGpV> a, b;
+};
+
+__device__ __forceinline__ void gq_pair_step(const GqPair &x, uint32_t obA, uint32_t obB, const GqSlot &sA,
+                                             const GqSlot &sB, const GateDesc &gd, const Geo &g, uint32_t *hA,
+                                             uint32_t *hB, double (*bnd)[kGpV][4], uint32_t *bigw, Acc &accA,
+                                             Acc &accB) {
+  const uint32_t tid = threadIdx.x;
+  double qar[kGpV], qai[kGpV], qbr[kGpV], qbi[kGpV];
+#pragma unroll
+  for (int v = 0; v < kGpV; v++) {
+    const uint32_t e = v * 256 + tid;
+    const double a0r = x.a.r[v], a0i = x.a.i[v], a1r = x.b.r[v], a1i = x.b.i[v];
+    double outAr = a0r, outAi = a0i, outBr = a1r, outBi = a1i;
+    // controls never include the target bit: A's index decides for the pair
+    if (sA.hi_ok && ((obA + e) & sA.mask_lo) == sA.vals_lo) {
+      cmul(gd.m2[0], gd.m2[1], a0r, a0i, outAr, outAi);
+      cmac(gd.m2[2], gd.m2[3], a1r, a1i, outAr, outAi);
+      cmul(gd.m2[4], gd.m2[5], a0r, a0i, outBr, outBi);
+      cmac(gd.m2[6], gd.m2[7], a1r, a1i, outBr, outBi);
+    }
+    quant_tile(outAr, sA, qar[v], accA);
+    quant_tile(outAi, sA, qai[v], accA);
+    quant_tile(outBr, sB, qbr[v], accB);
+    quant_tile(outBi, sB, qbi[v], accB);
+  }
+  tile_symbols_full<kGpV>(qar, qai, hA, bnd, bigw, g, sA.out, obA, accA);
+  tile_symbols_full<kGpV>(qbr, qbi, hB, bnd, bigw, g, sB.out, obB, accB);
+}
+
 // A one-target gate whose partner lies in another tile (target bit t at or
 // above the tile size): a workgroup takes both tiles of a pair, so every
 // amplitude is read once.  In the batch's flat index (slot * L + offset) the
 // partner of amplitude f is f ^ 2^t.  Slice-index targets pair slot uA (bit
 // clear) with uB = uA + 2^(t - slice_log2), tile for tile; in-slice targets
-// pair tiles of one slot.  Results go to partials x (tile A) and G + x (tile B).
+// pair tiles of one slot.  Two tile pairs are in flight.
+__global__ void __launch_bounds__(256, 2) k_gate_quant_pair_pipe(Slots sl, Geo g, const uint64_t *slot_slice,
+                                                                 GateDesc gd, QuantParams qp, Ctl *ctl,
+                                                                 uint32_t pass) {
+  if (ctl->flags) return;
+  __shared__ uint32_t hA[kNSym], hB[kNSym];
+  __shared__ double bnd[2][kGpV][4];
+  __shared__ uint64_t wred[4][4];
+  __shared__ uint32_t bigw[4];
+  for (uint32_t s = threadIdx.x; s < (uint32_t)kNSym; s += 256) hA[s] = hB[s] = 0;
+  const uint32_t ntiles = (uint32_t)(g.L / kGpTile), L = (uint32_t)g.L;
+  const int t = gd.tloc[0];
+  const bool cross = t >= g.slice_log2;
+  uint32_t uA, uB, npairs;
+  int b = 0;
+  if (cross) {
+    const uint32_t sb = t - g.slice_log2, y = blockIdx.y;
+    uA = ((y >> sb) << (sb + 1)) | (y & ((1u << sb) - 1));
+    uB = uA | (1u << sb);
+    npairs = ntiles;
+  } else {
+    uA = uB = blockIdx.y;
+    b = t - 9;  // log2 of the tile size
+    npairs = ntiles / 2;
+  }
+  const uint32_t G = gridDim.x, w0 = blockIdx.x, n = npairs / G;
+  const GqSlot sA = gq_slot(sl, g, slot_slice, gd, qp, uA), sB = gq_slot(sl, g, slot_slice, gd, qp, uB);
+  Acc accA, accB;
+  accA.zero();
+  accB.zero();
+  auto pair_of = [&](uint32_t k) { return k < n ? w0 + k * G : w0; };  // past the end: pair w0 again
+  auto tA_of = [&](uint32_t w) { return cross ? w : ((w >> b) << (b + 1)) | (w & ((1u << b) - 1)); };
+  auto tB_of = [&](uint32_t w) { return cross ? w : tA_of(w) | (1u << b); };
+  auto load = [&](GqPair &x, uint32_t w) {
+    gq_load(x.a, sA.ws, L, tA_of(w) * kGpTile);
+    gq_load(x.b, sB.ws, L, tB_of(w) * kGpTile);
+  };
+  auto step = [&](const GqPair &x, uint32_t w) {
+    gq_pair_step(x, tA_of(w) * kGpTile, tB_of(w) * kGpTile, sA, sB, gd, g, hA, hB, bnd, bigw, accA, accB);
+  };
+  GqPair P, Q;
+  load(P, w0);
+  if (n == 1) {
+    step(P, w0);
+  } else {
+    load(Q, pair_of(1));
+    step(P, w0);
+    load(P, pair_of(2));
+    for (uint32_t k = 1; k + 1 < n; k += 2) {
+      step(Q, pair_of(k));
+      load(Q, pair_of(k + 2));
+      step(P, pair_of(k + 1));
+      load(P, pair_of(k + 3));
+    }
+    step(Q, pair_of(n - 1));
+  }
+  // partial results: x for both slots of a cross-slice pair; x and G + x
+  // when both tiles belong to one slot
+  write_partial(accA, hA, wred, sl, uA, blockIdx.x, ctl, pass);
+  write_partial(accB, hB, wred, sl, uB, cross ? blockIdx.x : gridDim.x + blockIdx.x, ctl, pass);
+}
+
+// The paired gate_quant without pipelining, on tiles of 1024 amplitudes: used
+// when chunks are longer than the pipelined kernel's tile (a tile must start
+// at a chunk head).  Partial results are numbered as in the pipelined kernel.
 template <int V>
 __global__ void __launch_bounds__(256, 2) k_gate_quant_pair(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
                                                             QuantParams qp, Ctl *ctl, uint32_t pass) {
@@ -894,7 +1390,7 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant_pair(Slots sl, Geo g, con
     tile_symbols<V, true>(qbr, qbi, hB, bnd, g, soB, obB, C, accB);
   }
   write_partial(accA, hA, wred, sl, uA, blockIdx.x, ctl, pass);
-  write_partial(accB, hB, wred, sl, uB, gridDim.x + blockIdx.x, ctl, pass);
+  write_partial(accB, hB, wred, sl, uB, cross ? blockIdx.x : gridDim.x + blockIdx.x, ctl, pass);
 }
 
 // ---------------------------------------------------------------- codebook
@@ -928,7 +1424,7 @@ __device__ void bitonic_sort(uint64_t *key, uint32_t P) {
 }
 
 __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot_slice, StateMeta nxt,
-                                                  Ctl *ctl) {
+                                                  uint32_t nparts, Ctl *ctl) {
   if (ctl->flags) return;
   __shared__ uint64_t key[kNSym];
   __shared__ uint32_t wgt[kNSym];
@@ -941,16 +1437,14 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   __shared__ uint32_t scratch[20];
   __shared__ uint64_t s64[16];
   const uint32_t u = blockIdx.x, tid = threadIdx.x;
-  {  // sums of the gate_quant workgroups of this slot
+  {  // sums of the gate_quant workgroups of this slot (partials [0, nparts))
     uint64_t lo = 0, hi = 0, ne = 0, eb = 0;
-    uint64_t *pp = sl.part + (uint64_t)u * kGqParts * 4;
-    for (uint32_t i = tid; i < kGqParts; i += blockDim.x) {
-      uint64_t t = lo + pp[4 * i];
-      hi += pp[4 * i + 1] + (t < lo);
-      lo = t;
-      ne += pp[4 * i + 2];
-      eb = pp[4 * i + 3] > eb ? pp[4 * i + 3] : eb;
-      pp[4 * i] = pp[4 * i + 1] = pp[4 * i + 2] = pp[4 * i + 3] = 0;  // consumed
+    const uint64_t *pp = sl.part + (uint64_t)u * kGqParts * 4;
+    if (tid < nparts) {
+      lo = pp[4 * tid];
+      hi = pp[4 * tid + 1];
+      ne = pp[4 * tid + 2];
+      eb = pp[4 * tid + 3];
     }
     for (int off = 32; off > 0; off >>= 1) {
       uint64_t ol = __shfl_xor(lo, off, 64), oh = __shfl_xor(hi, off, 64);
@@ -985,17 +1479,22 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   }
   // used symbols, compacted in symbol order (4 consecutive symbols per thread)
   uint32_t hv[4], cnt = 0;
-  {  // histogram = sum of the partial histograms (cleared after reading)
+  {  // histogram = sum of the partial histograms; all loads of a group of 16
+     // partials are issued before the first add
     uint4 acc4 = make_uint4(0, 0, 0, 0);
-    uint32_t *hp = sl.hpart + (uint64_t)u * kGqParts * kNSym;
-    for (uint32_t pi = 0; pi < kGqParts; pi++) {
-      uint4 *q4 = (uint4 *)(hp + (uint64_t)pi * kNSym) + tid;
-      const uint4 x = *q4;
-      acc4.x += x.x;
-      acc4.y += x.y;
-      acc4.z += x.z;
-      acc4.w += x.w;
-      if (x.x | x.y | x.z | x.w) *q4 = make_uint4(0, 0, 0, 0);
+    const uint4 *hp = (const uint4 *)(sl.hpart + (uint64_t)u * kGqParts * kNSym) + tid;
+    for (uint32_t p0 = 0; p0 < nparts; p0 += 16) {
+      uint4 x[16];
+#pragma unroll
+      for (int i = 0; i < 16; i++) x[i] = hp[(p0 + i) * (kNSym / 4)];  // p0 + i < kGqParts: in bounds
+#pragma unroll
+      for (int i = 0; i < 16; i++) {
+        if (p0 + i >= nparts) x[i] = make_uint4(0, 0, 0, 0);  // not written by this pass
+        acc4.x += x[i].x;
+        acc4.y += x[i].y;
+        acc4.z += x[i].z;
+        acc4.w += x[i].w;
+      }
     }
     hv[0] = acc4.x;
     hv[1] = acc4.y;
@@ -1124,8 +1623,12 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
 // ------------------------------------------------------------------ encode
 // One wavefront per chunk, four consecutive symbols per lane per step: code
 // lengths -> wavefront prefix sum -> bit positions; a lane's codes are joined
-// into one 64-bit field and OR-ed into the chunk's words staged in LDS, which
-// then go to the chunk's fixed-size staging slot.
+// into one 64-bit field and OR-ed into the chunk's words staged in LDS.
+// Four wavefronts only load and code (a chunk each per round); a fifth only
+// stores the previous round's chunks to their fixed-size staging slots.  So
+// no wavefront mixes loads and stores (a wait for a load would otherwise
+// also wait for earlier stores), and the LDS chunk buffers are double-buffered
+// between rounds.
 
 __device__ __forceinline__ void put_bits(uint32_t *lw, uint64_t v, int n, uint64_t pos) {
   while (n > 0) {
@@ -1139,106 +1642,135 @@ __device__ __forceinline__ void put_bits(uint32_t *lw, uint64_t v, int n, uint64
   }
 }
 
-constexpr int kEncWaves = 4;
+constexpr int kEncWaves = 4;  // coding wavefronts; one more stores
 
-// Chunks [cb, ce) of slot blockIdx.y; wavefront w takes chunks cb + w, cb + w + 4,
-// ...; every wavefront runs the same number of rounds so barriers line up.
-__global__ void __launch_bounds__(256) k_encode(Slots sl, Geo g, uint32_t chunks_per_block, const Ctl *ctl) {
+// Symbols j .. j + 3 of a chunk of B values (1 past the end, never coded).
+__device__ __forceinline__ uint2 enc_syms(const uint16_t *sym, uint64_t j, uint64_t B) {
+  if (j + 3 < B) return *(const uint2 *)(sym + j);  // four aligned symbols in one load
+  uint32_t t[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) t[k] = j + k < B ? sym[j + k] : 1u;
+  return make_uint2(t[0] | (t[1] << 16), t[2] | (t[3] << 16));
+}
+
+// Chunks [cb, ce) of slot blockIdx.y; coding wavefront w takes chunks cb + w,
+// cb + w + 4, ...; every wavefront runs the same number of rounds so that
+// barriers line up.  STEPS = ceil(B / 256) steps of 256 symbols per chunk.
+template <int STEPS>
+__global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Geo g, uint32_t chunks_per_block,
+                                                                    const Ctl *ctl) {
   if (ctl->flags) return;
-  extern __shared__ uint32_t lw_all[];
+  extern __shared__ uint32_t lw_all[];  // [2][kEncWaves][stage_words]
   __shared__ uint32_t codes[kNSym];
+  __shared__ uint32_t cnw[2][kEncWaves];  // words of each coded chunk
   __shared__ uint32_t wsum[kEncWaves];
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
   const uint32_t u = blockIdx.y;
   const uint32_t cb = blockIdx.x * chunks_per_block;
   const uint32_t ce = cb + chunks_per_block < g.nchunks ? cb + chunks_per_block : g.nchunks;
   const uint32_t W = sl.stage_words;
-  uint32_t *lw = lw_all + (uint64_t)wave * W;
   for (uint32_t s = threadIdx.x; s < (uint32_t)kNSym; s += blockDim.x) codes[s] = sl.codes[(uint64_t)u * kNSym + s];
-  __syncthreads();
   const uint64_t Bc = 1ull << g.chunk_log2;
-  uint32_t words_here = 0;
   const uint32_t rounds = (chunks_per_block + kEncWaves - 1) / kEncWaves;
-  for (uint32_t r = 0; r < rounds; r++) {  // the same count in every wavefront
+  const uint64_t slot0 = (uint64_t)u * 2 * g.L;
+  uint32_t words_here = 0;
+  uint2 cur[STEPS], nxt[STEPS];  // this and the next round's symbols of the lane
+  auto load_round = [&](uint2 (&d)[STEPS], uint32_t r) {
     const uint32_t c = cb + r * kEncWaves + wave;
-    const bool active = c < ce;
-    const uint64_t B = active ? Bc : 0;
-    const uint64_t base = (uint64_t)u * 2 * g.L + (uint64_t)(active ? c : 0) * Bc;
-    const uint16_t *sym = sl.sym + base;
-    const int64_t *esc = sl.esc + base;
-    uint64_t run = 0;
-    uint32_t zeroed = 0;  // words [0, zeroed) of lw are cleared for this chunk
-    for (uint64_t j0 = 0; j0 < B; j0 += 256) {
-      const uint64_t j = j0 + 4 * (uint64_t)lane;
-      uint32_t s[4], cw[4], bl = 0;
-      bool has_esc = false;
-      if (j + 3 < B) {  // four aligned symbols in one load
-        const uint2 v4 = *(const uint2 *)(sym + j);
-        s[0] = v4.x & 0xffffu;
-        s[1] = v4.x >> 16;
-        s[2] = v4.y & 0xffffu;
-        s[3] = v4.y >> 16;
-      } else {
+    const uint64_t B = c < ce && r < rounds ? Bc : 0;
+    const uint16_t *sym = sl.sym + slot0 + (uint64_t)(c < ce ? c : 0) * Bc;
 #pragma unroll
-        for (int k = 0; k < 4; k++) s[k] = j + k < B ? sym[j + k] : 1u;
-      }
+    for (int i = 0; i < STEPS; i++) d[i] = enc_syms(sym, (uint64_t)i * 256 + 4 * (uint64_t)lane, B);
+  };
+  if (wave < kEncWaves) load_round(cur, 0);
+  __syncthreads();  // code table in LDS
+  for (uint32_t r = 0; r <= rounds; r++) {  // one more round: the store wavefront drains the last one
+    const uint32_t buf = r & 1u;
+    if (wave < kEncWaves && r < rounds) {
+      load_round(nxt, r + 1);
+      const uint32_t c = cb + r * kEncWaves + wave;
+      const bool active = c < ce;
+      const uint64_t B = active ? Bc : 0;
+      const int64_t *esc = sl.esc + slot0 + (uint64_t)(active ? c : 0) * Bc;
+      uint32_t *lw = lw_all + (uint64_t)(buf * kEncWaves + wave) * W;
+      uint64_t run = 0;
+      uint32_t zeroed = 0;  // words [0, zeroed) of lw are cleared for this chunk
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        cw[k] = 0;
-        if (j + k < B) {
-          cw[k] = codes[s[k]];
-          bl += cw[k] & 0xffu;
-          if (s[k] == 0) {
-            has_esc = true;
-            bl += kEscBits + (uint32_t)bitlen64(zigzag(esc[j + k]));
-          }
-        }
-      }
-      const uint32_t inc = wave_incl_scan(bl);
-      const uint32_t tot = (uint32_t)__shfl((int)inc, 63, 64);
-      uint64_t pos = run + inc - bl;
-      uint32_t end = (uint32_t)((run + tot + 31) >> 5);
-      if (end > W) end = W;
-      for (uint32_t w = zeroed + lane; w < end; w += 64) lw[w] = 0;
-      zeroed = end > zeroed ? end : zeroed;
-      // LDS operations of one wavefront execute in issue order: a compiler
-      // barrier keeps the clearing stores ahead of the OR-ing below
-      __asm__ __volatile__("" ::: "memory");
-      run += tot;
-      if (pos + bl > 32ull * W) continue;  // cannot happen for a consistent codebook
-      if (!has_esc) {
-        uint64_t acc = 0;
-#pragma unroll
-        for (int k = 0; k < 4; k++) acc = (acc << (cw[k] & 0xffu)) | (cw[k] >> 8);
-        put_bits(lw, acc, (int)bl, pos);
-      } else {
+      for (int i = 0; i < STEPS; i++) {
+        const uint64_t j = (uint64_t)i * 256 + 4 * (uint64_t)lane;
+        uint32_t sv[4], cw[4], bl = 0;
+        sv[0] = cur[i].x & 0xffffu;
+        sv[1] = cur[i].x >> 16;
+        sv[2] = cur[i].y & 0xffffu;
+        sv[3] = cur[i].y >> 16;
+        bool has_esc = false;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-          if (j + k >= B) break;
-          const uint32_t len = cw[k] & 0xffu;
-          put_bits(lw, cw[k] >> 8, (int)len, pos);
-          pos += len;
-          if (s[k] == 0) {
-            const uint64_t z = zigzag(esc[j + k]);
-            const int nb = bitlen64(z);
-            put_bits(lw, (uint64_t)nb, kEscBits, pos);
-            put_bits(lw, z, nb, pos + kEscBits);
-            pos += kEscBits + nb;
+          cw[k] = 0;
+          if (j + k < B) {
+            cw[k] = codes[sv[k]];
+            bl += cw[k] & 0xffu;
+            if (sv[k] == 0) {
+              has_esc = true;
+              bl += kEscBits + (uint32_t)bitlen64(zigzag(esc[j + k]));
+            }
+          }
+        }
+        const uint32_t inc = wave_incl_scan(bl);
+        const uint32_t tot = (uint32_t)__shfl((int)inc, 63, 64);
+        uint64_t pos = run + inc - bl;
+        uint32_t end = (uint32_t)((run + tot + 31) >> 5);
+        if (end > W) end = W;
+        for (uint32_t w = zeroed + lane; w < end; w += 64) lw[w] = 0;
+        zeroed = end > zeroed ? end : zeroed;
+        // LDS operations of one wavefront execute in issue order: a compiler
+        // barrier keeps the clearing stores ahead of the OR-ing below
+        __asm__ __volatile__("" ::: "memory");
+        run += tot;
+        if (pos + bl > 32ull * W) continue;  // cannot happen for a consistent codebook
+        if (!has_esc) {
+          uint64_t acc = 0;
+#pragma unroll
+          for (int k = 0; k < 4; k++) acc = (acc << (cw[k] & 0xffu)) | (cw[k] >> 8);
+          put_bits(lw, acc, (int)bl, pos);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            if (j + k >= B) break;
+            const uint32_t len = cw[k] & 0xffu;
+            put_bits(lw, cw[k] >> 8, (int)len, pos);
+            pos += len;
+            if (sv[k] == 0) {
+              const uint64_t z = zigzag(esc[j + k]);
+              const int nb = bitlen64(z);
+              put_bits(lw, (uint64_t)nb, kEscBits, pos);
+              put_bits(lw, z, nb, pos + kEscBits);
+              pos += kEscBits + nb;
+            }
           }
         }
       }
+      uint32_t nw = (uint32_t)((run + 31) >> 5);
+      if (nw > W) nw = W;  // at most 68 bits per value: never reached by a consistent codebook
+      if (lane == 0) cnw[buf][wave] = nw;
+      if (active) words_here += nw;
+#pragma unroll
+      for (int i = 0; i < STEPS; i++) cur[i] = nxt[i];
+    } else if (wave == kEncWaves && r > 0) {  // store the previous round's chunks
+      const uint32_t pb = buf ^ 1u;
+      for (uint32_t w = 0; w < (uint32_t)kEncWaves; w++) {
+        const uint32_t c = cb + (r - 1) * kEncWaves + w;
+        if (c >= ce) break;
+        const uint32_t nw = cnw[pb][w];
+        const uint32_t *src = lw_all + (uint64_t)(pb * kEncWaves + w) * W;
+        uint32_t *dst = sl.stage + ((uint64_t)u * g.nchunks + c) * W;
+        for (uint32_t i = lane; i < nw; i += 64) dst[i] = src[i];
+        if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = nw;
+      }
     }
-    lds_sync();
-    if (active) {
-      const uint32_t nw = (uint32_t)((run + 31) >> 5);
-      uint32_t *dst = sl.stage + ((uint64_t)u * g.nchunks + c) * W;
-      for (uint32_t i = lane; i < nw; i += 64) dst[i] = lw[i];
-      if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = nw;
-      words_here += nw;
-    }
-    lds_sync();
+    lds_sync();  // round r coded; round r - 1 read out of LDS
   }
-  if (lane == 0) wsum[wave] = words_here;
+  if (wave < kEncWaves && lane == 0) wsum[wave] = words_here;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t t = 0;
@@ -1399,8 +1931,13 @@ void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *
 
 void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                    const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl, uint32_t pass) {
-  dim3 grid(grid1(g.nchunks, kDecLanes), (unsigned)nslots);
-  hipLaunchKernelGGL(k_decode, grid, dim3(kDecLanes), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
+  const uint32_t per_wg = 64u * kDecWaves;
+  dim3 grid(grid1(g.nchunks, per_wg), (unsigned)nslots);
+  const bool full = (1ull << g.chunk_log2) >= (uint64_t)kDecRow && g.nchunks % per_wg == 0;
+  if (full)
+    hipLaunchKernelGGL(k_decode<true>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
+  else
+    hipLaunchKernelGGL(k_decode<false>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
 }
 
 static int gate_kind(const GateDesc &gd) {
@@ -1432,59 +1969,89 @@ void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, co
   hipLaunchKernelGGL(k_rel_step, dim3(grid1((uint64_t)nslots, 256)), dim3(256), 0, st, sl, nslots, rel, ctl);
 }
 
+// Returns the number of partial results per slot that the launch writes.
 template <int KIND>
-static void launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
-                        const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
+static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
+                            const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
   const uint64_t C = gq_tile(g.L);
   const uint32_t ntiles = (uint32_t)(g.L / C);
-  const dim3 grid(ntiles < kGqWgs ? ntiles : kGqWgs, (unsigned)nslots);
-  if (C == 1024) {  // whole tiles of 256 threads x 4 amplitudes
-    hipLaunchKernelGGL((k_gate_quant<KIND, 4, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass);
-    return;
+  const uint32_t G = ntiles < kGqWgs ? ntiles : kGqWgs;
+  const dim3 grid(G, (unsigned)nslots);
+  if (C == kGqTile) {  // whole tiles of 256 threads x 4 amplitudes
+    if (KIND == 3)
+      hipLaunchKernelGGL((k_gate_quant<3, 4, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass);
+    else
+      hipLaunchKernelGGL((k_gate_quant_pipe<KIND == 3 ? 0 : KIND>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl,
+                         pass);
+    return G;
   }
   const int threads = g.L >= 256 ? 256 : 64;
   hipLaunchKernelGGL((k_gate_quant<KIND, 4, false>), grid, dim3(threads), 0, st, sl, g, ss, gd, qp, ctl, pass);
+  return G;
 }
 
-void launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                       const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
+uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+                           const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
   const int kind = gate_kind(gd);
   if (kind == 1) {
     const uint64_t C = gq_tile(g.L);
-    if ((1ull << gd.tloc[0]) < C) {  // partner inside the tile
-      launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
-    } else if (g.L >= 1024) {       // partner in the paired tile
+    if ((1ull << gd.tloc[0]) < C)  // partner inside the tile
+      return launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+    if (g.L >= kGqTile) {  // partner in the paired tile (2^t >= 1024)
       const bool cross = gd.tloc[0] >= g.slice_log2;
-      const uint32_t ntiles = (uint32_t)(g.L / C);
+      if ((1ull << g.chunk_log2) > kGpTile) {  // tiles of 1024, no pipelining
+        const uint32_t ntiles = (uint32_t)(g.L / kGqTile);
+        const uint32_t npairs = cross ? ntiles : ntiles / 2;
+        const uint32_t G = npairs < kGqWgs ? npairs : kGqWgs;
+        const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
+        hipLaunchKernelGGL(k_gate_quant_pair<kGqV>, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
+        return cross ? G : 2 * G;
+      }
+      const uint32_t ntiles = (uint32_t)(g.L / kGpTile);
       const uint32_t npairs = cross ? ntiles : ntiles / 2;
-      const dim3 grid(npairs < kGqWgs ? npairs : kGqWgs, (unsigned)(cross ? nslots / 2 : nslots));
-      hipLaunchKernelGGL(k_gate_quant_pair<4>, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
-    } else {                        // short slices: general indexing
-      launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+      const uint32_t G = npairs < kGqWgs ? npairs : kGqWgs;
+      const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
+      hipLaunchKernelGGL(k_gate_quant_pair_pipe, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
+      return cross ? G : 2 * G;
     }
-    return;
+    return launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);  // short slices: general indexing
   }
   switch (kind) {
-    case 0: launch_gq_k<0>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass); break;
-    case 2: launch_gq_k<2>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass); break;
-    default: launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass); break;
+    case 0: return launch_gq_k<0>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+    case 2: return launch_gq_k<2>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+    default: return launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
   }
 }
 
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
-                     Ctl *ctl) {
-  hipLaunchKernelGGL(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, ctl);
+                     uint32_t nparts, Ctl *ctl) {
+  hipLaunchKernelGGL(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, nparts, ctl);
 }
 
 void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
-  // about four workgroups per CU over the batch, at least one chunk per wavefront
+  // about four workgroups per CU over the batch, at least one chunk per coding wavefront
   const uint64_t total = (uint64_t)nslots * g.nchunks;
   uint64_t cpb = total / 1024;
   if (cpb < kEncWaves) cpb = kEncWaves;
   if (cpb > g.nchunks) cpb = g.nchunks;
   dim3 grid(grid1(g.nchunks, (unsigned)cpb), (unsigned)nslots);
-  const size_t shm = (size_t)kEncWaves * sl.stage_words * 4;
-  hipLaunchKernelGGL(k_encode, grid, dim3(64 * kEncWaves), shm, st, sl, g, (uint32_t)cpb, ctl);
+  const size_t shm = (size_t)2 * kEncWaves * sl.stage_words * 4;
+  const dim3 block(64 * (kEncWaves + 1));
+  if (g.chunk_log2 <= 8) {
+    hipLaunchKernelGGL(k_encode<1>, grid, block, shm, st, sl, g, (uint32_t)cpb, ctl);
+    return;
+  }
+  // dynamic LDS above the default needs the attribute (chunks of 1024: ~70 KB)
+  static size_t shm_set = 0;
+  if (shm > shm_set) {
+    (void)hipFuncSetAttribute((const void *)k_encode<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipFuncSetAttribute((const void *)k_encode<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    shm_set = shm;
+  }
+  if (g.chunk_log2 == 9)
+    hipLaunchKernelGGL(k_encode<2>, grid, block, shm, st, sl, g, (uint32_t)cpb, ctl);
+  else
+    hipLaunchKernelGGL(k_encode<4>, grid, block, shm, st, sl, g, (uint32_t)cpb, ctl);
 }
 
 void launch_header(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
