@@ -45,6 +45,11 @@ extern "C" {
 #define SIM_EB_REL 0x1u  /* per slice: error_bound * max(max - min, 2^-24 max|a|) over its 2L values */
 #define SIM_FP64 0x0u    /* amplitudes and gate arithmetic in FP64 */
 #define SIM_PLAIN 0x0u   /* one pass per gate, exactly as in Algorithm 1 */
+#define SIM_FUSED 0x4u   /* runs of consecutive gates on at most SIM_FUSE_MAX qubits are applied
+                            as one dense block per pass (see sim_plan); blocks of 3 or more
+                            qubits run on FP64 matrix cores */
+
+#define SIM_FUSE_MAX 5   /* widest fused block, in qubits */
 
 /* ---- gate kinds */
 #define SIM_GATE_DENSE 1u /* 2^k x 2^k complex matrix on k = 1..5 targets, optional controls */
@@ -72,13 +77,31 @@ typedef struct sim_gate {
   const double *matrix;
 } sim_gate;
 
+/* One pass of a fused program (sim_plan).  Gates [first_gate, first_gate +
+ * n_gates) of the program form the pass.  fused == 0: a single gate, applied
+ * as in plain mode.  fused == 1: two or more gates whose qubits (targets and
+ * control bits) together are qubits[0..n_qubits), ascending; they are applied
+ * as the one 2^n_qubits x 2^n_qubits matrix U = G_last ... G_first, each
+ * gate embedded in the block's space (local bit i is qubits[i]) and the
+ * product formed left to right, U <- G U, with every term of every sum
+ * included in ascending order and the complex multiply-add of the gate
+ * kernels.  Layout is fixed: 40 bytes. */
+typedef struct sim_pass {
+  uint32_t first_gate;
+  uint32_t n_gates;
+  uint32_t fused;
+  uint32_t n_qubits;
+  uint32_t qubits[5];
+  uint32_t reserved;
+} sim_pass;
+
 /* Extended creation parameters; zero fields take the defaults. */
 typedef struct sim_config {
   int n_qubits;             /* 1..40 */
   int slice_log2;           /* L = 2^slice_log2 amplitudes per slice, 1..26, <= n_qubits */
   int chunk_log2;           /* B = 2^chunk_log2 values per coded chunk (0: 10), clipped to slice_log2 */
   double error_bound;       /* > 0 */
-  uint32_t mode;            /* SIM_EB_* | SIM_FP64 | SIM_PLAIN */
+  uint32_t mode;            /* SIM_EB_* | SIM_FP64 | SIM_PLAIN or SIM_FUSED */
   uint64_t workspace_bytes; /* budget for decompressed slices in flight (0: up to 16 GiB) */
   /* optional device-memory hooks used for every allocation of the handle
    * (e.g. a framework's caching allocator); both NULL: hipMalloc / hipFree */
@@ -141,7 +164,9 @@ int sim_set_allocator(sim_t *sim, void *(*alloc)(size_t, void *), void (*free_fn
 /* Enqueue all work of the handle on `hip_stream` (a hipStream_t) from now on. */
 int sim_set_stream(sim_t *sim, void *hip_stream);
 
-/* Apply gates[0..n) in order, one pass of Algorithm 1 per gate (Section II):
+/* Apply gates[0..n) in order, one pass of Algorithm 1 per gate (Section II),
+ * or in SIM_FUSED mode one pass per block of sim_plan's partition of the n
+ * gates (then *n_applied counts the gates of the completed passes):
  * for every slice group, decompress, normalise by the norm of the stored
  * state, apply the gate, recompress.  Gates whose targets are slice-index
  * qubits couple 2^m slices, which are processed together.  The gate array
@@ -151,6 +176,17 @@ int sim_set_stream(sim_t *sim, void *hip_stream);
  * SIM_EINVAL (bad gate; nothing after it runs), SIM_EBOUND, SIM_ENOMEM,
  * SIM_EDEVICE. */
 int sim_apply(sim_t *sim, const sim_gate *gates, size_t n, size_t *n_applied);
+
+/* The partition of gates[0..n) into passes that sim_apply uses in SIM_FUSED
+ * mode (host computation; needs no handle or device).  Greedy, in program
+ * order: a pass collects consecutive gates while the union of their qubits
+ * (targets and control bits of each gate; a phase gate's qubits are its
+ * control bits) has at most SIM_FUSE_MAX members; a gate that alone touches
+ * more qubits is a pass of its own.  A pass of one gate is plain.  The gates
+ * must be valid for n_qubits (SIM_EINVAL otherwise).  out (host memory,
+ * `cap` entries, may be NULL to count) receives the passes; *n_pass their
+ * number.  Returns SIM_ENOMEM if cap is too small (n_pass is still set). */
+int sim_plan(int n_qubits, const sim_gate *gates, size_t n, sim_pass *out, size_t cap, size_t *n_pass);
 
 /* Normalised amplitudes [begin, begin + count) into host memory `out`
  * (2 * count doubles, interleaved re, im): the stored state decompressed and

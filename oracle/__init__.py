@@ -45,6 +45,11 @@ class _Gate(C.Structure):
     ]
 
 
+class _Pass(C.Structure):
+    _fields_ = [("first", C.c_uint32), ("count", C.c_uint32), ("fused", C.c_uint32), ("k", C.c_uint32),
+                ("qubits", C.c_uint32 * 5), ("pad", C.c_uint32)]
+
+
 class _CStats(C.Structure):
     _fields_ = [("max_err", C.c_double), ("n_escapes", C.c_uint64), ("sumsq_lo", C.c_uint64),
                 ("sumsq_hi", C.c_uint64), ("step", C.c_double)]
@@ -97,6 +102,9 @@ def lib():
         L.orc_pass_group.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_uint32, C.POINTER(_Gate),
                                      C.c_double, C.c_int, P, P, P, P, P]
         L.orc_group_apply.argtypes = [C.POINTER(_Gate), C.c_int, C.c_int, P, P, P]
+        L.orc_plan.argtypes = [C.POINTER(_Gate), C.c_uint64, C.POINTER(_Pass), C.c_uint64, C.POINTER(C.c_uint64)]
+        L.orc_block_matrix.argtypes = [C.POINTER(_Gate), C.POINTER(_Pass), P]
+        L.orc_sim_apply_fused.argtypes = [C.c_void_p, C.POINTER(_Gate), C.c_uint64, C.POINTER(C.c_uint64)]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -344,6 +352,35 @@ def group_members(n: int, slice_log2: int, gate, j0: int) -> List[int]:
     return mem
 
 
+# ---------------------------------------------------------- fused passes
+
+def plan(gates: Sequence) -> List[Tuple[int, int, bool, Tuple[int, ...]]]:
+    """Fused-mode pass partition: (first gate, gate count, fused, qubits)."""
+    arr, keep = gate_array(gates)
+    n = C.c_uint64()
+    lib().orc_plan(arr, len(gates), None, 0, C.byref(n))
+    out = (_Pass * max(1, n.value))()
+    rc = lib().orc_plan(arr, len(gates), out, n.value, C.byref(n))
+    if rc:
+        raise OracleError(rc, "plan")
+    return [(p.first, p.count, bool(p.fused), tuple(p.qubits[i] for i in range(p.k))) for p in out[:n.value]]
+
+
+def block_matrix(gates: Sequence, first: int, count: int, qubits: Sequence[int]) -> np.ndarray:
+    """U = G_last ... G_first of gates[first:first + count] over `qubits`."""
+    arr, keep = gate_array(gates)
+    p = _Pass()
+    p.first, p.count, p.fused, p.k = first, count, 1, len(qubits)
+    for i, q in enumerate(qubits):
+        p.qubits[i] = q
+    dim = 1 << len(qubits)
+    U = np.zeros(2 * dim * dim)
+    rc = lib().orc_block_matrix(arr, C.byref(p), _ptr(U))
+    if rc:
+        raise OracleError(rc, "block_matrix")
+    return (U[0::2] + 1j * U[1::2]).reshape(dim, dim)
+
+
 # ------------------------------------------------------------- simulator
 
 class OracleSim:
@@ -380,10 +417,11 @@ class OracleSim:
         if rc:
             raise OracleError(rc, "sim_init")
 
-    def apply(self, gates: Sequence) -> int:
+    def apply(self, gates: Sequence, fused: bool = False) -> int:
         arr, keep = gate_array(gates)
         applied = C.c_uint64()
-        rc = lib().orc_sim_apply(self._h, arr, len(gates), C.byref(applied))
+        fn = lib().orc_sim_apply_fused if fused else lib().orc_sim_apply
+        rc = fn(self._h, arr, len(gates), C.byref(applied))
         if rc:
             raise OracleError(rc, f"sim_apply (after {applied.value} gates)")
         return applied.value

@@ -974,6 +974,189 @@ int orc_sim_apply(orc_sim *s, const orc_gate *gates, uint64_t ngates, uint64_t *
   return ORC_OK;
 }
 
+/* ------------------------------------------------------------ fused passes
+ * Fused mode (an extension of Algorithm 1 that changes only how gates are
+ * grouped into passes).  Walking the program in order, a pass takes
+ * consecutive gates for as long as the qubits they involve together number
+ * at most ORC_FUSE_MAX; a gate involves its target qubits and the qubits of
+ * its control mask (a phase gate only the latter).  A gate that by itself
+ * involves more qubits forms a pass alone.  A pass of one gate applies that
+ * gate; a pass of several applies, as one dense gate on its qubits in
+ * ascending order, the product U = G_last ... G_first of the gates written
+ * as matrices over those qubits (block index bit i is the i-th qubit). */
+#define ORC_FUSE_MAX 5
+
+typedef struct {
+  uint32_t first, count, fused, k;
+  uint32_t qubits[5];
+  uint32_t pad;
+} orc_pass;
+
+static uint64_t involved_qubits(const orc_gate *g) {
+  uint64_t q = g->ctrl_mask;
+  if (g->kind == ORC_DENSE)
+    for (uint32_t t = 0; t < g->n_targets; t++) q |= (uint64_t)1 << g->targets[t];
+  return q;
+}
+
+static int count_bits(uint64_t x) {
+  int c = 0;
+  while (x) {
+    x &= x - 1;
+    c++;
+  }
+  return c;
+}
+
+/* The pass partition; *npass receives the number of passes (out may be NULL
+ * to count only; ORC_ENOMEM if cap is too small). */
+int orc_plan(const orc_gate *gates, uint64_t n, orc_pass *out, uint64_t cap, uint64_t *npass) {
+  uint64_t np = 0, i = 0;
+  while (i < n) {
+    uint64_t q = involved_qubits(&gates[i]);
+    uint64_t end = i + 1;
+    while (count_bits(q) <= ORC_FUSE_MAX && end < n) {
+      uint64_t wider = q | involved_qubits(&gates[end]);
+      if (count_bits(wider) > ORC_FUSE_MAX) break;
+      q = wider;
+      end++;
+    }
+    if (out && np < cap) {
+      orc_pass *p = &out[np];
+      memset(p, 0, sizeof(*p));
+      p->first = (uint32_t)i;
+      p->count = (uint32_t)(end - i);
+      p->fused = p->count > 1;
+      if (p->fused)
+        for (uint32_t b = 0; b < 64; b++)
+          if (q & ((uint64_t)1 << b)) p->qubits[p->k++] = b;
+    }
+    np++;
+    i = end;
+  }
+  *npass = np;
+  return out && np > cap ? ORC_ENOMEM : ORC_OK;
+}
+
+/* Entry (row r, column c) of gate g written over the block qubits q[0..k):
+ * the amplitude that basis state c sends to basis state r. */
+static void gate_entry(const orc_gate *g, const uint32_t *q, uint32_t k, uint32_t r, uint32_t c, double *er,
+                       double *ei) {
+  /* block bit of each qubit of the gate */
+  int ctrl_ok = 1;
+  for (uint32_t i = 0; i < k; i++) {
+    uint64_t qb = (uint64_t)1 << q[i];
+    if (g->ctrl_mask & qb) ctrl_ok &= (((c >> i) & 1u) == ((g->ctrl_vals & qb) ? 1u : 0u));
+  }
+  *er = 0.0;
+  *ei = 0.0;
+  if (!ctrl_ok || g->kind == ORC_PHASE) {
+    if (r == c) {
+      if (ctrl_ok) {
+        *er = g->phase_re;
+        *ei = g->phase_im;
+      } else {
+        *er = 1.0;
+      }
+    }
+    return;
+  }
+  /* dense: the gate's row/column indices from the target bits, the other bits unchanged */
+  uint32_t gr = 0, gc = 0, rest_r = r, rest_c = c;
+  for (uint32_t t = 0; t < g->n_targets; t++) {
+    uint32_t pos = 0;
+    while (q[pos] != g->targets[t]) pos++;
+    gr |= ((r >> pos) & 1u) << t;
+    gc |= ((c >> pos) & 1u) << t;
+    rest_r &= ~(1u << pos);
+    rest_c &= ~(1u << pos);
+  }
+  if (rest_r != rest_c) return;
+  uint32_t gdim = 1u << g->n_targets;
+  *er = g->matrix[2 * (gr * gdim + gc)];
+  *ei = g->matrix[2 * (gr * gdim + gc) + 1];
+}
+
+/* U (2^k x 2^k, row-major, interleaved) of a fused pass. */
+int orc_block_matrix(const orc_gate *gates, const orc_pass *p, double *U) {
+  uint32_t k = p->k, dim = 1u << k;
+  double *G = (double *)malloc(sizeof(double) * 2 * dim * dim);
+  double *T = (double *)malloc(sizeof(double) * 2 * dim * dim);
+  if (!G || !T) {
+    free(G);
+    free(T);
+    return ORC_ENOMEM;
+  }
+  for (uint32_t r = 0; r < dim; r++)
+    for (uint32_t c = 0; c < dim; c++) {
+      U[2 * (r * dim + c)] = r == c ? 1.0 : 0.0;
+      U[2 * (r * dim + c) + 1] = 0.0;
+    }
+  for (uint32_t gi = p->first; gi < p->first + p->count; gi++) {
+    for (uint32_t r = 0; r < dim; r++)
+      for (uint32_t c = 0; c < dim; c++)
+        gate_entry(&gates[gi], p->qubits, k, r, c, &G[2 * (r * dim + c)], &G[2 * (r * dim + c) + 1]);
+    /* T = G U: every term, in ascending order */
+    for (uint32_t r = 0; r < dim; r++)
+      for (uint32_t c = 0; c < dim; c++) {
+        double tr = 0.0, ti = 0.0;
+        for (uint32_t m = 0; m < dim; m++)
+          cmac(G[2 * (r * dim + m)], G[2 * (r * dim + m) + 1], U[2 * (m * dim + c)], U[2 * (m * dim + c) + 1], &tr,
+               &ti);
+        T[2 * (r * dim + c)] = tr;
+        T[2 * (r * dim + c) + 1] = ti;
+      }
+    memcpy(U, T, sizeof(double) * 2 * dim * dim);
+  }
+  free(G);
+  free(T);
+  return ORC_OK;
+}
+
+/* Apply a program in fused mode; *applied counts the gates of completed
+ * passes. */
+int orc_sim_apply_fused(orc_sim *s, const orc_gate *gates, uint64_t ngates, uint64_t *applied) {
+  *applied = 0;
+  uint64_t np = 0;
+  orc_plan(gates, ngates, NULL, 0, &np);
+  orc_pass *plan = (orc_pass *)calloc(np ? np : 1, sizeof(orc_pass));
+  double *U = (double *)malloc(sizeof(double) * 2 * 32 * 32);
+  if (!plan || !U) {
+    free(plan);
+    free(U);
+    return ORC_ENOMEM;
+  }
+  orc_plan(gates, ngates, plan, np, &np);
+  int rc = ORC_OK;
+  for (uint64_t i = 0; i < np && rc == ORC_OK; i++) {
+    const orc_pass *p = &plan[i];
+    uint64_t one = 0;
+    if (!p->fused) {
+      rc = orc_sim_apply(s, &gates[p->first], 1, &one);
+    } else {
+      rc = orc_block_matrix(gates, p, U);
+      if (rc) break;
+      orc_gate g;
+      memset(&g, 0, sizeof(g));
+      if (p->k == 0) { /* global phases only */
+        g.kind = ORC_PHASE;
+        g.phase_re = U[0];
+        g.phase_im = U[1];
+      } else {
+        g.kind = ORC_DENSE;
+        g.n_targets = p->k;
+        for (uint32_t t = 0; t < p->k; t++) g.targets[t] = p->qubits[t];
+        g.matrix = U;
+      }
+      rc = orc_sim_apply(s, &g, 1, &one);
+    }
+    if (rc == ORC_OK) *applied += p->count;
+  }
+  free(plan);
+  free(U);
+  return rc;
+}
+
 /* Recompute one group's pass from given input records (used to check single
  * slices of a large state).  in_rec[u] belongs to slice mem[u]; scale is the
  * normalisation of the whole input state. */

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libcqsim.so")
 
 SIM_EB_ABS = 0x0
 SIM_EB_REL = 0x1
+SIM_FUSED = 0x4
 GATE_DENSE = 1
 GATE_PHASE = 2
 
@@ -31,7 +32,7 @@ ERRORS = {-1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EBOUND", -4: "SIM_ECORRUP
 # every entry point declared in include/cqsim.h
 EXPORTS = ("sim_create", "sim_create_ex", "sim_destroy", "sim_last_error", "sim_init_basis", "sim_init_product",
            "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_amplitudes", "sim_probabilities", "sim_stats",
-           "sim_record_size", "sim_export_slice", "sim_import_slice", "sim_kernel_times")
+           "sim_record_size", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan")
 
 
 class SimError(RuntimeError):
@@ -55,6 +56,11 @@ class ConfigStruct(C.Structure):
                 ("error_bound", C.c_double), ("mode", C.c_uint32), ("workspace_bytes", C.c_uint64),
                 ("alloc", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_ctx", C.c_void_p), ("stream", C.c_void_p),
                 ("arena_bytes", C.c_uint64)]
+
+
+class PassStruct(C.Structure):
+    _fields_ = [("first_gate", C.c_uint32), ("n_gates", C.c_uint32), ("fused", C.c_uint32),
+                ("n_qubits", C.c_uint32), ("qubits", C.c_uint32 * 5), ("reserved", C.c_uint32)]
 
 
 class StatsStruct(C.Structure):
@@ -100,6 +106,8 @@ def lib():
         L.sim_export_slice.argtypes = [P, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64)]
         L.sim_import_slice.argtypes = [P, C.c_uint64, P, C.c_uint64]
         L.sim_kernel_times.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_char_p)]
+        L.sim_plan.argtypes = [C.c_int, C.POINTER(GateStruct), C.c_size_t, C.POINTER(PassStruct), C.c_size_t,
+                               C.POINTER(C.c_size_t)]
         _lib = L
     return _lib
 
@@ -136,6 +144,17 @@ def gate_array(gates: Sequence):
         arr[i] = s
         keep.append(k)
     return arr, keep
+
+
+def plan(n_qubits: int, gates: Sequence) -> List[Tuple[int, int, bool, Tuple[int, ...]]]:
+    """sim_plan: the fused-mode passes as (first gate, gate count, fused, qubits)."""
+    arr, keep = gate_array(gates)
+    n = C.c_size_t()
+    _check(lib().sim_plan(n_qubits, arr, len(gates), None, 0, C.byref(n)), "sim_plan")
+    out = (PassStruct * max(1, n.value))()
+    _check(lib().sim_plan(n_qubits, arr, len(gates), out, n.value, C.byref(n)), "sim_plan")
+    return [(p.first_gate, p.n_gates, bool(p.fused), tuple(p.qubits[i] for i in range(p.n_qubits)))
+            for p in out[:n.value]]
 
 
 class _TorchMemory:
@@ -178,14 +197,14 @@ class Sim:
 
     def __init__(self, n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False,
                  chunk_log2: int = 0, workspace_bytes: int = 0, use_torch: Optional[bool] = None,
-                 arena_bytes: int = 0):
+                 arena_bytes: int = 0, fused: bool = False):
         L = lib()
         cfg = ConfigStruct()
         cfg.n_qubits = n_qubits
         cfg.slice_log2 = slice_log2
         cfg.chunk_log2 = chunk_log2
         cfg.error_bound = error_bound
-        cfg.mode = SIM_EB_REL if relative else SIM_EB_ABS
+        cfg.mode = (SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0)
         cfg.workspace_bytes = workspace_bytes
         cfg.arena_bytes = arena_bytes
         self._mem = None
@@ -201,6 +220,7 @@ class Sim:
         _check(L.sim_create_ex(C.byref(cfg), C.byref(h)), "sim_create")
         self._h = h
         self.n, self.slice_log2, self.error_bound, self.relative = n_qubits, slice_log2, error_bound, relative
+        self.fused = fused
         self.chunk_log2 = min(chunk_log2 or 10, slice_log2)
 
     def close(self):

@@ -48,9 +48,10 @@ int set_err(int code, const char *fmt, ...) {
   } while (0)
 
 enum KClass { K_BEGIN, K_RESET, K_INIT, K_DECODE, K_MINMAX, K_RELSTEP, K_GATEQ, K_CODEBOOK, K_ENCODE, K_HEADER,
-              K_COMPACT, K_READOUT, K_COUNT };
+              K_COMPACT, K_READOUT, K_DENSE, K_COUNT };
 const char *kClassNames =
-    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,encode,header,compact,readout";
+    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,encode,header,compact,readout,"
+    "dense_mfma";
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -88,6 +89,7 @@ struct sim_s {
   std::map<uint64_t, uint64_t *> tables;  // group mask -> slot order of all slices
   double *dmat = nullptr;
   size_t dmat_cap = 0;  // doubles
+  GateDesc ident{};     // the identity (kind 0): quantisation step of fused passes
   double *dfactors = nullptr;
   double *dstage = nullptr;
   size_t dstage_cap = 0;  // doubles
@@ -234,6 +236,119 @@ int slot_table(sim_t *s, uint64_t gm, const uint64_t **out) {
   return SIM_OK;
 }
 
+// ------------------------------------------------------------- fused passes
+// Qubits a gate acts on or depends on: targets and control bits (a phase
+// gate: its control bits).
+uint64_t gate_qubits(const sim_gate &g) {
+  uint64_t q = g.ctrl_mask;
+  if (g.kind == SIM_GATE_DENSE)
+    for (uint32_t k = 0; k < g.n_targets && k < 5; k++) q |= 1ull << g.targets[k];
+  return q;
+}
+
+struct PlanPass {
+  uint32_t first, count;
+  bool fused;
+  int k;          // block width (fused)
+  int qubits[5];  // ascending (fused)
+};
+
+// Greedy partition of a gate list into passes (the rule sim_plan documents).
+void plan_gates(const sim_gate *gates, size_t n, std::vector<PlanPass> &out) {
+  out.clear();
+  size_t i = 0;
+  while (i < n) {
+    uint64_t q = gate_qubits(gates[i]);
+    size_t j = i + 1;
+    if (__builtin_popcountll(q) <= SIM_FUSE_MAX) {
+      while (j < n) {
+        const uint64_t q2 = q | gate_qubits(gates[j]);
+        if (__builtin_popcountll(q2) > SIM_FUSE_MAX) break;
+        q = q2;
+        j++;
+      }
+    }
+    PlanPass p{};
+    p.first = (uint32_t)i;
+    p.count = (uint32_t)(j - i);
+    p.fused = p.count >= 2;
+    if (p.fused) {
+      for (int b = 0; b < 64; b++)
+        if ((q >> b) & 1) p.qubits[p.k++] = b;
+    }
+    out.push_back(p);
+    i = j;
+  }
+}
+
+// c += u * a in the order of the gate kernels
+inline void host_cmac(double ur, double ui, double ar, double ai, double &cr, double &ci) {
+  double pr = ur * ar;
+  double pi = ui * ai;
+  double qr = ur * ai;
+  double qi = ui * ar;
+  cr = cr + (pr - pi);
+  ci = ci + (qr + qi);
+}
+
+// U = G_last ... G_first of a fused pass, 2^k x 2^k complex, row-major,
+// interleaved; local bit i of a block index is qubit p.qubits[i].
+void block_matrix(const sim_gate *gates, const PlanPass &p, std::vector<double> &U) {
+  const uint32_t dim = 1u << p.k;
+  int loc[64];
+  for (int b = 0; b < 64; b++) loc[b] = -1;
+  for (int i = 0; i < p.k; i++) loc[p.qubits[i]] = i;
+  U.assign(2ull * dim * dim, 0.0);
+  for (uint32_t r = 0; r < dim; r++) U[2 * (r * dim + r)] = 1.0;
+  std::vector<double> G(2ull * dim * dim), T(2ull * dim * dim);
+  for (uint32_t gi = p.first; gi < p.first + p.count; gi++) {
+    const sim_gate &g = gates[gi];
+    std::fill(G.begin(), G.end(), 0.0);
+    // control bits as a local mask and values
+    uint32_t cmask = 0, cvals = 0;
+    for (int b = 0; b < 64; b++)
+      if ((g.ctrl_mask >> b) & 1) {
+        cmask |= 1u << loc[b];
+        if ((g.ctrl_vals >> b) & 1) cvals |= 1u << loc[b];
+      }
+    for (uint32_t c = 0; c < dim; c++) {
+      const bool on = (c & cmask) == cvals;
+      if (!on) {
+        G[2 * (c * dim + c)] = 1.0;
+        continue;
+      }
+      if (g.kind == SIM_GATE_PHASE) {
+        G[2 * (c * dim + c)] = g.phase_re;
+        G[2 * (c * dim + c) + 1] = g.phase_im;
+        continue;
+      }
+      const uint32_t kg = g.n_targets, gd = 1u << kg;
+      uint32_t tmask = 0, cm = 0;
+      for (uint32_t t = 0; t < kg; t++) {
+        const int lb = loc[g.targets[t]];
+        tmask |= 1u << lb;
+        cm |= ((c >> lb) & 1u) << t;
+      }
+      for (uint32_t rm = 0; rm < gd; rm++) {
+        uint32_t r = c & ~tmask;
+        for (uint32_t t = 0; t < kg; t++) r |= ((rm >> t) & 1u) << loc[g.targets[t]];
+        G[2 * (r * dim + c)] = g.matrix[2 * (rm * gd + cm)];
+        G[2 * (r * dim + c) + 1] = g.matrix[2 * (rm * gd + cm) + 1];
+      }
+    }
+    for (uint32_t r = 0; r < dim; r++)
+      for (uint32_t c = 0; c < dim; c++) {
+        double cr = 0.0, ci = 0.0;
+        for (uint32_t m = 0; m < dim; m++)
+          host_cmac(G[2 * (r * dim + m)], G[2 * (r * dim + m) + 1], U[2 * (m * dim + c)], U[2 * (m * dim + c) + 1],
+                    cr, ci);
+        T[2 * (r * dim + c)] = cr;
+        T[2 * (r * dim + c) + 1] = ci;
+      }
+    U.swap(T);
+  }
+}
+
 int validate_gate(const sim_t *s, const sim_gate &g, size_t idx) {
   const int n = s->geo.n;
   const uint64_t top = n >= 64 ? ~0ull : ((1ull << n) - 1);
@@ -335,16 +450,22 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
       launch_decode(st, s->slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass);
       s->kt_end();
     }
+    if (gd.kind == 4) {  // fused block on matrix cores, in place; then quantised as the identity
+      s->kt_begin(K_DENSE);
+      launch_dense_mfma(st, s->slots, s->geo, ns, gd, s->ctl);
+      s->kt_end();
+    }
     if (qp.rel) {
       s->kt_begin(K_MINMAX);
-      launch_gate_minmax(st, s->slots, s->geo, ss, ns, gd, s->ctl);
+      launch_gate_minmax(st, s->slots, s->geo, ss, ns, gd.kind == 4 ? s->ident : gd, s->ctl);
       s->kt_end();
       s->kt_begin(K_RELSTEP);
       launch_rel_step(st, s->slots, ns, qp.eb, s->ctl);
       s->kt_end();
     }
+    const GateDesc &gq = gd.kind == 4 ? s->ident : gd;
     s->kt_begin(K_GATEQ);
-    const uint32_t nparts = launch_gate_quant(st, s->slots, s->geo, ss, ns, gd, qp, s->ctl, pass);
+    const uint32_t nparts = launch_gate_quant(st, s->slots, s->geo, ss, ns, gq, qp, s->ctl, pass);
     s->kt_end();
     s->kt_begin(K_CODEBOOK);
     launch_codebook(st, s->slots, ss, ns, nxt, nparts, s->ctl);
@@ -463,7 +584,7 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
   if (sl2 < 1 || sl2 > n || sl2 > 26) return set_err(SIM_EINVAL, "slice_log2 %d outside 1..min(26, n)", sl2);
   if (!(cfg->error_bound > 0.0) || !std::isfinite(cfg->error_bound))
     return set_err(SIM_EINVAL, "error bound must be positive and finite");
-  if (cfg->mode & ~(SIM_EB_REL)) return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
+  if (cfg->mode & ~(SIM_EB_REL | SIM_FUSED)) return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
   int cl2 = cfg->chunk_log2 > 0 ? cfg->chunk_log2 : 10;
   if (cl2 > sl2) cl2 = sl2;
   if (cl2 > 10) return set_err(SIM_EINVAL, "chunk_log2 %d above 10", cl2);
@@ -602,40 +723,95 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
   if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
   size_t n_valid = 0;
   int vrc = SIM_OK;
-  size_t ndoubles = 0;
   for (; n_valid < n; n_valid++) {
     vrc = validate_gate(s, gates[n_valid], n_valid);
     if (vrc) break;
-    if (gates[n_valid].kind == SIM_GATE_DENSE) ndoubles += 2ull << (2 * gates[n_valid].n_targets);
   }
   std::string verr = vrc ? g_last_error : std::string();
-  if (ndoubles > s->dmat_cap) {
+  // passes: one per gate, or the fused partition of the valid gates
+  std::vector<PlanPass> plan;
+  if (s->mode & SIM_FUSED) {
+    plan_gates(gates, n_valid, plan);
+  } else {
+    plan.resize(n_valid);
+    for (size_t i = 0; i < n_valid; i++) plan[i] = PlanPass{(uint32_t)i, 1u, false, 0, {0, 0, 0, 0, 0}};
+  }
+  // host matrices of all passes, then one copy to the device
+  std::vector<double> hm;
+  std::vector<size_t> moff(plan.size(), 0);
+  std::vector<sim_gate> pg(plan.size());  // the gate each pass applies
+  std::vector<int> kind4(plan.size(), 0);
+  std::vector<double> U;
+  size_t n_pass = 0;
+  for (; n_pass < plan.size(); n_pass++) {
+    const PlanPass &p = plan[n_pass];
+    if (!p.fused) {
+      pg[n_pass] = gates[p.first];
+      if (pg[n_pass].kind == SIM_GATE_DENSE) {
+        const size_t cnt = 2ull << (2 * pg[n_pass].n_targets);
+        moff[n_pass] = hm.size();
+        hm.insert(hm.end(), pg[n_pass].matrix, pg[n_pass].matrix + cnt);
+      }
+      continue;
+    }
+    block_matrix(gates, p, U);
+    sim_gate g{};
+    if (p.k == 0) {  // global phases only
+      g.kind = SIM_GATE_PHASE;
+      g.phase_re = U[0];
+      g.phase_im = U[1];
+      pg[n_pass] = g;
+      continue;
+    }
+    g.kind = SIM_GATE_DENSE;
+    g.n_targets = (uint32_t)p.k;
+    for (int i = 0; i < p.k; i++) g.targets[i] = (uint32_t)p.qubits[i];
+    int m = 0;
+    for (int i = 0; i < p.k; i++) m += p.qubits[i] >= s->geo.slice_log2;
+    if ((1 << m) > s->W) {
+      vrc = set_err(SIM_ENOMEM, "fused pass %zu: group of %d slices exceeds the workspace", n_pass, 1 << m);
+      verr = g_last_error;
+      break;
+    }
+    moff[n_pass] = hm.size();
+    if (p.k <= 2) {  // narrow blocks run through the plain kernels
+      hm.insert(hm.end(), U.begin(), U.end());
+    } else {  // real embedding [[Ur, -Ui], [Ui, Ur]] for the matrix cores
+      const uint32_t dim = 1u << p.k, D = 2 * dim;
+      const size_t base = hm.size();
+      hm.resize(base + (size_t)D * D);
+      for (uint32_t r = 0; r < dim; r++)
+        for (uint32_t c = 0; c < dim; c++) {
+          const double ur = U[2 * (r * dim + c)], ui = U[2 * (r * dim + c) + 1];
+          hm[base + (size_t)r * D + c] = ur;
+          hm[base + (size_t)r * D + dim + c] = -ui;
+          hm[base + (size_t)(dim + r) * D + c] = ui;
+          hm[base + (size_t)(dim + r) * D + dim + c] = ur;
+        }
+      kind4[n_pass] = 1;
+    }
+    pg[n_pass] = g;
+  }
+  if (hm.size() > s->dmat_cap) {
     s->dfree(s->dmat);
     s->dmat = nullptr;
     s->dmat_cap = 0;
-    int rc = s->dalloc((void **)&s->dmat, 8 * ndoubles);
+    int rc = s->dalloc((void **)&s->dmat, 8 * hm.size());
     if (rc) return rc;
-    s->dmat_cap = ndoubles;
+    s->dmat_cap = hm.size();
   }
-  std::vector<double> hm(ndoubles);
-  std::vector<GateDesc> descs(n_valid);
-  std::vector<uint64_t> gms(n_valid);
-  size_t off = 0;
-  for (size_t i = 0; i < n_valid; i++) {
-    const sim_gate &g = gates[i];
-    const double *dm = nullptr;
-    if (g.kind == SIM_GATE_DENSE) {
-      size_t cnt = 2ull << (2 * g.n_targets);
-      memcpy(hm.data() + off, g.matrix, 8 * cnt);
-      dm = s->dmat + off;
-      off += cnt;
-    }
-    descs[i] = make_desc(s, g, dm, &gms[i]);
+  std::vector<GateDesc> descs(n_pass);
+  std::vector<uint64_t> gms(n_pass);
+  for (size_t i = 0; i < n_pass; i++) {
+    const bool dense = pg[i].kind == SIM_GATE_DENSE;
+    if (dense && plan[i].fused && !kind4[i]) pg[i].matrix = hm.data() + moff[i];  // host copy, read by make_desc
+    descs[i] = make_desc(s, pg[i], dense ? s->dmat + moff[i] : nullptr, &gms[i]);
+    if (kind4[i]) descs[i].kind = 4;
   }
-  if (ndoubles) HIP_TRY(hipMemcpy(s->dmat, hm.data(), 8 * ndoubles, hipMemcpyHostToDevice));
+  if (!hm.empty()) HIP_TRY(hipMemcpy(s->dmat, hm.data(), 8 * hm.size(), hipMemcpyHostToDevice));
   size_t applied = 0;
   HIP_TRY(hipEventRecord(s->ev0, s->stream));
-  int rc = n_valid ? run_passes(s, descs.data(), gms.data(), n_valid, -1, 0, &applied) : SIM_OK;
+  int rc = n_pass ? run_passes(s, descs.data(), gms.data(), n_pass, -1, 0, &applied) : SIM_OK;
   HIP_TRY(hipEventRecord(s->ev1, s->stream));
   HIP_TRY(hipEventSynchronize(s->ev1));
   float ms = 0;
@@ -643,11 +819,57 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
   s->elapsed += ms * 1e-3;
   s->passes += applied;
   if (s->kt_on) s->kt_flush();
-  if (n_applied) *n_applied = applied;
+  size_t gates_done = 0;
+  for (size_t i = 0; i < applied; i++) gates_done += plan[i].count;
+  if (n_applied) *n_applied = gates_done;
   if (rc) return rc;
   if (vrc) {
     g_last_error = verr;
     return vrc;
+  }
+  return SIM_OK;
+}
+
+// validity of a gate for n qubits (no handle: no workspace limits)
+static int check_gate_n(int n, const sim_gate &g, size_t idx) {
+  const uint64_t top = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  if (g.ctrl_mask & ~top) return set_err(SIM_EINVAL, "gate %zu: control mask beyond %d qubits", idx, n);
+  if (g.ctrl_vals & ~g.ctrl_mask) return set_err(SIM_EINVAL, "gate %zu: control values outside the mask", idx);
+  if (g.kind == SIM_GATE_PHASE) return SIM_OK;
+  if (g.kind != SIM_GATE_DENSE) return set_err(SIM_EINVAL, "gate %zu: unknown kind %u", idx, g.kind);
+  if (g.n_targets < 1 || g.n_targets > 5) return set_err(SIM_EINVAL, "gate %zu: %u targets", idx, g.n_targets);
+  if (!g.matrix) return set_err(SIM_EINVAL, "gate %zu: no matrix", idx);
+  uint64_t tm = 0;
+  for (uint32_t k = 0; k < g.n_targets; k++) {
+    if ((int)g.targets[k] >= n) return set_err(SIM_EINVAL, "gate %zu: target %u beyond %d qubits", idx, g.targets[k], n);
+    if (tm & (1ull << g.targets[k])) return set_err(SIM_EINVAL, "gate %zu: repeated target", idx);
+    tm |= 1ull << g.targets[k];
+  }
+  if (tm & g.ctrl_mask) return set_err(SIM_EINVAL, "gate %zu: controls overlap targets", idx);
+  return SIM_OK;
+}
+
+int sim_plan(int n_qubits, const sim_gate *gates, size_t n, sim_pass *out, size_t cap, size_t *n_pass) {
+  if (n_pass) *n_pass = 0;
+  if (n_qubits < 1 || n_qubits > 40) return set_err(SIM_EINVAL, "n_qubits %d out of range", n_qubits);
+  if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
+  for (size_t i = 0; i < n; i++) {
+    int rc = check_gate_n(n_qubits, gates[i], i);
+    if (rc) return rc;
+  }
+  std::vector<PlanPass> plan;
+  plan_gates(gates, n, plan);
+  if (n_pass) *n_pass = plan.size();
+  if (!out) return SIM_OK;
+  if (cap < plan.size()) return set_err(SIM_ENOMEM, "%zu passes do not fit %zu entries", plan.size(), cap);
+  for (size_t i = 0; i < plan.size(); i++) {
+    sim_pass &o = out[i];
+    memset(&o, 0, sizeof(o));
+    o.first_gate = plan[i].first;
+    o.n_gates = plan[i].count;
+    o.fused = plan[i].fused ? 1u : 0u;
+    o.n_qubits = plan[i].fused ? (uint32_t)plan[i].k : 0u;
+    for (int k = 0; k < plan[i].k; k++) o.qubits[k] = (uint32_t)plan[i].qubits[k];
   }
   return SIM_OK;
 }

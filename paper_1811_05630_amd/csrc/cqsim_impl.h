@@ -57,7 +57,8 @@ struct Ctl {
 // target k sits at local bit tloc[k] (targets below slice_log2 keep their bit,
 // slice-bit targets are renumbered slice_log2, slice_log2 + 1, ... in order).
 struct GateDesc {
-  int kind;               // 0: identity, 1: dense, 2: phase
+  int kind;               // 0: identity, 1: dense, 2: phase, 4: fused dense block of 3..5
+                          // qubits on matrix cores (mat: its 2^(k+1) square real embedding)
   int k;                  // number of targets
   int m;                  // slice-bit targets
   int pad0;
@@ -148,6 +149,9 @@ void launch_header(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
                    uint32_t pass);
 void launch_compact(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                     uint8_t *arena, const StateMeta &nxt, Ctl *ctl);
+// fused block (kind 4) applied in place to the decompressed slots
+void launch_dense_mfma(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const GateDesc &gd,
+                       const Ctl *ctl);
 void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,
                     int probabilities, double *out);
 

@@ -577,7 +577,7 @@ __device__ __forceinline__ void add_squares(const double (&qr)[V], const double 
                                             uint64_t &hi) {
   bool small = true;
 #pragma unroll
-  for (int v = 0; v < V; v++) small &= (fabs(qr[v]) < 2147483648.0) & (fabs(qi[v]) < 2147483648.0);
+  for (int v = 0; v < V; v++) small = small && fabs(qr[v]) < 2147483648.0 && fabs(qi[v]) < 2147483648.0;
   if (__ballot(!small) == 0) {
 #pragma unroll
     for (int v = 0; v < V; v++) {
@@ -798,7 +798,7 @@ __device__ __forceinline__ void tile_symbols_full(const double (&qr)[V], const d
   const uint32_t Bm = (1u << g.chunk_log2) - 1;
   bool small = true;
 #pragma unroll
-  for (int v = 0; v < V; v++) small &= (fabs(qr[v]) < 0x1p24) & (fabs(qi[v]) < 0x1p24);
+  for (int v = 0; v < V; v++) small = small && fabs(qr[v]) < 0x1p24 && fabs(qi[v]) < 0x1p24;
   const bool wbig = __ballot(!small) != 0;
   if (lane == 63) {
 #pragma unroll
@@ -816,7 +816,7 @@ __device__ __forceinline__ void tile_symbols_full(const double (&qr)[V], const d
     double dr[V], di[V];
 #pragma unroll
     for (int v = 0; v < V; v++) {
-      acc.ok &= (fabs(qr[v]) < kPMax) & (fabs(qi[v]) < kPMax);
+      acc.ok = acc.ok && fabs(qr[v]) < kPMax && fabs(qi[v]) < kPMax;
       const uint32_t o = ob + v * T + tid;
       const double up_r = __shfl_up(qr[v], 1, 64), up_i = __shfl_up(qi[v], 1, 64);
       double pr = 0.0, pi = 0.0;  // predecessor in the chunk (0 at a chunk head)
@@ -1887,6 +1887,86 @@ __global__ void __launch_bounds__(256) k_compact(Slots sl, Geo g, const uint64_t
     const uint32_t w0 = offs[c], nw = offs[c + 1] - w0;
     const uint32_t *src = sl.stage + ((uint64_t)u * g.nchunks + c) * sl.stage_words;
     for (uint32_t i = lane; i < nw; i += 64) words[w0 + i] = src[i];
+  }
+}
+
+// ------------------------------------------------------------ fused blocks
+// A dense block of K = 3..5 qubits (several gates fused on the host) applied
+// in place to the decompressed slots on FP64 matrix cores.  With the real
+// embedding M = [[Ur, -Ui], [Ui, Ur]] (D = 2^(K+1) rows) and, for a base
+// amplitude b (all target bits clear), x_b = (re of its 2^K members, im of
+// its 2^K members), the outputs are y_b = M x_b.  A wavefront takes 16 bases
+// at a time: Y (D x 16) = M (D x D) X (D x 16) in (D / 16) x (D / 4)
+// v_mfma_f64_16x16x4f64 steps.  Operand layouts of that instruction: A
+// (16 x 4): lane l holds A[l % 16][l / 16]; B (4 x 16): lane l holds
+// B[l / 16][l % 16]; C and D (16 x 16): register i of lane l holds
+// D[4 i + l / 16][l % 16] for i = 0..3.  Member c of base b has the flat batch index f_b | dep[c],
+// where f_b is the base counter with a zero inserted at every target bit.
+// A wavefront reads all inputs of its 16 bases before it writes their
+// outputs, and no two wavefronts share a base, so updating in place is safe.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+__global__ void __launch_bounds__(256) k_dense_mfma(Slots sl, Geo g, GateDesc gd, uint64_t nbases, const Ctl *ctl) {
+  if (ctl->flags) return;
+  constexpr int NM = 1 << K, D = 2 * NM, RB = D / 16, KS = D / 4;
+  const uint32_t lane = lane_id(), col = lane & 15u, quad = lane >> 4;
+  double a[RB][KS];  // this lane's entries of M for every step
+#pragma unroll
+  for (int R = 0; R < RB; R++)
+#pragma unroll
+    for (int s = 0; s < KS; s++) a[R][s] = gd.mat[(uint64_t)(16 * R + col) * D + 4 * s + quad];
+  const uint64_t L = g.L;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwv = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t jb = wave * 16; jb < nbases; jb += nwv * 16) {
+    const uint64_t j = jb + col;
+    const bool valid = j < nbases;
+    uint64_t f = valid ? j : jb;  // lanes past the last base read base jb and store nothing
+#pragma unroll
+    for (int t = 0; t < K; t++) {  // target positions ascend
+      const int p = gd.tloc[t];
+      f = ((f >> p) << (p + 1)) | (f & ((1ull << p) - 1));
+    }
+    double x[KS];
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+      const uint32_t r = 4 * s + quad;
+      const uint64_t fm = f | gd.dep[r & (NM - 1)];
+      x[s] = sl.ws[(fm >> g.slice_log2) * 2 * L + (r >= (uint32_t)NM ? L : 0) + (fm & (L - 1))];
+    }
+    dbl4 acc[RB];
+#pragma unroll
+    for (int R = 0; R < RB; R++) acc[R] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < KS; s++)
+#pragma unroll
+      for (int R = 0; R < RB; R++) acc[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[R][s], x[s], acc[R], 0, 0, 0);
+    if (valid) {
+#pragma unroll
+      for (int R = 0; R < RB; R++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const uint32_t r = 16 * R + 4 * i + quad;
+          const uint64_t fm = f | gd.dep[r & (NM - 1)];
+          sl.ws[(fm >> g.slice_log2) * 2 * L + (r >= (uint32_t)NM ? L : 0) + (fm & (L - 1))] = acc[R][i];
+        }
+    }
+  }
+}
+
+void launch_dense_mfma(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const GateDesc &gd,
+                       const Ctl *ctl) {
+  const uint64_t nbases = ((uint64_t)nslots * g.L) >> gd.k;
+  const uint64_t waves = (nbases + 15) / 16;
+  uint64_t blocks = (waves + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  const dim3 grid((unsigned)blocks), block(256);
+  switch (gd.k) {
+    case 3: hipLaunchKernelGGL(k_dense_mfma<3>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
+    case 4: hipLaunchKernelGGL(k_dense_mfma<4>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
+    default: hipLaunchKernelGGL(k_dense_mfma<5>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
   }
 }
 

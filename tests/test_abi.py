@@ -45,6 +45,8 @@ int main(void) {
   printf("sim_gate %zu\n", sizeof(sim_gate));
   printf("sim_config %zu\n", sizeof(sim_config));
   printf("sim_stats_t %zu\n", sizeof(sim_stats_t));
+  printf("sim_pass %zu\n", sizeof(sim_pass));
+  F(sim_pass, n_qubits); F(sim_pass, qubits);
   F(sim_gate, targets); F(sim_gate, ctrl_mask); F(sim_gate, phase_re); F(sim_gate, matrix);
   F(sim_config, error_bound); F(sim_config, workspace_bytes); F(sim_config, alloc); F(sim_config, stream);
   F(sim_config, arena_bytes);
@@ -64,7 +66,8 @@ def test_struct_layouts_match_header():
     got = dict(line.split() for line in out.strip().splitlines())
     py = {
         "sim_gate": C.sizeof(cq.GateStruct), "sim_config": C.sizeof(cq.ConfigStruct),
-        "sim_stats_t": C.sizeof(cq.StatsStruct),
+        "sim_stats_t": C.sizeof(cq.StatsStruct), "sim_pass": C.sizeof(cq.PassStruct),
+        "sim_pass.n_qubits": cq.PassStruct.n_qubits.offset, "sim_pass.qubits": cq.PassStruct.qubits.offset,
         "sim_gate.targets": cq.GateStruct.targets.offset, "sim_gate.ctrl_mask": cq.GateStruct.ctrl_mask.offset,
         "sim_gate.phase_re": cq.GateStruct.phase_re.offset, "sim_gate.matrix": cq.GateStruct.matrix.offset,
         "sim_config.error_bound": cq.ConfigStruct.error_bound.offset,
@@ -77,6 +80,7 @@ def test_struct_layouts_match_header():
     }
     assert {k: int(v) for k, v in got.items()} == py
     assert py["sim_gate"] == 72
+    assert py["sim_pass"] == 40
 
 
 def test_binding_converts_gates_without_the_device():
