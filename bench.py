@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_F64_PEAK_TFLOPS = 78.6
 METRIC = "state amps/s via decompress+gate+compress at error bound; ratio; p99 latency"
 KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 
@@ -53,6 +54,9 @@ def parse():
     ap.add_argument("--chunk-log2", type=int, default=8)
     ap.add_argument("--latency-passes", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", choices=("grover24", "qft30", "grover34"), default="grover24",
+                    help="grover24 (default, the headline line); qft30: 30-qubit QFT of a product state in "
+                         "fused mode; grover34: a window of 34-qubit Grover search")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 256 MiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -120,16 +124,67 @@ def copy_probe():
                       "launches": reps, "ms_per_launch": ms, "GBps": 16 * n / ms / 1e6}), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(the multi-GPU slice sharding is a design, not an implementation)", file=sys.stderr)
-        sys.exit(2)
-    if args.copy_probe:
-        copy_probe()
-        return
+def report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config, mfma_flops=None, extra=None):
+    """The JSON line shared by all workloads."""
     import numpy as np
+    N = 1 << w.n_qubits
+    comp = st2["compressed_bytes"]
+    esc = (st2["escapes"] - st1["escapes"]) / K  # escapes coded per pass
+    ms_launch = {k: v[0] / v[1] for k, v in kt.items() if v[1] > 0}
+    per_pass = {k: v[1] / K for k, v in kt.items() if v[1] > 0}
+    dom = max((k for k in ms_launch if k in ("decode", "gate_quant", "codebook", "encode", "header", "compact",
+                                               "dense_mfma")), key=lambda k: kt[k][0])
+    avg_ms = ms_launch[dom]
+    if dom == "dense_mfma":
+        flops = mfma_flops / kt[dom][1]  # per launch
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / MFMA_F64_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flops_per_launch": flops, "avg_launch_ms": avg_ms}
+    else:
+        algo = kernel_bytes(dom, N, comp, comp, sim.nslices, esc) / per_pass[dom]
+        achieved = algo / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic_for(dom) if args.workload == "grover24" else None,
+                "algorithmic_bytes_per_launch": algo, "avg_launch_ms": avg_ms}
+    pipe_bytes = 2 * 16 * N + 2 * comp  # B_alg: planes written and read once + records in and out
+    pipe_achieved = pipe_bytes * K / dt / 1e9
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "amps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": dt / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": config,
+        "ratio": N * 16 / comp,
+        "min_ratio": st2["min_ratio"],
+        "max_abs_codec_err": st2["max_abs_codec_err"],
+        "kernel_ms_per_launch": ms_launch,
+        "kernel_launches_per_pass": per_pass,
+        "roofline": roof,
+        "pipeline_roofline": {"bytes_per_pass": pipe_bytes, "achieved": pipe_achieved, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": pipe_achieved / HBM_PEAK_GBS},
+    }
+    if lat:
+        line["latency_ms_per_pass"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+    if mfma_flops and "dense_mfma" in kt and kt["dense_mfma"][0] > 0:
+        t = mfma_flops / (kt["dense_mfma"][0] * 1e-3) / 1e12
+        line["mfma"] = {"achieved": t, "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": t / MFMA_F64_PEAK_TFLOPS}
+    if extra:
+        line.update(extra)
+    return line
+
+
+def run_grover24(args):
     import torch
     import paper_1811_05630_amd as cq
     import qcircuits as qc
@@ -171,51 +226,146 @@ def main():
         a = time.perf_counter()
         sim.apply(gates[pos + i:pos + i + 1])
         lat.append((time.perf_counter() - a) * 1e3)
-    pos += args.latency_passes
-
-    comp = st2["compressed_bytes"]
-    esc = (st2["escapes"] - st1["escapes"]) / K  # escapes coded per pass
-    ms_launch = {k: v[0] / v[1] for k, v in kt.items() if v[1] > 0}
-    dom = max((k for k in ms_launch if k in ("decode", "gate_quant", "codebook", "encode", "header", "compact")),
-              key=lambda k: kt[k][0])
-    avg_ms = ms_launch[dom]
-    algo = kernel_bytes(dom, N, comp, comp, sim.nslices, esc)
-    achieved = algo / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_for(dom)
-    pipe_bytes = 2 * 16 * N + 2 * comp  # B_alg: planes written and read once + records in and out
-    pipe_achieved = pipe_bytes * K / dt / 1e9
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "amps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": Wm,
-        "ms_per_step": dt / K * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "grover24: 24-qubit Grover search, marked index from seed 0, 64 slices of 2^18 "
-                               "amplitudes, absolute bound 1e-7, plain mode (one pass per gate)",
-                   "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
-                   "error_bound": w.error_bound, "passes_timed": K, "first_timed_gate": n + Wm},
-        "ratio": N * 16 / comp,
-        "min_ratio": st2["min_ratio"],
-        "max_abs_codec_err": st2["max_abs_codec_err"],
-        "latency_ms_per_pass": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "kernel_ms_per_launch": ms_launch,
-        "kernel_launches_per_pass": {k: v[1] / K for k, v in kt.items() if v[1] > 0},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": algo, "avg_launch_ms": avg_ms},
-        "pipeline_roofline": {"bytes_per_pass": pipe_bytes, "achieved": pipe_achieved, "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": pipe_achieved / HBM_PEAK_GBS},
-    }
+    config = {"workload": "grover24: 24-qubit Grover search, marked index from seed 0, 64 slices of 2^18 "
+                          "amplitudes, absolute bound 1e-7, plain mode (one pass per gate)",
+              "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
+              "error_bound": w.error_bound, "passes_timed": K, "first_timed_gate": n + Wm}
+    line = report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.chunk_log2)
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def run_qft30(args):
+    """30-qubit QFT of a seeded product state in fused mode: 256 slices of
+    2^22, relative bound 1e-4.  One step is one fused pass; the timed region
+    is the whole circuit (after one untimed run of it)."""
+    import torch
+    import paper_1811_05630_amd as cq
+    import qcircuits as qc
+
+    w = qc.qft_product_workload(seed=args.seed)
+    n, N = w.n_qubits, 1 << w.n_qubits
+    plan = cq.plan(n, w.gates)
+    K = len(plan)
+    flops = sum(8 * (1 << len(q)) * N for (_, _, fused, q) in plan if fused and len(q) >= 3)
+    sim = cq.Sim(n, w.slice_log2, w.error_bound, relative=True, chunk_log2=args.chunk_log2, fused=True,
+                 workspace_bytes=64 << 30, arena_bytes=4 << 30)
+    sim.init_product(w.factors)
+    sim.apply(w.gates)  # warm-up: the whole circuit once
+    sim.init_product(w.factors)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.apply(w.gates)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sim.init_product(w.factors)
+    st1 = sim.stats()
+    sim.kernel_times(True)
+    sim.apply(w.gates)
+    torch.cuda.synchronize()
+    kt = sim.kernel_times(False)
+    st2 = sim.stats()
+    config = {"workload": "qft30_product: 30-qubit QFT of a product state (angles from seed 0), 256 slices of "
+                          "2^22 amplitudes, relative bound 1e-4, fused mode (blocks of up to 5 qubits)",
+              "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
+              "error_bound": w.error_bound, "gates": len(w.gates), "passes": K,
+              "workspace_slots": st2["workspace_slots"]}
+    extra = {"gate_amps_per_s": len(w.gates) * N / dt}
+    line = report(args, w, sim, K * N / dt, K, 1, dt, kt, st1, st2, None, config, mfma_flops=flops, extra=extra)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_sample(w, args.cpu_seconds, args.chunk_log2, fused_k=5)
+    return line
+
+
+def run_grover34(args):
+    """A window of 34-qubit Grover search (1024 slices of 2^24, absolute bound
+    1e-8): the first passes of the H layer untimed, the next `steps` passes
+    timed."""
+    import torch
+    import paper_1811_05630_amd as cq
+    import qcircuits as qc
+
+    w = qc.grover_workload(n=34, slice_log2=24, eb=1e-8, seed=args.seed, iterations=2)
+    n, N = w.n_qubits, 1 << w.n_qubits
+    K = min(args.steps, 20)
+    Wm = min(args.warmup, 10)
+    sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, workspace_bytes=96 << 30,
+                 arena_bytes=48 << 30)
+    g = w.gates
+    sim.apply(g[:Wm])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.apply(g[Wm:Wm + K])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st1 = sim.stats()
+    sim.kernel_times(True)
+    sim.apply(g[Wm + K:Wm + 2 * K])
+    torch.cuda.synchronize()
+    kt = sim.kernel_times(False)
+    st2 = sim.stats()
+    config = {"workload": "grover34 window: 34-qubit Grover search (marked index from seed 0), 1024 slices of "
+                          "2^24 amplitudes, absolute bound 1e-8, plain mode; passes %d..%d timed"
+                          % (Wm, Wm + K - 1),
+              "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
+              "error_bound": w.error_bound, "passes_timed": K, "workspace_slots": st2["workspace_slots"]}
+    line = report(args, w, sim, K * N / dt, K, Wm, dt, kt, st1, st2, None, config)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_sample(w, args.cpu_seconds, args.chunk_log2, fused_k=0)
+    return line
+
+
+def cpu_sample(w, seconds, chunk_log2, fused_k):
+    """The oracle on a bounded sample of a large workload: one slice of the
+    workload's shape, compressed by the oracle itself, put through repeated
+    single-slice passes (a 5-qubit dense block for the fused workload, else
+    H on qubit 3) on one host thread."""
+    import numpy as np
+    import oracle
+    import qcircuits as qc
+    L = 1 << w.slice_log2
+    mode = oracle.REL if w.relative else oracle.ABS
+    if w.factors is not None:  # the product state's first slice
+        f = np.asarray(w.factors)
+        amp = np.ones(L, dtype=complex)
+        idx = np.arange(L)
+        for q in range(w.slice_log2):
+            amp *= np.where((idx >> q) & 1, f[q, 1], f[q, 0])
+        amp *= np.prod(f[w.slice_log2:, 0])
+    else:  # the state after the H layer
+        amp = np.full(L, 2.0 ** (-w.n_qubits / 2), dtype=complex)
+    rec, _ = oracle.compress_slice(amp.real.copy(), amp.imag.copy(), w.slice_log2, chunk_log2, w.error_bound, mode)
+    if fused_k:
+        r = np.random.default_rng(1)
+        a = r.standard_normal((32, 32)) + 1j * r.standard_normal((32, 32))
+        gate = qc.U([0, 1, 2, 3, 4], np.linalg.qr(a)[0])
+    else:
+        gate = qc.H(3)
+    oracle.set_threads(1)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        rec = oracle.pass_group(w.n_qubits, w.slice_log2, chunk_log2, w.error_bound, mode, gate,
+                                1.0, [0], [rec])[0]
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done * L / dt, "unit": "amps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} single-slice passes ({'5-qubit dense block' if fused_k else 'H on qubit 3'}) "
+                      f"over one slice of 2^{w.slice_log2} amplitudes, {dt:.1f} s, one thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(the multi-GPU slice sharding is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    run = {"grover24": run_grover24, "qft30": run_qft30, "grover34": run_grover34}[args.workload]
+    print(json.dumps(run(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -506,22 +506,23 @@ __device__ __forceinline__ bool quantise(double v, double step, double recip, do
   return err <= ebj;
 }
 
-// relative bound: min/max of the gate's output over every slot.  Workgroups
-// are whole wavefronts; a workgroup covers C = min(blockDim, L) amplitudes of
-// one slot and threads past C only take part in the reductions.
+// relative bound: min/max of the gate's output over every slot.  Workgroup
+// (x, u) of G per slot takes amplitudes x * T + tid, stepping by G * T,
+// reduces them, and adds its result with one atomic per workgroup (the
+// keys are order-preserving integers, so min/max are exact).
 template <int KIND>
 __global__ void __launch_bounds__(256) k_gate_minmax(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
                                                      const Ctl *ctl) {
   if (ctl->flags) return;
-  const uint64_t C = (uint64_t)blockDim.x < g.L ? (uint64_t)blockDim.x : g.L;
-  const uint64_t i = (uint64_t)blockIdx.x * C + threadIdx.x;
-  const uint32_t u = (uint32_t)(((uint64_t)blockIdx.x * C) >> g.slice_log2);
+  const uint32_t u = blockIdx.y, T = blockDim.x;
   uint64_t kmin = ~0ull, kmax = 0ull;
-  if (threadIdx.x < C) {
+  for (uint64_t o = (uint64_t)blockIdx.x * T + threadIdx.x; o < g.L; o += (uint64_t)gridDim.x * T) {
     double re, im;
-    eval_amp<KIND>(sl.ws, g, slot_slice, gd, u, i & (g.L - 1), re, im);
-    kmin = dkey(re) < dkey(im) ? dkey(re) : dkey(im);
-    kmax = dkey(re) < dkey(im) ? dkey(im) : dkey(re);
+    eval_amp<KIND>(sl.ws, g, slot_slice, gd, u, o, re, im);
+    const uint64_t a = dkey(re), b = dkey(im);
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    kmin = lo < kmin ? lo : kmin;
+    kmax = hi > kmax ? hi : kmax;
   }
   for (int off = 32; off > 0; off >>= 1) {
     uint64_t a = __shfl_xor(kmin, off, 64), b = __shfl_xor(kmax, off, 64);
@@ -535,7 +536,7 @@ __global__ void __launch_bounds__(256) k_gate_minmax(Slots sl, Geo g, const uint
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (uint32_t w = 1; w < blockDim.x / 64; w++) {
+    for (uint32_t w = 1; w < T / 64; w++) {
       kmin = smin[w] < kmin ? smin[w] : kmin;
       kmax = smax[w] > kmax ? smax[w] : kmax;
     }
@@ -2030,9 +2031,11 @@ template <int KIND>
 static void launch_minmax_k(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
                             const GateDesc &gd, const Ctl *ctl) {
   const int threads = g.L >= 256 ? 256 : 64;
-  const uint64_t C = (uint64_t)threads < g.L ? (uint64_t)threads : g.L;
-  const uint64_t total = (uint64_t)nslots * g.L;
-  hipLaunchKernelGGL(k_gate_minmax<KIND>, dim3((unsigned)(total / C)), dim3(threads), 0, st, sl, g, ss, gd, ctl);
+  const uint64_t per_wg = (uint64_t)threads * 16;  // at least 16 amplitudes per thread
+  uint64_t G = (g.L + per_wg - 1) / per_wg;
+  if (G > 64) G = 64;
+  hipLaunchKernelGGL(k_gate_minmax<KIND>, dim3((unsigned)G, (unsigned)nslots), dim3(threads), 0, st, sl, g, ss, gd,
+                     ctl);
 }
 
 void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
