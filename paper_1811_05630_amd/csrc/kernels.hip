@@ -1309,6 +1309,298 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant_pair_pipe(Slots sl, Geo g
   write_partial(accB, hB, wred, sl, uB, cross ? blockIdx.x : gridDim.x + blockIdx.x, ctl, pass);
 }
 
+// ------------------------------------------ gate + quantise, wave ranges
+// For chunks of at most 256 values, every wavefront works alone on ranges of
+// 256 consecutive amplitudes of a slot (element v * 64 + lane, v < 4).  A
+// range starts at a chunk head, so the Lorenzo predecessor of an element is
+// in the same wavefront (the lane below, or lane 63 at v - 1): the range loop
+// has no workgroup barrier, and the workgroup shares only the LDS histogram.
+// Loads are pipelined as in the whole-tile kernels: [loads of this range]
+// [stores of the previous range] [loads of the next range].
+
+constexpr uint32_t kWr = 256;  // amplitudes per wavefront range
+
+struct WRange {
+  double r[4], i[4];
+};
+
+__device__ __forceinline__ void wr_load(WRange &x, __amdgpu_buffer_rsrc_t ws, uint32_t L, uint32_t ob) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    x.r[v] = buf_ld_f64(ws, 8 * (ob + v * 64 + lane));
+    x.i[v] = buf_ld_f64(ws, 8 * (L + ob + v * 64 + lane));
+  }
+}
+
+__device__ __forceinline__ double lane63(double x) {  // the value of lane 63, in every lane
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Symbols, escapes, squares and histogram of one range at offset ob (a
+// chunk head).  Integer path when every |q| of the wavefront is below 2^24
+// (the choice only changes the arithmetic, not the result).
+__device__ __forceinline__ void wr_symbols(const double (&qr)[4], const double (&qi)[4], uint32_t *h, const Geo &g,
+                                           const SlotBuf &sb, uint32_t ob, Acc &acc) {
+  const uint32_t lane = lane_id();
+  const uint32_t Bm = (1u << g.chunk_log2) - 1;
+  bool small = true;
+#pragma unroll
+  for (int v = 0; v < 4; v++) small = small && fabs(qr[v]) < 0x1p24 && fabs(qi[v]) < 0x1p24;
+  uint32_t sr[4], si[4];
+  bool any_esc = false;
+  if (__ballot(!small) != 0) {
+    double dr[4], di[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      acc.ok = acc.ok && fabs(qr[v]) < kPMax && fabs(qi[v]) < kPMax;
+      const uint32_t o = ob + v * 64 + lane;
+      double pr = __shfl_up(qr[v], 1, 64), pi = __shfl_up(qi[v], 1, 64);
+      if (v > 0) {
+        const double lr = lane63(qr[v - 1]), li = lane63(qi[v - 1]);
+        if (lane == 0) {
+          pr = lr;
+          pi = li;
+        }
+      }
+      if ((o & Bm) == 0) pr = pi = 0.0;  // chunk head: predictor 0
+      dr[v] = qr[v] - pr;  // exact: integers below 2^49
+      di[v] = qi[v] - pi;
+      const bool er = !(fabs(dr[v]) < (double)kR), ei = !(fabs(di[v]) < (double)kR);
+      sr[v] = er ? 0u : (uint32_t)((int)dr[v] + kR);
+      si[v] = ei ? 0u : (uint32_t)((int)di[v] + kR);
+      any_esc = any_esc || er || ei;
+      acc.nesc += (uint32_t)er + (uint32_t)ei;
+      buf_st_u16(sb.sym, 2 * o, sr[v]);
+      buf_st_u16(sb.sym, 2 * (sb.L + o), si[v]);
+    }
+    if (__ballot(any_esc)) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const uint32_t o = ob + v * 64 + lane;
+        if (sr[v] == 0) buf_st_i64(sb.esc, 8 * o, (int64_t)dr[v]);
+        if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + o), (int64_t)di[v]);
+      }
+    }
+    add_squares<4>(qr, qi, acc.lo, acc.hi);
+  } else {
+    int ir[4], ii[4], dr[4], di[4];
+    int64_t t = 0;  // sum of q^2 of this thread's 8 values, below 2^51
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      ir[v] = (int)qr[v];  // exact: |q| < 2^24
+      ii[v] = (int)qi[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const uint32_t o = ob + v * 64 + lane;
+      int pr = lane_below(ir[v]), pi = lane_below(ii[v]);
+      if (v > 0) {
+        const int lr = __builtin_amdgcn_readlane(ir[v - 1], 63), li = __builtin_amdgcn_readlane(ii[v - 1], 63);
+        if (lane == 0) {
+          pr = lr;
+          pi = li;
+        }
+      }
+      if ((o & Bm) == 0) pr = pi = 0;  // chunk head (lane 0 at v = 0 always is one)
+      dr[v] = ir[v] - pr;  // |d| < 2^25
+      di[v] = ii[v] - pi;
+      const bool er = (uint32_t)(dr[v] + (kR - 1)) > (uint32_t)(2 * kR - 2);  // !(|d| < R)
+      const bool ei = (uint32_t)(di[v] + (kR - 1)) > (uint32_t)(2 * kR - 2);
+      sr[v] = er ? 0u : (uint32_t)(dr[v] + kR);
+      si[v] = ei ? 0u : (uint32_t)(di[v] + kR);
+      any_esc = any_esc || er || ei;
+      acc.nesc += (uint32_t)er + (uint32_t)ei;
+      buf_st_u16(sb.sym, 2 * o, sr[v]);
+      buf_st_u16(sb.sym, 2 * (sb.L + o), si[v]);
+      t += (int64_t)ir[v] * ir[v];
+      t += (int64_t)ii[v] * ii[v];
+    }
+    if (__ballot(any_esc)) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const uint32_t o = ob + v * 64 + lane;
+        if (sr[v] == 0) buf_st_i64(sb.esc, 8 * o, (int64_t)dr[v]);
+        if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + o), (int64_t)di[v]);
+      }
+    }
+    const uint64_t x = acc.lo + (uint64_t)t;
+    acc.hi += x < acc.lo;
+    acc.lo = x;
+  }
+  hist_full<4>(sr, si, h);
+}
+
+// Gate and quantisation of one range.  KIND 0: identity; 1: one target t <
+// 8 (partner element e ^ 2^t: another lane for t < 6, the same lane at v ^
+// 2^(t-6) otherwise); 2: phase.
+template <int KIND>
+__device__ __forceinline__ void wr_step(const WRange &x, uint32_t ob, const GqSlot &s, const GateDesc &gd,
+                                        const Geo &g, uint32_t *h, Acc &acc) {
+  const uint32_t lane = lane_id();
+  double qr[4], qi[4];
+  double pr[4], pi[4];
+  uint32_t bit = 0;
+  if (KIND == 1) {
+    const int tb = gd.tloc[0];
+    bit = 1u << tb;
+    if (tb >= 6) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        pr[v] = tb == 6 ? x.r[v ^ 1] : x.r[v ^ 2];
+        pi[v] = tb == 6 ? x.i[v ^ 1] : x.i[v ^ 2];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        pr[v] = __shfl_xor(x.r[v], (int)bit, 64);
+        pi[v] = __shfl_xor(x.i[v], (int)bit, 64);
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    const uint32_t o = ob + v * 64 + lane;
+    double re = x.r[v], im = x.i[v];
+    const bool on = s.hi_ok && (o & s.mask_lo) == s.vals_lo;
+    if (KIND == 2 && on) {
+      cmul(gd.ph_re, gd.ph_im, x.r[v], x.i[v], re, im);
+    } else if (KIND == 1 && on) {
+      const bool row = (o & bit) != 0;  // column 0: the amplitude with the target bit clear
+      const double a0r = row ? pr[v] : x.r[v], a0i = row ? pi[v] : x.i[v];
+      const double a1r = row ? x.r[v] : pr[v], a1i = row ? x.i[v] : pi[v];
+      const double u0r = row ? gd.m2[4] : gd.m2[0], u0i = row ? gd.m2[5] : gd.m2[1];
+      const double u1r = row ? gd.m2[6] : gd.m2[2], u1i = row ? gd.m2[7] : gd.m2[3];
+      double cr, ci;
+      cmul(u0r, u0i, a0r, a0i, cr, ci);
+      cmac(u1r, u1i, a1r, a1i, cr, ci);
+      re = cr;
+      im = ci;
+    }
+    quant_tile(re, s, qr[v], acc);
+    quant_tile(im, s, qi[v], acc);
+  }
+  wr_symbols(qr, qi, h, g, s.out, ob, acc);
+}
+
+// Wavefront w of workgroup (x, u) takes ranges x * 4 + w + k * 4G of slot u.
+template <int KIND>
+__global__ void __launch_bounds__(256, 2) k_gq_wave(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
+                                                    QuantParams qp, Ctl *ctl, uint32_t pass) {
+  if (ctl->flags) return;
+  __shared__ uint32_t h[kNSym];
+  __shared__ uint64_t wred[4][4];
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kNSym; i += 256) h[i] = 0;
+  __syncthreads();
+  const uint32_t u = blockIdx.y, L = (uint32_t)g.L;
+  const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t n = (L / kWr) / nwv;  // ranges per wavefront: 1 or even
+  const GqSlot s = gq_slot(sl, g, slot_slice, gd, qp, u);
+  Acc acc;
+  acc.zero();
+  auto range_of = [&](uint32_t k) { return (k < n ? w0 + k * nwv : w0) * kWr; };  // past the end: w0 again
+  WRange A, B;
+  wr_load(A, s.ws, L, range_of(0));
+  if (n == 1) {
+    wr_step<KIND>(A, range_of(0), s, gd, g, h, acc);
+  } else {
+    wr_load(B, s.ws, L, range_of(1));
+    wr_step<KIND>(A, range_of(0), s, gd, g, h, acc);
+    wr_load(A, s.ws, L, range_of(2));
+    for (uint32_t k = 1; k + 1 < n; k += 2) {
+      wr_step<KIND>(B, range_of(k), s, gd, g, h, acc);
+      wr_load(B, s.ws, L, range_of(k + 2));
+      wr_step<KIND>(A, range_of(k + 1), s, gd, g, h, acc);
+      wr_load(A, s.ws, L, range_of(k + 3));
+    }
+    wr_step<KIND>(B, range_of(n - 1), s, gd, g, h, acc);
+  }
+  write_partial(acc, h, wred, sl, u, blockIdx.x, ctl, pass);
+}
+
+// One-target gate whose partner is in another range (2^t >= 256): a
+// wavefront takes range pairs.  In-slice targets pair ranges rA (range bit
+// t - 8 clear) and rB = rA | 2^(t-8) of one slot, whose results share one
+// histogram; slice-index targets pair the same range of slots uA and uB.
+// One pair in registers: the gate and quantisation of a pair free its
+// registers, the next pair's loads go there, then the symbols are stored --
+// so at every step the pending operations are [next loads][these stores].
+__device__ __forceinline__ void wr_pair_quant(const WRange &a, const WRange &b, uint32_t obA, const GqSlot &sA,
+                                              const GqSlot &sB, const GateDesc &gd, double (&qar)[4],
+                                              double (&qai)[4], double (&qbr)[4], double (&qbi)[4], Acc &accA,
+                                              Acc &accB) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    const double a0r = a.r[v], a0i = a.i[v], a1r = b.r[v], a1i = b.i[v];
+    double outAr = a0r, outAi = a0i, outBr = a1r, outBi = a1i;
+    if (sA.hi_ok && ((obA + v * 64 + lane) & sA.mask_lo) == sA.vals_lo) {
+      cmul(gd.m2[0], gd.m2[1], a0r, a0i, outAr, outAi);
+      cmac(gd.m2[2], gd.m2[3], a1r, a1i, outAr, outAi);
+      cmul(gd.m2[4], gd.m2[5], a0r, a0i, outBr, outBi);
+      cmac(gd.m2[6], gd.m2[7], a1r, a1i, outBr, outBi);
+    }
+    quant_tile(outAr, sA, qar[v], accA);
+    quant_tile(outAi, sA, qai[v], accA);
+    quant_tile(outBr, sB, qbr[v], accB);
+    quant_tile(outBi, sB, qbi[v], accB);
+  }
+}
+
+__global__ void __launch_bounds__(256, 2) k_gq_wave_pair(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
+                                                         QuantParams qp, Ctl *ctl, uint32_t pass) {
+  if (ctl->flags) return;
+  __shared__ uint32_t hA[kNSym], hB[kNSym];
+  __shared__ uint64_t wred[4][4];
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kNSym; i += 256) hA[i] = hB[i] = 0;
+  __syncthreads();
+  const uint32_t L = (uint32_t)g.L, nr = L / kWr;
+  const int t = gd.tloc[0];
+  const bool cross = t >= g.slice_log2;
+  uint32_t uA, uB, npairs;
+  int b = 0;
+  if (cross) {
+    const uint32_t sb = t - g.slice_log2, y = blockIdx.y;
+    uA = ((y >> sb) << (sb + 1)) | (y & ((1u << sb) - 1));
+    uB = uA | (1u << sb);
+    npairs = nr;
+  } else {
+    uA = uB = blockIdx.y;
+    b = t - 8;  // log2 of the range size
+    npairs = nr / 2;
+  }
+  const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6), n = npairs / nwv;
+  const GqSlot sA = gq_slot(sl, g, slot_slice, gd, qp, uA), sB = gq_slot(sl, g, slot_slice, gd, qp, uB);
+  // one slot: both ranges' results go to one histogram and one sum
+  uint32_t *hb = cross ? hB : hA;
+  Acc accA, accB;
+  accA.zero();
+  accB.zero();
+  Acc &accb = cross ? accB : accA;
+  auto pair_of = [&](uint32_t k) { return k < n ? w0 + k * nwv : w0; };  // past the end: pair w0 again
+  auto rA = [&](uint32_t w) { return (cross ? w : ((w >> b) << (b + 1)) | (w & ((1u << b) - 1))) * kWr; };
+  auto rB = [&](uint32_t w) { return cross ? w * kWr : rA(w) | (kWr << b); };
+  WRange xa, xb;
+  double qar[4], qai[4], qbr[4], qbi[4];
+  auto step = [&](uint32_t k) {  // quantise pair k (in xa, xb), load pair k + 1, store pair k's symbols
+    const uint32_t w = pair_of(k), wn = pair_of(k + 1);
+    wr_pair_quant(xa, xb, rA(w), sA, sB, gd, qar, qai, qbr, qbi, accA, accb);
+    wr_load(xa, sA.ws, L, rA(wn));
+    wr_load(xb, sB.ws, L, rB(wn));
+    wr_symbols(qar, qai, hA, g, sA.out, rA(w), accA);
+    wr_symbols(qbr, qbi, hb, g, sB.out, rB(w), accb);
+  };
+  wr_load(xa, sA.ws, L, rA(w0));
+  wr_load(xb, sB.ws, L, rB(w0));
+  step(0);
+  for (uint32_t k = 1; k < n; k++) step(k);
+  write_partial(accA, hA, wred, sl, uA, blockIdx.x, ctl, pass);
+  if (cross) write_partial(accB, hB, wred, sl, uB, blockIdx.x, ctl, pass);
+}
+
 // The paired gate_quant without pipelining, on tiles of 1024 amplitudes: used
 // when chunks are longer than the pipelined kernel's tile (a tile must start
 // at a chunk head).  Partial results are numbered as in the pipelined kernel.
@@ -2056,6 +2348,14 @@ void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, co
 template <int KIND>
 static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
                             const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
+  // wavefront ranges (a one-target gate only with its partner in the range)
+  if (KIND != 3 && g.chunk_log2 <= 8 && g.L >= 4 * kWr && (KIND != 1 || (1ull << gd.tloc[0]) < kWr)) {
+    const uint32_t nr = (uint32_t)(g.L / kWr);
+    const uint32_t G = nr / 4 < kGqWgs ? nr / 4 : kGqWgs;
+    hipLaunchKernelGGL((k_gq_wave<KIND == 3 ? 0 : KIND>), dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss,
+                       gd, qp, ctl, pass);
+    return G;
+  }
   const uint64_t C = gq_tile(g.L);
   const uint32_t ntiles = (uint32_t)(g.L / C);
   const uint32_t G = ntiles < kGqWgs ? ntiles : kGqWgs;
@@ -2078,6 +2378,18 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
   const int kind = gate_kind(gd);
   if (kind == 1) {
     const uint64_t C = gq_tile(g.L);
+    if (g.chunk_log2 <= 8 && g.L >= 4 * kWr) {  // wavefront ranges
+      if ((1ull << gd.tloc[0]) < kWr) return launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+      const bool cross = gd.tloc[0] >= g.slice_log2;
+      const uint32_t nr = (uint32_t)(g.L / kWr);
+      const uint32_t npairs = cross ? nr : nr / 2;
+      if (npairs >= 4) {
+        const uint32_t G = npairs / 4 < kGqWgs ? npairs / 4 : kGqWgs;
+        const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
+        hipLaunchKernelGGL(k_gq_wave_pair, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
+        return G;
+      }
+    }
     if ((1ull << gd.tloc[0]) < C)  // partner inside the tile
       return launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
     if (g.L >= kGqTile) {  // partner in the paired tile (2^t >= 1024)

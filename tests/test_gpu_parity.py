@@ -105,6 +105,9 @@ def test_qft12_basis_every_pass_identical():
 GEOMETRIES = [  # n, slice_log2, chunk_log2, eb
     (3, 1, 1, 1e-6), (4, 2, 1, 1e-5), (5, 3, 7, 1e-6), (6, 3, 2, 1e-7), (7, 7, 3, 1e-6),
     (8, 4, 3, 1e-6), (9, 6, 4, 1e-8), (10, 5, 5, 1e-6), (11, 9, 6, 1e-7), (12, 11, 10, 1e-6),
+    # slices of 2^10 .. 2^12 with chunks of at most 256 values (the wavefront-range kernels):
+    # targets inside a range (lanes, v), range pairs in a slice, slice pairs
+    (12, 10, 8, 1e-6), (13, 11, 7, 1e-7), (14, 12, 5, 1e-6), (13, 12, 8, 1e-8),
 ]
 
 
@@ -206,14 +209,15 @@ def test_deterministic_and_allocator_independent():
     assert out[0] == out[1] == out[2]
 
 
-def test_grover24_full_size_window():
+@pytest.mark.parametrize("cl", [8, 10])
+def test_grover24_full_size_window(cl):
     """The benchmark geometry (24 qubits, 64 slices of 2^18, bound 1e-7) over the
     initial H layer, one oracle and the first diffusion gates."""
     w = qc.grover_workload()
-    say("grover24 window", w.n_qubits, w.slice_log2, w.error_bound)
+    say("grover24 window", w.n_qubits, w.slice_log2, w.error_bound, "chunk", cl)
     gates = w.gates[:24 + 1 + 10]
     oracle.set_threads(0)
-    sim, orc = run_both(w.n_qubits, w.slice_log2, 10, w.error_bound, gates, check_every=len(gates))
+    sim, orc = run_both(w.n_qubits, w.slice_log2, cl, w.error_bound, gates, check_every=len(gates))
     idx = [0, 1, 17, 63]
     a = sim.amplitudes(0, 1 << 12)
     assert np.array_equal(a, orc.amplitudes(0, 1 << 12))
