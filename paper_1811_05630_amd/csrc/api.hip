@@ -47,11 +47,10 @@ int set_err(int code, const char *fmt, ...) {
       return set_err(SIM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
   } while (0)
 
-enum KClass { K_BEGIN, K_RESET, K_INIT, K_DECODE, K_MINMAX, K_RELSTEP, K_GATEQ, K_CODEBOOK, K_ENCODE, K_HEADER,
-              K_COMPACT, K_READOUT, K_DENSE, K_COUNT };
+enum KClass { K_BEGIN, K_RESET, K_INIT, K_DECODE, K_MINMAX, K_RELSTEP, K_GATEQ, K_CODEBOOK, K_ENCODE, K_FINISH,
+              K_READOUT, K_DENSE, K_COUNT };
 const char *kClassNames =
-    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,encode,header,compact,readout,"
-    "dense_mfma";
+    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,encode,finish,readout,dense_mfma";
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -188,6 +187,7 @@ int alloc_slots(sim_t *s) {
   if ((rc = s->dalloc((void **)&sl.nused, 4 * W))) return rc;
   if ((rc = s->dalloc((void **)&sl.chunk_words, 4 * W * s->geo.nchunks))) return rc;
   if ((rc = s->dalloc((void **)&sl.words, 4 * W))) return rc;
+  if ((rc = s->dalloc((void **)&sl.blk_words, 4 * W * kMaxEncBlocks))) return rc;
   if ((rc = s->dalloc((void **)&sl.sq, 16 * W))) return rc;
   if ((rc = s->dalloc((void **)&sl.nesc, 4 * W))) return rc;
   if ((rc = s->dalloc((void **)&sl.minmax, 16 * W))) return rc;
@@ -201,7 +201,7 @@ int alloc_slots(sim_t *s) {
 
 uint64_t per_slot_bytes(const Geo &g) {
   return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 2) + 4ull * kGqParts * (kNSym + 8) + 4ull * g.nchunks +
-         4ull * g.nchunks * stage_words_for(g.chunk_log2) + 128;
+         4ull * g.nchunks * stage_words_for(g.chunk_log2) + 4ull * kMaxEncBlocks + 128;
 }
 
 // Slot order of every slice for gates whose slice-index targets form `gm`:
@@ -473,11 +473,8 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
     s->kt_begin(K_ENCODE);
     launch_encode(st, s->slots, s->geo, ns, s->ctl);
     s->kt_end();
-    s->kt_begin(K_HEADER);
-    launch_header(st, s->slots, s->geo, ss, ns, qp, s->arena[1 - c], s->arena_cap[1 - c], nxt, s->ctl, pass);
-    s->kt_end();
-    s->kt_begin(K_COMPACT);
-    launch_compact(st, s->slots, s->geo, ss, ns, s->arena[1 - c], nxt, s->ctl);
+    s->kt_begin(K_FINISH);
+    launch_finish(st, s->slots, s->geo, ss, ns, qp, s->arena[1 - c], s->arena_cap[1 - c], nxt, s->ctl, pass);
     s->kt_end();
   }
   s->cur = 1 - c;
@@ -495,7 +492,10 @@ int read_ctl(sim_t *s) {
 int clear_flags(sim_t *s) {
   s->h_ctl->flags = 0;
   s->h_ctl->fail_pass = 0;
+  s->h_ctl->pending_bump = 0;  // a failed batch's records are not counted
+  s->h_ctl->pending_bytes = 0;
   HIP_TRY(hipMemcpyAsync(&s->ctl->flags, &s->h_ctl->flags, 8, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(&s->ctl->pending_bump, &s->h_ctl->pending_bump, 16, hipMemcpyHostToDevice, s->stream));
   launch_reset_slots(s->stream, s->slots, s->W);
   HIP_TRY(hipStreamSynchronize(s->stream));
   return check_launch("reset_slots");
@@ -528,6 +528,8 @@ int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, i
         rc = enqueue_pass(s, GateDesc{}, 0, init_kind, x);
       if (rc) return rc;
     }
+    // count the records of the last batch (settle only)
+    launch_begin_pass(s->stream, s->ctl, s->meta[s->cur], s->nslices, s->kscale, 3);
     if ((rc = read_ctl(s))) return rc;
     const uint32_t flags = s->h_ctl->flags;
     if (!flags) {

@@ -46,8 +46,8 @@ struct Ctl {
   uint32_t fail_pass;     // pass counter value of the first failure
   double N;               // norm of the stored state at the start of this pass
   double s;               // 1 / sqrt(N)
-  uint64_t pending_bump;  // aligned bytes of the batch being written (header -> compact)
-  uint64_t pending_bytes; // exact bytes of that batch
+  uint64_t pending_bump;  // aligned bytes of the last batch written; added to bump and
+  uint64_t pending_bytes; // cur_bytes by the next launch that starts a batch or a pass
   uint64_t pad[4];
 };
 
@@ -89,9 +89,8 @@ struct Geo {
 // Per-slot scratch of one batch of decompressed slices.
 // Every gate_quant workgroup overwrites its partial results (hpart, part)
 // whole, and the codebook kernel reads only those of the current launch.
-// Accumulators are zero between uses: sq and nesc are cleared by the header
-// kernel, words by the compact kernel and minmax by the relative-step kernel,
-// each right after its last reader.
+// words is cleared by the codebook kernel before encode adds to it; minmax
+// is cleared by the relative-step kernel after reading it.
 struct Slots {
   double *ws;             // [W][2L] decompressed values (re plane, im plane)
   uint16_t *sym;          // [W][2L] symbols
@@ -99,13 +98,15 @@ struct Slots {
   uint32_t *codes;        // [W][1024] code << 8 | length
   uint16_t *symtab;       // [W][1024] canonical symbol table
   uint32_t *nused;        // [W]
-  uint32_t *chunk_words;  // [W][nchunks]
-  uint32_t *words;        // [W] total words
+  uint32_t *chunk_words;  // [W][nchunks] word offset of each chunk inside its encode block
+  uint32_t *words;        // [W] total words (zeroed by the codebook kernel, added by encode)
+  uint32_t *blk_words;    // [W][kMaxEncBlocks] words of each encode block
   uint64_t *sq;           // [W][2] sum p^2 (lo, hi)
   uint32_t *nesc;         // [W]
   uint64_t *minmax;       // [W][2] ordered keys of min and max (relative bound)
   double *qstep;          // [W][3] step, recip, bound (relative bound)
-  uint32_t *stage;        // [W][nchunks][stage_words] encoded chunks before compaction
+  uint32_t *stage;        // [W][nchunks][stage_words]: each encode block's chunks, packed from the
+                          // start of the block's region, before they move into the record
   uint32_t stage_words;   // capacity of one chunk: ceil(B * 68 / 32) words
   // gate_quant writes, per slot, up to kGqParts partial results (one per
   // workgroup and tile role) without atomics; the codebook kernel adds them
@@ -126,7 +127,9 @@ struct StateMeta {
 // All launches go to `st`; `pass` is the global pass counter (for failure
 // reporting); `slot_slice` lists the slice held by every slot of the batch.
 // with_norm: 0 = a pass that builds an initial state, 1 = a gate pass,
-// 2 = read-out only (scales without touching the pass counters).
+// 2 = read-out only (scales without touching the pass counters), 3 = only
+// count the records of the last batch written.  Every mode first counts
+// the last batch.
 void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *kscale,
                        int with_norm);
 void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots);
@@ -144,11 +147,11 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
                      uint32_t nparts, Ctl *ctl);
 void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
-void launch_header(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+// records of the batch: offsets in the output arena, headers, symbol tables,
+// chunk offsets, bit streams, per-slice metadata
+void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                    const QuantParams &qp, uint8_t *arena, uint64_t arena_cap, const StateMeta &nxt, Ctl *ctl,
                    uint32_t pass);
-void launch_compact(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                    uint8_t *arena, const StateMeta &nxt, Ctl *ctl);
 // fused block (kind 4) applied in place to the decompressed slots
 void launch_dense_mfma(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const GateDesc &gd,
                        const Ctl *ctl);
@@ -159,6 +162,7 @@ void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t firs
 // the chunk length); workgroups per slot and partial results per slot
 inline uint64_t gq_tile(uint64_t L) { return L < 1024 ? L : 1024; }
 constexpr uint32_t kGqWgs = 16;
+constexpr uint32_t kMaxEncBlocks = 1024;  // encode (and finish) workgroups per slot, at most
 constexpr uint32_t kGqParts = 2 * kGqWgs;
 
 // words of one chunk's staging slot

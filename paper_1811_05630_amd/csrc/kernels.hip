@@ -135,6 +135,16 @@ __device__ __forceinline__ uint32_t ld32(const uint8_t *p) { return *(const uint
 
 // ----------------------------------------------------------- begin pass
 
+// The records of the last batch are counted by the launch that starts the
+// next batch or pass (the batch's own workgroups all read the arena position
+// it started from, so none of them may move it).
+__device__ __forceinline__ void settle(Ctl *ctl) {
+  ctl->bump += ctl->pending_bump;
+  ctl->cur_bytes += ctl->pending_bytes;
+  ctl->pending_bump = 0;
+  ctl->pending_bytes = 0;
+}
+
 __device__ __forceinline__ double norm_leaf(const double *step, const uint64_t *sq, uint64_t j) {
   double s = step[j];
   double p = (double)sq[2 * j + 1] * 0x1p64 + (double)sq[2 * j];
@@ -164,12 +174,13 @@ __global__ void __launch_bounds__(1024) k_begin_pass(Ctl *ctl, const double *ste
   __shared__ double part[1024];
   __shared__ double s_sh;
   const uint32_t tid = threadIdx.x, T = blockDim.x;
-  if (with_norm != 2 && tid == 0) {  // a pass starts writing the other arena
+  if (tid == 0) settle(ctl);
+  if ((with_norm == 0 || with_norm == 1) && tid == 0) {  // a pass starts writing the other arena
     if (ctl->cur_bytes > ctl->peak_bytes) ctl->peak_bytes = ctl->cur_bytes;
     ctl->bump = 0;
     ctl->cur_bytes = 0;
   }
-  if (with_norm == 0) return;
+  if (with_norm == 0 || with_norm == 3) return;
   uint64_t active;
   if (S <= T) {
     part[tid] = tid < S ? norm_leaf(step, sq, tid) : 0.0;
@@ -1730,6 +1741,10 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   __shared__ uint32_t scratch[20];
   __shared__ uint64_t s64[16];
   const uint32_t u = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) {
+    if (u == 0) settle(ctl);
+    sl.words[u] = 0;  // encode adds the slot's words
+  }
   {  // sums of the gate_quant workgroups of this slot (partials [0, nparts))
     uint64_t lo = 0, hi = 0, ne = 0, eb = 0;
     const uint64_t *pp = sl.part + (uint64_t)u * kGqParts * 4;
@@ -1956,7 +1971,6 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Ge
   extern __shared__ uint32_t lw_all[];  // [2][kEncWaves][stage_words]
   __shared__ uint32_t codes[kNSym];
   __shared__ uint32_t cnw[2][kEncWaves];  // words of each coded chunk
-  __shared__ uint32_t wsum[kEncWaves];
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
   const uint32_t u = blockIdx.y;
   const uint32_t cb = blockIdx.x * chunks_per_block;
@@ -1966,7 +1980,10 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Ge
   const uint64_t Bc = 1ull << g.chunk_log2;
   const uint32_t rounds = (chunks_per_block + kEncWaves - 1) / kEncWaves;
   const uint64_t slot0 = (uint64_t)u * 2 * g.L;
-  uint32_t words_here = 0;
+  // the block's chunks, packed from the start of its staging region
+  // (store wavefront only; capacity W words per chunk)
+  uint32_t *blk = sl.stage + ((uint64_t)u * g.nchunks + cb) * W;
+  uint32_t packed = 0;
   uint2 cur[STEPS], nxt[STEPS];  // this and the next round's symbols of the lane
   auto load_round = [&](uint2 (&d)[STEPS], uint32_t r) {
     const uint32_t c = cb + r * kEncWaves + wave;
@@ -1996,16 +2013,20 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Ge
         sv[1] = cur[i].x >> 16;
         sv[2] = cur[i].y & 0xffffu;
         sv[3] = cur[i].y >> 16;
-        bool has_esc = false;
+        uint64_t z[4];   // zigzag code of an escaped difference
+        uint32_t nb[4];  // its bit length (0: no escape)
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           cw[k] = 0;
+          z[k] = 0;
+          nb[k] = 0;
           if (j + k < B) {
             cw[k] = codes[sv[k]];
             bl += cw[k] & 0xffu;
             if (sv[k] == 0) {
-              has_esc = true;
-              bl += kEscBits + (uint32_t)bitlen64(zigzag(esc[j + k]));
+              z[k] = zigzag(esc[j + k]);
+              nb[k] = (uint32_t)bitlen64(z[k]);
+              bl += kEscBits + nb[k];
             }
           }
         }
@@ -2021,10 +2042,16 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Ge
         __asm__ __volatile__("" ::: "memory");
         run += tot;
         if (pos + bl > 32ull * W) continue;  // cannot happen for a consistent codebook
-        if (!has_esc) {
+        if (bl <= 64) {  // the lane's codes and escape payloads as one field (every part below 64 bits)
           uint64_t acc = 0;
 #pragma unroll
-          for (int k = 0; k < 4; k++) acc = (acc << (cw[k] & 0xffu)) | (cw[k] >> 8);
+          for (int k = 0; k < 4; k++) {
+            acc = (acc << (cw[k] & 0xffu)) | (cw[k] >> 8);
+            if (nb[k]) {  // an escape: 6-bit length, then the payload (|d| >= R: never empty)
+              acc = (acc << kEscBits) | nb[k];
+              acc = (acc << nb[k]) | z[k];
+            }
+          }
           put_bits(lw, acc, (int)bl, pos);
         } else {
 #pragma unroll
@@ -2034,78 +2061,91 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Ge
             put_bits(lw, cw[k] >> 8, (int)len, pos);
             pos += len;
             if (sv[k] == 0) {
-              const uint64_t z = zigzag(esc[j + k]);
-              const int nb = bitlen64(z);
-              put_bits(lw, (uint64_t)nb, kEscBits, pos);
-              put_bits(lw, z, nb, pos + kEscBits);
-              pos += kEscBits + nb;
+              put_bits(lw, (uint64_t)nb[k], kEscBits, pos);
+              put_bits(lw, z[k], (int)nb[k], pos + kEscBits);
+              pos += kEscBits + nb[k];
             }
           }
         }
       }
       uint32_t nw = (uint32_t)((run + 31) >> 5);
       if (nw > W) nw = W;  // at most 68 bits per value: never reached by a consistent codebook
-      if (lane == 0) cnw[buf][wave] = nw;
-      if (active) words_here += nw;
+      if (lane == 0) cnw[buf][wave] = active ? nw : 0u;
 #pragma unroll
       for (int i = 0; i < STEPS; i++) cur[i] = nxt[i];
-    } else if (wave == kEncWaves && r > 0) {  // store the previous round's chunks
+    } else if (wave == kEncWaves && r > 0) {  // store the previous round's chunks, packed
       const uint32_t pb = buf ^ 1u;
       for (uint32_t w = 0; w < (uint32_t)kEncWaves; w++) {
         const uint32_t c = cb + (r - 1) * kEncWaves + w;
         if (c >= ce) break;
         const uint32_t nw = cnw[pb][w];
         const uint32_t *src = lw_all + (uint64_t)(pb * kEncWaves + w) * W;
-        uint32_t *dst = sl.stage + ((uint64_t)u * g.nchunks + c) * W;
-        for (uint32_t i = lane; i < nw; i += 64) dst[i] = src[i];
-        if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = nw;
+        for (uint32_t i = lane; i < nw; i += 64) blk[packed + i] = src[i];
+        if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = packed;
+        packed += nw;
       }
     }
     lds_sync();  // round r coded; round r - 1 read out of LDS
   }
-  if (wave < kEncWaves && lane == 0) wsum[wave] = words_here;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (int w = 0; w < kEncWaves; w++) t += wsum[w];
-    if (t) atomicAdd(&sl.words[u], t);
+  if (wave == kEncWaves && lane == 0) {
+    sl.blk_words[(uint64_t)u * kMaxEncBlocks + blockIdx.x] = packed;
+    if (packed) atomicAdd(&sl.words[u], packed);
   }
 }
 
-// ------------------------------------------------------------------ header
-// One workgroup per slot.  Every workgroup sizes all records of the batch
-// (slot order), so it knows its record's offset and the batch total; the
-// total must fit the arena or the pass fails with an overflow flag.
+// ------------------------------------------------------------------ finish
+// Workgroup (b, u) takes encode block b of slot u.  Every workgroup sizes all
+// records of the batch (slot order), so it knows its record's offset and the
+// batch total, which must fit the arena (else the pass fails with an overflow
+// flag); the words before its block are the totals of the slot's earlier
+// blocks.  It writes its chunks' offsets and copies their packed words into
+// the record; block 0 also writes the header, symbol table and last offset
+// and the slice's metadata.  The batch total becomes pending and is counted
+// by the next launch that starts a batch or pass.
 
-__global__ void __launch_bounds__(256) k_header(Slots sl, Geo g, const uint64_t *slot_slice, int nslots,
-                                                QuantParams qp, uint8_t *arena, uint64_t cap, StateMeta nxt, Ctl *ctl,
-                                                uint32_t pass) {
+__global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t *slot_slice, int nslots,
+                                                QuantParams qp, uint8_t *arena, uint64_t cap, StateMeta nxt,
+                                                uint32_t cpb, Ctl *ctl, uint32_t pass) {
   if (ctl->flags) return;
-  __shared__ uint32_t scratch[20];
   __shared__ uint64_t s64[16];
-  __shared__ uint32_t carry;
-  const uint32_t u = blockIdx.x, tid = threadIdx.x;
+  const uint32_t u = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
   const uint32_t nch = g.nchunks;
   uint64_t pre = 0, tot = 0, ex = 0;
   for (int v = tid; v < nslots; v += blockDim.x) {
-    const uint64_t b = rec_bytes(sl.nused[v], nch, sl.words[v]);
-    const uint64_t ba = (b + kRecAlign - 1) & ~(kRecAlign - 1);
+    const uint64_t bytes = rec_bytes(sl.nused[v], nch, sl.words[v]);
+    const uint64_t ba = (bytes + kRecAlign - 1) & ~(kRecAlign - 1);
     tot += ba;
-    ex += b;
+    ex += bytes;
     if ((uint32_t)v < u) pre += ba;
   }
   pre = block_sum64(pre, s64);
   tot = block_sum64(tot, s64);
   ex = block_sum64(ex, s64);
+  uint64_t bp = 0;  // words of the slot's earlier blocks
+  for (uint32_t i = tid; i < b; i += blockDim.x) bp += sl.blk_words[(uint64_t)u * kMaxEncBlocks + i];
+  bp = block_sum64(bp, s64);
   const uint64_t base = ctl->bump;
   if (base + tot > cap) {
-    if (tid == 0) fail(ctl, kFlagOverflow, pass);
+    if (tid == 0 && b == 0 && u == 0) fail(ctl, kFlagOverflow, pass);
     return;
   }
-  const uint64_t slice = slot_slice[u];
+  if (tid == 0 && b == 0 && u == 0) {
+    ctl->pending_bump = tot;
+    ctl->pending_bytes = ex;
+  }
   const uint64_t off = base + pre;
   uint8_t *rec = arena + off;
   const uint32_t n_used = sl.nused[u], words = sl.words[u];
+  uint32_t *offs = (uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
+  uint32_t *stream = offs + nch + 1;
+  const uint32_t cb = b * cpb, ce = cb + cpb < nch ? cb + cpb : nch;
+  for (uint32_t c = cb + tid; c < ce; c += blockDim.x)
+    offs[c] = (uint32_t)bp + sl.chunk_words[(uint64_t)u * nch + c];
+  const uint32_t nw = sl.blk_words[(uint64_t)u * kMaxEncBlocks + b];
+  const uint32_t *src = sl.stage + ((uint64_t)u * nch + cb) * sl.stage_words;
+  for (uint32_t i = tid; i < nw; i += blockDim.x) stream[bp + i] = src[i];
+  if (b != 0) return;
+  const uint64_t slice = slot_slice[u];
   const double step = qp.rel ? sl.qstep[3 * u] : qp.step;
   if (tid == 0) {
     const uint64_t sq_lo = sl.sq[2 * u], sq_hi = sl.sq[2 * u + 1];
@@ -2128,59 +2168,11 @@ __global__ void __launch_bounds__(256) k_header(Slots sl, Geo g, const uint64_t 
     nxt.step[slice] = step;
     nxt.sq[2 * slice] = sq_lo;
     nxt.sq[2 * slice + 1] = sq_hi;
-    sl.sq[2 * u] = 0;  // consumed
-    sl.sq[2 * u + 1] = 0;
-    sl.nesc[u] = 0;
-    if (u == 0) {
-      ctl->pending_bump = tot;
-      ctl->pending_bytes = ex;
-    }
-    carry = 0;
+    offs[nch] = words;
   }
   uint16_t *tab = (uint16_t *)(rec + kHdr);
   for (uint32_t i = tid; i < n_used; i += blockDim.x) tab[i] = sl.symtab[(uint64_t)u * kNSym + i];
   if (tid == 0 && (n_used & 1)) tab[n_used] = 0;
-  uint32_t *offs = (uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
-  const uint32_t *cw = sl.chunk_words + (uint64_t)u * nch;
-  __syncthreads();
-  for (uint32_t t0 = 0; t0 < nch; t0 += blockDim.x) {
-    uint32_t c = t0 + tid;
-    uint32_t x = c < nch ? cw[c] : 0u, t;
-    uint32_t p = block_excl_scan(x, scratch, &t);
-    if (c < nch) offs[c] = carry + p;
-    __syncthreads();
-    if (tid == 0) carry += t;
-    __syncthreads();
-  }
-  if (tid == 0) offs[nch] = words;
-}
-
-// ----------------------------------------------------------------- compact
-
-__global__ void __launch_bounds__(256) k_compact(Slots sl, Geo g, const uint64_t *slot_slice, uint8_t *arena,
-                                                 StateMeta nxt, uint32_t chunks_per_block, Ctl *ctl) {
-  if (ctl->flags) return;
-  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
-  const uint32_t u = blockIdx.y;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sl.words[u] = 0;  // consumed
-    if (u == 0) {
-      ctl->bump += ctl->pending_bump;
-      ctl->cur_bytes += ctl->pending_bytes;
-    }
-  }
-  const uint64_t slice = slot_slice[u];
-  uint8_t *rec = arena + nxt.rec_off[slice];
-  const uint32_t n_used = ld32(rec + 12);
-  const uint32_t *offs = (const uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
-  uint32_t *words = (uint32_t *)(offs + g.nchunks + 1);
-  const uint32_t cb = blockIdx.x * chunks_per_block;
-  const uint32_t ce = cb + chunks_per_block < g.nchunks ? cb + chunks_per_block : g.nchunks;
-  for (uint32_t c = cb + wave; c < ce; c += 4) {
-    const uint32_t w0 = offs[c], nw = offs[c + 1] - w0;
-    const uint32_t *src = sl.stage + ((uint64_t)u * g.nchunks + c) * sl.stage_words;
-    for (uint32_t i = lane; i < nw; i += 64) words[w0 + i] = src[i];
-  }
 }
 
 // ------------------------------------------------------------ fused blocks
@@ -2423,17 +2415,26 @@ void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice
   hipLaunchKernelGGL(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, nparts, ctl);
 }
 
-void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
-  // about four workgroups per CU over the batch, at least one chunk per coding wavefront
+// chunks per encode (and finish) workgroup: about four workgroups per CU over
+// the batch, at least one chunk per coding wavefront, at most kMaxEncBlocks
+// workgroups per slot
+static uint32_t enc_chunks_per_block(const Geo &g, int nslots) {
   const uint64_t total = (uint64_t)nslots * g.nchunks;
   uint64_t cpb = total / 1024;
   if (cpb < kEncWaves) cpb = kEncWaves;
+  const uint64_t least = (g.nchunks + kMaxEncBlocks - 1) / kMaxEncBlocks;
+  if (cpb < least) cpb = least;
   if (cpb > g.nchunks) cpb = g.nchunks;
-  dim3 grid(grid1(g.nchunks, (unsigned)cpb), (unsigned)nslots);
+  return (uint32_t)cpb;
+}
+
+void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
+  const uint32_t cpb = enc_chunks_per_block(g, nslots);
+  dim3 grid(grid1(g.nchunks, cpb), (unsigned)nslots);
   const size_t shm = (size_t)2 * kEncWaves * sl.stage_words * 4;
   const dim3 block(64 * (kEncWaves + 1));
   if (g.chunk_log2 <= 8) {
-    hipLaunchKernelGGL(k_encode<1>, grid, block, shm, st, sl, g, (uint32_t)cpb, ctl);
+    hipLaunchKernelGGL(k_encode<1>, grid, block, shm, st, sl, g, cpb, ctl);
     return;
   }
   // dynamic LDS above the default needs the attribute (chunks of 1024: ~70 KB)
@@ -2444,26 +2445,18 @@ void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, co
     shm_set = shm;
   }
   if (g.chunk_log2 == 9)
-    hipLaunchKernelGGL(k_encode<2>, grid, block, shm, st, sl, g, (uint32_t)cpb, ctl);
+    hipLaunchKernelGGL(k_encode<2>, grid, block, shm, st, sl, g, cpb, ctl);
   else
-    hipLaunchKernelGGL(k_encode<4>, grid, block, shm, st, sl, g, (uint32_t)cpb, ctl);
+    hipLaunchKernelGGL(k_encode<4>, grid, block, shm, st, sl, g, cpb, ctl);
 }
 
-void launch_header(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
+void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                    const QuantParams &qp, uint8_t *arena, uint64_t arena_cap, const StateMeta &nxt, Ctl *ctl,
                    uint32_t pass) {
-  hipLaunchKernelGGL(k_header, dim3((unsigned)nslots), dim3(256), 0, st, sl, g, slot_slice, nslots, qp, arena,
-                     arena_cap, nxt, ctl, pass);
-}
-
-void launch_compact(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                    uint8_t *arena, const StateMeta &nxt, Ctl *ctl) {
-  const uint64_t total = (uint64_t)nslots * g.nchunks;
-  uint64_t cpb = total / 2048;
-  if (cpb < 4) cpb = 4;
-  if (cpb > g.nchunks) cpb = g.nchunks;
-  dim3 grid(grid1(g.nchunks, (unsigned)cpb), (unsigned)nslots);
-  hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, st, sl, g, slot_slice, arena, nxt, (uint32_t)cpb, ctl);
+  const uint32_t cpb = enc_chunks_per_block(g, nslots);
+  dim3 grid(grid1(g.nchunks, cpb), (unsigned)nslots);
+  hipLaunchKernelGGL(k_finish, grid, dim3(256), 0, st, sl, g, slot_slice, nslots, qp, arena, arena_cap, nxt, cpb,
+                     ctl, pass);
 }
 
 void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,
