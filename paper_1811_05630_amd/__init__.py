@@ -146,6 +146,42 @@ def gate_array(gates: Sequence):
     return arr, keep
 
 
+class Circuit:
+    """Gates marshalled once into a sim_gate array (with the matrices they
+    point to), so that applying them, or any contiguous range of them, does no
+    per-gate Python work. Slicing with a step of 1 returns a view."""
+
+    def __init__(self, gates: Sequence = (), _base=None, _start: int = 0, _n: int = 0):
+        if _base is None:
+            self._arr, self._keep = gate_array(gates)
+            self._start, self._n = 0, len(gates)
+        else:
+            self._arr, self._keep = _base._arr, _base._keep
+            self._start, self._n = _start, _n
+
+    def __len__(self):
+        return self._n
+
+    def __getitem__(self, key):
+        if not isinstance(key, slice):
+            raise TypeError("Circuit supports slices only")
+        a, b, step = key.indices(self._n)
+        if step != 1:
+            raise ValueError("Circuit slices need a step of 1")
+        return Circuit(_base=self, _start=self._start + a, _n=max(0, b - a))
+
+    def pointer(self):
+        return C.cast(C.byref(self._arr, self._start * C.sizeof(GateStruct)), C.POINTER(GateStruct))
+
+
+def _gate_ptr(gates):
+    """(pointer, count, keep-alive) for a Circuit or any sequence of gates."""
+    if isinstance(gates, Circuit):
+        return gates.pointer(), len(gates), gates
+    arr, keep = gate_array(gates)
+    return C.cast(arr, C.POINTER(GateStruct)), len(gates), (arr, keep)
+
+
 def plan(n_qubits: int, gates: Sequence) -> List[Tuple[int, int, bool, Tuple[int, ...]]]:
     """sim_plan: the fused-mode passes as (first gate, gate count, fused, qubits)."""
     arr, keep = gate_array(gates)
@@ -253,18 +289,19 @@ class Sim:
         _check(lib().sim_init_product(self._h, f.ctypes.data_as(C.c_void_p)), "sim_init_product")
 
     def apply(self, gates: Sequence) -> int:
-        arr, keep = gate_array(gates)
+        """Apply a Circuit (or a sequence of gates, marshalled on each call)."""
+        ptr, cnt, keep = _gate_ptr(gates)
         n = C.c_size_t()
-        rc = lib().sim_apply(self._h, arr, len(gates), C.byref(n))
+        rc = lib().sim_apply(self._h, ptr, cnt, C.byref(n))
         if rc:
             raise SimError(rc, f"sim_apply after {n.value} gates: {lib().sim_last_error().decode()}")
         return n.value
 
     def apply_partial(self, gates: Sequence) -> Tuple[int, int]:
         """Like apply, but returns (status, gates applied) instead of raising."""
-        arr, keep = gate_array(gates)
+        ptr, cnt, keep = _gate_ptr(gates)
         n = C.c_size_t()
-        rc = lib().sim_apply(self._h, arr, len(gates), C.byref(n))
+        rc = lib().sim_apply(self._h, ptr, cnt, C.byref(n))
         return rc, n.value
 
     def amplitudes(self, begin: int = 0, count: Optional[int] = None) -> np.ndarray:

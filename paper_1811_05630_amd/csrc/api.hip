@@ -145,15 +145,17 @@ struct sim_s {
     }
     kt_used = 0;
   }
+  // the next launch records its own start and end (kernel time only)
   void kt_begin(int cls) {
     if (!kt_on) return;
     if (kt_used + 2 > kt_pool.size()) kt_flush();
     kt_cls[kt_used / 2] = cls;
-    hipEventRecord(kt_pool[kt_used++], stream);
+    launch_timer().start = kt_pool[kt_used++];
+    launch_timer().stop = kt_pool[kt_used++];
   }
   void kt_end() {
     if (!kt_on) return;
-    hipEventRecord(kt_pool[kt_used++], stream);
+    launch_timer() = LaunchTimer{};
   }
 };
 
@@ -171,7 +173,7 @@ int alloc_meta(sim_t *s, StateMeta &m) {
   if ((rc = s->dalloc((void **)&m.rec_len, 4 * s->nslices))) return rc;
   if ((rc = s->dalloc((void **)&m.step, 8 * s->nslices))) return rc;
   if ((rc = s->dalloc((void **)&m.sq, 16 * s->nslices))) return rc;
-  if ((rc = s->dalloc((void **)&m.dtab, 2ull * (1u << kLMax) * s->nslices))) return rc;
+  if ((rc = s->dalloc((void **)&m.dtab, 4ull * (1u << kLMax) * s->nslices))) return rc;
   return SIM_OK;
 }
 
@@ -534,6 +536,12 @@ int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, i
     const uint32_t flags = s->h_ctl->flags;
     if (!flags) {
       applied = total;
+      // the next pass writes the other arena: give it a quarter above the
+      // stored state's size now, since an overflow inside a later batch
+      // costs a device synchronisation, a reallocation and a replay
+      const int tgt = 1 - s->cur;
+      const uint64_t want = s->h_ctl->bump + s->h_ctl->bump / 4;
+      if (want > s->arena_cap[tgt]) (void)grow_arena(s, tgt, want);  // on failure the next batch retries
       break;
     }
     const uint32_t done = s->h_ctl->fail_pass - start_pass;  // passes that completed
@@ -1049,16 +1057,23 @@ int sim_import_slice(sim_t *s, uint64_t j, const void *buf, uint64_t len) {
     const uint8_t *r = (const uint8_t *)buf;
     uint32_t n_used;
     memcpy(&n_used, r + 12, 4);
-    std::vector<uint16_t> dt(1u << kLMax);
+    std::vector<uint16_t> one(1u << kLMax);
     uint32_t at = 0;
     for (uint32_t k = 0; k < n_used; k++) {
       uint16_t e;
       memcpy(&e, r + kHdr + 2 * k, 2);
       const uint32_t size = 1u << (kLMax - (e >> 10));
-      for (uint32_t i = 0; i < size; i++) dt[at + i] = e;
+      for (uint32_t i = 0; i < size; i++) one[at + i] = e;
       at += size;
     }
-    HIP_TRY(hipMemcpy(s->meta[a].dtab + j * (1u << kLMax), dt.data(), 2u << kLMax, hipMemcpyHostToDevice));
+    std::vector<uint32_t> dt(1u << kLMax);
+    for (uint32_t e = 0; e < (1u << kLMax); e++) {
+      const uint32_t s1 = one[e] & 1023u, l1 = one[e] >> 10;
+      const uint32_t e2 = (e << l1) & ((1u << kLMax) - 1);
+      const uint32_t s2 = one[e2] & 1023u, l2 = one[e2] >> 10;
+      dt[e] = dtab_entry(s1, l1, s2, l2, s1 != 0 && s2 != 0 && l1 + l2 <= (uint32_t)kLMax);
+    }
+    HIP_TRY(hipMemcpy(s->meta[a].dtab + j * (1u << kLMax), dt.data(), 4u << kLMax, hipMemcpyHostToDevice));
   }
   s->h_ctl->bump = off + align_up(len, kRecAlign);
   s->h_ctl->cur_bytes = s->h_ctl->cur_bytes - old_len + len;
@@ -1079,9 +1094,7 @@ int sim_kernel_times(sim_t *s, int enable, double *out, int cap, const char **na
     if (on && s->kt_pool.empty()) {
       s->kt_pool.resize(8192);
       s->kt_cls.resize(4096);
-      // timing-only events: no system-scope fence (and no cache writeback)
-      // between the kernels they bracket
-      for (auto &e : s->kt_pool) hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+      for (auto &e : s->kt_pool) hipEventCreate(&e);
     }
     s->kt_on = on;
     for (double &v : s->kt_ms) v = 0;

@@ -33,6 +33,14 @@ constexpr int kEscBits = 6;   // escape payload: 6-bit length, then zigzag(d)
 constexpr double kPMax = 281474976710656.0;  // 2^48: |p| must stay below
 constexpr uint64_t kRecAlign = 256;          // records start on 256-byte boundaries
 
+// Decoder table entry for a 12-bit peek at the stream: the first code's
+// symbol and length, and -- when the next code also lies inside the 12 bits
+// and neither symbol is the escape -- the second symbol and length.
+//   bits 0-9 symbol 1, 10-13 length 1, 14-23 symbol 2, 24-27 length 2, 28 second present
+inline __host__ __device__ uint32_t dtab_entry(uint32_t s1, uint32_t l1, uint32_t s2, uint32_t l2, bool two) {
+  return s1 | (l1 << 10) | (two ? (s2 << 14) | (l2 << 24) | (1u << 28) : 0u);
+}
+
 // ------------------------------------------------------------- control block
 enum : uint32_t { kFlagBound = 1u, kFlagOverflow = 2u, kFlagCorrupt = 4u };
 
@@ -120,8 +128,17 @@ struct StateMeta {
   uint32_t *rec_len;      // [S] exact record bytes
   double *step;           // [S]
   uint64_t *sq;           // [S][2]
-  uint16_t *dtab;         // [S][4096] decoder lookup table derived from the record's symbol table
+  uint32_t *dtab;         // [S][4096] decoder table derived from the record's symbol table (dtab_entry)
 };
+
+// ---------------------------------------------------------------- timing
+// Events that the next kernel launch of this thread records when the kernel
+// starts and when it ends (both null: none).  The host scheduler sets them
+// around one launch to time it.
+struct LaunchTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchTimer &launch_timer();
 
 // -------------------------------------------------------------- launchers
 // All launches go to `st`; `pass` is the global pass counter (for failure

@@ -21,11 +21,28 @@
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "cqsim_impl.h"
 
 namespace cq {
+
+LaunchTimer &launch_timer() {
+  static thread_local LaunchTimer t;
+  return t;
+}
+
+// a launch that is being timed goes through the AMD launch call that records
+// the thread's timing events at kernel start and end; other launches take the
+// ordinary (cheaper) path
+#define CQ_LAUNCH(K, G, B, S, ST, ...)                                                                    \
+  do {                                                                                                    \
+    if (launch_timer().start)                                                                             \
+      hipExtLaunchKernelGGL(K, G, B, S, ST, launch_timer().start, launch_timer().stop, 0, __VA_ARGS__);   \
+    else                                                                                                  \
+      hipLaunchKernelGGL(K, G, B, S, ST, __VA_ARGS__);                                                    \
+  } while (0)
 
 // ------------------------------------------------------------------ helpers
 
@@ -81,14 +98,17 @@ __device__ __forceinline__ void lds_sync() {
   __asm__ __volatile__("" ::: "memory");
 }
 
-// inclusive scan of a u32 over one wavefront
+// inclusive scan of a u32 over one (full) wavefront with DPP: a scan inside
+// every row of 16 lanes (shifts by 1, 2, 4 and 8, lanes shifted in from
+// outside the row read 0), then lane 15 of each row added to the next row
+// (rows 1 and 3) and lane 31 added to rows 2 and 3
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= (uint32_t)off) x += y;
-  }
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111 /* row_shr:1 */, 0xF, 0xF, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112 /* row_shr:2 */, 0xF, 0xF, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114 /* row_shr:4 */, 0xF, 0xF, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118 /* row_shr:8 */, 0xF, 0xF, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142 /* row_bcast:15 */, 0xA, 0xF, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143 /* row_bcast:31 */, 0xC, 0xF, false);
   return x;
 }
 
@@ -322,7 +342,7 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
                                                            const uint8_t *arena, StateMeta cur, const double *kscale,
                                                            Ctl *ctl, uint32_t pass) {
   if (ctl->flags) return;
-  __shared__ uint16_t dtab[1 << kLMax];
+  __shared__ uint32_t dtab[1 << kLMax];
   __shared__ double stg[kDecWaves][64 * kDecPitch];
   __shared__ uint32_t pf[kDecPf][64 * kDecWaves];
   const uint32_t u = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
@@ -361,7 +381,7 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
   {
     const uint4 *src = (const uint4 *)(cur.dtab + slice * (1u << kLMax));
     uint4 *dst = (uint4 *)dtab;
-    for (uint32_t i = tid; i < (1u << kLMax) / 8; i += 64 * kDecWaves) dst[i] = src[i];
+    for (uint32_t i = tid; i < (1u << kLMax) / 4; i += 64 * kDecWaves) dst[i] = src[i];
   }
   // words [from, from + kDecPf) of the chunk; the address of a word past the
   // end is replaced by a valid one (the load is always issued)
@@ -389,10 +409,22 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
   __builtin_amdgcn_s_waitcnt(0);
   for (uint64_t j0 = 0; j0 < B; j0 += R) {
     if (active) {
-      for (uint32_t q = 0; q < R; q++) {
+      for (uint32_t q = 0; q < R;) {
         if (br.nbits < kLMax) br.refill(pf, tid);
         const uint32_t e = dtab[(uint32_t)(br.buf >> (64 - kLMax))];
-        const uint32_t sym = e & 1023u, len = e >> 10;
+        const uint32_t sym = e & 1023u;
+        if ((e >> 28) && q + 1 < R) {  // two symbols, neither an escape
+          const uint32_t len = ((e >> 10) & 15u) + ((e >> 24) & 15u);
+          br.buf <<= len;
+          br.nbits -= (int)len;
+          p += (double)((int)sym - kR);
+          st[lane * kDecPitch + q] = p * k;
+          p += (double)((int)((e >> 14) & 1023u) - kR);
+          st[lane * kDecPitch + q + 1] = p * k;
+          q += 2;
+          continue;
+        }
+        const uint32_t len = (e >> 10) & 15u;
         br.buf <<= len;
         br.nbits -= (int)len;
         double d;
@@ -415,6 +447,7 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
         }
         p += d;
         st[lane * kDecPitch + q] = p * k;
+        q++;
       }
     }
     prefetch(br.wi);  // the next round's words, ahead of this round's stores
@@ -1737,6 +1770,7 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   __shared__ uint8_t lens[kNSym];
   __shared__ uint32_t lav[kNSym];
   __shared__ uint16_t ent[kNSym];
+  __shared__ uint16_t one[1 << kLMax];  // one-symbol decoder table
   __shared__ uint32_t q[kLMax + 1];
   __shared__ uint32_t scratch[20];
   __shared__ uint64_t s64[16];
@@ -1916,14 +1950,23 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
     pre += sz[k];
   }
   __syncthreads();
-  uint16_t *dt = nxt.dtab + slot_slice[u] * (1u << kLMax);
+  // decoder table of the new record: the one-symbol table first (in LDS),
+  // then entries with a second symbol where both codes fit the 12 bits
   for (uint32_t e = tid; e < (1u << kLMax); e += blockDim.x) {
     uint32_t lo = 0, hi = n;  // last entry whose interval starts at or before e
     while (hi - lo > 1) {
       uint32_t mid = (lo + hi) >> 1;
       if (lav[mid] <= e) lo = mid; else hi = mid;
     }
-    dt[e] = ent[lo];
+    one[e] = ent[lo];
+  }
+  __syncthreads();
+  uint32_t *dt = nxt.dtab + slot_slice[u] * (1u << kLMax);
+  for (uint32_t e = tid; e < (1u << kLMax); e += blockDim.x) {
+    const uint32_t s1 = one[e] & 1023u, l1 = one[e] >> 10;
+    const uint32_t e2 = (e << l1) & ((1u << kLMax) - 1);
+    const uint32_t s2 = one[e2] & 1023u, l2 = one[e2] >> 10;
+    dt[e] = dtab_entry(s1, l1, s2, l2, s1 != 0 && s2 != 0 && l1 + l2 <= (uint32_t)kLMax);
   }
   if (tid == 0) sl.nused[u] = n;
 }
@@ -1965,7 +2008,7 @@ __device__ __forceinline__ uint2 enc_syms(const uint16_t *sym, uint64_t j, uint6
 // cb + w + 4, ...; every wavefront runs the same number of rounds so that
 // barriers line up.  STEPS = ceil(B / 256) steps of 256 symbols per chunk.
 template <int STEPS>
-__global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Geo g, uint32_t chunks_per_block,
+__global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_encode(Slots sl, Geo g, uint32_t chunks_per_block,
                                                                     const Ctl *ctl) {
   if (ctl->flags) return;
   extern __shared__ uint32_t lw_all[];  // [2][kEncWaves][stage_words]
@@ -1984,24 +2027,51 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Ge
   // (store wavefront only; capacity W words per chunk)
   uint32_t *blk = sl.stage + ((uint64_t)u * g.nchunks + cb) * W;
   uint32_t packed = 0;
-  uint2 cur[STEPS], nxt[STEPS];  // this and the next round's symbols of the lane
-  auto load_round = [&](uint2 (&d)[STEPS], uint32_t r) {
+  // symbols arrive two rounds ahead, escaped differences one round ahead:
+  // round r issues the symbol loads of round r + 2 and the escape loads of
+  // round r + 1 (whose symbols are already there), then codes round r.  An
+  // escape load is issued by every lane through a buffer resource; lanes
+  // without an escape use an offset past the end, which reads nothing.
+  const __amdgpu_buffer_rsrc_t escb = buf_rsrc(sl.esc + slot0, (uint32_t)(16 * g.L));
+  uint2 cur[STEPS], nxt[STEPS], nn[STEPS];
+  int64_t ecur[STEPS][4], enxt[STEPS][4];
+  auto load_syms = [&](uint2 (&d)[STEPS], uint32_t r) {
     const uint32_t c = cb + r * kEncWaves + wave;
     const uint64_t B = c < ce && r < rounds ? Bc : 0;
     const uint16_t *sym = sl.sym + slot0 + (uint64_t)(c < ce ? c : 0) * Bc;
 #pragma unroll
     for (int i = 0; i < STEPS; i++) d[i] = enc_syms(sym, (uint64_t)i * 256 + 4 * (uint64_t)lane, B);
   };
-  if (wave < kEncWaves) load_round(cur, 0);
+  auto load_escs = [&](int64_t (&e)[STEPS][4], const uint2 (&d)[STEPS], uint32_t r) {
+    const uint32_t c = cb + r * kEncWaves + wave;
+    const uint64_t B = c < ce && r < rounds ? Bc : 0;
+#pragma unroll
+    for (int i = 0; i < STEPS; i++) {
+      const uint32_t sv[4] = {d[i].x & 0xffffu, d[i].x >> 16, d[i].y & 0xffffu, d[i].y >> 16};
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const uint64_t j = (uint64_t)i * 256 + 4 * (uint64_t)lane + k;
+        const bool is_esc = j < B && sv[k] == 0;
+        const uint32_t off = is_esc ? (uint32_t)(8 * ((uint64_t)c * Bc + j)) : 0xFFFFFFF0u;
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(escb, off, 0, 0);
+        e[i][k] = (int64_t)(((uint64_t)x.y << 32) | x.x);
+      }
+    }
+  };
+  if (wave < kEncWaves) {
+    load_syms(cur, 0);
+    load_syms(nxt, 1);
+    load_escs(ecur, cur, 0);
+  }
   __syncthreads();  // code table in LDS
   for (uint32_t r = 0; r <= rounds; r++) {  // one more round: the store wavefront drains the last one
     const uint32_t buf = r & 1u;
     if (wave < kEncWaves && r < rounds) {
-      load_round(nxt, r + 1);
+      load_syms(nn, r + 2);
+      load_escs(enxt, nxt, r + 1);
       const uint32_t c = cb + r * kEncWaves + wave;
       const bool active = c < ce;
       const uint64_t B = active ? Bc : 0;
-      const int64_t *esc = sl.esc + slot0 + (uint64_t)(active ? c : 0) * Bc;
       uint32_t *lw = lw_all + (uint64_t)(buf * kEncWaves + wave) * W;
       uint64_t run = 0;
       uint32_t zeroed = 0;  // words [0, zeroed) of lw are cleared for this chunk
@@ -2024,14 +2094,14 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Ge
             cw[k] = codes[sv[k]];
             bl += cw[k] & 0xffu;
             if (sv[k] == 0) {
-              z[k] = zigzag(esc[j + k]);
+              z[k] = zigzag(ecur[i][k]);
               nb[k] = (uint32_t)bitlen64(z[k]);
               bl += kEscBits + nb[k];
             }
           }
         }
         const uint32_t inc = wave_incl_scan(bl);
-        const uint32_t tot = (uint32_t)__shfl((int)inc, 63, 64);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
         uint64_t pos = run + inc - bl;
         uint32_t end = (uint32_t)((run + tot + 31) >> 5);
         if (end > W) end = W;
@@ -2072,7 +2142,12 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), 4) k_encode(Slots sl, Ge
       if (nw > W) nw = W;  // at most 68 bits per value: never reached by a consistent codebook
       if (lane == 0) cnw[buf][wave] = active ? nw : 0u;
 #pragma unroll
-      for (int i = 0; i < STEPS; i++) cur[i] = nxt[i];
+      for (int i = 0; i < STEPS; i++) {
+        cur[i] = nxt[i];
+        nxt[i] = nn[i];
+#pragma unroll
+        for (int k = 0; k < 4; k++) ecur[i][k] = enxt[i][k];
+      }
     } else if (wave == kEncWaves && r > 0) {  // store the previous round's chunks, packed
       const uint32_t pb = buf ^ 1u;
       for (uint32_t w = 0; w < (uint32_t)kEncWaves; w++) {
@@ -2249,9 +2324,9 @@ void launch_dense_mfma(hipStream_t st, const Slots &sl, const Geo &g, int nslots
   if (blocks < 1) blocks = 1;
   const dim3 grid((unsigned)blocks), block(256);
   switch (gd.k) {
-    case 3: hipLaunchKernelGGL(k_dense_mfma<3>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
-    case 4: hipLaunchKernelGGL(k_dense_mfma<4>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
-    default: hipLaunchKernelGGL(k_dense_mfma<5>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
+    case 3: CQ_LAUNCH(k_dense_mfma<3>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
+    case 4: CQ_LAUNCH(k_dense_mfma<4>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
+    default: CQ_LAUNCH(k_dense_mfma<5>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
   }
 }
 
@@ -2275,22 +2350,23 @@ __global__ void k_readout(Slots sl, Geo g, uint64_t first, uint64_t count, int p
 
 // =============================================================== launchers
 
+
 static inline unsigned grid1(uint64_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *kscale,
                        int with_norm) {
-  hipLaunchKernelGGL(k_begin_pass, dim3(1), dim3(1024), 0, st, ctl, cur.step, cur.sq, nslices, kscale, with_norm);
+  CQ_LAUNCH(k_begin_pass, dim3(1), dim3(1024), 0, st, ctl, cur.step, cur.sq, nslices, kscale, with_norm);
 }
 
 void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots) {
   uint64_t n = (uint64_t)nslots * kGqParts * kNSym;
-  hipLaunchKernelGGL(k_reset_slots, dim3(grid1(n, 256)), dim3(256), 0, st, sl, nslots);
+  CQ_LAUNCH(k_reset_slots, dim3(grid1(n, 256)), dim3(256), 0, st, sl, nslots);
 }
 
 void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots, int kind,
                  uint64_t x, const double *factors, const Ctl *ctl) {
   uint64_t total = (uint64_t)nslots * g.L;
-  hipLaunchKernelGGL(k_init, dim3(grid1(total, 256)), dim3(256), 0, st, sl, g, slot_slice, total, kind, x, factors,
+  CQ_LAUNCH(k_init, dim3(grid1(total, 256)), dim3(256), 0, st, sl, g, slot_slice, total, kind, x, factors,
                      ctl);
 }
 
@@ -2300,9 +2376,9 @@ void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
   dim3 grid(grid1(g.nchunks, per_wg), (unsigned)nslots);
   const bool full = (1ull << g.chunk_log2) >= (uint64_t)kDecRow && g.nchunks % per_wg == 0;
   if (full)
-    hipLaunchKernelGGL(k_decode<true>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
+    CQ_LAUNCH(k_decode<true>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
   else
-    hipLaunchKernelGGL(k_decode<false>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
+    CQ_LAUNCH(k_decode<false>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
 }
 
 static int gate_kind(const GateDesc &gd) {
@@ -2318,7 +2394,7 @@ static void launch_minmax_k(hipStream_t st, const Slots &sl, const Geo &g, const
   const uint64_t per_wg = (uint64_t)threads * 16;  // at least 16 amplitudes per thread
   uint64_t G = (g.L + per_wg - 1) / per_wg;
   if (G > 64) G = 64;
-  hipLaunchKernelGGL(k_gate_minmax<KIND>, dim3((unsigned)G, (unsigned)nslots), dim3(threads), 0, st, sl, g, ss, gd,
+  CQ_LAUNCH(k_gate_minmax<KIND>, dim3((unsigned)G, (unsigned)nslots), dim3(threads), 0, st, sl, g, ss, gd,
                      ctl);
 }
 
@@ -2333,7 +2409,7 @@ void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uin
 }
 
 void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl) {
-  hipLaunchKernelGGL(k_rel_step, dim3(grid1((uint64_t)nslots, 256)), dim3(256), 0, st, sl, nslots, rel, ctl);
+  CQ_LAUNCH(k_rel_step, dim3(grid1((uint64_t)nslots, 256)), dim3(256), 0, st, sl, nslots, rel, ctl);
 }
 
 // Returns the number of partial results per slot that the launch writes.
@@ -2344,7 +2420,7 @@ static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const
   if (KIND != 3 && g.chunk_log2 <= 8 && g.L >= 4 * kWr && (KIND != 1 || (1ull << gd.tloc[0]) < kWr)) {
     const uint32_t nr = (uint32_t)(g.L / kWr);
     const uint32_t G = nr / 4 < kGqWgs ? nr / 4 : kGqWgs;
-    hipLaunchKernelGGL((k_gq_wave<KIND == 3 ? 0 : KIND>), dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss,
+    CQ_LAUNCH((k_gq_wave<KIND == 3 ? 0 : KIND>), dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss,
                        gd, qp, ctl, pass);
     return G;
   }
@@ -2354,14 +2430,14 @@ static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const
   const dim3 grid(G, (unsigned)nslots);
   if (C == kGqTile) {  // whole tiles of 256 threads x 4 amplitudes
     if (KIND == 3)
-      hipLaunchKernelGGL((k_gate_quant<3, 4, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass);
+      CQ_LAUNCH((k_gate_quant<3, 4, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass);
     else
-      hipLaunchKernelGGL((k_gate_quant_pipe<KIND == 3 ? 0 : KIND>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl,
+      CQ_LAUNCH((k_gate_quant_pipe<KIND == 3 ? 0 : KIND>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl,
                          pass);
     return G;
   }
   const int threads = g.L >= 256 ? 256 : 64;
-  hipLaunchKernelGGL((k_gate_quant<KIND, 4, false>), grid, dim3(threads), 0, st, sl, g, ss, gd, qp, ctl, pass);
+  CQ_LAUNCH((k_gate_quant<KIND, 4, false>), grid, dim3(threads), 0, st, sl, g, ss, gd, qp, ctl, pass);
   return G;
 }
 
@@ -2378,7 +2454,7 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
       if (npairs >= 4) {
         const uint32_t G = npairs / 4 < kGqWgs ? npairs / 4 : kGqWgs;
         const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
-        hipLaunchKernelGGL(k_gq_wave_pair, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
+        CQ_LAUNCH(k_gq_wave_pair, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
         return G;
       }
     }
@@ -2391,14 +2467,14 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
         const uint32_t npairs = cross ? ntiles : ntiles / 2;
         const uint32_t G = npairs < kGqWgs ? npairs : kGqWgs;
         const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
-        hipLaunchKernelGGL(k_gate_quant_pair<kGqV>, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
+        CQ_LAUNCH(k_gate_quant_pair<kGqV>, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
         return cross ? G : 2 * G;
       }
       const uint32_t ntiles = (uint32_t)(g.L / kGpTile);
       const uint32_t npairs = cross ? ntiles : ntiles / 2;
       const uint32_t G = npairs < kGqWgs ? npairs : kGqWgs;
       const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
-      hipLaunchKernelGGL(k_gate_quant_pair_pipe, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
+      CQ_LAUNCH(k_gate_quant_pair_pipe, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
       return cross ? G : 2 * G;
     }
     return launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);  // short slices: general indexing
@@ -2412,7 +2488,7 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
 
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
                      uint32_t nparts, Ctl *ctl) {
-  hipLaunchKernelGGL(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, nparts, ctl);
+  CQ_LAUNCH(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, nparts, ctl);
 }
 
 // chunks per encode (and finish) workgroup: about four workgroups per CU over
@@ -2434,7 +2510,7 @@ void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, co
   const size_t shm = (size_t)2 * kEncWaves * sl.stage_words * 4;
   const dim3 block(64 * (kEncWaves + 1));
   if (g.chunk_log2 <= 8) {
-    hipLaunchKernelGGL(k_encode<1>, grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH(k_encode<1>, grid, block, shm, st, sl, g, cpb, ctl);
     return;
   }
   // dynamic LDS above the default needs the attribute (chunks of 1024: ~70 KB)
@@ -2445,9 +2521,9 @@ void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, co
     shm_set = shm;
   }
   if (g.chunk_log2 == 9)
-    hipLaunchKernelGGL(k_encode<2>, grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH(k_encode<2>, grid, block, shm, st, sl, g, cpb, ctl);
   else
-    hipLaunchKernelGGL(k_encode<4>, grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH(k_encode<4>, grid, block, shm, st, sl, g, cpb, ctl);
 }
 
 void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
@@ -2455,13 +2531,13 @@ void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
                    uint32_t pass) {
   const uint32_t cpb = enc_chunks_per_block(g, nslots);
   dim3 grid(grid1(g.nchunks, cpb), (unsigned)nslots);
-  hipLaunchKernelGGL(k_finish, grid, dim3(256), 0, st, sl, g, slot_slice, nslots, qp, arena, arena_cap, nxt, cpb,
+  CQ_LAUNCH(k_finish, grid, dim3(256), 0, st, sl, g, slot_slice, nslots, qp, arena, arena_cap, nxt, cpb,
                      ctl, pass);
 }
 
 void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,
                     int probabilities, double *out) {
-  hipLaunchKernelGGL(k_readout, dim3(grid1(count, 256)), dim3(256), 0, st, sl, g, first_amp, count, probabilities,
+  CQ_LAUNCH(k_readout, dim3(grid1(count, 256)), dim3(256), 0, st, sl, g, first_amp, count, probabilities,
                      out);
 }
 

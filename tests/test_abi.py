@@ -93,6 +93,22 @@ def test_binding_converts_gates_without_the_device():
     assert m[2 * (1 * 4 + 2)] == 1.0  # SWAP row 1, column 2
 
 
+def test_circuit_slices_point_into_one_marshalled_array():
+    import ctypes as C
+    import qcircuits as qc
+    gates = [qc.H(q) for q in range(6)] + [qc.CP(1, 4, 0.5), qc.SWAP(0, 5)]
+    circ = cq.Circuit(gates)
+    assert len(circ) == 8
+    base = C.addressof(circ.pointer().contents)
+    sub = circ[2:7][1:3]  # gates 3 and 4
+    assert len(sub) == 2
+    assert C.addressof(sub.pointer().contents) == base + 3 * C.sizeof(cq.GateStruct)
+    assert sub.pointer()[0].targets[0] == 3 and sub.pointer()[1].targets[0] == 4
+    assert len(circ[7:100]) == 1 and len(circ[5:2]) == 0
+    with pytest.raises(ValueError):
+        circ[::2]
+
+
 def test_no_device_means_a_loud_failure():
     """Without a GPU the library refuses to run (no CPU fallback)."""
     try:

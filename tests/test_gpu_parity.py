@@ -149,6 +149,31 @@ def test_workspace_batches_and_arena_growth():
     assert st["arena_bytes"] > 2 * 8192  # grew at least once
 
 
+def test_arena_overflow_inside_one_batch():
+    """One batch from a minimal arena: the records outgrow it mid-batch, the
+    failed pass and those after it are replayed into a larger arena."""
+    n, sl, cl, eb = 12, 7, 6, 1e-7
+    say("overflow mid-batch", n, sl, cl, eb)
+    gates = qc.random_layered(n, 3, seed=9)
+    sim, orc = run_both(n, sl, cl, eb, gates, check_every=len(gates), arena_bytes=4096)
+    assert sim.stats()["arena_bytes"] > 2 * 4096
+
+
+def test_circuit_slices_match_gate_lists():
+    n, sl, cl, eb = 11, 7, 6, 1e-6
+    say("circuit slices", n, sl, cl, eb)
+    gates = gate_zoo(n, seed=4)
+    a = cq.Sim(n, sl, eb, chunk_log2=cl)
+    b = cq.Sim(n, sl, eb, chunk_log2=cl)
+    circ = cq.Circuit(gates)
+    h = len(gates) // 2
+    a.apply(gates[:h])
+    a.apply(gates[h:])
+    b.apply(circ[:h])
+    b.apply(circ[h:])
+    assert a.records() == b.records()
+
+
 def test_invalid_gate_stops_with_completed_prefix():
     n, sl, cl, eb = 8, 5, 4, 1e-6
     say("invalid gate", n, sl)
