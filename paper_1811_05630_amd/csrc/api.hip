@@ -440,6 +440,11 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
   s->kt_begin(K_BEGIN);
   launch_begin_pass(st, s->ctl, cur, s->nslices, s->kscale, init_kind >= 0 ? 0 : 1);
   s->kt_end();
+  const GateDesc &gq = gd.kind == 4 ? s->ident : gd;
+  // compact workspace (int32 codes) when decode feeds the quantising kernel
+  // directly and that kernel reads it; the device still falls back to FP64
+  // for a pass whose codes may not fit
+  const bool compact = init_kind < 0 && !qp.rel && gd.kind != 4 && gq_compact(s->geo, gq);
   for (uint64_t b0 = 0; b0 < s->nslices; b0 += (uint64_t)s->W) {
     const int ns = (int)std::min<uint64_t>((uint64_t)s->W, s->nslices - b0);
     const uint64_t *ss = table + b0;
@@ -449,7 +454,7 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
       s->kt_end();
     } else {
       s->kt_begin(K_DECODE);
-      launch_decode(st, s->slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass);
+      launch_decode(st, s->slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass, compact);
       s->kt_end();
     }
     if (gd.kind == 4) {  // fused block on matrix cores, in place; then quantised as the identity
@@ -465,9 +470,8 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
       launch_rel_step(st, s->slots, ns, qp.eb, s->ctl);
       s->kt_end();
     }
-    const GateDesc &gq = gd.kind == 4 ? s->ident : gd;
     s->kt_begin(K_GATEQ);
-    const uint32_t nparts = launch_gate_quant(st, s->slots, s->geo, ss, ns, gq, qp, s->ctl, pass);
+    const uint32_t nparts = launch_gate_quant(st, s->slots, s->geo, ss, ns, gq, qp, s->ctl, pass, compact, s->kscale);
     s->kt_end();
     s->kt_begin(K_CODEBOOK);
     launch_codebook(st, s->slots, ss, ns, nxt, nparts, s->ctl);
@@ -496,8 +500,11 @@ int clear_flags(sim_t *s) {
   s->h_ctl->fail_pass = 0;
   s->h_ctl->pending_bump = 0;  // a failed batch's records are not counted
   s->h_ctl->pending_bytes = 0;
+  s->h_ctl->wide = 1;  // the failed pass may have changed the flag: the replay decodes to FP64
+  s->h_ctl->wide_next = 1;
   HIP_TRY(hipMemcpyAsync(&s->ctl->flags, &s->h_ctl->flags, 8, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(&s->ctl->pending_bump, &s->h_ctl->pending_bump, 16, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(&s->ctl->wide, &s->h_ctl->wide, 8, hipMemcpyHostToDevice, s->stream));
   launch_reset_slots(s->stream, s->slots, s->W);
   HIP_TRY(hipStreamSynchronize(s->stream));
   return check_launch("reset_slots");
@@ -660,6 +667,7 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
     return set_err(SIM_ENOMEM, "pinned host allocation failed");
   }
   memset(s->h_ctl, 0, sizeof(Ctl));
+  s->h_ctl->wide = s->h_ctl->wide_next = 1;
   if (hipMemcpy(s->ctl, s->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice) != hipSuccess) {
     sim_destroy(s);
     return set_err(SIM_EDEVICE, "control block upload failed");
@@ -910,7 +918,7 @@ static int readout(sim_t *s, uint64_t begin, uint64_t count, double *out, int pr
     const uint64_t j1 = std::min<uint64_t>((end + L - 1) / L, j0 + (uint64_t)s->W);
     const int ns = (int)(j1 - j0);
     launch_decode(s->stream, s->slots, s->geo, table + j0, ns, s->arena[s->cur], s->meta[s->cur], s->kscale, s->ctl,
-                  s->pass_counter);
+                  s->pass_counter, false);
     const uint64_t bend = std::min<uint64_t>(end, j1 * L);
     uint64_t k = i;
     while (k < bend) {
@@ -1078,6 +1086,9 @@ int sim_import_slice(sim_t *s, uint64_t j, const void *buf, uint64_t len) {
   s->h_ctl->bump = off + align_up(len, kRecAlign);
   s->h_ctl->cur_bytes = s->h_ctl->cur_bytes - old_len + len;
   HIP_TRY(hipMemcpy(&s->ctl->bump, &s->h_ctl->bump, 16, hipMemcpyHostToDevice));
+  // the record's codes are not known to fit int32: the next pass decodes to FP64
+  s->h_ctl->wide_next = 1;
+  HIP_TRY(hipMemcpy(&s->ctl->wide_next, &s->h_ctl->wide_next, 4, hipMemcpyHostToDevice));
   return SIM_OK;
 }
 

@@ -56,7 +56,11 @@ struct Ctl {
   double s;               // 1 / sqrt(N)
   uint64_t pending_bump;  // aligned bytes of the last batch written; added to bump and
   uint64_t pending_bytes; // cur_bytes by the next launch that starts a batch or a pass
-  uint64_t pad[4];
+  uint32_t wide;          // 1: the records of this pass may hold |q| >= 2^31 (the decoded
+                          // workspace is FP64); 0: every q fits int32 (compact workspace)
+  uint32_t wide_next;     // set by any quantisation of this pass that produced |q| >= 2^31;
+                          // moved to `wide` by the next pass's begin
+  uint64_t pad[3];
 };
 
 // ---------------------------------------------------------------- gate block
@@ -152,14 +156,21 @@ void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t 
 void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots);
 void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots, int kind,
                  uint64_t x, const double *factors, const Ctl *ctl);
+// compact: the gate_quant launch of this pass reads a compact workspace when
+// ctl->wide is clear (gq_compact below); decode then writes int32 codes q
+// instead of the FP64 values q * kscale
 void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl, uint32_t pass);
+                   const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl, uint32_t pass,
+                   bool compact);
 void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                         const GateDesc &gd, const Ctl *ctl);
 void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl);
 // returns the number of partial results per slot that the launch writes
 uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                           const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass);
+                           const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass, bool compact,
+                           const double *kscale);
+// whether the gate_quant kernel chosen for gd can read a compact workspace
+bool gq_compact(const Geo &g, const GateDesc &gd);
 // nparts: partial results per slot written by the preceding gate_quant launch
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
                      uint32_t nparts, Ctl *ctl);

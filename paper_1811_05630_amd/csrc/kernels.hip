@@ -199,6 +199,8 @@ __global__ void __launch_bounds__(1024) k_begin_pass(Ctl *ctl, const double *ste
     if (ctl->cur_bytes > ctl->peak_bytes) ctl->peak_bytes = ctl->cur_bytes;
     ctl->bump = 0;
     ctl->cur_bytes = 0;
+    ctl->wide = ctl->wide_next;  // the codes this pass decodes came from the last quantisation
+    ctl->wide_next = 0;
   }
   if (with_norm == 0 || with_norm == 3) return;
   uint64_t active;
@@ -286,21 +288,48 @@ __global__ void k_init(Slots sl, Geo g, const uint64_t *slot_slice, uint64_t tot
 
 // ------------------------------------------------------------------ decode
 // One lane per chunk: the lane walks its chunk's bit stream serially (12-bit
-// peek into the decoder table, escapes carry the exact difference), keeps the
-// running sum p and writes a = p * k.  Four wavefronts share one decoder
-// table.  Values go out in rounds of 16 per lane through an LDS tile, so that
-// every store instruction writes whole 128-byte lines.
-// Stream words come from a per-lane LDS slot that holds the next kDecPf words
-// of the chunk, loaded while the previous round's values were being stored:
-// the loads are issued before those stores, so waiting for them never waits
-// for the stores (one in-order counter covers both on CDNA).  A round that
-// needs more words than the slot holds reads them from global memory.
+// peek into the decoder table, escapes carry the exact difference) and keeps
+// the running sum p.  It writes the FP64 value a = p * k, or in a compact
+// workspace the int32 code p itself.  Four wavefronts share one decoder
+// table.  Values go out in rounds through an LDS tile (16 FP64 or 32 int32
+// values per lane and round), so that every store instruction writes whole
+// 128-byte lines.
+// Stream words come from a per-lane LDS slot that holds the next PF words of
+// the chunk, loaded while the previous round's values were being stored: the
+// loads are issued before those stores, so waiting for them never waits for
+// the stores (one in-order counter covers both on CDNA).  A round that needs
+// more words than the slot holds reads them from global memory.
 
-constexpr int kDecWaves = 4;   // wavefronts per workgroup
-constexpr int kDecRow = 16;    // values per lane per round
-constexpr int kDecPitch = 17;  // LDS row pitch in doubles (breaks bank conflicts)
-constexpr int kDecPf = 8;      // stream words prefetched per lane per round
+constexpr int kDecWaves = 4;       // wavefronts per workgroup
+constexpr int kDecPfMax = 12;      // largest slot (words per lane)
+constexpr int kDecStage = 64 * 17 * 8;  // tile bytes per wavefront: 64 rows of 16 FP64 or 32 int32 values, padded
 
+// The running sum p: FP64 (exact below 2^53) for the FP64 workspace; for
+// the compact one, whose codes all lie below 2^31 in magnitude, uint32
+// arithmetic modulo 2^32, which is exact for every partial sum as each of
+// them is such a code (an escaped difference may be larger, its sum is not).
+template <bool C32>
+struct DecFmt {  // FP64 workspace
+  using T = double;
+  using P = double;
+  static constexpr int R = 16, PITCH = 17, PF = 8;
+  static __device__ __forceinline__ double add(double p, int d) { return p + (double)d; }
+  static __device__ __forceinline__ double add_esc(double p, int64_t d) { return p + (double)d; }
+  static __device__ __forceinline__ double val(double p, double k) { return p * k; }
+};
+template <>
+struct DecFmt<true> {  // compact workspace: the code itself
+  using T = int32_t;
+  using P = uint32_t;
+  static constexpr int R = 32, PITCH = 33, PF = 12;
+  static __device__ __forceinline__ uint32_t add(uint32_t p, int d) { return p + (uint32_t)d; }
+  static __device__ __forceinline__ uint32_t add_esc(uint32_t p, int64_t d) { return p + (uint32_t)(uint64_t)d; }
+  static __device__ __forceinline__ int32_t val(uint32_t p, double) { return (int32_t)p; }
+};
+static_assert(64 * DecFmt<true>::PITCH * 4 <= kDecStage && 64 * DecFmt<false>::PITCH * 8 <= kDecStage, "tile");
+static_assert(DecFmt<true>::PF <= kDecPfMax && DecFmt<false>::PF <= kDecPfMax, "slot");
+
+template <int PF>
 struct BitReader {
   const uint32_t *w;  // the chunk's words (global)
   uint32_t nw;        // number of words
@@ -313,7 +342,7 @@ struct BitReader {
       uint32_t word = 0;
       const uint32_t d = wi - wbase;
       if (wi < nw) {
-        if (d < (uint32_t)kDecPf) {
+        if (d < (uint32_t)PF) {
           word = pf[d][tid];
         } else {  // past the prefetched words: wait for this load here, so
                   // that the common path after the join waits for LDS only
@@ -335,33 +364,22 @@ struct BitReader {
   }
 };
 
-// FULL: chunks of at least 16 values and a whole number of workgroups of
-// chunks per slot (every lane active, 16 values per round).
-template <bool FULL>
-__global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
-                                                           const uint8_t *arena, StateMeta cur, const double *kscale,
-                                                           Ctl *ctl, uint32_t pass) {
-  if (ctl->flags) return;
-  __shared__ uint32_t dtab[1 << kLMax];
-  __shared__ double stg[kDecWaves][64 * kDecPitch];
-  __shared__ uint32_t pf[kDecPf][64 * kDecWaves];
-  const uint32_t u = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-  const uint64_t slice = slot_slice[u];
-  const uint8_t *rec = arena + cur.rec_off[slice];
-  const uint32_t n_used = ld32(rec + 12);
-  const uint32_t nchunks = ld32(rec + 16);
-  const uint32_t n_words = ld32(rec + 20);
-  if (ld32(rec) != kMagic || n_used < 1 || n_used > (uint32_t)kNSym || nchunks != g.nchunks ||
-      ld32(rec + 8) != (uint32_t)g.chunk_log2) {
-    if (tid == 0) fail(ctl, kFlagCorrupt, pass);
-    return;
-  }
+// The chunks of one workgroup (after the record checks).  FULL: chunks of at
+// least 32 values and a whole number of workgroups of chunks per slot (every
+// lane active, whole rounds).
+template <bool FULL, bool C32>
+__device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, const StateMeta &cur, uint64_t slice,
+                                              uint32_t u, const uint32_t *offs, uint32_t nchunks, uint32_t n_words,
+                                              double k, uint32_t *dtab, uint8_t *stg,
+                                              uint32_t (*pf)[64 * kDecWaves], Ctl *ctl, uint32_t pass) {
+  using F = DecFmt<C32>;
+  using T = typename F::T;
+  constexpr int PF = F::PF, RMAX = F::R, PITCH = F::PITCH;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
   const uint32_t c0 = (blockIdx.x * kDecWaves + wave) * 64u;  // first chunk of this wavefront
   const uint32_t c = c0 + lane;
   const bool active = FULL || c < nchunks;
-  const uint32_t sym_bytes = (2 * n_used + 3) & ~3u;
-  const uint32_t *offs = (const uint32_t *)(rec + kHdr + sym_bytes);
-  BitReader br;
+  BitReader<PF> br;
   uint32_t w0 = 0;
   br.nw = 0;
   if (active) {
@@ -383,27 +401,26 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
     uint4 *dst = (uint4 *)dtab;
     for (uint32_t i = tid; i < (1u << kLMax) / 4; i += 64 * kDecWaves) dst[i] = src[i];
   }
-  // words [from, from + kDecPf) of the chunk; the address of a word past the
+  // words [from, from + PF) of the chunk; the address of a word past the
   // end is replaced by a valid one (the load is always issued)
-  uint32_t nx[kDecPf];
+  uint32_t nx[PF];
   auto prefetch = [&](uint32_t from) {
 #pragma unroll
-    for (int i = 0; i < kDecPf; i++) nx[i] = *(from + i < br.nw ? br.w + from + i : offs);
+    for (int i = 0; i < PF; i++) nx[i] = *(from + i < br.nw ? br.w + from + i : offs);
   };
   auto to_slot = [&]() {
     br.wbase = br.wi;
 #pragma unroll
-    for (int i = 0; i < kDecPf; i++) pf[i][tid] = nx[i];  // words past the chunk's end are never read
+    for (int i = 0; i < PF; i++) pf[i][tid] = nx[i];  // words past the chunk's end are never read
   };
   prefetch(0);
   __syncthreads();  // decoder table in LDS
   to_slot();
   const uint64_t B = 1ull << g.chunk_log2;
-  const uint32_t R = FULL ? (uint32_t)kDecRow : (B < (uint64_t)kDecRow ? (uint32_t)B : (uint32_t)kDecRow);
-  const double k = kscale[slice];
-  double *out = sl.ws + (uint64_t)u * 2 * g.L;
-  double *st = stg[wave];
-  double p = 0.0;  // running integer sum, exact in FP64 below 2^53
+  const uint32_t R = FULL ? (uint32_t)RMAX : (B < (uint64_t)RMAX ? (uint32_t)B : (uint32_t)RMAX);
+  T *out = (T *)(sl.ws + (uint64_t)u * 2 * g.L);
+  T *st = (T *)(stg + wave * kDecStage);
+  typename F::P p = 0;  // running sum
   // nothing is in flight when the rounds start, so no load issued here is
   // waited for inside them (where a wait would also wait for the stores)
   __builtin_amdgcn_s_waitcnt(0);
@@ -413,22 +430,10 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
         if (br.nbits < kLMax) br.refill(pf, tid);
         const uint32_t e = dtab[(uint32_t)(br.buf >> (64 - kLMax))];
         const uint32_t sym = e & 1023u;
-        if ((e >> 28) && q + 1 < R) {  // two symbols, neither an escape
-          const uint32_t len = ((e >> 10) & 15u) + ((e >> 24) & 15u);
+        if (sym == 0) {  // escape (never part of a two-symbol entry)
+          const uint32_t len = (e >> 10) & 15u;
           br.buf <<= len;
           br.nbits -= (int)len;
-          p += (double)((int)sym - kR);
-          st[lane * kDecPitch + q] = p * k;
-          p += (double)((int)((e >> 14) & 1023u) - kR);
-          st[lane * kDecPitch + q + 1] = p * k;
-          q += 2;
-          continue;
-        }
-        const uint32_t len = (e >> 10) & 15u;
-        br.buf <<= len;
-        br.nbits -= (int)len;
-        double d;
-        if (sym == 0) {
           if (br.nbits < kEscBits) br.refill(pf, tid);
           const int nb = (int)br.take(kEscBits);
           uint64_t z;
@@ -441,13 +446,24 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
             if (br.nbits < nb) br.refill(pf, tid);
             z = br.take(nb);
           }
-          d = (double)unzigzag(z);
-        } else {
-          d = (double)((int)sym - kR);
+          p = F::add_esc(p, unzigzag(z));
+          st[lane * PITCH + q] = F::val(p, k);
+          q++;
+          continue;
         }
-        p += d;
-        st[lane * kDecPitch + q] = p * k;
-        q++;
+        // one or two symbols on one path for every lane; the second value
+        // is written in any case (at q + 1 <= R, inside the padded row) and
+        // overwritten later when it was not decoded
+        const bool two = (e >> 28) && q + 1 < R;
+        const uint32_t len = ((e >> 10) & 15u) + (two ? ((e >> 24) & 15u) : 0u);
+        br.buf <<= len;
+        br.nbits -= (int)len;
+        p = F::add(p, (int)sym - kR);
+        st[lane * PITCH + q] = F::val(p, k);
+        const typename F::P p2 = F::add(p, (int)((e >> 14) & 1023u) - kR);
+        st[lane * PITCH + q + 1] = F::val(p2, k);
+        p = two ? p2 : p;
+        q += two ? 2u : 1u;
       }
     }
     prefetch(br.wi);  // the next round's words, ahead of this round's stores
@@ -456,14 +472,14 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
     __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
     if (FULL) {
 #pragma unroll
-      for (int i = 0; i < kDecRow; i++) {
-        const uint32_t idx = (uint32_t)i * 64u + lane, row = idx >> 4, col = idx & 15u;
-        out[(uint64_t)(c0 + row) * B + j0 + col] = st[row * kDecPitch + col];
+      for (int i = 0; i < RMAX; i++) {
+        const uint32_t idx = (uint32_t)i * 64u + lane, row = idx / RMAX, col = idx % RMAX;
+        out[(uint64_t)(c0 + row) * B + j0 + col] = st[row * PITCH + col];
       }
     } else {
       for (uint32_t idx = lane; idx < 64u * R; idx += 64u) {
         const uint32_t row = idx / R, col = idx % R;
-        if (c0 + row < nchunks) out[(uint64_t)(c0 + row) * B + j0 + col] = st[row * kDecPitch + col];
+        if (c0 + row < nchunks) out[(uint64_t)(c0 + row) * B + j0 + col] = st[row * PITCH + col];
       }
     }
     // the next round's slot; its words were loaded before the stores above,
@@ -471,6 +487,37 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
     to_slot();
     __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");  // tile read before the next round writes it
   }
+}
+
+template <bool FULL>
+__global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
+                                                           const uint8_t *arena, StateMeta cur, const double *kscale,
+                                                           Ctl *ctl, uint32_t pass, int compact_ok) {
+  if (ctl->flags) return;
+  // compact workspace: the int32 codes q themselves (every |q| < 2^31), the
+  // gate kernel multiplies by the slice's scale; else the FP64 values q * k
+  const bool c32 = compact_ok && !ctl->wide;
+  __shared__ uint32_t dtab[1 << kLMax];
+  __shared__ __align__(16) uint8_t stg[kDecWaves * kDecStage];
+  __shared__ uint32_t pf[kDecPfMax][64 * kDecWaves];
+  const uint32_t u = blockIdx.y, tid = threadIdx.x;
+  const uint64_t slice = slot_slice[u];
+  const uint8_t *rec = arena + cur.rec_off[slice];
+  const uint32_t n_used = ld32(rec + 12);
+  const uint32_t nchunks = ld32(rec + 16);
+  const uint32_t n_words = ld32(rec + 20);
+  if (ld32(rec) != kMagic || n_used < 1 || n_used > (uint32_t)kNSym || nchunks != g.nchunks ||
+      ld32(rec + 8) != (uint32_t)g.chunk_log2) {
+    if (tid == 0) fail(ctl, kFlagCorrupt, pass);
+    return;
+  }
+  const uint32_t sym_bytes = (2 * n_used + 3) & ~3u;
+  const uint32_t *offs = (const uint32_t *)(rec + kHdr + sym_bytes);
+  if (c32)
+    decode_chunks<FULL, true>(sl, g, cur, slice, u, offs, nchunks, n_words, 0.0, dtab, stg, pf, ctl, pass);
+  else
+    decode_chunks<FULL, false>(sl, g, cur, slice, u, offs, nchunks, n_words, kscale[slice], dtab, stg, pf, ctl,
+                               pass);
 }
 
 // ------------------------------------------------------------ gate + quantise
@@ -666,13 +713,31 @@ struct Acc {
   uint32_t nesc;
   double emax;
   bool ok;
+  bool wide;  // some |q| >= 2^31: the next pass needs an FP64 workspace
   __device__ __forceinline__ void zero() {
     lo = hi = 0;
     nesc = 0;
     emax = 0.0;
     ok = true;
+    wide = false;
+  }
+  __device__ __forceinline__ void merge(const Acc &o) {  // exact: integer sums, max, flags
+    const uint64_t x = lo + o.lo;
+    hi += o.hi + (x < lo);
+    lo = x;
+    nesc += o.nesc;
+    emax = fmax(emax, o.emax);
+    ok = ok && o.ok;
+    wide = wide || o.wide;
   }
 };
+
+// codes outside int32 (only on the paths taken when some |q| >= 2^24)
+template <int V>
+__device__ __forceinline__ void note_wide(const double (&qr)[V], const double (&qi)[V], Acc &acc) {
+#pragma unroll
+  for (int v = 0; v < V; v++) acc.wide = acc.wide || !(fabs(qr[v]) < 0x1p31) || !(fabs(qi[v]) < 0x1p31);
+}
 
 // Symbols of one tile of C consecutive amplitudes from offset ob (a chunk
 // head: C is a multiple of the chunk length): Lorenzo differences inside
@@ -729,6 +794,7 @@ __device__ __forceinline__ void tile_symbols(const double (&qr)[V], const double
     nval += 2;
   }
   add_squares<V>(qr, qi, acc.lo, acc.hi);  // values past C are zero
+  note_wide<V>(qr, qi, acc);
   // histogram: a wavefront whose values all share one symbol adds once
   const bool any = nval != 0;
   const uint32_t s0 = (uint32_t)__shfl((int)sr[0], 0, 64);
@@ -896,6 +962,7 @@ __device__ __forceinline__ void tile_symbols_full(const double (&qr)[V], const d
       }
     }
     add_squares<V>(qr, qi, acc.lo, acc.hi);
+    note_wide<V>(qr, qi, acc);
   } else {
     int ir[V], ii[V], dr[V], di[V];
     bool any_esc = false;
@@ -967,6 +1034,7 @@ __device__ __forceinline__ void write_partial(Acc &acc, uint32_t *h, uint64_t (*
     wred[wave][3] = (uint64_t)__double_as_longlong(em);
   }
   if (__ballot(!acc.ok) && lane == 0) fail(ctl, kFlagBound, pass);
+  if (__ballot(acc.wide) && lane == 0) atomicOr(&ctl->wide_next, 1u);
   __syncthreads();
   if (pidx >= kGqParts) return;  // launches never exceed the partial count
   uint32_t *hp = sl.hpart + ((uint64_t)u * kGqParts + pidx) * kNSym;
@@ -1364,8 +1432,11 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant_pair_pipe(Slots sl, Geo g
 
 constexpr uint32_t kWr = 256;  // amplitudes per wavefront range
 
-struct WRange {
+struct WRange {  // FP64 workspace: the values
   double r[4], i[4];
+};
+struct WRange32 {  // compact workspace: the int32 codes, times the slice's scale on use
+  int32_t r[4], i[4];
 };
 
 __device__ __forceinline__ void wr_load(WRange &x, __amdgpu_buffer_rsrc_t ws, uint32_t L, uint32_t ob) {
@@ -1375,6 +1446,26 @@ __device__ __forceinline__ void wr_load(WRange &x, __amdgpu_buffer_rsrc_t ws, ui
     x.r[v] = buf_ld_f64(ws, 8 * (ob + v * 64 + lane));
     x.i[v] = buf_ld_f64(ws, 8 * (L + ob + v * 64 + lane));
   }
+}
+__device__ __forceinline__ void wr_load(WRange32 &x, __amdgpu_buffer_rsrc_t ws, uint32_t L, uint32_t ob) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    x.r[v] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ws, 4 * (ob + v * 64 + lane), 0, 0);
+    x.i[v] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ws, 4 * (L + ob + v * 64 + lane), 0, 0);
+  }
+}
+// the values of a loaded range: (double)q * k rounds exactly like the FP64
+// workspace's q * k
+__device__ __forceinline__ const WRange &wr_val(const WRange &x, double) { return x; }
+__device__ __forceinline__ WRange wr_val(const WRange32 &x, double k) {
+  WRange y;
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    y.r[v] = (double)x.r[v] * k;
+    y.i[v] = (double)x.i[v] * k;
+  }
+  return y;
 }
 
 __device__ __forceinline__ double lane63(double x) {  // the value of lane 63, in every lane
@@ -1430,6 +1521,7 @@ __device__ __forceinline__ void wr_symbols(const double (&qr)[4], const double (
       }
     }
     add_squares<4>(qr, qi, acc.lo, acc.hi);
+    note_wide<4>(qr, qi, acc);
   } else {
     int ir[4], ii[4], dr[4], di[4];
     int64_t t = 0;  // sum of q^2 of this thread's 8 values, below 2^51
@@ -1531,37 +1623,49 @@ __device__ __forceinline__ void wr_step(const WRange &x, uint32_t ob, const GqSl
 }
 
 // Wavefront w of workgroup (x, u) takes ranges x * 4 + w + k * 4G of slot u.
+// R: WRange (FP64 workspace) or WRange32 (compact workspace).
+template <int KIND, typename R>
+__device__ __forceinline__ void gq_wave_ranges(const GqSlot &s, double k, const GateDesc &gd, const Geo &g,
+                                               uint32_t *h, Acc &acc) {
+  const uint32_t L = (uint32_t)g.L;
+  const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t n = (L / kWr) / nwv;  // ranges per wavefront: 1 or even
+  auto range_of = [&](uint32_t j) { return (j < n ? w0 + j * nwv : w0) * kWr; };  // past the end: w0 again
+  R A, B;
+  wr_load(A, s.ws, L, range_of(0));
+  if (n == 1) {
+    wr_step<KIND>(wr_val(A, k), range_of(0), s, gd, g, h, acc);
+  } else {
+    wr_load(B, s.ws, L, range_of(1));
+    wr_step<KIND>(wr_val(A, k), range_of(0), s, gd, g, h, acc);
+    wr_load(A, s.ws, L, range_of(2));
+    for (uint32_t j = 1; j + 1 < n; j += 2) {
+      wr_step<KIND>(wr_val(B, k), range_of(j), s, gd, g, h, acc);
+      wr_load(B, s.ws, L, range_of(j + 2));
+      wr_step<KIND>(wr_val(A, k), range_of(j + 1), s, gd, g, h, acc);
+      wr_load(A, s.ws, L, range_of(j + 3));
+    }
+    wr_step<KIND>(wr_val(B, k), range_of(n - 1), s, gd, g, h, acc);
+  }
+}
+
 template <int KIND>
 __global__ void __launch_bounds__(256, 2) k_gq_wave(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
-                                                    QuantParams qp, Ctl *ctl, uint32_t pass) {
+                                                    QuantParams qp, Ctl *ctl, uint32_t pass, const double *kscale,
+                                                    int compact_ok) {
   if (ctl->flags) return;
   __shared__ uint32_t h[kNSym];
   __shared__ uint64_t wred[4][4];
   for (uint32_t i = threadIdx.x; i < (uint32_t)kNSym; i += 256) h[i] = 0;
   __syncthreads();
-  const uint32_t u = blockIdx.y, L = (uint32_t)g.L;
-  const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const uint32_t n = (L / kWr) / nwv;  // ranges per wavefront: 1 or even
+  const uint32_t u = blockIdx.y;
   const GqSlot s = gq_slot(sl, g, slot_slice, gd, qp, u);
   Acc acc;
   acc.zero();
-  auto range_of = [&](uint32_t k) { return (k < n ? w0 + k * nwv : w0) * kWr; };  // past the end: w0 again
-  WRange A, B;
-  wr_load(A, s.ws, L, range_of(0));
-  if (n == 1) {
-    wr_step<KIND>(A, range_of(0), s, gd, g, h, acc);
-  } else {
-    wr_load(B, s.ws, L, range_of(1));
-    wr_step<KIND>(A, range_of(0), s, gd, g, h, acc);
-    wr_load(A, s.ws, L, range_of(2));
-    for (uint32_t k = 1; k + 1 < n; k += 2) {
-      wr_step<KIND>(B, range_of(k), s, gd, g, h, acc);
-      wr_load(B, s.ws, L, range_of(k + 2));
-      wr_step<KIND>(A, range_of(k + 1), s, gd, g, h, acc);
-      wr_load(A, s.ws, L, range_of(k + 3));
-    }
-    wr_step<KIND>(B, range_of(n - 1), s, gd, g, h, acc);
-  }
+  if (compact_ok && !ctl->wide)
+    gq_wave_ranges<KIND, WRange32>(s, kscale[slot_slice[u]], gd, g, h, acc);
+  else
+    gq_wave_ranges<KIND, WRange>(s, 0.0, gd, g, h, acc);
   write_partial(acc, h, wred, sl, u, blockIdx.x, ctl, pass);
 }
 
@@ -1594,8 +1698,34 @@ __device__ __forceinline__ void wr_pair_quant(const WRange &a, const WRange &b, 
   }
 }
 
+template <typename R>
+__device__ __forceinline__ void gq_wave_pairs(const GqSlot &sA, const GqSlot &sB, double kA, double kB, bool cross,
+                                              int b, uint32_t n, const GateDesc &gd, const Geo &g, uint32_t *hA,
+                                              uint32_t *hb, Acc &accA, Acc &accB) {
+  const uint32_t L = (uint32_t)g.L;
+  const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  auto pair_of = [&](uint32_t j) { return j < n ? w0 + j * nwv : w0; };  // past the end: pair w0 again
+  auto rA = [&](uint32_t w) { return (cross ? w : ((w >> b) << (b + 1)) | (w & ((1u << b) - 1))) * kWr; };
+  auto rB = [&](uint32_t w) { return cross ? w * kWr : rA(w) | (kWr << b); };
+  R xa, xb;
+  double qar[4], qai[4], qbr[4], qbi[4];
+  auto step = [&](uint32_t j) {  // quantise pair j (in xa, xb), load pair j + 1, store pair j's symbols
+    const uint32_t w = pair_of(j), wn = pair_of(j + 1);
+    wr_pair_quant(wr_val(xa, kA), wr_val(xb, kB), rA(w), sA, sB, gd, qar, qai, qbr, qbi, accA, accB);
+    wr_load(xa, sA.ws, L, rA(wn));
+    wr_load(xb, sB.ws, L, rB(wn));
+    wr_symbols(qar, qai, hA, g, sA.out, rA(w), accA);
+    wr_symbols(qbr, qbi, hb, g, sB.out, rB(w), accB);
+  };
+  wr_load(xa, sA.ws, L, rA(w0));
+  wr_load(xb, sB.ws, L, rB(w0));
+  step(0);
+  for (uint32_t j = 1; j < n; j++) step(j);
+}
+
 __global__ void __launch_bounds__(256, 2) k_gq_wave_pair(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
-                                                         QuantParams qp, Ctl *ctl, uint32_t pass) {
+                                                         QuantParams qp, Ctl *ctl, uint32_t pass,
+                                                         const double *kscale, int compact_ok) {
   if (ctl->flags) return;
   __shared__ uint32_t hA[kNSym], hB[kNSym];
   __shared__ uint64_t wred[4][4];
@@ -1616,31 +1746,19 @@ __global__ void __launch_bounds__(256, 2) k_gq_wave_pair(Slots sl, Geo g, const 
     b = t - 8;  // log2 of the range size
     npairs = nr / 2;
   }
-  const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6), n = npairs / nwv;
+  const uint32_t n = npairs / (gridDim.x * 4);
   const GqSlot sA = gq_slot(sl, g, slot_slice, gd, qp, uA), sB = gq_slot(sl, g, slot_slice, gd, qp, uB);
   // one slot: both ranges' results go to one histogram and one sum
   uint32_t *hb = cross ? hB : hA;
   Acc accA, accB;
   accA.zero();
   accB.zero();
-  Acc &accb = cross ? accB : accA;
-  auto pair_of = [&](uint32_t k) { return k < n ? w0 + k * nwv : w0; };  // past the end: pair w0 again
-  auto rA = [&](uint32_t w) { return (cross ? w : ((w >> b) << (b + 1)) | (w & ((1u << b) - 1))) * kWr; };
-  auto rB = [&](uint32_t w) { return cross ? w * kWr : rA(w) | (kWr << b); };
-  WRange xa, xb;
-  double qar[4], qai[4], qbr[4], qbi[4];
-  auto step = [&](uint32_t k) {  // quantise pair k (in xa, xb), load pair k + 1, store pair k's symbols
-    const uint32_t w = pair_of(k), wn = pair_of(k + 1);
-    wr_pair_quant(xa, xb, rA(w), sA, sB, gd, qar, qai, qbr, qbi, accA, accb);
-    wr_load(xa, sA.ws, L, rA(wn));
-    wr_load(xb, sB.ws, L, rB(wn));
-    wr_symbols(qar, qai, hA, g, sA.out, rA(w), accA);
-    wr_symbols(qbr, qbi, hb, g, sB.out, rB(w), accb);
-  };
-  wr_load(xa, sA.ws, L, rA(w0));
-  wr_load(xb, sB.ws, L, rB(w0));
-  step(0);
-  for (uint32_t k = 1; k < n; k++) step(k);
+  if (compact_ok && !ctl->wide)
+    gq_wave_pairs<WRange32>(sA, sB, kscale[slot_slice[uA]], kscale[slot_slice[uB]], cross, b, n, gd, g, hA, hb,
+                            accA, accB);
+  else
+    gq_wave_pairs<WRange>(sA, sB, 0.0, 0.0, cross, b, n, gd, g, hA, hb, accA, accB);
+  if (!cross) accA.merge(accB);
   write_partial(accA, hA, wred, sl, uA, blockIdx.x, ctl, pass);
   if (cross) write_partial(accB, hB, wred, sl, uB, blockIdx.x, ctl, pass);
 }
@@ -2371,14 +2489,16 @@ void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *
 }
 
 void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl, uint32_t pass) {
+                   const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl, uint32_t pass,
+                   bool compact) {
   const uint32_t per_wg = 64u * kDecWaves;
   dim3 grid(grid1(g.nchunks, per_wg), (unsigned)nslots);
-  const bool full = (1ull << g.chunk_log2) >= (uint64_t)kDecRow && g.nchunks % per_wg == 0;
+  const bool full = (1ull << g.chunk_log2) >= (uint64_t)DecFmt<true>::R && g.nchunks % per_wg == 0;
+  const int c = compact ? 1 : 0;
   if (full)
-    CQ_LAUNCH(k_decode<true>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
+    CQ_LAUNCH(k_decode<true>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c);
   else
-    CQ_LAUNCH(k_decode<false>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass);
+    CQ_LAUNCH(k_decode<false>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c);
 }
 
 static int gate_kind(const GateDesc &gd) {
@@ -2412,16 +2532,31 @@ void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, co
   CQ_LAUNCH(k_rel_step, dim3(grid1((uint64_t)nslots, 256)), dim3(256), 0, st, sl, nslots, rel, ctl);
 }
 
+// Kernels over wavefront ranges (chunks of at most 256 values, slices of at
+// least 1024 amplitudes): 1 for one range at a time (identity, phase, or a
+// one-target gate whose partner is in the range), 2 for range pairs (a
+// one-target gate with its partner in another range of the slice or in
+// another slice), 0 when neither applies.
+static int wave_route(const Geo &g, const GateDesc &gd, int kind) {
+  if (g.chunk_log2 > 8 || g.L < 4 * kWr) return 0;
+  if (kind == 0 || kind == 2) return 1;
+  if (kind != 1) return 0;
+  if ((1ull << gd.tloc[0]) < kWr) return 1;
+  const bool cross = gd.tloc[0] >= g.slice_log2;
+  const uint32_t nr = (uint32_t)(g.L / kWr);
+  return (cross ? nr : nr / 2) >= 4 ? 2 : 0;
+}
+
 // Returns the number of partial results per slot that the launch writes.
 template <int KIND>
 static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
-                            const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
-  // wavefront ranges (a one-target gate only with its partner in the range)
-  if (KIND != 3 && g.chunk_log2 <= 8 && g.L >= 4 * kWr && (KIND != 1 || (1ull << gd.tloc[0]) < kWr)) {
+                            const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass, bool compact,
+                            const double *kscale) {
+  if (KIND != 3 && wave_route(g, gd, KIND) == 1) {
     const uint32_t nr = (uint32_t)(g.L / kWr);
     const uint32_t G = nr / 4 < kGqWgs ? nr / 4 : kGqWgs;
     CQ_LAUNCH((k_gq_wave<KIND == 3 ? 0 : KIND>), dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss,
-                       gd, qp, ctl, pass);
+                       gd, qp, ctl, pass, kscale, compact ? 1 : 0);
     return G;
   }
   const uint64_t C = gq_tile(g.L);
@@ -2441,25 +2576,30 @@ static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const
   return G;
 }
 
+bool gq_compact(const Geo &g, const GateDesc &gd) { return wave_route(g, gd, gate_kind(gd)) != 0; }
+
+// compact: read a compact workspace when ctl->wide is clear (only the
+// wavefront-range kernels can; gq_compact tells whether gd goes there)
 uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                           const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass) {
+                           const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass, bool compact,
+                           const double *kscale) {
   const int kind = gate_kind(gd);
   if (kind == 1) {
     const uint64_t C = gq_tile(g.L);
-    if (g.chunk_log2 <= 8 && g.L >= 4 * kWr) {  // wavefront ranges
-      if ((1ull << gd.tloc[0]) < kWr) return launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+    const int wr = wave_route(g, gd, kind);
+    if (wr == 1) return launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass, compact, kscale);
+    if (wr == 2) {
       const bool cross = gd.tloc[0] >= g.slice_log2;
       const uint32_t nr = (uint32_t)(g.L / kWr);
       const uint32_t npairs = cross ? nr : nr / 2;
-      if (npairs >= 4) {
-        const uint32_t G = npairs / 4 < kGqWgs ? npairs / 4 : kGqWgs;
-        const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
-        CQ_LAUNCH(k_gq_wave_pair, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
-        return G;
-      }
+      const uint32_t G = npairs / 4 < kGqWgs ? npairs / 4 : kGqWgs;
+      const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
+      CQ_LAUNCH(k_gq_wave_pair, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass, kscale,
+                compact ? 1 : 0);
+      return G;
     }
     if ((1ull << gd.tloc[0]) < C)  // partner inside the tile
-      return launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+      return launch_gq_k<1>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass, false, kscale);
     if (g.L >= kGqTile) {  // partner in the paired tile (2^t >= 1024)
       const bool cross = gd.tloc[0] >= g.slice_log2;
       if ((1ull << g.chunk_log2) > kGpTile) {  // tiles of 1024, no pipelining
@@ -2477,12 +2617,12 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
       CQ_LAUNCH(k_gate_quant_pair_pipe, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass);
       return cross ? G : 2 * G;
     }
-    return launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);  // short slices: general indexing
+    return launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass, false, kscale);  // short slices
   }
   switch (kind) {
-    case 0: return launch_gq_k<0>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
-    case 2: return launch_gq_k<2>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
-    default: return launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass);
+    case 0: return launch_gq_k<0>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass, compact, kscale);
+    case 2: return launch_gq_k<2>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass, compact, kscale);
+    default: return launch_gq_k<3>(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass, false, kscale);
   }
 }
 

@@ -188,6 +188,18 @@ def test_invalid_gate_stops_with_completed_prefix():
     assert_same_records(sim, orc, "prefix")
 
 
+def test_codes_beyond_int32_switch_the_workspace_format():
+    """With a bound of 1e-10 a concentrated state has codes |q| > 2^31: the
+    passes after it decode to an FP64 workspace, those after a spread state to
+    the compact int32 one; the records match the oracle's through every switch."""
+    n, sl, cl, eb = 12, 10, 8, 1e-10
+    say("wide codes", n, sl, cl, eb)
+    layer = [qc.H(q) for q in range(n)]
+    gates = ([qc.H(0), qc.H(11), qc.X(3)] + layer + [qc.P(5, 0.3), qc.H(2), qc.H(2)] + layer +
+             [qc.CP(1, 10, 0.7), qc.H(7), qc.H(10)])
+    run_both(n, sl, cl, eb, gates, check_every=1)
+
+
 def test_too_fine_bound_is_refused():
     say("ebound")
     with pytest.raises(cq.SimError) as e:
