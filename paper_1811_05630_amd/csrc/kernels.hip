@@ -355,6 +355,23 @@ struct BitReader {
       wi++;
     }
   }
+  // one word when at most 32 bits are left: a step consumes at most kLMax
+  // bits, so calling this before every step keeps at least 20 in buf
+  __device__ __forceinline__ void refill1(const uint32_t (*pf)[64 * kDecWaves], uint32_t tid) {
+    if (nbits <= 32) {
+      const uint32_t d = wi - wbase;
+      uint32_t word;
+      if (d < (uint32_t)PF) {  // past the chunk's end the slot holds words that are never consumed
+        word = pf[d][tid];
+      } else {
+        word = wi < nw ? w[wi] : 0u;
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), as in refill
+      }
+      buf |= (uint64_t)word << (32 - nbits);
+      nbits += 32;
+      wi++;
+    }
+  }
   __device__ __forceinline__ uint64_t take(int n) {  // 0 <= n <= 32, needs nbits >= n
     if (n == 0) return 0;
     uint64_t v = buf >> (64 - n);
@@ -427,7 +444,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   for (uint64_t j0 = 0; j0 < B; j0 += R) {
     if (active) {
       for (uint32_t q = 0; q < R;) {
-        if (br.nbits < kLMax) br.refill(pf, tid);
+        br.refill1(pf, tid);
         const uint32_t e = dtab[(uint32_t)(br.buf >> (64 - kLMax))];
         const uint32_t sym = e & 1023u;
         if (sym == 0) {  // escape (never part of a two-symbol entry)
