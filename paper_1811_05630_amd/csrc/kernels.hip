@@ -841,28 +841,37 @@ __device__ __forceinline__ void tile_symbols(const double (&qr)[V], const double
   lds_sync();  // bnd is reused by the next tile
 }
 
-// LDS histogram update of one thread's 2V symbols of a whole tile: a
-// wavefront whose symbols are all equal adds once, otherwise every thread
-// adds its runs of equal symbols.
+// LDS histogram update of one thread's 2V symbols of a whole tile.  The
+// real and the imaginary parts are counted apart (their differences follow
+// different patterns): a wavefront whose symbols of one part are all equal
+// adds them once, otherwise every thread adds its runs of equal symbols.
 template <int V>
-__device__ __forceinline__ void hist_full(const uint32_t (&sr)[V], const uint32_t (&si)[V], uint32_t *h) {
+__device__ __forceinline__ void hist_part(const uint32_t (&sv)[V], uint32_t *h) {
   bool uni = true;
 #pragma unroll
-  for (int v = 0; v < V; v++) uni &= (sr[v] == sr[0]) & (si[v] == sr[0]);
-  const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sr[0]);
-  if (__ballot(!(uni && sr[0] == s0)) == 0) {
-    if (lane_id() == 0) atomicAdd(&h[s0], 2u * V * 64u);
+  for (int v = 1; v < V; v++) uni &= sv[v] == sv[0];
+  const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sv[0]);
+  if (__ballot(!(uni && sv[0] == s0)) == 0) {
+    if (lane_id() == 0) atomicAdd(&h[s0], (uint32_t)V * 64u);
   } else {
-    uint32_t cs = sr[0], cn = 0;
+    uint32_t cs = sv[0], cn = 1;
 #pragma unroll
-    for (int v = 0; v < V; v++) {
-      if (sr[v] != cs) { atomicAdd(&h[cs], cn); cs = sr[v]; cn = 0; }
-      cn++;
-      if (si[v] != cs) { atomicAdd(&h[cs], cn); cs = si[v]; cn = 0; }
+    for (int v = 1; v < V; v++) {
+      if (sv[v] != cs) {
+        atomicAdd(&h[cs], cn);
+        cs = sv[v];
+        cn = 0;
+      }
       cn++;
     }
     atomicAdd(&h[cs], cn);
   }
+}
+
+template <int V>
+__device__ __forceinline__ void hist_full(const uint32_t (&sr)[V], const uint32_t (&si)[V], uint32_t *h) {
+  hist_part<V>(sr, h);
+  hist_part<V>(si, h);
 }
 
 // ------------------------------------------------ buffer memory operations
@@ -1587,51 +1596,103 @@ __device__ __forceinline__ void wr_symbols(const double (&qr)[4], const double (
   hist_full<4>(sr, si, h);
 }
 
+// Coefficients of a one-target gate for the element itself and for its
+// partner.  Row 0 (target bit clear) gives u00 a + u01 b, row 1 gives
+// u10 b + u11 a; the sum of the two products is commutative, so both rows
+// compute cs a + co b with cs the diagonal and co the off-diagonal entry of
+// the element's row, bit for bit like the product in column order.
+struct GateCoef {
+  double sr, si, pr, pi;
+};
+__device__ __forceinline__ GateCoef gate_coef(const GateDesc &gd, bool row) {
+  GateCoef c;
+  c.sr = row ? gd.m2[6] : gd.m2[0];
+  c.si = row ? gd.m2[7] : gd.m2[1];
+  c.pr = row ? gd.m2[4] : gd.m2[2];
+  c.pi = row ? gd.m2[5] : gd.m2[3];
+  return c;
+}
+__device__ __forceinline__ void gate_pair(const GateCoef &c, double ar, double ai, double br, double bi, double &re,
+                                          double &im) {
+  double cr, ci;
+  cmul(c.sr, c.si, ar, ai, cr, ci);
+  cmac(c.pr, c.pi, br, bi, cr, ci);
+  re = cr;
+  im = ci;
+}
+
+// The loaded values of a range, and the value of lane ^ m (a partner in
+// another lane): compact ranges exchange the int32 codes before conversion.
+__device__ __forceinline__ void wr_vals(const WRange &x, double, double (&ar)[4], double (&ai)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    ar[v] = x.r[v];
+    ai[v] = x.i[v];
+  }
+}
+__device__ __forceinline__ void wr_vals(const WRange32 &x, double k, double (&ar)[4], double (&ai)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    ar[v] = (double)x.r[v] * k;
+    ai[v] = (double)x.i[v] * k;
+  }
+}
+__device__ __forceinline__ void wr_lane_partner(const WRange &x, double, uint32_t m, double (&br)[4],
+                                                double (&bi)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    br[v] = __shfl_xor(x.r[v], (int)m, 64);
+    bi[v] = __shfl_xor(x.i[v], (int)m, 64);
+  }
+}
+__device__ __forceinline__ void wr_lane_partner(const WRange32 &x, double k, uint32_t m, double (&br)[4],
+                                                double (&bi)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    br[v] = (double)__shfl_xor(x.r[v], (int)m, 64) * k;
+    bi[v] = (double)__shfl_xor(x.i[v], (int)m, 64) * k;
+  }
+}
+
 // Gate and quantisation of one range.  KIND 0: identity; 1: one target t <
-// 8 (partner element e ^ 2^t: another lane for t < 6, the same lane at v ^
-// 2^(t-6) otherwise); 2: phase.
-template <int KIND>
-__device__ __forceinline__ void wr_step(const WRange &x, uint32_t ob, const GqSlot &s, const GateDesc &gd,
-                                        const Geo &g, uint32_t *h, Acc &acc) {
+// 6, partner element e ^ 2^t in another lane (c0 holds this lane's
+// coefficients); 5: one target t = 6 or 7, partner at v ^ 2^(t-6) in the
+// same lane (c0, c1: the coefficients of rows 0 and 1); 2: phase.  Elements
+// whose control bits do not hold keep their value (a select).
+template <int KIND, typename R>
+__device__ __forceinline__ void wr_step(const R &x, double k, const GateCoef &c0, const GateCoef &c1, uint32_t ob,
+                                        const GqSlot &s, const GateDesc &gd, const Geo &g, uint32_t *h, Acc &acc) {
   const uint32_t lane = lane_id();
-  double qr[4], qi[4];
-  double pr[4], pi[4];
-  uint32_t bit = 0;
-  if (KIND == 1) {
-    const int tb = gd.tloc[0];
-    bit = 1u << tb;
-    if (tb >= 6) {
+  double ar[4], ai[4], br[4], bi[4];
+  wr_vals(x, k, ar, ai);
+  const int tb = KIND == 1 || KIND == 5 ? gd.tloc[0] : 0;
+  if (KIND == 1) wr_lane_partner(x, k, 1u << tb, br, bi);
+  if (KIND == 5) {
 #pragma unroll
-      for (int v = 0; v < 4; v++) {
-        pr[v] = tb == 6 ? x.r[v ^ 1] : x.r[v ^ 2];
-        pi[v] = tb == 6 ? x.i[v ^ 1] : x.i[v ^ 2];
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        pr[v] = __shfl_xor(x.r[v], (int)bit, 64);
-        pi[v] = __shfl_xor(x.i[v], (int)bit, 64);
-      }
+    for (int v = 0; v < 4; v++) {
+      br[v] = tb == 6 ? ar[v ^ 1] : ar[v ^ 2];
+      bi[v] = tb == 6 ? ai[v ^ 1] : ai[v ^ 2];
     }
   }
+  const bool all_on = s.hi_ok && s.mask_lo == 0;  // no control bit inside the slice
+  double qr[4], qi[4];
 #pragma unroll
   for (int v = 0; v < 4; v++) {
     const uint32_t o = ob + v * 64 + lane;
-    double re = x.r[v], im = x.i[v];
-    const bool on = s.hi_ok && (o & s.mask_lo) == s.vals_lo;
-    if (KIND == 2 && on) {
-      cmul(gd.ph_re, gd.ph_im, x.r[v], x.i[v], re, im);
-    } else if (KIND == 1 && on) {
-      const bool row = (o & bit) != 0;  // column 0: the amplitude with the target bit clear
-      const double a0r = row ? pr[v] : x.r[v], a0i = row ? pi[v] : x.i[v];
-      const double a1r = row ? x.r[v] : pr[v], a1i = row ? x.i[v] : pi[v];
-      const double u0r = row ? gd.m2[4] : gd.m2[0], u0i = row ? gd.m2[5] : gd.m2[1];
-      const double u1r = row ? gd.m2[6] : gd.m2[2], u1i = row ? gd.m2[7] : gd.m2[3];
-      double cr, ci;
-      cmul(u0r, u0i, a0r, a0i, cr, ci);
-      cmac(u1r, u1i, a1r, a1i, cr, ci);
-      re = cr;
-      im = ci;
+    double re = ar[v], im = ai[v];
+    if (KIND != 0) {
+      double gr, gi;
+      if (KIND == 2) {
+        cmul(gd.ph_re, gd.ph_im, ar[v], ai[v], gr, gi);
+      } else if (KIND == 1) {
+        gate_pair(c0, ar[v], ai[v], br[v], bi[v], gr, gi);
+      } else {  // row of element v: bit t - 6 of v (uniform)
+        const bool row = v == 3 || (v == 1 && tb == 6) || (v == 2 && tb == 7);
+        gate_pair(row ? c1 : c0, ar[v], ai[v], br[v], bi[v], gr, gi);
+      }
+      const bool on = all_on || (s.hi_ok && (o & s.mask_lo) == s.vals_lo);
+      re = on ? gr : re;
+      im = on ? gi : im;
     }
     quant_tile(re, s, qr[v], acc);
     quant_tile(im, s, qi[v], acc);
@@ -1648,21 +1709,24 @@ __device__ __forceinline__ void gq_wave_ranges(const GqSlot &s, double k, const 
   const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint32_t n = (L / kWr) / nwv;  // ranges per wavefront: 1 or even
   auto range_of = [&](uint32_t j) { return (j < n ? w0 + j * nwv : w0) * kWr; };  // past the end: w0 again
+  // KIND 1: this lane's row (bit t of the lane); KIND 5: rows 0 and 1
+  const GateCoef c0 = gate_coef(gd, KIND == 1 && ((lane_id() >> gd.tloc[0]) & 1) != 0);
+  const GateCoef c1 = gate_coef(gd, KIND == 5);
   R A, B;
   wr_load(A, s.ws, L, range_of(0));
   if (n == 1) {
-    wr_step<KIND>(wr_val(A, k), range_of(0), s, gd, g, h, acc);
+    wr_step<KIND>(A, k, c0, c1, range_of(0), s, gd, g, h, acc);
   } else {
     wr_load(B, s.ws, L, range_of(1));
-    wr_step<KIND>(wr_val(A, k), range_of(0), s, gd, g, h, acc);
+    wr_step<KIND>(A, k, c0, c1, range_of(0), s, gd, g, h, acc);
     wr_load(A, s.ws, L, range_of(2));
     for (uint32_t j = 1; j + 1 < n; j += 2) {
-      wr_step<KIND>(wr_val(B, k), range_of(j), s, gd, g, h, acc);
+      wr_step<KIND>(B, k, c0, c1, range_of(j), s, gd, g, h, acc);
       wr_load(B, s.ws, L, range_of(j + 2));
-      wr_step<KIND>(wr_val(A, k), range_of(j + 1), s, gd, g, h, acc);
+      wr_step<KIND>(A, k, c0, c1, range_of(j + 1), s, gd, g, h, acc);
       wr_load(A, s.ws, L, range_of(j + 3));
     }
-    wr_step<KIND>(wr_val(B, k), range_of(n - 1), s, gd, g, h, acc);
+    wr_step<KIND>(B, k, c0, c1, range_of(n - 1), s, gd, g, h, acc);
   }
 }
 
@@ -2572,8 +2636,12 @@ static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const
   if (KIND != 3 && wave_route(g, gd, KIND) == 1) {
     const uint32_t nr = (uint32_t)(g.L / kWr);
     const uint32_t G = nr / 4 < kGqWgs ? nr / 4 : kGqWgs;
-    CQ_LAUNCH((k_gq_wave<KIND == 3 ? 0 : KIND>), dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss,
-                       gd, qp, ctl, pass, kscale, compact ? 1 : 0);
+    if (KIND == 1 && gd.tloc[0] >= 6)  // partner in the same lane
+      CQ_LAUNCH(k_gq_wave<5>, dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale,
+                compact ? 1 : 0);
+    else
+      CQ_LAUNCH((k_gq_wave<KIND == 3 ? 0 : KIND>), dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss,
+                gd, qp, ctl, pass, kscale, compact ? 1 : 0);
     return G;
   }
   const uint64_t C = gq_tile(g.L);
