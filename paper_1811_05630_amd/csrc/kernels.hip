@@ -2192,6 +2192,18 @@ __device__ __forceinline__ void put_bits(uint32_t *lw, uint64_t v, int n, uint64
   }
 }
 
+// A field of n <= 64 bits at bit position pos: at most three words, each
+// touched only where the field has bits in it.
+__device__ __forceinline__ void put_field(uint32_t *lw, uint64_t v, int n, uint64_t pos) {
+  if (n <= 0) return;
+  const uint32_t w = (uint32_t)(pos >> 5);
+  const int off = (int)(pos & 31);
+  const uint64_t f = v << (64 - n);  // left-aligned
+  atomicOr(&lw[w], (uint32_t)(f >> (32 + off)));
+  if (off + n > 32) atomicOr(&lw[w + 1], (uint32_t)(f >> off));
+  if (off + n > 64) atomicOr(&lw[w + 2], (uint32_t)(f << (32 - off)));
+}
+
 constexpr int kEncWaves = 4;  // coding wavefronts; one more stores
 
 // Symbols j .. j + 3 of a chunk of B values (1 past the end, never coded).
@@ -2284,15 +2296,23 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
         sv[3] = cur[i].y >> 16;
         uint64_t z[4];   // zigzag code of an escaped difference
         uint32_t nb[4];  // its bit length (0: no escape)
+        bool esc[4], any = false;
+#pragma unroll
+        for (int k = 0; k < 4; k++) cw[k] = codes[sv[k]];  // every symbol is a table index
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-          cw[k] = 0;
+          const bool valid = j + k < B;
+          cw[k] = valid ? cw[k] : 0u;
+          bl += cw[k] & 0xffu;
+          esc[k] = valid && sv[k] == 0;
+          any = any || esc[k];
           z[k] = 0;
           nb[k] = 0;
-          if (j + k < B) {
-            cw[k] = codes[sv[k]];
-            bl += cw[k] & 0xffu;
-            if (sv[k] == 0) {
+        }
+        if (__ballot(any)) {
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            if (esc[k]) {
               z[k] = zigzag(ecur[i][k]);
               nb[k] = (uint32_t)bitlen64(z[k]);
               bl += kEscBits + nb[k];
@@ -2321,7 +2341,7 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
               acc = (acc << nb[k]) | z[k];
             }
           }
-          put_bits(lw, acc, (int)bl, pos);
+          put_field(lw, acc, (int)bl, pos);
         } else {
 #pragma unroll
           for (int k = 0; k < 4; k++) {
