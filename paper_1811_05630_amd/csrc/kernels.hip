@@ -1942,10 +1942,26 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant_pair(Slots sl, Geo g, con
 // table of the new record.
 
 __device__ void bitonic_sort(uint64_t *key, uint32_t P) {
+  if (P <= 64) {  // one wavefront, in registers: no barrier between stages
+    if (threadIdx.x < 64) {
+      const uint32_t lane = threadIdx.x;
+      uint64_t a = lane < P ? key[lane] : ~0ull;
+      for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          const uint64_t b = __shfl_xor(a, (int)j, 64);
+          const bool asc = (lane & k) == 0, lower = (lane & j) == 0;
+          a = (lower == asc) ? (a < b ? a : b) : (a < b ? b : a);
+        }
+      }
+      if (lane < P) key[lane] = a;
+    }
+    __syncthreads();
+    return;
+  }
   for (uint32_t k = 2; k <= P; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       for (uint32_t p = threadIdx.x; p < P / 2; p += blockDim.x) {
-        uint32_t i = (p / j) * 2 * j + (p % j);
+        uint32_t i = 2 * p - (p & (j - 1));  // (p / j) * 2j + p % j, j a power of two
         uint32_t ixj = i + j;
         bool asc = (i & k) == 0;
         uint64_t a = key[i], b = key[ixj];
@@ -2150,14 +2166,40 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   }
   __syncthreads();
   // decoder table of the new record: the one-symbol table first (in LDS),
-  // then entries with a second symbol where both codes fit the 12 bits
-  for (uint32_t e = tid; e < (1u << kLMax); e += blockDim.x) {
-    uint32_t lo = 0, hi = n;  // last entry whose interval starts at or before e
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (lav[mid] <= e) lo = mid; else hi = mid;
+  // then entries with a second symbol where both codes fit the 12 bits.
+  // Entry e belongs to the last code whose interval starts at or before e:
+  // every code marks its first entry with its index, a prefix maximum
+  // spreads the marks (starts increase with the index; code 0 starts at 0).
+  {
+    constexpr uint32_t kPer = (1u << kLMax) / 256;  // entries per thread
+    for (uint32_t e = tid; e < (1u << kLMax); e += blockDim.x) one[e] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += blockDim.x)
+      if (lav[i] < (1u << kLMax)) one[lav[i]] = (uint16_t)i;
+    __syncthreads();
+    uint32_t m[kPer], run = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+      const uint32_t x = one[tid * kPer + k];
+      run = x > run ? x : run;
+      m[k] = run;
     }
-    one[e] = ent[lo];
+    // exclusive prefix maximum of the threads' maxima
+    uint32_t inc = run;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)inc, off, 64);
+      if (lane_id() >= (uint32_t)off) inc = y > inc ? y : inc;
+    }
+    if (lane_id() == 63) scratch[tid >> 6] = inc;
+    uint32_t before = (uint32_t)__shfl_up((int)inc, 1, 64);
+    if (lane_id() == 0) before = 0;
+    __syncthreads();
+    for (uint32_t w = 0; w < (tid >> 6); w++) before = scratch[w] > before ? scratch[w] : before;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+      const uint32_t x = m[k] > before ? m[k] : before;
+      one[tid * kPer + k] = ent[x];
+    }
   }
   __syncthreads();
   uint32_t *dt = nxt.dtab + slot_slice[u] * (1u << kLMax);
