@@ -1994,6 +1994,12 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
     if (u == 0) settle(ctl);
     sl.words[u] = 0;  // encode adds the slot's words
   }
+  // the first 16 partial histograms (loaded now, summed below): every load
+  // is issued before the sums' loads are waited for
+  const uint4 *hp = (const uint4 *)(sl.hpart + (uint64_t)u * kGqParts * kNSym) + tid;
+  uint4 x0[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) x0[i] = hp[i * (kNSym / 4)];  // i < kGqParts: in bounds
   {  // sums of the gate_quant workgroups of this slot (partials [0, nparts))
     uint64_t lo = 0, hi = 0, ne = 0, eb = 0;
     const uint64_t *pp = sl.part + (uint64_t)u * kGqParts * 4;
@@ -2039,11 +2045,10 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   {  // histogram = sum of the partial histograms; all loads of a group of 16
      // partials are issued before the first add
     uint4 acc4 = make_uint4(0, 0, 0, 0);
-    const uint4 *hp = (const uint4 *)(sl.hpart + (uint64_t)u * kGqParts * kNSym) + tid;
     for (uint32_t p0 = 0; p0 < nparts; p0 += 16) {
       uint4 x[16];
 #pragma unroll
-      for (int i = 0; i < 16; i++) x[i] = hp[(p0 + i) * (kNSym / 4)];  // p0 + i < kGqParts: in bounds
+      for (int i = 0; i < 16; i++) x[i] = p0 == 0 ? x0[i] : hp[(p0 + i) * (kNSym / 4)];  // p0 + i < kGqParts
 #pragma unroll
       for (int i = 0; i < 16; i++) {
         if (p0 + i >= nparts) x[i] = make_uint4(0, 0, 0, 0);  // not written by this pass
@@ -2109,18 +2114,18 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
       nx = t;
       len_cur = n + np;
     }
-    if (tid == 0) {
+    if (tid < 64) {  // one wavefront: the leaves before position m, counted by ballots
       uint32_t m = 2 * n - 2;
       for (int l = 1; l < kLMax; l++) {
-        uint32_t lo = 0, hi = n;  // leaves placed before position m
-        while (lo < hi) {
-          uint32_t mid = (lo + hi) >> 1;
-          if (LP[l][mid] < m) lo = mid + 1; else hi = mid;
+        uint32_t lo = 0;  // LP[l][.] increases with the leaf index
+        for (uint32_t i0 = 0; i0 < n; i0 += 64) {
+          const uint32_t i = i0 + tid;
+          lo += (uint32_t)__popcll(__ballot(i < n && LP[l][i] < m));
         }
-        q[l] = lo;
+        if (tid == 0) q[l] = lo;
         m = 2 * (m - lo);
       }
-      q[kLMax] = m;
+      if (tid == 0) q[kLMax] = m;
     }
     __syncthreads();
     for (uint32_t i = tid; i < n; i += blockDim.x) {
