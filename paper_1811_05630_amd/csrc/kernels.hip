@@ -1730,10 +1730,30 @@ __device__ __forceinline__ void gq_wave_ranges(const GqSlot &s, double k, const 
   }
 }
 
+// The same ranges from an FP64 workspace one at a time (no loads ahead):
+// the compact kernels' path for a pass whose codes do not fit int32.
 template <int KIND>
-__global__ void __launch_bounds__(256, 2) k_gq_wave(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
-                                                    QuantParams qp, Ctl *ctl, uint32_t pass, const double *kscale,
-                                                    int compact_ok) {
+__device__ __forceinline__ void gq_wave_ranges_fp64(const GqSlot &s, const GateDesc &gd, const Geo &g, uint32_t *h,
+                                                    Acc &acc) {
+  const uint32_t L = (uint32_t)g.L;
+  const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t n = (L / kWr) / nwv;
+  const GateCoef c0 = gate_coef(gd, KIND == 1 && ((lane_id() >> gd.tloc[0]) & 1) != 0);
+  const GateCoef c1 = gate_coef(gd, KIND == 5);
+  for (uint32_t j = 0; j < n; j++) {
+    WRange A;
+    wr_load(A, s.ws, L, (w0 + j * nwv) * kWr);
+    wr_step<KIND>(A, 0.0, c0, c1, (w0 + j * nwv) * kWr, s, gd, g, h, acc);
+  }
+}
+
+// C32: the workspace is compact unless ctl->wide (decode was told so); else
+// it is FP64.  The compact kernels without a lane exchange fit three
+// workgroups per CU without spilling.
+template <int KIND, bool C32>
+__global__ void __launch_bounds__(256, C32 && KIND != 1 ? 3 : 2) k_gq_wave(Slots sl, Geo g, const uint64_t *slot_slice,
+                                                              GateDesc gd, QuantParams qp, Ctl *ctl, uint32_t pass,
+                                                              const double *kscale) {
   if (ctl->flags) return;
   __shared__ uint32_t h[kNSym];
   __shared__ uint64_t wred[4][4];
@@ -1743,10 +1763,12 @@ __global__ void __launch_bounds__(256, 2) k_gq_wave(Slots sl, Geo g, const uint6
   const GqSlot s = gq_slot(sl, g, slot_slice, gd, qp, u);
   Acc acc;
   acc.zero();
-  if (compact_ok && !ctl->wide)
+  if (!C32)
+    gq_wave_ranges<KIND, WRange>(s, 0.0, gd, g, h, acc);
+  else if (!ctl->wide)
     gq_wave_ranges<KIND, WRange32>(s, kscale[slot_slice[u]], gd, g, h, acc);
   else
-    gq_wave_ranges<KIND, WRange>(s, 0.0, gd, g, h, acc);
+    gq_wave_ranges_fp64<KIND>(s, gd, g, h, acc);
   write_partial(acc, h, wred, sl, u, blockIdx.x, ctl, pass);
 }
 
@@ -1804,9 +1826,31 @@ __device__ __forceinline__ void gq_wave_pairs(const GqSlot &sA, const GqSlot &sB
   for (uint32_t j = 1; j < n; j++) step(j);
 }
 
-__global__ void __launch_bounds__(256, 2) k_gq_wave_pair(Slots sl, Geo g, const uint64_t *slot_slice, GateDesc gd,
-                                                         QuantParams qp, Ctl *ctl, uint32_t pass,
-                                                         const double *kscale, int compact_ok) {
+// The range pairs from an FP64 workspace one pair at a time (no loads
+// ahead): the compact kernel's path for a pass whose codes do not fit int32.
+__device__ __forceinline__ void gq_wave_pairs_fp64(const GqSlot &sA, const GqSlot &sB, bool cross, int b, uint32_t n,
+                                                   const GateDesc &gd, const Geo &g, uint32_t *hA, uint32_t *hb,
+                                                   Acc &accA, Acc &accB) {
+  const uint32_t L = (uint32_t)g.L;
+  const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  for (uint32_t j = 0; j < n; j++) {
+    const uint32_t w = w0 + j * nwv;
+    const uint32_t ra = (cross ? w : ((w >> b) << (b + 1)) | (w & ((1u << b) - 1))) * kWr;
+    const uint32_t rb = cross ? w * kWr : ra | (kWr << b);
+    WRange xa, xb;
+    double qar[4], qai[4], qbr[4], qbi[4];
+    wr_load(xa, sA.ws, L, ra);
+    wr_load(xb, sB.ws, L, rb);
+    wr_pair_quant(xa, xb, ra, sA, sB, gd, qar, qai, qbr, qbi, accA, accB);
+    wr_symbols(qar, qai, hA, g, sA.out, ra, accA);
+    wr_symbols(qbr, qbi, hb, g, sB.out, rb, accB);
+  }
+}
+
+template <bool C32>
+__global__ void __launch_bounds__(256, 2) k_gq_wave_pair(Slots sl, Geo g, const uint64_t *slot_slice,
+                                                                   GateDesc gd, QuantParams qp, Ctl *ctl,
+                                                                   uint32_t pass, const double *kscale) {
   if (ctl->flags) return;
   __shared__ uint32_t hA[kNSym], hB[kNSym];
   __shared__ uint64_t wred[4][4];
@@ -1834,11 +1878,13 @@ __global__ void __launch_bounds__(256, 2) k_gq_wave_pair(Slots sl, Geo g, const 
   Acc accA, accB;
   accA.zero();
   accB.zero();
-  if (compact_ok && !ctl->wide)
+  if (!C32)
+    gq_wave_pairs<WRange>(sA, sB, 0.0, 0.0, cross, b, n, gd, g, hA, hb, accA, accB);
+  else if (!ctl->wide)
     gq_wave_pairs<WRange32>(sA, sB, kscale[slot_slice[uA]], kscale[slot_slice[uB]], cross, b, n, gd, g, hA, hb,
                             accA, accB);
   else
-    gq_wave_pairs<WRange>(sA, sB, 0.0, 0.0, cross, b, n, gd, g, hA, hb, accA, accB);
+    gq_wave_pairs_fp64(sA, sB, cross, b, n, gd, g, hA, hb, accA, accB);
   if (!cross) accA.merge(accB);
   write_partial(accA, hA, wred, sl, uA, blockIdx.x, ctl, pass);
   if (cross) write_partial(accB, hB, wred, sl, uB, blockIdx.x, ctl, pass);
@@ -2703,12 +2749,20 @@ static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const
   if (KIND != 3 && wave_route(g, gd, KIND) == 1) {
     const uint32_t nr = (uint32_t)(g.L / kWr);
     const uint32_t G = nr / 4 < kGqWgs ? nr / 4 : kGqWgs;
-    if (KIND == 1 && gd.tloc[0] >= 6)  // partner in the same lane
-      CQ_LAUNCH(k_gq_wave<5>, dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale,
-                compact ? 1 : 0);
-    else
-      CQ_LAUNCH((k_gq_wave<KIND == 3 ? 0 : KIND>), dim3(G, (unsigned)nslots), dim3(256), 0, st, sl, g, ss,
-                gd, qp, ctl, pass, kscale, compact ? 1 : 0);
+    constexpr int K = KIND == 3 ? 0 : KIND;
+    const dim3 grid(G, (unsigned)nslots);
+    const bool same_lane = KIND == 1 && gd.tloc[0] >= 6;  // partner in the same lane
+    if (compact) {
+      if (same_lane)
+        CQ_LAUNCH((k_gq_wave<5, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+      else
+        CQ_LAUNCH((k_gq_wave<K, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+    } else {
+      if (same_lane)
+        CQ_LAUNCH((k_gq_wave<5, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+      else
+        CQ_LAUNCH((k_gq_wave<K, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+    }
     return G;
   }
   const uint64_t C = gq_tile(g.L);
@@ -2746,8 +2800,10 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
       const uint32_t npairs = cross ? nr : nr / 2;
       const uint32_t G = npairs / 4 < kGqWgs ? npairs / 4 : kGqWgs;
       const dim3 grid(G, (unsigned)(cross ? nslots / 2 : nslots));
-      CQ_LAUNCH(k_gq_wave_pair, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass, kscale,
-                compact ? 1 : 0);
+      if (compact)
+        CQ_LAUNCH(k_gq_wave_pair<true>, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass, kscale);
+      else
+        CQ_LAUNCH(k_gq_wave_pair<false>, grid, dim3(256), 0, st, sl, g, slot_slice, gd, qp, ctl, pass, kscale);
       return G;
     }
     if ((1ull << gd.tloc[0]) < C)  // partner inside the tile
