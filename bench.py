@@ -35,16 +35,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # the reading of the same counter for the copy probe.  Valid only for the
 # kernel source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
-    "gate_quant": {"kernels_sha256": "e69808607803fe77ba78419f64eba59c50b899fda678bb740f7cf12ba18ba405",
-                  "bytes_per_launch": 339070742},
-    "decode": {"kernels_sha256": "e69808607803fe77ba78419f64eba59c50b899fda678bb740f7cf12ba18ba405",
-              "bytes_per_launch": 271912031},
-    "encode": {"kernels_sha256": "e69808607803fe77ba78419f64eba59c50b899fda678bb740f7cf12ba18ba405",
-              "bytes_per_launch": 81232969},
-    "codebook": {"kernels_sha256": "e69808607803fe77ba78419f64eba59c50b899fda678bb740f7cf12ba18ba405",
-                "bytes_per_launch": 5236426},
-    "finish": {"kernels_sha256": "e69808607803fe77ba78419f64eba59c50b899fda678bb740f7cf12ba18ba405",
-              "bytes_per_launch": 8759831},
+    "gate_quant": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
+                  "bytes_per_launch": 225299680},
+    "decode": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
+              "bytes_per_launch": 151117228},
+    "encode": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
+              "bytes_per_launch": 83529957},
+    "codebook": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
+                "bytes_per_launch": 5821287},
+    "finish": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
+              "bytes_per_launch": 10036131},
 }
 
 
@@ -66,11 +66,13 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_bytes(name, n_amps, c_in, c_out, n_slices, escapes):
+def kernel_bytes(name, n_amps, c_in, c_out, n_slices, escapes, plane_bytes=16):
     """Algorithmic HBM bytes of one launch of each kernel class over the whole
-    state (2^n amplitudes in two FP64 planes; one u16 symbol per value; 8 bytes
-    per escaped difference; c_in / c_out compressed bytes read / written)."""
-    planes = 16 * n_amps
+    state (2^n amplitudes in two planes of plane_bytes / 2 bytes per value:
+    16 for FP64 values, 8 for the compact int32 codes; one u16 symbol per
+    value; 8 bytes per escaped difference; c_in / c_out compressed bytes read /
+    written)."""
+    planes = plane_bytes * n_amps
     syms = 4 * n_amps
     return {
         "decode": c_in + planes,                   # records in, FP64 planes out
@@ -128,7 +130,16 @@ def copy_probe():
                       "launches": reps, "ms_per_launch": ms, "GBps": 16 * n / ms / 1e6}), flush=True)
 
 
-def report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config, mfma_flops=None, extra=None):
+def compact_workspace(w, relative, chunk_log2):
+    """Whether the passes of a plain-mode workload run on the compact int32
+    workspace: an absolute bound whose codes fit int32 (|q| <= 1 / (2 eb) for a
+    normalised state), chunks of at most 256 values and slices of at least
+    1024 amplitudes (the wavefront-range gate kernels)."""
+    return (not relative and chunk_log2 <= 8 and w.slice_log2 >= 10 and 1.0 / (2 * w.error_bound) < 2 ** 30)
+
+
+def report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config, mfma_flops=None, extra=None,
+           plane_bytes=16):
     """The JSON line shared by all workloads."""
     import numpy as np
     N = 1 << w.n_qubits
@@ -146,7 +157,7 @@ def report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config, mfma_flops
                 "unit": "TFLOP/s", "frac": achieved / MFMA_F64_PEAK_TFLOPS, "traffic": None,
                 "algorithmic_flops_per_launch": flops, "avg_launch_ms": avg_ms}
     else:
-        algo = kernel_bytes(dom, N, comp, comp, sim.nslices, esc) / per_pass[dom]
+        algo = kernel_bytes(dom, N, comp, comp, sim.nslices, esc, plane_bytes) / per_pass[dom]
         achieved = algo / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
@@ -237,7 +248,8 @@ def run_grover24(args):
                           "amplitudes, absolute bound 1e-7, plain mode (one pass per gate)",
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
               "error_bound": w.error_bound, "passes_timed": K, "first_timed_gate": n + Wm}
-    line = report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config)
+    line = report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config,
+                  plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.chunk_log2)
     return line
@@ -318,7 +330,8 @@ def run_grover34(args):
                           % (Wm, Wm + K - 1),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
               "error_bound": w.error_bound, "passes_timed": K, "workspace_slots": st2["workspace_slots"]}
-    line = report(args, w, sim, K * N / dt, K, Wm, dt, kt, st1, st2, None, config)
+    line = report(args, w, sim, K * N / dt, K, Wm, dt, kt, st1, st2, None, config,
+                  plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_sample(w, args.cpu_seconds, args.chunk_log2, fused_k=0)
     return line
