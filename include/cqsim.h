@@ -44,6 +44,10 @@ extern "C" {
 #define SIM_EB_ABS 0x0u  /* |a - a'| <= error_bound for every real and imaginary part */
 #define SIM_EB_REL 0x1u  /* per slice: error_bound * max(max - min, 2^-24 max|a|) over its 2L values */
 #define SIM_FP64 0x0u    /* amplitudes and gate arithmetic in FP64 */
+#define SIM_FP32 0x2u    /* amplitudes, gate matrices, initial factors and every product and sum
+                            of the gate arithmetic rounded to FP32 (an extension: the paper
+                            works in FP64); quantisation, the bound check and the norm stay
+                            FP64, applied to the FP32 values; raw bytes are 8 per amplitude */
 #define SIM_PLAIN 0x0u   /* one pass per gate, exactly as in Algorithm 1 */
 #define SIM_FUSED 0x4u   /* runs of consecutive gates on at most SIM_FUSE_MAX qubits are applied
                             as one dense block per pass (see sim_plan); blocks of 3 or more
@@ -101,7 +105,7 @@ typedef struct sim_config {
   int slice_log2;           /* L = 2^slice_log2 amplitudes per slice, 1..26, <= n_qubits */
   int chunk_log2;           /* B = 2^chunk_log2 values per coded chunk (0: 10), clipped to slice_log2 */
   double error_bound;       /* > 0 */
-  uint32_t mode;            /* SIM_EB_* | SIM_FP64 | SIM_PLAIN or SIM_FUSED */
+  uint32_t mode;            /* SIM_EB_* | SIM_FP64 or SIM_FP32 | SIM_PLAIN or SIM_FUSED */
   uint64_t workspace_bytes; /* budget for decompressed slices in flight (0: up to 16 GiB) */
   /* optional device-memory hooks used for every allocation of the handle
    * (e.g. a framework's caching allocator); both NULL: hipMalloc / hipFree */
@@ -116,7 +120,7 @@ typedef struct sim_config {
 
 /* Statistics (Section III measures compression ratio, fidelity and time). */
 typedef struct sim_stats_t {
-  uint64_t raw_bytes;           /* 16 * 2^n: the uncompressed FP64 state */
+  uint64_t raw_bytes;           /* 16 * 2^n: the uncompressed FP64 state (8 * 2^n with SIM_FP32) */
   uint64_t compressed_bytes;    /* sum of the slice records now stored */
   uint64_t peak_compressed;     /* largest total after any pass (sets the minimum ratio) */
   double ratio;                 /* raw_bytes / compressed_bytes */

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 ABS = 0
 REL = 1
+FP32 = 2  # mode bit: FP32 working values and gate arithmetic (quantiser and norm stay FP64)
 
 R = 512
 NSYM = 1024
@@ -67,6 +68,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.orc_sv_apply.argtypes = [C.c_int, P, P, C.POINTER(_Gate)]
+        L.orc_sv_apply_mode.argtypes = [C.c_int, P, P, C.POINTER(_Gate), C.c_uint32]
         L.orc_abs_step.argtypes = [C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_rel_step.argtypes = [C.c_double, P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]
@@ -76,6 +78,7 @@ def lib():
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.POINTER(_CStats)]
         L.orc_decode_p.argtypes = [P, C.c_uint64, P]
         L.orc_decompress_slice.argtypes = [P, C.c_uint64, C.c_double, P, P]
+        L.orc_decompress_slice_mode.argtypes = [P, C.c_uint64, C.c_double, C.c_uint32, P, P]
         L.orc_norm.argtypes = [C.c_int, P, P, P]
         L.orc_norm.restype = C.c_double
         L.orc_rsqrt.argtypes = [C.c_double]
@@ -149,12 +152,13 @@ def gate_array(gates: Sequence) -> Tuple[C.Array, list]:
 
 # ------------------------------------------------------------ state vector
 
-def sv_apply(n: int, psi: np.ndarray, gate) -> np.ndarray:
-    """Apply one gate to an uncompressed FP64 state (returns a new array)."""
+def sv_apply(n: int, psi: np.ndarray, gate, mode: int = 0) -> np.ndarray:
+    """Apply one gate to an uncompressed state (returns a new array); mode
+    FP32: the state holds FP32 values and the gate runs in FP32 arithmetic."""
     re = np.ascontiguousarray(psi.real, dtype=np.float64).copy()
     im = np.ascontiguousarray(psi.imag, dtype=np.float64).copy()
     s, keep = _gate_struct(gate)
-    rc = lib().orc_sv_apply(n, _ptr(re), _ptr(im), C.byref(s))
+    rc = lib().orc_sv_apply_mode(n, _ptr(re), _ptr(im), C.byref(s), mode)
     if rc:
         raise OracleError(rc, "sv_apply")
     return re + 1j * im
@@ -272,13 +276,13 @@ def decode_p(rec: bytes) -> np.ndarray:
     return p
 
 
-def decompress_slice(rec: bytes, kscale: float) -> np.ndarray:
+def decompress_slice(rec: bytes, kscale: float, mode: int = 0) -> np.ndarray:
     hdr = parse_header(rec)
     L = 1 << hdr["slice_log2"]
     re = np.zeros(L)
     im = np.zeros(L)
     buf = np.frombuffer(rec, dtype=np.uint8).copy()
-    rc = lib().orc_decompress_slice(_ptr(buf), len(rec), kscale, _ptr(re), _ptr(im))
+    rc = lib().orc_decompress_slice_mode(_ptr(buf), len(rec), kscale, mode, _ptr(re), _ptr(im))
     if rc:
         raise OracleError(rc, "decompress_slice")
     return re + 1j * im

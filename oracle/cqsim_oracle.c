@@ -65,6 +65,30 @@ static void cmac(double ur, double ui, double ar, double ai, double *cr, double 
   *ci = *ci + (qr + qi);
 }
 
+/* FP32 mode (mode bit ORC_FP32; an extension, the paper works in FP64): every
+ * value of the working form -- decoded amplitudes, gate matrix entries and
+ * phases, initial factors -- is an FP32 number, and every product and sum of
+ * the gate arithmetic is rounded to FP32.  One FP64 operation on two FP32
+ * numbers rounded once to FP32 is the FP32 result itself, since 53 >= 2*24 + 2
+ * bits make the double rounding innocuous (Figueroa, 1995).  Quantisation,
+ * the bound check and the norm stay FP64, applied to the FP32 values. */
+#define ORC_FP32 2u
+
+static double r32(double x) { return (double)(float)x; }
+
+static void cmac_m(int fp32, double ur, double ui, double ar, double ai, double *cr, double *ci) {
+  if (!fp32) {
+    cmac(ur, ui, ar, ai, cr, ci);
+    return;
+  }
+  double pr = r32(ur * ar);
+  double pi = r32(ui * ai);
+  double qr = r32(ur * ai);
+  double qi = r32(ui * ar);
+  *cr = r32(*cr + r32(pr - pi));
+  *ci = r32(*ci + r32(qr + qi));
+}
+
 /* ------------------------------------------------------------ gate on a group
  * A group is a set of M = 2^m slices whose indices differ only in the slice
  * bits of the gate's targets.  amp_re[u] / amp_im[u] hold slice slices[u],
@@ -80,15 +104,16 @@ static double *locate(int nmem, const uint64_t *slices, double **planes, int sli
 }
 
 static int apply_gate_group(const orc_gate *g, int slice_log2, int nmem, const uint64_t *slices,
-                            double **re, double **im) {
+                            double **re, double **im, int fp32) {
   uint64_t L = (uint64_t)1 << slice_log2;
   if (g->kind == ORC_PHASE) {
+    const double phr = fp32 ? r32(g->phase_re) : g->phase_re, phi = fp32 ? r32(g->phase_im) : g->phase_im;
     for (int u = 0; u < nmem; u++) {
       for (uint64_t o = 0; o < L; o++) {
         uint64_t gi = (slices[u] << slice_log2) | o;
         if ((gi & g->ctrl_mask) != g->ctrl_vals) continue;
         double cr = 0.0, ci = 0.0;
-        cmac(g->phase_re, g->phase_im, re[u][o], im[u][o], &cr, &ci);
+        cmac_m(fp32, phr, phi, re[u][o], im[u][o], &cr, &ci);
         re[u][o] = cr;
         im[u][o] = ci;
       }
@@ -122,7 +147,10 @@ static int apply_gate_group(const orc_gate *g, int slice_log2, int nmem, const u
         double cr = 0.0, ci = 0.0;
         for (int c = 0; c < dim; c++) {
           const double *u2 = g->matrix + 2 * (r * dim + c);
-          cmac(u2[0], u2[1], in_r[c], in_i[c], &cr, &ci);
+          if (fp32)
+            cmac_m(1, r32(u2[0]), r32(u2[1]), in_r[c], in_i[c], &cr, &ci);
+          else
+            cmac(u2[0], u2[1], in_r[c], in_i[c], &cr, &ci);
         }
         out_r[r] = cr;
         out_i[r] = ci;
@@ -138,14 +166,17 @@ static int apply_gate_group(const orc_gate *g, int slice_log2, int nmem, const u
 
 /* The gate on one group of slices given as raw planes (no compression). */
 int orc_group_apply(const orc_gate *g, int slice_log2, int nmem, const uint64_t *slices, double **re, double **im) {
-  return apply_gate_group(g, slice_log2, nmem, slices, re, im);
+  return apply_gate_group(g, slice_log2, nmem, slices, re, im, 0);
 }
 
-/* Uncompressed state vector: the whole state is one slice of 2^n amplitudes. */
-int orc_sv_apply(int n, double *re, double *im, const orc_gate *g) {
+/* Uncompressed state vector: the whole state is one slice of 2^n amplitudes
+ * (mode: ORC_FP32 or 0). */
+int orc_sv_apply_mode(int n, double *re, double *im, const orc_gate *g, uint32_t mode) {
   uint64_t zero = 0;
-  return apply_gate_group(g, n, 1, &zero, &re, &im);
+  return apply_gate_group(g, n, 1, &zero, &re, &im, (mode & ORC_FP32) != 0);
 }
+
+int orc_sv_apply(int n, double *re, double *im, const orc_gate *g) { return orc_sv_apply_mode(n, re, im, g, 0); }
 
 /* -------------------------------------------------------------- quantiser */
 
@@ -355,7 +386,8 @@ typedef struct {
 } orc_cstats;
 
 /* Compress one slice (Re plane then Im plane, L values each).
- * mode bit 0: 0 = absolute bound eb, 1 = relative bound eb.
+ * mode bit 0: 0 = absolute bound eb, 1 = relative bound eb (bit 1, ORC_FP32, does not
+ * change the compressor: the values it gets are then FP32 numbers).
  * On success *out is a malloc'ed record of *out_len bytes. */
 int orc_compress_slice(const double *re, const double *im, int slice_log2, int chunk_log2, double eb,
                        uint32_t mode, uint8_t **out, uint64_t *out_len, orc_cstats *st) {
@@ -682,7 +714,9 @@ int orc_decode_p(const uint8_t *rec, uint64_t len, int64_t *p) {
 }
 
 /* Decompress into planes, a = p * kscale (kscale = step * normalisation). */
-int orc_decompress_slice(const uint8_t *rec, uint64_t len, double kscale, double *re, double *im) {
+/* a = p * kscale, rounded to FP32 in FP32 mode */
+int orc_decompress_slice_mode(const uint8_t *rec, uint64_t len, double kscale, uint32_t mode, double *re,
+                              double *im) {
   orc_rec h;
   int rc = orc_parse(rec, len, &h);
   if (rc) return rc;
@@ -694,10 +728,18 @@ int orc_decompress_slice(const uint8_t *rec, uint64_t len, double kscale, double
     for (uint64_t i = 0; i < L; i++) {
       re[i] = (double)p[i] * kscale;
       im[i] = (double)p[L + i] * kscale;
+      if (mode & ORC_FP32) {
+        re[i] = r32(re[i]);
+        im[i] = r32(im[i]);
+      }
     }
   }
   free(p);
   return rc;
+}
+
+int orc_decompress_slice(const uint8_t *rec, uint64_t len, double kscale, double *re, double *im) {
+  return orc_decompress_slice_mode(rec, len, kscale, 0, re, im);
 }
 
 /* ----------------------------------------------------------- normalisation */
@@ -806,11 +848,13 @@ int orc_sim_init(orc_sim *s, int kind, uint64_t x, const double *f) {
       } else if (kind == 1) {
         re[o] = gi == x ? 1.0 : 0.0;
       } else {
+        const int fp32 = (s->mode & ORC_FP32) != 0;
         double ar = 1.0, ai = 0.0;
         for (int q = 0; q < s->n; q++) {
           int b = (int)((gi >> q) & 1);
           double cr = 0.0, ci = 0.0;
-          cmac(f[4 * q + 2 * b], f[4 * q + 2 * b + 1], ar, ai, &cr, &ci);
+          const double fr = f[4 * q + 2 * b], fi = f[4 * q + 2 * b + 1];
+          cmac_m(fp32, fp32 ? r32(fr) : fr, fp32 ? r32(fi) : fi, ar, ai, &cr, &ci);
           ar = cr;
           ai = ci;
         }
@@ -904,9 +948,10 @@ static int process_group(const orc_sim *s, const orc_gate *g, double scale, int 
   for (int u = 0; u < nmem && rc == ORC_OK; u++) {
     uint64_t j = mem[u];
     double k = s->step[j] * scale;                                          /* Normalize */
-    rc = orc_decompress_slice(s->rec[j], s->rec_len[j], k, re[u], im[u]);   /* Decompress */
+    rc = orc_decompress_slice_mode(s->rec[j], s->rec_len[j], k, s->mode, re[u], im[u]); /* Decompress */
   }
-  if (rc == ORC_OK) rc = apply_gate_group(g, s->slice_log2, nmem, mem, re, im); /* GateComputation */
+  if (rc == ORC_OK)
+    rc = apply_gate_group(g, s->slice_log2, nmem, mem, re, im, (s->mode & ORC_FP32) != 0); /* GateComputation */
   for (int u = 0; u < nmem && rc == ORC_OK; u++)                              /* Compress */
     rc = orc_compress_slice(re[u], im[u], s->slice_log2, s->chunk_log2, s->eb, s->mode, &orec[u], &olen[u], &ost[u]);
   for (int u = 0; u < nmem; u++) {
@@ -1192,8 +1237,8 @@ int orc_pass_group(int n, int slice_log2, int chunk_log2, double eb, uint32_t mo
     im[u] = (double *)malloc(sizeof(double) * L);
   }
   for (int u = 0; u < nmem && rc == ORC_OK; u++)
-    rc = orc_decompress_slice(recs[u], lens[u], steps[u] * scale, re[u], im[u]);
-  if (rc == ORC_OK) rc = apply_gate_group(g, slice_log2, nmem, mem, re, im);
+    rc = orc_decompress_slice_mode(recs[u], lens[u], steps[u] * scale, mode, re[u], im[u]);
+  if (rc == ORC_OK) rc = apply_gate_group(g, slice_log2, nmem, mem, re, im, (mode & ORC_FP32) != 0);
   for (int u = 0; u < nmem && rc == ORC_OK; u++) {
     orc_cstats st;
     rc = orc_compress_slice(re[u], im[u], slice_log2, s.chunk_log2, eb, mode, &out_rec[u], &out_len[u], &st);
@@ -1228,7 +1273,7 @@ int orc_sim_amplitudes(const orc_sim *s, uint64_t begin, uint64_t count, double 
   uint64_t i = begin;
   while (i < begin + count && rc == ORC_OK) {
     uint64_t j = i >> s->slice_log2;
-    rc = orc_decompress_slice(s->rec[j], s->rec_len[j], s->step[j] * scale, re, im);
+    rc = orc_decompress_slice_mode(s->rec[j], s->rec_len[j], s->step[j] * scale, s->mode, re, im);
     uint64_t end = (j + 1) << s->slice_log2;
     if (end > begin + count) end = begin + count;
     for (; i < end && rc == ORC_OK; i++) {

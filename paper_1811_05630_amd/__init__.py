@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libcqsim.so")
 
 SIM_EB_ABS = 0x0
 SIM_EB_REL = 0x1
+SIM_FP32 = 0x2
 SIM_FUSED = 0x4
 GATE_DENSE = 1
 GATE_PHASE = 2
@@ -233,14 +234,15 @@ class Sim:
 
     def __init__(self, n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False,
                  chunk_log2: int = 0, workspace_bytes: int = 0, use_torch: Optional[bool] = None,
-                 arena_bytes: int = 0, fused: bool = False):
+                 arena_bytes: int = 0, fused: bool = False, fp32: bool = False):
         L = lib()
         cfg = ConfigStruct()
         cfg.n_qubits = n_qubits
         cfg.slice_log2 = slice_log2
         cfg.chunk_log2 = chunk_log2
         cfg.error_bound = error_bound
-        cfg.mode = (SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0)
+        cfg.mode = ((SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0) |
+                    (SIM_FP32 if fp32 else 0))
         cfg.workspace_bytes = workspace_bytes
         cfg.arena_bytes = arena_bytes
         self._mem = None
@@ -257,6 +259,7 @@ class Sim:
         self._h = h
         self.n, self.slice_log2, self.error_bound, self.relative = n_qubits, slice_log2, error_bound, relative
         self.fused = fused
+        self.fp32 = fp32
         self.chunk_log2 = min(chunk_log2 or 10, slice_log2)
 
     def close(self):

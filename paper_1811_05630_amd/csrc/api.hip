@@ -24,6 +24,15 @@
 #include "cqsim_impl.h"
 
 using namespace cq;
+using cq::f64::launch_begin_pass;
+using cq::f64::launch_codebook;
+using cq::f64::launch_encode;
+using cq::f64::launch_finish;
+using cq::f64::launch_rel_step;
+using cq::f64::launch_reset_slots;
+
+// the amplitude launcher of the simulator's precision (SIM_FP32: namespace f32)
+#define AMP(sim, fn) ((sim)->fp32 ? cq::f32::fn : cq::f64::fn)
 
 namespace {
 
@@ -64,6 +73,7 @@ struct sim_s {
   Geo geo{};
   double eb = 0;
   uint32_t mode = 0;
+  bool fp32 = false;  // SIM_FP32: working values, gate matrices and factors rounded to FP32
   uint64_t nslices = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -381,8 +391,8 @@ GateDesc make_desc(const sim_t *s, const sim_gate &g, const double *dmat, uint64
   *gm_out = 0;
   if (g.kind == SIM_GATE_PHASE) {
     d.kind = 2;
-    d.ph_re = g.phase_re;
-    d.ph_im = g.phase_im;
+    d.ph_re = s->fp32 ? (double)(float)g.phase_re : g.phase_re;
+    d.ph_im = s->fp32 ? (double)(float)g.phase_im : g.phase_im;
     return d;
   }
   const int sl2 = s->geo.slice_log2;
@@ -444,34 +454,34 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
   // compact workspace (int32 codes) when decode feeds the quantising kernel
   // directly and that kernel reads it; the device still falls back to FP64
   // for a pass whose codes may not fit
-  const bool compact = init_kind < 0 && !qp.rel && gd.kind != 4 && gq_compact(s->geo, gq);
+  const bool compact = init_kind < 0 && !qp.rel && gd.kind != 4 && AMP(s, gq_compact)(s->geo, gq);
   for (uint64_t b0 = 0; b0 < s->nslices; b0 += (uint64_t)s->W) {
     const int ns = (int)std::min<uint64_t>((uint64_t)s->W, s->nslices - b0);
     const uint64_t *ss = table + b0;
     if (init_kind >= 0) {
       s->kt_begin(K_INIT);
-      launch_init(st, s->slots, s->geo, ss, ns, init_kind, x, s->dfactors, s->ctl);
+      AMP(s, launch_init)(st, s->slots, s->geo, ss, ns, init_kind, x, s->dfactors, s->ctl);
       s->kt_end();
     } else {
       s->kt_begin(K_DECODE);
-      launch_decode(st, s->slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass, compact);
+      AMP(s, launch_decode)(st, s->slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass, compact);
       s->kt_end();
     }
     if (gd.kind == 4) {  // fused block on matrix cores, in place; then quantised as the identity
       s->kt_begin(K_DENSE);
-      launch_dense_mfma(st, s->slots, s->geo, ns, gd, s->ctl);
+      AMP(s, launch_dense_mfma)(st, s->slots, s->geo, ns, gd, s->ctl);
       s->kt_end();
     }
     if (qp.rel) {
       s->kt_begin(K_MINMAX);
-      launch_gate_minmax(st, s->slots, s->geo, ss, ns, gd.kind == 4 ? s->ident : gd, s->ctl);
+      AMP(s, launch_gate_minmax)(st, s->slots, s->geo, ss, ns, gd.kind == 4 ? s->ident : gd, s->ctl);
       s->kt_end();
       s->kt_begin(K_RELSTEP);
       launch_rel_step(st, s->slots, ns, qp.eb, s->ctl);
       s->kt_end();
     }
     s->kt_begin(K_GATEQ);
-    const uint32_t nparts = launch_gate_quant(st, s->slots, s->geo, ss, ns, gq, qp, s->ctl, pass, compact, s->kscale);
+    const uint32_t nparts = AMP(s, launch_gate_quant)(st, s->slots, s->geo, ss, ns, gq, qp, s->ctl, pass, compact, s->kscale);
     s->kt_end();
     s->kt_begin(K_CODEBOOK);
     launch_codebook(st, s->slots, ss, ns, nxt, nparts, s->ctl);
@@ -601,7 +611,8 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
   if (sl2 < 1 || sl2 > n || sl2 > 26) return set_err(SIM_EINVAL, "slice_log2 %d outside 1..min(26, n)", sl2);
   if (!(cfg->error_bound > 0.0) || !std::isfinite(cfg->error_bound))
     return set_err(SIM_EINVAL, "error bound must be positive and finite");
-  if (cfg->mode & ~(SIM_EB_REL | SIM_FUSED)) return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
+  if (cfg->mode & ~(SIM_EB_REL | SIM_FP32 | SIM_FUSED))
+    return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
   int cl2 = cfg->chunk_log2 > 0 ? cfg->chunk_log2 : 10;
   if (cl2 > sl2) cl2 = sl2;
   if (cl2 > 10) return set_err(SIM_EINVAL, "chunk_log2 %d above 10", cl2);
@@ -626,6 +637,7 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
   s->geo.nchunks = (uint32_t)((2ull << sl2) >> cl2);
   s->eb = cfg->error_bound;
   s->mode = cfg->mode;
+  s->fp32 = (cfg->mode & SIM_FP32) != 0;
   s->nslices = 1ull << (n - sl2);
   if ((cfg->alloc == nullptr) != (cfg->free_fn == nullptr)) {
     delete s;
@@ -731,7 +743,10 @@ int sim_init_basis(sim_t *s, uint64_t x) {
 
 int sim_init_product(sim_t *s, const double *factors) {
   if (!s || !factors) return set_err(SIM_EINVAL, "null argument");
-  HIP_TRY(hipMemcpy(s->dfactors, factors, 32 * (size_t)s->geo.n, hipMemcpyHostToDevice));
+  std::vector<double> f(factors, factors + 4 * (size_t)s->geo.n);
+  if (s->fp32)
+    for (double &v : f) v = (double)(float)v;
+  HIP_TRY(hipMemcpy(s->dfactors, f.data(), 32 * (size_t)s->geo.n, hipMemcpyHostToDevice));
   return run_passes(s, nullptr, nullptr, 0, 2, 0, nullptr);
 }
 
@@ -818,11 +833,13 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
     if (rc) return rc;
     s->dmat_cap = hm.size();
   }
+  if (s->fp32)  // FP32 gate arithmetic takes FP32 matrix entries
+    for (double &v : hm) v = (double)(float)v;
   std::vector<GateDesc> descs(n_pass);
   std::vector<uint64_t> gms(n_pass);
   for (size_t i = 0; i < n_pass; i++) {
     const bool dense = pg[i].kind == SIM_GATE_DENSE;
-    if (dense && plan[i].fused && !kind4[i]) pg[i].matrix = hm.data() + moff[i];  // host copy, read by make_desc
+    if (dense && !kind4[i]) pg[i].matrix = hm.data() + moff[i];  // host copy, read by make_desc
     descs[i] = make_desc(s, pg[i], dense ? s->dmat + moff[i] : nullptr, &gms[i]);
     if (kind4[i]) descs[i].kind = 4;
   }
@@ -917,13 +934,13 @@ static int readout(sim_t *s, uint64_t begin, uint64_t count, double *out, int pr
     const uint64_t j0 = i / L;
     const uint64_t j1 = std::min<uint64_t>((end + L - 1) / L, j0 + (uint64_t)s->W);
     const int ns = (int)(j1 - j0);
-    launch_decode(s->stream, s->slots, s->geo, table + j0, ns, s->arena[s->cur], s->meta[s->cur], s->kscale, s->ctl,
+    AMP(s, launch_decode)(s->stream, s->slots, s->geo, table + j0, ns, s->arena[s->cur], s->meta[s->cur], s->kscale, s->ctl,
                   s->pass_counter, false);
     const uint64_t bend = std::min<uint64_t>(end, j1 * L);
     uint64_t k = i;
     while (k < bend) {
       const uint64_t cnt = std::min<uint64_t>(bend - k, stage_amps);
-      launch_readout(s->stream, s->slots, s->geo, k - j0 * L, cnt, probs, s->dstage);
+      AMP(s, launch_readout)(s->stream, s->slots, s->geo, k - j0 * L, cnt, probs, s->dstage);
       HIP_TRY(hipMemcpyAsync(out + (k - begin) * per, s->dstage, 8 * cnt * per, hipMemcpyDeviceToHost, s->stream));
       HIP_TRY(hipStreamSynchronize(s->stream));
       k += cnt;
@@ -951,7 +968,7 @@ int sim_stats(sim_t *s, sim_stats_t *out) {
   if (rc) return rc;
   const Ctl &c = *s->h_ctl;
   memset(out, 0, sizeof(*out));
-  out->raw_bytes = 16ull << s->geo.n;
+  out->raw_bytes = (s->fp32 ? 8ull : 16ull) << s->geo.n;
   out->compressed_bytes = c.cur_bytes;
   out->peak_compressed = std::max(c.peak_bytes, c.cur_bytes);
   out->ratio = c.cur_bytes ? (double)out->raw_bytes / (double)c.cur_bytes : 0.0;

@@ -147,6 +147,36 @@ LaunchTimer &launch_timer();
 // -------------------------------------------------------------- launchers
 // All launches go to `st`; `pass` is the global pass counter (for failure
 // reporting); `slot_slice` lists the slice held by every slot of the batch.
+//
+// The kernels that compute amplitudes exist twice: in namespace f64 (every
+// value and operation in FP64) and in namespace f32 (the same source compiled
+// with every value of the working form and every gate operation rounded to
+// FP32; SIM_FP32).  The kernels that only count, code and move bits exist in
+// f64 only and serve both.
+#define CQ_AMPLITUDE_LAUNCHERS                                                                                  \
+  void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,      \
+                   int kind, uint64_t x, const double *factors, const Ctl *ctl);                                \
+  /* compact: the gate_quant launch of this pass reads a compact workspace when ctl->wide is clear          \
+     (gq_compact below); decode then writes int32 codes q instead of the values q * kscale */                 \
+  void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,    \
+                     const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl,               \
+                     uint32_t pass, bool compact);                                                             \
+  void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice,           \
+                          int nslots, const GateDesc &gd, const Ctl *ctl);                                     \
+  /* returns the number of partial results per slot that the launch writes */                                 \
+  uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice,        \
+                             int nslots, const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass,   \
+                             bool compact, const double *kscale);                                              \
+  /* whether the gate_quant kernel chosen for gd can read a compact workspace */                               \
+  bool gq_compact(const Geo &g, const GateDesc &gd);                                                           \
+  /* fused block (kind 4) applied in place to the decompressed slots */                                        \
+  void launch_dense_mfma(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const GateDesc &gd,        \
+                         const Ctl *ctl);                                                                      \
+  void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,       \
+                      int probabilities, double *out);
+
+namespace f64 {
+CQ_AMPLITUDE_LAUNCHERS
 // with_norm: 0 = a pass that builds an initial state, 1 = a gate pass,
 // 2 = read-out only (scales without touching the pass counters), 3 = only
 // count the records of the last batch written.  Every mode first counts
@@ -154,23 +184,7 @@ LaunchTimer &launch_timer();
 void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *kscale,
                        int with_norm);
 void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots);
-void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots, int kind,
-                 uint64_t x, const double *factors, const Ctl *ctl);
-// compact: the gate_quant launch of this pass reads a compact workspace when
-// ctl->wide is clear (gq_compact below); decode then writes int32 codes q
-// instead of the FP64 values q * kscale
-void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                   const uint8_t *arena, const StateMeta &cur, const double *kscale, Ctl *ctl, uint32_t pass,
-                   bool compact);
-void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                        const GateDesc &gd, const Ctl *ctl);
 void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl);
-// returns the number of partial results per slot that the launch writes
-uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
-                           const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass, bool compact,
-                           const double *kscale);
-// whether the gate_quant kernel chosen for gd can read a compact workspace
-bool gq_compact(const Geo &g, const GateDesc &gd);
 // nparts: partial results per slot written by the preceding gate_quant launch
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
                      uint32_t nparts, Ctl *ctl);
@@ -180,11 +194,11 @@ void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, co
 void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                    const QuantParams &qp, uint8_t *arena, uint64_t arena_cap, const StateMeta &nxt, Ctl *ctl,
                    uint32_t pass);
-// fused block (kind 4) applied in place to the decompressed slots
-void launch_dense_mfma(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const GateDesc &gd,
-                       const Ctl *ctl);
-void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,
-                    int probabilities, double *out);
+}  // namespace f64
+
+namespace f32 {
+CQ_AMPLITUDE_LAUNCHERS
+}  // namespace f32
 
 // amplitudes per gate_quant tile (a power of two, at most L, a multiple of
 // the chunk length); workgroups per slot and partial results per slot

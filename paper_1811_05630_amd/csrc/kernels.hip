@@ -4,20 +4,24 @@
 //   begin_pass  norm of the stored state -> normalisation scale per slice
 //   decode      Decompress(S) + Normalize(S): canonical-Huffman decode with a
 //               4096-entry LDS table, exact escapes, prefix sum inside each
-//               chunk, a = p * (step * s); stores staged through LDS so that
-//               every wavefront writes whole 128-byte lines
+//               chunk: the codes q, or a = q * (step * s); stores staged
+//               through LDS so that every wavefront writes whole 128-byte lines
 //   gate_quant  GateComputation(G, S) and the first half of Compress(S):
 //               error-bounded quantisation, chunked Lorenzo difference,
 //               symbols, escapes, histogram, exact sum of p^2
 //   codebook    package-merge code lengths (limit 12), canonical codes, the
 //               decoder table of the new record
 //   encode      bit packing, most significant bit first, one wavefront per
-//               chunk, into a fixed-size staging slot per chunk
-//   header      record sizes -> offsets in the output arena; record header,
-//               symbol table and chunk word offsets
-//   compact     copy each chunk's words from staging into its record
+//               chunk, packed per encode block into staging
+//   finish      record sizes -> offsets in the output arena; record header,
+//               symbol table, chunk word offsets and bit streams
 // FP64 arithmetic is never contracted into FMAs (the pragma below), so every
 // rounding happens exactly as in the stream definition.
+//
+// This file is compiled twice: as namespace f64, and with CQ_FP32 = 1 (from
+// kernels_fp32.hip) as namespace f32, where every value of the working form
+// and every result of the gate arithmetic is rounded to FP32 (rw below).  The
+// kernels that do not compute amplitudes are built in f64 only.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -26,12 +30,31 @@
 
 #include "cqsim_impl.h"
 
+#ifndef CQ_FP32
+#define CQ_FP32 0
+#endif
+#if CQ_FP32
+#define CQ_PREC f32
+#else
+#define CQ_PREC f64
+#endif
+
 namespace cq {
 
+#if !CQ_FP32
 LaunchTimer &launch_timer() {
   static thread_local LaunchTimer t;
   return t;
 }
+#endif
+
+namespace CQ_PREC {
+
+// A value of the working form: FP64, or FP32 held in an FP64 register.  One
+// FP64 +, - or * of two FP32 numbers rounded once to FP32 is the FP32 result
+// itself (53 >= 2 * 24 + 2 bits make the double rounding innocuous), so the
+// FP32 build computes FP32 arithmetic exactly by rounding every result.
+__device__ __forceinline__ double rw(double x) { return CQ_FP32 ? (double)(float)x : x; }
 
 // a launch that is being timed goes through the AMD launch call that records
 // the thread's timing events at kernel start and end; other launches take the
@@ -48,23 +71,23 @@ LaunchTimer &launch_timer() {
 
 __device__ __forceinline__ void cmac(double ur, double ui, double ar, double ai, double &cr, double &ci) {
   // c += u * a with the fixed operation order of every gate
-  double pr = ur * ar;
-  double pi = ui * ai;
-  double qr = ur * ai;
-  double qi = ui * ar;
-  cr = cr + (pr - pi);
-  ci = ci + (qr + qi);
+  double pr = rw(ur * ar);
+  double pi = rw(ui * ai);
+  double qr = rw(ur * ai);
+  double qi = rw(ui * ar);
+  cr = rw(cr + rw(pr - pi));
+  ci = rw(ci + rw(qr + qi));
 }
 
 // u * a as the first term of a sum: equal to cmac from c = 0 except for the
 // sign of an exact zero, which no quantisation code can see
 __device__ __forceinline__ void cmul(double ur, double ui, double ar, double ai, double &cr, double &ci) {
-  double pr = ur * ar;
-  double pi = ui * ai;
-  double qr = ur * ai;
-  double qi = ui * ar;
-  cr = pr - pi;
-  ci = qr + qi;
+  double pr = rw(ur * ar);
+  double pi = rw(ui * ai);
+  double qr = rw(ur * ai);
+  double qi = rw(ui * ar);
+  cr = rw(pr - pi);
+  ci = rw(qr + qi);
 }
 
 __device__ __forceinline__ uint64_t zigzag(int64_t d) { return ((uint64_t)d << 1) ^ (uint64_t)(d >> 63); }
@@ -153,6 +176,7 @@ __device__ __forceinline__ uint64_t rec_bytes(uint32_t n_used, uint32_t nchunks,
 
 __device__ __forceinline__ uint32_t ld32(const uint8_t *p) { return *(const uint32_t *)p; }
 
+#if !CQ_FP32  // kernels that do not compute amplitudes: f64 build only
 // ----------------------------------------------------------- begin pass
 
 // The records of the last batch are counted by the launch that starts the
@@ -255,6 +279,8 @@ __global__ void k_reset_slots(Slots sl, int nslots) {
   }
 }
 
+#endif  // !CQ_FP32
+
 // ------------------------------------------------------------------ init
 
 __global__ void k_init(Slots sl, Geo g, const uint64_t *slot_slice, uint64_t total, int kind, uint64_t x,
@@ -315,7 +341,7 @@ struct DecFmt {  // FP64 workspace
   static constexpr int R = 16, PITCH = 17, PF = 8;
   static __device__ __forceinline__ double add(double p, int d) { return p + (double)d; }
   static __device__ __forceinline__ double add_esc(double p, int64_t d) { return p + (double)d; }
-  static __device__ __forceinline__ double val(double p, double k) { return p * k; }
+  static __device__ __forceinline__ double val(double p, double k) { return rw(p * k); }
 };
 template <>
 struct DecFmt<true> {  // compact workspace: the code itself
@@ -655,6 +681,7 @@ __global__ void __launch_bounds__(256) k_gate_minmax(Slots sl, Geo g, const uint
 
 // relative bound: eb_j = rel * max(max - min, 2^-24 max|a|); step = largest
 // power of two <= 2 eb_j (1 when eb_j is 0)
+#if !CQ_FP32
 __global__ void k_rel_step(Slots sl, int nslots, double rel, const Ctl *ctl) {
   if (ctl->flags) return;
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -677,6 +704,7 @@ __global__ void k_rel_step(Slots sl, int nslots, double rel, const Ctl *ctl) {
   sl.qstep[3 * u + 1] = recip;
   sl.qstep[3 * u + 2] = e;
 }
+#endif  // !CQ_FP32
 
 // Sum of q^2 over a thread's integer-valued doubles |q| < 2^48, added to a
 // 128-bit (lo, hi) sum.  When every value of the wavefront is below 2^31 the
@@ -1488,8 +1516,8 @@ __device__ __forceinline__ WRange wr_val(const WRange32 &x, double k) {
   WRange y;
 #pragma unroll
   for (int v = 0; v < 4; v++) {
-    y.r[v] = (double)x.r[v] * k;
-    y.i[v] = (double)x.i[v] * k;
+    y.r[v] = rw((double)x.r[v] * k);
+    y.i[v] = rw((double)x.i[v] * k);
   }
   return y;
 }
@@ -1633,8 +1661,8 @@ __device__ __forceinline__ void wr_vals(const WRange &x, double, double (&ar)[4]
 __device__ __forceinline__ void wr_vals(const WRange32 &x, double k, double (&ar)[4], double (&ai)[4]) {
 #pragma unroll
   for (int v = 0; v < 4; v++) {
-    ar[v] = (double)x.r[v] * k;
-    ai[v] = (double)x.i[v] * k;
+    ar[v] = rw((double)x.r[v] * k);
+    ai[v] = rw((double)x.i[v] * k);
   }
 }
 __device__ __forceinline__ void wr_lane_partner(const WRange &x, double, uint32_t m, double (&br)[4],
@@ -1649,8 +1677,8 @@ __device__ __forceinline__ void wr_lane_partner(const WRange32 &x, double k, uin
                                                 double (&bi)[4]) {
 #pragma unroll
   for (int v = 0; v < 4; v++) {
-    br[v] = (double)__shfl_xor(x.r[v], (int)m, 64) * k;
-    bi[v] = (double)__shfl_xor(x.i[v], (int)m, 64) * k;
+    br[v] = rw((double)__shfl_xor(x.r[v], (int)m, 64) * k);
+    bi[v] = rw((double)__shfl_xor(x.i[v], (int)m, 64) * k);
   }
 }
 
@@ -1975,6 +2003,7 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant_pair(Slots sl, Geo g, con
   write_partial(accB, hB, wred, sl, uB, cross ? blockIdx.x : gridDim.x + blockIdx.x, ctl, pass);
 }
 
+#if !CQ_FP32  // coding kernels: f64 build only
 // ---------------------------------------------------------------- codebook
 // One workgroup per slot.  Package-merge (Larmore & Hirschberg) in its
 // coin-collector form: level 12 holds the leaves (sorted by count, then
@@ -2562,6 +2591,8 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
   if (tid == 0 && (n_used & 1)) tab[n_used] = 0;
 }
 
+#endif  // !CQ_FP32
+
 // ------------------------------------------------------------ fused blocks
 // A dense block of K = 3..5 qubits (several gates fused on the host) applied
 // in place to the decompressed slots on FP64 matrix cores.  With the real
@@ -2621,7 +2652,7 @@ __global__ void __launch_bounds__(256) k_dense_mfma(Slots sl, Geo g, GateDesc gd
         for (int i = 0; i < 4; i++) {
           const uint32_t r = 16 * R + 4 * i + quad;
           const uint64_t fm = f | gd.dep[r & (NM - 1)];
-          sl.ws[(fm >> g.slice_log2) * 2 * L + (r >= (uint32_t)NM ? L : 0) + (fm & (L - 1))] = acc[R][i];
+          sl.ws[(fm >> g.slice_log2) * 2 * L + (r >= (uint32_t)NM ? L : 0) + (fm & (L - 1))] = rw(acc[R][i]);
         }
     }
   }
@@ -2665,6 +2696,7 @@ __global__ void k_readout(Slots sl, Geo g, uint64_t first, uint64_t count, int p
 
 static inline unsigned grid1(uint64_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
+#if !CQ_FP32
 void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *kscale,
                        int with_norm) {
   CQ_LAUNCH(k_begin_pass, dim3(1), dim3(1024), 0, st, ctl, cur.step, cur.sq, nslices, kscale, with_norm);
@@ -2674,6 +2706,8 @@ void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots) {
   uint64_t n = (uint64_t)nslots * kGqParts * kNSym;
   CQ_LAUNCH(k_reset_slots, dim3(grid1(n, 256)), dim3(256), 0, st, sl, nslots);
 }
+
+#endif  // !CQ_FP32
 
 void launch_init(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots, int kind,
                  uint64_t x, const double *factors, const Ctl *ctl) {
@@ -2722,9 +2756,11 @@ void launch_gate_minmax(hipStream_t st, const Slots &sl, const Geo &g, const uin
   }
 }
 
+#if !CQ_FP32
 void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl) {
   CQ_LAUNCH(k_rel_step, dim3(grid1((uint64_t)nslots, 256)), dim3(256), 0, st, sl, nslots, rel, ctl);
 }
+#endif  // !CQ_FP32
 
 // Kernels over wavefront ranges (chunks of at most 256 values, slices of at
 // least 1024 amplitudes): 1 for one range at a time (identity, phase, or a
@@ -2834,6 +2870,7 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
   }
 }
 
+#if !CQ_FP32
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
                      uint32_t nparts, Ctl *ctl) {
   CQ_LAUNCH(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, nparts, ctl);
@@ -2883,10 +2920,13 @@ void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
                      ctl, pass);
 }
 
+#endif  // !CQ_FP32
+
 void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,
                     int probabilities, double *out) {
   CQ_LAUNCH(k_readout, dim3(grid1(count, 256)), dim3(256), 0, st, sl, g, first_amp, count, probabilities,
                      out);
 }
 
+}  // namespace CQ_PREC
 }  // namespace cq
