@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--chunk-log2", type=int, default=8)
     ap.add_argument("--latency-passes", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--fp32", action="store_true",
+                    help="FP32 mode (grover24, grover34): FP32 working values and gate arithmetic")
     ap.add_argument("--workload", choices=("grover24", "qft30", "grover34"), default="grover24",
                     help="grover24 (default, the headline line); qft30: 30-qubit QFT of a product state in "
                          "fused mode; grover34: a window of 34-qubit Grover search")
@@ -95,10 +97,10 @@ def traffic_for(kernel):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(w, seconds, chunk_log2):
+def cpu_baseline(w, seconds, chunk_log2, fp32=False):
     import oracle
     threads = oracle.num_threads()
-    sim = oracle.OracleSim(w.n_qubits, w.slice_log2, chunk_log2, w.error_bound)
+    sim = oracle.OracleSim(w.n_qubits, w.slice_log2, chunk_log2, w.error_bound, oracle.FP32 if fp32 else oracle.ABS)
     n0 = w.n_qubits  # bring the oracle to the timed region's starting point
     sim.apply(w.gates[:n0])
     done = 0
@@ -163,7 +165,8 @@ def report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config, mfma_flops
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": traffic_for(dom) if args.workload == "grover24" else None,
                 "algorithmic_bytes_per_launch": algo, "avg_launch_ms": avg_ms}
-    pipe_bytes = 2 * 16 * N + 2 * comp  # B_alg: planes written and read once + records in and out
+    b = 8 if getattr(args, "fp32", False) else 16  # bytes per amplitude of the working form
+    pipe_bytes = 2 * b * N + 2 * comp  # B_alg: planes written and read once + records in and out
     pipe_achieved = pipe_bytes * K / dt / 1e9
     line = {
         "metric": METRIC,
@@ -176,10 +179,10 @@ def report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config, mfma_flops
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if getattr(args, "fp32", False) else "f64",
         "data": "synthetic",
         "config": config,
-        "ratio": N * 16 / comp,
+        "ratio": st2["raw_bytes"] / comp,
         "min_ratio": st2["min_ratio"],
         "max_abs_codec_err": st2["max_abs_codec_err"],
         "kernel_ms_per_launch": ms_launch,
@@ -210,7 +213,8 @@ def run_grover24(args):
     K, Wm = args.steps, args.warmup
     # record arenas sized up front for a ratio of 4 or better (the circuit
     # stays above 6), so that no reallocation falls inside a timed batch
-    sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, arena_bytes=(16 << n) // 4)
+    sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, arena_bytes=(16 << n) // 4,
+                 fp32=args.fp32)
     # initial H layer (untimed), then warm-up passes
     # the circuit is marshalled once, outside every timed region
     gates = cq.Circuit(w.gates)
@@ -245,13 +249,14 @@ def run_grover24(args):
         sim.apply(gates[pos + i:pos + i + 1])
         lat.append((time.perf_counter() - a) * 1e3)
     config = {"workload": "grover24: 24-qubit Grover search, marked index from seed 0, 64 slices of 2^18 "
-                          "amplitudes, absolute bound 1e-7, plain mode (one pass per gate)",
+                          "amplitudes, absolute bound 1e-7, plain mode (one pass per gate)" +
+                          (", FP32 mode" if args.fp32 else ""),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
-              "error_bound": w.error_bound, "passes_timed": K, "first_timed_gate": n + Wm}
+              "error_bound": w.error_bound, "passes_timed": K, "first_timed_gate": n + Wm, "fp32": args.fp32}
     line = report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config,
                   plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.chunk_log2)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.chunk_log2, args.fp32)
     return line
 
 
@@ -311,7 +316,7 @@ def run_grover34(args):
     K = min(args.steps, 20)
     Wm = min(args.warmup, 10)
     sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, workspace_bytes=96 << 30,
-                 arena_bytes=48 << 30)
+                 arena_bytes=48 << 30, fp32=args.fp32)
     g = cq.Circuit(w.gates)  # marshalled once, outside the timed region
     sim.apply(g[:Wm])
     torch.cuda.synchronize()
@@ -326,18 +331,19 @@ def run_grover34(args):
     kt = sim.kernel_times(False)
     st2 = sim.stats()
     config = {"workload": "grover34 window: 34-qubit Grover search (marked index from seed 0), 1024 slices of "
-                          "2^24 amplitudes, absolute bound 1e-8, plain mode; passes %d..%d timed"
-                          % (Wm, Wm + K - 1),
+                          "2^24 amplitudes, absolute bound 1e-8, plain mode; passes %d..%d timed%s"
+                          % (Wm, Wm + K - 1, ", FP32 mode" if args.fp32 else ""),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
-              "error_bound": w.error_bound, "passes_timed": K, "workspace_slots": st2["workspace_slots"]}
+              "error_bound": w.error_bound, "passes_timed": K, "workspace_slots": st2["workspace_slots"],
+              "fp32": args.fp32}
     line = report(args, w, sim, K * N / dt, K, Wm, dt, kt, st1, st2, None, config,
                   plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_sample(w, args.cpu_seconds, args.chunk_log2, fused_k=0)
+        line["cpu_baseline"] = cpu_sample(w, args.cpu_seconds, args.chunk_log2, fused_k=0, fp32=args.fp32)
     return line
 
 
-def cpu_sample(w, seconds, chunk_log2, fused_k):
+def cpu_sample(w, seconds, chunk_log2, fused_k, fp32=False):
     """The oracle on a bounded sample of a large workload: one slice of the
     workload's shape, compressed by the oracle itself, put through repeated
     single-slice passes (a 5-qubit dense block for the fused workload, else
@@ -346,7 +352,7 @@ def cpu_sample(w, seconds, chunk_log2, fused_k):
     import oracle
     import qcircuits as qc
     L = 1 << w.slice_log2
-    mode = oracle.REL if w.relative else oracle.ABS
+    mode = (oracle.REL if w.relative else oracle.ABS) | (oracle.FP32 if fp32 else 0)
     if w.factors is not None:  # the product state's first slice
         f = np.asarray(w.factors)
         amp = np.ones(L, dtype=complex)
