@@ -1684,29 +1684,19 @@ __device__ __forceinline__ void wr_lane_partner(const WRange32 &x, double k, uin
 
 // Gate and quantisation of one range.  KIND 0: identity; 1: one target t <
 // 6, partner element e ^ 2^t in another lane (c0 holds this lane's
-// coefficients); 5: one target t = 6 or 7, partner at v ^ 2^(t-6) in the
-// same lane (c0, c1: the coefficients of rows 0 and 1); 2: phase.  Elements
-// whose control bits do not hold keep their value (a select).
-template <int KIND, typename R>
-__device__ __forceinline__ void wr_step(const R &x, double k, const GateCoef &c0, const GateCoef &c1, uint32_t ob,
-                                        const GqSlot &s, const GateDesc &gd, const Geo &g, uint32_t *h, Acc &acc) {
+// coefficients); 6 and 7: one target t = 6 or 7, partner at v ^ 2^(t-6) in
+// the same lane (c0, c1: the coefficients of rows 0 and 1); 2: phase.
+// ALLON: no control bit inside the slice (every element takes the gate);
+// otherwise elements whose control bits do not hold keep their value.
+template <int KIND, bool ALLON>
+__device__ __forceinline__ void wr_gate_quant(const double (&ar)[4], const double (&ai)[4], const double (&br)[4],
+                                              const double (&bi)[4], const GateCoef &c0, const GateCoef &c1,
+                                              uint32_t ob, const GqSlot &s, const GateDesc &gd, const Geo &g,
+                                              uint32_t *h, Acc &acc) {
   const uint32_t lane = lane_id();
-  double ar[4], ai[4], br[4], bi[4];
-  wr_vals(x, k, ar, ai);
-  const int tb = KIND == 1 || KIND == 5 ? gd.tloc[0] : 0;
-  if (KIND == 1) wr_lane_partner(x, k, 1u << tb, br, bi);
-  if (KIND == 5) {
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      br[v] = tb == 6 ? ar[v ^ 1] : ar[v ^ 2];
-      bi[v] = tb == 6 ? ai[v ^ 1] : ai[v ^ 2];
-    }
-  }
-  const bool all_on = s.hi_ok && s.mask_lo == 0;  // no control bit inside the slice
   double qr[4], qi[4];
 #pragma unroll
   for (int v = 0; v < 4; v++) {
-    const uint32_t o = ob + v * 64 + lane;
     double re = ar[v], im = ai[v];
     if (KIND != 0) {
       double gr, gi;
@@ -1714,18 +1704,44 @@ __device__ __forceinline__ void wr_step(const R &x, double k, const GateCoef &c0
         cmul(gd.ph_re, gd.ph_im, ar[v], ai[v], gr, gi);
       } else if (KIND == 1) {
         gate_pair(c0, ar[v], ai[v], br[v], bi[v], gr, gi);
-      } else {  // row of element v: bit t - 6 of v (uniform)
-        const bool row = v == 3 || (v == 1 && tb == 6) || (v == 2 && tb == 7);
+      } else {  // row of element v: bit t - 6 of v
+        const bool row = ((v >> (KIND - 6)) & 1) != 0;
         gate_pair(row ? c1 : c0, ar[v], ai[v], br[v], bi[v], gr, gi);
       }
-      const bool on = all_on || (s.hi_ok && (o & s.mask_lo) == s.vals_lo);
-      re = on ? gr : re;
-      im = on ? gi : im;
+      if (ALLON) {
+        re = gr;
+        im = gi;
+      } else {
+        const bool on = s.hi_ok && ((ob + v * 64 + lane) & s.mask_lo) == s.vals_lo;
+        re = on ? gr : re;
+        im = on ? gi : im;
+      }
     }
     quant_tile(re, s, qr[v], acc);
     quant_tile(im, s, qi[v], acc);
   }
   wr_symbols(qr, qi, h, g, s.out, ob, acc);
+}
+
+template <int KIND, typename R>
+__device__ __forceinline__ void wr_step(const R &x, double k, const GateCoef &c0, const GateCoef &c1, uint32_t ob,
+                                        const GqSlot &s, const GateDesc &gd, const Geo &g, uint32_t *h, Acc &acc) {
+  double ar[4], ai[4], br[4], bi[4];
+  wr_vals(x, k, ar, ai);
+  if (KIND == 1) wr_lane_partner(x, k, 1u << gd.tloc[0], br, bi);
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    if (KIND == 6 || KIND == 7) {
+      br[v] = ar[v ^ (1 << (KIND - 6))];
+      bi[v] = ai[v ^ (1 << (KIND - 6))];
+    } else if (KIND != 1) {
+      br[v] = bi[v] = 0.0;
+    }
+  }
+  if (KIND == 0 || (s.hi_ok && s.mask_lo == 0))
+    wr_gate_quant<KIND, true>(ar, ai, br, bi, c0, c1, ob, s, gd, g, h, acc);
+  else
+    wr_gate_quant<KIND, false>(ar, ai, br, bi, c0, c1, ob, s, gd, g, h, acc);
 }
 
 // Wavefront w of workgroup (x, u) takes ranges x * 4 + w + k * 4G of slot u.
@@ -1739,7 +1755,7 @@ __device__ __forceinline__ void gq_wave_ranges(const GqSlot &s, double k, const 
   auto range_of = [&](uint32_t j) { return (j < n ? w0 + j * nwv : w0) * kWr; };  // past the end: w0 again
   // KIND 1: this lane's row (bit t of the lane); KIND 5: rows 0 and 1
   const GateCoef c0 = gate_coef(gd, KIND == 1 && ((lane_id() >> gd.tloc[0]) & 1) != 0);
-  const GateCoef c1 = gate_coef(gd, KIND == 5);
+  const GateCoef c1 = gate_coef(gd, KIND == 6 || KIND == 7);
   R A, B;
   wr_load(A, s.ws, L, range_of(0));
   if (n == 1) {
@@ -1767,7 +1783,7 @@ __device__ __forceinline__ void gq_wave_ranges_fp64(const GqSlot &s, const GateD
   const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint32_t n = (L / kWr) / nwv;
   const GateCoef c0 = gate_coef(gd, KIND == 1 && ((lane_id() >> gd.tloc[0]) & 1) != 0);
-  const GateCoef c1 = gate_coef(gd, KIND == 5);
+  const GateCoef c1 = gate_coef(gd, KIND == 6 || KIND == 7);
   for (uint32_t j = 0; j < n; j++) {
     WRange A;
     wr_load(A, s.ws, L, (w0 + j * nwv) * kWr);
@@ -1776,10 +1792,10 @@ __device__ __forceinline__ void gq_wave_ranges_fp64(const GqSlot &s, const GateD
 }
 
 // C32: the workspace is compact unless ctl->wide (decode was told so); else
-// it is FP64.  The compact kernels without a lane exchange fit three
-// workgroups per CU without spilling.
+// it is FP64.  The compact identity kernel fits three workgroups per CU
+// without spilling.
 template <int KIND, bool C32>
-__global__ void __launch_bounds__(256, C32 && KIND != 1 ? 3 : 2) k_gq_wave(Slots sl, Geo g, const uint64_t *slot_slice,
+__global__ void __launch_bounds__(256, C32 && KIND == 0 ? 3 : 2) k_gq_wave(Slots sl, Geo g, const uint64_t *slot_slice,
                                                               GateDesc gd, QuantParams qp, Ctl *ctl, uint32_t pass,
                                                               const double *kscale) {
   if (ctl->flags) return;
@@ -2787,15 +2803,19 @@ static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const
     const uint32_t G = nr / 4 < kGqWgs ? nr / 4 : kGqWgs;
     constexpr int K = KIND == 3 ? 0 : KIND;
     const dim3 grid(G, (unsigned)nslots);
-    const bool same_lane = KIND == 1 && gd.tloc[0] >= 6;  // partner in the same lane
+    const int t = KIND == 1 ? gd.tloc[0] : 0;  // 6, 7: partner in the same lane
     if (compact) {
-      if (same_lane)
-        CQ_LAUNCH((k_gq_wave<5, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+      if (t == 6)
+        CQ_LAUNCH((k_gq_wave<6, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+      else if (t == 7)
+        CQ_LAUNCH((k_gq_wave<7, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
       else
         CQ_LAUNCH((k_gq_wave<K, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
     } else {
-      if (same_lane)
-        CQ_LAUNCH((k_gq_wave<5, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+      if (t == 6)
+        CQ_LAUNCH((k_gq_wave<6, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+      else if (t == 7)
+        CQ_LAUNCH((k_gq_wave<7, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
       else
         CQ_LAUNCH((k_gq_wave<K, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
     }
