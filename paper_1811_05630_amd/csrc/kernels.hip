@@ -2369,6 +2369,9 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
   const uint32_t ce = cb + chunks_per_block < g.nchunks ? cb + chunks_per_block : g.nchunks;
   const uint32_t W = sl.stage_words;
   for (uint32_t s = threadIdx.x; s < (uint32_t)kNSym; s += blockDim.x) codes[s] = sl.codes[(uint64_t)u * kNSym + s];
+  // chunk buffers start cleared; afterwards the store wavefront clears the
+  // words it copies out
+  for (uint32_t i = threadIdx.x; i < 2u * kEncWaves * sl.stage_words; i += blockDim.x) lw_all[i] = 0;
   const uint64_t Bc = 1ull << g.chunk_log2;
   const uint32_t rounds = (chunks_per_block + kEncWaves - 1) / kEncWaves;
   const uint64_t slot0 = (uint64_t)u * 2 * g.L;
@@ -2412,7 +2415,7 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
     load_syms(nxt, 1);
     load_escs(ecur, cur, 0);
   }
-  __syncthreads();  // code table in LDS
+  __syncthreads();  // code table in LDS, chunk buffers cleared
   for (uint32_t r = 0; r <= rounds; r++) {  // one more round: the store wavefront drains the last one
     const uint32_t buf = r & 1u;
     if (wave < kEncWaves && r < rounds) {
@@ -2422,8 +2425,7 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       const bool active = c < ce;
       const uint64_t B = active ? Bc : 0;
       uint32_t *lw = lw_all + (uint64_t)(buf * kEncWaves + wave) * W;
-      uint64_t run = 0;
-      uint32_t zeroed = 0;  // words [0, zeroed) of lw are cleared for this chunk
+      uint64_t run = 0;  // the buffer lw is all zero (cleared by the store wavefront)
 #pragma unroll
       for (int i = 0; i < STEPS; i++) {
         const uint64_t j = (uint64_t)i * 256 + 4 * (uint64_t)lane;
@@ -2447,7 +2449,8 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
           z[k] = 0;
           nb[k] = 0;
         }
-        if (__ballot(any)) {
+        const bool wave_esc = __ballot(any) != 0;
+        if (wave_esc) {
 #pragma unroll
           for (int k = 0; k < 4; k++) {
             if (esc[k]) {
@@ -2460,16 +2463,14 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
         const uint32_t inc = wave_incl_scan(bl);
         const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
         uint64_t pos = run + inc - bl;
-        uint32_t end = (uint32_t)((run + tot + 31) >> 5);
-        if (end > W) end = W;
-        for (uint32_t w = zeroed + lane; w < end; w += 64) lw[w] = 0;
-        zeroed = end > zeroed ? end : zeroed;
-        // LDS operations of one wavefront execute in issue order: a compiler
-        // barrier keeps the clearing stores ahead of the OR-ing below
-        __asm__ __volatile__("" ::: "memory");
         run += tot;
         if (pos + bl > 32ull * W) continue;  // cannot happen for a consistent codebook
-        if (bl <= 64) {  // the lane's codes and escape payloads as one field (every part below 64 bits)
+        if (!wave_esc) {  // four codes of at most 12 bits: one field
+          uint64_t acc = 0;
+#pragma unroll
+          for (int k = 0; k < 4; k++) acc = (acc << (cw[k] & 0xffu)) | (cw[k] >> 8);
+          put_field(lw, acc, (int)bl, pos);
+        } else if (bl <= 64) {  // the lane's codes and escape payloads as one field (every part below 64 bits)
           uint64_t acc = 0;
 #pragma unroll
           for (int k = 0; k < 4; k++) {
@@ -2511,8 +2512,11 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
         const uint32_t c = cb + (r - 1) * kEncWaves + w;
         if (c >= ce) break;
         const uint32_t nw = cnw[pb][w];
-        const uint32_t *src = lw_all + (uint64_t)(pb * kEncWaves + w) * W;
-        for (uint32_t i = lane; i < nw; i += 64) blk[packed + i] = src[i];
+        uint32_t *src = lw_all + (uint64_t)(pb * kEncWaves + w) * W;
+        for (uint32_t i = lane; i < nw; i += 64) {  // copied out, then cleared for the round after next
+          blk[packed + i] = src[i];
+          src[i] = 0;
+        }
         if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = packed;
         packed += nw;
       }
