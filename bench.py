@@ -35,16 +35,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # the reading of the same counter for the copy probe.  Valid only for the
 # kernel source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
-    "gate_quant": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
-                  "bytes_per_launch": 225299680},
-    "decode": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
-              "bytes_per_launch": 151117228},
-    "encode": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
-              "bytes_per_launch": 83529957},
-    "codebook": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
-                "bytes_per_launch": 5821287},
-    "finish": {"kernels_sha256": "4533275ed0eaedcbf0f977f7c9f138a556ce524319ff3de8bf6da52e49cca91b",
-              "bytes_per_launch": 10036131},
+    "gate_quant": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
+                  "bytes_per_launch": 225129317},
+    "decode": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
+              "bytes_per_launch": 151137667},
+    "encode": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
+              "bytes_per_launch": 83539651},
+    "codebook": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
+                "bytes_per_launch": 5822720},
+    "finish": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
+              "bytes_per_launch": 10031899},
 }
 
 
