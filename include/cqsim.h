@@ -216,6 +216,26 @@ int sim_export_slice(sim_t *sim, uint64_t j, void *buf, uint64_t cap, uint64_t *
  * and must have the handle's slice and chunk sizes. */
 int sim_import_slice(sim_t *sim, uint64_t j, const void *buf, uint64_t len);
 
+/* ---- captured gate programs (HIP graphs)
+ * For callers that apply one gate program many times (a Grover iteration, a
+ * circuit served repeatedly) and want no per-pass host work.
+ * sim_graph_create records the passes of gates[0..n) (plain or fused, as
+ * sim_apply would run them) into a HIP graph without running them; the
+ * matrices are copied, the gates need not outlive the call.  Every gate must
+ * be valid (SIM_EINVAL otherwise, no graph).  sim_graph_launch applies the
+ * program to the current state with the same result as sim_apply and the
+ * same failure semantics; *n_applied counts the gates of completed passes.
+ * The graph replays as captured only from the arena parity and arena
+ * allocations it was captured on: after an odd number of other passes the
+ * program runs through the ordinary launches, and after an arena has grown
+ * it is captured again first (both automatic).  A graph belongs to its
+ * handle: destroy it before sim_destroy; launches on one handle must not
+ * overlap. */
+typedef struct sim_graph_s sim_graph_t;
+int sim_graph_create(sim_t *sim, const sim_gate *gates, size_t n, sim_graph_t **out);
+int sim_graph_launch(sim_t *sim, sim_graph_t *graph, size_t *n_applied);
+void sim_graph_destroy(sim_graph_t *graph);
+
 /* Device time (milliseconds, summed since the last reset) spent in each of
  * the library's kernel classes, measured with HIP events on the handle's
  * stream when enabled.  `names` receives a static comma-separated list of the

@@ -13,6 +13,7 @@ usable, the constructor raises.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 import os
 from typing import Iterable, List, Optional, Sequence, Tuple
 
@@ -33,7 +34,8 @@ ERRORS = {-1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EBOUND", -4: "SIM_ECORRUP
 # every entry point declared in include/cqsim.h
 EXPORTS = ("sim_create", "sim_create_ex", "sim_destroy", "sim_last_error", "sim_init_basis", "sim_init_product",
            "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_amplitudes", "sim_probabilities", "sim_stats",
-           "sim_record_size", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan")
+           "sim_record_size", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan",
+           "sim_graph_create", "sim_graph_launch", "sim_graph_destroy")
 
 
 class SimError(RuntimeError):
@@ -107,6 +109,10 @@ def lib():
         L.sim_export_slice.argtypes = [P, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64)]
         L.sim_import_slice.argtypes = [P, C.c_uint64, P, C.c_uint64]
         L.sim_kernel_times.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_char_p)]
+        L.sim_graph_create.argtypes = [P, C.POINTER(GateStruct), C.c_size_t, C.POINTER(P)]
+        L.sim_graph_launch.argtypes = [P, P, C.POINTER(C.c_size_t)]
+        L.sim_graph_destroy.argtypes = [P]
+        L.sim_graph_destroy.restype = None
         L.sim_plan.argtypes = [C.c_int, C.POINTER(GateStruct), C.c_size_t, C.POINTER(PassStruct), C.c_size_t,
                                C.POINTER(C.c_size_t)]
         _lib = L
@@ -263,6 +269,8 @@ class Sim:
         self.chunk_log2 = min(chunk_log2 or 10, slice_log2)
 
     def close(self):
+        for g in list(getattr(self, "_graphs", ())):  # a graph must go before its handle
+            g.close()
         if self._h:
             lib().sim_destroy(self._h)
             self._h = None
@@ -342,6 +350,11 @@ class Sim:
         b = np.frombuffer(rec, dtype=np.uint8).copy()
         _check(lib().sim_import_slice(self._h, j, b.ctypes.data_as(C.c_void_p), len(rec)), "sim_import_slice")
 
+    def graph(self, gates: Sequence) -> "Graph":
+        """sim_graph_create: the program captured once, to be applied with
+        Graph.launch() as often as needed."""
+        return Graph(self, gates)
+
     def kernel_times(self, enable: Optional[bool] = None) -> dict:
         """Per-kernel-class device time since the last reset, as
         {class: (milliseconds, launches)}; enable=True/False switches the event
@@ -354,3 +367,35 @@ class Sim:
             _check(k, "sim_kernel_times")
         cls = names.value.decode().split(",")
         return {cls[i]: (out[i], int(out[k + i])) for i in range(k)}
+
+
+class Graph:
+    """A gate program captured into a HIP graph on one Sim (sim_graph_*).
+    launch() applies it to the Sim's current state, like Sim.apply."""
+
+    def __init__(self, sim: "Sim", gates: Sequence):
+        ptr, cnt, keep = _gate_ptr(gates)
+        h = C.c_void_p()
+        _check(lib().sim_graph_create(sim._h, ptr, cnt, C.byref(h)), "sim_graph_create")
+        self._h, self.sim, self.n_gates = h, sim, cnt
+        if not hasattr(sim, "_graphs"):
+            sim._graphs = weakref.WeakSet()
+        sim._graphs.add(self)
+
+    def launch(self) -> int:
+        n = C.c_size_t()
+        rc = lib().sim_graph_launch(self.sim._h, self._h, C.byref(n))
+        if rc:
+            raise SimError(rc, f"sim_graph_launch after {n.value} gates: {lib().sim_last_error().decode()}")
+        return n.value
+
+    def close(self):
+        if self._h:
+            lib().sim_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -106,6 +106,7 @@ struct sim_s {
   uint64_t passes = 0;
   double elapsed = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream on which gate programs are captured into graphs
 
   bool kt_on = false;
   std::vector<hipEvent_t> kt_pool;
@@ -713,6 +714,7 @@ void sim_destroy(sim_t *s) {
   for (hipEvent_t e : s->kt_pool) hipEventDestroy(e);
   if (s->ev0) hipEventDestroy(s->ev0);
   if (s->ev1) hipEventDestroy(s->ev1);
+  if (s->cap_stream) hipStreamDestroy(s->cap_stream);
   if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
   delete s;
 }
@@ -750,19 +752,32 @@ int sim_init_product(sim_t *s, const double *factors) {
   return run_passes(s, nullptr, nullptr, 0, 2, 0, nullptr);
 }
 
-int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
-  if (n_applied) *n_applied = 0;
-  if (!s) return set_err(SIM_EINVAL, "null handle");
-  if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
+// The passes of a gate program: the plan (one pass per gate, or the fused
+// partition), the gate each pass applies and its host matrices (FP32-rounded
+// in FP32 mode).  Gates from the first invalid one on are dropped (vrc, verr).
+struct PassSet {
   size_t n_valid = 0;
   int vrc = SIM_OK;
+  std::string verr;
+  std::vector<PlanPass> plan;
+  std::vector<double> hm;
+  std::vector<size_t> moff;
+  std::vector<sim_gate> pg;
+  std::vector<int> kind4;
+  size_t n_pass = 0;
+};
+
+static void prepare_passes(sim_t *s, const sim_gate *gates, size_t n, PassSet &P) {
+  size_t &n_valid = P.n_valid;
+  int &vrc = P.vrc;
   for (; n_valid < n; n_valid++) {
     vrc = validate_gate(s, gates[n_valid], n_valid);
     if (vrc) break;
   }
-  std::string verr = vrc ? g_last_error : std::string();
+  P.verr = vrc ? g_last_error : std::string();
+  std::string &verr = P.verr;
   // passes: one per gate, or the fused partition of the valid gates
-  std::vector<PlanPass> plan;
+  std::vector<PlanPass> &plan = P.plan;
   if (s->mode & SIM_FUSED) {
     plan_gates(gates, n_valid, plan);
   } else {
@@ -770,12 +785,16 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
     for (size_t i = 0; i < n_valid; i++) plan[i] = PlanPass{(uint32_t)i, 1u, false, 0, {0, 0, 0, 0, 0}};
   }
   // host matrices of all passes, then one copy to the device
-  std::vector<double> hm;
-  std::vector<size_t> moff(plan.size(), 0);
-  std::vector<sim_gate> pg(plan.size());  // the gate each pass applies
-  std::vector<int> kind4(plan.size(), 0);
+  std::vector<double> &hm = P.hm;
+  std::vector<size_t> &moff = P.moff;
+  std::vector<sim_gate> &pg = P.pg;  // the gate each pass applies
+  std::vector<int> &kind4 = P.kind4;
+  moff.assign(plan.size(), 0);
+  pg.assign(plan.size(), sim_gate{});
+  kind4.assign(plan.size(), 0);
   std::vector<double> U;
-  size_t n_pass = 0;
+  size_t &n_pass = P.n_pass;
+  n_pass = 0;
   for (; n_pass < plan.size(); n_pass++) {
     const PlanPass &p = plan[n_pass];
     if (!p.fused) {
@@ -825,6 +844,34 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
     }
     pg[n_pass] = g;
   }
+  if (s->fp32)  // FP32 gate arithmetic takes FP32 matrix entries
+    for (double &v : hm) v = (double)(float)v;
+}
+
+// Descriptors of the passes, their matrices at dev (a device copy of P.hm).
+static void pass_descs(const sim_t *s, PassSet &P, double *dev, std::vector<GateDesc> &descs,
+                       std::vector<uint64_t> &gms) {
+  descs.resize(P.n_pass);
+  gms.resize(P.n_pass);
+  for (size_t i = 0; i < P.n_pass; i++) {
+    const bool dense = P.pg[i].kind == SIM_GATE_DENSE;
+    if (dense && !P.kind4[i]) P.pg[i].matrix = P.hm.data() + P.moff[i];  // host copy, read by make_desc
+    descs[i] = make_desc(s, P.pg[i], dense ? dev + P.moff[i] : nullptr, &gms[i]);
+    if (P.kind4[i]) descs[i].kind = 4;
+  }
+}
+
+int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
+  if (n_applied) *n_applied = 0;
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
+  PassSet P;
+  prepare_passes(s, gates, n, P);
+  std::vector<double> &hm = P.hm;
+  std::vector<PlanPass> &plan = P.plan;
+  const size_t n_pass = P.n_pass;
+  int vrc = P.vrc;
+  std::string verr = P.verr;
   if (hm.size() > s->dmat_cap) {
     s->dfree(s->dmat);
     s->dmat = nullptr;
@@ -833,16 +880,9 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
     if (rc) return rc;
     s->dmat_cap = hm.size();
   }
-  if (s->fp32)  // FP32 gate arithmetic takes FP32 matrix entries
-    for (double &v : hm) v = (double)(float)v;
-  std::vector<GateDesc> descs(n_pass);
-  std::vector<uint64_t> gms(n_pass);
-  for (size_t i = 0; i < n_pass; i++) {
-    const bool dense = pg[i].kind == SIM_GATE_DENSE;
-    if (dense && !kind4[i]) pg[i].matrix = hm.data() + moff[i];  // host copy, read by make_desc
-    descs[i] = make_desc(s, pg[i], dense ? s->dmat + moff[i] : nullptr, &gms[i]);
-    if (kind4[i]) descs[i].kind = 4;
-  }
+  std::vector<GateDesc> descs;
+  std::vector<uint64_t> gms;
+  pass_descs(s, P, s->dmat, descs, gms);
   if (!hm.empty()) HIP_TRY(hipMemcpy(s->dmat, hm.data(), 8 * hm.size(), hipMemcpyHostToDevice));
   size_t applied = 0;
   HIP_TRY(hipEventRecord(s->ev0, s->stream));
@@ -863,6 +903,178 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
     return vrc;
   }
   return SIM_OK;
+}
+
+// ------------------------------------------------------------ gate graphs
+
+struct sim_graph_s {
+  sim_t *sim = nullptr;
+  PassSet P;                        // the program's passes and host matrices
+  double *dmat = nullptr;           // device copy of the matrices (the handle's allocator)
+  std::vector<GateDesc> descs;
+  std::vector<uint64_t> gms;
+  hipGraphExec_t exec = nullptr;    // the passes as captured
+  int start_cur = 0;                // arena parity they start from
+  uint32_t start_pass = 0;          // pass numbers [start_pass, start_pass + n) baked into the kernels
+  uint8_t *arena[2] = {nullptr, nullptr};
+  uint64_t cap[2] = {0, 0};
+};
+
+static bool graph_current(const sim_graph_t *G) {
+  const sim_t *s = G->sim;
+  return G->exec && s->cur == G->start_cur && s->arena[0] == G->arena[0] && s->arena[1] == G->arena[1] &&
+         s->arena_cap[0] == G->cap[0] && s->arena_cap[1] == G->cap[1];
+}
+
+// Record the program's passes from the current arena parity.  Nothing runs:
+// the state and parity are unchanged, the pass numbers are reserved.
+static int graph_capture(sim_graph_t *G) {
+  sim_t *s = G->sim;
+  if (G->exec) {
+    hipGraphExecDestroy(G->exec);
+    G->exec = nullptr;
+  }
+  int rc;
+  for (size_t i = 0; i < G->P.n_pass; i++) {  // slot tables exist before the capture (they copy to the device)
+    const uint64_t *t;
+    if ((rc = slot_table(s, G->gms[i], &t))) return rc;
+  }
+  if (!s->cap_stream && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return set_err(SIM_EDEVICE, "capture stream creation failed");
+  const bool kt = s->kt_on;  // launches in a graph record no timing events
+  s->kt_on = false;
+  const int cur0 = s->cur;
+  const uint32_t pc0 = s->pass_counter;
+  hipStream_t saved = s->stream;
+  s->stream = s->cap_stream;
+  hipGraph_t graph = nullptr;
+  rc = SIM_OK;
+  hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    rc = set_err(SIM_EDEVICE, "graph capture could not start: %s", hipGetErrorString(e));
+  } else {
+    for (size_t i = 0; i < G->P.n_pass && rc == SIM_OK; i++) rc = enqueue_pass(s, G->descs[i], G->gms[i], -1, 0);
+    e = hipStreamEndCapture(s->cap_stream, &graph);
+    if (rc == SIM_OK && e != hipSuccess) rc = set_err(SIM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  s->stream = saved;
+  s->cur = cur0;
+  s->pass_counter = pc0 + (uint32_t)G->P.n_pass;
+  s->kt_on = kt;
+  if (rc == SIM_OK && (e = hipGraphInstantiate(&G->exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+    G->exec = nullptr;
+    rc = set_err(SIM_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+  }
+  if (graph) hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  if (rc) return rc;
+  G->start_cur = cur0;
+  G->start_pass = pc0;
+  for (int a = 0; a < 2; a++) {
+    G->arena[a] = s->arena[a];
+    G->cap[a] = s->arena_cap[a];
+  }
+  return SIM_OK;
+}
+
+void sim_graph_destroy(sim_graph_t *G) {
+  if (!G) return;
+  if (G->exec) hipGraphExecDestroy(G->exec);
+  if (G->dmat) G->sim->dfree(G->dmat);
+  delete G;
+}
+
+int sim_graph_create(sim_t *s, const sim_gate *gates, size_t n, sim_graph_t **out) {
+  if (!out) return set_err(SIM_EINVAL, "null argument");
+  *out = nullptr;
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
+  sim_graph_t *G = new sim_graph_s();
+  G->sim = s;
+  prepare_passes(s, gates, n, G->P);
+  int rc = G->P.vrc;
+  if (rc) {
+    g_last_error = G->P.verr;
+    delete G;
+    return rc;
+  }
+  if (!G->P.hm.empty()) {
+    if ((rc = s->dalloc((void **)&G->dmat, 8 * G->P.hm.size()))) {
+      delete G;
+      return rc;
+    }
+  }
+  pass_descs(s, G->P, G->dmat, G->descs, G->gms);
+  if (!G->P.hm.empty() &&
+      hipMemcpy(G->dmat, G->P.hm.data(), 8 * G->P.hm.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    sim_graph_destroy(G);
+    return set_err(SIM_EDEVICE, "matrix upload failed");
+  }
+  if ((rc = graph_capture(G))) {
+    sim_graph_destroy(G);
+    return rc;
+  }
+  *out = G;
+  return SIM_OK;
+}
+
+int sim_graph_launch(sim_t *s, sim_graph_t *G, size_t *n_applied) {
+  if (n_applied) *n_applied = 0;
+  if (!s || !G || G->sim != s) return set_err(SIM_EINVAL, "graph does not belong to this handle");
+  const size_t n = G->P.n_pass;
+  if (n == 0) return SIM_OK;
+  size_t applied = 0;
+  int rc = SIM_OK;
+  HIP_TRY(hipEventRecord(s->ev0, s->stream));
+  if (s->cur != G->start_cur) {  // the other parity: ordinary launches of the same passes
+    rc = run_passes(s, G->descs.data(), G->gms.data(), n, -1, 0, &applied);
+  } else {
+    if (!graph_current(G)) rc = graph_capture(G);  // an arena has been reallocated since
+    if (rc == SIM_OK) {
+      HIP_TRY(hipGraphLaunch(G->exec, s->stream));
+      // count the records of the last batch, then check the passes
+      const int end_cur = G->start_cur ^ (int)(n & 1);
+      launch_begin_pass(s->stream, s->ctl, s->meta[end_cur], s->nslices, s->kscale, 3);
+      if ((rc = read_ctl(s)) == SIM_OK) {
+        const uint32_t flags = s->h_ctl->flags;
+        if (!flags) {
+          applied = n;
+          s->cur = end_cur;
+          const int tgt = 1 - s->cur;  // as after every batch: room for the next pass
+          const uint64_t want = s->h_ctl->bump + s->h_ctl->bump / 4;
+          if (want > s->arena_cap[tgt]) (void)grow_arena(s, tgt, want);
+        } else {
+          const uint32_t done = s->h_ctl->fail_pass - G->start_pass;  // passes that completed
+          s->cur = G->start_cur ^ (int)(done & 1);
+          applied = done;
+          if ((rc = clear_flags(s)) == SIM_OK) {
+            if (flags & kFlagOverflow) {  // the rest through ordinary launches, into a larger arena
+              if ((rc = grow_arena(s, 1 - s->cur, 0)) == SIM_OK) {
+                size_t more = 0;
+                rc = run_passes(s, G->descs.data() + done, G->gms.data() + done, n - done, -1, 0, &more);
+                applied += more;
+              }
+            } else if (flags & kFlagCorrupt) {
+              rc = set_err(SIM_ECORRUPT, "a stored slice record failed its consistency checks");
+            } else {
+              rc = set_err(SIM_EBOUND, "a value could not be coded within the error bound (|p| >= 2^48 or bound check)");
+            }
+          }
+        }
+      }
+    }
+  }
+  HIP_TRY(hipEventRecord(s->ev1, s->stream));
+  HIP_TRY(hipEventSynchronize(s->ev1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, s->ev0, s->ev1);
+  s->elapsed += ms * 1e-3;
+  s->passes += applied;
+  if (s->kt_on) s->kt_flush();
+  size_t gates_done = 0;
+  for (size_t i = 0; i < applied; i++) gates_done += G->P.plan[i].count;
+  if (n_applied) *n_applied = gates_done;
+  return rc;
 }
 
 // validity of a gate for n qubits (no handle: no workspace limits)
