@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--fp32", action="store_true",
                     help="FP32 mode (grover24, grover34): FP32 working values and gate arithmetic")
-    ap.add_argument("--workload", choices=("grover24", "qft30", "grover34"), default="grover24",
+    ap.add_argument("--workload", choices=("grover24", "qft30", "grover34", "qft12"), default="grover24",
                     help="grover24 (default, the headline line); qft30: 30-qubit QFT of a product state in "
                          "fused mode; grover34: a window of 34-qubit Grover search")
     ap.add_argument("--copy-probe", action="store_true",
@@ -260,6 +260,57 @@ def run_grover24(args):
     return line
 
 
+def run_qft12(args):
+    """The 12-qubit QFT of a basis state (84 passes over 4 slices of 2^10,
+    absolute bound 1e-6): a latency-bound program, applied again and again
+    to the state (QFT^4 = I keeps it a QFT image of a basis state).  Timed as
+    one captured graph per program (the value) and through sim_apply (the
+    `eager_amps_per_s` beside it)."""
+    import torch
+    import paper_1811_05630_amd as cq
+    import qcircuits as qc
+
+    w = qc.qft_basis_workload(seed=args.seed)
+    n, N = w.n_qubits, 1 << w.n_qubits
+    R = max(1, args.steps // 10)  # programs per timed region
+    # chunks of 32 values: 256 chunks decode in parallel (one lane each)
+    sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=5)
+    sim.init_basis(w.basis)
+    circ = cq.Circuit(w.gates)
+    graph = sim.graph(circ)
+    for _ in range(max(1, args.warmup // 10)):
+        sim.apply(circ)
+        graph.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(R):
+        sim.apply(circ)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(R):
+        graph.launch()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    K = R * len(w.gates)
+    st1 = sim.stats()
+    sim.kernel_times(True)
+    sim.apply(circ)
+    torch.cuda.synchronize()
+    kt = sim.kernel_times(False)
+    st2 = sim.stats()
+    config = {"workload": "qft12: 12-qubit QFT of a basis state (seed 0), 4 slices of 2^10 amplitudes, absolute "
+                          "bound 1e-6, chunks of 32 values, the 84-gate program captured as one HIP graph and launched %d "
+                          "times" % R,
+              "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": 5, "error_bound": w.error_bound,
+              "passes_timed": K}
+    extra = {"eager_amps_per_s": K * N / t_eager, "graph_speedup": t_eager / t_graph,
+             "ms_per_program": {"graph": t_graph / R * 1e3, "eager": t_eager / R * 1e3}}
+    line = report(args, w, sim, K * N / t_graph, K, args.warmup, t_graph, kt, st1, st2, None, config, extra=extra)
+    graph.close()
+    return line
+
+
 def run_qft30(args):
     """30-qubit QFT of a seeded product state in fused mode: 256 slices of
     2^22, relative bound 1e-4.  One step is one fused pass; the timed region
@@ -391,7 +442,7 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    run = {"grover24": run_grover24, "qft30": run_qft30, "grover34": run_grover34}[args.workload]
+    run = {"grover24": run_grover24, "qft30": run_qft30, "grover34": run_grover34, "qft12": run_qft12}[args.workload]
     print(json.dumps(run(args)), flush=True)
 
 
