@@ -2032,6 +2032,15 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant_pair(Slots sl, Geo g, con
 // [0, 4096) in (length, symbol) order; the same intervals fill the decoder
 // table of the new record.
 
+// Orders the LDS accesses of one wavefront's lanes around this point: the
+// wavefront's LDS instructions execute in program order, so only the
+// compiler has to be kept from moving accesses across it.
+__device__ __forceinline__ void lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ void bitonic_sort(uint64_t *key, uint32_t P) {
   if (P <= 64) {  // one wavefront, in registers: no barrier between stages
     if (threadIdx.x < 64) {
@@ -2076,8 +2085,9 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   __shared__ uint8_t lens[kNSym];
   __shared__ uint32_t lav[kNSym];
   __shared__ uint16_t ent[kNSym];
-  __shared__ uint16_t one[1 << kLMax];  // one-symbol decoder table
+  __shared__ __align__(16) uint16_t one[1 << kLMax];  // one-symbol decoder table
   __shared__ uint32_t q[kLMax + 1];
+  __shared__ uint32_t chg[kLMax];
   __shared__ uint32_t scratch[20];
   __shared__ uint64_t s64[16];
   const uint32_t u = blockIdx.x, tid = threadIdx.x;
@@ -2173,14 +2183,73 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   bitonic_sort(key, P);
   for (uint32_t i = tid; i < n; i += blockDim.x) wgt[i] = (uint32_t)(key[i] >> 10);
   __syncthreads();
-  if (n >= 2) {
-    uint32_t *cur = LA, *nx = LB;
-    for (uint32_t i = tid; i < n; i += blockDim.x) cur[i] = wgt[i];
-    uint32_t len_cur = n;
-    __syncthreads();
+  // Up to 64 leaves the levels are built by wavefront 0 alone, synchronised
+  // by lds_order() (its LDS instructions run in program order) instead of
+  // workgroup barriers; the other wavefronts wait at the barrier below.  Up
+  // to 32 leaves a level has at most 63 items, one per lane: the merge ranks
+  // are counted over broadcast lanes, in registers.
+  const bool one_wave = n <= 64;
+  if (n >= 2 && n <= 32 && tid < 64) {
+    const uint32_t lane = tid;
+    const uint32_t w = lane < n ? wgt[lane] : 0u;
+    uint32_t cur = w, len_cur = n;
+    int lfix = 1;
     for (int l = kLMax - 1; l >= 1; l--) {
       const uint32_t np = len_cur / 2;
-      for (uint32_t i = tid; i < n; i += blockDim.x) {
+      const uint32_t a = (uint32_t)__shfl((int)cur, (int)((2 * lane) & 63), 64);
+      const uint32_t b = (uint32_t)__shfl((int)cur, (int)((2 * lane + 1) & 63), 64);
+      const uint32_t pk = a + b;  // package `lane` (lane < np)
+      uint32_t cl = 0, cp = 0;    // packages lighter than leaf `lane`; leaves not heavier than package `lane`
+      for (uint32_t j = 0; j < n; j++) {
+        const uint32_t wj = (uint32_t)__builtin_amdgcn_readlane((int)w, (int)j);
+        cp += wj <= pk ? 1u : 0u;
+        if (j < np) {
+          const uint32_t pj = (uint32_t)__builtin_amdgcn_readlane((int)pk, (int)j);
+          cl += pj < w ? 1u : 0u;
+        }
+      }
+      if (lane < n) {
+        LA[lane + cl] = w;
+        LP[l][lane] = (uint16_t)(lane + cl);
+      }
+      if (lane < np) LA[lane + cp] = pk;
+      const uint32_t len_nx = n + np;
+      lds_order();
+      const uint32_t nxv = lane < len_nx ? LA[lane] : 0u;
+      lds_order();  // every lane has read LA before the next level writes it
+      const bool same = len_nx == len_cur && __ballot(nxv != cur) == 0;
+      cur = nxv;
+      len_cur = len_nx;
+      if (same) {
+        lfix = l;
+        break;
+      }
+    }
+    uint32_t m = 2 * n - 2;  // the leaves before position m, counted by ballots
+    for (int l = 1; l < kLMax; l++) {
+      const int lp = l < lfix ? lfix : l;
+      const uint32_t lo = (uint32_t)__popcll(__ballot(lane < n && LP[lp][lane] < m));
+      if (lane == 0) q[l] = lo;
+      m = 2 * (m - lo);
+    }
+    if (lane == 0) q[kLMax] = m;
+  } else if (n >= 2 && (!one_wave || tid < 64)) {
+    const uint32_t nthr = one_wave ? 64u : blockDim.x;
+    uint32_t *cur = LA, *nx = LB;
+    for (uint32_t i = tid; i < n; i += nthr) cur[i] = wgt[i];
+    uint32_t len_cur = n;
+    if (tid < kLMax) chg[tid] = 0;
+    if (one_wave) lds_order(); else __syncthreads();
+    // Level l is a function of level l + 1 alone, and so are the leaves'
+    // positions in it.  Once a level equals the one above, every lower level
+    // equals it too and has the same leaf positions: the loop stops there and
+    // the levels below read LP[lfix].
+    int lfix = 1;
+    for (int l = kLMax - 1; l >= 1; l--) {
+      const uint32_t np = len_cur / 2;
+      const bool same_len = len_cur == n + np;
+      bool diff = false;
+      for (uint32_t i = tid; i < n; i += nthr) {
         const uint32_t wi = wgt[i];
         uint32_t lo = 0, hi = np;  // packages lighter than the leaf
         while (lo < hi) {
@@ -2189,8 +2258,9 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
         }
         nx[i + lo] = wi;
         LP[l][i] = (uint16_t)(i + lo);
+        diff |= !same_len || cur[i + lo] != wi;
       }
-      for (uint32_t k = tid; k < np; k += blockDim.x) {
+      for (uint32_t k = tid; k < np; k += nthr) {
         const uint32_t pv = cur[2 * k] + cur[2 * k + 1];
         uint32_t lo = 0, hi = n;  // leaves not heavier than the package
         while (lo < hi) {
@@ -2198,33 +2268,41 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
           if (wgt[mid] <= pv) lo = mid + 1; else hi = mid;
         }
         nx[k + lo] = pv;
+        diff |= !same_len || cur[k + lo] != pv;
       }
-      __syncthreads();
+      if (diff) chg[l] = 1;
+      if (one_wave) lds_order(); else __syncthreads();
       uint32_t *t = cur;
       cur = nx;
       nx = t;
       len_cur = n + np;
+      if (!chg[l]) {  // the same value in every thread after the barrier
+        lfix = l;
+        break;
+      }
     }
     if (tid < 64) {  // one wavefront: the leaves before position m, counted by ballots
       uint32_t m = 2 * n - 2;
       for (int l = 1; l < kLMax; l++) {
-        uint32_t lo = 0;  // LP[l][.] increases with the leaf index
+        const int lp = l < lfix ? lfix : l;
+        uint32_t lo = 0;  // LP[lp][.] increases with the leaf index
         for (uint32_t i0 = 0; i0 < n; i0 += 64) {
           const uint32_t i = i0 + tid;
-          lo += (uint32_t)__popcll(__ballot(i < n && LP[l][i] < m));
+          lo += (uint32_t)__popcll(__ballot(i < n && LP[lp][i] < m));
         }
         if (tid == 0) q[l] = lo;
         m = 2 * (m - lo);
       }
       if (tid == 0) q[kLMax] = m;
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  if (n >= 2)
     for (uint32_t i = tid; i < n; i += blockDim.x) {
       uint32_t len = 0;
       for (int l = 1; l <= kLMax; l++) len += i < q[l] ? 1u : 0u;
       lens[key[i] & 1023] = (uint8_t)len;
     }
-  }
   __syncthreads();
   // canonical order (length, symbol)
   for (uint32_t i = tid; i < n; i += blockDim.x) {
@@ -2267,18 +2345,24 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
   // every code marks its first entry with its index, a prefix maximum
   // spreads the marks (starts increase with the index; code 0 starts at 0).
   {
-    constexpr uint32_t kPer = (1u << kLMax) / 256;  // entries per thread
-    for (uint32_t e = tid; e < (1u << kLMax); e += blockDim.x) one[e] = 0;
+    constexpr uint32_t kPer = (1u << kLMax) / 256;  // entries per thread: two uint4
+    uint4 *one4 = (uint4 *)one + 2 * tid;
+    one4[0] = make_uint4(0, 0, 0, 0);
+    one4[1] = make_uint4(0, 0, 0, 0);
     __syncthreads();
     for (uint32_t i = tid; i < n; i += blockDim.x)
       if (lav[i] < (1u << kLMax)) one[lav[i]] = (uint16_t)i;
     __syncthreads();
     uint32_t m[kPer], run = 0;
+    {
+      const uint4 a = one4[0], b = one4[1];
+      const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (uint32_t k = 0; k < kPer; k++) {
-      const uint32_t x = one[tid * kPer + k];
-      run = x > run ? x : run;
-      m[k] = run;
+      for (uint32_t k = 0; k < kPer; k++) {
+        const uint32_t x = (w[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+        run = x > run ? x : run;
+        m[k] = run;
+      }
     }
     // exclusive prefix maximum of the threads' maxima
     uint32_t inc = run;
@@ -2291,15 +2375,20 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
     if (lane_id() == 0) before = 0;
     __syncthreads();
     for (uint32_t w = 0; w < (tid >> 6); w++) before = scratch[w] > before ? scratch[w] : before;
+    uint32_t w[8];
 #pragma unroll
-    for (uint32_t k = 0; k < kPer; k++) {
-      const uint32_t x = m[k] > before ? m[k] : before;
-      one[tid * kPer + k] = ent[x];
+    for (uint32_t k = 0; k < kPer; k += 2) {
+      const uint32_t x0 = m[k] > before ? m[k] : before, x1 = m[k + 1] > before ? m[k + 1] : before;
+      w[k >> 1] = (uint32_t)ent[x0] | ((uint32_t)ent[x1] << 16);
     }
+    one4[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    one4[1] = make_uint4(w[4], w[5], w[6], w[7]);
   }
   __syncthreads();
   uint32_t *dt = nxt.dtab + slot_slice[u] * (1u << kLMax);
-  for (uint32_t e = tid; e < (1u << kLMax); e += blockDim.x) {
+#pragma unroll
+  for (uint32_t k = 0; k < (1u << kLMax) / 256; k++) {  // all LDS reads issued before the stores
+    const uint32_t e = k * 256 + tid;
     const uint32_t s1 = one[e] & 1023u, l1 = one[e] >> 10;
     const uint32_t e2 = (e << l1) & ((1u << kLMax) - 1);
     const uint32_t s2 = one[e2] & 1023u, l2 = one[e2] >> 10;
