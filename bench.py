@@ -60,9 +60,13 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--fp32", action="store_true",
                     help="FP32 mode (grover24, grover34): FP32 working values and gate arithmetic")
-    ap.add_argument("--workload", choices=("grover24", "qft30", "grover34", "qft12"), default="grover24",
+    ap.add_argument("--workload", choices=("grover24", "qft30", "grover34", "qft12", "serve"), default="grover24",
                     help="grover24 (default, the headline line); qft30: 30-qubit QFT of a product state in "
                          "fused mode; grover34: a window of 34-qubit Grover search")
+    ap.add_argument("--jobs", type=int, default=200, help="serve: jobs in the timed stream")
+    ap.add_argument("--arrival-ms", type=float, default=25.0, help="serve: mean gap between arrivals")
+    ap.add_argument("--max-active", type=int, default=4, help="serve: jobs running at once, at most")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device-memory budget")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 256 MiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -394,6 +398,118 @@ def run_grover34(args):
     return line
 
 
+def serve_jobs(count, seed):
+    """A seeded stream of independent jobs: n ~ U{16..24}, absolute bound
+    log-uniform in [1e-7, 1e-4], FP32 or FP64 with equal odds, and one of three
+    families with equal odds -- Grover (1..8 iterations, random marked index,
+    from |0...0>), the QFT of a random basis state, or 20 random layers of U3
+    gates and CZ on a random perfect matching (from |0...0>).  64 slices per
+    state (at most 2^18 amplitudes each), chunks of 256 values."""
+    import numpy as np
+    import qcircuits as qc
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for i in range(count):
+        n = int(rng.integers(16, 25))
+        fam = int(rng.integers(0, 3))
+        eb = float(10 ** rng.uniform(-7, -4))
+        fp32 = bool(rng.integers(0, 2))
+        job = dict(n=n, sl=min(18, n - 6), eb=eb, fp32=fp32, family=fam, init="zero", basis=0)
+        if fam == 0:
+            job["gates"] = qc.grover(n, int(rng.integers(0, 1 << n)), int(rng.integers(1, 9)))
+        elif fam == 1:
+            job["gates"] = qc.qft(n)
+            job["init"], job["basis"] = "basis", int(rng.integers(0, 1 << n))
+        else:
+            job["gates"] = qc.random_layered(n, 20, seed=int(rng.integers(0, 1 << 31)))
+        jobs.append(job)
+    return jobs
+
+
+def run_serve(args):
+    """Serving: jobs arrive as a Poisson stream (mean gap --arrival-ms) and
+    run on the job server, up to --max-active at once within a device-memory
+    budget.  Value: amplitude-passes of all jobs per second of makespan (first
+    arrival to last completion); beside it the job latency percentiles
+    (completion - arrival).  A sample of jobs is run again alone and compared
+    bit for bit."""
+    import numpy as np
+    import paper_1811_05630_amd as cq
+    rng = np.random.Generator(np.random.PCG64(args.seed + 1))
+    n_jobs = args.jobs
+    jobs = serve_jobs(n_jobs + 2, args.seed)
+    warm, jobs = jobs[:2], jobs[2:]
+    for j in jobs + warm:
+        j["circ"] = cq.Circuit(j["gates"])
+    keep = 4096  # leading amplitudes returned per job (compared in the alone check)
+
+    def submit(srv, j):
+        return srv.submit(j["n"], j["sl"], j["eb"], j["circ"], family=j["family"], init=j["init"], basis=j["basis"],
+                          fp32=j["fp32"], chunk_log2=args.chunk_log2, out_count=keep)
+
+    budget = int(args.budget_gib * (1 << 30))
+    srv = cq.Server(budget, args.max_active)
+    for j in warm:
+        submit(srv, j)
+    srv.drain(timeout=600)
+    gaps = rng.exponential(args.arrival_ms / 1e3, size=n_jobs)
+    arrive = np.cumsum(gaps) - gaps[0]
+    t_base = srv.clock()
+    ids, done, k = {}, [], 0
+    while k < n_jobs or len(done) < n_jobs:
+        now = srv.clock() - t_base
+        while k < n_jobs and arrive[k] <= now:
+            ids[submit(srv, jobs[k])] = k
+            k += 1
+        wait = (arrive[k] - (srv.clock() - t_base)) if k < n_jobs else 1.0
+        got = srv.wait(timeout=max(0.0, min(wait, 1.0)))
+        done += got
+        if got and len(done) % 50 < len(got):
+            print(f"[serve] {len(done)}/{n_jobs} jobs done", file=sys.stderr, flush=True)
+    srv.close()
+    bad = [d for d in done if d["status"] != 0]
+    if bad:
+        raise RuntimeError(f"{len(bad)} jobs failed, first: {bad[0]['error']}")
+    t0 = min(d["t_submit"] for d in done)
+    t1 = max(d["t_end"] for d in done)
+    makespan = t1 - t0
+    amp_passes = sum(d["stats"]["passes"] * (1 << jobs[ids[d["id"]]]["n"]) for d in done)
+    lat = np.array([d["t_end"] - d["t_submit"] for d in done]) * 1e3
+    wait_q = np.array([d["t_start"] - d["t_submit"] for d in done]) * 1e3
+    service = np.array([d["t_end"] - d["t_start"] for d in done]) * 1e3
+    # the same jobs alone (one at a time) give the same bits
+    sample = [d for d in done if ids[d["id"]] < 6]
+    alone = cq.Server(budget, 1)
+    alone_ids = [submit(alone, jobs[ids[d["id"]]]) for d in sample]
+    again = {r["id"]: r for r in alone.drain(600)}
+    alone.close()
+    same = all(np.array_equal(d["amplitudes"].view(np.uint64), again[a]["amplitudes"].view(np.uint64)) and
+               d["stats"]["compressed_bytes"] == again[a]["stats"]["compressed_bytes"]
+               for d, a in zip(sample, alone_ids))
+    fams = ["grover", "qft", "layered"]
+    return {
+        "metric": METRIC, "value": amp_passes / makespan, "unit": "amps/s", "n_gpus": 1, "steps": n_jobs,
+        "warmup": len(warm), "ms_per_step": makespan / n_jobs * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "serve: %d independent jobs, Poisson arrivals (mean gap %g ms), n ~ U{16..24}, "
+                               "absolute bound log-uniform [1e-7, 1e-4], FP32/FP64 1:1, Grover (1..8 iterations) / "
+                               "QFT of a basis state / 20 random U3+CZ layers 1:1:1, up to %d jobs at once within "
+                               "%g GiB" % (n_jobs, args.arrival_ms, args.max_active, args.budget_gib),
+                   "jobs": n_jobs, "max_active": args.max_active, "budget_bytes": budget,
+                   "chunk_log2": args.chunk_log2, "seed": args.seed},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "queue_wait_ms": {"p50": float(np.percentile(wait_q, 50)), "p99": float(np.percentile(wait_q, 99))},
+        "service_ms": {"p50": float(np.percentile(service, 50)), "p99": float(np.percentile(service, 99))},
+        "jobs_per_s": n_jobs / makespan,
+        "overlap": float(service.sum() / 1e3 / makespan),
+        "ratio": {"final_median": float(np.median([d["stats"]["ratio"] for d in done])),
+                  "min_over_jobs": float(min(d["stats"]["min_ratio"] for d in done))},
+        "jobs_by_family": {f: sum(1 for d in done if d["family"] == i) for i, f in enumerate(fams)},
+        "alone_equals_mixed": {"checked": len(sample), "identical": bool(same)},
+        "roofline": None,
+    }
+
+
 def cpu_sample(w, seconds, chunk_log2, fused_k, fp32=False):
     """The oracle on a bounded sample of a large workload: one slice of the
     workload's shape, compressed by the oracle itself, put through repeated
@@ -436,13 +552,14 @@ def cpu_sample(w, seconds, chunk_log2, fused_k, fp32=False):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU slice sharding is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
         return
-    run = {"grover24": run_grover24, "qft30": run_qft30, "grover34": run_grover34, "qft12": run_qft12}[args.workload]
+    run = {"grover24": run_grover24, "qft30": run_qft30, "grover34": run_grover34, "qft12": run_qft12,
+           "serve": run_serve}[args.workload]
     print(json.dumps(run(args)), flush=True)
 
 

@@ -132,6 +132,7 @@ typedef struct sim_stats_t {
   double elapsed_s;             /* device time spent in sim_apply */
   uint64_t arena_bytes;         /* device bytes held for compressed records (both buffers) */
   uint64_t workspace_slots;     /* slices decompressed at once */
+  uint64_t device_bytes;        /* every device byte the handle holds now */
 } sim_stats_t;
 
 /* Create a simulator holding |0...0>, compressed (Algorithm 1 starts from a
@@ -141,6 +142,14 @@ typedef struct sim_stats_t {
  * codes to stay below 2^48 in magnitude). */
 int sim_create(int n_qubits, int slice_log2, double error_bound, uint32_t mode, sim_t **out);
 int sim_create_ex(const sim_config *cfg, sim_t **out);
+
+/* Device bytes that sim_create_ex(cfg) would hold once the initial state is
+ * built (every buffer of the handle, both record arenas at their initial
+ * capacity and the slot order of slice-local gates); later growth (arena
+ * doubling, gate groups on slice-index qubits, fused-block matrices, readout
+ * staging) is not included.  Host-only: touches no device.  Errors: as
+ * sim_create_ex for the configuration's fields (allocator and stream ignored). */
+int sim_footprint(const sim_config *cfg, uint64_t *bytes);
 
 /* Release all device memory of the handle.  NULL is ignored. */
 void sim_destroy(sim_t *sim);
@@ -245,6 +254,89 @@ void sim_graph_destroy(sim_graph_t *graph);
  * turns the per-kernel events on and resets the sums, enable == 0 turns them
  * off, enable < 0 only reads. */
 int sim_kernel_times(sim_t *sim, int enable, double *out, int cap, const char **names);
+
+/* ---- job server (an extension: the paper simulates one circuit at a time)
+ * For callers that run many independent circuits on one device (a request
+ * queue of simulation jobs).  Each admitted job gets its own handle and one
+ * of `max_active` HIP streams, driven by a host worker thread, so the passes
+ * of different jobs run on the device at the same time; jobs stay compressed
+ * in device memory while they run.
+ * Admission is first come, first served: the job at the head of the queue
+ * starts when fewer than max_active jobs run and the projected footprints of
+ * the running jobs plus its own fit `budget_bytes` (or nothing runs).  The
+ * projected footprint is sim_footprint() of the job's configuration with
+ * each record arena sized by a per-family ratio model: 8 bytes per amplitude
+ * (int32 codes for both components) until a job of the family has finished,
+ * afterwards 1.25 x raw bytes / (the smallest minimum ratio seen in the
+ * family), never above 8 bytes per amplitude.  A job whose records outgrow
+ * the projection still completes (its arenas double).  Device memory of
+ * finished jobs is cached for later jobs (requests are rounded up to
+ * multiples of 64 KiB and of an eighth of their largest power of two; the
+ * cache holds at most `budget_bytes`).
+ * Jobs share nothing but the device: a job's records, amplitudes and
+ * statistics do not depend on the jobs that run beside it. */
+#define SRV_INIT_ZERO 0u    /* start from |0...0> */
+#define SRV_INIT_BASIS 1u   /* start from |basis> */
+#define SRV_INIT_PRODUCT 2u /* start from the product state of `factors` */
+#define SRV_FAMILIES 16u    /* ratio-model classes */
+
+typedef struct srv_s srv_t;
+
+typedef struct srv_job {
+  sim_config cfg;         /* alloc, free_fn and stream must be NULL (the server provides
+                             them); arena_bytes 0: sized by the ratio model */
+  uint32_t family;        /* ratio-model class, < SRV_FAMILIES (e.g. one per circuit family) */
+  uint32_t init;          /* SRV_INIT_* */
+  uint64_t basis;         /* SRV_INIT_BASIS: the basis index */
+  const double *factors;  /* SRV_INIT_PRODUCT: 4 * n_qubits doubles as for sim_init_product;
+                             host memory, copied by srv_submit */
+  const sim_gate *gates;  /* the program; host memory, copied (matrices too) by srv_submit */
+  size_t n_gates;
+  double *out;            /* host buffer for amplitudes [out_begin, out_begin + out_count) as
+                             sim_amplitudes writes them, filled when the job ends; NULL: none.
+                             Owned by the caller; must stay valid until srv_wait reports the job */
+  uint64_t out_begin;
+  uint64_t out_count;
+} srv_job;
+
+typedef struct srv_done {
+  uint64_t id;               /* as returned by srv_submit */
+  int status;                /* SIM_OK or the code of the first failing call */
+  uint32_t family;
+  uint64_t applied;          /* gates applied */
+  uint64_t projected_bytes;  /* footprint the job was admitted with */
+  uint64_t device_bytes;     /* device bytes its handle held at the end */
+  double t_submit, t_start, t_end; /* seconds on the server clock (srv_clock) */
+  sim_stats_t stats;         /* final statistics (zero if the handle was never created) */
+  char error[160];           /* sim_last_error() of the failing call, or empty */
+} srv_done;
+
+/* Start a server with `max_active` (1..64) workers and streams.  Errors:
+ * SIM_EINVAL, SIM_EDEVICE (no gfx950 device). */
+int srv_create(uint64_t budget_bytes, int max_active, srv_t **out);
+
+/* Queue a job; *id receives its number (1, 2, ...).  Errors: SIM_EINVAL
+ * (configuration, family, init or pointers), SIM_ENOMEM (the projected
+ * footprint alone exceeds the budget).  The job's gates are validated when it
+ * runs (the status reports a bad gate). */
+int srv_submit(srv_t *srv, const srv_job *job, uint64_t *id);
+
+/* Move up to `cap` finished jobs not yet reported into out[0..*n_out), in
+ * completion order.  Waits up to timeout_s seconds for the first one (0: do
+ * not wait); returns at once with *n_out = 0 when no job is queued or
+ * running. */
+int srv_wait(srv_t *srv, srv_done *out, size_t cap, size_t *n_out, double timeout_s);
+
+/* Seconds since srv_create (the clock of srv_done's times). */
+double srv_clock(srv_t *srv);
+
+/* The footprint the job would be admitted with now (the model changes as
+ * jobs finish). */
+int srv_projected_bytes(srv_t *srv, const srv_job *job, uint64_t *bytes);
+
+/* Cancel queued jobs, wait for running ones, release everything.  Finished
+ * jobs not yet reported are dropped.  NULL is ignored. */
+void srv_destroy(srv_t *srv);
 
 #ifdef __cplusplus
 }

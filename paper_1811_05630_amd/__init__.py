@@ -35,7 +35,11 @@ ERRORS = {-1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EBOUND", -4: "SIM_ECORRUP
 EXPORTS = ("sim_create", "sim_create_ex", "sim_destroy", "sim_last_error", "sim_init_basis", "sim_init_product",
            "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_amplitudes", "sim_probabilities", "sim_stats",
            "sim_record_size", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan",
-           "sim_graph_create", "sim_graph_launch", "sim_graph_destroy")
+           "sim_graph_create", "sim_graph_launch", "sim_graph_destroy", "sim_footprint",
+           "srv_create", "srv_submit", "srv_wait", "srv_clock", "srv_projected_bytes", "srv_destroy")
+
+SRV_INIT_ZERO, SRV_INIT_BASIS, SRV_INIT_PRODUCT = 0, 1, 2
+SRV_FAMILIES = 16
 
 
 class SimError(RuntimeError):
@@ -70,7 +74,21 @@ class StatsStruct(C.Structure):
     _fields_ = [("raw_bytes", C.c_uint64), ("compressed_bytes", C.c_uint64), ("peak_compressed", C.c_uint64),
                 ("ratio", C.c_double), ("min_ratio", C.c_double), ("passes", C.c_uint64),
                 ("escapes", C.c_uint64), ("last_norm", C.c_double), ("max_abs_codec_err", C.c_double),
-                ("elapsed_s", C.c_double), ("arena_bytes", C.c_uint64), ("workspace_slots", C.c_uint64)]
+                ("elapsed_s", C.c_double), ("arena_bytes", C.c_uint64), ("workspace_slots", C.c_uint64),
+                ("device_bytes", C.c_uint64)]
+
+
+class SrvJobStruct(C.Structure):
+    _fields_ = [("cfg", ConfigStruct), ("family", C.c_uint32), ("init", C.c_uint32), ("basis", C.c_uint64),
+                ("factors", C.c_void_p), ("gates", C.POINTER(GateStruct)), ("n_gates", C.c_size_t),
+                ("out", C.c_void_p), ("out_begin", C.c_uint64), ("out_count", C.c_uint64)]
+
+
+class SrvDoneStruct(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int), ("family", C.c_uint32), ("applied", C.c_uint64),
+                ("projected_bytes", C.c_uint64), ("device_bytes", C.c_uint64), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_end", C.c_double), ("stats", StatsStruct),
+                ("error", C.c_char * 160)]
 
 
 _lib = None
@@ -115,6 +133,15 @@ def lib():
         L.sim_graph_destroy.restype = None
         L.sim_plan.argtypes = [C.c_int, C.POINTER(GateStruct), C.c_size_t, C.POINTER(PassStruct), C.c_size_t,
                                C.POINTER(C.c_size_t)]
+        L.sim_footprint.argtypes = [C.POINTER(ConfigStruct), C.POINTER(C.c_uint64)]
+        L.srv_create.argtypes = [C.c_uint64, C.c_int, C.POINTER(P)]
+        L.srv_submit.argtypes = [P, C.POINTER(SrvJobStruct), C.POINTER(C.c_uint64)]
+        L.srv_wait.argtypes = [P, C.POINTER(SrvDoneStruct), C.c_size_t, C.POINTER(C.c_size_t), C.c_double]
+        L.srv_clock.argtypes = [P]
+        L.srv_clock.restype = C.c_double
+        L.srv_projected_bytes.argtypes = [P, C.POINTER(SrvJobStruct), C.POINTER(C.c_uint64)]
+        L.srv_destroy.argtypes = [P]
+        L.srv_destroy.restype = None
         _lib = L
     return _lib
 
@@ -399,3 +426,125 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def _config(n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False, chunk_log2: int = 0,
+            workspace_bytes: int = 0, arena_bytes: int = 0, fused: bool = False, fp32: bool = False) -> ConfigStruct:
+    cfg = ConfigStruct()
+    cfg.n_qubits = n_qubits
+    cfg.slice_log2 = slice_log2
+    cfg.chunk_log2 = chunk_log2
+    cfg.error_bound = error_bound
+    cfg.mode = ((SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0) | (SIM_FP32 if fp32 else 0))
+    cfg.workspace_bytes = workspace_bytes
+    cfg.arena_bytes = arena_bytes
+    return cfg
+
+
+def footprint(n_qubits: int, slice_log2: int, error_bound: float, **kw) -> int:
+    """sim_footprint: device bytes a new Sim of this configuration holds (host-only)."""
+    b = C.c_uint64()
+    _check(lib().sim_footprint(C.byref(_config(n_qubits, slice_log2, error_bound, **kw)), C.byref(b)),
+           "sim_footprint")
+    return b.value
+
+
+class Server:
+    """A job server (srv_*): independent simulations run side by side on the
+    device, admitted first come, first served within a device-memory budget.
+
+    submit() queues a job and returns its id; wait() returns finished jobs as
+    dicts (id, status, times on the server clock, statistics, and the
+    requested amplitudes as a complex array)."""
+
+    def __init__(self, budget_bytes: int, max_active: int = 4):
+        h = C.c_void_p()
+        self._h = None
+        _check(lib().srv_create(int(budget_bytes), int(max_active), C.byref(h)), "srv_create")
+        self._h = h
+        self._keep = {}  # job id -> objects that must outlive the job (gates, factors, output)
+
+    def _job(self, n_qubits, slice_log2, error_bound, gates=(), family=0, init="zero", basis=0, factors=None,
+             out_count=0, out_begin=0, **cfg):
+        j = SrvJobStruct()
+        j.cfg = _config(n_qubits, slice_log2, error_bound, **cfg)
+        j.family = family
+        j.init = {"zero": SRV_INIT_ZERO, "basis": SRV_INIT_BASIS, "product": SRV_INIT_PRODUCT}[init]
+        j.basis = basis
+        keep = []
+        if factors is not None:
+            f = np.ascontiguousarray(np.asarray(factors, dtype=np.complex128)).view(np.float64).copy()
+            assert f.size == 4 * n_qubits
+            j.factors = f.ctypes.data_as(C.c_void_p)
+            keep.append(f)
+        if len(gates):
+            ptr, cnt, k = _gate_ptr(gates)
+            j.gates, j.n_gates = ptr, cnt
+            keep.append(k)
+        out = None
+        if out_count:
+            out = np.zeros(2 * out_count)
+            j.out, j.out_begin, j.out_count = out.ctypes.data_as(C.c_void_p), out_begin, out_count
+        return j, keep, out
+
+    def submit(self, n_qubits: int, slice_log2: int, error_bound: float, gates: Sequence = (), **kw) -> int:
+        """Queue a job.  Keywords: family, init ('zero' | 'basis' | 'product'),
+        basis, factors, out_count / out_begin (amplitudes to return), and the
+        Sim configuration (relative, chunk_log2, workspace_bytes, arena_bytes,
+        fused, fp32)."""
+        j, keep, out = self._job(n_qubits, slice_log2, error_bound, gates, **kw)
+        i = C.c_uint64()
+        _check(lib().srv_submit(self._h, C.byref(j), C.byref(i)), "srv_submit")
+        self._keep[i.value] = (keep, out)
+        return i.value
+
+    def projected_bytes(self, n_qubits: int, slice_log2: int, error_bound: float, **kw) -> int:
+        j, keep, out = self._job(n_qubits, slice_log2, error_bound, **kw)
+        b = C.c_uint64()
+        _check(lib().srv_projected_bytes(self._h, C.byref(j), C.byref(b)), "srv_projected_bytes")
+        return b.value
+
+    def clock(self) -> float:
+        return lib().srv_clock(self._h)
+
+    def wait(self, timeout: float = 0.0, cap: int = 256) -> List[dict]:
+        buf = (SrvDoneStruct * cap)()
+        n = C.c_size_t()
+        _check(lib().srv_wait(self._h, buf, cap, C.byref(n), float(timeout)), "srv_wait")
+        res = []
+        for d in buf[:n.value]:
+            r = {k: getattr(d, k) for k, _ in SrvDoneStruct._fields_ if k not in ("stats", "error")}
+            r["stats"] = {k: getattr(d.stats, k) for k, _ in StatsStruct._fields_}
+            r["error"] = d.error.decode()
+            keep, out = self._keep.pop(d.id, (None, None))
+            if out is not None:
+                r["amplitudes"] = out[0::2] + 1j * out[1::2]
+            res.append(r)
+        return res
+
+    def drain(self, timeout: float = 600.0) -> List[dict]:
+        """Wait until every submitted job has finished; returns them all."""
+        res = []
+        while self._keep:
+            got = self.wait(timeout)
+            if not got:
+                raise TimeoutError(f"jobs {sorted(self._keep)} not finished within {timeout} s")
+            res += got
+        return res
+
+    def close(self):
+        if self._h:
+            lib().srv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

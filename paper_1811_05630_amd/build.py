@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcqsim.so")
-SOURCES = ["kernels.hip", "kernels_fp32.hip", "api.hip"]
+SOURCES = ["kernels.hip", "kernels_fp32.hip", "api.hip", "serve.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wl,--no-undefined",

@@ -49,6 +49,12 @@ int set_err(int code, const char *fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+int cq::fail(int code, const char *msg) { return set_err(code, "%s", msg); }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                    \
   do {                                                                                   \
     hipError_t e_ = (expr);                                                              \
@@ -83,8 +89,11 @@ struct sim_s {
   struct Owner {
     void (*free_fn)(void *, void *);  // NULL: hipFree
     void *ctx;
+    size_t bytes;
   };
   std::map<void *, Owner> owned;
+  uint64_t dev_bytes = 0;  // sum over `owned`
+  bool dry = false;        // count the bytes of every dalloc, allocate nothing (sim_footprint)
 
   Ctl *ctl = nullptr;
   Ctl *h_ctl = nullptr;  // pinned host copy
@@ -118,10 +127,15 @@ struct sim_s {
   int dalloc(void **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
+    if (dry) {
+      dev_bytes += bytes;
+      return SIM_OK;
+    }
     if (al_fn) {
       *p = al_fn(bytes, al_ctx);
       if (!*p) return set_err(SIM_ENOMEM, "allocator hook returned NULL for %zu bytes", bytes);
-      owned[*p] = Owner{al_free, al_ctx};
+      owned[*p] = Owner{al_free, al_ctx, bytes};
+      dev_bytes += bytes;
       return SIM_OK;
     }
     hipError_t e = hipMalloc(p, bytes);
@@ -129,7 +143,8 @@ struct sim_s {
       *p = nullptr;
       return set_err(SIM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
-    owned[*p] = Owner{nullptr, nullptr};
+    owned[*p] = Owner{nullptr, nullptr, bytes};
+    dev_bytes += bytes;
     return SIM_OK;
   }
   void dfree(void *p) {
@@ -140,6 +155,7 @@ struct sim_s {
       it->second.free_fn(p, it->second.ctx);
     else
       hipFree(p);
+    dev_bytes -= it->second.bytes;
     owned.erase(it);
   }
 
@@ -604,9 +620,13 @@ int sim_create(int n_qubits, int slice_log2, double error_bound, uint32_t mode, 
   return sim_create_ex(&c, out);
 }
 
-int sim_create_ex(const sim_config *cfg, sim_t **out) {
-  if (!cfg || !out) return set_err(SIM_EINVAL, "null argument");
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Geometry, workspace slots and arena capacity of a configuration; shared by
+// sim_create_ex and sim_footprint.
+int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   const int n = cfg->n_qubits, sl2 = cfg->slice_log2;
   if (n < 1 || n > 40) return set_err(SIM_EINVAL, "n_qubits %d outside 1..40", n);
   if (sl2 < 1 || sl2 > n || sl2 > 26) return set_err(SIM_EINVAL, "slice_log2 %d outside 1..min(26, n)", sl2);
@@ -617,6 +637,72 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
   int cl2 = cfg->chunk_log2 > 0 ? cfg->chunk_log2 : 10;
   if (cl2 > sl2) cl2 = sl2;
   if (cl2 > 10) return set_err(SIM_EINVAL, "chunk_log2 %d above 10", cl2);
+  s->geo.n = n;
+  s->geo.slice_log2 = sl2;
+  s->geo.chunk_log2 = cl2;
+  s->geo.L = 1ull << sl2;
+  s->geo.nchunks = (uint32_t)((2ull << sl2) >> cl2);
+  s->eb = cfg->error_bound;
+  s->mode = cfg->mode;
+  s->fp32 = (cfg->mode & SIM_FP32) != 0;
+  s->nslices = 1ull << (n - sl2);
+  // workspace: a power of two number of slots within the budget; the default
+  // budget always holds one full 32-slice group (a dense gate on five
+  // slice-index qubits); an explicit budget is honoured and gates whose group
+  // does not fit are refused with SIM_ENOMEM
+  const uint64_t budget = cfg->workspace_bytes ? cfg->workspace_bytes : (16ull << 30);
+  uint64_t W = 1;
+  while (W * 2 <= s->nslices && W * 2 * per_slot_bytes(s->geo) <= budget) W *= 2;
+  if (!cfg->workspace_bytes) W = std::max<uint64_t>(W, std::min<uint64_t>(s->nslices, 32));
+  s->W = (int)W;
+  *arena_cap = cfg->arena_bytes ? std::max<uint64_t>(cfg->arena_bytes, 4096)
+                                : std::max<uint64_t>(4 * min_record_total(s), 16ull << 20);
+  return SIM_OK;
+}
+
+// Every device buffer of a new handle (in dry mode: only their sizes).
+int alloc_state(sim_t *s, uint64_t cap) {
+  int rc;
+  if ((rc = s->dalloc((void **)&s->ctl, sizeof(Ctl))) || (rc = alloc_meta(s, s->meta[0])) ||
+      (rc = alloc_meta(s, s->meta[1])) || (rc = s->dalloc((void **)&s->kscale, 8 * s->nslices)) ||
+      (rc = alloc_slots(s)) || (rc = s->dalloc((void **)&s->dfactors, 32 * (size_t)s->geo.n)))
+    return rc;
+  for (int a = 0; a < 2; a++) {
+    if ((rc = s->dalloc((void **)&s->arena[a], cap))) return rc;
+    s->arena_cap[a] = cap;
+  }
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_footprint(const sim_config *cfg, uint64_t *bytes) {
+  if (!cfg || !bytes) return set_err(SIM_EINVAL, "null argument");
+  *bytes = 0;
+  sim_t s;
+  s.dry = true;
+  uint64_t cap = 0;
+  int rc = configure(cfg, &s, &cap);
+  if (rc) return rc;
+  alloc_state(&s, cap);
+  // plus the slot order of slice-local gates, made by the pass that builds
+  // the initial state
+  *bytes = s.dev_bytes + 8 * s.nslices;
+  return SIM_OK;
+}
+
+int sim_create_ex(const sim_config *cfg, sim_t **out) {
+  if (!cfg || !out) return set_err(SIM_EINVAL, "null argument");
+  *out = nullptr;
+  {
+    sim_t probe;
+    uint64_t cap;
+    int rc = configure(cfg, &probe, &cap);
+    if (rc) return rc;
+  }
+  if ((cfg->alloc == nullptr) != (cfg->free_fn == nullptr)) return set_err(SIM_EINVAL, "allocator needs both functions");
 
   int ndev = 0;
   hipError_t de = hipGetDeviceCount(&ndev);
@@ -631,19 +717,8 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
     return set_err(SIM_EDEVICE, "device %s is not gfx950", prop.gcnArchName);
 
   sim_t *s = new sim_t();
-  s->geo.n = n;
-  s->geo.slice_log2 = sl2;
-  s->geo.chunk_log2 = cl2;
-  s->geo.L = 1ull << sl2;
-  s->geo.nchunks = (uint32_t)((2ull << sl2) >> cl2);
-  s->eb = cfg->error_bound;
-  s->mode = cfg->mode;
-  s->fp32 = (cfg->mode & SIM_FP32) != 0;
-  s->nslices = 1ull << (n - sl2);
-  if ((cfg->alloc == nullptr) != (cfg->free_fn == nullptr)) {
-    delete s;
-    return set_err(SIM_EINVAL, "allocator needs both functions");
-  }
+  uint64_t cap = 0;
+  configure(cfg, s, &cap);
   s->al_fn = cfg->alloc;
   s->al_free = cfg->free_fn;
   s->al_ctx = cfg->alloc_ctx;
@@ -659,19 +734,8 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
   }
   hipEventCreate(&s->ev0);
   hipEventCreate(&s->ev1);
-  // workspace: a power of two number of slots within the budget; the default
-  // budget always holds one full 32-slice group (a dense gate on five
-  // slice-index qubits); an explicit budget is honoured and gates whose group
-  // does not fit are refused with SIM_ENOMEM
-  const uint64_t budget = cfg->workspace_bytes ? cfg->workspace_bytes : (16ull << 30);
-  uint64_t W = 1;
-  while (W * 2 <= s->nslices && W * 2 * per_slot_bytes(s->geo) <= budget) W *= 2;
-  if (!cfg->workspace_bytes) W = std::max<uint64_t>(W, std::min<uint64_t>(s->nslices, 32));
-  s->W = (int)W;
   int rc;
-  if ((rc = s->dalloc((void **)&s->ctl, sizeof(Ctl))) || (rc = alloc_meta(s, s->meta[0])) ||
-      (rc = alloc_meta(s, s->meta[1])) || (rc = s->dalloc((void **)&s->kscale, 8 * s->nslices)) ||
-      (rc = alloc_slots(s)) || (rc = s->dalloc((void **)&s->dfactors, 32 * (size_t)n))) {
+  if ((rc = alloc_state(s, cap))) {
     sim_destroy(s);
     return rc;
   }
@@ -686,15 +750,6 @@ int sim_create_ex(const sim_config *cfg, sim_t **out) {
     return set_err(SIM_EDEVICE, "control block upload failed");
   }
   launch_reset_slots(s->stream, s->slots, s->W);
-  const uint64_t cap =
-      cfg->arena_bytes ? std::max<uint64_t>(cfg->arena_bytes, 4096) : std::max<uint64_t>(4 * min_record_total(s), 16ull << 20);
-  for (int a = 0; a < 2; a++) {
-    if ((rc = s->dalloc((void **)&s->arena[a], cap))) {
-      sim_destroy(s);
-      return rc;
-    }
-    s->arena_cap[a] = cap;
-  }
   rc = run_passes(s, nullptr, nullptr, 0, 0, 0, nullptr);
   if (rc) {
     sim_destroy(s);
@@ -1194,6 +1249,7 @@ int sim_stats(sim_t *s, sim_stats_t *out) {
   out->elapsed_s = s->elapsed;
   out->arena_bytes = s->arena_cap[0] + s->arena_cap[1];
   out->workspace_slots = (uint64_t)s->W;
+  out->device_bytes = s->dev_bytes;
   return SIM_OK;
 }
 

@@ -212,4 +212,7 @@ inline uint32_t stage_words_for(int chunk_log2) {
   return (uint32_t)((((uint64_t)1 << chunk_log2) * (kLMax + kEscBits + 50) + 31) / 32 + 1);
 }
 
+// Sets the calling thread's sim_last_error() text; returns `code`.
+int fail(int code, const char *msg);
+
 }  // namespace cq

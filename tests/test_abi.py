@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "cqsim.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b((?:sim|srv)_[a-z_]+)\s*\(", src)))
 
 
 def test_header_declares_the_binding_exports():
@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(L, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", cq.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r"\bT (sim_[a-z_]+)\b", out))
+    exported = set(re.findall(r"\bT ((?:sim|srv)_[a-z_]+)\b", out))
     assert set(declared_functions()) <= exported
 
 
@@ -51,6 +51,12 @@ int main(void) {
   F(sim_config, error_bound); F(sim_config, workspace_bytes); F(sim_config, alloc); F(sim_config, stream);
   F(sim_config, arena_bytes);
   F(sim_stats_t, ratio); F(sim_stats_t, max_abs_codec_err); F(sim_stats_t, workspace_slots);
+  F(sim_stats_t, device_bytes);
+  printf("srv_job %zu\n", sizeof(srv_job));
+  printf("srv_done %zu\n", sizeof(srv_done));
+  F(srv_job, family); F(srv_job, basis); F(srv_job, factors); F(srv_job, gates); F(srv_job, n_gates);
+  F(srv_job, out); F(srv_job, out_count);
+  F(srv_done, status); F(srv_done, applied); F(srv_done, t_submit); F(srv_done, stats); F(srv_done, error);
   return 0;
 }
 """
@@ -77,6 +83,12 @@ def test_struct_layouts_match_header():
         "sim_stats_t.ratio": cq.StatsStruct.ratio.offset,
         "sim_stats_t.max_abs_codec_err": cq.StatsStruct.max_abs_codec_err.offset,
         "sim_stats_t.workspace_slots": cq.StatsStruct.workspace_slots.offset,
+        "sim_stats_t.device_bytes": cq.StatsStruct.device_bytes.offset,
+        "srv_job": C.sizeof(cq.SrvJobStruct), "srv_done": C.sizeof(cq.SrvDoneStruct),
+        **{f"srv_job.{f}": getattr(cq.SrvJobStruct, f).offset
+           for f in ("family", "basis", "factors", "gates", "n_gates", "out", "out_count")},
+        **{f"srv_done.{f}": getattr(cq.SrvDoneStruct, f).offset
+           for f in ("status", "applied", "t_submit", "stats", "error")},
     }
     assert {k: int(v) for k, v in got.items()} == py
     assert py["sim_gate"] == 72
@@ -121,4 +133,35 @@ def test_no_device_means_a_loud_failure():
         pytest.skip("libcqsim.so not built")
     with pytest.raises(cq.SimError) as e:
         cq.Sim(4, 2, 1e-6, use_torch=False)
+    assert e.value.rc == -5
+
+
+def test_footprint_without_the_device():
+    """sim_footprint is host arithmetic: arenas count twice, the workspace
+    budget bounds the slot buffers, bad configurations are refused."""
+    if not os.path.exists(cq.LIB_PATH):
+        pytest.skip("libcqsim.so not built")
+    base = cq.footprint(14, 10, 1e-6, arena_bytes=1 << 20)
+    assert cq.footprint(14, 10, 1e-6, arena_bytes=3 << 20) - base == 2 * (2 << 20)
+    assert cq.footprint(15, 10, 1e-6, arena_bytes=1 << 20) > base
+    small = cq.footprint(14, 10, 1e-6, arena_bytes=1 << 20, workspace_bytes=1)  # one slot
+    assert small < base
+    # FP32 changes the raw size only, not the buffers of a handle
+    assert cq.footprint(14, 10, 1e-6, arena_bytes=1 << 20, fp32=True) == base
+    with pytest.raises(cq.SimError) as e:
+        cq.footprint(14, 15, 1e-6)
+    assert e.value.rc == -1
+
+
+def test_server_without_a_device_fails_loudly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    if not os.path.exists(cq.LIB_PATH):
+        pytest.skip("libcqsim.so not built")
+    with pytest.raises(cq.SimError) as e:
+        cq.Server(1 << 30, 2)
     assert e.value.rc == -5
