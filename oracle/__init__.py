@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 ABS = 0
 REL = 1
 FP32 = 2  # mode bit: FP32 working values and gate arithmetic (quantiser and norm stay FP64)
+ZERO_CHUNKS = 8  # mode bit: a chunk whose codes are all zero is stored with no words
 
 R = 512
 NSYM = 1024
@@ -293,9 +294,17 @@ def parse_header(rec: bytes) -> dict:
     u32 = np.frombuffer(rec[:32], dtype="<u4")
     step = float(np.frombuffer(rec[32:40], dtype="<f8")[0])
     lo, hi = (int(x) for x in np.frombuffer(rec[40:56], dtype="<u8"))
+    flags = int(np.frombuffer(rec[56:60], dtype="<u4")[0])
     return dict(magic=int(u32[0]), slice_log2=int(u32[1]), chunk_log2=int(u32[2]), n_used=int(u32[3]),
                 n_chunks=int(u32[4]), n_words=int(u32[5]), n_escapes=int(u32[6]), total=int(u32[7]),
-                step=step, sumsq=(hi << 64) | lo)
+                step=step, sumsq=(hi << 64) | lo, flags=flags)
+
+
+def chunk_offsets(rec: bytes) -> np.ndarray:
+    """The n_chunks + 1 word offsets of a record's chunks."""
+    h = parse_header(rec)
+    o = 64 + ((2 * h["n_used"] + 3) & ~3)
+    return np.frombuffer(rec[o:o + 4 * (h["n_chunks"] + 1)], dtype="<u4").astype(np.int64)
 
 
 def symtab(rec: bytes) -> List[Tuple[int, int]]:

@@ -74,6 +74,15 @@ static void cmac(double ur, double ui, double ar, double ai, double *cr, double 
  * the bound check and the norm stay FP64, applied to the FP32 values. */
 #define ORC_FP32 2u
 
+/* Zero chunks (mode bit ORC_ZERO_CHUNKS; an extension toward the paper's
+ * remark that other compressors may suit the state better, Section V): a
+ * chunk whose codes p are all zero -- every symbol the zero difference R --
+ * is stored with no words; its offset repeats.  The histogram, and so the
+ * code, still counts its symbols.  Header word 14 bit 0 marks such records.
+ * (A one-symbol code has no bits at all, so there every chunk is empty and
+ * decodes to that symbol.) */
+#define ORC_ZERO_CHUNKS 8u
+
 static double r32(double x) { return (double)(float)x; }
 
 static void cmac_m(int fp32, double ur, double ui, double ar, double ai, double *cr, double *ci) {
@@ -387,7 +396,8 @@ typedef struct {
 
 /* Compress one slice (Re plane then Im plane, L values each).
  * mode bit 0: 0 = absolute bound eb, 1 = relative bound eb (bit 1, ORC_FP32, does not
- * change the compressor: the values it gets are then FP32 numbers).
+ * change the compressor: the values it gets are then FP32 numbers); ORC_ZERO_CHUNKS:
+ * all-zero chunks take no words.
  * On success *out is a malloc'ed record of *out_len bytes. */
 int orc_compress_slice(const double *re, const double *im, int slice_log2, int chunk_log2, double eb,
                        uint32_t mode, uint8_t **out, uint64_t *out_len, orc_cstats *st) {
@@ -478,13 +488,17 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
     free(v); free(p); free(d); free(sym); free(cbits); free(coff);
     return ORC_ENOMEM;
   }
+  const int zc = (mode & ORC_ZERO_CHUNKS) != 0;
   for (uint64_t c = 0; c < nchunks; c++) {
     uint64_t bits = 0;
+    int all_zero = 1;
     for (uint64_t j = 0; j < B; j++) {
       uint64_t i = c * B + j;
       bits += lens[sym[i]];
       if (sym[i] == 0) bits += ORC_ESC_LEN_BITS + (uint64_t)bitlen(zigzag(d[i]));
+      if (sym[i] != ORC_R) all_zero = 0;
     }
+    if (zc && all_zero) bits = 0;
     cbits[c] = bits;
     coff[c + 1] = coff[c] + (bits + 31) / 32;
   }
@@ -511,7 +525,7 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
   wrf64(rec + 32, step);
   wr64(rec + 40, (uint64_t)sumsq);
   wr64(rec + 48, (uint64_t)(sumsq >> 64));
-  wr32(rec + 56, 0);
+  wr32(rec + 56, zc ? 1u : 0u);
   wr32(rec + 60, 0);
   /* symbol table in canonical order: by code length, then by symbol */
   uint8_t *tab = rec + ORC_HDR;
@@ -532,6 +546,7 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
     return ORC_ENOMEM;
   }
   for (uint64_t c = 0; c < nchunks; c++) {
+    if (cbits[c] == 0) continue; /* a zero chunk, or a one-symbol code */
     bitw bw;
     bw.words = words + coff[c];
     bw.pos = 0;
@@ -564,7 +579,7 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
 /* ----------------------------------------------------------- decompressor */
 
 typedef struct {
-  uint32_t slice_log2, chunk_log2, n_used, n_chunks, n_words, n_escapes, total;
+  uint32_t slice_log2, chunk_log2, n_used, n_chunks, n_words, n_escapes, total, flags;
   double step;
   uint64_t sumsq_lo, sumsq_hi;
   const uint8_t *symtab;
@@ -584,6 +599,8 @@ int orc_parse(const uint8_t *rec, uint64_t len, orc_rec *h) {
   h->step = rdf64(rec + 32);
   h->sumsq_lo = rd64(rec + 40);
   h->sumsq_hi = rd64(rec + 48);
+  h->flags = rd32(rec + 56);
+  if (h->flags > 1 || rd32(rec + 60) != 0) return ORC_ECORRUPT;
   if (h->slice_log2 > 26 || h->chunk_log2 > h->slice_log2) return ORC_ECORRUPT;
   if (h->n_chunks != (uint32_t)((2ull << h->slice_log2) >> h->chunk_log2)) return ORC_ECORRUPT;
   if (h->n_used < 1 || h->n_used > ORC_NSYM) return ORC_ECORRUPT;
@@ -672,6 +689,11 @@ int orc_decode_p(const uint8_t *rec, uint64_t len, int64_t *p) {
   for (uint64_t c = 0; c < h.n_chunks; c++) {
     uint32_t w0 = rd32(h.offs + 4 * c), w1 = rd32(h.offs + 4 * (c + 1));
     if (w1 < w0 || w1 > h.n_words) return ORC_ECORRUPT;
+    if (w1 == w0 && h.n_used > 1) { /* an empty chunk under a real code: all zero */
+      if (!(h.flags & 1)) return ORC_ECORRUPT;
+      for (uint64_t j = 0; j < B; j++) p[c * B + j] = 0;
+      continue;
+    }
     bitr br;
     br.w = (const uint32_t *)(h.words + 4 * (uint64_t)w0);
     br.nw = w1 - w0;
