@@ -53,6 +53,11 @@ extern "C" {
                             as one dense block per pass (see sim_plan); blocks of 3 or more
                             qubits run on FP64 matrix cores */
 
+#define SIM_ZERO_CHUNKS 0x8u /* a chunk whose codes are all zero is stored with no words (an
+                                extension for sparse states; header word 14 bit 0 marks such
+                                records).  Codes, amplitudes and norms are those of the mode
+                                without it; only record sizes shrink */
+
 #define SIM_FUSE_MAX 5   /* widest fused block, in qubits */
 
 /* ---- gate kinds */

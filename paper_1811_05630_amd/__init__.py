@@ -26,6 +26,7 @@ SIM_EB_ABS = 0x0
 SIM_EB_REL = 0x1
 SIM_FP32 = 0x2
 SIM_FUSED = 0x4
+SIM_ZERO_CHUNKS = 0x8
 GATE_DENSE = 1
 GATE_PHASE = 2
 
@@ -267,17 +268,11 @@ class Sim:
 
     def __init__(self, n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False,
                  chunk_log2: int = 0, workspace_bytes: int = 0, use_torch: Optional[bool] = None,
-                 arena_bytes: int = 0, fused: bool = False, fp32: bool = False):
+                 arena_bytes: int = 0, fused: bool = False, fp32: bool = False, zero_chunks: bool = False):
         L = lib()
-        cfg = ConfigStruct()
-        cfg.n_qubits = n_qubits
-        cfg.slice_log2 = slice_log2
-        cfg.chunk_log2 = chunk_log2
-        cfg.error_bound = error_bound
-        cfg.mode = ((SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0) |
-                    (SIM_FP32 if fp32 else 0))
-        cfg.workspace_bytes = workspace_bytes
-        cfg.arena_bytes = arena_bytes
+        cfg = _config(n_qubits, slice_log2, error_bound, relative=relative, chunk_log2=chunk_log2,
+                      workspace_bytes=workspace_bytes, arena_bytes=arena_bytes, fused=fused, fp32=fp32,
+                      zero_chunks=zero_chunks)
         self._mem = None
         if use_torch is None:
             use_torch = _torch_ready()
@@ -293,6 +288,7 @@ class Sim:
         self.n, self.slice_log2, self.error_bound, self.relative = n_qubits, slice_log2, error_bound, relative
         self.fused = fused
         self.fp32 = fp32
+        self.zero_chunks = zero_chunks
         self.chunk_log2 = min(chunk_log2 or 10, slice_log2)
 
     def close(self):
@@ -429,13 +425,15 @@ class Graph:
 
 
 def _config(n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False, chunk_log2: int = 0,
-            workspace_bytes: int = 0, arena_bytes: int = 0, fused: bool = False, fp32: bool = False) -> ConfigStruct:
+            workspace_bytes: int = 0, arena_bytes: int = 0, fused: bool = False, fp32: bool = False,
+            zero_chunks: bool = False) -> ConfigStruct:
     cfg = ConfigStruct()
     cfg.n_qubits = n_qubits
     cfg.slice_log2 = slice_log2
     cfg.chunk_log2 = chunk_log2
     cfg.error_bound = error_bound
-    cfg.mode = ((SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0) | (SIM_FP32 if fp32 else 0))
+    cfg.mode = ((SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0) | (SIM_FP32 if fp32 else 0) |
+                (SIM_ZERO_CHUNKS if zero_chunks else 0))
     cfg.workspace_bytes = workspace_bytes
     cfg.arena_bytes = arena_bytes
     return cfg

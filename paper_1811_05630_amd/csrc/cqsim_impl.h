@@ -96,6 +96,8 @@ struct Geo {
   int chunk_log2;
   uint32_t nchunks;       // 2L / B
   uint64_t L;
+  uint32_t zero_chunks;   // SIM_ZERO_CHUNKS: all-zero chunks are stored with no words
+  uint32_t zero_in;       // the stored records may hold zero chunks (the mode, or an imported record)
 };
 
 // Per-slot scratch of one batch of decompressed slices.

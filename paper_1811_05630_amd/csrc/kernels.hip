@@ -409,11 +409,11 @@ struct BitReader {
 
 // The chunks of one workgroup (after the record checks).  FULL: chunks of at
 // least 32 values and a whole number of workgroups of chunks per slot (every
-// lane active, whole rounds).
-template <bool FULL, bool C32>
+// lane active, whole rounds).  ZC: the records may hold zero chunks.
+template <bool FULL, bool C32, bool ZC>
 __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, const StateMeta &cur, uint64_t slice,
                                               uint32_t u, const uint32_t *offs, uint32_t nchunks, uint32_t n_words,
-                                              double k, uint32_t *dtab, uint8_t *stg,
+                                              uint32_t n_used, double k, uint32_t *dtab, uint8_t *stg,
                                               uint32_t (*pf)[64 * kDecWaves], Ctl *ctl, uint32_t pass) {
   using F = DecFmt<C32>;
   using T = typename F::T;
@@ -435,6 +435,10 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
       br.nw = w1 - w0;
     }
   }
+  // an empty chunk under a code of two or more symbols is a zero chunk (a
+  // one-symbol code has no bits: its chunks are empty and decode normally)
+  const bool zero = ZC && active && br.nw == 0 && n_used > 1;
+  constexpr uint32_t kZeroPair = (uint32_t)kR | ((uint32_t)kR << 14) | (1u << 28);  // dtab_entry(R, 0, R, 0, true)
   br.w = offs + (nchunks + 1) + w0;
   br.wi = 0;
   br.buf = 0;
@@ -471,7 +475,8 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
     if (active) {
       for (uint32_t q = 0; q < R;) {
         br.refill1(pf, tid);
-        const uint32_t e = dtab[(uint32_t)(br.buf >> (64 - kLMax))];
+        // a zero chunk reads two zero differences of no bits per step
+        const uint32_t e = (ZC && zero) ? kZeroPair : dtab[(uint32_t)(br.buf >> (64 - kLMax))];
         const uint32_t sym = e & 1023u;
         if (sym == 0) {  // escape (never part of a two-symbol entry)
           const uint32_t len = (e >> 10) & 15u;
@@ -532,7 +537,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   }
 }
 
-template <bool FULL>
+template <bool FULL, bool ZC>
 __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
                                                            const uint8_t *arena, StateMeta cur, const double *kscale,
                                                            Ctl *ctl, uint32_t pass, int compact_ok) {
@@ -557,10 +562,11 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
   const uint32_t sym_bytes = (2 * n_used + 3) & ~3u;
   const uint32_t *offs = (const uint32_t *)(rec + kHdr + sym_bytes);
   if (c32)
-    decode_chunks<FULL, true>(sl, g, cur, slice, u, offs, nchunks, n_words, 0.0, dtab, stg, pf, ctl, pass);
+    decode_chunks<FULL, true, ZC>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, 0.0, dtab, stg, pf, ctl,
+                                  pass);
   else
-    decode_chunks<FULL, false>(sl, g, cur, slice, u, offs, nchunks, n_words, kscale[slice], dtab, stg, pf, ctl,
-                               pass);
+    decode_chunks<FULL, false, ZC>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, kscale[slice], dtab, stg,
+                                   pf, ctl, pass);
 }
 
 // ------------------------------------------------------------ gate + quantise
@@ -2433,19 +2439,19 @@ __device__ __forceinline__ void put_field(uint32_t *lw, uint64_t v, int n, uint6
 
 constexpr int kEncWaves = 4;  // coding wavefronts; one more stores
 
-// Symbols j .. j + 3 of a chunk of B values (1 past the end, never coded).
+// Symbols j .. j + 3 of a chunk of B values (the zero difference R past the end, never coded).
 __device__ __forceinline__ uint2 enc_syms(const uint16_t *sym, uint64_t j, uint64_t B) {
   if (j + 3 < B) return *(const uint2 *)(sym + j);  // four aligned symbols in one load
   uint32_t t[4];
 #pragma unroll
-  for (int k = 0; k < 4; k++) t[k] = j + k < B ? sym[j + k] : 1u;
+  for (int k = 0; k < 4; k++) t[k] = j + k < B ? sym[j + k] : (uint32_t)kR;
   return make_uint2(t[0] | (t[1] << 16), t[2] | (t[3] << 16));
 }
 
 // Chunks [cb, ce) of slot blockIdx.y; coding wavefront w takes chunks cb + w,
 // cb + w + 4, ...; every wavefront runs the same number of rounds so that
 // barriers line up.  STEPS = ceil(B / 256) steps of 256 symbols per chunk.
-template <int STEPS>
+template <int STEPS, bool ZC>
 __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_encode(Slots sl, Geo g, uint32_t chunks_per_block,
                                                                     const Ctl *ctl) {
   if (ctl->flags) return;
@@ -2515,6 +2521,7 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       const uint64_t B = active ? Bc : 0;
       uint32_t *lw = lw_all + (uint64_t)(buf * kEncWaves + wave) * W;
       uint64_t run = 0;  // the buffer lw is all zero (cleared by the store wavefront)
+      bool nz = false;   // zero-chunk records: a symbol other than the zero difference
 #pragma unroll
       for (int i = 0; i < STEPS; i++) {
         const uint64_t j = (uint64_t)i * 256 + 4 * (uint64_t)lane;
@@ -2537,6 +2544,10 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
           any = any || esc[k];
           z[k] = 0;
           nb[k] = 0;
+        }
+        if (ZC) {  // positions past the chunk's end hold the zero difference
+          constexpr uint32_t kRR = (uint32_t)kR | ((uint32_t)kR << 16);
+          nz = nz || cur[i].x != kRR || cur[i].y != kRR;
         }
         const bool wave_esc = __ballot(any) != 0;
         if (wave_esc) {
@@ -2587,6 +2598,10 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       }
       uint32_t nw = (uint32_t)((run + 31) >> 5);
       if (nw > W) nw = W;  // at most 68 bits per value: never reached by a consistent codebook
+      if (ZC && __ballot(nz) == 0) {  // zero-chunk records: an all-zero chunk keeps no words
+        for (uint32_t i = lane; i < nw; i += 64) lw[i] = 0;  // after the lanes' writes (LDS in order)
+        nw = 0;
+      }
       if (lane == 0) cnw[buf][wave] = active ? nw : 0u;
 #pragma unroll
       for (int i = 0; i < STEPS; i++) {
@@ -2686,7 +2701,7 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
     *(double *)(rec + 32) = step;
     *(uint64_t *)(rec + 40) = sq_lo;
     *(uint64_t *)(rec + 48) = sq_hi;
-    h32[14] = 0;
+    h32[14] = g.zero_chunks ? 1u : 0u;  // empty chunks are zero chunks
     h32[15] = 0;
     nxt.rec_off[slice] = off;
     nxt.rec_len[slice] = h32[7];
@@ -2832,10 +2847,18 @@ void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
   dim3 grid(grid1(g.nchunks, per_wg), (unsigned)nslots);
   const bool full = (1ull << g.chunk_log2) >= (uint64_t)DecFmt<true>::R && g.nchunks % per_wg == 0;
   const int c = compact ? 1 : 0;
-  if (full)
-    CQ_LAUNCH(k_decode<true>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c);
-  else
-    CQ_LAUNCH(k_decode<false>, grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c);
+  if (g.zero_in) {
+    if (full)
+      CQ_LAUNCH((k_decode<true, true>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c);
+    else
+      CQ_LAUNCH((k_decode<false, true>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass,
+                c);
+  } else if (full) {
+    CQ_LAUNCH((k_decode<true, false>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c);
+  } else {
+    CQ_LAUNCH((k_decode<false, false>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass,
+              c);
+  }
 }
 
 static int gate_kind(const GateDesc &gd) {
@@ -3002,26 +3025,36 @@ static uint32_t enc_chunks_per_block(const Geo &g, int nslots) {
   return (uint32_t)cpb;
 }
 
-void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
+template <bool ZC>
+void launch_encode_zc(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
   const uint32_t cpb = enc_chunks_per_block(g, nslots);
   dim3 grid(grid1(g.nchunks, cpb), (unsigned)nslots);
   const size_t shm = (size_t)2 * kEncWaves * sl.stage_words * 4;
   const dim3 block(64 * (kEncWaves + 1));
   if (g.chunk_log2 <= 8) {
-    CQ_LAUNCH(k_encode<1>, grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH((k_encode<1, ZC>), grid, block, shm, st, sl, g, cpb, ctl);
     return;
   }
-  // dynamic LDS above the default needs the attribute (chunks of 1024: ~70 KB)
-  static size_t shm_set = 0;
-  if (shm > shm_set) {
-    (void)hipFuncSetAttribute((const void *)k_encode<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    (void)hipFuncSetAttribute((const void *)k_encode<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    shm_set = shm;
-  }
+  // dynamic LDS above the default needs the attribute: set once to the
+  // largest request (chunks of 1024 values, ~70 KB)
+  static const bool attrs = [] {
+    const int most = (int)(2 * kEncWaves * stage_words_for(10) * 4);
+    (void)hipFuncSetAttribute((const void *)k_encode<4, ZC>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    (void)hipFuncSetAttribute((const void *)k_encode<2, ZC>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    return true;
+  }();
+  (void)attrs;
   if (g.chunk_log2 == 9)
-    CQ_LAUNCH(k_encode<2>, grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH((k_encode<2, ZC>), grid, block, shm, st, sl, g, cpb, ctl);
   else
-    CQ_LAUNCH(k_encode<4>, grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH((k_encode<4, ZC>), grid, block, shm, st, sl, g, cpb, ctl);
+}
+
+void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
+  if (g.zero_chunks)
+    launch_encode_zc<true>(st, sl, g, nslots, ctl);
+  else
+    launch_encode_zc<false>(st, sl, g, nslots, ctl);
 }
 
 void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
