@@ -250,6 +250,19 @@ int sim_graph_create(sim_t *sim, const sim_gate *gates, size_t n, sim_graph_t **
 int sim_graph_launch(sim_t *sim, sim_graph_t *graph, size_t *n_applied);
 void sim_graph_destroy(sim_graph_t *graph);
 
+/* Chunk-length autotuning (B = 2^chunk_log2 values per coded chunk is a format
+ * parameter, recorded in every record header).  For each chunk_log2 in
+ * [lo, hi] (within 1..10) a fresh handle of configuration *cfg (its
+ * chunk_log2 ignored) applies gates[0..n): the first n/4 untimed, the rest
+ * timed on the device as in sim_apply.  *best receives the fastest (ties: the
+ * smaller record total); ms_per_gate[k] and bytes[k] (each hi - lo + 1
+ * entries, or NULL) receive the timed milliseconds per gate and the record
+ * total after the program for chunk_log2 = lo + k.  Every handle is destroyed
+ * before the call returns.  Errors: SIM_EINVAL (range, n < 2), and any error
+ * of creating or running a candidate. */
+int sim_tune_chunk(const sim_config *cfg, const sim_gate *gates, size_t n, int lo, int hi, int *best,
+                   double *ms_per_gate, uint64_t *bytes);
+
 /* Device time (milliseconds, summed since the last reset) spent in each of
  * the library's kernel classes, measured with HIP events on the handle's
  * stream when enabled.  `names` receives a static comma-separated list of the

@@ -37,7 +37,8 @@ EXPORTS = ("sim_create", "sim_create_ex", "sim_destroy", "sim_last_error", "sim_
            "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_amplitudes", "sim_probabilities", "sim_stats",
            "sim_record_size", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan",
            "sim_graph_create", "sim_graph_launch", "sim_graph_destroy", "sim_footprint",
-           "srv_create", "srv_submit", "srv_wait", "srv_clock", "srv_projected_bytes", "srv_destroy")
+           "sim_tune_chunk", "srv_create", "srv_submit", "srv_wait", "srv_clock", "srv_projected_bytes",
+           "srv_destroy")
 
 SRV_INIT_ZERO, SRV_INIT_BASIS, SRV_INIT_PRODUCT = 0, 1, 2
 SRV_FAMILIES = 16
@@ -135,6 +136,8 @@ def lib():
         L.sim_plan.argtypes = [C.c_int, C.POINTER(GateStruct), C.c_size_t, C.POINTER(PassStruct), C.c_size_t,
                                C.POINTER(C.c_size_t)]
         L.sim_footprint.argtypes = [C.POINTER(ConfigStruct), C.POINTER(C.c_uint64)]
+        L.sim_tune_chunk.argtypes = [C.POINTER(ConfigStruct), C.POINTER(GateStruct), C.c_size_t, C.c_int, C.c_int,
+                                     C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.srv_create.argtypes = [C.c_uint64, C.c_int, C.POINTER(P)]
         L.srv_submit.argtypes = [P, C.POINTER(SrvJobStruct), C.POINTER(C.c_uint64)]
         L.srv_wait.argtypes = [P, C.POINTER(SrvDoneStruct), C.c_size_t, C.POINTER(C.c_size_t), C.c_double]
@@ -445,6 +448,20 @@ def footprint(n_qubits: int, slice_log2: int, error_bound: float, **kw) -> int:
     _check(lib().sim_footprint(C.byref(_config(n_qubits, slice_log2, error_bound, **kw)), C.byref(b)),
            "sim_footprint")
     return b.value
+
+
+def tune_chunk(n_qubits: int, slice_log2: int, error_bound: float, gates: Sequence, lo: int = 5, hi: int = 10,
+               **kw) -> Tuple[int, dict]:
+    """sim_tune_chunk: the fastest chunk_log2 in [lo, hi] for this
+    configuration and gate sample, and {chunk_log2: (ms per gate, record bytes)}."""
+    cfg = _config(n_qubits, slice_log2, error_bound, **kw)
+    ptr, cnt, keep = _gate_ptr(gates)
+    k = hi - lo + 1
+    ms = (C.c_double * max(k, 1))()  # a bad range is refused by the library
+    by = (C.c_uint64 * max(k, 1))()
+    best = C.c_int()
+    _check(lib().sim_tune_chunk(C.byref(cfg), ptr, cnt, lo, hi, C.byref(best), ms, by), "sim_tune_chunk")
+    return best.value, {lo + i: (ms[i], by[i]) for i in range(k)}
 
 
 class Server:

@@ -1043,6 +1043,40 @@ void sim_graph_destroy(sim_graph_t *G) {
   delete G;
 }
 
+int sim_tune_chunk(const sim_config *cfg, const sim_gate *gates, size_t n, int lo, int hi, int *best,
+                   double *ms_per_gate, uint64_t *bytes) {
+  if (!cfg || !best || (n && !gates)) return set_err(SIM_EINVAL, "null argument");
+  if (n < 2) return set_err(SIM_EINVAL, "tuning needs at least two gates");
+  if (lo < 1 || hi > 10 || lo > hi) return set_err(SIM_EINVAL, "chunk range %d..%d outside 1..10", lo, hi);
+  *best = 0;
+  double best_ms = 0.0;
+  uint64_t best_bytes = 0;
+  const size_t warm = n / 4 ? n / 4 : 1;  // first passes untimed (arena growth, first launches)
+  for (int cl = lo; cl <= hi; cl++) {
+    sim_config c = *cfg;
+    c.chunk_log2 = cl;
+    sim_t *s = nullptr;
+    int rc = sim_create_ex(&c, &s);
+    size_t done = 0;
+    if (!rc) rc = sim_apply(s, gates, warm, &done);
+    double t0 = s ? s->elapsed : 0.0;
+    if (!rc) rc = sim_apply(s, gates + warm, n - warm, &done);
+    sim_stats_t st;
+    if (!rc) rc = sim_stats(s, &st);
+    const double ms = rc ? 0.0 : (s->elapsed - t0) * 1e3 / (double)(n - warm);
+    sim_destroy(s);
+    if (rc) return rc;
+    if (ms_per_gate) ms_per_gate[cl - lo] = ms;
+    if (bytes) bytes[cl - lo] = st.compressed_bytes;
+    if (*best == 0 || ms < best_ms || (ms == best_ms && st.compressed_bytes < best_bytes)) {
+      *best = cl;
+      best_ms = ms;
+      best_bytes = st.compressed_bytes;
+    }
+  }
+  return SIM_OK;
+}
+
 int sim_graph_create(sim_t *s, const sim_gate *gates, size_t n, sim_graph_t **out) {
   if (!out) return set_err(SIM_EINVAL, "null argument");
   *out = nullptr;
