@@ -35,16 +35,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # the reading of the same counter for the copy probe.  Valid only for the
 # kernel source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
-    "gate_quant": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
-                  "bytes_per_launch": 225129317},
-    "decode": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
-              "bytes_per_launch": 151137667},
-    "encode": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
-              "bytes_per_launch": 83539651},
-    "codebook": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
-                "bytes_per_launch": 5822720},
-    "finish": {"kernels_sha256": "c9a2259ad3ff9be40ebb1f243d03a23424ecaf0aa2b2f113c54f0c67aa610ecb",
-              "bytes_per_launch": 10031899},
+    "gate_quant": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
+                  "bytes_per_launch": 225156315},
+    "decode": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
+              "bytes_per_launch": 151205474},
+    "encode": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
+              "bytes_per_launch": 83541733},
+    "codebook": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
+                "bytes_per_launch": 5848601},
+    "finish": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
+              "bytes_per_launch": 10036029},
 }
 
 
