@@ -443,11 +443,6 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   br.wi = 0;
   br.buf = 0;
   br.nbits = 0;
-  {
-    const uint4 *src = (const uint4 *)(cur.dtab + slice * (1u << kLMax));
-    uint4 *dst = (uint4 *)dtab;
-    for (uint32_t i = tid; i < (1u << kLMax) / 4; i += 64 * kDecWaves) dst[i] = src[i];
-  }
   // words [from, from + PF) of the chunk; the address of a word past the
   // end is replaced by a valid one (the load is always issued)
   uint32_t nx[PF];
@@ -545,11 +540,21 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
   // compact workspace: the int32 codes q themselves (every |q| < 2^31), the
   // gate kernel multiplies by the slice's scale; else the FP64 values q * k
   const bool c32 = compact_ok && !ctl->wide;
-  __shared__ uint32_t dtab[1 << kLMax];
+  __shared__ __align__(16) uint32_t dtab[1 << kLMax];
   __shared__ __align__(16) uint8_t stg[kDecWaves * kDecStage];
   __shared__ uint32_t pf[kDecPfMax][64 * kDecWaves];
   const uint32_t u = blockIdx.y, tid = threadIdx.x;
   const uint64_t slice = slot_slice[u];
+  // the slice's decoder table (16 KiB, its own buffer): its loads go out
+  // with the record header's, and reach LDS before decode_chunks' barrier
+  constexpr uint32_t kT = 64 * kDecWaves, kN = (1u << kLMax) / 4 / kT;
+  static_assert(kN * kT == (1u << kLMax) / 4, "whole uint4 rows per thread");
+  uint4 dt[kN];
+  {
+    const uint4 *src = (const uint4 *)(cur.dtab + slice * (1u << kLMax));
+#pragma unroll
+    for (uint32_t k = 0; k < kN; k++) dt[k] = src[tid + k * kT];
+  }
   const uint8_t *rec = arena + cur.rec_off[slice];
   const uint32_t n_used = ld32(rec + 12);
   const uint32_t nchunks = ld32(rec + 16);
@@ -559,6 +564,8 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
     if (tid == 0) fail(ctl, kFlagCorrupt, pass);
     return;
   }
+#pragma unroll
+  for (uint32_t k = 0; k < kN; k++) ((uint4 *)dtab)[tid + k * kT] = dt[k];
   const uint32_t sym_bytes = (2 * n_used + 3) & ~3u;
   const uint32_t *offs = (const uint32_t *)(rec + kHdr + sym_bytes);
   if (c32)
@@ -2456,14 +2463,16 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
                                                                     const Ctl *ctl) {
   if (ctl->flags) return;
   extern __shared__ uint32_t lw_all[];  // [2][kEncWaves][stage_words]
-  __shared__ uint32_t codes[kNSym];
+  __shared__ __align__(16) uint32_t codes[kNSym];
   __shared__ uint32_t cnw[2][kEncWaves];  // words of each coded chunk
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
   const uint32_t u = blockIdx.y;
   const uint32_t cb = blockIdx.x * chunks_per_block;
   const uint32_t ce = cb + chunks_per_block < g.nchunks ? cb + chunks_per_block : g.nchunks;
   const uint32_t W = sl.stage_words;
-  for (uint32_t s = threadIdx.x; s < (uint32_t)kNSym; s += blockDim.x) codes[s] = sl.codes[(uint64_t)u * kNSym + s];
+  static_assert(64 * (kEncWaves + 1) >= kNSym / 4, "one uint4 of the code table per thread");
+  if (threadIdx.x < (uint32_t)kNSym / 4)  // the code table with one load per thread
+    ((uint4 *)codes)[threadIdx.x] = ((const uint4 *)(sl.codes + (uint64_t)u * kNSym))[threadIdx.x];
   // chunk buffers start cleared; afterwards the store wavefront clears the
   // words it copies out
   for (uint32_t i = threadIdx.x; i < 2u * kEncWaves * sl.stage_words; i += blockDim.x) lw_all[i] = 0;
