@@ -2657,23 +2657,60 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
                                                 uint32_t cpb, Ctl *ctl, uint32_t pass) {
   if (ctl->flags) return;
   __shared__ uint64_t s64[16];
-  const uint32_t u = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+  const uint32_t u = blockIdx.y, b = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
   const uint32_t nch = g.nchunks;
+  const uint32_t cb = b * cpb, ce = cb + cpb < nch ? cb + cpb : nch;
+  // Every load whose address is known at entry goes out before the first
+  // wait: the first element of each loop below, this block's first staged
+  // words (up to kU per thread, within the block's staging region), the arena
+  // position and, for block 0, the slot's header fields and symbol table.
+  constexpr uint32_t kU = 8;
+  const uint32_t *src = sl.stage + ((uint64_t)u * nch + cb) * sl.stage_words;
+  const uint64_t region = (uint64_t)(ce - cb) * sl.stage_words;
+  uint32_t sw[kU];
+#pragma unroll
+  for (uint32_t k = 0; k < kU; k++) {
+    const uint64_t i = (uint64_t)k * T + tid;
+    sw[k] = i < region ? src[i] : 0u;
+  }
+  const uint32_t nu0 = tid < (uint32_t)nslots ? sl.nused[tid] : 0u;
+  const uint32_t wd0 = tid < (uint32_t)nslots ? sl.words[tid] : 0u;
+  const uint32_t *bw = sl.blk_words + (uint64_t)u * kMaxEncBlocks;
+  const uint32_t bw0 = tid < b ? bw[tid] : 0u;
+  const uint32_t *cw = sl.chunk_words + (uint64_t)u * nch;
+  const uint32_t cw0 = cb + tid < ce ? cw[cb + tid] : 0u;
+  const uint32_t nw = bw[b];
+  const uint64_t base = ctl->bump;
+  const uint32_t n_used = sl.nused[u], words = sl.words[u];
+  uint2 tab0 = make_uint2(0, 0);  // symbol table entries 4 tid .. 4 tid + 3 (block 0)
+  uint32_t nesc = 0;
+  uint64_t sq_lo = 0, sq_hi = 0, slice = 0;
+  double qstep = 0.0;
+  if (b == 0) {
+    if (4 * tid < (uint32_t)kNSym) tab0 = ((const uint2 *)(sl.symtab + (uint64_t)u * kNSym))[tid];
+    if (tid == 0) {
+      nesc = sl.nesc[u];
+      sq_lo = sl.sq[2 * u];
+      sq_hi = sl.sq[2 * u + 1];
+      slice = slot_slice[u];
+      if (qp.rel) qstep = sl.qstep[3 * u];
+    }
+  }
+  // record sizes of the batch (slot order) and this slot's offset among them
   uint64_t pre = 0, tot = 0, ex = 0;
-  for (int v = tid; v < nslots; v += blockDim.x) {
-    const uint64_t bytes = rec_bytes(sl.nused[v], nch, sl.words[v]);
+  for (uint32_t v = tid; v < (uint32_t)nslots; v += T) {
+    const uint64_t bytes = v == tid ? rec_bytes(nu0, nch, wd0) : rec_bytes(sl.nused[v], nch, sl.words[v]);
     const uint64_t ba = (bytes + kRecAlign - 1) & ~(kRecAlign - 1);
     tot += ba;
     ex += bytes;
-    if ((uint32_t)v < u) pre += ba;
+    if (v < u) pre += ba;
   }
   pre = block_sum64(pre, s64);
   tot = block_sum64(tot, s64);
   ex = block_sum64(ex, s64);
   uint64_t bp = 0;  // words of the slot's earlier blocks
-  for (uint32_t i = tid; i < b; i += blockDim.x) bp += sl.blk_words[(uint64_t)u * kMaxEncBlocks + i];
+  for (uint32_t i = tid; i < b; i += T) bp += i == tid ? bw0 : bw[i];
   bp = block_sum64(bp, s64);
-  const uint64_t base = ctl->bump;
   if (base + tot > cap) {
     if (tid == 0 && b == 0 && u == 0) fail(ctl, kFlagOverflow, pass);
     return;
@@ -2684,20 +2721,18 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
   }
   const uint64_t off = base + pre;
   uint8_t *rec = arena + off;
-  const uint32_t n_used = sl.nused[u], words = sl.words[u];
   uint32_t *offs = (uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
   uint32_t *stream = offs + nch + 1;
-  const uint32_t cb = b * cpb, ce = cb + cpb < nch ? cb + cpb : nch;
-  for (uint32_t c = cb + tid; c < ce; c += blockDim.x)
-    offs[c] = (uint32_t)bp + sl.chunk_words[(uint64_t)u * nch + c];
-  const uint32_t nw = sl.blk_words[(uint64_t)u * kMaxEncBlocks + b];
-  const uint32_t *src = sl.stage + ((uint64_t)u * nch + cb) * sl.stage_words;
-  for (uint32_t i = tid; i < nw; i += blockDim.x) stream[bp + i] = src[i];
+  for (uint32_t c = cb + tid; c < ce; c += T) offs[c] = (uint32_t)bp + (c == cb + tid ? cw0 : cw[c]);
+#pragma unroll
+  for (uint32_t k = 0; k < kU; k++) {
+    const uint32_t i = k * T + tid;
+    if (i < nw) stream[bp + i] = sw[k];
+  }
+  for (uint32_t i = kU * T + tid; i < nw; i += T) stream[bp + i] = src[i];
   if (b != 0) return;
-  const uint64_t slice = slot_slice[u];
-  const double step = qp.rel ? sl.qstep[3 * u] : qp.step;
+  const double step = qp.rel ? qstep : qp.step;
   if (tid == 0) {
-    const uint64_t sq_lo = sl.sq[2 * u], sq_hi = sl.sq[2 * u + 1];
     uint32_t *h32 = (uint32_t *)rec;
     h32[0] = kMagic;
     h32[1] = (uint32_t)g.slice_log2;
@@ -2705,7 +2740,7 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
     h32[3] = n_used;
     h32[4] = nch;
     h32[5] = words;
-    h32[6] = sl.nesc[u];
+    h32[6] = nesc;
     h32[7] = (uint32_t)rec_bytes(n_used, nch, words);
     *(double *)(rec + 32) = step;
     *(uint64_t *)(rec + 40) = sq_lo;
@@ -2719,8 +2754,14 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
     nxt.sq[2 * slice + 1] = sq_hi;
     offs[nch] = words;
   }
+  // the symbol table, padded with a zero entry to 4 bytes
   uint16_t *tab = (uint16_t *)(rec + kHdr);
-  for (uint32_t i = tid; i < n_used; i += blockDim.x) tab[i] = sl.symtab[(uint64_t)u * kNSym + i];
+  const uint32_t e[4] = {tab0.x & 0xffffu, tab0.x >> 16, tab0.y & 0xffffu, tab0.y >> 16};
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) {
+    const uint32_t i = 4 * tid + k;
+    if (i < n_used) tab[i] = (uint16_t)e[k];
+  }
   if (tid == 0 && (n_used & 1)) tab[n_used] = 0;
 }
 
