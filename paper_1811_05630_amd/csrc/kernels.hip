@@ -2705,12 +2705,26 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
     ex += bytes;
     if (v < u) pre += ba;
   }
-  pre = block_sum64(pre, s64);
-  tot = block_sum64(tot, s64);
-  ex = block_sum64(ex, s64);
   uint64_t bp = 0;  // words of the slot's earlier blocks
   for (uint32_t i = tid; i < b; i += T) bp += i == tid ? bw0 : bw[i];
-  bp = block_sum64(bp, s64);
+  {  // the four block sums at once (4 wavefronts x 4 values in s64)
+    uint64_t x[4] = {pre, tot, ex, bp};
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      for (int off = 32; off > 0; off >>= 1) x[k] += __shfl_xor(x[k], off, 64);
+    if (lane_id() == 0)
+      for (int k = 0; k < 4; k++) s64[4 * (tid >> 6) + k] = x[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      x[k] = 0;
+      for (uint32_t w = 0; w < T / 64; w++) x[k] += s64[4 * w + k];
+    }
+    pre = x[0];
+    tot = x[1];
+    ex = x[2];
+    bp = x[3];
+  }
   if (base + tot > cap) {
     if (tid == 0 && b == 0 && u == 0) fail(ctl, kFlagOverflow, pass);
     return;
