@@ -35,16 +35,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # the reading of the same counter for the copy probe.  Valid only for the
 # kernel source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
-    "gate_quant": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
-                  "bytes_per_launch": 225156315},
-    "decode": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
-              "bytes_per_launch": 151205474},
-    "encode": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
-              "bytes_per_launch": 83541733},
-    "codebook": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
-                "bytes_per_launch": 5848601},
-    "finish": {"kernels_sha256": "7b3a1289eb0b8f9633d3540a8e318cc64b45559ebaf238636d6bf278467fe546",
-              "bytes_per_launch": 10036029},
+    "gate_quant": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
+                  "bytes_per_launch": 225115782},
+    "decode": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
+              "bytes_per_launch": 151174596},
+    "encode": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
+              "bytes_per_launch": 83541010},
+    "codebook": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
+                "bytes_per_launch": 5848645},
+    "finish": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
+              "bytes_per_launch": 15121587},
 }
 
 
