@@ -74,3 +74,29 @@ def test_zero_chunk_records_import_and_checks():
     with pytest.raises(cq.SimError) as e:
         dst.import_record(withempty[0], bytes(bad))
     assert e.value.rc == -4
+
+
+def test_graph_recaptures_when_zero_chunk_records_arrive():
+    """A graph captured with the plain decoder is captured again once the
+    handle holds imported zero-chunk records; it matches sim_apply."""
+    n, sl, cl, eb = 10, 7, 4, 1e-6
+    head = qc.grover(n, 5, 1)[:n + 4]
+    prog = [qc.H(0), qc.H(1)]  # two passes: the graph starts from its own arena parity again
+    say("zero chunks: graph, then imported zero-chunk records")
+    src = cq.Sim(n, sl, eb, chunk_log2=cl, zero_chunks=True)
+    src.apply(head)
+    dst = cq.Sim(n, sl, eb, chunk_log2=cl)
+    ref = cq.Sim(n, sl, eb, chunk_log2=cl)
+    g = dst.graph(prog)
+    assert g.launch() == len(prog)
+    ref.apply(prog)
+    recs = src.records()
+    assert any(empty_chunks(r) and oracle.parse_header(r)["n_used"] > 1 for r in recs)
+    for j, r in enumerate(recs):
+        dst.import_record(j, r)
+        ref.import_record(j, r)
+    assert g.launch() == len(prog)
+    ref.apply(prog)
+    assert np.array_equal(dst.amplitudes().view(np.float64), ref.amplitudes().view(np.float64))
+    assert dst.records() == ref.records()
+    g.close()
