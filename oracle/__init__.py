@@ -21,6 +21,7 @@ ABS = 0
 REL = 1
 FP32 = 2  # mode bit: FP32 working values and gate arithmetic (quantiser and norm stay FP64)
 ZERO_CHUNKS = 8  # mode bit: a chunk whose codes are all zero is stored with no words
+CONST_CHUNKS = 16  # mode bit: a chunk whose values all equal its head keeps only the head (offset bit 31)
 
 R = 512
 NSYM = 1024
@@ -304,7 +305,14 @@ def chunk_offsets(rec: bytes) -> np.ndarray:
     """The n_chunks + 1 word offsets of a record's chunks."""
     h = parse_header(rec)
     o = 64 + ((2 * h["n_used"] + 3) & ~3)
-    return np.frombuffer(rec[o:o + 4 * (h["n_chunks"] + 1)], dtype="<u4").astype(np.int64)
+    return np.frombuffer(rec[o:o + 4 * (h["n_chunks"] + 1)], dtype="<u4").astype(np.int64) & 0x7FFFFFFF
+
+
+def constant_chunks(rec: bytes) -> np.ndarray:
+    """The chunks marked constant (bit 31 of their word offset)."""
+    h = parse_header(rec)
+    o = 64 + ((2 * h["n_used"] + 3) & ~3)
+    return (np.frombuffer(rec[o:o + 4 * h["n_chunks"]], dtype="<u4") >> 31).astype(bool)
 
 
 def symtab(rec: bytes) -> List[Tuple[int, int]]:

@@ -83,6 +83,16 @@ static void cmac(double ur, double ui, double ar, double ai, double *cr, double 
  * decodes to that symbol.) */
 #define ORC_ZERO_CHUNKS 8u
 
+/* Constant chunks (mode bit ORC_CONST_CHUNKS; an extension of the same kind):
+ * a chunk of two or more values whose differences after the head are all zero
+ * (every value equals the head's) keeps only the head's code (and escape);
+ * bit 31 of its word offset marks it, and header word 14 bit 1 marks records
+ * that may hold such chunks.  The histogram still counts every symbol.  With
+ * ORC_ZERO_CHUNKS as well, an all-zero chunk is a zero chunk (no words, no
+ * mark). */
+#define ORC_CONST_CHUNKS 16u
+#define ORC_CONST_MARK 0x80000000u
+
 static double r32(double x) { return (double)(float)x; }
 
 static void cmac_m(int fp32, double ur, double ui, double ar, double ai, double *cr, double *ci) {
@@ -489,16 +499,32 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
     return ORC_ENOMEM;
   }
   const int zc = (mode & ORC_ZERO_CHUNKS) != 0;
+  const int cc = (mode & ORC_CONST_CHUNKS) != 0;
+  uint8_t *cconst = (uint8_t *)calloc(nchunks, 1);
+  if (!cconst) {
+    free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+    return ORC_ENOMEM;
+  }
   for (uint64_t c = 0; c < nchunks; c++) {
-    uint64_t bits = 0;
-    int all_zero = 1;
+    uint64_t bits = 0, head_bits = 0;
+    int all_zero = 1, rest_zero = 1;
     for (uint64_t j = 0; j < B; j++) {
       uint64_t i = c * B + j;
-      bits += lens[sym[i]];
-      if (sym[i] == 0) bits += ORC_ESC_LEN_BITS + (uint64_t)bitlen(zigzag(d[i]));
-      if (sym[i] != ORC_R) all_zero = 0;
+      uint64_t b = lens[sym[i]];
+      if (sym[i] == 0) b += ORC_ESC_LEN_BITS + (uint64_t)bitlen(zigzag(d[i]));
+      bits += b;
+      if (j == 0) head_bits = b;
+      if (sym[i] != ORC_R) {
+        all_zero = 0;
+        if (j > 0) rest_zero = 0;
+      }
     }
-    if (zc && all_zero) bits = 0;
+    if (zc && all_zero) {
+      bits = 0;
+    } else if (cc && B > 1 && rest_zero) {
+      cconst[c] = 1;
+      bits = head_bits;
+    }
     cbits[c] = bits;
     coff[c + 1] = coff[c] + (bits + 31) / 32;
   }
@@ -506,12 +532,12 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
   uint64_t symtab_bytes = ((2 * (uint64_t)n_used) + 3) & ~(uint64_t)3;
   uint64_t total = ORC_HDR + symtab_bytes + 4 * (nchunks + 1) + 4 * n_words;
   if (total > 0xFFFFFFFFull) {
-    free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+    free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
     return ORC_EINVAL;
   }
   uint8_t *rec = (uint8_t *)calloc(total, 1);
   if (!rec) {
-    free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+    free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
     return ORC_ENOMEM;
   }
   wr32(rec + 0, ORC_MAGIC);
@@ -525,7 +551,7 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
   wrf64(rec + 32, step);
   wr64(rec + 40, (uint64_t)sumsq);
   wr64(rec + 48, (uint64_t)(sumsq >> 64));
-  wr32(rec + 56, zc ? 1u : 0u);
+  wr32(rec + 56, (zc ? 1u : 0u) | (cc ? 2u : 0u));
   wr32(rec + 60, 0);
   /* symbol table in canonical order: by code length, then by symbol */
   uint8_t *tab = rec + ORC_HDR;
@@ -539,10 +565,11 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
     }
   }
   uint8_t *offs = tab + symtab_bytes;
-  for (uint64_t c = 0; c <= nchunks; c++) wr32(offs + 4 * c, (uint32_t)coff[c]);
+  for (uint64_t c = 0; c <= nchunks; c++)
+    wr32(offs + 4 * c, (uint32_t)coff[c] | (c < nchunks && cconst[c] ? ORC_CONST_MARK : 0u));
   uint32_t *words = (uint32_t *)calloc(n_words ? n_words : 1, sizeof(uint32_t));
   if (!words) {
-    free(rec); free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+    free(rec); free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
     return ORC_ENOMEM;
   }
   for (uint64_t c = 0; c < nchunks; c++) {
@@ -550,7 +577,7 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
     bitw bw;
     bw.words = words + coff[c];
     bw.pos = 0;
-    for (uint64_t j = 0; j < B; j++) {
+    for (uint64_t j = 0; j < (cconst[c] ? 1 : B); j++) { /* a constant chunk: the head only */
       uint64_t i = c * B + j;
       put_bits(&bw, codes[sym[i]], lens[sym[i]]);
       if (sym[i] == 0) {
@@ -572,7 +599,7 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
   }
   *out = rec;
   *out_len = total;
-  free(v); free(p); free(d); free(sym); free(cbits); free(coff);
+  free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
   return ORC_OK;
 }
 
@@ -600,7 +627,7 @@ int orc_parse(const uint8_t *rec, uint64_t len, orc_rec *h) {
   h->sumsq_lo = rd64(rec + 40);
   h->sumsq_hi = rd64(rec + 48);
   h->flags = rd32(rec + 56);
-  if (h->flags > 1 || rd32(rec + 60) != 0) return ORC_ECORRUPT;
+  if (h->flags > 3 || rd32(rec + 60) != 0) return ORC_ECORRUPT;
   if (h->slice_log2 > 26 || h->chunk_log2 > h->slice_log2) return ORC_ECORRUPT;
   if (h->n_chunks != (uint32_t)((2ull << h->slice_log2) >> h->chunk_log2)) return ORC_ECORRUPT;
   if (h->n_used < 1 || h->n_used > ORC_NSYM) return ORC_ECORRUPT;
@@ -687,9 +714,13 @@ int orc_decode_p(const uint8_t *rec, uint64_t len, int64_t *p) {
   }
   uint64_t B = (uint64_t)1 << h.chunk_log2;
   for (uint64_t c = 0; c < h.n_chunks; c++) {
-    uint32_t w0 = rd32(h.offs + 4 * c), w1 = rd32(h.offs + 4 * (c + 1));
+    uint32_t o0 = rd32(h.offs + 4 * c), o1 = rd32(h.offs + 4 * (c + 1));
+    const int cconst = (o0 & ORC_CONST_MARK) != 0;
+    if (cconst && !(h.flags & 2)) return ORC_ECORRUPT;
+    if (c + 1 == h.n_chunks && (o1 & ORC_CONST_MARK)) return ORC_ECORRUPT;
+    uint32_t w0 = o0 & ~ORC_CONST_MARK, w1 = o1 & ~ORC_CONST_MARK;
     if (w1 < w0 || w1 > h.n_words) return ORC_ECORRUPT;
-    if (w1 == w0 && h.n_used > 1) { /* an empty chunk under a real code: all zero */
+    if (!cconst && w1 == w0 && h.n_used > 1) { /* an empty chunk under a real code: all zero */
       if (!(h.flags & 1)) return ORC_ECORRUPT;
       for (uint64_t j = 0; j < B; j++) p[c * B + j] = 0;
       continue;
@@ -700,6 +731,10 @@ int orc_decode_p(const uint8_t *rec, uint64_t len, int64_t *p) {
     br.pos = 0;
     int64_t prev = 0;
     for (uint64_t j = 0; j < B; j++) {
+      if (cconst && j > 0) { /* a constant chunk: every value is the head's */
+        p[c * B + j] = prev;
+        continue;
+      }
       int sym;
       if (h.n_used == 1) {
         sym = syms[0];

@@ -92,7 +92,7 @@ def test_empty_chunk_without_the_flag_is_corrupt():
     struct.pack_into("<I", bad, 56, 0)
     with pytest.raises(oracle.OracleError):
         oracle.decode_p(bytes(bad))
-    struct.pack_into("<I", bad, 56, 2)  # unknown flag
+    struct.pack_into("<I", bad, 56, 4)  # unknown flag
     with pytest.raises(oracle.OracleError):
         oracle.decode_p(bytes(bad))
 
