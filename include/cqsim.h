@@ -57,6 +57,11 @@ extern "C" {
                                 extension for sparse states; header word 14 bit 0 marks such
                                 records).  Codes, amplitudes and norms are those of the mode
                                 without it; only record sizes shrink */
+#define SIM_CONST_CHUNKS 0x10u /* a chunk whose values all equal its first keeps only the first
+                                  one's code; bit 31 of its word offset marks it, header word 14
+                                  bit 1 marks such records (an extension for states with flat
+                                  stretches).  With SIM_ZERO_CHUNKS an all-zero chunk stays a zero
+                                  chunk.  Codes, amplitudes and norms are unchanged */
 
 #define SIM_FUSE_MAX 5   /* widest fused block, in qubits */
 

@@ -27,6 +27,7 @@ SIM_EB_REL = 0x1
 SIM_FP32 = 0x2
 SIM_FUSED = 0x4
 SIM_ZERO_CHUNKS = 0x8
+SIM_CONST_CHUNKS = 0x10
 GATE_DENSE = 1
 GATE_PHASE = 2
 
@@ -271,11 +272,12 @@ class Sim:
 
     def __init__(self, n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False,
                  chunk_log2: int = 0, workspace_bytes: int = 0, use_torch: Optional[bool] = None,
-                 arena_bytes: int = 0, fused: bool = False, fp32: bool = False, zero_chunks: bool = False):
+                 arena_bytes: int = 0, fused: bool = False, fp32: bool = False, zero_chunks: bool = False,
+                 const_chunks: bool = False):
         L = lib()
         cfg = _config(n_qubits, slice_log2, error_bound, relative=relative, chunk_log2=chunk_log2,
                       workspace_bytes=workspace_bytes, arena_bytes=arena_bytes, fused=fused, fp32=fp32,
-                      zero_chunks=zero_chunks)
+                      zero_chunks=zero_chunks, const_chunks=const_chunks)
         self._mem = None
         if use_torch is None:
             use_torch = _torch_ready()
@@ -292,6 +294,7 @@ class Sim:
         self.fused = fused
         self.fp32 = fp32
         self.zero_chunks = zero_chunks
+        self.const_chunks = const_chunks
         self.chunk_log2 = min(chunk_log2 or 10, slice_log2)
 
     def close(self):
@@ -429,14 +432,14 @@ class Graph:
 
 def _config(n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False, chunk_log2: int = 0,
             workspace_bytes: int = 0, arena_bytes: int = 0, fused: bool = False, fp32: bool = False,
-            zero_chunks: bool = False) -> ConfigStruct:
+            zero_chunks: bool = False, const_chunks: bool = False) -> ConfigStruct:
     cfg = ConfigStruct()
     cfg.n_qubits = n_qubits
     cfg.slice_log2 = slice_log2
     cfg.chunk_log2 = chunk_log2
     cfg.error_bound = error_bound
     cfg.mode = ((SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0) | (SIM_FP32 if fp32 else 0) |
-                (SIM_ZERO_CHUNKS if zero_chunks else 0))
+                (SIM_ZERO_CHUNKS if zero_chunks else 0) | (SIM_CONST_CHUNKS if const_chunks else 0))
     cfg.workspace_bytes = workspace_bytes
     cfg.arena_bytes = arena_bytes
     return cfg

@@ -632,7 +632,7 @@ int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   if (sl2 < 1 || sl2 > n || sl2 > 26) return set_err(SIM_EINVAL, "slice_log2 %d outside 1..min(26, n)", sl2);
   if (!(cfg->error_bound > 0.0) || !std::isfinite(cfg->error_bound))
     return set_err(SIM_EINVAL, "error bound must be positive and finite");
-  if (cfg->mode & ~(SIM_EB_REL | SIM_FP32 | SIM_FUSED | SIM_ZERO_CHUNKS))
+  if (cfg->mode & ~(SIM_EB_REL | SIM_FP32 | SIM_FUSED | SIM_ZERO_CHUNKS | SIM_CONST_CHUNKS))
     return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
   int cl2 = cfg->chunk_log2 > 0 ? cfg->chunk_log2 : 10;
   if (cl2 > sl2) cl2 = sl2;
@@ -643,7 +643,8 @@ int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   s->geo.L = 1ull << sl2;
   s->geo.nchunks = (uint32_t)((2ull << sl2) >> cl2);
   s->geo.zero_chunks = (cfg->mode & SIM_ZERO_CHUNKS) ? 1u : 0u;
-  s->geo.zero_in = s->geo.zero_chunks;
+  s->geo.const_chunks = (cfg->mode & SIM_CONST_CHUNKS) ? 1u : 0u;
+  s->geo.fmt_in = s->geo.zero_chunks | (s->geo.const_chunks << 1);
   s->eb = cfg->error_bound;
   s->mode = cfg->mode;
   s->fp32 = (cfg->mode & SIM_FP32) != 0;
@@ -975,13 +976,13 @@ struct sim_graph_s {
   uint32_t start_pass = 0;          // pass numbers [start_pass, start_pass + n) baked into the kernels
   uint8_t *arena[2] = {nullptr, nullptr};
   uint64_t cap[2] = {0, 0};
-  uint32_t zero_in = 0;             // the decoder variant captured (zero chunks or not)
+  uint32_t fmt_in = 0;              // the decoder variant captured (record formats it reads)
 };
 
 static bool graph_current(const sim_graph_t *G) {
   const sim_t *s = G->sim;
   return G->exec && s->cur == G->start_cur && s->arena[0] == G->arena[0] && s->arena[1] == G->arena[1] &&
-         s->arena_cap[0] == G->cap[0] && s->arena_cap[1] == G->cap[1] && s->geo.zero_in == G->zero_in;
+         s->arena_cap[0] == G->cap[0] && s->arena_cap[1] == G->cap[1] && s->geo.fmt_in == G->fmt_in;
 }
 
 // Record the program's passes from the current arena parity.  Nothing runs:
@@ -1032,7 +1033,7 @@ static int graph_capture(sim_graph_t *G) {
     G->arena[a] = s->arena[a];
     G->cap[a] = s->arena_cap[a];
   }
-  G->zero_in = s->geo.zero_in;
+  G->fmt_in = s->geo.fmt_in;
   return SIM_OK;
 }
 
@@ -1342,16 +1343,21 @@ static int check_record(const sim_t *s, const uint8_t *r, uint64_t len, double *
   }
   if (kraft != (1ull << kLMax)) return set_err(SIM_ECORRUPT, "symbol table is not a complete prefix code");
   const uint32_t flags = rd32(56);
-  if (flags > 1 || rd32(60) != 0) return set_err(SIM_ECORRUPT, "unknown header flags");
+  if (flags > 3 || rd32(60) != 0) return set_err(SIM_ECORRUPT, "unknown header flags");
   const uint64_t ooff = kHdr + ((2ull * n_used + 3) & ~3ull);
   uint32_t prevw = 0;
+  bool prev_const = false;
   for (uint32_t c = 0; c <= nch; c++) {
-    uint32_t w = rd32(ooff + 4ull * c);
+    const uint32_t x = rd32(ooff + 4ull * c);
+    const bool cst = (x >> 31) != 0;
+    const uint32_t w = x & 0x7FFFFFFFu;
+    if (cst && (!(flags & 2) || c == nch)) return set_err(SIM_ECORRUPT, "bad constant-chunk mark");
     if (w < prevw || w > nw || (c == 0 && w != 0) || (c == nch && w != nw))
       return set_err(SIM_ECORRUPT, "bad chunk offsets");
-    if (c > 0 && w == prevw && n_used > 1 && !(flags & 1))
+    if (c > 0 && w == prevw && n_used > 1 && !prev_const && !(flags & 1))
       return set_err(SIM_ECORRUPT, "empty chunk in a record without zero chunks");
     prevw = w;
+    prev_const = cst;
   }
   memcpy(step, r + 32, 8);
   memcpy(sq, r + 40, 16);
@@ -1416,7 +1422,7 @@ int sim_import_slice(sim_t *s, uint64_t j, const void *buf, uint64_t len) {
   // a record with zero chunks: from now on the decoder handles them
   uint32_t flags;
   memcpy(&flags, (const uint8_t *)buf + 56, 4);
-  if (flags & 1) s->geo.zero_in = 1;
+  s->geo.fmt_in |= flags & 3u;
   // the record's codes are not known to fit int32: the next pass decodes to FP64
   s->h_ctl->wide_next = 1;
   HIP_TRY(hipMemcpy(&s->ctl->wide_next, &s->h_ctl->wide_next, 4, hipMemcpyHostToDevice));

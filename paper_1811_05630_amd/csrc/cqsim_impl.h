@@ -97,7 +97,9 @@ struct Geo {
   uint32_t nchunks;       // 2L / B
   uint64_t L;
   uint32_t zero_chunks;   // SIM_ZERO_CHUNKS: all-zero chunks are stored with no words
-  uint32_t zero_in;       // the stored records may hold zero chunks (the mode, or an imported record)
+  uint32_t const_chunks;  // SIM_CONST_CHUNKS: constant chunks keep their head only (offset bit 31)
+  uint32_t fmt_in;        // the stored records may hold zero chunks (bit 0) or constant chunks (bit 1):
+                          // the modes, or imported records
 };
 
 // Per-slot scratch of one batch of decompressed slices.

@@ -409,8 +409,9 @@ struct BitReader {
 
 // The chunks of one workgroup (after the record checks).  FULL: chunks of at
 // least 32 values and a whole number of workgroups of chunks per slot (every
-// lane active, whole rounds).  ZC: the records may hold zero chunks.
-template <bool FULL, bool C32, bool ZC>
+// lane active, whole rounds).  FMT: the records may hold zero chunks (bit 0)
+// or constant chunks (bit 1).
+template <bool FULL, bool C32, int FMT>
 __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, const StateMeta &cur, uint64_t slice,
                                               uint32_t u, const uint32_t *offs, uint32_t nchunks, uint32_t n_words,
                                               uint32_t n_used, double k, uint32_t *dtab, uint8_t *stg,
@@ -425,9 +426,16 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   BitReader<PF> br;
   uint32_t w0 = 0;
   br.nw = 0;
+  constexpr bool ZC = (FMT & 1) != 0, CC = (FMT & 2) != 0;
+  bool cconst = false;  // a constant chunk: its head, then the zero difference
   if (active) {
     w0 = offs[c];
-    const uint32_t w1 = offs[c + 1];
+    uint32_t w1 = offs[c + 1];
+    if (CC) {
+      cconst = (w0 >> 31) != 0;
+      w0 &= 0x7FFFFFFFu;
+      w1 &= 0x7FFFFFFFu;
+    }
     if (w1 < w0 || w1 > n_words) {
       fail(ctl, kFlagCorrupt, pass);
       w0 = 0;
@@ -437,7 +445,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   }
   // an empty chunk under a code of two or more symbols is a zero chunk (a
   // one-symbol code has no bits: its chunks are empty and decode normally)
-  const bool zero = ZC && active && br.nw == 0 && n_used > 1;
+  const bool zero = ZC && active && !cconst && br.nw == 0 && n_used > 1;
   constexpr uint32_t kZeroPair = (uint32_t)kR | ((uint32_t)kR << 14) | (1u << 28);  // dtab_entry(R, 0, R, 0, true)
   br.w = offs + (nchunks + 1) + w0;
   br.wi = 0;
@@ -470,8 +478,10 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
     if (active) {
       for (uint32_t q = 0; q < R;) {
         br.refill1(pf, tid);
-        // a zero chunk reads two zero differences of no bits per step
-        const uint32_t e = (ZC && zero) ? kZeroPair : dtab[(uint32_t)(br.buf >> (64 - kLMax))];
+        // a zero chunk reads two zero differences of no bits per step, and
+        // so does a constant chunk after its head
+        const bool fill = (ZC && zero) || (CC && cconst && (j0 > 0 || q > 0));
+        const uint32_t e = fill ? kZeroPair : dtab[(uint32_t)(br.buf >> (64 - kLMax))];
         const uint32_t sym = e & 1023u;
         if (sym == 0) {  // escape (never part of a two-symbol entry)
           const uint32_t len = (e >> 10) & 15u;
@@ -497,7 +507,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
         // one or two symbols on one path for every lane; the second value
         // is written in any case (at q + 1 <= R, inside the padded row) and
         // overwritten later when it was not decoded
-        const bool two = (e >> 28) && q + 1 < R;
+        const bool two = (e >> 28) && q + 1 < R && !(CC && cconst && j0 == 0 && q == 0);  // a lone head
         const uint32_t len = ((e >> 10) & 15u) + (two ? ((e >> 24) & 15u) : 0u);
         br.buf <<= len;
         br.nbits -= (int)len;
@@ -532,7 +542,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   }
 }
 
-template <bool FULL, bool ZC>
+template <bool FULL, int FMT>
 __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
                                                            const uint8_t *arena, StateMeta cur, const double *kscale,
                                                            Ctl *ctl, uint32_t pass, int compact_ok) {
@@ -569,11 +579,11 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
   const uint32_t sym_bytes = (2 * n_used + 3) & ~3u;
   const uint32_t *offs = (const uint32_t *)(rec + kHdr + sym_bytes);
   if (c32)
-    decode_chunks<FULL, true, ZC>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, 0.0, dtab, stg, pf, ctl,
-                                  pass);
+    decode_chunks<FULL, true, FMT>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, 0.0, dtab, stg, pf, ctl,
+                                   pass);
   else
-    decode_chunks<FULL, false, ZC>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, kscale[slice], dtab, stg,
-                                   pf, ctl, pass);
+    decode_chunks<FULL, false, FMT>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, kscale[slice], dtab, stg,
+                                    pf, ctl, pass);
 }
 
 // ------------------------------------------------------------ gate + quantise
@@ -2458,9 +2468,12 @@ __device__ __forceinline__ uint2 enc_syms(const uint16_t *sym, uint64_t j, uint6
 // Chunks [cb, ce) of slot blockIdx.y; coding wavefront w takes chunks cb + w,
 // cb + w + 4, ...; every wavefront runs the same number of rounds so that
 // barriers line up.  STEPS = ceil(B / 256) steps of 256 symbols per chunk.
-template <int STEPS, bool ZC>
+// FMT: bit 0 zero chunks (no words), bit 1 constant chunks (the head only,
+// marked by bit 31 of the chunk's word offset).
+template <int STEPS, int FMT>
 __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_encode(Slots sl, Geo g, uint32_t chunks_per_block,
                                                                     const Ctl *ctl) {
+  constexpr bool ZC = (FMT & 1) != 0, CC = (FMT & 2) != 0;
   if (ctl->flags) return;
   extern __shared__ uint32_t lw_all[];  // [2][kEncWaves][stage_words]
   __shared__ __align__(16) uint32_t codes[kNSym];
@@ -2531,6 +2544,16 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       uint32_t *lw = lw_all + (uint64_t)(buf * kEncWaves + wave) * W;
       uint64_t run = 0;  // the buffer lw is all zero (cleared by the store wavefront)
       bool nz = false;   // zero-chunk records: a symbol other than the zero difference
+      bool cchunk = false;  // constant-chunk records: every symbol after the head is the zero difference
+      if (CC) {  // positions past the chunk's end hold the zero difference
+        bool rest = false;
+#pragma unroll
+        for (int i = 0; i < STEPS; i++) {
+          const uint32_t x = (i == 0 && lane == 0) ? ((cur[i].x & 0xffff0000u) | (uint32_t)kR) : cur[i].x;
+          rest = rest || x != ((uint32_t)kR | ((uint32_t)kR << 16)) || cur[i].y != ((uint32_t)kR | ((uint32_t)kR << 16));
+        }
+        cchunk = active && __ballot(rest) == 0;
+      }
 #pragma unroll
       for (int i = 0; i < STEPS; i++) {
         const uint64_t j = (uint64_t)i * 256 + 4 * (uint64_t)lane;
@@ -2546,7 +2569,7 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
         for (int k = 0; k < 4; k++) cw[k] = codes[sv[k]];  // every symbol is a table index
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-          const bool valid = j + k < B;
+          const bool valid = j + k < B && !(CC && cchunk && j + k > 0);  // a constant chunk codes its head only
           cw[k] = valid ? cw[k] : 0u;
           bl += cw[k] & 0xffu;
           esc[k] = valid && sv[k] == 0;
@@ -2607,11 +2630,14 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       }
       uint32_t nw = (uint32_t)((run + 31) >> 5);
       if (nw > W) nw = W;  // at most 68 bits per value: never reached by a consistent codebook
+      bool zchunk = false;
       if (ZC && __ballot(nz) == 0) {  // zero-chunk records: an all-zero chunk keeps no words
         for (uint32_t i = lane; i < nw; i += 64) lw[i] = 0;  // after the lanes' writes (LDS in order)
         nw = 0;
+        zchunk = true;
       }
-      if (lane == 0) cnw[buf][wave] = active ? nw : 0u;
+      const uint32_t mark = (CC && cchunk && !zchunk) ? 0x80000000u : 0u;
+      if (lane == 0) cnw[buf][wave] = active ? (nw | mark) : 0u;
 #pragma unroll
       for (int i = 0; i < STEPS; i++) {
         cur[i] = nxt[i];
@@ -2624,13 +2650,14 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       for (uint32_t w = 0; w < (uint32_t)kEncWaves; w++) {
         const uint32_t c = cb + (r - 1) * kEncWaves + w;
         if (c >= ce) break;
-        const uint32_t nw = cnw[pb][w];
+        const uint32_t v = cnw[pb][w];
+        const uint32_t nw = CC ? v & 0x7FFFFFFFu : v;
         uint32_t *src = lw_all + (uint64_t)(pb * kEncWaves + w) * W;
         for (uint32_t i = lane; i < nw; i += 64) {  // copied out, then cleared for the round after next
           blk[packed + i] = src[i];
           src[i] = 0;
         }
-        if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = packed;
+        if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = packed | (CC ? v & 0x80000000u : 0u);
         packed += nw;
       }
     }
@@ -2737,7 +2764,10 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
   uint8_t *rec = arena + off;
   uint32_t *offs = (uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
   uint32_t *stream = offs + nch + 1;
-  for (uint32_t c = cb + tid; c < ce; c += T) offs[c] = (uint32_t)bp + (c == cb + tid ? cw0 : cw[c]);
+  for (uint32_t c = cb + tid; c < ce; c += T) {  // a constant chunk's mark (bit 31) travels with its offset
+    const uint32_t x = c == cb + tid ? cw0 : cw[c];
+    offs[c] = ((uint32_t)bp + (x & 0x7FFFFFFFu)) | (x & 0x80000000u);
+  }
 #pragma unroll
   for (uint32_t k = 0; k < kU; k++) {
     const uint32_t i = k * T + tid;
@@ -2759,7 +2789,7 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
     *(double *)(rec + 32) = step;
     *(uint64_t *)(rec + 40) = sq_lo;
     *(uint64_t *)(rec + 48) = sq_hi;
-    h32[14] = g.zero_chunks ? 1u : 0u;  // empty chunks are zero chunks
+    h32[14] = (g.zero_chunks ? 1u : 0u) | (g.const_chunks ? 2u : 0u);  // zero chunks; constant chunks
     h32[15] = 0;
     nxt.rec_off[slice] = off;
     nxt.rec_len[slice] = h32[7];
@@ -2911,18 +2941,15 @@ void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
   dim3 grid(grid1(g.nchunks, per_wg), (unsigned)nslots);
   const bool full = (1ull << g.chunk_log2) >= (uint64_t)DecFmt<true>::R && g.nchunks % per_wg == 0;
   const int c = compact ? 1 : 0;
-  if (g.zero_in) {
-    if (full)
-      CQ_LAUNCH((k_decode<true, true>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c);
-    else
-      CQ_LAUNCH((k_decode<false, true>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass,
-                c);
-  } else if (full) {
-    CQ_LAUNCH((k_decode<true, false>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c);
-  } else {
-    CQ_LAUNCH((k_decode<false, false>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass,
-              c);
+#define CQ_DEC(FULL_, FMT_) \
+  CQ_LAUNCH((k_decode<FULL_, FMT_>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c)
+  switch (g.fmt_in & 3u) {
+    case 0: if (full) CQ_DEC(true, 0); else CQ_DEC(false, 0); break;
+    case 1: if (full) CQ_DEC(true, 1); else CQ_DEC(false, 1); break;
+    case 2: if (full) CQ_DEC(true, 2); else CQ_DEC(false, 2); break;
+    default: if (full) CQ_DEC(true, 3); else CQ_DEC(false, 3); break;
   }
+#undef CQ_DEC
 }
 
 static int gate_kind(const GateDesc &gd) {
@@ -3089,36 +3116,38 @@ static uint32_t enc_chunks_per_block(const Geo &g, int nslots) {
   return (uint32_t)cpb;
 }
 
-template <bool ZC>
-void launch_encode_zc(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
+template <int FMT>
+void launch_encode_fmt(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
   const uint32_t cpb = enc_chunks_per_block(g, nslots);
   dim3 grid(grid1(g.nchunks, cpb), (unsigned)nslots);
   const size_t shm = (size_t)2 * kEncWaves * sl.stage_words * 4;
   const dim3 block(64 * (kEncWaves + 1));
   if (g.chunk_log2 <= 8) {
-    CQ_LAUNCH((k_encode<1, ZC>), grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH((k_encode<1, FMT>), grid, block, shm, st, sl, g, cpb, ctl);
     return;
   }
   // dynamic LDS above the default needs the attribute: set once to the
   // largest request (chunks of 1024 values, ~70 KB)
   static const bool attrs = [] {
     const int most = (int)(2 * kEncWaves * stage_words_for(10) * 4);
-    (void)hipFuncSetAttribute((const void *)k_encode<4, ZC>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
-    (void)hipFuncSetAttribute((const void *)k_encode<2, ZC>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    (void)hipFuncSetAttribute((const void *)k_encode<4, FMT>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    (void)hipFuncSetAttribute((const void *)k_encode<2, FMT>, hipFuncAttributeMaxDynamicSharedMemorySize, most);
     return true;
   }();
   (void)attrs;
   if (g.chunk_log2 == 9)
-    CQ_LAUNCH((k_encode<2, ZC>), grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH((k_encode<2, FMT>), grid, block, shm, st, sl, g, cpb, ctl);
   else
-    CQ_LAUNCH((k_encode<4, ZC>), grid, block, shm, st, sl, g, cpb, ctl);
+    CQ_LAUNCH((k_encode<4, FMT>), grid, block, shm, st, sl, g, cpb, ctl);
 }
 
 void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
-  if (g.zero_chunks)
-    launch_encode_zc<true>(st, sl, g, nslots, ctl);
-  else
-    launch_encode_zc<false>(st, sl, g, nslots, ctl);
+  switch ((g.zero_chunks ? 1 : 0) | (g.const_chunks ? 2 : 0)) {
+    case 0: launch_encode_fmt<0>(st, sl, g, nslots, ctl); break;
+    case 1: launch_encode_fmt<1>(st, sl, g, nslots, ctl); break;
+    case 2: launch_encode_fmt<2>(st, sl, g, nslots, ctl); break;
+    default: launch_encode_fmt<3>(st, sl, g, nslots, ctl); break;
+  }
 }
 
 void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
