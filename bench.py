@@ -64,6 +64,8 @@ def parse():
                     help="grover24: also report the chunk-length autotuner's table (sim_tune_chunk) on the circuit")
     ap.add_argument("--zero-chunks", action="store_true",
                     help="grover24: zero-chunk records (all-zero chunks stored with no words)")
+    ap.add_argument("--const-chunks", action="store_true",
+                    help="grover24: constant-chunk records (a chunk of equal values keeps its first only)")
     ap.add_argument("--workload", choices=("grover24", "qft30", "grover34", "qft12", "serve"), default="grover24",
                     help="grover24 (default, the headline line); qft30: 30-qubit QFT of a product state in "
                          "fused mode; grover34: a window of 34-qubit Grover search")
@@ -234,7 +236,8 @@ def run_grover24(args):
     # record arenas sized up front for a ratio of 4 or better (the circuit
     # stays above 6), so that no reallocation falls inside a timed batch
     sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, arena_bytes=(16 << n) // 4,
-                 fp32=args.fp32, zero_chunks=args.zero_chunks)
+                 fp32=args.fp32, zero_chunks=args.zero_chunks,
+                 const_chunks=args.const_chunks)
     # initial H layer (untimed), then warm-up passes
     # the circuit is marshalled once, outside every timed region
     gates = cq.Circuit(w.gates)
@@ -271,15 +274,17 @@ def run_grover24(args):
     config = {"workload": "grover24: 24-qubit Grover search, marked index from seed 0, 64 slices of 2^18 "
                           "amplitudes, absolute bound 1e-7, plain mode (one pass per gate)" +
                           (", FP32 mode" if args.fp32 else "") +
-                          (", zero-chunk records" if args.zero_chunks else ""),
+                          (", zero-chunk records" if args.zero_chunks else "") +
+                          (", constant-chunk records" if args.const_chunks else ""),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
               "error_bound": w.error_bound, "passes_timed": K, "first_timed_gate": n + Wm, "fp32": args.fp32,
-              "zero_chunks": args.zero_chunks}
+              "zero_chunks": args.zero_chunks, "const_chunks": args.const_chunks}
     line = report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config,
                   plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16)
     if args.tune:  # the H layer and 300 Grover gates on fresh handles, chunks of 2^5 .. 2^10
         best, table = cq.tune_chunk(n, w.slice_log2, w.error_bound, gates[:n + 300], lo=5, hi=10,
-                                    fp32=args.fp32, zero_chunks=args.zero_chunks)
+                                    fp32=args.fp32, zero_chunks=args.zero_chunks,
+                 const_chunks=args.const_chunks)
         line["autotune"] = {"best_chunk_log2": best,
                             "ms_per_gate": {str(c): round(v[0], 4) for c, v in table.items()},
                             "record_bytes": {str(c): int(v[1]) for c, v in table.items()}}
