@@ -35,16 +35,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # the reading of the same counter for the copy probe.  Valid only for the
 # kernel source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
-    "gate_quant": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
-                  "bytes_per_launch": 225115782},
-    "decode": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
-              "bytes_per_launch": 151174596},
-    "encode": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
-              "bytes_per_launch": 83541010},
-    "codebook": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
-                "bytes_per_launch": 5848645},
-    "finish": {"kernels_sha256": "019fb01a925d117fbeff29d7942455290f42e4133f7f71f4601b6fc8a098f125",
-              "bytes_per_launch": 15121587},
+    "gate_quant": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
+                  "bytes_per_launch": 225122858},
+    "decode": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
+              "bytes_per_launch": 151242036},
+    "encode": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
+              "bytes_per_launch": 83529066},
+    "codebook": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
+                "bytes_per_launch": 5819734},
+    "finish": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
+              "bytes_per_launch": 15121536},
 }
 
 
