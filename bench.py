@@ -35,15 +35,15 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # the reading of the same counter for the copy probe.  Valid only for the
 # kernel source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
-    "gate_quant": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
-                  "bytes_per_launch": 225122858},
-    "decode": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
-              "bytes_per_launch": 151242036},
-    "encode": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
-              "bytes_per_launch": 83529066},
-    "codebook": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
-                "bytes_per_launch": 5819734},
-    "finish": {"kernels_sha256": "50b403968fd4d72860e46a16889e776697943df04b88b30bf5d565599eff39a0",
+    "gate_quant": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+                  "bytes_per_launch": 224755957},
+    "decode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+              "bytes_per_launch": 148202290},
+    "encode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+              "bytes_per_launch": 83529241},
+    "codebook": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+                "bytes_per_launch": 5819729},
+    "finish": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
               "bytes_per_launch": 15121536},
 }
 

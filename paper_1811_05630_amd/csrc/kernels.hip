@@ -523,16 +523,19 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
     // the tile is private to the wavefront: its LDS operations complete in
     // order, so waiting for them is enough before other lanes read
     __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
+    // streaming stores: the workspace is read once, by the next kernel, and
+    // is larger than the L2 caches
     if (FULL) {
 #pragma unroll
       for (int i = 0; i < RMAX; i++) {
         const uint32_t idx = (uint32_t)i * 64u + lane, row = idx / RMAX, col = idx % RMAX;
-        out[(uint64_t)(c0 + row) * B + j0 + col] = st[row * PITCH + col];
+        __builtin_nontemporal_store(st[row * PITCH + col], &out[(uint64_t)(c0 + row) * B + j0 + col]);
       }
     } else {
       for (uint32_t idx = lane; idx < 64u * R; idx += 64u) {
         const uint32_t row = idx / R, col = idx % R;
-        if (c0 + row < nchunks) out[(uint64_t)(c0 + row) * B + j0 + col] = st[row * PITCH + col];
+        if (c0 + row < nchunks)
+          __builtin_nontemporal_store(st[row * PITCH + col], &out[(uint64_t)(c0 + row) * B + j0 + col]);
       }
     }
     // the next round's slot; its words were loaded before the stores above,
@@ -1524,12 +1527,13 @@ __device__ __forceinline__ void wr_load(WRange &x, __amdgpu_buffer_rsrc_t ws, ui
     x.i[v] = buf_ld_f64(ws, 8 * (L + ob + v * 64 + lane));
   }
 }
+// (streaming loads, cache policy bit 1: the codes are read once)
 __device__ __forceinline__ void wr_load(WRange32 &x, __amdgpu_buffer_rsrc_t ws, uint32_t L, uint32_t ob) {
   const uint32_t lane = lane_id();
 #pragma unroll
   for (int v = 0; v < 4; v++) {
-    x.r[v] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ws, 4 * (ob + v * 64 + lane), 0, 0);
-    x.i[v] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ws, 4 * (L + ob + v * 64 + lane), 0, 0);
+    x.r[v] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ws, 4 * (ob + v * 64 + lane), 0, 2);
+    x.i[v] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ws, 4 * (L + ob + v * 64 + lane), 0, 2);
   }
 }
 // the values of a loaded range: (double)q * k rounds exactly like the FP64
