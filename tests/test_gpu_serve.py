@@ -176,3 +176,32 @@ def test_a_failing_job_does_not_disturb_the_others():
     assert np.array_equal(bits(done[good[0]]["amplitudes"]), bits(ampl))
     for g in good:
         assert done[g]["status"] == 0
+
+
+def test_server_runs_fused_relative_and_record_mode_jobs():
+    """Jobs of other configurations (fused blocks, a relative bound, zero and
+    constant chunks) on the server: the same bits as each one run alone."""
+    jobs = [
+        dict(n=10, sl=7, eb=1e-4, gates=qc.qft(10), kw=dict(relative=True), init=("basis", 9)),
+        dict(n=11, sl=8, eb=1e-6, gates=qc.qft(11), kw=dict(fused=True), init=("basis", 5)),
+        dict(n=12, sl=9, eb=1e-6, gates=qc.grover(12, 7, 1), kw=dict(zero_chunks=True, const_chunks=True)),
+    ]
+    say("serve: fused, relative and record-mode jobs")
+    with cq.Server(budget_bytes=8 << 30, max_active=3) as srv:
+        ids = []
+        for j in jobs:
+            kw = dict(j["kw"], chunk_log2=5, out_count=1 << j["n"], family=QFT)
+            if "init" in j:
+                kw.update(init="basis", basis=j["init"][1])
+            ids.append(srv.submit(j["n"], j["sl"], j["eb"], cq.Circuit(j["gates"]), **kw))
+        done = {d["id"]: d for d in srv.drain(timeout=300)}
+    for i, j in zip(ids, jobs):
+        d = done[i]
+        assert d["status"] == 0, d["error"]
+        s = cq.Sim(j["n"], j["sl"], j["eb"], chunk_log2=5, **j["kw"])
+        if "init" in j:
+            s.init_basis(j["init"][1])
+        s.apply(j["gates"])
+        assert np.array_equal(bits(d["amplitudes"]), bits(s.amplitudes())), f"job {i}"
+        assert d["stats"]["compressed_bytes"] == s.stats()["compressed_bytes"]
+        s.close()
