@@ -2,18 +2,24 @@
 
 One step is one pass of Algorithm 1 (Section II of the paper) over the whole
 state: every slice is decompressed, normalised, updated by one gate and
-recompressed.  The workload is 24-qubit Grover search (marked index from seed
-0), 64 slices of 2^18 amplitudes, absolute error bound 1e-7, FP64.  Inputs
-are synthetic (the paper's circuits are not available); the timed passes are
-Grover iterations (oracle + diffusion gates) after the initial H layer.
+recompressed.  The default workload is the largest configuration that fits one
+GPU: 34-qubit Grover search (marked index from seed 0), 1024 slices of 2^24
+amplitudes (an uncompressed FP64 state of 256 GiB, held only compressed),
+absolute error bound 1e-8, FP64.  Inputs are synthetic (the paper's circuits
+are not available).  The initial H layer runs untimed; the timed passes start
+at the first Grover iteration's oracle and run into its diffusion layer, where
+every slice holds nonzero amplitudes.  The same window is then run in FP32
+mode, and both read-outs are compared on sampled amplitudes (with the exact
+state beside them).
 
 Prints one JSON line: throughput in state amplitudes per second (amplitude-
-passes: 2^24 per step), the compression ratio, per-pass latency percentiles,
+passes: 2^34 per step), the compression ratio, per-pass latency percentiles,
 the roofline position of the dominant kernel (device times from HIP events on
-the library's stream), and the CPU oracle timed on a bounded sample.
+the library's stream), and the CPU oracle timed on sampled slices.
 
-`--copy-probe` instead times a plain device copy of known size; its HBM
-counter readings calibrate the per-kernel traffic figures below.
+`--workload grover24 | qft30 | qft12 | serve` runs the other configurations;
+`--copy-probe` times a plain device copy of known size, whose HBM counter
+readings calibrate the per-kernel traffic figures below.
 """
 import argparse
 import hashlib
@@ -30,52 +36,66 @@ MFMA_F64_PEAK_TFLOPS = 78.6
 METRIC = "state amps/s via decompress+gate+compress at error bound; ratio; p99 latency"
 KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 
-# HBM bytes per launch of a kernel class at the default workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script, each scaled by
-# the reading of the same counter for the copy probe.  Valid only for the
-# kernel source they were taken on (sha256 of kernels.hip).
+# HBM bytes per launch of a kernel class, per workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script, each scaled by the
+# reading of the same counter for the copy probe.  Valid only for the kernel
+# source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
-    "gate_quant": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                  "bytes_per_launch": 224755957},
-    "decode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-              "bytes_per_launch": 148202290},
-    "encode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-              "bytes_per_launch": 83529241},
-    "codebook": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                "bytes_per_launch": 5819729},
-    "finish": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-              "bytes_per_launch": 15121536},
+    "grover24": {
+        "gate_quant": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+                       "bytes_per_launch": 224755957},
+        "decode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+                   "bytes_per_launch": 148202290},
+        "encode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+                   "bytes_per_launch": 83529241},
+        "codebook": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+                     "bytes_per_launch": 5819729},
+        "finish": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
+                   "bytes_per_launch": 15121536},
+    },
 }
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None, help="timed passes (default: 20; grover24: 1000)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed passes before them (default: 5; grover24: 100)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk-log2", type=int, default=8)
-    ap.add_argument("--latency-passes", type=int, default=200)
+    ap.add_argument("--latency-passes", type=int, default=None, help="single-pass calls timed for the "
+                    "latency percentiles (default: 20; grover24: 200)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--fp32", action="store_true",
-                    help="FP32 mode (grover24, grover34): FP32 working values and gate arithmetic")
+                    help="grover24: FP32 mode (FP32 working values and gate arithmetic); grover34 runs both "
+                         "precisions")
+    ap.add_argument("--no-fp32", action="store_true", help="grover34: skip the FP32 leg")
     ap.add_argument("--tune", action="store_true",
                     help="grover24: also report the chunk-length autotuner's table (sim_tune_chunk) on the circuit")
     ap.add_argument("--zero-chunks", action="store_true",
                     help="grover24: zero-chunk records (all-zero chunks stored with no words)")
     ap.add_argument("--const-chunks", action="store_true",
                     help="grover24: constant-chunk records (a chunk of equal values keeps its first only)")
-    ap.add_argument("--workload", choices=("grover24", "qft30", "grover34", "qft12", "serve"), default="grover24",
-                    help="grover24 (default, the headline line); qft30: 30-qubit QFT of a product state in "
-                         "fused mode; grover34: a window of 34-qubit Grover search")
+    ap.add_argument("--workload", choices=("grover34", "grover24", "qft30", "qft12", "serve"), default="grover34",
+                    help="grover34 (default, the headline line: 34-qubit Grover search, FP64 and FP32); "
+                         "grover24: 24-qubit Grover search; qft30: 30-qubit QFT of a product state in fused "
+                         "mode; qft12: 12-qubit QFT as a captured graph; serve: the job server")
     ap.add_argument("--jobs", type=int, default=200, help="serve: jobs in the timed stream")
     ap.add_argument("--arrival-ms", type=float, default=60.0, help="serve: mean gap between arrivals")
     ap.add_argument("--max-active", type=int, default=4, help="serve: jobs running at once, at most")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device-memory budget")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 256 MiB device copy (counter calibration) and exit")
-    return ap.parse_args()
+    args = ap.parse_args()
+    big = args.workload == "grover24"
+    if args.steps is None:
+        args.steps = 1000 if big else 20
+    if args.warmup is None:
+        args.warmup = 100 if big else 5
+    if args.latency_passes is None:
+        args.latency_passes = 200 if big else 20
+    return args
 
 
 def kernel_bytes(name, n_amps, c_in, c_out, n_slices, escapes, plane_bytes=16):
@@ -100,8 +120,8 @@ def source_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
 
 
-def traffic_for(kernel):
-    rec = MEASURED_TRAFFIC.get(kernel)
+def traffic_for(workload, kernel):
+    rec = MEASURED_TRAFFIC.get(workload, {}).get(kernel)
     if not rec or rec["kernels_sha256"] != source_sha():
         return None
     return rec["bytes_per_launch"]
@@ -163,7 +183,7 @@ def compact_workspace(w, relative, chunk_log2):
 
 
 def report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config, mfma_flops=None, extra=None,
-           plane_bytes=16):
+           plane_bytes=16, nslices=None):
     """The JSON line shared by all workloads."""
     import numpy as np
     N = 1 << w.n_qubits
@@ -181,11 +201,11 @@ def report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config, mfma_flops
                 "unit": "TFLOP/s", "frac": achieved / MFMA_F64_PEAK_TFLOPS, "traffic": None,
                 "algorithmic_flops_per_launch": flops, "avg_launch_ms": avg_ms}
     else:
-        algo = kernel_bytes(dom, N, comp, comp, sim.nslices, esc, plane_bytes) / per_pass[dom]
+        algo = kernel_bytes(dom, N, comp, comp, nslices or sim.nslices, esc, plane_bytes) / per_pass[dom]
         achieved = algo / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": traffic_for(dom) if args.workload == "grover24" else None,
+                "traffic": traffic_for(args.workload, dom),
                 "algorithmic_bytes_per_launch": algo, "avg_launch_ms": avg_ms}
     b = 8 if getattr(args, "fp32", False) else 16  # bytes per amplitude of the working form
     pipe_bytes = 2 * b * N + 2 * comp  # B_alg: planes written and read once + records in and out
@@ -387,44 +407,185 @@ def run_qft30(args):
     return line
 
 
-def run_grover34(args):
-    """A window of 34-qubit Grover search (1024 slices of 2^24, absolute bound
-    1e-8): the first passes of the H layer untimed, the next `steps` passes
-    timed."""
-    import torch
-    import paper_1811_05630_amd as cq
-    import qcircuits as qc
+def grover_exact(n, marked, layer_done, idx):
+    """Exact amplitudes at indices idx of the Grover circuit after its initial
+    H layer, the first oracle and H on qubits 0..layer_done-1 of the first
+    diffusion (uncompressed arithmetic: the state before the diffusion is
+    c (1 - 2 [i = w]) with c = 2^(-n/2); H on the j low qubits maps it to
+    c 2^(j/2) [low_j(i) = 0] - 2 c 2^(-j/2) (-1)^popcount(low_j(i) & w) [high(i) = high(w)])."""
+    import numpy as np
+    idx = np.asarray(idx, dtype=np.int64)
+    j = layer_done
+    c = 2.0 ** (-n / 2)
+    low = (1 << j) - 1
+    a = np.where((idx & low) == 0, c * 2.0 ** (j / 2), 0.0)
+    par = np.array([bin(int(i) & marked & low).count("1") & 1 for i in idx])
+    same = (idx >> j) == (marked >> j)
+    a = a - np.where(same, 2 * c * 2.0 ** (-j / 2) * np.where(par == 1, -1.0, 1.0), 0.0)
+    return a.astype(np.complex128)
 
-    w = qc.grover_workload(n=34, slice_log2=24, eb=1e-8, seed=args.seed, iterations=2)
+
+def grover34_sample_ranges(n, sl, marked, seed=11):
+    """Amplitude ranges read out for the precision comparison: 64 runs of 4096
+    amplitudes at seeded slice offsets, plus the run holding the marked index."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    starts = sorted({int(x) << 12 for x in rng.integers(0, 1 << (n - 12), size=64)} | {(marked >> 12) << 12})
+    return [(b, 4096) for b in starts]
+
+
+def run_grover34_leg(args, w, fp32, K, Wm):
+    """One precision of the headline: the prelude untimed, Wm warm-up passes
+    (the end of the initial H layer), K timed passes from the first oracle on;
+    then the same window again from |0...0> with per-kernel event timing, and
+    single-pass latencies after it."""
+    import torch
+    import numpy as np
+    import paper_1811_05630_amd as cq
     n, N = w.n_qubits, 1 << w.n_qubits
-    K = min(args.steps, 20)
-    Wm = min(args.warmup, 10)
+    start = n  # the first oracle
+    assert Wm <= start
     sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, workspace_bytes=96 << 30,
-                 arena_bytes=48 << 30, fp32=args.fp32)
+                 arena_bytes=16 << 30, fp32=fp32)
     g = cq.Circuit(w.gates)  # marshalled once, outside the timed region
-    sim.apply(g[:Wm])
+    assert len(g) >= start + K + args.latency_passes
+
+    def prelude():
+        sim.init_basis(0)
+        sim.apply(g[:start - Wm])
+        sim.apply(g[start - Wm:start])  # warm-up passes
+
+    prelude()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.apply(g[Wm:Wm + K])
+    sim.apply(g[start:start + K])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    st2 = sim.stats()
+    samples = grover34_sample_ranges(n, w.slice_log2, w.basis)
+    read = np.concatenate([sim.amplitudes(b, c) for b, c in samples])
+    # the same window with per-kernel events (HIP events on the library's stream)
+    prelude()
     st1 = sim.stats()
     sim.kernel_times(True)
-    sim.apply(g[Wm + K:Wm + 2 * K])
+    sim.apply(g[start:start + K])
     torch.cuda.synchronize()
     kt = sim.kernel_times(False)
-    st2 = sim.stats()
-    config = {"workload": "grover34 window: 34-qubit Grover search (marked index from seed 0), 1024 slices of "
-                          "2^24 amplitudes, absolute bound 1e-8, plain mode; passes %d..%d timed%s"
-                          % (Wm, Wm + K - 1, ", FP32 mode" if args.fp32 else ""),
+    st3 = sim.stats()
+    lat = []
+    for i in range(args.latency_passes):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sim.apply(g[start + K + i:start + K + i + 1])
+        lat.append((time.perf_counter() - a) * 1e3)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return dict(dt=dt, kt=kt, st1=st1, st2=st2, st3=st3, lat=lat, read=read, samples=samples)
+
+
+def run_grover34(args):
+    """The headline: 34-qubit Grover search (1024 slices of 2^24, absolute
+    bound 1e-8), FP64, timed from the first oracle into its diffusion layer;
+    the FP32 leg beside it."""
+    import numpy as np
+    import qcircuits as qc
+
+    w = qc.grover_workload(n=34, slice_log2=24, eb=1e-8, seed=args.seed, iterations=1)
+    n, N = w.n_qubits, 1 << w.n_qubits
+    K, Wm = args.steps, args.warmup
+    start = n
+    print("[bench] grover34 FP64 leg", file=sys.stderr, flush=True)
+    r64 = run_grover34_leg(args, w, False, K, Wm)
+    layer_done = max(0, min(n, K - 1))  # diffusion H gates inside the window
+    idx = np.concatenate([np.arange(b, b + c) for b, c in r64["samples"]])
+    exact = grover_exact(n, w.basis, layer_done, idx) if K <= n + 1 else None
+
+    def err(a, b):
+        d = a - b
+        return {"max_abs": float(np.max(np.abs(d))), "l2": float(np.linalg.norm(d)),
+                "l2_rel": float(np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300))}
+
+    config = {"workload": "grover34: 34-qubit Grover search (marked index from seed %d), 1024 slices of 2^24 "
+                          "amplitudes (raw FP64 state 256 GiB, held compressed), absolute bound 1e-8, plain mode, "
+                          "FP64; passes %d..%d timed (the first oracle, then H on qubits 0..%d of its diffusion; "
+                          "every slice holds nonzero amplitudes), after the initial H layer"
+                          % (args.seed, start, start + K - 1, K - 2),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
-              "error_bound": w.error_bound, "passes_timed": K, "workspace_slots": st2["workspace_slots"],
-              "fp32": args.fp32}
-    line = report(args, w, sim, K * N / dt, K, Wm, dt, kt, st1, st2, None, config,
-                  plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16)
+              "error_bound": w.error_bound, "passes_timed": K, "first_timed_pass": start,
+              "workspace_slots": r64["st2"]["workspace_slots"], "fp32": False}
+    line = report(args, w, None, K * N / r64["dt"], K, Wm, r64["dt"], r64["kt"], r64["st1"], r64["st3"],
+                  r64["lat"], config, plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16,
+                  nslices=1 << (n - w.slice_log2))
+    acc = {"sample": "%d amplitudes in %d runs of 4096 (seeded offsets and the marked index's run)"
+                     % (idx.size, len(r64["samples"]))}
+    if exact is not None:
+        acc["fp64_vs_exact"] = err(r64["read"], exact)
+    if not args.no_fp32:
+        print("[bench] grover34 FP32 leg", file=sys.stderr, flush=True)
+        r32 = run_grover34_leg(args, w, True, K, Wm)
+        acc["fp32_vs_fp64"] = err(r32["read"], r64["read"])
+        if exact is not None:
+            acc["fp32_vs_exact"] = err(r32["read"], exact)
+        kt32 = r32["kt"]
+        ms32 = {k: v[0] / v[1] for k, v in kt32.items() if v[1] > 0}
+        line["fp32"] = {"value": K * N / r32["dt"], "unit": "amps/s", "ms_per_step": r32["dt"] / K * 1e3,
+                        "ratio": r32["st3"]["raw_bytes"] / r32["st3"]["compressed_bytes"],
+                        "min_ratio": r32["st3"]["min_ratio"], "kernel_ms_per_launch": ms32,
+                        "max_abs_codec_err": r32["st3"]["max_abs_codec_err"],
+                        "latency_ms_per_pass": {"p50": float(np.percentile(r32["lat"], 50)),
+                                                "p99": float(np.percentile(r32["lat"], 99))}
+                        if r32["lat"] else None}
+    line["accuracy"] = acc
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_sample(w, args.cpu_seconds, args.chunk_log2, fused_k=0, fp32=args.fp32)
+        print("[bench] grover34 CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_grover34(w, args.cpu_seconds, args.chunk_log2, K)
     return line
+
+
+def cpu_grover34(w, seconds, chunk_log2, K):
+    """The oracle on sampled slices of the headline window: one slice of the
+    state the window starts from (after the initial H layer every slice holds
+    the same values, 2^-17, and the oracle compresses it itself) put through
+    the window's slice-local passes (H on qubits 0, 1, ...) by
+    oracle.pass_group, each worker on its own slice; all workers for `seconds`,
+    then one for a third of that."""
+    import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    import qcircuits as qc
+    L = 1 << w.slice_log2
+    amp = np.full(L, 2.0 ** (-w.n_qubits / 2))
+    rec0, _ = oracle.compress_slice(amp, np.zeros(L), w.slice_log2, chunk_log2, w.error_bound, oracle.ABS)
+    # the scale of the whole stored state: 1024 equal slices
+    h = oracle.parse_header(rec0)
+    s = oracle.rsqrt(oracle.norm(np.full(1 << (w.n_qubits - w.slice_log2), h["step"]),
+                                 [h["sumsq"]] * (1 << (w.n_qubits - w.slice_log2))))
+    gates = [qc.H(q) for q in range(min(K, w.slice_log2))]
+
+    def worker(deadline):
+        rec, done, t = rec0, 0, time.perf_counter()
+        while time.perf_counter() < deadline:
+            rec = oracle.pass_group(w.n_qubits, w.slice_log2, chunk_log2, w.error_bound, oracle.ABS,
+                                    gates[done % len(gates)], s, [0], [rec])[0]
+            done += 1
+        return done
+
+    threads = min(16, len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        counts = list(ex.map(worker, [t0 + seconds] * threads))
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    one = worker(t1 + seconds / 3)
+    dt1 = time.perf_counter() - t1
+    total = sum(counts)
+    return {"value": total * L / dt, "unit": "amps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{total} single-slice passes (H on qubits 0..{len(gates) - 1} in turn) over slices of 2^"
+                      f"{w.slice_log2} amplitudes of the window's starting state, compressed by the oracle; "
+                      f"{threads} threads, one slice each, {dt:.1f} s",
+            "one_thread": {"value": one * L / dt1, "unit": "amps/s",
+                           "sample": f"{one} such passes on one thread, {dt1:.1f} s"}}
 
 
 def serve_jobs(count, seed):
@@ -587,7 +748,7 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    run = {"grover24": run_grover24, "qft30": run_qft30, "grover34": run_grover34, "qft12": run_qft12,
+    run = {"grover34": run_grover34, "grover24": run_grover24, "qft30": run_qft30, "qft12": run_qft12,
            "serve": run_serve}[args.workload]
     print(json.dumps(run(args)), flush=True)
 

@@ -230,6 +230,13 @@ uint64_t sim_record_size(sim_t *sim, uint64_t j);
  * self-describing: header, symbol table, chunk word offsets, bit stream. */
 int sim_export_slice(sim_t *sim, uint64_t j, void *buf, uint64_t cap, uint64_t *len);
 
+/* The 64-byte headers of the stored records of slices [first, first + count)
+ * into host memory `out` (64 * count bytes, caller-owned): per slice the
+ * step, the exact sum p^2 of its codes and its sizes -- what Normalize needs
+ * from every slice (Algorithm 1; the norm of the stored state), without the
+ * bit streams.  Synchronises the stream.  Errors: SIM_EINVAL (range). */
+int sim_record_headers(sim_t *sim, uint64_t first, uint64_t count, void *out);
+
 /* Replace the stored record of slice j by `len` bytes from host memory
  * (checkpoint restore).  The record is checked for consistency (SIM_ECORRUPT)
  * and must have the handle's slice and chunk sizes. */

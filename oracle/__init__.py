@@ -92,6 +92,7 @@ def lib():
         L.orc_sim_apply.argtypes = [C.c_void_p, C.POINTER(_Gate), C.c_uint64, C.POINTER(C.c_uint64)]
         L.orc_sim_scale.argtypes = [C.c_void_p]
         L.orc_sim_scale.restype = C.c_double
+        L.orc_sim_set_record.argtypes = [C.c_void_p, C.c_uint64, P, C.c_uint64]
         L.orc_sim_nslices.argtypes = [C.c_void_p]
         L.orc_sim_nslices.restype = C.c_uint64
         L.orc_sim_record_len.argtypes = [C.c_void_p, C.c_uint64]
@@ -110,6 +111,22 @@ def lib():
         L.orc_plan.argtypes = [C.POINTER(_Gate), C.c_uint64, C.POINTER(_Pass), C.c_uint64, C.POINTER(C.c_uint64)]
         L.orc_block_matrix.argtypes = [C.POINTER(_Gate), C.POINTER(_Pass), P]
         L.orc_sim_apply_fused.argtypes = [C.c_void_p, C.POINTER(_Gate), C.c_uint64, C.POINTER(C.c_uint64)]
+        L.orc_group_apply_local.argtypes = [C.POINTER(_Gate), C.c_int, C.c_int, P, P, P, C.c_int]
+        L.orc_vsim_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_uint32]
+        L.orc_vsim_create.restype = C.c_void_p
+        L.orc_vsim_destroy.argtypes = [C.c_void_p]
+        L.orc_vsim_init.argtypes = [C.c_void_p, C.c_int, C.c_uint64, P]
+        L.orc_vsim_apply.argtypes = [C.c_void_p, C.POINTER(_Gate), C.c_uint64, C.POINTER(C.c_uint64)]
+        L.orc_vsim_apply_fused.argtypes = [C.c_void_p, C.POINTER(_Gate), C.c_uint64, C.POINTER(C.c_uint64)]
+        L.orc_vsim_amplitudes.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, P]
+        L.orc_vsim_scale.argtypes = [C.c_void_p]
+        L.orc_vsim_scale.restype = C.c_double
+        L.orc_vsim_get.argtypes = [C.c_void_p, P, P, P, P]
+        L.orc_vsim_set.argtypes = [C.c_void_p, P, P, P, P, C.c_uint64, C.c_double]
+        L.orc_vsim_passes.argtypes = [C.c_void_p]
+        L.orc_vsim_passes.restype = C.c_uint64
+        L.orc_vsim_max_err.argtypes = [C.c_void_p]
+        L.orc_vsim_max_err.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -361,6 +378,24 @@ def pass_group(n: int, slice_log2: int, chunk_log2: int, eb: float, mode: int, g
     return res
 
 
+def group_apply_local(gate, slice_log2: int, members: Sequence[int], planes: List[np.ndarray],
+                      fp32: bool = False) -> List[np.ndarray]:
+    """group_apply through the code-level runner's addressing (local index
+    member * L + offset) instead of the search over members."""
+    s, keep = _gate_struct(gate)
+    m = len(members)
+    re = [np.ascontiguousarray(p.real, dtype=np.float64).copy() for p in planes]
+    im = [np.ascontiguousarray(p.imag, dtype=np.float64).copy() for p in planes]
+    rp = (C.c_void_p * m)(*[a.ctypes.data for a in re])
+    ip = (C.c_void_p * m)(*[a.ctypes.data for a in im])
+    mem = np.array(members, dtype=np.uint64)
+    rc = lib().orc_group_apply_local(C.byref(s), slice_log2, m, _ptr(mem), C.cast(rp, C.c_void_p),
+                                     C.cast(ip, C.c_void_p), int(fp32))
+    if rc:
+        raise OracleError(rc, "group_apply_local")
+    return [r + 1j * i for r, i in zip(re, im)]
+
+
 def group_members(n: int, slice_log2: int, gate, j0: int) -> List[int]:
     bits = [t - slice_log2 for t in gate.targets if t >= slice_log2] if gate.kind == 1 else []
     mem = []
@@ -462,6 +497,15 @@ class OracleSim:
     def records(self) -> List[bytes]:
         return [self.record(j) for j in range(self.nslices)]
 
+    def set_records(self, records: Sequence[bytes]):
+        """Replace every stored record (a state built elsewhere)."""
+        assert len(records) == self.nslices
+        for j, r in enumerate(records):
+            b = np.frombuffer(r, dtype=np.uint8).copy()
+            rc = lib().orc_sim_set_record(self._h, j, _ptr(b), len(r))
+            if rc:
+                raise OracleError(rc, f"set_record {j}")
+
     def scale(self) -> float:
         return lib().orc_sim_scale(self._h)
 
@@ -482,6 +526,107 @@ class OracleSim:
 
     def max_err(self) -> float:
         return float(lib().orc_sim_max_err(self._h))
+
+
+class CodeSim:
+    """Algorithm 1 at the level of the quantised codes (the lossless stages of
+    the codec elided, since they return the codes they are given): the same
+    amplitudes as OracleSim, for runs too long for the full codec.  Codes are
+    held as int32 (a pass that needs more fails with ORC_EBOUND)."""
+
+    def __init__(self, n: int, slice_log2: int, eb: float, mode: int = ABS):
+        self.n, self.slice_log2, self.eb, self.mode = n, slice_log2, eb, mode
+        self._h = lib().orc_vsim_create(n, slice_log2, eb, mode)
+        if not self._h:
+            raise OracleError(-2, "vsim_create")
+        self._init(0, 0, None)
+
+    def _init(self, kind, x, f):
+        rc = lib().orc_vsim_init(self._h, kind, x, None if f is None else _ptr(f))
+        if rc:
+            raise OracleError(rc, "vsim_init")
+
+    def close(self):
+        if self._h:
+            lib().orc_vsim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nslices(self) -> int:
+        return 1 << (self.n - self.slice_log2)
+
+    def init_basis(self, x: int):
+        self._init(1, x, None)
+
+    def init_product(self, factors: np.ndarray):
+        self._init(2, 0, np.ascontiguousarray(np.asarray(factors, dtype=np.complex128)).view(np.float64).copy())
+
+    def apply(self, gates: Sequence, fused: bool = False) -> int:
+        arr, keep = gate_array(gates)
+        applied = C.c_uint64()
+        fn = lib().orc_vsim_apply_fused if fused else lib().orc_vsim_apply
+        rc = fn(self._h, arr, len(gates), C.byref(applied))
+        if rc:
+            raise OracleError(rc, f"vsim_apply (after {applied.value} gates)")
+        return applied.value
+
+    def amplitudes(self, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = (1 << self.n) - begin
+        out = np.zeros(2 * count)
+        rc = lib().orc_vsim_amplitudes(self._h, begin, count, _ptr(out))
+        if rc:
+            raise OracleError(rc, "vsim_amplitudes")
+        return out[0::2] + 1j * out[1::2]
+
+    def amplitude_words(self, begin: int = 0, count: Optional[int] = None) -> np.ndarray:
+        """The read-out as interleaved (re, im) FP64 values (the layout of
+        sim_amplitudes), without the complex conversion."""
+        if count is None:
+            count = (1 << self.n) - begin
+        out = np.zeros(2 * count)
+        rc = lib().orc_vsim_amplitudes(self._h, begin, count, _ptr(out))
+        if rc:
+            raise OracleError(rc, "vsim_amplitudes")
+        return out
+
+    def scale(self) -> float:
+        return lib().orc_vsim_scale(self._h)
+
+    def state(self) -> dict:
+        S, L2 = self.nslices, 2 << self.slice_log2
+        d = dict(codes=np.zeros((S, L2), dtype=np.int32), step=np.zeros(S), lo=np.zeros(S, dtype=np.uint64),
+                 hi=np.zeros(S, dtype=np.uint64))
+        lib().orc_vsim_get(self._h, _ptr(d["codes"]), _ptr(d["step"]), _ptr(d["lo"]), _ptr(d["hi"]))
+        d["passes"] = int(lib().orc_vsim_passes(self._h))
+        d["max_err"] = float(lib().orc_vsim_max_err(self._h))
+        return d
+
+    def set_state(self, d: dict):
+        S, L2 = self.nslices, 2 << self.slice_log2
+        codes = np.ascontiguousarray(d["codes"], dtype=np.int32)
+        assert codes.shape == (S, L2)
+        st = np.ascontiguousarray(d["step"], dtype=np.float64)
+        lo = np.ascontiguousarray(d["lo"], dtype=np.uint64)
+        hi = np.ascontiguousarray(d["hi"], dtype=np.uint64)
+        lib().orc_vsim_set(self._h, _ptr(codes), _ptr(st), _ptr(lo), _ptr(hi), int(d["passes"]),
+                           float(d["max_err"]))
+
+    def codes(self, j: int) -> np.ndarray:
+        return self.state()["codes"][j].astype(np.int64)
+
+    @property
+    def passes(self) -> int:
+        return int(lib().orc_vsim_passes(self._h))
+
+    def max_err(self) -> float:
+        return float(lib().orc_vsim_max_err(self._h))
 
 
 def num_threads() -> int:

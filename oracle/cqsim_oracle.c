@@ -75,7 +75,7 @@ static void cmac(double ur, double ui, double ar, double ai, double *cr, double 
 #define ORC_FP32 2u
 
 /* Zero chunks (mode bit ORC_ZERO_CHUNKS; an extension toward the paper's
- * remark that other compressors may suit the state better, Section V): a
+ * remark that other compressors may suit the state better, Section IV): a
  * chunk whose codes p are all zero -- every symbol the zero difference R --
  * is stored with no words; its offset repeats.  The histogram, and so the
  * code, still counts its symbols.  Header word 14 bit 0 marks such records.
@@ -404,6 +404,39 @@ typedef struct {
   double step;
 } orc_cstats;
 
+/* Error-bounded quantisation, the first stage of Compress: the step from the
+ * bound (absolute, or relative to the values' range when mode bit 0 is set),
+ * then p = rint(v * r) for every value, refused (ORC_EBOUND) when |p| reaches
+ * 2^48 or |v - p * step| exceeds the bound.  *sumsq receives sum p^2 exactly. */
+static int quantise(const double *v, uint64_t nv, double eb, uint32_t mode, int64_t *p, double *step_out,
+                    double *max_err_out, unsigned __int128 *sumsq_out) {
+  double step, r, ebj;
+  if (mode & 1) {
+    orc_rel_step(eb, v, nv, &step, &r, &ebj);
+  } else {
+    orc_abs_step(eb, &step, &r);
+    ebj = eb;
+  }
+  double max_err = 0.0;
+  unsigned __int128 sumsq = 0;
+  for (uint64_t i = 0; i < nv; i++) {
+    double t = v[i] * r;
+    double q = rint(t);
+    if (!(fabs(q) < (double)ORC_PMAX)) return ORC_EBOUND;
+    p[i] = (int64_t)q;
+    double back = (double)p[i] * step;
+    double err = fabs(v[i] - back);
+    if (err > ebj) return ORC_EBOUND;
+    if (err > max_err) max_err = err;
+    unsigned __int128 sq = (unsigned __int128)((__int128)p[i] * (__int128)p[i]);
+    sumsq += sq;
+  }
+  *step_out = step;
+  *max_err_out = max_err;
+  *sumsq_out = sumsq;
+  return ORC_OK;
+}
+
 /* Compress one slice (Re plane then Im plane, L values each).
  * mode bit 0: 0 = absolute bound eb, 1 = relative bound eb (bit 1, ORC_FP32, does not
  * change the compressor: the values it gets are then FP32 numbers); ORC_ZERO_CHUNKS:
@@ -428,35 +461,9 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
   memcpy(v, re, sizeof(double) * L);
   memcpy(v + L, im, sizeof(double) * L);
 
-  double step, r, ebj;
-  if (mode & 1) {
-    orc_rel_step(eb, v, nv, &step, &r, &ebj);
-  } else {
-    orc_abs_step(eb, &step, &r);
-    ebj = eb;
-  }
-  int rc = ORC_OK;
-  double max_err = 0.0;
-  unsigned __int128 sumsq = 0;
-  /* error-bounded quantisation */
-  for (uint64_t i = 0; i < nv; i++) {
-    double t = v[i] * r;
-    double q = rint(t);
-    if (!(fabs(q) < (double)ORC_PMAX)) {
-      rc = ORC_EBOUND;
-      break;
-    }
-    p[i] = (int64_t)q;
-    double back = (double)p[i] * step;
-    double err = fabs(v[i] - back);
-    if (err > ebj) {
-      rc = ORC_EBOUND;
-      break;
-    }
-    if (err > max_err) max_err = err;
-    unsigned __int128 sq = (unsigned __int128)((__int128)p[i] * (__int128)p[i]);
-    sumsq += sq;
-  }
+  double step, max_err;
+  unsigned __int128 sumsq;
+  int rc = quantise(v, nv, eb, mode, p, &step, &max_err, &sumsq);
   if (rc != ORC_OK) {
     free(v); free(p); free(d); free(sym);
     return rc;
@@ -1307,6 +1314,27 @@ int orc_pass_group(int n, int slice_log2, int chunk_log2, double eb, uint32_t mo
   return rc;
 }
 
+/* Replace the stored record of slice j by a copy of rec (a state built
+ * elsewhere, e.g. to recompute one pass from given records).  The record
+ * must parse and have the simulator's geometry. */
+int orc_sim_set_record(orc_sim *s, uint64_t j, const uint8_t *rec, uint64_t len) {
+  orc_rec h;
+  if (j >= s->nslices) return ORC_EINVAL;
+  int rc = orc_parse(rec, len, &h);
+  if (rc) return rc;
+  if ((int)h.slice_log2 != s->slice_log2 || (int)h.chunk_log2 != s->chunk_log2) return ORC_EINVAL;
+  uint8_t *c = (uint8_t *)malloc(len);
+  if (!c) return ORC_ENOMEM;
+  memcpy(c, rec, len);
+  free(s->rec[j]);
+  s->rec[j] = c;
+  s->rec_len[j] = len;
+  s->step[j] = h.step;
+  s->sq_lo[j] = h.sumsq_lo;
+  s->sq_hi[j] = h.sumsq_hi;
+  return ORC_OK;
+}
+
 uint64_t orc_sim_nslices(const orc_sim *s) { return s->nslices; }
 uint64_t orc_sim_record_len(const orc_sim *s, uint64_t j) { return j < s->nslices ? s->rec_len[j] : 0; }
 int orc_sim_record(const orc_sim *s, uint64_t j, uint8_t *buf, uint64_t cap) {
@@ -1359,3 +1387,503 @@ void orc_set_threads(int t) {
   (void)t;
 #endif
 }
+
+/* ------------------------------------------------------- code-level runner
+ * The stages of Compress after the quantiser -- Lorenzo difference, symbols,
+ * escapes, Huffman code, record layout -- are lossless: Decompress returns
+ * exactly the codes p that Compress was given.  The amplitudes of a run of
+ * Algorithm 1 therefore depend only on the codes, the steps and the norm, and
+ * this runner keeps just those: the codes p of every slice (as int32; a pass
+ * that makes a code of magnitude 2^31 or more is refused with ORC_EBOUND),
+ * and the step and sum p^2 of every slice.  A pass is the full simulator's
+ * pass without the lossless stages: the global scale s from the norm of the
+ * stored state, a = p * (step_j * s), the gate on each group of slices, the
+ * quantiser.  It can follow runs far too long for the full codec (hundreds of
+ * thousands of passes over 2^24 amplitudes); tests check that it reproduces
+ * the full simulator's codes and amplitudes. */
+
+/* The gate on one group, as apply_gate_group computes it -- the same
+ * operations on the same operands in the same order -- with the amplitudes
+ * addressed by a local index u * L + o (member u, offset o): target bits
+ * below slice_log2 keep their position, the slice-bit targets take bits
+ * slice_log2, slice_log2 + 1, ... in the order group_of gives the members. */
+static int apply_gate_local(const orc_gate *g, int slice_log2, int nmem, const uint64_t *mem, double **re,
+                            double **im, int fp32) {
+  if (g->kind == ORC_PHASE) return apply_gate_group(g, slice_log2, nmem, mem, re, im, fp32);
+  if (g->kind != ORC_DENSE || g->n_targets < 1 || g->n_targets > 5) return ORC_EINVAL;
+  const uint64_t L = (uint64_t)1 << slice_log2, omask = L - 1;
+  const int k = (int)g->n_targets, dim = 1 << k;
+  uint64_t off[32], tl = 0;
+  int lb[5], nslice = 0;
+  for (int t = 0; t < k; t++) {
+    lb[t] = (int)g->targets[t] < slice_log2 ? (int)g->targets[t] : slice_log2 + nslice++;
+    tl |= (uint64_t)1 << lb[t];
+  }
+  if ((1 << nslice) != nmem) return ORC_EINVAL;
+  for (int m = 0; m < dim; m++) {
+    off[m] = 0;
+    for (int t = 0; t < k; t++)
+      if ((m >> t) & 1) off[m] |= (uint64_t)1 << lb[t];
+  }
+  double ur[1024], ui[1024];
+  for (int e = 0; e < dim * dim; e++) {
+    ur[e] = fp32 ? r32(g->matrix[2 * e]) : g->matrix[2 * e];
+    ui[e] = fp32 ? r32(g->matrix[2 * e + 1]) : g->matrix[2 * e + 1];
+  }
+  double in_r[32], in_i[32], out_r[32], out_i[32];
+  const uint64_t total = (uint64_t)nmem << slice_log2;
+  if (k == 1) { /* the loop below written out for one target */
+    for (uint64_t li = 0; li < total; li++) {
+      if (li & tl) continue;
+      const uint64_t gi = (mem[li >> slice_log2] << slice_log2) | (li & omask);
+      if ((gi & g->ctrl_mask) != g->ctrl_vals) continue;
+      const uint64_t x1 = li | off[1];
+      double *r0 = &re[li >> slice_log2][li & omask], *i0 = &im[li >> slice_log2][li & omask];
+      double *r1 = &re[x1 >> slice_log2][x1 & omask], *i1 = &im[x1 >> slice_log2][x1 & omask];
+      const double a0r = *r0, a0i = *i0, a1r = *r1, a1i = *i1;
+      double c0r = 0.0, c0i = 0.0, c1r = 0.0, c1i = 0.0;
+      cmac_m(fp32, ur[0], ui[0], a0r, a0i, &c0r, &c0i);
+      cmac_m(fp32, ur[1], ui[1], a1r, a1i, &c0r, &c0i);
+      cmac_m(fp32, ur[2], ui[2], a0r, a0i, &c1r, &c1i);
+      cmac_m(fp32, ur[3], ui[3], a1r, a1i, &c1r, &c1i);
+      *r0 = c0r;
+      *i0 = c0i;
+      *r1 = c1r;
+      *i1 = c1i;
+    }
+    return ORC_OK;
+  }
+  for (uint64_t li = 0; li < total; li++) {
+    if (li & tl) continue;
+    const uint64_t gi = (mem[li >> slice_log2] << slice_log2) | (li & omask);
+    if ((gi & g->ctrl_mask) != g->ctrl_vals) continue;
+    for (int m = 0; m < dim; m++) {
+      const uint64_t x = li | off[m];
+      in_r[m] = re[x >> slice_log2][x & omask];
+      in_i[m] = im[x >> slice_log2][x & omask];
+    }
+    for (int r = 0; r < dim; r++) {
+      double cr = 0.0, ci = 0.0;
+      for (int c = 0; c < dim; c++) cmac_m(fp32, ur[r * dim + c], ui[r * dim + c], in_r[c], in_i[c], &cr, &ci);
+      out_r[r] = cr;
+      out_i[r] = ci;
+    }
+    for (int m = 0; m < dim; m++) {
+      const uint64_t x = li | off[m];
+      re[x >> slice_log2][x & omask] = out_r[m];
+      im[x >> slice_log2][x & omask] = out_i[m];
+    }
+  }
+  return ORC_OK;
+}
+
+/* The same gate through both addressings (tests compare them). */
+int orc_group_apply_local(const orc_gate *g, int slice_log2, int nmem, const uint64_t *slices, double **re,
+                          double **im, int fp32) {
+  return apply_gate_local(g, slice_log2, nmem, slices, re, im, fp32);
+}
+
+typedef struct {
+  int n, slice_log2;
+  double eb;
+  uint32_t mode;
+  uint64_t nslices, L;
+  int32_t *p; /* [nslices][2L]: real plane, then imaginary plane */
+  double *step;
+  uint64_t *sq_lo, *sq_hi;
+  int32_t *p2; /* the same for the output of a pass */
+  double *step2;
+  uint64_t *lo2, *hi2;
+  double max_err;
+  uint64_t passes;
+} orc_vsim;
+
+void orc_vsim_destroy(orc_vsim *s);
+
+orc_vsim *orc_vsim_create(int n, int slice_log2, double eb, uint32_t mode) {
+  if (n < 1 || n > 40 || slice_log2 < 1 || slice_log2 > n || slice_log2 > 26) return NULL;
+  orc_vsim *s = (orc_vsim *)calloc(1, sizeof(orc_vsim));
+  if (!s) return NULL;
+  s->n = n;
+  s->slice_log2 = slice_log2;
+  s->eb = eb;
+  s->mode = mode;
+  s->nslices = (uint64_t)1 << (n - slice_log2);
+  s->L = (uint64_t)1 << slice_log2;
+  s->p = (int32_t *)calloc(s->nslices * 2 * s->L, sizeof(int32_t));
+  s->step = (double *)calloc(s->nslices, sizeof(double));
+  s->sq_lo = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+  s->sq_hi = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+  s->p2 = (int32_t *)calloc(s->nslices * 2 * s->L, sizeof(int32_t));
+  s->step2 = (double *)calloc(s->nslices, sizeof(double));
+  s->lo2 = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+  s->hi2 = (uint64_t *)calloc(s->nslices, sizeof(uint64_t));
+  if (!s->p || !s->step || !s->sq_lo || !s->sq_hi || !s->p2 || !s->step2 || !s->lo2 || !s->hi2) {
+    orc_vsim_destroy(s);
+    return NULL;
+  }
+  return s;
+}
+
+void orc_vsim_destroy(orc_vsim *s) {
+  if (!s) return;
+  free(s->p); free(s->step); free(s->sq_lo); free(s->sq_hi);
+  free(s->p2); free(s->step2); free(s->lo2); free(s->hi2);
+  free(s);
+}
+
+/* Quantise one slice's 2L values into codes; fills the slice's step and
+ * sum p^2 into the given outputs. */
+static int vsim_quantise(const orc_vsim *s, const double *v, int32_t *codes, int64_t *tmp, double *step,
+                         uint64_t *lo, uint64_t *hi, double *max_err) {
+  unsigned __int128 sq;
+  int rc = quantise(v, 2 * s->L, s->eb, s->mode, tmp, step, max_err, &sq);
+  if (rc) return rc;
+  for (uint64_t i = 0; i < 2 * s->L; i++) {
+    if (tmp[i] > INT32_MAX || tmp[i] < -INT32_MAX) return ORC_EBOUND;
+    codes[i] = (int32_t)tmp[i];
+  }
+  *lo = (uint64_t)sq;
+  *hi = (uint64_t)(sq >> 64);
+  return ORC_OK;
+}
+
+/* Initial states as orc_sim_init builds them. */
+int orc_vsim_init(orc_vsim *s, int kind, uint64_t x, const double *f) {
+  const uint64_t L = s->L;
+  const int fp32 = (s->mode & ORC_FP32) != 0;
+  int rc_all = ORC_OK;
+  double err_all = 0.0;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t j = 0; j < (int64_t)s->nslices; j++) {
+    double *v = (double *)calloc(2 * L, sizeof(double));
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * 2 * L);
+    int rc = v && tmp ? ORC_OK : ORC_ENOMEM;
+    for (uint64_t o = 0; o < L && rc == ORC_OK; o++) {
+      uint64_t gi = ((uint64_t)j << s->slice_log2) | o;
+      if (kind == 0) {
+        v[o] = gi == 0 ? 1.0 : 0.0;
+      } else if (kind == 1) {
+        v[o] = gi == x ? 1.0 : 0.0;
+      } else {
+        double ar = 1.0, ai = 0.0;
+        for (int q = 0; q < s->n; q++) {
+          int b = (int)((gi >> q) & 1);
+          double cr = 0.0, ci = 0.0;
+          const double fr = f[4 * q + 2 * b], fi = f[4 * q + 2 * b + 1];
+          cmac_m(fp32, fp32 ? r32(fr) : fr, fp32 ? r32(fi) : fi, ar, ai, &cr, &ci);
+          ar = cr;
+          ai = ci;
+        }
+        v[o] = ar;
+        v[L + o] = ai;
+      }
+    }
+    double err = 0.0;
+    if (rc == ORC_OK)
+      rc = vsim_quantise(s, v, s->p + (uint64_t)j * 2 * L, tmp, &s->step[j], &s->sq_lo[j], &s->sq_hi[j], &err);
+#pragma omp critical
+    {
+      if (rc) rc_all = rc;
+      if (err > err_all) err_all = err;
+    }
+    free(v);
+    free(tmp);
+  }
+  if (err_all > s->max_err) s->max_err = err_all;
+  return rc_all;
+}
+
+double orc_vsim_scale(const orc_vsim *s) {
+  return orc_rsqrt(orc_norm((int)s->nslices, s->step, s->sq_lo, s->sq_hi));
+}
+
+/* One pass of one gate.  The new codes go to a second buffer, so a failing
+ * pass leaves the state as it was. */
+static int vsim_pass(orc_vsim *s, const orc_gate *g, int32_t *np, double *nstep, uint64_t *nlo, uint64_t *nhi) {
+  const uint64_t L = s->L;
+  const int fp32 = (s->mode & ORC_FP32) != 0;
+  const double scale = orc_vsim_scale(s);
+  orc_sim view; /* for the group helpers: geometry only */
+  memset(&view, 0, sizeof(view));
+  view.n = s->n;
+  view.slice_log2 = s->slice_log2;
+  view.nslices = s->nslices;
+  int rc = check_gate(&view, g);
+  if (rc) return rc;
+  const uint64_t gm = group_mask(&view, g);
+  int rc_all = ORC_OK;
+  double err_all = 0.0;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t j0 = 0; j0 < (int64_t)s->nslices; j0++) {
+    if ((uint64_t)j0 & gm) continue; /* not a group leader */
+    uint64_t mem[32];
+    const int nmem = group_of(&view, g, (uint64_t)j0, mem);
+    double *buf = (double *)malloc(sizeof(double) * 2 * L * (uint64_t)nmem);
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * 2 * L);
+    int rc2 = buf && tmp ? ORC_OK : ORC_ENOMEM;
+    double *re[32], *im[32];
+    double err = 0.0;
+    for (int u = 0; u < nmem && rc2 == ORC_OK; u++) { /* Decompress + Normalize */
+      const uint64_t j = mem[u];
+      const double k = s->step[j] * scale;
+      const int32_t *c = s->p + j * 2 * L;
+      double *v = buf + (uint64_t)u * 2 * L;
+      for (uint64_t i = 0; i < 2 * L; i++) {
+        double a = (double)c[i] * k;
+        v[i] = fp32 ? r32(a) : a;
+      }
+      re[u] = v;
+      im[u] = v + L;
+    }
+    if (rc2 == ORC_OK) rc2 = apply_gate_local(g, s->slice_log2, nmem, mem, re, im, fp32); /* GateComputation */
+    for (int u = 0; u < nmem && rc2 == ORC_OK; u++) {                                    /* Compress */
+      const uint64_t j = mem[u];
+      double e = 0.0;
+      rc2 = vsim_quantise(s, buf + (uint64_t)u * 2 * L, np + j * 2 * L, tmp, &nstep[j], &nlo[j], &nhi[j], &e);
+      if (e > err) err = e;
+    }
+#pragma omp critical
+    {
+      if (rc2) rc_all = rc2;
+      if (err > err_all) err_all = err;
+    }
+    free(buf);
+    free(tmp);
+  }
+  if (rc_all == ORC_OK && err_all > s->max_err) s->max_err = err_all;
+  return rc_all;
+}
+
+/* ABS mode with a one-target dense gate or a phase gate: Decompress,
+ * Normalize, GateComputation and the quantiser in one sweep over each group
+ * of one or two slices, with the operations of the general pass on every
+ * value (apply_gate_group's complex multiply-adds, quantise's steps and
+ * checks; sum p^2 is exact, so its order does not matter).  Returns 1 when
+ * the gate is not of this kind (the general pass runs instead). */
+static int vsim_pass_abs1(orc_vsim *s, const orc_gate *g, int32_t *np, double *nstep, uint64_t *nlo,
+                          uint64_t *nhi, int *rc_out) {
+  if ((s->mode & 1) || !(g->kind == ORC_PHASE || (g->kind == ORC_DENSE && g->n_targets == 1))) return 1;
+  const uint64_t L = s->L, sl2 = (uint64_t)s->slice_log2;
+  const int fp32 = (s->mode & ORC_FP32) != 0;
+  const double scale = orc_vsim_scale(s);
+  double step, r;
+  orc_abs_step(s->eb, &step, &r);
+  const double eb = s->eb;
+  const int dense = g->kind == ORC_DENSE;
+  const uint64_t t = dense ? g->targets[0] : 0;
+  const int cross = dense && t >= sl2;            /* pairs across two slices */
+  const uint64_t gm = cross ? (uint64_t)1 << (t - sl2) : 0;
+  const uint64_t tb = dense && !cross ? (uint64_t)1 << t : 0;
+  double u[8];
+  if (dense)
+    for (int e = 0; e < 8; e++) u[e] = fp32 ? r32(g->matrix[e]) : g->matrix[e];
+  const double phr = fp32 ? r32(g->phase_re) : g->phase_re, phi = fp32 ? r32(g->phase_im) : g->phase_im;
+  int rc_all = ORC_OK;
+  double err_all = 0.0;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t j0 = 0; j0 < (int64_t)s->nslices; j0++) {
+    if ((uint64_t)j0 & gm) continue;
+    const uint64_t ja = (uint64_t)j0, jb = ja | gm;
+    const double ka = s->step[ja] * scale, kb = s->step[jb] * scale;
+    const int32_t *pa = s->p + ja * 2 * L, *pb = s->p + jb * 2 * L;
+    int32_t *oa = np + ja * 2 * L, *ob = np + jb * 2 * L;
+    unsigned __int128 sqa = 0, sqb = 0;
+    double err = 0.0;
+    int bad = 0;
+#define CQ_DEC(c, k) (fp32 ? r32((double)(c) * (k)) : (double)(c) * (k))
+#define CQ_QUANT(v, dst, sq)                                                     \
+  do {                                                                           \
+    const double q_ = rint((v) * r);                                             \
+    if (!(fabs(q_) < 2147483648.0)) {                                            \
+      bad = 1;                                                                   \
+      (dst) = 0;                                                                 \
+    } else {                                                                     \
+      const int64_t p_ = (int64_t)q_;                                            \
+      const double e_ = fabs((v) - (double)p_ * step);                           \
+      if (e_ > eb) bad = 1;                                                      \
+      if (e_ > err) err = e_;                                                    \
+      (dst) = (int32_t)p_;                                                       \
+      (sq) += (unsigned __int128)((__int128)p_ * (__int128)p_);                  \
+    }                                                                            \
+  } while (0)
+    if (!dense) { /* phase gate: one slice */
+      for (uint64_t o = 0; o < L; o++) {
+        const uint64_t gi = (ja << sl2) | o;
+        double ar = CQ_DEC(pa[o], ka), ai = CQ_DEC(pa[L + o], ka);
+        if ((gi & g->ctrl_mask) == g->ctrl_vals) {
+          double cr = 0.0, ci = 0.0;
+          cmac_m(fp32, phr, phi, ar, ai, &cr, &ci);
+          ar = cr;
+          ai = ci;
+        }
+        CQ_QUANT(ar, oa[o], sqa);
+        CQ_QUANT(ai, oa[L + o], sqa);
+      }
+    } else {
+      /* pairs (x0, x1): x1 = x0 | tb inside slice ja, or offset o of slices ja and jb */
+      const uint64_t npair = cross ? L : L / 2;
+      for (uint64_t i = 0; i < npair; i++) {
+        const uint64_t o0 = cross ? i : ((i & ~(tb - 1)) << 1) | (i & (tb - 1));
+        const uint64_t o1 = cross ? i : (o0 | tb);
+        const int32_t *p1 = cross ? pb : pa;
+        int32_t *q1 = cross ? ob : oa;
+        const double k1 = cross ? kb : ka;
+        const uint64_t g0 = (ja << sl2) | o0;  /* controls never touch the target bit */
+        double a0r = CQ_DEC(pa[o0], ka), a0i = CQ_DEC(pa[L + o0], ka);
+        double a1r = CQ_DEC(p1[o1], k1), a1i = CQ_DEC(p1[L + o1], k1);
+        if ((g0 & g->ctrl_mask) == g->ctrl_vals) {
+          double c0r = 0.0, c0i = 0.0, c1r = 0.0, c1i = 0.0;
+          cmac_m(fp32, u[0], u[1], a0r, a0i, &c0r, &c0i);
+          cmac_m(fp32, u[2], u[3], a1r, a1i, &c0r, &c0i);
+          cmac_m(fp32, u[4], u[5], a0r, a0i, &c1r, &c1i);
+          cmac_m(fp32, u[6], u[7], a1r, a1i, &c1r, &c1i);
+          a0r = c0r;
+          a0i = c0i;
+          a1r = c1r;
+          a1i = c1i;
+        }
+        CQ_QUANT(a0r, oa[o0], sqa);
+        CQ_QUANT(a0i, oa[L + o0], sqa);
+        if (cross) {
+          CQ_QUANT(a1r, q1[o1], sqb);
+          CQ_QUANT(a1i, q1[L + o1], sqb);
+        } else {
+          CQ_QUANT(a1r, q1[o1], sqa);
+          CQ_QUANT(a1i, q1[L + o1], sqa);
+        }
+      }
+    }
+#undef CQ_DEC
+#undef CQ_QUANT
+    nstep[ja] = step;
+    nlo[ja] = (uint64_t)sqa;
+    nhi[ja] = (uint64_t)(sqa >> 64);
+    if (cross) {
+      nstep[jb] = step;
+      nlo[jb] = (uint64_t)sqb;
+      nhi[jb] = (uint64_t)(sqb >> 64);
+    }
+#pragma omp critical
+    {
+      if (bad) rc_all = ORC_EBOUND;
+      if (err > err_all) err_all = err;
+    }
+  }
+  if (rc_all == ORC_OK && err_all > s->max_err) s->max_err = err_all;
+  *rc_out = rc_all;
+  return 0;
+}
+
+static int vsim_run(orc_vsim *s, const orc_gate *g) {
+  int rc = ORC_OK;
+  orc_sim view; /* geometry for check_gate */
+  memset(&view, 0, sizeof(view));
+  view.n = s->n;
+  view.slice_log2 = s->slice_log2;
+  view.nslices = s->nslices;
+  if ((rc = check_gate(&view, g))) return rc;
+  if (vsim_pass_abs1(s, g, s->p2, s->step2, s->lo2, s->hi2, &rc)) rc = vsim_pass(s, g, s->p2, s->step2, s->lo2, s->hi2);
+  if (rc == ORC_OK) {
+    int32_t *t = s->p; s->p = s->p2; s->p2 = t;
+    double *ts = s->step; s->step = s->step2; s->step2 = ts;
+    uint64_t *tl = s->sq_lo; s->sq_lo = s->lo2; s->lo2 = tl;
+    uint64_t *th = s->sq_hi; s->sq_hi = s->hi2; s->hi2 = th;
+    s->passes++;
+  }
+  return rc;
+}
+
+/* Plain mode: one pass per gate; *applied counts completed passes. */
+int orc_vsim_apply(orc_vsim *s, const orc_gate *gates, uint64_t ngates, uint64_t *applied) {
+  *applied = 0;
+  for (uint64_t i = 0; i < ngates; i++) {
+    int rc = vsim_run(s, &gates[i]);
+    if (rc) return rc;
+    *applied = i + 1;
+  }
+  return ORC_OK;
+}
+
+/* Fused mode, with the partition and block matrices of orc_sim_apply_fused;
+ * *applied counts the gates of completed passes. */
+int orc_vsim_apply_fused(orc_vsim *s, const orc_gate *gates, uint64_t ngates, uint64_t *applied) {
+  *applied = 0;
+  uint64_t np = 0;
+  orc_plan(gates, ngates, NULL, 0, &np);
+  orc_pass *plan = (orc_pass *)calloc(np ? np : 1, sizeof(orc_pass));
+  double *U = (double *)malloc(sizeof(double) * 2 * 32 * 32);
+  if (!plan || !U) {
+    free(plan);
+    free(U);
+    return ORC_ENOMEM;
+  }
+  orc_plan(gates, ngates, plan, np, &np);
+  int rc = ORC_OK;
+  for (uint64_t i = 0; i < np && rc == ORC_OK; i++) {
+    const orc_pass *p = &plan[i];
+    if (!p->fused) {
+      rc = vsim_run(s, &gates[p->first]);
+    } else {
+      rc = orc_block_matrix(gates, p, U);
+      if (rc) break;
+      orc_gate g;
+      memset(&g, 0, sizeof(g));
+      if (p->k == 0) {
+        g.kind = ORC_PHASE;
+        g.phase_re = U[0];
+        g.phase_im = U[1];
+      } else {
+        g.kind = ORC_DENSE;
+        g.n_targets = p->k;
+        for (uint32_t t = 0; t < p->k; t++) g.targets[t] = p->qubits[t];
+        g.matrix = U;
+      }
+      rc = vsim_run(s, &g);
+    }
+    if (rc == ORC_OK) *applied += p->count;
+  }
+  free(plan);
+  free(U);
+  return rc;
+}
+
+/* Normalised amplitudes [begin, begin + count), interleaved (re, im), as
+ * orc_sim_amplitudes reads them out. */
+int orc_vsim_amplitudes(const orc_vsim *s, uint64_t begin, uint64_t count, double *out) {
+  const uint64_t N = (uint64_t)1 << s->n, L = s->L;
+  if (begin > N || count > N - begin) return ORC_EINVAL;
+  const double scale = orc_vsim_scale(s);
+  const int fp32 = (s->mode & ORC_FP32) != 0;
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < (int64_t)count; t++) {
+    const uint64_t i = begin + (uint64_t)t, j = i >> s->slice_log2, o = i & (L - 1);
+    const double k = s->step[j] * scale;
+    double ar = (double)s->p[j * 2 * L + o] * k, ai = (double)s->p[j * 2 * L + L + o] * k;
+    out[2 * t] = fp32 ? r32(ar) : ar;
+    out[2 * t + 1] = fp32 ? r32(ai) : ai;
+  }
+  return ORC_OK;
+}
+
+/* The whole state: codes [nslices][2L], steps, sum p^2 (low, high words);
+ * get copies it out, set replaces it (a checkpoint of a long run). */
+void orc_vsim_get(const orc_vsim *s, int32_t *codes, double *step, uint64_t *lo, uint64_t *hi) {
+  memcpy(codes, s->p, sizeof(int32_t) * s->nslices * 2 * s->L);
+  memcpy(step, s->step, sizeof(double) * s->nslices);
+  memcpy(lo, s->sq_lo, sizeof(uint64_t) * s->nslices);
+  memcpy(hi, s->sq_hi, sizeof(uint64_t) * s->nslices);
+}
+
+void orc_vsim_set(orc_vsim *s, const int32_t *codes, const double *step, const uint64_t *lo, const uint64_t *hi,
+                  uint64_t passes, double max_err) {
+  memcpy(s->p, codes, sizeof(int32_t) * s->nslices * 2 * s->L);
+  memcpy(s->step, step, sizeof(double) * s->nslices);
+  memcpy(s->sq_lo, lo, sizeof(uint64_t) * s->nslices);
+  memcpy(s->sq_hi, hi, sizeof(uint64_t) * s->nslices);
+  s->passes = passes;
+  s->max_err = max_err;
+}
+
+uint64_t orc_vsim_passes(const orc_vsim *s) { return s->passes; }
+double orc_vsim_max_err(const orc_vsim *s) { return s->max_err; }

@@ -36,7 +36,7 @@ ERRORS = {-1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EBOUND", -4: "SIM_ECORRUP
 # every entry point declared in include/cqsim.h
 EXPORTS = ("sim_create", "sim_create_ex", "sim_destroy", "sim_last_error", "sim_init_basis", "sim_init_product",
            "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_amplitudes", "sim_probabilities", "sim_stats",
-           "sim_record_size", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan",
+           "sim_record_size", "sim_record_headers", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan",
            "sim_graph_create", "sim_graph_launch", "sim_graph_destroy", "sim_footprint",
            "sim_tune_chunk", "srv_create", "srv_submit", "srv_wait", "srv_clock", "srv_projected_bytes",
            "srv_destroy")
@@ -128,6 +128,7 @@ def lib():
         L.sim_record_size.argtypes = [P, C.c_uint64]
         L.sim_record_size.restype = C.c_uint64
         L.sim_export_slice.argtypes = [P, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64)]
+        L.sim_record_headers.argtypes = [P, C.c_uint64, C.c_uint64, P]
         L.sim_import_slice.argtypes = [P, C.c_uint64, P, C.c_uint64]
         L.sim_kernel_times.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_char_p)]
         L.sim_graph_create.argtypes = [P, C.POINTER(GateStruct), C.c_size_t, C.POINTER(P)]
@@ -243,6 +244,11 @@ class _TorchMemory:
         def _alloc(nbytes, ctx):
             try:
                 t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+                # The caching allocator may hand out a block whose last use is
+                # still queued on torch's current stream; the library may run
+                # on another stream (its own, when torch's is the null
+                # stream), so that work must finish before the block is used.
+                torch.cuda.current_stream().synchronize()
             except Exception:
                 return None
             p = t.data_ptr()
@@ -273,7 +279,11 @@ class Sim:
     def __init__(self, n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False,
                  chunk_log2: int = 0, workspace_bytes: int = 0, use_torch: Optional[bool] = None,
                  arena_bytes: int = 0, fused: bool = False, fp32: bool = False, zero_chunks: bool = False,
-                 const_chunks: bool = False):
+                 const_chunks: bool = False, allocator=None):
+        """allocator: optional (ALLOC_FN, FREE_FN) pair of device-memory hooks
+        (sim_config.alloc / free_fn); the caller keeps them alive as long as
+        the Sim.  Otherwise torch's caching allocator (when torch sees a
+        device) or hipMalloc."""
         L = lib()
         cfg = _config(n_qubits, slice_log2, error_bound, relative=relative, chunk_log2=chunk_log2,
                       workspace_bytes=workspace_bytes, arena_bytes=arena_bytes, fused=fused, fp32=fp32,
@@ -281,7 +291,10 @@ class Sim:
         self._mem = None
         if use_torch is None:
             use_torch = _torch_ready()
-        if use_torch:
+        if allocator is not None:
+            cfg.alloc, cfg.free_fn = allocator
+            self._hooks = allocator
+        elif use_torch:
             self._mem = _TorchMemory()
             cfg.alloc = self._mem.alloc
             cfg.free_fn = self._mem.free
@@ -371,6 +384,16 @@ class Sim:
         _check(lib().sim_export_slice(self._h, j, buf.ctypes.data_as(C.c_void_p), n, C.byref(ln)),
                "sim_export_slice")
         return buf[:ln.value].tobytes()
+
+    def headers(self, first: int = 0, count: Optional[int] = None) -> List[bytes]:
+        """The 64-byte headers of the stored records of slices [first, first + count)."""
+        if count is None:
+            count = self.nslices - first
+        buf = np.zeros(64 * max(count, 1), dtype=np.uint8)
+        _check(lib().sim_record_headers(self._h, first, count, buf.ctypes.data_as(C.c_void_p)),
+               "sim_record_headers")
+        b = buf.tobytes()
+        return [b[64 * i:64 * (i + 1)] for i in range(count)]
 
     def records(self, which: Optional[Iterable[int]] = None) -> List[bytes]:
         return [self.record(j) for j in (range(self.nslices) if which is None else which)]

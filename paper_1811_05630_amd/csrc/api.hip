@@ -537,14 +537,38 @@ int clear_flags(sim_t *s) {
   return check_launch("reset_slots");
 }
 
+uint64_t min_record_total(const sim_t *s);
+
+// Replace arena `which` (its contents are dead: the output of the next pass)
+// by one of at least max(2 x its capacity, min_cap, the smallest possible
+// state) bytes.  The old block is freed first, so that the peak stays low;
+// when the larger one cannot be had, the old capacity is requested again
+// and SIM_ENOMEM returned.  An arena that cannot be restored either is left
+// empty (capacity 0), and ensure_arenas refuses the next pass.
 int grow_arena(sim_t *s, int which, uint64_t min_cap) {
-  uint64_t cap = std::max<uint64_t>(2 * s->arena_cap[which], min_cap);
+  const uint64_t old = s->arena_cap[which];
+  const uint64_t cap = std::max<uint64_t>(std::max<uint64_t>(2 * old, min_cap), 4 * min_record_total(s));
   s->dfree(s->arena[which]);
   s->arena[which] = nullptr;
   s->arena_cap[which] = 0;
   int rc = s->dalloc((void **)&s->arena[which], cap);
-  if (rc) return rc;
-  s->arena_cap[which] = cap;
+  if (rc == SIM_OK) {
+    s->arena_cap[which] = cap;
+    return SIM_OK;
+  }
+  const std::string why = g_last_error;
+  if (old && s->dalloc((void **)&s->arena[which], old) == SIM_OK) s->arena_cap[which] = old;
+  return set_err(SIM_ENOMEM, "record arena could not grow to %llu bytes: %s", (unsigned long long)cap, why.c_str());
+}
+
+// Both arenas must exist before passes are enqueued (a failed growth may
+// have left one empty): allocate a missing one at the initial size.
+int ensure_arenas(sim_t *s) {
+  for (int a = 0; a < 2; a++)
+    if (!s->arena[a]) {
+      int rc = grow_arena(s, a, std::max<uint64_t>(s->arena_cap[1 - a], 16ull << 20));
+      if (rc) return rc;
+    }
   return SIM_OK;
 }
 
@@ -554,7 +578,13 @@ int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, i
   size_t applied = 0;
   int rc = SIM_OK;
   size_t total = descs ? n : 1;
-  for (int attempt = 0; applied < total && attempt < 64; attempt++) {
+  if (applied_out) *applied_out = 0;
+  if ((rc = ensure_arenas(s))) return rc;
+  for (int attempt = 0; applied < total; attempt++) {
+    if (attempt == 64) {
+      rc = set_err(SIM_ENOMEM, "a pass overflowed its record arena 64 times in a row");
+      break;
+    }
     const uint32_t start_pass = s->pass_counter;
     const int cur_start = s->cur;
     for (size_t i = applied; i < total; i++) {
@@ -572,19 +602,21 @@ int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, i
       applied = total;
       // the next pass writes the other arena: give it a quarter above the
       // stored state's size now, since an overflow inside a later batch
-      // costs a device synchronisation, a reallocation and a replay
+      // costs a device synchronisation, a reallocation and a replay.  This
+      // growth is optional: when it fails the arena keeps its size, and an
+      // overflow later grows it then (or reports SIM_ENOMEM)
       const int tgt = 1 - s->cur;
       const uint64_t want = s->h_ctl->bump + s->h_ctl->bump / 4;
-      if (want > s->arena_cap[tgt]) (void)grow_arena(s, tgt, want);  // on failure the next batch retries
+      if (want > s->arena_cap[tgt]) (void)grow_arena(s, tgt, want);
       break;
     }
     const uint32_t done = s->h_ctl->fail_pass - start_pass;  // passes that completed
     s->cur = cur_start ^ (int)(done & 1);
     s->pass_counter = start_pass + done;
     applied += done;
-    if ((rc = clear_flags(s))) return rc;
+    if ((rc = clear_flags(s))) break;
     if (flags & kFlagOverflow) {
-      if ((rc = grow_arena(s, 1 - s->cur, 0))) return rc;
+      if ((rc = grow_arena(s, 1 - s->cur, 0))) break;
       continue;
     }
     if (flags & kFlagCorrupt) {
@@ -1119,6 +1151,7 @@ int sim_graph_launch(sim_t *s, sim_graph_t *G, size_t *n_applied) {
   if (n == 0) return SIM_OK;
   size_t applied = 0;
   int rc = SIM_OK;
+  if ((rc = ensure_arenas(s))) return rc;
   HIP_TRY(hipEventRecord(s->ev0, s->stream));
   if (s->cur != G->start_cur) {  // the other parity: ordinary launches of the same passes
     rc = run_passes(s, G->descs.data(), G->gms.data(), n, -1, 0, &applied);
@@ -1318,6 +1351,19 @@ int sim_export_slice(sim_t *s, uint64_t j, void *buf, uint64_t cap, uint64_t *le
   if (cap < len) return set_err(SIM_EINVAL, "buffer of %llu bytes is smaller than the record (%u)",
                                 (unsigned long long)cap, len);
   HIP_TRY(hipMemcpy(buf, s->arena[s->cur] + off, len, hipMemcpyDeviceToHost));
+  return SIM_OK;
+}
+
+int sim_record_headers(sim_t *s, uint64_t first, uint64_t count, void *out) {
+  if (!s || (count && !out)) return set_err(SIM_EINVAL, "null argument");
+  if (first > s->nslices || count > s->nslices - first) return set_err(SIM_EINVAL, "slice range out of bounds");
+  if (!count) return SIM_OK;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  std::vector<uint64_t> off(count);
+  HIP_TRY(hipMemcpy(off.data(), s->meta[s->cur].rec_off + first, 8 * count, hipMemcpyDeviceToHost));
+  uint8_t *o = (uint8_t *)out;
+  for (uint64_t i = 0; i < count; i++)
+    HIP_TRY(hipMemcpy(o + (uint64_t)kHdr * i, s->arena[s->cur] + off[i], kHdr, hipMemcpyDeviceToHost));
   return SIM_OK;
 }
 

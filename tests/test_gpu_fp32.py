@@ -57,21 +57,59 @@ def test_fp32_grover_small():
     assert np.array_equal(sim.amplitudes(), orc.amplitudes())
 
 
+def decoded_state32(recs):
+    """The stored state decoded by the oracle in FP32 mode, scaled like a read-out."""
+    s = oracle.scale_from_records(recs)
+    return np.concatenate([oracle.decompress_slice(r, oracle.parse_header(r)["step"] * s, oracle.FP32)
+                           for r in recs])
+
+
 def test_fp32_fused_blocks():
+    """Fused QFT in FP32 mode, one pass at a time against the oracle's FP32
+    fused pass from the same records.  Blocks of 1-2 qubits run the plain
+    kernels: byte-equal.  Blocks of 3-5 qubits: the oracle rounds every
+    product and partial sum to FP32, the matrix cores sum in FP64 and round
+    once, so a gate output may differ by up to
+        ((2^k + 2) sqrt(2) sqrt(2^k) + 1) 2^-24 max|a|
+    (recursive summation of the 2^k complex terms, |sum_c u_rc a_c| <=
+    ||u_r|| ||a|| <= sqrt(2^k) max|a| for a unitary row), and its code by that
+    plus one step."""
     n, sl, cl, eb = 11, 8, 6, 1e-7
     say("fp32 fused", n, sl, cl, eb)
     gates = qc.qft(n)
-    sim = cq.Sim(n, sl, eb, chunk_log2=cl, fused=True, fp32=True)
-    orc = oracle.OracleSim(n, sl, cl, eb, oracle.FP32)
     x = 1234
+    sim = cq.Sim(n, sl, eb, chunk_log2=cl, fused=True, fp32=True)
     sim.init_basis(x)
-    orc.init_basis(x)
-    assert sim.apply(gates) == len(gates)
-    orc.apply(gates, fused=True)
-    a, b = sim.amplitudes(), orc.amplitudes()
+    step = oracle.abs_step(eb)[0]
+    plan = cq.plan(n, gates)
+    bound = 0.0  # first-order bound of the distance to the exact result
+    for first, count, fused, qubits in plan:
+        recs = sim.records()
+        orc = oracle.OracleSim(n, sl, cl, eb, oracle.FP32)
+        orc.set_records(recs)
+        amax = float(np.max(np.abs(decoded_state32(recs))))
+        k = len(qubits) if fused else len(gates[first].targets)
+        rnd = ((2 ** k + 2) * math.sqrt(2) * math.sqrt(2 ** k) + 1) * 2.0 ** -24 * amax
+        bound += math.sqrt(2 << n) * (eb + rnd)
+        orc.apply(gates[first:first + count], fused=True)
+        assert sim.apply(gates[first:first + count]) == count
+        got = sim.records()
+        if not fused or len(qubits) <= 2:
+            assert got == orc.records(), f"pass at gate {first}"
+            continue
+        tol = step + rnd
+        for j in range(orc.nslices):
+            a = oracle.decompress_slice(got[j], oracle.parse_header(got[j])["step"], oracle.FP32)
+            b = oracle.decompress_slice(orc.record(j), oracle.parse_header(orc.record(j))["step"], oracle.FP32)
+            d = float(np.max(np.abs(a - b)))
+            assert d <= tol, f"pass at gate {first}, slice {j}: {d} > {tol}"
+    a = sim.amplitudes()
     assert np.array_equal(a.real, a.real.astype(np.float32).astype(np.float64))
-    assert np.max(np.abs(a - b)) <= 4 * eb * len(cq.plan(n, gates))
+    assert np.array_equal(decoded_state32(sim.records()), a)
     want = np.exp(2j * np.pi * x * np.arange(1 << n) / (1 << n)) / math.sqrt(1 << n)
+    # first-order bound against the exact result: each pass adds at most
+    # sqrt(2N) (eb + the FP32 rounding of its gate outputs)
+    assert np.linalg.norm(a - want) <= bound
     assert abs(np.vdot(want, a)) ** 2 > 0.999
 
 
