@@ -242,6 +242,30 @@ int sim_record_headers(sim_t *sim, uint64_t first, uint64_t count, void *out);
  * and must have the handle's slice and chunk sizes. */
 int sim_import_slice(sim_t *sim, uint64_t j, const void *buf, uint64_t len);
 
+/* ---- allocation-free apply
+ * For callers that cannot allocate device memory once the handle exists
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): sim_apply's passes with the same results (the same kernels,
+ * byte-identical records), calling no hipMalloc, hipFree or allocator hook.
+ * The decompressed slots, per-slot partial results, slot orders and gate
+ * matrices of the passes live in a scratch array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends, instead of the
+ * handle's workspace; slices are processed in as many batches as the array
+ * needs.  Differences from sim_apply:
+ *   - the whole program is checked first; an invalid gate runs nothing;
+ *   - a pass needing a group of slices (2^m slices for m slice-index targets)
+ *     larger than the array holds is refused with SIM_ENOMEM before anything
+ *     runs (one slot of 2^k amplitudes takes about 52 x 2^k bytes: slices of
+ *     2^21 amplitudes never fit, slices of 2^20 only one at a time);
+ *   - the record arenas do not grow: a pass that overflows its output arena
+ *     fails with SIM_ENOMEM, leaving the state of the last completed pass
+ *     (*n_applied counts its gates); create the handle with enough
+ *     arena_bytes, or let sim_apply grow the arenas first.
+ * The array is shared by every call on one GPU and keeps the last call's
+ * contents (each call clears what it counts into): calls that overlap in
+ * time on one GPU, from any handles or threads, race and must not be made. */
+int sim_apply_noalloc(sim_t *sim, const sim_gate *gates, size_t n, size_t *n_applied);
+
 /* ---- captured gate programs (HIP graphs)
  * For callers that apply one gate program many times (a Grover iteration, a
  * circuit served repeatedly) and want no per-pass host work.

@@ -35,7 +35,7 @@ ERRORS = {-1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EBOUND", -4: "SIM_ECORRUP
 
 # every entry point declared in include/cqsim.h
 EXPORTS = ("sim_create", "sim_create_ex", "sim_destroy", "sim_last_error", "sim_init_basis", "sim_init_product",
-           "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_amplitudes", "sim_probabilities", "sim_stats",
+           "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_apply_noalloc", "sim_amplitudes", "sim_probabilities", "sim_stats",
            "sim_record_size", "sim_record_headers", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan",
            "sim_graph_create", "sim_graph_launch", "sim_graph_destroy", "sim_footprint",
            "sim_tune_chunk", "srv_create", "srv_submit", "srv_wait", "srv_clock", "srv_projected_bytes",
@@ -122,6 +122,7 @@ def lib():
         L.sim_set_allocator.argtypes = [P, ALLOC_FN, FREE_FN, P]
         L.sim_set_stream.argtypes = [P, P]
         L.sim_apply.argtypes = [P, C.POINTER(GateStruct), C.c_size_t, C.POINTER(C.c_size_t)]
+        L.sim_apply_noalloc.argtypes = [P, C.POINTER(GateStruct), C.c_size_t, C.POINTER(C.c_size_t)]
         L.sim_amplitudes.argtypes = [P, C.c_uint64, C.c_uint64, P]
         L.sim_probabilities.argtypes = [P, C.c_uint64, C.c_uint64, P]
         L.sim_stats.argtypes = [P, C.POINTER(StatsStruct)]
@@ -349,6 +350,14 @@ class Sim:
         if rc:
             raise SimError(rc, f"sim_apply after {n.value} gates: {lib().sim_last_error().decode()}")
         return n.value
+
+    def apply_noalloc(self, gates: Sequence) -> Tuple[int, int]:
+        """sim_apply_noalloc: the passes on the library's scratch array, with
+        no device allocation; returns (status, gates applied)."""
+        ptr, cnt, keep = _gate_ptr(gates)
+        n = C.c_size_t()
+        rc = lib().sim_apply_noalloc(self._h, ptr, cnt, C.byref(n))
+        return rc, n.value
 
     def apply_partial(self, gates: Sequence) -> Tuple[int, int]:
         """Like apply, but returns (status, gates applied) instead of raising."""

@@ -17,7 +17,9 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "cqsim.h"
@@ -105,6 +107,15 @@ struct sim_s {
   Slots slots{};
   int W = 0;
   std::map<uint64_t, uint64_t *> tables;  // group mask -> slot order of all slices
+  // The workspace that passes run on: the handle's own (slots, W, tables),
+  // or, during sim_apply_noalloc, one carved from the scratch array, with
+  // every slot table present and no device allocation allowed.
+  const Slots *wslots = nullptr;
+  int wW = 0;
+  const std::map<uint64_t, uint64_t *> *wtables = nullptr;
+  bool no_alloc = false;
+  const Slots &run_slots() const { return wslots ? *wslots : slots; }
+  int run_W() const { return wslots ? wW : W; }
   double *dmat = nullptr;
   size_t dmat_cap = 0;  // doubles
   GateDesc ident{};     // the identity (kind 0): quantisation step of fused passes
@@ -228,6 +239,39 @@ int alloc_slots(sim_t *s) {
   return SIM_OK;
 }
 
+// The fields of a W-slot workspace laid out from `base` (each 256-byte
+// aligned), with the sizes alloc_slots gives them; base == nullptr only
+// measures.  Returns the bytes used.
+uint64_t carve_slots(const Geo &g, uint64_t W, uint8_t *base, Slots *sl) {
+  const uint64_t L2 = 2 * g.L;
+  uint64_t off = 0;
+  auto take = [&](auto **ptr, uint64_t bytes) {
+    using T = std::remove_reference_t<decltype(**ptr)>;
+    *ptr = base ? (T *)(base + off) : nullptr;
+    off = align_up(off + bytes, 256);
+  };
+  Slots t{};
+  Slots &o = sl ? *sl : t;
+  take(&o.ws, 8 * W * L2);
+  take(&o.sym, 2 * W * L2);
+  take(&o.esc, 8 * W * L2);
+  take(&o.codes, 4 * W * kNSym);
+  take(&o.symtab, 2 * W * kNSym);
+  take(&o.nused, 4 * W);
+  take(&o.chunk_words, 4 * W * g.nchunks);
+  take(&o.words, 4 * W);
+  take(&o.blk_words, 4 * W * kMaxEncBlocks);
+  take(&o.sq, 16 * W);
+  take(&o.nesc, 4 * W);
+  take(&o.minmax, 16 * W);
+  take(&o.qstep, 24 * W);
+  take(&o.part, 32ull * W * kGqParts);
+  take(&o.hpart, 4ull * W * kGqParts * kNSym);
+  o.stage_words = stage_words_for(g.chunk_log2);
+  take(&o.stage, 4ull * W * g.nchunks * o.stage_words);
+  return off;
+}
+
 uint64_t per_slot_bytes(const Geo &g) {
   return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 2) + 4ull * kGqParts * (kNSym + 8) + 4ull * g.nchunks +
          4ull * g.nchunks * stage_words_for(g.chunk_log2) + 4ull * kMaxEncBlocks + 128;
@@ -237,6 +281,12 @@ uint64_t per_slot_bytes(const Geo &g) {
 // groups (slices equal outside gm) are contiguous, members ordered by the
 // bits of gm in ascending order.
 int slot_table(sim_t *s, uint64_t gm, const uint64_t **out) {
+  if (s->wtables) {  // the scratch workspace: every table was placed before the passes
+    auto it = s->wtables->find(gm);
+    if (it == s->wtables->end()) return set_err(SIM_EINVAL, "no slot order for group mask 0x%llx", (unsigned long long)gm);
+    *out = it->second;
+    return SIM_OK;
+  }
   auto it = s->tables.find(gm);
   if (it != s->tables.end()) {
     *out = it->second;
@@ -472,42 +522,44 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
   // directly and that kernel reads it; the device still falls back to FP64
   // for a pass whose codes may not fit
   const bool compact = init_kind < 0 && !qp.rel && gd.kind != 4 && AMP(s, gq_compact)(s->geo, gq);
-  for (uint64_t b0 = 0; b0 < s->nslices; b0 += (uint64_t)s->W) {
-    const int ns = (int)std::min<uint64_t>((uint64_t)s->W, s->nslices - b0);
+  const Slots &slots = s->run_slots();
+  const uint64_t W = (uint64_t)s->run_W();
+  for (uint64_t b0 = 0; b0 < s->nslices; b0 += W) {
+    const int ns = (int)std::min<uint64_t>(W, s->nslices - b0);
     const uint64_t *ss = table + b0;
     if (init_kind >= 0) {
       s->kt_begin(K_INIT);
-      AMP(s, launch_init)(st, s->slots, s->geo, ss, ns, init_kind, x, s->dfactors, s->ctl);
+      AMP(s, launch_init)(st, slots, s->geo, ss, ns, init_kind, x, s->dfactors, s->ctl);
       s->kt_end();
     } else {
       s->kt_begin(K_DECODE);
-      AMP(s, launch_decode)(st, s->slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass, compact);
+      AMP(s, launch_decode)(st, slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass, compact);
       s->kt_end();
     }
     if (gd.kind == 4) {  // fused block on matrix cores, in place; then quantised as the identity
       s->kt_begin(K_DENSE);
-      AMP(s, launch_dense_mfma)(st, s->slots, s->geo, ns, gd, s->ctl);
+      AMP(s, launch_dense_mfma)(st, slots, s->geo, ns, gd, s->ctl);
       s->kt_end();
     }
     if (qp.rel) {
       s->kt_begin(K_MINMAX);
-      AMP(s, launch_gate_minmax)(st, s->slots, s->geo, ss, ns, gd.kind == 4 ? s->ident : gd, s->ctl);
+      AMP(s, launch_gate_minmax)(st, slots, s->geo, ss, ns, gd.kind == 4 ? s->ident : gd, s->ctl);
       s->kt_end();
       s->kt_begin(K_RELSTEP);
-      launch_rel_step(st, s->slots, ns, qp.eb, s->ctl);
+      launch_rel_step(st, slots, ns, qp.eb, s->ctl);
       s->kt_end();
     }
     s->kt_begin(K_GATEQ);
-    const uint32_t nparts = AMP(s, launch_gate_quant)(st, s->slots, s->geo, ss, ns, gq, qp, s->ctl, pass, compact, s->kscale);
+    const uint32_t nparts = AMP(s, launch_gate_quant)(st, slots, s->geo, ss, ns, gq, qp, s->ctl, pass, compact, s->kscale);
     s->kt_end();
     s->kt_begin(K_CODEBOOK);
-    launch_codebook(st, s->slots, ss, ns, nxt, nparts, s->ctl);
+    launch_codebook(st, slots, ss, ns, nxt, nparts, s->ctl);
     s->kt_end();
     s->kt_begin(K_ENCODE);
-    launch_encode(st, s->slots, s->geo, ns, s->ctl);
+    launch_encode(st, slots, s->geo, ns, s->ctl);
     s->kt_end();
     s->kt_begin(K_FINISH);
-    launch_finish(st, s->slots, s->geo, ss, ns, qp, s->arena[1 - c], s->arena_cap[1 - c], nxt, s->ctl, pass);
+    launch_finish(st, slots, s->geo, ss, ns, qp, s->arena[1 - c], s->arena_cap[1 - c], nxt, s->ctl, pass);
     s->kt_end();
   }
   s->cur = 1 - c;
@@ -532,7 +584,7 @@ int clear_flags(sim_t *s) {
   HIP_TRY(hipMemcpyAsync(&s->ctl->flags, &s->h_ctl->flags, 8, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(&s->ctl->pending_bump, &s->h_ctl->pending_bump, 16, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(&s->ctl->wide, &s->h_ctl->wide, 8, hipMemcpyHostToDevice, s->stream));
-  launch_reset_slots(s->stream, s->slots, s->W);
+  launch_reset_slots(s->stream, s->run_slots(), s->run_W());
   HIP_TRY(hipStreamSynchronize(s->stream));
   return check_launch("reset_slots");
 }
@@ -566,6 +618,7 @@ int grow_arena(sim_t *s, int which, uint64_t min_cap) {
 int ensure_arenas(sim_t *s) {
   for (int a = 0; a < 2; a++)
     if (!s->arena[a]) {
+      if (s->no_alloc) return set_err(SIM_ENOMEM, "a record arena is missing (an earlier growth failed)");
       int rc = grow_arena(s, a, std::max<uint64_t>(s->arena_cap[1 - a], 16ull << 20));
       if (rc) return rc;
     }
@@ -607,7 +660,7 @@ int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, i
       // overflow later grows it then (or reports SIM_ENOMEM)
       const int tgt = 1 - s->cur;
       const uint64_t want = s->h_ctl->bump + s->h_ctl->bump / 4;
-      if (want > s->arena_cap[tgt]) (void)grow_arena(s, tgt, want);
+      if (want > s->arena_cap[tgt] && !s->no_alloc) (void)grow_arena(s, tgt, want);
       break;
     }
     const uint32_t done = s->h_ctl->fail_pass - start_pass;  // passes that completed
@@ -616,6 +669,11 @@ int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, i
     applied += done;
     if ((rc = clear_flags(s))) break;
     if (flags & kFlagOverflow) {
+      if (s->no_alloc) {
+        rc = set_err(SIM_ENOMEM, "a pass needs more than the %llu bytes of its record arena, which the "
+                     "allocation-free entry point cannot grow", (unsigned long long)s->arena_cap[1 - s->cur]);
+        break;
+      }
       if ((rc = grow_arena(s, 1 - s->cur, 0))) break;
       continue;
     }
@@ -1473,6 +1531,141 @@ int sim_import_slice(sim_t *s, uint64_t j, const void *buf, uint64_t len) {
   s->h_ctl->wide_next = 1;
   HIP_TRY(hipMemcpy(&s->ctl->wide_next, &s->h_ctl->wide_next, 4, hipMemcpyHostToDevice));
   return SIM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free apply
+// Scratch of sim_apply_noalloc: the decompressed slots and per-slot
+// partial results of a pass, the slot order of every slice group and the
+// pass's gate matrices.  One array per GPU, held until the process ends;
+// every call on that GPU uses it, so calls that overlap on one GPU race.
+constexpr uint64_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, uint8_t *> g_scratch_ptr;  // device -> device address of `scratch`
+
+// The device address of the scratch array on the current device, looked up
+// once per device.
+int scratch_address(uint8_t **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_err(SIM_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, (uint8_t *)p).first;
+  }
+  *out = it->second;
+  return SIM_OK;
+}
+
+// Host slot order of all slices for group mask gm (as slot_table builds it).
+void slot_order(uint64_t nslices, uint64_t gm, std::vector<uint64_t> &h) {
+  std::vector<int> bits;
+  for (int b = 0; b < 64; b++)
+    if ((gm >> b) & 1) bits.push_back(b);
+  h.clear();
+  for (uint64_t j0 = 0; j0 < nslices; j0++) {
+    if (j0 & gm) continue;
+    for (uint64_t r = 0; r < (1ull << bits.size()); r++) {
+      uint64_t j = j0;
+      for (size_t b = 0; b < bits.size(); b++)
+        if ((r >> b) & 1) j |= 1ull << bits[b];
+      h.push_back(j);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_apply_noalloc(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
+  if (n_applied) *n_applied = 0;
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
+  uint8_t *base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc) return rc;
+  PassSet P;
+  prepare_passes(s, gates, n, P);
+  if (P.vrc) {  // nothing runs: the whole program is checked first
+    g_last_error = P.verr;
+    return P.vrc;
+  }
+  const size_t n_pass = P.n_pass;
+  if (n_pass == 0) return SIM_OK;
+  // slice groups of the passes and their slot orders
+  std::vector<GateDesc> descs;
+  std::vector<uint64_t> gms;
+  pass_descs(s, P, nullptr, descs, gms);
+  std::vector<uint64_t> masks(gms.begin(), gms.end());
+  std::sort(masks.begin(), masks.end());
+  masks.erase(std::unique(masks.begin(), masks.end()), masks.end());
+  int mmax = 0;
+  for (uint64_t gm : masks) mmax = std::max(mmax, __builtin_popcountll(gm));
+  // layout: [slots][one slot order per group mask][matrices]
+  const uint64_t tab_bytes = align_up(8 * s->nslices, 256);
+  const uint64_t fixed = masks.size() * tab_bytes + align_up(8 * P.hm.size(), 256);
+  uint64_t W = 0;
+  for (uint64_t w = 1; w <= s->nslices; w *= 2)
+    if (carve_slots(s->geo, w, nullptr, nullptr) + fixed <= kScratchBytes) W = w;
+  if (W < (1ull << mmax))
+    return set_err(SIM_ENOMEM,
+                   "the allocation-free entry point holds %llu bytes of scratch; a group of %d slices of 2^%d "
+                   "amplitudes needs %llu",
+                   (unsigned long long)kScratchBytes, 1 << mmax, s->geo.slice_log2,
+                   (unsigned long long)(carve_slots(s->geo, 1ull << mmax, nullptr, nullptr) + fixed));
+  Slots sl{};
+  uint64_t off = carve_slots(s->geo, W, base, &sl);
+  std::map<uint64_t, uint64_t *> tables;
+  std::vector<std::vector<uint64_t>> host_tables(masks.size());
+  for (size_t i = 0; i < masks.size(); i++) {
+    slot_order(s->nslices, masks[i], host_tables[i]);
+    uint64_t *d = (uint64_t *)(base + off);
+    off += tab_bytes;
+    HIP_TRY(hipMemcpyAsync(d, host_tables[i].data(), 8 * s->nslices, hipMemcpyHostToDevice, s->stream));
+    tables[masks[i]] = d;
+  }
+  double *dmat = (double *)(base + off);
+  if (!P.hm.empty())
+    HIP_TRY(hipMemcpyAsync(dmat, P.hm.data(), 8 * P.hm.size(), hipMemcpyHostToDevice, s->stream));
+  pass_descs(s, P, dmat, descs, gms);
+  // the array keeps the last call's contents: clear what the passes count into
+  launch_reset_slots(s->stream, sl, (int)W);
+  if ((rc = check_launch("reset_slots"))) return rc;
+  s->wslots = &sl;
+  s->wW = (int)W;
+  s->wtables = &tables;
+  s->no_alloc = true;
+  size_t applied = 0;
+  HIP_TRY(hipEventRecord(s->ev0, s->stream));
+  rc = run_passes(s, descs.data(), gms.data(), n_pass, -1, 0, &applied);
+  s->wslots = nullptr;
+  s->wW = 0;
+  s->wtables = nullptr;
+  s->no_alloc = false;
+  // the host copies of tables and matrices stay alive until the stream has
+  // passed them (run_passes synchronises)
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipEventRecord(s->ev1, s->stream));
+  HIP_TRY(hipEventSynchronize(s->ev1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, s->ev0, s->ev1);
+  s->elapsed += ms * 1e-3;
+  s->passes += applied;
+  if (s->kt_on) s->kt_flush();
+  size_t gates_done = 0;
+  for (size_t i = 0; i < applied; i++) gates_done += P.plan[i].count;
+  if (n_applied) *n_applied = gates_done;
+  return rc;
 }
 
 int sim_kernel_times(sim_t *s, int enable, double *out, int cap, const char **names) {
