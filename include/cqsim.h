@@ -65,20 +65,39 @@ extern "C" {
 
 #define SIM_FUSE_MAX 5   /* widest fused block, in qubits */
 
-/* ---- gate kinds */
-#define SIM_GATE_DENSE 1u /* 2^k x 2^k complex matrix on k = 1..5 targets, optional controls */
-#define SIM_GATE_PHASE 2u /* multiply amplitude i by phase where (i & ctrl_mask) == ctrl_vals */
+/* ---- gate kinds (Section II: the circuit is a sequence of gates applied one
+ * by one).  Every kind also takes the extra controls ctrl_mask / ctrl_vals: it
+ * acts only on amplitudes i with (i & ctrl_mask) == ctrl_vals.  Named kinds
+ * are turned into a matrix or a phase on the host, in FP64, before a pass
+ * runs; they give the same records as the DENSE or PHASE gate with that
+ * matrix or phase. */
+#define SIM_GATE_DENSE 1u /* 2^k x 2^k complex `matrix` on targets[0..k), k = n_targets = 1..5 */
+#define SIM_GATE_PHASE 2u /* n_targets = 0: amplitude i times (params[0] + i params[1]) */
+#define SIM_GATE_H 3u     /* Hadamard on targets[0]: sqrt(1/2) [[1, 1], [1, -1]] */
+#define SIM_GATE_X 4u     /* NOT on targets[0] */
+#define SIM_GATE_Z 5u     /* -1 where bit targets[0] is 1 */
+#define SIM_GATE_P 6u     /* e^{i params[0]} where bit targets[0] is 1 */
+#define SIM_GATE_CP 7u    /* e^{i params[0]} where bits targets[0] and targets[1] are both 1 */
+#define SIM_GATE_CZ 8u    /* -1 where bits targets[0] and targets[1] are both 1 */
+#define SIM_GATE_SWAP 9u  /* exchange of qubits targets[0] and targets[1] */
+#define SIM_GATE_U3 10u   /* OpenQASM 2 u3(theta, phi, lambda) = (params[0], params[1], params[2]) on
+                             targets[0]: [[c, -e^{i lambda} s], [e^{i phi} s, e^{i(phi+lambda)} c]],
+                             c = cos(theta/2), s = sin(theta/2) (each entry one FP64 product) */
+#define SIM_GATE_MCZ 11u  /* -1 where every bit of targets[0..n_targets) is 1 (n_targets = 1..5);
+                             wider multi-controlled Z: SIM_GATE_PHASE with params (-1, 0) and the
+                             qubits in ctrl_mask and ctrl_vals */
+#define SIM_GATE_U1Q 12u  /* one-qubit gate: the 2 x 2 complex `matrix` on targets[0] */
 
 typedef struct sim_s sim_t;
 
 /* One gate of the program (Section II: the program is processed gate by gate).
- * DENSE: local index m = sum_k bit(i, targets[k]) << k selects the row and
- *   column of `matrix` (row-major, 2^k x 2^k complex, interleaved re, im; host
- *   memory, copied by sim_apply).  The gate acts only where
- *   (i & ctrl_mask) == ctrl_vals; controls must not overlap targets.
- * PHASE: n_targets = 0; amplitude i is multiplied by (phase_re + i phase_im)
- *   where (i & ctrl_mask) == ctrl_vals (Z, CZ, controlled phases, oracles).
- * Layout is fixed: 72 bytes, naturally aligned. */
+ * DENSE (and U1Q): local index m = sum_k bit(i, targets[k]) << k selects the
+ *   row and column of `matrix` (row-major, 2^k x 2^k complex, interleaved
+ *   re, im; host memory, copied by sim_apply).
+ * PHASE: amplitude i is multiplied by (params[0] + i params[1]) where
+ *   (i & ctrl_mask) == ctrl_vals (Z, CZ, controlled phases, oracles).
+ * The other kinds are listed above.  Controls must not overlap targets.
+ * Layout is fixed: 80 bytes, naturally aligned. */
 typedef struct sim_gate {
   uint32_t kind;
   uint32_t n_targets;
@@ -86,8 +105,7 @@ typedef struct sim_gate {
   uint32_t reserved;
   uint64_t ctrl_mask;
   uint64_t ctrl_vals;
-  double phase_re;
-  double phase_im;
+  double params[3];
   const double *matrix;
 } sim_gate;
 
@@ -143,6 +161,10 @@ typedef struct sim_stats_t {
   uint64_t arena_bytes;         /* device bytes held for compressed records (both buffers) */
   uint64_t workspace_slots;     /* slices decompressed at once */
   uint64_t device_bytes;        /* every device byte the handle holds now */
+  double min_slice_ratio;       /* smallest ratio of one slice now: raw slice bytes (16 L, or 8 L with
+                                   SIM_FP32) / its record bytes */
+  uint64_t gates;               /* gates of the program applied since creation (passes count the
+                                   passes; in SIM_FUSED mode a pass applies one or more gates) */
 } sim_stats_t;
 
 /* Create a simulator holding |0...0>, compressed (Algorithm 1 starts from a
@@ -167,10 +189,12 @@ void sim_destroy(sim_t *sim);
 /* Text of the last failure on this thread (never NULL). */
 const char *sim_last_error(void);
 
-/* Replace the state by the basis state |x> (x < 2^n) and compress it. */
+/* Replace the state by the basis state |x> (x < 2^n) and compress it
+ * (Algorithm 1 starts from a compressed state: its first step is Decompress). */
 int sim_init_basis(sim_t *sim, uint64_t x);
 
-/* Replace the state by the product state prod_q f_q(b_q) with
+/* Replace the state by the product state prod_q f_q(b_q) (compressed, as
+ * sim_init_basis) with
  * f_q(0) = cos(theta_q / 2), f_q(1) = e^{i phi_q} sin(theta_q / 2); `factors`
  * is host memory of n_qubits * 4 doubles (f_q(0).re, f_q(0).im, f_q(1).re,
  * f_q(1).im), computed by the caller.  The product is formed from (1, 0) with
@@ -201,22 +225,29 @@ int sim_set_stream(sim_t *sim, void *hip_stream);
 int sim_apply(sim_t *sim, const sim_gate *gates, size_t n, size_t *n_applied);
 
 /* The partition of gates[0..n) into passes that sim_apply uses in SIM_FUSED
- * mode (host computation; needs no handle or device).  Greedy, in program
- * order: a pass collects consecutive gates while the union of their qubits
- * (targets and control bits of each gate; a phase gate's qubits are its
- * control bits) has at most SIM_FUSE_MAX members; a gate that alone touches
- * more qubits is a pass of its own.  A pass of one gate is plain.  The gates
- * must be valid for n_qubits (SIM_EINVAL otherwise).  out (host memory,
- * `cap` entries, may be NULL to count) receives the passes; *n_pass their
- * number.  Returns SIM_ENOMEM if cap is too small (n_pass is still set). */
-int sim_plan(int n_qubits, const sim_gate *gates, size_t n, sim_pass *out, size_t cap, size_t *n_pass);
+ * mode (an extension: Algorithm 1 makes one pass per gate, and fused mode
+ * groups gates into passes; host computation, nothing is enqueued).  Greedy,
+ * in program order: a pass collects consecutive gates while the union of
+ * their qubits (targets and control bits of each gate; a phase gate's qubits
+ * are its control bits) has at most SIM_FUSE_MAX members; a gate that alone
+ * touches more qubits is a pass of its own.  A pass of one gate is plain.
+ * The gates must be valid for the handle's qubits (SIM_EINVAL otherwise).
+ * out (host memory, `cap` entries, may be NULL to count) receives the passes;
+ * *n_pass their number.  Returns SIM_ENOMEM if cap is too small (n_pass is
+ * still set). */
+int sim_plan(const sim_t *sim, const sim_gate *gates, size_t n, sim_pass *out, size_t cap, size_t *n_pass);
+
+/* sim_plan for n_qubits qubits without a handle (the same partition). */
+int sim_plan_qubits(int n_qubits, const sim_gate *gates, size_t n, sim_pass *out, size_t cap, size_t *n_pass);
 
 /* Normalised amplitudes [begin, begin + count) into host memory `out`
  * (2 * count doubles, interleaved re, im): the stored state decompressed and
- * scaled by the same normalisation a pass would use. */
+ * scaled by the same normalisation a pass would use (Section III compares
+ * the final amplitudes with the uncompressed simulation to measure fidelity). */
 int sim_amplitudes(sim_t *sim, uint64_t begin, uint64_t count, double *out);
 
-/* |a_i|^2 of the same normalised amplitudes into host memory (count doubles). */
+/* |a_i|^2 of the same normalised amplitudes into host memory (count doubles):
+ * the measurement probabilities (Section III: Grover's success probability). */
 int sim_probabilities(sim_t *sim, uint64_t begin, uint64_t count, double *out);
 
 /* Fill *out (host memory).  Synchronises the stream. */

@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+LIB_PATH = os.environ.get("CQ_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 ABS = 0
 REL = 1

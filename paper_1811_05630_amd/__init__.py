@@ -30,13 +30,15 @@ SIM_ZERO_CHUNKS = 0x8
 SIM_CONST_CHUNKS = 0x10
 GATE_DENSE = 1
 GATE_PHASE = 2
+# named kinds (include/cqsim.h): matrices and phases made by the library from params
+GATE_H, GATE_X, GATE_Z, GATE_P, GATE_CP, GATE_CZ, GATE_SWAP, GATE_U3, GATE_MCZ, GATE_U1Q = range(3, 13)
 
 ERRORS = {-1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EBOUND", -4: "SIM_ECORRUPT", -5: "SIM_EDEVICE"}
 
 # every entry point declared in include/cqsim.h
 EXPORTS = ("sim_create", "sim_create_ex", "sim_destroy", "sim_last_error", "sim_init_basis", "sim_init_product",
            "sim_set_allocator", "sim_set_stream", "sim_apply", "sim_apply_noalloc", "sim_amplitudes", "sim_probabilities", "sim_stats",
-           "sim_record_size", "sim_record_headers", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan",
+           "sim_record_size", "sim_record_headers", "sim_export_slice", "sim_import_slice", "sim_kernel_times", "sim_plan", "sim_plan_qubits",
            "sim_graph_create", "sim_graph_launch", "sim_graph_destroy", "sim_footprint",
            "sim_tune_chunk", "srv_create", "srv_submit", "srv_wait", "srv_clock", "srv_projected_bytes",
            "srv_destroy")
@@ -54,7 +56,7 @@ class SimError(RuntimeError):
 class GateStruct(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("n_targets", C.c_uint32), ("targets", C.c_uint32 * 5),
                 ("reserved", C.c_uint32), ("ctrl_mask", C.c_uint64), ("ctrl_vals", C.c_uint64),
-                ("phase_re", C.c_double), ("phase_im", C.c_double), ("matrix", C.POINTER(C.c_double))]
+                ("params", C.c_double * 3), ("matrix", C.POINTER(C.c_double))]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -78,7 +80,7 @@ class StatsStruct(C.Structure):
                 ("ratio", C.c_double), ("min_ratio", C.c_double), ("passes", C.c_uint64),
                 ("escapes", C.c_uint64), ("last_norm", C.c_double), ("max_abs_codec_err", C.c_double),
                 ("elapsed_s", C.c_double), ("arena_bytes", C.c_uint64), ("workspace_slots", C.c_uint64),
-                ("device_bytes", C.c_uint64)]
+                ("device_bytes", C.c_uint64), ("min_slice_ratio", C.c_double), ("gates", C.c_uint64)]
 
 
 class SrvJobStruct(C.Structure):
@@ -136,8 +138,10 @@ def lib():
         L.sim_graph_launch.argtypes = [P, P, C.POINTER(C.c_size_t)]
         L.sim_graph_destroy.argtypes = [P]
         L.sim_graph_destroy.restype = None
-        L.sim_plan.argtypes = [C.c_int, C.POINTER(GateStruct), C.c_size_t, C.POINTER(PassStruct), C.c_size_t,
+        L.sim_plan.argtypes = [P, C.POINTER(GateStruct), C.c_size_t, C.POINTER(PassStruct), C.c_size_t,
                                C.POINTER(C.c_size_t)]
+        L.sim_plan_qubits.argtypes = [C.c_int, C.POINTER(GateStruct), C.c_size_t, C.POINTER(PassStruct), C.c_size_t,
+                                      C.POINTER(C.c_size_t)]
         L.sim_footprint.argtypes = [C.POINTER(ConfigStruct), C.POINTER(C.c_uint64)]
         L.sim_tune_chunk.argtypes = [C.POINTER(ConfigStruct), C.POINTER(GateStruct), C.c_size_t, C.c_int, C.c_int,
                                      C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
@@ -158,20 +162,35 @@ def _check(rc: int, what: str):
         raise SimError(rc, f"{what}: {lib().sim_last_error().decode()}")
 
 
+class Named:
+    """A gate of a named kind (GATE_H .. GATE_U1Q): the library makes its
+    matrix or phase from `params`."""
+
+    def __init__(self, kind: int, targets: Sequence[int] = (), params: Sequence[float] = (), ctrl_mask: int = 0,
+                 ctrl_vals: int = 0, matrix=None):
+        self.kind, self.targets, self.params = int(kind), tuple(targets), tuple(params)
+        self.ctrl_mask, self.ctrl_vals, self.matrix = ctrl_mask, ctrl_vals, matrix
+
+
 def gate_struct(g) -> Tuple[GateStruct, Optional[np.ndarray]]:
-    """sim_gate from any object with kind, targets, ctrl_mask, ctrl_vals, matrix, phase."""
+    """sim_gate from any object with kind, targets, ctrl_mask, ctrl_vals and
+    matrix or phase (DENSE / PHASE), or params (named kinds)."""
     s = GateStruct()
     s.kind = int(g.kind)
-    tg = tuple(g.targets) if g.kind == GATE_DENSE else ()
+    tg = tuple(g.targets) if g.kind != GATE_PHASE else ()
     s.n_targets = len(tg)
     for i, t in enumerate(tg):
         s.targets[i] = int(t)
     s.ctrl_mask = int(g.ctrl_mask)
     s.ctrl_vals = int(g.ctrl_vals)
-    ph = complex(getattr(g, "phase", 1.0))
-    s.phase_re, s.phase_im = ph.real, ph.imag
+    if g.kind == GATE_PHASE:
+        ph = complex(getattr(g, "phase", 1.0))
+        s.params[0], s.params[1] = ph.real, ph.imag
+    else:
+        for i, v in enumerate(getattr(g, "params", ())[:3]):
+            s.params[i] = float(v)
     keep = None
-    if g.kind == GATE_DENSE:
+    if getattr(g, "matrix", None) is not None and g.kind in (GATE_DENSE, GATE_U1Q):
         keep = np.ascontiguousarray(np.asarray(g.matrix, dtype=np.complex128)).view(np.float64).copy()
         s.matrix = keep.ctypes.data_as(C.POINTER(C.c_double))
     return s, keep
@@ -223,13 +242,18 @@ def _gate_ptr(gates):
     return C.cast(arr, C.POINTER(GateStruct)), len(gates), (arr, keep)
 
 
-def plan(n_qubits: int, gates: Sequence) -> List[Tuple[int, int, bool, Tuple[int, ...]]]:
-    """sim_plan: the fused-mode passes as (first gate, gate count, fused, qubits)."""
+def plan(n_qubits, gates: Sequence) -> List[Tuple[int, int, bool, Tuple[int, ...]]]:
+    """sim_plan (n_qubits a Sim) or sim_plan_qubits (n_qubits an int): the
+    fused-mode passes as (first gate, gate count, fused, qubits)."""
     arr, keep = gate_array(gates)
     n = C.c_size_t()
-    _check(lib().sim_plan(n_qubits, arr, len(gates), None, 0, C.byref(n)), "sim_plan")
+    if isinstance(n_qubits, Sim):
+        fn, first, name = lib().sim_plan, n_qubits._h, "sim_plan"
+    else:
+        fn, first, name = lib().sim_plan_qubits, int(n_qubits), "sim_plan_qubits"
+    _check(fn(first, arr, len(gates), None, 0, C.byref(n)), name)
     out = (PassStruct * max(1, n.value))()
-    _check(lib().sim_plan(n_qubits, arr, len(gates), out, n.value, C.byref(n)), "sim_plan")
+    _check(fn(first, arr, len(gates), out, n.value, C.byref(n)), name)
     return [(p.first_gate, p.n_gates, bool(p.fused), tuple(p.qubits[i] for i in range(p.n_qubits)))
             for p in out[:n.value]]
 

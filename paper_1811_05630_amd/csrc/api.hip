@@ -124,6 +124,7 @@ struct sim_s {
   size_t dstage_cap = 0;  // doubles
   uint32_t pass_counter = 0;
   uint64_t passes = 0;
+  uint64_t gates = 0;  // program gates applied (a fused pass applies one or more)
   double elapsed = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream on which gate programs are captured into graphs
@@ -397,8 +398,8 @@ void block_matrix(const sim_gate *gates, const PlanPass &p, std::vector<double> 
         continue;
       }
       if (g.kind == SIM_GATE_PHASE) {
-        G[2 * (c * dim + c)] = g.phase_re;
-        G[2 * (c * dim + c) + 1] = g.phase_im;
+        G[2 * (c * dim + c)] = g.params[0];
+        G[2 * (c * dim + c) + 1] = g.params[1];
         continue;
       }
       const uint32_t kg = g.n_targets, gd = 1u << kg;
@@ -426,6 +427,117 @@ void block_matrix(const sim_gate *gates, const PlanPass &p, std::vector<double> 
       }
     U.swap(T);
   }
+}
+
+// A named gate kind written as the DENSE or PHASE gate it stands for (host
+// FP64 arithmetic; each U3 entry is one product of libm values, in the form
+// the header gives).  mat receives up to 32 doubles (a 4 x 4 complex matrix)
+// and must outlive `out`.  DENSE and PHASE pass through.
+int expand_gate(const sim_gate &g, size_t idx, sim_gate &out, double *mat) {
+  out = g;
+  auto need = [&](uint32_t k) {
+    return g.n_targets == k ? SIM_OK : set_err(SIM_EINVAL, "gate %zu: kind %u takes %u targets, not %u", idx, g.kind, k,
+                                                g.n_targets);
+  };
+  auto phase_on = [&](uint64_t bits, double re, double im) {
+    if (g.ctrl_mask & bits) return set_err(SIM_EINVAL, "gate %zu: controls overlap targets", idx);
+    out.kind = SIM_GATE_PHASE;
+    out.n_targets = 0;
+    out.ctrl_mask = g.ctrl_mask | bits;
+    out.ctrl_vals = g.ctrl_vals | bits;
+    out.params[0] = re;
+    out.params[1] = im;
+    out.params[2] = 0.0;
+    out.matrix = nullptr;
+    return SIM_OK;
+  };
+  auto bit = [&](uint32_t k) { return g.targets[k] < 64 ? 1ull << g.targets[k] : 0ull; };
+  auto dense = [&](uint32_t k, const double *m) {
+    const size_t cnt = 2ull << (2 * k);
+    std::copy(m, m + cnt, mat);
+    out.kind = SIM_GATE_DENSE;
+    out.n_targets = k;
+    out.matrix = mat;
+    return SIM_OK;
+  };
+  int rc;
+  switch (g.kind) {
+    case SIM_GATE_DENSE:
+    case SIM_GATE_PHASE:
+      return SIM_OK;
+    case SIM_GATE_U1Q:
+      if ((rc = need(1))) return rc;
+      if (!g.matrix) return set_err(SIM_EINVAL, "gate %zu: no matrix", idx);
+      return dense(1, g.matrix);
+    case SIM_GATE_H: {
+      if ((rc = need(1))) return rc;
+      const double h = std::sqrt(0.5);
+      const double m[8] = {h, 0.0, h, 0.0, h, 0.0, -h, 0.0};
+      return dense(1, m);
+    }
+    case SIM_GATE_X: {
+      if ((rc = need(1))) return rc;
+      const double m[8] = {0.0, 0.0, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0};
+      return dense(1, m);
+    }
+    case SIM_GATE_Z:
+      if ((rc = need(1))) return rc;
+      return phase_on(bit(0), -1.0, 0.0);
+    case SIM_GATE_P:
+      if ((rc = need(1))) return rc;
+      return phase_on(bit(0), std::cos(g.params[0]), std::sin(g.params[0]));
+    case SIM_GATE_CP:
+      if ((rc = need(2))) return rc;
+      if (g.targets[0] == g.targets[1]) return set_err(SIM_EINVAL, "gate %zu: repeated target", idx);
+      return phase_on(bit(0) | bit(1), std::cos(g.params[0]), std::sin(g.params[0]));
+    case SIM_GATE_CZ:
+      if ((rc = need(2))) return rc;
+      if (g.targets[0] == g.targets[1]) return set_err(SIM_EINVAL, "gate %zu: repeated target", idx);
+      return phase_on(bit(0) | bit(1), -1.0, 0.0);
+    case SIM_GATE_MCZ: {
+      if (g.n_targets < 1 || g.n_targets > 5) return set_err(SIM_EINVAL, "gate %zu: MCZ on %u targets", idx, g.n_targets);
+      uint64_t b = 0;
+      for (uint32_t k = 0; k < g.n_targets; k++) {
+        if (b & bit(k)) return set_err(SIM_EINVAL, "gate %zu: repeated target", idx);
+        b |= bit(k);
+      }
+      return phase_on(b, -1.0, 0.0);
+    }
+    case SIM_GATE_SWAP: {
+      if ((rc = need(2))) return rc;
+      double m[32] = {0.0};
+      m[2 * (0 * 4 + 0)] = m[2 * (1 * 4 + 2)] = m[2 * (2 * 4 + 1)] = m[2 * (3 * 4 + 3)] = 1.0;
+      return dense(2, m);
+    }
+    case SIM_GATE_U3: {
+      if ((rc = need(1))) return rc;
+      const double th = g.params[0], ph = g.params[1], la = g.params[2];
+      const double c = std::cos(th / 2), sn = std::sin(th / 2);
+      const double m[8] = {c, 0.0, -std::cos(la) * sn, -std::sin(la) * sn,
+                           std::cos(ph) * sn, std::sin(ph) * sn, std::cos(ph + la) * c, std::sin(ph + la) * c};
+      return dense(1, m);
+    }
+    default:
+      return set_err(SIM_EINVAL, "gate %zu: unknown kind %u", idx, g.kind);
+  }
+}
+
+// The gates with every named kind expanded; stops at the first gate that
+// cannot be expanded (its status is returned, *n_ok counts the gates before it).
+int expand_gates(const sim_gate *gates, size_t n, std::vector<sim_gate> &out, std::vector<double> &mats,
+                 size_t *n_ok) {
+  out.assign(n, sim_gate{});
+  mats.assign(32 * n, 0.0);  // never reallocated: gates point into it
+  for (size_t i = 0; i < n; i++) {
+    const int rc = expand_gate(gates[i], i, out[i], mats.data() + 32 * i);
+    if (rc) {
+      *n_ok = i;
+      out.resize(i);
+      return rc;
+    }
+  }
+  *n_ok = n;
+  return SIM_OK;
 }
 
 int validate_gate(const sim_t *s, const sim_gate &g, size_t idx) {
@@ -458,8 +570,8 @@ GateDesc make_desc(const sim_t *s, const sim_gate &g, const double *dmat, uint64
   *gm_out = 0;
   if (g.kind == SIM_GATE_PHASE) {
     d.kind = 2;
-    d.ph_re = s->fp32 ? (double)(float)g.phase_re : g.phase_re;
-    d.ph_im = s->fp32 ? (double)(float)g.phase_im : g.phase_im;
+    d.ph_re = s->fp32 ? (double)(float)g.params[0] : g.params[0];
+    d.ph_im = s->fp32 ? (double)(float)g.params[1] : g.params[1];
     return d;
   }
   const int sl2 = s->geo.slice_log2;
@@ -904,6 +1016,8 @@ int sim_init_product(sim_t *s, const double *factors) {
 // partition), the gate each pass applies and its host matrices (FP32-rounded
 // in FP32 mode).  Gates from the first invalid one on are dropped (vrc, verr).
 struct PassSet {
+  std::vector<sim_gate> eg;  // the program with named kinds expanded
+  std::vector<double> emat;  // matrices of expanded named kinds (eg points here)
   size_t n_valid = 0;
   int vrc = SIM_OK;
   std::string verr;
@@ -915,12 +1029,18 @@ struct PassSet {
   size_t n_pass = 0;
 };
 
-static void prepare_passes(sim_t *s, const sim_gate *gates, size_t n, PassSet &P) {
+static void prepare_passes(sim_t *s, const sim_gate *gates_in, size_t n_in, PassSet &P) {
   size_t &n_valid = P.n_valid;
   int &vrc = P.vrc;
+  size_t n = 0;
+  vrc = expand_gates(gates_in, n_in, P.eg, P.emat, &n);
+  const sim_gate *gates = P.eg.data();
   for (; n_valid < n; n_valid++) {
-    vrc = validate_gate(s, gates[n_valid], n_valid);
-    if (vrc) break;
+    const int rc = validate_gate(s, gates[n_valid], n_valid);
+    if (rc) {
+      vrc = rc;
+      break;
+    }
   }
   P.verr = vrc ? g_last_error : std::string();
   std::string &verr = P.verr;
@@ -958,8 +1078,8 @@ static void prepare_passes(sim_t *s, const sim_gate *gates, size_t n, PassSet &P
     sim_gate g{};
     if (p.k == 0) {  // global phases only
       g.kind = SIM_GATE_PHASE;
-      g.phase_re = U[0];
-      g.phase_im = U[1];
+      g.params[0] = U[0];
+      g.params[1] = U[1];
       pg[n_pass] = g;
       continue;
     }
@@ -1044,6 +1164,7 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
   if (s->kt_on) s->kt_flush();
   size_t gates_done = 0;
   for (size_t i = 0; i < applied; i++) gates_done += plan[i].count;
+  s->gates += gates_done;
   if (n_applied) *n_applied = gates_done;
   if (rc) return rc;
   if (vrc) {
@@ -1258,6 +1379,7 @@ int sim_graph_launch(sim_t *s, sim_graph_t *G, size_t *n_applied) {
   if (s->kt_on) s->kt_flush();
   size_t gates_done = 0;
   for (size_t i = 0; i < applied; i++) gates_done += G->P.plan[i].count;
+  s->gates += gates_done;
   if (n_applied) *n_applied = gates_done;
   return rc;
 }
@@ -1281,12 +1403,18 @@ static int check_gate_n(int n, const sim_gate &g, size_t idx) {
   return SIM_OK;
 }
 
-int sim_plan(int n_qubits, const sim_gate *gates, size_t n, sim_pass *out, size_t cap, size_t *n_pass) {
+int sim_plan_qubits(int n_qubits, const sim_gate *gates_in, size_t n, sim_pass *out, size_t cap, size_t *n_pass) {
   if (n_pass) *n_pass = 0;
   if (n_qubits < 1 || n_qubits > 40) return set_err(SIM_EINVAL, "n_qubits %d out of range", n_qubits);
-  if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
+  if (n && !gates_in) return set_err(SIM_EINVAL, "null gate array");
+  std::vector<sim_gate> eg;
+  std::vector<double> emat;
+  size_t n_ok = 0;
+  int rc = expand_gates(gates_in, n, eg, emat, &n_ok);
+  if (rc) return rc;
+  const sim_gate *gates = eg.data();
   for (size_t i = 0; i < n; i++) {
-    int rc = check_gate_n(n_qubits, gates[i], i);
+    rc = check_gate_n(n_qubits, gates[i], i);
     if (rc) return rc;
   }
   std::vector<PlanPass> plan;
@@ -1304,6 +1432,12 @@ int sim_plan(int n_qubits, const sim_gate *gates, size_t n, sim_pass *out, size_
     for (int k = 0; k < plan[i].k; k++) o.qubits[k] = (uint32_t)plan[i].qubits[k];
   }
   return SIM_OK;
+}
+
+int sim_plan(const sim_t *s, const sim_gate *gates, size_t n, sim_pass *out, size_t cap, size_t *n_pass) {
+  if (n_pass) *n_pass = 0;
+  if (!s) return set_err(SIM_EINVAL, "null handle");
+  return sim_plan_qubits(s->geo.n, gates, n, out, cap, n_pass);
 }
 
 static int readout(sim_t *s, uint64_t begin, uint64_t count, double *out, int probs) {
@@ -1380,6 +1514,11 @@ int sim_stats(sim_t *s, sim_stats_t *out) {
   out->arena_bytes = s->arena_cap[0] + s->arena_cap[1];
   out->workspace_slots = (uint64_t)s->W;
   out->device_bytes = s->dev_bytes;
+  out->gates = s->gates;
+  std::vector<uint32_t> len(s->nslices);
+  HIP_TRY(hipMemcpy(len.data(), s->meta[s->cur].rec_len, 4 * s->nslices, hipMemcpyDeviceToHost));
+  const uint32_t big = *std::max_element(len.begin(), len.end());
+  out->min_slice_ratio = big ? (double)((s->fp32 ? 8ull : 16ull) << s->geo.slice_log2) / (double)big : 0.0;
   return SIM_OK;
 }
 
@@ -1664,6 +1803,7 @@ int sim_apply_noalloc(sim_t *s, const sim_gate *gates, size_t n, size_t *n_appli
   if (s->kt_on) s->kt_flush();
   size_t gates_done = 0;
   for (size_t i = 0; i < applied; i++) gates_done += P.plan[i].count;
+  s->gates += gates_done;
   if (n_applied) *n_applied = gates_done;
   return rc;
 }

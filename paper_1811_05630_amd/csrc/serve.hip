@@ -298,13 +298,14 @@ int srv_submit(srv_t *S, const srv_job *job, uint64_t *id) {
   J->spec = *job;
   size_t nm = 0;
   for (size_t i = 0; i < job->n_gates; i++)
-    if (job->gates[i].kind == SIM_GATE_DENSE && job->gates[i].matrix && job->gates[i].n_targets <= 5)
+    if ((job->gates[i].kind == SIM_GATE_DENSE || job->gates[i].kind == SIM_GATE_U1Q) && job->gates[i].matrix &&
+        job->gates[i].n_targets <= 5)
       nm += 2ull << (2 * job->gates[i].n_targets);
   J->mats.resize(nm);
   J->gates.assign(job->gates, job->gates + job->n_gates);
   size_t off = 0;
   for (sim_gate &g : J->gates) {
-    if (g.kind == SIM_GATE_DENSE && g.matrix && g.n_targets <= 5) {
+    if ((g.kind == SIM_GATE_DENSE || g.kind == SIM_GATE_U1Q) && g.matrix && g.n_targets <= 5) {
       const size_t m = 2ull << (2 * g.n_targets);
       std::copy(g.matrix, g.matrix + m, J->mats.begin() + off);
       g.matrix = J->mats.data() + off;

@@ -47,11 +47,11 @@ int main(void) {
   printf("sim_stats_t %zu\n", sizeof(sim_stats_t));
   printf("sim_pass %zu\n", sizeof(sim_pass));
   F(sim_pass, n_qubits); F(sim_pass, qubits);
-  F(sim_gate, targets); F(sim_gate, ctrl_mask); F(sim_gate, phase_re); F(sim_gate, matrix);
+  F(sim_gate, targets); F(sim_gate, ctrl_mask); F(sim_gate, params); F(sim_gate, matrix);
   F(sim_config, error_bound); F(sim_config, workspace_bytes); F(sim_config, alloc); F(sim_config, stream);
   F(sim_config, arena_bytes);
   F(sim_stats_t, ratio); F(sim_stats_t, max_abs_codec_err); F(sim_stats_t, workspace_slots);
-  F(sim_stats_t, device_bytes);
+  F(sim_stats_t, device_bytes); F(sim_stats_t, min_slice_ratio); F(sim_stats_t, gates);
   printf("srv_job %zu\n", sizeof(srv_job));
   printf("srv_done %zu\n", sizeof(srv_done));
   F(srv_job, family); F(srv_job, basis); F(srv_job, factors); F(srv_job, gates); F(srv_job, n_gates);
@@ -75,7 +75,7 @@ def test_struct_layouts_match_header():
         "sim_stats_t": C.sizeof(cq.StatsStruct), "sim_pass": C.sizeof(cq.PassStruct),
         "sim_pass.n_qubits": cq.PassStruct.n_qubits.offset, "sim_pass.qubits": cq.PassStruct.qubits.offset,
         "sim_gate.targets": cq.GateStruct.targets.offset, "sim_gate.ctrl_mask": cq.GateStruct.ctrl_mask.offset,
-        "sim_gate.phase_re": cq.GateStruct.phase_re.offset, "sim_gate.matrix": cq.GateStruct.matrix.offset,
+        "sim_gate.params": cq.GateStruct.params.offset, "sim_gate.matrix": cq.GateStruct.matrix.offset,
         "sim_config.error_bound": cq.ConfigStruct.error_bound.offset,
         "sim_config.workspace_bytes": cq.ConfigStruct.workspace_bytes.offset,
         "sim_config.alloc": cq.ConfigStruct.alloc.offset, "sim_config.stream": cq.ConfigStruct.stream.offset,
@@ -84,6 +84,8 @@ def test_struct_layouts_match_header():
         "sim_stats_t.max_abs_codec_err": cq.StatsStruct.max_abs_codec_err.offset,
         "sim_stats_t.workspace_slots": cq.StatsStruct.workspace_slots.offset,
         "sim_stats_t.device_bytes": cq.StatsStruct.device_bytes.offset,
+        "sim_stats_t.min_slice_ratio": cq.StatsStruct.min_slice_ratio.offset,
+        "sim_stats_t.gates": cq.StatsStruct.gates.offset,
         "srv_job": C.sizeof(cq.SrvJobStruct), "srv_done": C.sizeof(cq.SrvDoneStruct),
         **{f"srv_job.{f}": getattr(cq.SrvJobStruct, f).offset
            for f in ("family", "basis", "factors", "gates", "n_gates", "out", "out_count")},
@@ -91,7 +93,7 @@ def test_struct_layouts_match_header():
            for f in ("status", "applied", "t_submit", "stats", "error")},
     }
     assert {k: int(v) for k, v in got.items()} == py
-    assert py["sim_gate"] == 72
+    assert py["sim_gate"] == 80
     assert py["sim_pass"] == 40
 
 
@@ -101,8 +103,31 @@ def test_binding_converts_gates_without_the_device():
     arr, keep = cq.gate_array([qc.H(3), qc.CP(1, 4, 0.25), qc.SWAP(0, 7)])
     assert arr[0].kind == cq.GATE_DENSE and arr[0].n_targets == 1 and arr[0].targets[0] == 3
     assert arr[1].kind == cq.GATE_PHASE and arr[1].ctrl_mask == 0b10010
+    assert abs(complex(arr[1].params[0], arr[1].params[1]) - complex(np.cos(0.25), np.sin(0.25))) < 1e-15
     m = np.ctypeslib.as_array(arr[2].matrix, shape=(32,))
     assert m[2 * (1 * 4 + 2)] == 1.0  # SWAP row 1, column 2
+
+
+def test_named_kinds_marshal_their_params():
+    g = cq.Named(cq.GATE_U3, (5,), (0.1, 0.2, 0.3), ctrl_mask=1, ctrl_vals=1)
+    arr, keep = cq.gate_array([g, cq.Named(cq.GATE_CZ, (1, 2))])
+    assert arr[0].kind == cq.GATE_U3 and arr[0].n_targets == 1 and arr[0].targets[0] == 5
+    assert list(arr[0].params) == [0.1, 0.2, 0.3] and not arr[0].matrix
+    assert arr[1].kind == cq.GATE_CZ and arr[1].n_targets == 2
+
+
+def test_plan_expands_named_kinds_without_the_device():
+    """sim_plan_qubits is host code: named kinds plan like the gates they stand for."""
+    if not os.path.exists(cq.LIB_PATH):
+        pytest.skip("libcqsim.so not built")
+    import qcircuits as qc
+    named = [cq.Named(cq.GATE_H, (0,)), cq.Named(cq.GATE_CP, (0, 1), (0.5,)), cq.Named(cq.GATE_SWAP, (2, 7)),
+             cq.Named(cq.GATE_MCZ, (0, 1, 2, 3, 4, 5)[:5])]
+    plain = [qc.H(0), qc.CP(0, 1, 0.5), qc.SWAP(2, 7), qc.MCPHASE(0b11111, 0b11111, -1)]
+    assert cq.plan(10, named) == cq.plan(10, plain)
+    with pytest.raises(cq.SimError) as e:
+        cq.plan(10, [cq.Named(cq.GATE_CZ, (3,))])
+    assert e.value.rc == -1
 
 
 def test_circuit_slices_point_into_one_marshalled_array():
