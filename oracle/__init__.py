@@ -22,6 +22,7 @@ REL = 1
 FP32 = 2  # mode bit: FP32 working values and gate arithmetic (quantiser and norm stay FP64)
 ZERO_CHUNKS = 8  # mode bit: a chunk whose codes are all zero is stored with no words
 CONST_CHUNKS = 16  # mode bit: a chunk whose values all equal its head keeps only the head (offset bit 31)
+PWREL = 32  # mode bit: pointwise-relative bound (|v - v'| <= eb |v| for every value)
 
 R = 512
 NSYM = 1024
@@ -83,6 +84,8 @@ def lib():
         L.orc_decompress_slice_mode.argtypes = [P, C.c_uint64, C.c_double, C.c_uint32, P, P]
         L.orc_norm.argtypes = [C.c_int, P, P, P]
         L.orc_norm.restype = C.c_double
+        L.orc_norm_mode.argtypes = [C.c_int, P, P, P, C.c_uint32]
+        L.orc_norm_mode.restype = C.c_double
         L.orc_rsqrt.argtypes = [C.c_double]
         L.orc_rsqrt.restype = C.c_double
         L.orc_sim_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_uint32]
@@ -313,9 +316,10 @@ def parse_header(rec: bytes) -> dict:
     step = float(np.frombuffer(rec[32:40], dtype="<f8")[0])
     lo, hi = (int(x) for x in np.frombuffer(rec[40:56], dtype="<u8"))
     flags = int(np.frombuffer(rec[56:60], dtype="<u4")[0])
+    pw_bits = int(np.frombuffer(rec[60:64], dtype="<u4")[0])
     return dict(magic=int(u32[0]), slice_log2=int(u32[1]), chunk_log2=int(u32[2]), n_used=int(u32[3]),
                 n_chunks=int(u32[4]), n_words=int(u32[5]), n_escapes=int(u32[6]), total=int(u32[7]),
-                step=step, sumsq=(hi << 64) | lo, flags=flags)
+                step=step, sumsq=(hi << 64) | lo, flags=flags, pw_bits=pw_bits)
 
 
 def chunk_offsets(rec: bytes) -> np.ndarray:
@@ -338,11 +342,13 @@ def symtab(rec: bytes) -> List[Tuple[int, int]]:
     return [(int(x) & 1023, int(x) >> 10) for x in e]
 
 
-def norm(steps: np.ndarray, sumsq: Sequence[int]) -> float:
+def norm(steps: np.ndarray, sumsq: Sequence[int], mode: int = 0) -> float:
+    """N of the stored state from every slice's step and sum field (mode
+    PWREL: the sum fields hold FP64 squared norms)."""
     st = np.ascontiguousarray(steps, dtype=np.float64)
     lo = np.array([int(s) & ((1 << 64) - 1) for s in sumsq], dtype=np.uint64)
     hi = np.array([int(s) >> 64 for s in sumsq], dtype=np.uint64)
-    return lib().orc_norm(st.size, _ptr(st), _ptr(lo), _ptr(hi))
+    return lib().orc_norm_mode(st.size, _ptr(st), _ptr(lo), _ptr(hi), mode)
 
 
 def rsqrt(N: float) -> float:
@@ -350,8 +356,10 @@ def rsqrt(N: float) -> float:
 
 
 def scale_from_records(records: Sequence[bytes]) -> float:
+    """The normalisation of a stored state from its records (or their headers)."""
     hs = [parse_header(r) for r in records]
-    return rsqrt(norm(np.array([h["step"] for h in hs]), [h["sumsq"] for h in hs]))
+    pw = PWREL if any(h["flags"] & 4 for h in hs) else 0
+    return rsqrt(norm(np.array([h["step"] for h in hs]), [h["sumsq"] for h in hs], pw))
 
 
 def pass_group(n: int, slice_log2: int, chunk_log2: int, eb: float, mode: int, gate, scale: float,

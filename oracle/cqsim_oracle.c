@@ -93,6 +93,37 @@ static void cmac(double ur, double ui, double ar, double ai, double *cr, double 
 #define ORC_CONST_CHUNKS 16u
 #define ORC_CONST_MARK 0x80000000u
 
+/* Pointwise-relative bound (mode bit ORC_PWREL; an extension, one reading of
+ * the bound Section II sets for each amplitude number): every real and
+ * imaginary value v is stored as the FP64 number nearest to it that has b
+ * mantissa bits, b the least integer with 2^-(b+1) <= eb, so that
+ * |v - v'| <= eb |v| and zero stays zero.  The integer code of v is its IEEE
+ * bit pattern without the sign, rounded to b mantissa bits (half to even) and
+ * shifted right by 52 - b, negated for negative v: a monotone, logarithm-like
+ * integer that the Lorenzo difference and the Huffman code take like any
+ * other code.  Such records have step 1.0, header word 15 = b and flags
+ * bit 2; their 16-byte sum field holds, in its low 8 bytes, the FP64 squared
+ * norm of the slice's decoded values, summed as a pairwise tree over the 2L
+ * values in order (the codes' squares are no norm here). */
+#define ORC_PWREL 32u
+#define ORC_PW_MAXBITS 20
+
+/* b for a pointwise-relative bound eb, or -1 when eb is out of range. */
+static int pw_bits(double eb) {
+  if (!(eb > 0.0) || !(eb < 0.5)) return -1;
+  int b = 0;
+  while (b <= ORC_PW_MAXBITS && ldexp(1.0, -(b + 1)) > eb) b++;
+  return b <= ORC_PW_MAXBITS ? b : -1;
+}
+
+/* The value of pointwise-relative code c with b mantissa bits. */
+static double pw_value(int64_t c, int b) {
+  uint64_t m = (uint64_t)(c < 0 ? -c : c) << (52 - b);
+  double x;
+  memcpy(&x, &m, 8);
+  return c < 0 ? -x : x;
+}
+
 static double r32(double x) { return (double)(float)x; }
 
 static void cmac_m(int fp32, double ur, double ui, double ar, double ai, double *cr, double *ci) {
@@ -437,6 +468,43 @@ static int quantise(const double *v, uint64_t nv, double eb, uint32_t mode, int6
   return ORC_OK;
 }
 
+/* Pointwise-relative quantisation (ORC_PWREL) of nv values, nv a power of
+ * two: the codes, the largest |v - v'| and the pairwise-tree sum of v'^2. */
+static int quantise_pw(const double *v, uint64_t nv, double eb, int64_t *p, double *max_err_out, double *norm_out) {
+  const int b = pw_bits(eb);
+  if (b < 0) return ORC_EINVAL;
+  const int sh = 52 - b;
+  double *x = (double *)malloc(sizeof(double) * nv);
+  if (!x) return ORC_ENOMEM;
+  double max_err = 0.0;
+  for (uint64_t i = 0; i < nv; i++) {
+    uint64_t bits;
+    memcpy(&bits, &v[i], 8);
+    const uint64_t mag = bits & 0x7FFFFFFFFFFFFFFFull;
+    const uint64_t half = (uint64_t)1 << (sh - 1);
+    const uint64_t c = (mag + (half - 1) + ((mag >> sh) & 1)) >> sh; /* round half to even */
+    if (c >= ((uint64_t)2047 << b)) { /* infinite or not a number, or rounds to infinity */
+      free(x);
+      return ORC_EBOUND;
+    }
+    p[i] = (bits >> 63) ? -(int64_t)c : (int64_t)c;
+    const double back = pw_value(p[i], b);
+    const double err = fabs(v[i] - back);
+    if (!(err <= eb * fabs(v[i]))) {
+      free(x);
+      return ORC_EBOUND;
+    }
+    if (err > max_err) max_err = err;
+    x[i] = back * back;
+  }
+  for (uint64_t m = nv; m > 1; m /= 2)
+    for (uint64_t i = 0; i < m / 2; i++) x[i] = x[2 * i] + x[2 * i + 1];
+  *norm_out = x[0];
+  *max_err_out = max_err;
+  free(x);
+  return ORC_OK;
+}
+
 /* Compress one slice (Re plane then Im plane, L values each).
  * mode bit 0: 0 = absolute bound eb, 1 = relative bound eb (bit 1, ORC_FP32, does not
  * change the compressor: the values it gets are then FP32 numbers); ORC_ZERO_CHUNKS:
@@ -463,7 +531,18 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
 
   double step, max_err;
   unsigned __int128 sumsq;
-  int rc = quantise(v, nv, eb, mode, p, &step, &max_err, &sumsq);
+  const int pw = (mode & ORC_PWREL) != 0;
+  int rc;
+  if (pw) {
+    double pn;
+    rc = quantise_pw(v, nv, eb, p, &max_err, &pn);
+    uint64_t pb;
+    memcpy(&pb, &pn, 8);
+    sumsq = pb;
+    step = 1.0;
+  } else {
+    rc = quantise(v, nv, eb, mode, p, &step, &max_err, &sumsq);
+  }
   if (rc != ORC_OK) {
     free(v); free(p); free(d); free(sym);
     return rc;
@@ -558,8 +637,8 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
   wrf64(rec + 32, step);
   wr64(rec + 40, (uint64_t)sumsq);
   wr64(rec + 48, (uint64_t)(sumsq >> 64));
-  wr32(rec + 56, (zc ? 1u : 0u) | (cc ? 2u : 0u));
-  wr32(rec + 60, 0);
+  wr32(rec + 56, (zc ? 1u : 0u) | (cc ? 2u : 0u) | (pw ? 4u : 0u));
+  wr32(rec + 60, pw ? (uint32_t)pw_bits(eb) : 0u);
   /* symbol table in canonical order: by code length, then by symbol */
   uint8_t *tab = rec + ORC_HDR;
   uint32_t k = 0;
@@ -613,7 +692,7 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
 /* ----------------------------------------------------------- decompressor */
 
 typedef struct {
-  uint32_t slice_log2, chunk_log2, n_used, n_chunks, n_words, n_escapes, total, flags;
+  uint32_t slice_log2, chunk_log2, n_used, n_chunks, n_words, n_escapes, total, flags, pw_bits;
   double step;
   uint64_t sumsq_lo, sumsq_hi;
   const uint8_t *symtab;
@@ -634,7 +713,10 @@ int orc_parse(const uint8_t *rec, uint64_t len, orc_rec *h) {
   h->sumsq_lo = rd64(rec + 40);
   h->sumsq_hi = rd64(rec + 48);
   h->flags = rd32(rec + 56);
-  if (h->flags > 3 || rd32(rec + 60) != 0) return ORC_ECORRUPT;
+  h->pw_bits = rd32(rec + 60);
+  if (h->flags > 7) return ORC_ECORRUPT;
+  if (h->flags & 4 ? (h->pw_bits > ORC_PW_MAXBITS || h->step != 1.0 || h->sumsq_hi != 0) : h->pw_bits != 0)
+    return ORC_ECORRUPT;
   if (h->slice_log2 > 26 || h->chunk_log2 > h->slice_log2) return ORC_ECORRUPT;
   if (h->n_chunks != (uint32_t)((2ull << h->slice_log2) >> h->chunk_log2)) return ORC_ECORRUPT;
   if (h->n_used < 1 || h->n_used > ORC_NSYM) return ORC_ECORRUPT;
@@ -788,10 +870,11 @@ int orc_decompress_slice_mode(const uint8_t *rec, uint64_t len, double kscale, u
   int64_t *p = (int64_t *)malloc(sizeof(int64_t) * 2 * L);
   if (!p) return ORC_ENOMEM;
   rc = orc_decode_p(rec, len, p);
+  const int pw = (h.flags & 4) != 0;
   if (rc == ORC_OK) {
     for (uint64_t i = 0; i < L; i++) {
-      re[i] = (double)p[i] * kscale;
-      im[i] = (double)p[L + i] * kscale;
+      re[i] = (pw ? pw_value(p[i], (int)h.pw_bits) : (double)p[i]) * kscale;
+      im[i] = (pw ? pw_value(p[L + i], (int)h.pw_bits) : (double)p[L + i]) * kscale;
       if (mode & ORC_FP32) {
         re[i] = r32(re[i]);
         im[i] = r32(im[i]);
@@ -813,9 +896,14 @@ static double sumsq_to_double(uint64_t lo, uint64_t hi) { return (double)hi * 0x
 
 /* N = sum_j step_j^2 * P_j over the stored state, added as a pairwise tree over
  * slice indices (x_i <- x_2i + x_2i+1 level by level; count a power of two). */
-double orc_norm(int nslices, const double *step, const uint64_t *lo, const uint64_t *hi) {
+double orc_norm_mode(int nslices, const double *step, const uint64_t *lo, const uint64_t *hi, uint32_t mode) {
   double *x = (double *)malloc(sizeof(double) * (size_t)nslices);
-  for (int j = 0; j < nslices; j++) x[j] = (step[j] * step[j]) * sumsq_to_double(lo[j], hi[j]);
+  for (int j = 0; j < nslices; j++) {
+    if (mode & ORC_PWREL) /* the record holds the slice's squared norm itself */
+      memcpy(&x[j], &lo[j], 8);
+    else
+      x[j] = (step[j] * step[j]) * sumsq_to_double(lo[j], hi[j]);
+  }
   int m = nslices;
   while (m > 1) {
     for (int i = 0; i < m / 2; i++) x[i] = x[2 * i] + x[2 * i + 1];
@@ -824,6 +912,10 @@ double orc_norm(int nslices, const double *step, const uint64_t *lo, const uint6
   double N = x[0];
   free(x);
   return N;
+}
+
+double orc_norm(int nslices, const double *step, const uint64_t *lo, const uint64_t *hi) {
+  return orc_norm_mode(nslices, step, lo, hi, 0);
 }
 
 /* 1/sqrt(N) by ten Newton steps y <- y * (1.5 - (0.5 N y) y) from y = 1
@@ -953,7 +1045,7 @@ int orc_sim_init(orc_sim *s, int kind, uint64_t x, const double *f) {
 }
 
 double orc_sim_scale(const orc_sim *s) {
-  return orc_rsqrt(orc_norm((int)s->nslices, s->step, s->sq_lo, s->sq_hi));
+  return orc_rsqrt(orc_norm_mode((int)s->nslices, s->step, s->sq_lo, s->sq_hi, s->mode));
 }
 
 /* Slices whose index bits coincide except at the gate's target slice bits
@@ -1502,6 +1594,7 @@ void orc_vsim_destroy(orc_vsim *s);
 
 orc_vsim *orc_vsim_create(int n, int slice_log2, double eb, uint32_t mode) {
   if (n < 1 || n > 40 || slice_log2 < 1 || slice_log2 > n || slice_log2 > 26) return NULL;
+  if (mode & ORC_PWREL) return NULL; /* codes only: the pointwise-relative norm needs the values */
   orc_vsim *s = (orc_vsim *)calloc(1, sizeof(orc_vsim));
   if (!s) return NULL;
   s->n = n;
