@@ -63,6 +63,15 @@ extern "C" {
                                   stretches).  With SIM_ZERO_CHUNKS an all-zero chunk stays a zero
                                   chunk.  Codes, amplitudes and norms are unchanged */
 
+#define SIM_EB_PWREL 0x20u /* pointwise-relative bound: |a - a'| <= error_bound |a| for every real and
+                               imaginary part (an extension, one reading of Section II's bound for each
+                               amplitude number): each value is stored as the nearest FP64 number with
+                               b mantissa bits, b the least with 2^-(b+1) <= error_bound (0 < error_bound
+                               < 0.5, b <= 20); zeros stay zero.  Header word 14 bit 2 and word 15 = b
+                               mark such records, whose step is 1 and whose sum field holds the slice's
+                               squared norm as an FP64 value (a pairwise tree over its 2L values).
+                               Excludes SIM_EB_REL */
+
 #define SIM_FUSE_MAX 5   /* widest fused block, in qubits */
 
 /* ---- gate kinds (Section II: the circuit is a sequence of gates applied one

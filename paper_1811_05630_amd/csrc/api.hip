@@ -237,6 +237,7 @@ int alloc_slots(sim_t *s) {
   if ((rc = s->dalloc((void **)&sl.hpart, 4ull * W * kGqParts * kNSym))) return rc;
   sl.stage_words = stage_words_for(s->geo.chunk_log2);
   if ((rc = s->dalloc((void **)&sl.stage, 4ull * W * s->geo.nchunks * sl.stage_words))) return rc;
+  if ((rc = s->dalloc((void **)&sl.csum, 8ull * W * s->geo.nchunks))) return rc;
   return SIM_OK;
 }
 
@@ -270,11 +271,12 @@ uint64_t carve_slots(const Geo &g, uint64_t W, uint8_t *base, Slots *sl) {
   take(&o.hpart, 4ull * W * kGqParts * kNSym);
   o.stage_words = stage_words_for(g.chunk_log2);
   take(&o.stage, 4ull * W * g.nchunks * o.stage_words);
+  take(&o.csum, 8ull * W * g.nchunks);
   return off;
 }
 
 uint64_t per_slot_bytes(const Geo &g) {
-  return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 2) + 4ull * kGqParts * (kNSym + 8) + 4ull * g.nchunks +
+  return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 2) + 4ull * kGqParts * (kNSym + 8) + 12ull * g.nchunks +
          4ull * g.nchunks * stage_words_for(g.chunk_log2) + 4ull * kMaxEncBlocks + 128;
 }
 
@@ -607,6 +609,8 @@ GateDesc make_desc(const sim_t *s, const sim_gate &g, const double *dmat, uint64
 QuantParams quant_params(const sim_t *s) {
   QuantParams q;
   q.rel = (s->mode & SIM_EB_REL) ? 1 : 0;
+  q.pw = s->geo.pw_bits >= 0 ? 1 : 0;
+  q.pw_bits = s->geo.pw_bits;
   q.eb = s->eb;
   double step = (2.0 * s->eb) * (1.0 - 0x1p-20);
   q.step = step;
@@ -627,13 +631,13 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
   int rc = slot_table(s, init_kind >= 0 ? 0 : gm, &table);
   if (rc) return rc;
   s->kt_begin(K_BEGIN);
-  launch_begin_pass(st, s->ctl, cur, s->nslices, s->kscale, init_kind >= 0 ? 0 : 1);
+  launch_begin_pass(st, s->ctl, cur, s->nslices, s->kscale, init_kind >= 0 ? 0 : 1, s->geo.pw_bits >= 0);
   s->kt_end();
   const GateDesc &gq = gd.kind == 4 ? s->ident : gd;
   // compact workspace (int32 codes) when decode feeds the quantising kernel
   // directly and that kernel reads it; the device still falls back to FP64
   // for a pass whose codes may not fit
-  const bool compact = init_kind < 0 && !qp.rel && gd.kind != 4 && AMP(s, gq_compact)(s->geo, gq);
+  const bool compact = init_kind < 0 && !qp.rel && !qp.pw && gd.kind != 4 && AMP(s, gq_compact)(s->geo, gq);
   const Slots &slots = s->run_slots();
   const uint64_t W = (uint64_t)s->run_W();
   for (uint64_t b0 = 0; b0 < s->nslices; b0 += W) {
@@ -665,7 +669,7 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
     const uint32_t nparts = AMP(s, launch_gate_quant)(st, slots, s->geo, ss, ns, gq, qp, s->ctl, pass, compact, s->kscale);
     s->kt_end();
     s->kt_begin(K_CODEBOOK);
-    launch_codebook(st, slots, ss, ns, nxt, nparts, s->ctl);
+    launch_codebook(st, slots, ss, ns, nxt, nparts, s->ctl, qp.pw ? s->geo.nchunks : 0u);
     s->kt_end();
     s->kt_begin(K_ENCODE);
     launch_encode(st, slots, s->geo, ns, s->ctl);
@@ -760,7 +764,7 @@ int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, i
       if (rc) return rc;
     }
     // count the records of the last batch (settle only)
-    launch_begin_pass(s->stream, s->ctl, s->meta[s->cur], s->nslices, s->kscale, 3);
+    launch_begin_pass(s->stream, s->ctl, s->meta[s->cur], s->nslices, s->kscale, 3, s->geo.pw_bits >= 0);
     if ((rc = read_ctl(s))) return rc;
     const uint32_t flags = s->h_ctl->flags;
     if (!flags) {
@@ -834,8 +838,17 @@ int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   if (sl2 < 1 || sl2 > n || sl2 > 26) return set_err(SIM_EINVAL, "slice_log2 %d outside 1..min(26, n)", sl2);
   if (!(cfg->error_bound > 0.0) || !std::isfinite(cfg->error_bound))
     return set_err(SIM_EINVAL, "error bound must be positive and finite");
-  if (cfg->mode & ~(SIM_EB_REL | SIM_FP32 | SIM_FUSED | SIM_ZERO_CHUNKS | SIM_CONST_CHUNKS))
+  if (cfg->mode & ~(SIM_EB_REL | SIM_FP32 | SIM_FUSED | SIM_ZERO_CHUNKS | SIM_CONST_CHUNKS | SIM_EB_PWREL))
     return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
+  if ((cfg->mode & SIM_EB_REL) && (cfg->mode & SIM_EB_PWREL))
+    return set_err(SIM_EINVAL, "SIM_EB_REL and SIM_EB_PWREL exclude each other");
+  int pwb = -1;
+  if (cfg->mode & SIM_EB_PWREL) {  // the least b with 2^-(b+1) <= eb, at most 20
+    if (!(cfg->error_bound < 0.5)) return set_err(SIM_EINVAL, "a pointwise-relative bound must be below 0.5");
+    pwb = 0;
+    while (pwb <= 20 && std::ldexp(1.0, -(pwb + 1)) > cfg->error_bound) pwb++;
+    if (pwb > 20) return set_err(SIM_EINVAL, "a pointwise-relative bound below 2^-21 needs more than 20 mantissa bits");
+  }
   int cl2 = cfg->chunk_log2 > 0 ? cfg->chunk_log2 : 10;
   if (cl2 > sl2) cl2 = sl2;
   if (cl2 > 10) return set_err(SIM_EINVAL, "chunk_log2 %d above 10", cl2);
@@ -847,6 +860,7 @@ int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   s->geo.zero_chunks = (cfg->mode & SIM_ZERO_CHUNKS) ? 1u : 0u;
   s->geo.const_chunks = (cfg->mode & SIM_CONST_CHUNKS) ? 1u : 0u;
   s->geo.fmt_in = s->geo.zero_chunks | (s->geo.const_chunks << 1);
+  s->geo.pw_bits = pwb;
   s->eb = cfg->error_bound;
   s->mode = cfg->mode;
   s->fp32 = (cfg->mode & SIM_FP32) != 0;
@@ -1340,7 +1354,7 @@ int sim_graph_launch(sim_t *s, sim_graph_t *G, size_t *n_applied) {
       HIP_TRY(hipGraphLaunch(G->exec, s->stream));
       // count the records of the last batch, then check the passes
       const int end_cur = G->start_cur ^ (int)(n & 1);
-      launch_begin_pass(s->stream, s->ctl, s->meta[end_cur], s->nslices, s->kscale, 3);
+      launch_begin_pass(s->stream, s->ctl, s->meta[end_cur], s->nslices, s->kscale, 3, s->geo.pw_bits >= 0);
       if ((rc = read_ctl(s)) == SIM_OK) {
         const uint32_t flags = s->h_ctl->flags;
         if (!flags) {
@@ -1448,7 +1462,7 @@ static int readout(sim_t *s, uint64_t begin, uint64_t count, double *out, int pr
   int rc;
   const uint64_t *table;
   if ((rc = slot_table(s, 0, &table))) return rc;
-  launch_begin_pass(s->stream, s->ctl, s->meta[s->cur], s->nslices, s->kscale, 2);
+  launch_begin_pass(s->stream, s->ctl, s->meta[s->cur], s->nslices, s->kscale, 2, s->geo.pw_bits >= 0);
   const uint64_t L = s->geo.L;
   const uint64_t per = probs ? 1 : 2;
   const uint64_t stage_amps = std::min<uint64_t>(count, std::max<uint64_t>(L, 1ull << 24));
@@ -1586,7 +1600,11 @@ static int check_record(const sim_t *s, const uint8_t *r, uint64_t len, double *
   }
   if (kraft != (1ull << kLMax)) return set_err(SIM_ECORRUPT, "symbol table is not a complete prefix code");
   const uint32_t flags = rd32(56);
-  if (flags > 3 || rd32(60) != 0) return set_err(SIM_ECORRUPT, "unknown header flags");
+  if (flags > 7) return set_err(SIM_ECORRUPT, "unknown header flags");
+  // pointwise-relative records (flags bit 2, word 15 their mantissa bits) only in that mode, with its bits
+  const bool pw = (flags & 4) != 0;
+  if (pw != (s->geo.pw_bits >= 0) || rd32(60) != (pw ? (uint32_t)s->geo.pw_bits : 0u))
+    return set_err(SIM_ECORRUPT, "record's bound kind does not match the simulator");
   const uint64_t ooff = kHdr + ((2ull * n_used + 3) & ~3ull);
   uint32_t prevw = 0;
   bool prev_const = false;
@@ -1605,6 +1623,12 @@ static int check_record(const sim_t *s, const uint8_t *r, uint64_t len, double *
   memcpy(step, r + 32, 8);
   memcpy(sq, r + 40, 16);
   if (!(*step > 0.0) || !std::isfinite(*step)) return set_err(SIM_ECORRUPT, "bad step");
+  if (pw) {  // step 1, and the sum field an FP64 squared norm
+    double nrm;
+    memcpy(&nrm, &sq[0], 8);
+    if (*step != 1.0 || sq[1] != 0 || !(nrm >= 0.0) || !std::isfinite(nrm))
+      return set_err(SIM_ECORRUPT, "bad pointwise-relative header");
+  }
   return SIM_OK;
 }
 

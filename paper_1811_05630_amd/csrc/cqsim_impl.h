@@ -16,7 +16,10 @@ namespace cq {
 //   0  u32 magic 0x31535143         32 f64 step (quantisation step)
 //   4  u32 slice_log2                40 u64 sum p^2, low 64 bits
 //   8  u32 chunk_log2                48 u64 sum p^2, high 64 bits
-//  12  u32 n_used (coded symbols)    56 u32 0, 60 u32 0
+//  12  u32 n_used (coded symbols)    56 u32 flags: bit 0 zero chunks, bit 1 constant chunks,
+//                                       bit 2 pointwise-relative codes (step 1, the sum field
+//                                       an FP64 squared norm)
+//                                    60 u32 pointwise-relative mantissa bits, else 0
 //  16  u32 n_chunks = 2L/B
 //  20  u32 n_words (bit stream)
 //  24  u32 n_escapes
@@ -88,6 +91,8 @@ struct QuantParams {
   int rel;                // 0: absolute bound, 1: value-range-relative bound
   double eb;              // absolute bound, or the relative factor
   double step, recip;     // absolute mode: step = 2 eb (1 - 2^-20), recip = 1/step
+  int pw;                 // 1: pointwise-relative bound eb: each value rounded to pw_bits mantissa bits
+  int pw_bits;            // the least b with 2^-(b+1) <= eb (pointwise-relative mode)
 };
 
 struct Geo {
@@ -100,6 +105,8 @@ struct Geo {
   uint32_t const_chunks;  // SIM_CONST_CHUNKS: constant chunks keep their head only (offset bit 31)
   uint32_t fmt_in;        // the stored records may hold zero chunks (bit 0) or constant chunks (bit 1):
                           // the modes, or imported records
+  int pw_bits;            // -1, or pointwise-relative records: a code is a value's bit pattern without
+                          // the sign, rounded to pw_bits mantissa bits and shifted right by 52 - pw_bits
 };
 
 // Per-slot scratch of one batch of decompressed slices.
@@ -128,6 +135,8 @@ struct Slots {
   // workgroup and tile role) without atomics; the codebook kernel adds them
   uint32_t *hpart;        // [W][kGqParts][1024] partial histograms
   uint64_t *part;         // [W][kGqParts][4] sum p^2 lo, hi, escapes, max error bits
+  double *csum;           // [W][nchunks] pointwise-relative mode: each chunk's sum of squared stored
+                          // values as a pairwise tree in index order (the codebook sums the slice)
 };
 
 // Per-slice stored-state metadata (one copy per arena).
@@ -185,13 +194,15 @@ CQ_AMPLITUDE_LAUNCHERS
 // 2 = read-out only (scales without touching the pass counters), 3 = only
 // count the records of the last batch written.  Every mode first counts
 // the last batch.
+// pw: the records' sum fields hold FP64 squared norms (pointwise-relative mode)
 void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *kscale,
-                       int with_norm);
+                       int with_norm, bool pw = false);
 void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots);
 void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, const Ctl *ctl);
 // nparts: partial results per slot written by the preceding gate_quant launch
+// pw_nchunks: pointwise-relative mode, the slice's squared norm from its nchunks chunk sums (0: off)
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
-                     uint32_t nparts, Ctl *ctl);
+                     uint32_t nparts, Ctl *ctl, uint32_t pw_nchunks = 0);
 void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
 // records of the batch: offsets in the output arena, headers, symbol tables,
 // chunk offsets, bit streams, per-slice metadata

@@ -189,7 +189,10 @@ __device__ __forceinline__ void settle(Ctl *ctl) {
   ctl->pending_bytes = 0;
 }
 
-__device__ __forceinline__ double norm_leaf(const double *step, const uint64_t *sq, uint64_t j) {
+// A slice's term of N: step^2 x its exact sum p^2, or (pointwise-relative
+// records) the FP64 squared norm its sum field holds.
+__device__ __forceinline__ double norm_leaf(const double *step, const uint64_t *sq, uint64_t j, bool pw) {
+  if (pw) return __longlong_as_double((long long)sq[2 * j]);
   double s = step[j];
   double p = (double)sq[2 * j + 1] * 0x1p64 + (double)sq[2 * j];
   return (s * s) * p;
@@ -197,11 +200,11 @@ __device__ __forceinline__ double norm_leaf(const double *step, const uint64_t *
 
 // Pairwise sum of `b` (a power of two) consecutive leaves: the same balanced
 // tree as adding neighbours level by level.
-__device__ double pairwise_block(const double *step, const uint64_t *sq, uint64_t first, uint64_t b) {
+__device__ double pairwise_block(const double *step, const uint64_t *sq, uint64_t first, uint64_t b, bool pw) {
   double stk[48];
   int top = 0;
   for (uint64_t i = 0; i < b; i++) {
-    double v = norm_leaf(step, sq, first + i);
+    double v = norm_leaf(step, sq, first + i, pw);
     uint64_t k = i;
     while (k & 1) {
       v = stk[--top] + v;
@@ -213,7 +216,7 @@ __device__ double pairwise_block(const double *step, const uint64_t *sq, uint64_
 }
 
 __global__ void __launch_bounds__(1024) k_begin_pass(Ctl *ctl, const double *step, const uint64_t *sq, uint64_t S,
-                                                     double *kscale, int with_norm) {
+                                                     double *kscale, int with_norm, int pw) {
   if (ctl->flags) return;
   __shared__ double part[1024];
   __shared__ double s_sh;
@@ -229,11 +232,11 @@ __global__ void __launch_bounds__(1024) k_begin_pass(Ctl *ctl, const double *ste
   if (with_norm == 0 || with_norm == 3) return;
   uint64_t active;
   if (S <= T) {
-    part[tid] = tid < S ? norm_leaf(step, sq, tid) : 0.0;
+    part[tid] = tid < S ? norm_leaf(step, sq, tid, pw) : 0.0;
     active = S;
   } else {
     uint64_t b = S / T;
-    part[tid] = pairwise_block(step, sq, (uint64_t)tid * b, b);
+    part[tid] = pairwise_block(step, sq, (uint64_t)tid * b, b, pw);
     active = T;
   }
   __syncthreads();
@@ -411,6 +414,25 @@ struct BitReader {
 // least 32 values and a whole number of workgroups of chunks per slot (every
 // lane active, whole rounds).  FMT: the records may hold zero chunks (bit 0)
 // or constant chunks (bit 1).
+// The value of a pointwise-relative code q (an integer held in a double):
+// the bit pattern |q| << (52 - b) with q's sign.
+__device__ __forceinline__ double pw_value(double q, int b) {
+  const uint64_t m = (uint64_t)fabs(q) << (52 - b);
+  const double x = __longlong_as_double((long long)m);
+  return q < 0.0 ? -x : x;
+}
+
+// A decoded value: the code itself (compact workspace), else p k, or the
+// pointwise-relative value of p times k.
+template <bool C32>
+__device__ __forceinline__ typename DecFmt<C32>::T dec_val(typename DecFmt<C32>::P p, double k, int pwb) {
+  if constexpr (C32) {
+    return DecFmt<C32>::val(p, k);
+  } else {
+    return pwb >= 0 ? rw(pw_value(p, pwb) * k) : DecFmt<C32>::val(p, k);
+  }
+}
+
 template <bool FULL, bool C32, int FMT>
 __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, const StateMeta &cur, uint64_t slice,
                                               uint32_t u, const uint32_t *offs, uint32_t nchunks, uint32_t n_words,
@@ -500,7 +522,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
             z = br.take(nb);
           }
           p = F::add_esc(p, unzigzag(z));
-          st[lane * PITCH + q] = F::val(p, k);
+          st[lane * PITCH + q] = dec_val<C32>(p, k, g.pw_bits);
           q++;
           continue;
         }
@@ -512,9 +534,9 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
         br.buf <<= len;
         br.nbits -= (int)len;
         p = F::add(p, (int)sym - kR);
-        st[lane * PITCH + q] = F::val(p, k);
+        st[lane * PITCH + q] = dec_val<C32>(p, k, g.pw_bits);
         const typename F::P p2 = F::add(p, (int)((e >> 14) & 1023u) - kR);
-        st[lane * PITCH + q + 1] = F::val(p2, k);
+        st[lane * PITCH + q + 1] = dec_val<C32>(p2, k, g.pw_bits);
         p = two ? p2 : p;
         q += two ? 2u : 1u;
       }
@@ -664,6 +686,47 @@ __device__ __forceinline__ bool quantise(double v, double step, double recip, do
   double back = q * step;
   err = fabs(v - back);
   return err <= ebj;
+}
+
+// Pointwise-relative bound: v rounded to b mantissa bits (half to even on its
+// bit pattern); q = the rounded bit pattern without the sign, shifted right by
+// 52 - b, with v's sign; back = the stored value.  False if v is not finite
+// (or rounds to infinity) or |v - back| > eb |v|.
+__device__ __forceinline__ bool quantise_pw(double v, int b, double eb, double &q, double &err, double &back) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(v);
+  const uint64_t mag = bits & 0x7FFFFFFFFFFFFFFFull;
+  const int sh = 52 - b;
+  const uint64_t half = 1ull << (sh - 1);
+  const uint64_t c = (mag + (half - 1) + ((mag >> sh) & 1)) >> sh;
+  if (c >= (2047ull << b)) {
+    q = 0.0;
+    err = 0.0;
+    back = 0.0;
+    return false;
+  }
+  const double x = __longlong_as_double((long long)(c << sh));
+  const bool neg = (bits >> 63) != 0;
+  back = neg ? -x : x;
+  q = neg ? -(double)c : (double)c;
+  err = fabs(v - back);
+  return err <= eb * fabs(v);
+}
+
+// Pairwise sum of b (a power of two) consecutive values: the same balanced
+// tree as adding neighbours level by level.
+__device__ double tree_sum(const double *x, uint64_t first, uint64_t b) {
+  double stk[48];
+  int top = 0;
+  for (uint64_t i = 0; i < b; i++) {
+    double v = x[first + i];
+    uint64_t k = i;
+    while (k & 1) {
+      v = stk[--top] + v;
+      k >>= 1;
+    }
+    stk[top++] = v;
+  }
+  return stk[0];
 }
 
 // relative bound: min/max of the gate's output over every slot.  Workgroup
@@ -1181,10 +1244,14 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant(Slots sl, Geo g, const ui
   const uint32_t bit = KIND == 1 ? 1u << gd.tloc[0] : 0u;
   double step, recip, ebj;
   slot_quant(sl, qp, u, step, recip, ebj);
+  // pointwise-relative mode: the tile's squared stored values (real plane,
+  // imaginary plane), 2 C doubles of dynamic LDS (none otherwise)
+  extern __shared__ double pws[];
   Acc acc;
   acc.zero();
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += G) {
     const uint32_t ob = tile * C;
+    double sr[V], si[V];  // pointwise-relative mode: the stored values
     double ar[V], ai[V], br[V], bi[V];  // own amplitude; partner (one-target gates)
     // all loads first (whole tiles need no bounds checks), then arithmetic
 #pragma unroll
@@ -1229,9 +1296,53 @@ __global__ void __launch_bounds__(256, 2) k_gate_quant(Slots sl, Geo g, const ui
         }
       }
       double e1, e2;
-      acc.ok &= quantise(re, step, recip, ebj, qr[v], e1);
-      acc.ok &= quantise(im, step, recip, ebj, qi[v], e2);
+      if (qp.pw) {
+        acc.ok &= quantise_pw(re, qp.pw_bits, qp.eb, qr[v], e1, sr[v]);
+        acc.ok &= quantise_pw(im, qp.pw_bits, qp.eb, qi[v], e2, si[v]);
+      } else {
+        acc.ok &= quantise(re, step, recip, ebj, qr[v], e1);
+        acc.ok &= quantise(im, step, recip, ebj, qi[v], e2);
+      }
       acc.emax = fmax(acc.emax, fmax(e1, e2));
+    }
+    if (qp.pw) {  // each chunk's sum of squared stored values, a pairwise tree in index order
+#pragma unroll
+      for (int v = 0; v < V; v++) {
+        const uint32_t e = v * T + tid;
+        if (FULL || e < C) {
+          pws[e] = sr[v] * sr[v];
+          pws[C + e] = si[v] * si[v];
+        }
+      }
+      __syncthreads();
+      const uint32_t B = 1u << g.chunk_log2;
+      for (uint32_t m = C; m > C / B; m >>= 1) {  // m values per plane -> m / 2: x[i] = x[2i] + x[2i+1]
+        double t[8];
+        const uint32_t h2 = m / 2;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          const uint32_t i = k * T + tid;
+          t[k] = 0.0;
+          if (i < m) {
+            const uint32_t base = i < h2 ? 0u : C, j = i < h2 ? i : i - h2;
+            t[k] = pws[base + 2 * j] + pws[base + 2 * j + 1];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          const uint32_t i = k * T + tid;
+          if (i < m) pws[(i < h2 ? 0u : C) + (i < h2 ? i : i - h2)] = t[k];
+        }
+        __syncthreads();
+      }
+      const uint32_t nc = C / B;  // chunks of this tile per plane
+      double *cs = sl.csum + (uint64_t)u * g.nchunks;
+      for (uint32_t i = tid; i < 2 * nc; i += T) {
+        const uint32_t plane = i / nc, k = i - plane * nc;
+        cs[(uint64_t)plane * (g.L / B) + ob / B + k] = pws[plane * C + k];
+      }
+      __syncthreads();  // pws is refilled by the next tile
     }
     tile_symbols<V, FULL>(qr, qi, h, bnd, g, so, ob, C, acc);
   }
@@ -2103,7 +2214,7 @@ __device__ void bitonic_sort(uint64_t *key, uint32_t P) {
 }
 
 __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot_slice, StateMeta nxt,
-                                                  uint32_t nparts, Ctl *ctl) {
+                                                  uint32_t nparts, Ctl *ctl, uint32_t pw_nchunks) {
   if (ctl->flags) return;
   __shared__ uint64_t key[kNSym];
   __shared__ uint32_t wgt[kNSym];
@@ -2166,6 +2277,31 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
       sl.nesc[u] = (uint32_t)ne;
       atomicMax((unsigned long long *)&ctl->max_err_bits, (unsigned long long)eb);
       if (ne) atomicAdd((unsigned long long *)&ctl->escapes, (unsigned long long)ne);
+    }
+  }
+  if (pw_nchunks) {  // pointwise-relative records: the slice's squared norm, a pairwise tree over its chunks
+    __shared__ double ptree[256];
+    const uint32_t T = blockDim.x;
+    const double *cs = sl.csum + (uint64_t)u * pw_nchunks;
+    uint32_t active;
+    if (pw_nchunks >= T) {
+      const uint32_t b = pw_nchunks / T;
+      ptree[tid] = tree_sum(cs, (uint64_t)tid * b, b);
+      active = T;
+    } else {
+      ptree[tid] = tid < pw_nchunks ? cs[tid] : 0.0;
+      active = pw_nchunks;
+    }
+    __syncthreads();
+    for (uint32_t m = active; m > 1; m >>= 1) {
+      const double v = tid < m / 2 ? ptree[2 * tid] + ptree[2 * tid + 1] : 0.0;
+      __syncthreads();
+      if (tid < m / 2) ptree[tid] = v;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      sl.sq[2 * u] = (uint64_t)__double_as_longlong(ptree[0]);
+      sl.sq[2 * u + 1] = 0;
     }
   }
   // used symbols, compacted in symbol order (4 consecutive symbols per thread)
@@ -2779,7 +2915,7 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
   }
   for (uint32_t i = kU * T + tid; i < nw; i += T) stream[bp + i] = src[i];
   if (b != 0) return;
-  const double step = qp.rel ? qstep : qp.step;
+  const double step = qp.pw ? 1.0 : qp.rel ? qstep : qp.step;
   if (tid == 0) {
     uint32_t *h32 = (uint32_t *)rec;
     h32[0] = kMagic;
@@ -2793,8 +2929,9 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
     *(double *)(rec + 32) = step;
     *(uint64_t *)(rec + 40) = sq_lo;
     *(uint64_t *)(rec + 48) = sq_hi;
-    h32[14] = (g.zero_chunks ? 1u : 0u) | (g.const_chunks ? 2u : 0u);  // zero chunks; constant chunks
-    h32[15] = 0;
+    // zero chunks; constant chunks; pointwise-relative codes and their mantissa bits
+    h32[14] = (g.zero_chunks ? 1u : 0u) | (g.const_chunks ? 2u : 0u) | (qp.pw ? 4u : 0u);
+    h32[15] = qp.pw ? (uint32_t)qp.pw_bits : 0u;
     nxt.rec_off[slice] = off;
     nxt.rec_len[slice] = h32[7];
     nxt.step[slice] = step;
@@ -2920,8 +3057,9 @@ static inline unsigned grid1(uint64_t n, unsigned b) { return (unsigned)((n + b 
 
 #if !CQ_FP32
 void launch_begin_pass(hipStream_t st, Ctl *ctl, const StateMeta &cur, uint64_t nslices, double *kscale,
-                       int with_norm) {
-  CQ_LAUNCH(k_begin_pass, dim3(1), dim3(1024), 0, st, ctl, cur.step, cur.sq, nslices, kscale, with_norm);
+                       int with_norm, bool pw) {
+  CQ_LAUNCH(k_begin_pass, dim3(1), dim3(1024), 0, st, ctl, cur.step, cur.sq, nslices, kscale, with_norm,
+            pw ? 1 : 0);
 }
 
 void launch_reset_slots(hipStream_t st, const Slots &sl, int nslots) {
@@ -3053,10 +3191,40 @@ bool gq_compact(const Geo &g, const GateDesc &gd) { return wave_route(g, gd, gat
 
 // compact: read a compact workspace when ctl->wide is clear (only the
 // wavefront-range kernels can; gq_compact tells whether gd goes there)
+// Pointwise-relative mode: the tiled kernel with its general gate path
+// (identity, phase, or any dense gate through eval_amp) and 2 C doubles of
+// dynamic LDS for the chunk sums.
+static uint32_t launch_gq_pw(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
+                             const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass, int kind) {
+  const uint64_t C = gq_tile(g.L);
+  const uint32_t ntiles = (uint32_t)(g.L / C);
+  const uint32_t G = ntiles < kGqWgs ? ntiles : kGqWgs;
+  const dim3 grid(G, (unsigned)nslots);
+  const size_t shm = 16 * C;
+  if (C == kGqTile) {
+    if (kind == 0)
+      CQ_LAUNCH((k_gate_quant<0, 4, true>), grid, dim3(256), shm, st, sl, g, ss, gd, qp, ctl, pass);
+    else if (kind == 2)
+      CQ_LAUNCH((k_gate_quant<2, 4, true>), grid, dim3(256), shm, st, sl, g, ss, gd, qp, ctl, pass);
+    else
+      CQ_LAUNCH((k_gate_quant<3, 4, true>), grid, dim3(256), shm, st, sl, g, ss, gd, qp, ctl, pass);
+    return G;
+  }
+  const int threads = g.L >= 256 ? 256 : 64;
+  if (kind == 0)
+    CQ_LAUNCH((k_gate_quant<0, 4, false>), grid, dim3(threads), shm, st, sl, g, ss, gd, qp, ctl, pass);
+  else if (kind == 2)
+    CQ_LAUNCH((k_gate_quant<2, 4, false>), grid, dim3(threads), shm, st, sl, g, ss, gd, qp, ctl, pass);
+  else
+    CQ_LAUNCH((k_gate_quant<3, 4, false>), grid, dim3(threads), shm, st, sl, g, ss, gd, qp, ctl, pass);
+  return G;
+}
+
 uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
                            const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass, bool compact,
                            const double *kscale) {
   const int kind = gate_kind(gd);
+  if (qp.pw) return launch_gq_pw(st, sl, g, slot_slice, nslots, gd, qp, ctl, pass, kind);
   if (kind == 1) {
     const uint64_t C = gq_tile(g.L);
     const int wr = wave_route(g, gd, kind);
@@ -3103,8 +3271,8 @@ uint32_t launch_gate_quant(hipStream_t st, const Slots &sl, const Geo &g, const 
 
 #if !CQ_FP32
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
-                     uint32_t nparts, Ctl *ctl) {
-  CQ_LAUNCH(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, nparts, ctl);
+                     uint32_t nparts, Ctl *ctl, uint32_t pw_nchunks) {
+  CQ_LAUNCH(k_codebook, dim3((unsigned)nslots), dim3(256), 0, st, sl, slot_slice, nxt, nparts, ctl, pw_nchunks);
 }
 
 // chunks per encode (and finish) workgroup: about four workgroups per CU over
