@@ -1769,17 +1769,32 @@ __device__ __forceinline__ void wr_symbols(const double (&qr)[4], const double (
 // the element's row, bit for bit like the product in column order.
 struct GateCoef {
   double sr, si, pr, pi;
+  bool real;  // the gate's matrix has no imaginary parts (the same for every lane)
 };
+// whether a one-target gate's 2 x 2 matrix is real
+__device__ __forceinline__ bool real_m2(const GateDesc &gd) {
+  return gd.m2[1] == 0.0 && gd.m2[3] == 0.0 && gd.m2[5] == 0.0 && gd.m2[7] == 0.0;
+}
 __device__ __forceinline__ GateCoef gate_coef(const GateDesc &gd, bool row) {
   GateCoef c;
   c.sr = row ? gd.m2[6] : gd.m2[0];
   c.si = row ? gd.m2[7] : gd.m2[1];
   c.pr = row ? gd.m2[4] : gd.m2[2];
   c.pi = row ? gd.m2[5] : gd.m2[3];
+  c.real = real_m2(gd);
   return c;
 }
+// The complex multiply-adds of u0 a + u1 b.  With real coefficients the
+// products with a zero imaginary part are exact zeros, and adding them
+// changes at most the sign of an exact zero: the real path below gives the
+// same values with half the operations.
 __device__ __forceinline__ void gate_pair(const GateCoef &c, double ar, double ai, double br, double bi, double &re,
                                           double &im) {
+  if (c.real) {
+    re = rw(rw(c.sr * ar) + rw(c.pr * br));
+    im = rw(rw(c.sr * ai) + rw(c.pr * bi));
+    return;
+  }
   double cr, ci;
   cmul(c.sr, c.si, ar, ai, cr, ci);
   cmac(c.pr, c.pi, br, bi, cr, ci);
@@ -1839,7 +1854,12 @@ __device__ __forceinline__ void wr_gate_quant(const double (&ar)[4], const doubl
     if (KIND != 0) {
       double gr, gi;
       if (KIND == 2) {
-        cmul(gd.ph_re, gd.ph_im, ar[v], ai[v], gr, gi);
+        if (gd.ph_im == 0.0) {  // a real phase: u a with u_i = 0 (see gate_pair)
+          gr = rw(gd.ph_re * ar[v]);
+          gi = rw(gd.ph_re * ai[v]);
+        } else {
+          cmul(gd.ph_re, gd.ph_im, ar[v], ai[v], gr, gi);
+        }
       } else if (KIND == 1) {
         gate_pair(c0, ar[v], ai[v], br[v], bi[v], gr, gi);
       } else {  // row of element v: bit t - 6 of v
@@ -1966,15 +1986,23 @@ __device__ __forceinline__ void wr_pair_quant(const WRange &a, const WRange &b, 
                                               double (&qai)[4], double (&qbr)[4], double (&qbi)[4], Acc &accA,
                                               Acc &accB) {
   const uint32_t lane = lane_id();
+  const bool real = real_m2(gd);
 #pragma unroll
   for (int v = 0; v < 4; v++) {
     const double a0r = a.r[v], a0i = a.i[v], a1r = b.r[v], a1i = b.i[v];
     double outAr = a0r, outAi = a0i, outBr = a1r, outBi = a1i;
     if (sA.hi_ok && ((obA + v * 64 + lane) & sA.mask_lo) == sA.vals_lo) {
-      cmul(gd.m2[0], gd.m2[1], a0r, a0i, outAr, outAi);
-      cmac(gd.m2[2], gd.m2[3], a1r, a1i, outAr, outAi);
-      cmul(gd.m2[4], gd.m2[5], a0r, a0i, outBr, outBi);
-      cmac(gd.m2[6], gd.m2[7], a1r, a1i, outBr, outBi);
+      if (real) {  // real matrix: the same values with half the operations (see gate_pair)
+        outAr = rw(rw(gd.m2[0] * a0r) + rw(gd.m2[2] * a1r));
+        outAi = rw(rw(gd.m2[0] * a0i) + rw(gd.m2[2] * a1i));
+        outBr = rw(rw(gd.m2[4] * a0r) + rw(gd.m2[6] * a1r));
+        outBi = rw(rw(gd.m2[4] * a0i) + rw(gd.m2[6] * a1i));
+      } else {
+        cmul(gd.m2[0], gd.m2[1], a0r, a0i, outAr, outAi);
+        cmac(gd.m2[2], gd.m2[3], a1r, a1i, outAr, outAi);
+        cmul(gd.m2[4], gd.m2[5], a0r, a0i, outBr, outBi);
+        cmac(gd.m2[6], gd.m2[7], a1r, a1i, outBr, outBi);
+      }
     }
     quant_tile(outAr, sA, qar[v], accA);
     quant_tile(outAi, sA, qai[v], accA);
