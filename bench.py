@@ -696,7 +696,8 @@ def run_serve(args):
         "metric": METRIC, "value": amp_passes / makespan, "unit": "amps/s", "n_gpus": 1, "steps": n_jobs,
         "warmup": len(warm), "ms_per_step": makespan / n_jobs * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": "serve: %d independent jobs, Poisson arrivals (mean gap %g ms), n ~ U{16..24}, "
+        "config": {"workload": "serve: %d independent jobs, Poisson arrivals (mean gap %g ms), n ~ U{16..24} (the 16..28 "
+                               "mix narrowed so that the stream finishes in seconds), "
                                "absolute bound log-uniform [1e-7, 1e-4], FP32/FP64 1:1, Grover (1..8 iterations) / "
                                "QFT of a basis state / 20 random U3+CZ layers 1:1:1, up to %d jobs at once within "
                                "%g GiB" % (n_jobs, args.arrival_ms, args.max_active, args.budget_gib),

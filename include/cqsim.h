@@ -47,7 +47,10 @@ extern "C" {
 #define SIM_FP32 0x2u    /* amplitudes, gate matrices, initial factors and every product and sum
                             of the gate arithmetic rounded to FP32 (an extension: the paper
                             works in FP64); quantisation, the bound check and the norm stay
-                            FP64, applied to the FP32 values; raw bytes are 8 per amplitude */
+                            FP64, applied to the FP32 values; raw bytes are 8 per amplitude.
+                            The bound holds for the stored value q*step; the working value
+                            read back is that value rounded to FP32, so it lies within
+                            error_bound + 2^-24 |a| of the gate output */
 #define SIM_PLAIN 0x0u   /* one pass per gate, exactly as in Algorithm 1 */
 #define SIM_FUSED 0x4u   /* runs of consecutive gates on at most SIM_FUSE_MAX qubits are applied
                             as one dense block per pass (see sim_plan); blocks of 3 or more

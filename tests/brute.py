@@ -109,3 +109,43 @@ def qft_basis_closed_form(n, x):
     N = 1 << n
     y = np.arange(N)
     return np.exp(2j * np.pi * ((x * y) % N) / N) / math.sqrt(N)
+
+
+class QftProductExact:
+    """Exact QFT of a product state, a block of 2^m output indices at a time.
+
+    QFT maps psi to sqrt(N) * ifft(psi); for psi(x) = prod_q f_q(x_q) the sum
+    over x factorises: out(y) = prod_q (f_q(0) + f_q(1) w^(2^q y)) / sqrt 2 with
+    w = exp(2 pi i / N).  Write y = hi 2^m + lo: for q >= n - m the factor
+    depends on lo alone (2^q hi 2^m is a multiple of N), so their product is
+    one vector over lo; for q < n - m, w^(2^q y) = w^(2^(q+m) hi) w^(2^q lo)."""
+
+    def __init__(self, factors, m):
+        f = np.asarray(factors, dtype=np.complex128)
+        self.n, self.m = len(f), m
+        n, N = self.n, 1 << self.n
+        self.f = f
+        lo = np.arange(1 << m, dtype=np.int64)
+        self.low = np.ones(1 << m, dtype=np.complex128)
+        self.e = {}
+        for q in range(n):
+            ang = (2 * math.pi / N) * ((lo << q) & (N - 1)).astype(np.float64)
+            e = np.cos(ang) + 1j * np.sin(ang)
+            if q >= n - m:
+                self.low *= (f[q, 0] + f[q, 1] * e) / math.sqrt(2)
+            else:
+                self.e[q] = e
+
+    def block(self, hi):
+        """Amplitudes at y = hi 2^m .. hi 2^m + 2^m - 1."""
+        n, N = self.n, 1 << self.n
+        out = self.low.copy()
+        t = np.empty_like(out)
+        for q, e in self.e.items():
+            k = (hi << (q + self.m)) & (N - 1)
+            c = complex(math.cos(2 * math.pi * k / N), math.sin(2 * math.pi * k / N))
+            np.multiply(e, self.f[q, 1] * c, out=t)
+            t += self.f[q, 0]
+            t *= 1 / math.sqrt(2)
+            out *= t
+        return out

@@ -171,6 +171,56 @@ def test_qft30_fused_sampled_groups():
         done = pi + 1
 
 
+def test_qft30_full_run_closed_form():
+    """The whole 30-qubit fused QFT of the product state: the read-out against
+    the exact QFT of the product state over all 2^30 amplitudes, within the
+    first-order bound summed from the steps the run's own records hold."""
+    from concurrent.futures import ThreadPoolExecutor
+    from tests.brute import QftProductExact
+    w = qc.qft_product_workload()
+    n, sl, rel, cl = w.n_qubits, w.slice_log2, w.error_bound, 8
+    plan = cq.plan(n, w.gates)
+    say("qft30 full run", n, sl, rel, "chunk", cl, "passes", len(plan))
+    sim = cq.Sim(n, sl, rel, relative=True, chunk_log2=cl, fused=True, workspace_bytes=64 << 30,
+                 arena_bytes=4 << 30)
+    L = 1 << sl
+
+    def eps():
+        steps = np.array([oracle.parse_header(h)["step"] for h in sim.headers()])
+        return math.sqrt(float(np.sum(2 * L * (steps / 2) ** 2)))
+
+    sim.init_product(w.factors)
+    bound = 0.0
+    e = eps()
+    bound += e / (1 - e)
+    circ = cq.Circuit(w.gates)
+    for first, count, _, _ in plan:
+        assert sim.apply(circ[first:first + count]) == count
+        e = eps()
+        bound += e / (1 - e)
+    tol = 1.01 * bound + 1e-12
+    m = 24
+    ex = QftProductExact(w.factors, m)
+
+    def block(hi, got):
+        want = ex.block(hi)
+        d = got - want
+        return float(np.vdot(d, d).real), float(np.max(np.abs(d))), np.vdot(want, got)
+
+    parts, pending = [], []
+    with ThreadPoolExecutor(8) as pool:
+        for hi in range(1 << (n - m)):
+            pending.append(pool.submit(block, hi, sim.amplitudes(hi << m, 1 << m)))
+            if len(pending) >= 12:
+                parts.append(pending.pop(0).result())
+        parts += [f.result() for f in pending]
+    l2 = math.sqrt(sum(p[0] for p in parts))
+    mx = max(p[1] for p in parts)
+    fid = abs(sum(p[2] for p in parts)) ** 2
+    print(f"  l2 {l2:.4e}  max_abs {mx:.4e}  fidelity {fid:.12f}  bound {tol:.4e}", flush=True)
+    assert l2 <= tol
+
+
 # ---------------------------------------------------------- fused trips
 
 def random_unitary(k, seed):
@@ -221,3 +271,44 @@ def test_more_than_1024_slices(n, sl, cl):
     gates = qc.random_layered(n, 1, seed=n) + qc.grover(n, 1234 % (1 << n), iterations=1)
     sim, orc = run_both(n, sl, cl, 1e-6, gates, check_every=max(1, len(gates) // 4))
     assert np.array_equal(sim.amplitudes(), orc.amplitudes())
+
+
+# ------------------------------------------------------------------ c2
+
+def test_grover24_full_run():
+    """The whole 24-qubit Grover circuit (315,192 passes over 64 slices of
+    2^18, absolute bound 1e-7): the read-out bit-equal to the oracle's run of
+    the same circuit (tests/golden/grover24_full.json, written by
+    tests/golden/make_fullsize.py from the oracle alone) and within the stated
+    distance of Grover's closed form."""
+    import hashlib
+    from tests.brute import grover_closed_form
+    path = os.path.join(GOLDEN, "grover24_full.json")
+    with open(path) as f:
+        want = json.load(f)
+    w = qc.grover_workload(seed=0)
+    n, sl, eb = w.n_qubits, w.slice_log2, w.error_bound
+    assert (n, sl, eb, w.basis, len(w.gates)) == (want["n_qubits"], want["slice_log2"], want["error_bound"],
+                                                  want["marked"], want["passes"])
+    say("grover24 full run", n, sl, eb, "passes", len(w.gates))
+    sim = cq.Sim(n, sl, eb, chunk_log2=8, arena_bytes=(16 << n) // 4)
+    circ = cq.Circuit(w.gates)
+    step = 40000
+    for a in range(0, len(circ), step):
+        assert sim.apply(circ[a:a + step]) == min(step, len(circ) - a)
+        print(f"  pass {min(a + step, len(circ))}", flush=True)
+    amp = sim.amplitudes()
+    words = np.empty(2 * amp.size)
+    words[0::2], words[1::2] = amp.real, amp.imag
+    sha = hashlib.sha256(words.astype("<f8").tobytes()).hexdigest()
+    for i, (re, im) in want["sample"].items():
+        i = int(i)
+        assert (amp[i].real, amp[i].imag) == (float.fromhex(re), float.fromhex(im)), f"amplitude {i}"
+    assert sha == want["readout_sha256"]
+    exact = grover_closed_form(n, w.basis, want["iterations"])
+    err = float(np.linalg.norm(amp - exact))
+    print(f"  l2 error vs closed form {err:.4e} (oracle {want['vs_closed_form']['l2']:.4e}, "
+          f"tolerance {want['tolerance']['l2']:.4e})", flush=True)
+    assert err <= want["tolerance"]["l2"]
+    st = sim.stats()
+    assert st["passes"] == len(w.gates) and st["max_abs_codec_err"] <= eb

@@ -142,3 +142,20 @@ def test_product_state_is_kron_of_factors():
     got = oracle.product_state(f)
     assert np.max(np.abs(got - want)) < 1e-15
     assert abs(np.linalg.norm(got) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("n,m", [(6, 2), (10, 4), (11, 11)])
+def test_qft_product_closed_form_blocks(n, m):
+    """The block-wise closed form used for the 30-qubit check equals sqrt(N)
+    ifft of the Kronecker product state and the oracle's run of the QFT."""
+    from brute import QftProductExact
+    theta, phi = qc.product_angles(n, 2)
+    f = qc.product_factors(theta, phi)
+    psi = np.ones(1, dtype=np.complex128)
+    for q in range(n - 1, -1, -1):
+        psi = np.kron(psi, f[q])
+    want = math.sqrt(1 << n) * np.fft.ifft(psi)
+    ex = QftProductExact(f, m)
+    got = np.concatenate([ex.block(h) for h in range(1 << (n - m))])
+    assert np.max(np.abs(got - want)) < 1e-13
+    assert np.max(np.abs(got - oracle.sv_run(n, qc.qft(n), psi))) < 1e-12
