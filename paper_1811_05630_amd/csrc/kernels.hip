@@ -1818,25 +1818,58 @@ __device__ __forceinline__ void wr_vals(const WRange32 &x, double k, double (&ar
     ai[v] = rw((double)x.i[v] * k);
   }
 }
-__device__ __forceinline__ void wr_lane_partner(const WRange &x, double, uint32_t m, double (&br)[4],
-                                                double (&bi)[4]) {
-#pragma unroll
-  for (int v = 0; v < 4; v++) {
-    br[v] = __shfl_xor(x.r[v], (int)m, 64);
-    bi[v] = __shfl_xor(x.i[v], (int)m, 64);
+// The value of lane l ^ 2^T (T < 6) without going through LDS: DPP inside
+// rows of 16 lanes (quad permutations, row rotations), the row swaps of
+// gfx950 across rows.  A swap of x with itself leaves x's lower row (half) in
+// the first result and its upper one in the second, each in both positions.
+template <int T>
+__device__ __forceinline__ int xor_lanes(int x) {
+  static_assert(T >= 0 && T < 6, "a partner inside the wavefront");
+  if constexpr (T == 0) {
+    return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+  } else if constexpr (T == 1) {
+    return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+  } else if constexpr (T == 2) {
+    const int a = __builtin_amdgcn_mov_dpp(x, 0x124, 0xF, 0xF, false);  // row_ror 4: lane i <- (i - 4) mod 16
+    const int b = __builtin_amdgcn_mov_dpp(x, 0x12C, 0xF, 0xF, false);  // row_ror 12: lane i <- (i + 4) mod 16
+    return (lane_id() & 4u) ? a : b;
+  } else if constexpr (T == 3) {
+    return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);  // row_ror 8: lane i <- i ^ 8
+  } else if constexpr (T == 4) {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)x, false, false);
+    return (int)((lane_id() & 16u) ? r[0] : r[1]);
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+    return (int)((lane_id() & 32u) ? r[0] : r[1]);
   }
 }
-__device__ __forceinline__ void wr_lane_partner(const WRange32 &x, double k, uint32_t m, double (&br)[4],
-                                                double (&bi)[4]) {
+template <int T>
+__device__ __forceinline__ double xor_lanes(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)xor_lanes<T>((int)(uint32_t)b), hi = (uint32_t)xor_lanes<T>((int)(uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+template <int T>
+__device__ __forceinline__ void wr_lane_partner(const WRange &x, double, double (&br)[4], double (&bi)[4]) {
 #pragma unroll
   for (int v = 0; v < 4; v++) {
-    br[v] = rw((double)__shfl_xor(x.r[v], (int)m, 64) * k);
-    bi[v] = rw((double)__shfl_xor(x.i[v], (int)m, 64) * k);
+    br[v] = xor_lanes<T>(x.r[v]);
+    bi[v] = xor_lanes<T>(x.i[v]);
   }
 }
+template <int T>
+__device__ __forceinline__ void wr_lane_partner(const WRange32 &x, double k, double (&br)[4], double (&bi)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    br[v] = rw((double)xor_lanes<T>(x.r[v]) * k);
+    bi[v] = rw((double)xor_lanes<T>(x.i[v]) * k);
+  }
+}
+// KIND 10 + t of the wavefront-range kernels: one target t < 6, the partner in lane ^ 2^t
+constexpr bool lane_x(int kind) { return kind >= 10 && kind <= 15; }
 
-// Gate and quantisation of one range.  KIND 0: identity; 1: one target t <
-// 6, partner element e ^ 2^t in another lane (c0 holds this lane's
+// Gate and quantisation of one range.  KIND 0: identity; 10 + t: one target
+// t < 6, partner element e ^ 2^t in another lane (c0 holds this lane's
 // coefficients); 6 and 7: one target t = 6 or 7, partner at v ^ 2^(t-6) in
 // the same lane (c0, c1: the coefficients of rows 0 and 1); 2: phase.
 // ALLON: no control bit inside the slice (every element takes the gate);
@@ -1860,7 +1893,7 @@ __device__ __forceinline__ void wr_gate_quant(const double (&ar)[4], const doubl
         } else {
           cmul(gd.ph_re, gd.ph_im, ar[v], ai[v], gr, gi);
         }
-      } else if (KIND == 1) {
+      } else if (lane_x(KIND)) {
         gate_pair(c0, ar[v], ai[v], br[v], bi[v], gr, gi);
       } else {  // row of element v: bit t - 6 of v
         const bool row = ((v >> (KIND - 6)) & 1) != 0;
@@ -1886,13 +1919,13 @@ __device__ __forceinline__ void wr_step(const R &x, double k, const GateCoef &c0
                                         const GqSlot &s, const GateDesc &gd, const Geo &g, uint32_t *h, Acc &acc) {
   double ar[4], ai[4], br[4], bi[4];
   wr_vals(x, k, ar, ai);
-  if (KIND == 1) wr_lane_partner(x, k, 1u << gd.tloc[0], br, bi);
+  if constexpr (lane_x(KIND)) wr_lane_partner<KIND - 10>(x, k, br, bi);
 #pragma unroll
   for (int v = 0; v < 4; v++) {
     if (KIND == 6 || KIND == 7) {
       br[v] = ar[v ^ (1 << (KIND - 6))];
       bi[v] = ai[v ^ (1 << (KIND - 6))];
-    } else if (KIND != 1) {
+    } else if (!lane_x(KIND)) {
       br[v] = bi[v] = 0.0;
     }
   }
@@ -1911,8 +1944,8 @@ __device__ __forceinline__ void gq_wave_ranges(const GqSlot &s, double k, const 
   const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint32_t n = (L / kWr) / nwv;  // ranges per wavefront: 1 or even
   auto range_of = [&](uint32_t j) { return (j < n ? w0 + j * nwv : w0) * kWr; };  // past the end: w0 again
-  // KIND 1: this lane's row (bit t of the lane); KIND 5: rows 0 and 1
-  const GateCoef c0 = gate_coef(gd, KIND == 1 && ((lane_id() >> gd.tloc[0]) & 1) != 0);
+  // KIND 10 + t: this lane's row (bit t of the lane); KIND 6, 7: rows 0 and 1
+  const GateCoef c0 = gate_coef(gd, lane_x(KIND) && ((lane_id() >> (KIND - 10)) & 1) != 0);
   const GateCoef c1 = gate_coef(gd, KIND == 6 || KIND == 7);
   R A, B;
   wr_load(A, s.ws, L, range_of(0));
@@ -1940,7 +1973,7 @@ __device__ __forceinline__ void gq_wave_ranges_fp64(const GqSlot &s, const GateD
   const uint32_t L = (uint32_t)g.L;
   const uint32_t nwv = gridDim.x * 4, w0 = blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint32_t n = (L / kWr) / nwv;
-  const GateCoef c0 = gate_coef(gd, KIND == 1 && ((lane_id() >> gd.tloc[0]) & 1) != 0);
+  const GateCoef c0 = gate_coef(gd, lane_x(KIND) && ((lane_id() >> (KIND - 10)) & 1) != 0);
   const GateCoef c1 = gate_coef(gd, KIND == 6 || KIND == 7);
   for (uint32_t j = 0; j < n; j++) {
     WRange A;
@@ -3170,6 +3203,26 @@ static int wave_route(const Geo &g, const GateDesc &gd, int kind) {
   return (cross ? nr : nr / 2) >= 4 ? 2 : 0;
 }
 
+template <bool C32>
+static void launch_gq_wave(int kind, dim3 grid, hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss,
+                           const GateDesc &gd, const QuantParams &qp, Ctl *ctl, uint32_t pass, const double *kscale) {
+#define CQ_GQW(K) CQ_LAUNCH((k_gq_wave<K, C32>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale)
+  switch (kind) {
+    case 0: CQ_GQW(0); break;
+    case 2: CQ_GQW(2); break;
+    case 6: CQ_GQW(6); break;
+    case 7: CQ_GQW(7); break;
+    case 10: CQ_GQW(10); break;
+    case 11: CQ_GQW(11); break;
+    case 12: CQ_GQW(12); break;
+    case 13: CQ_GQW(13); break;
+    case 14: CQ_GQW(14); break;
+    case 15: CQ_GQW(15); break;
+    default: break;
+  }
+#undef CQ_GQW
+}
+
 // Returns the number of partial results per slot that the launch writes.
 template <int KIND>
 static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *ss, int nslots,
@@ -3180,22 +3233,12 @@ static uint32_t launch_gq_k(hipStream_t st, const Slots &sl, const Geo &g, const
     const uint32_t G = nr / 4 < kGqWgs ? nr / 4 : kGqWgs;
     constexpr int K = KIND == 3 ? 0 : KIND;
     const dim3 grid(G, (unsigned)nslots);
-    const int t = KIND == 1 ? gd.tloc[0] : 0;  // 6, 7: partner in the same lane
-    if (compact) {
-      if (t == 6)
-        CQ_LAUNCH((k_gq_wave<6, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
-      else if (t == 7)
-        CQ_LAUNCH((k_gq_wave<7, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
-      else
-        CQ_LAUNCH((k_gq_wave<K, true>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
-    } else {
-      if (t == 6)
-        CQ_LAUNCH((k_gq_wave<6, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
-      else if (t == 7)
-        CQ_LAUNCH((k_gq_wave<7, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
-      else
-        CQ_LAUNCH((k_gq_wave<K, false>), grid, dim3(256), 0, st, sl, g, ss, gd, qp, ctl, pass, kscale);
-    }
+    // one target: t < 6 partner in another lane (kernel 10 + t), 6 and 7 in the same lane
+    const int kk = KIND == 1 ? (gd.tloc[0] < 6 ? 10 + gd.tloc[0] : gd.tloc[0]) : K;
+    if (compact)
+      launch_gq_wave<true>(kk, grid, st, sl, g, ss, gd, qp, ctl, pass, kscale);
+    else
+      launch_gq_wave<false>(kk, grid, st, sl, g, ss, gd, qp, ctl, pass, kscale);
     return G;
   }
   const uint64_t C = gq_tile(g.L);
