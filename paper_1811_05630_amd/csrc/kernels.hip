@@ -2631,18 +2631,6 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
 // also wait for earlier stores), and the LDS chunk buffers are double-buffered
 // between rounds.
 
-__device__ __forceinline__ void put_bits(uint32_t *lw, uint64_t v, int n, uint64_t pos) {
-  while (n > 0) {
-    const uint32_t w = (uint32_t)(pos >> 5);
-    const int off = (int)(pos & 31);
-    const int take = n < 32 - off ? n : 32 - off;
-    const uint32_t piece = (uint32_t)((v >> (n - take)) & ((1ull << take) - 1));
-    atomicOr(&lw[w], piece << (32 - off - take));
-    n -= take;
-    pos += take;
-  }
-}
-
 // A field of n <= 64 bits at bit position pos: at most three words, each
 // touched only where the field has bits in it.
 __device__ __forceinline__ void put_field(uint32_t *lw, uint64_t v, int n, uint64_t pos) {
@@ -2814,17 +2802,34 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
             }
           }
           put_field(lw, acc, (int)bl, pos);
-        } else {
+        } else {  // two symbols per field where they fit in 64 bits, else a field per code and per payload
 #pragma unroll
-          for (int k = 0; k < 4; k++) {
-            if (j + k >= B) break;
-            const uint32_t len = cw[k] & 0xffu;
-            put_bits(lw, cw[k] >> 8, (int)len, pos);
-            pos += len;
-            if (sv[k] == 0) {
-              put_bits(lw, (uint64_t)nb[k], kEscBits, pos);
-              put_bits(lw, z[k], (int)nb[k], pos + kEscBits);
-              pos += kEscBits + nb[k];
+          for (int k = 0; k < 4; k += 2) {
+            const uint32_t l0 = (cw[k] & 0xffu) + (nb[k] ? kEscBits + nb[k] : 0u);
+            const uint32_t l1 = (cw[k + 1] & 0xffu) + (nb[k + 1] ? kEscBits + nb[k + 1] : 0u);
+            if (l0 + l1 <= 64) {
+              uint64_t acc = 0;
+#pragma unroll
+              for (int kk = k; kk < k + 2; kk++) {
+                acc = (acc << (cw[kk] & 0xffu)) | (cw[kk] >> 8);
+                if (nb[kk]) {
+                  acc = (acc << kEscBits) | nb[kk];
+                  acc = (acc << nb[kk]) | z[kk];
+                }
+              }
+              put_field(lw, acc, (int)(l0 + l1), pos);
+              pos += l0 + l1;
+            } else {
+#pragma unroll
+              for (int kk = k; kk < k + 2; kk++) {
+                const uint32_t len = cw[kk] & 0xffu;
+                put_field(lw, cw[kk] >> 8, (int)len, pos);
+                pos += len;
+                if (nb[kk]) {  // 6-bit length and payload: at most 54 bits
+                  put_field(lw, ((uint64_t)nb[kk] << nb[kk]) | z[kk], kEscBits + (int)nb[kk], pos);
+                  pos += kEscBits + nb[kk];
+                }
+              }
             }
           }
         }
@@ -2974,7 +2979,22 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
     const uint32_t i = k * T + tid;
     if (i < nw) stream[bp + i] = sw[k];
   }
-  for (uint32_t i = kU * T + tid; i < nw; i += T) stream[bp + i] = src[i];
+  // the rest in steps of kB words per thread: every load of a step is issued
+  // before its stores, so a step waits for memory once, not once per word
+  constexpr uint32_t kB = 32;
+  for (uint32_t i0 = kU * T; i0 < nw; i0 += kB * T) {
+    uint32_t v[kB];
+#pragma unroll
+    for (uint32_t k = 0; k < kB; k++) {
+      const uint32_t i = i0 + k * T + tid;
+      v[k] = i < nw ? src[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kB; k++) {
+      const uint32_t i = i0 + k * T + tid;
+      if (i < nw) stream[bp + i] = v[k];
+    }
+  }
   if (b != 0) return;
   const double step = qp.pw ? 1.0 : qp.rel ? qstep : qp.step;
   if (tid == 0) {
