@@ -2633,7 +2633,7 @@ __global__ void __launch_bounds__(256) k_codebook(Slots sl, const uint64_t *slot
 
 // A field of n <= 64 bits at bit position pos: at most three words, each
 // touched only where the field has bits in it.
-__device__ __forceinline__ void put_field(uint32_t *lw, uint64_t v, int n, uint64_t pos) {
+__device__ __forceinline__ void put_field(uint32_t *lw, uint64_t v, int n, uint32_t pos) {
   if (n <= 0) return;
   const uint32_t w = (uint32_t)(pos >> 5);
   const int off = (int)(pos & 31);
@@ -2692,17 +2692,30 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
   // without an escape use an offset past the end, which reads nothing.
   const __amdgpu_buffer_rsrc_t escb = buf_rsrc(sl.esc + slot0, (uint32_t)(16 * g.L));
   uint2 cur[STEPS], nxt[STEPS], nn[STEPS];
-  int64_t ecur[STEPS][4], enxt[STEPS][4];
+  int64_t ecur[STEPS][4] = {}, enxt[STEPS][4] = {};
   auto load_syms = [&](uint2 (&d)[STEPS], uint32_t r) {
     const uint32_t c = cb + r * kEncWaves + wave;
-    const uint64_t B = c < ce && r < rounds ? Bc : 0;
+    const bool live = c < ce && r < rounds;
     const uint16_t *sym = sl.sym + slot0 + (uint64_t)(c < ce ? c : 0) * Bc;
+    if (live && Bc >= 256) {  // whole steps of 256: every lane's four symbols lie inside the chunk
 #pragma unroll
-    for (int i = 0; i < STEPS; i++) d[i] = enc_syms(sym, (uint64_t)i * 256 + 4 * (uint64_t)lane, B);
+      for (int i = 0; i < STEPS; i++) d[i] = *(const uint2 *)(sym + i * 256 + 4 * lane);
+    } else {
+      const uint64_t B = live ? Bc : 0;
+#pragma unroll
+      for (int i = 0; i < STEPS; i++) d[i] = enc_syms(sym, (uint64_t)i * 256 + 4 * (uint64_t)lane, B);
+    }
   };
+  // escaped differences of a round whose symbols are in d; nothing is loaded
+  // (and e is never read) when no lane of the wavefront holds an escape
   auto load_escs = [&](int64_t (&e)[STEPS][4], const uint2 (&d)[STEPS], uint32_t r) {
     const uint32_t c = cb + r * kEncWaves + wave;
     const uint64_t B = c < ce && r < rounds ? Bc : 0;
+    bool zsym = false;
+#pragma unroll
+    for (int i = 0; i < STEPS; i++)
+      zsym = zsym || (d[i].x & 0xffffu) == 0 || (d[i].x >> 16) == 0 || (d[i].y & 0xffffu) == 0 || (d[i].y >> 16) == 0;
+    if (__ballot(zsym) == 0) return;
 #pragma unroll
     for (int i = 0; i < STEPS; i++) {
       const uint32_t sv[4] = {d[i].x & 0xffffu, d[i].x >> 16, d[i].y & 0xffffu, d[i].y >> 16};
@@ -2729,9 +2742,10 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       load_escs(enxt, nxt, r + 1);
       const uint32_t c = cb + r * kEncWaves + wave;
       const bool active = c < ce;
-      const uint64_t B = active ? Bc : 0;
+      const uint32_t B = active ? (uint32_t)Bc : 0u;
+      const bool full = B == 256u * STEPS;  // every position of every step lies inside the chunk
       uint32_t *lw = lw_all + (uint64_t)(buf * kEncWaves + wave) * W;
-      uint64_t run = 0;  // the buffer lw is all zero (cleared by the store wavefront)
+      uint32_t run = 0;  // the buffer lw is all zero (cleared by the store wavefront)
       bool nz = false;   // zero-chunk records: a symbol other than the zero difference
       bool cchunk = false;  // constant-chunk records: every symbol after the head is the zero difference
       if (CC) {  // positions past the chunk's end hold the zero difference
@@ -2745,7 +2759,7 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       }
 #pragma unroll
       for (int i = 0; i < STEPS; i++) {
-        const uint64_t j = (uint64_t)i * 256 + 4 * (uint64_t)lane;
+        const uint32_t j = (uint32_t)i * 256u + 4u * lane;
         uint32_t sv[4], cw[4], bl = 0;
         sv[0] = cur[i].x & 0xffffu;
         sv[1] = cur[i].x >> 16;
@@ -2758,7 +2772,7 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
         for (int k = 0; k < 4; k++) cw[k] = codes[sv[k]];  // every symbol is a table index
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-          const bool valid = j + k < B && !(CC && cchunk && j + k > 0);  // a constant chunk codes its head only
+          const bool valid = (full || j + k < B) && !(CC && cchunk && j + k > 0);  // a constant chunk codes its head only
           cw[k] = valid ? cw[k] : 0u;
           bl += cw[k] & 0xffu;
           esc[k] = valid && sv[k] == 0;
@@ -2783,9 +2797,9 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
         }
         const uint32_t inc = wave_incl_scan(bl);
         const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-        uint64_t pos = run + inc - bl;
+        uint32_t pos = run + inc - bl;
         run += tot;
-        if (pos + bl > 32ull * W) continue;  // cannot happen for a consistent codebook
+        if (pos + bl > 32u * W) continue;  // cannot happen for a consistent codebook
         if (!wave_esc) {  // four codes of at most 12 bits: one field
           uint64_t acc = 0;
 #pragma unroll
