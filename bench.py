@@ -42,28 +42,28 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
     "grover34": {
-        "decode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                 "bytes_per_launch": 9192108473},
-        "gate_quant": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                 "bytes_per_launch": 14189887780},
-        "codebook": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                 "bytes_per_launch": 5827156},
-        "encode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                 "bytes_per_launch": 6980876190},
-        "finish": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                 "bytes_per_launch": 1082560152},
+        "decode": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 9191657220},
+        "gate_quant": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 14189855149},
+        "codebook": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 5839575},
+        "encode": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 6980882713},
+        "finish": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 1074944972},
     },
     "grover24": {
-        "gate_quant": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                       "bytes_per_launch": 224755957},
-        "decode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                   "bytes_per_launch": 148202290},
-        "encode": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                   "bytes_per_launch": 83529241},
-        "codebook": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                     "bytes_per_launch": 5819729},
-        "finish": {"kernels_sha256": "14635b34ee73d11dc7666f6203b19b8e5cbef487a9b4fe57f93921bdc8b5a09c",
-                   "bytes_per_launch": 15121536},
+        "decode": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 149626206},
+        "gate_quant": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 221611842},
+        "codebook": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 5862115},
+        "encode": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 82770950},
+        "finish": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
+                 "bytes_per_launch": 16511362},
     },
 }
 
