@@ -23,6 +23,8 @@ FP32 = 2  # mode bit: FP32 working values and gate arithmetic (quantiser and nor
 ZERO_CHUNKS = 8  # mode bit: a chunk whose codes are all zero is stored with no words
 CONST_CHUNKS = 16  # mode bit: a chunk whose values all equal its head keeps only the head (offset bit 31)
 PWREL = 32  # mode bit: pointwise-relative bound (|v - v'| <= eb |v| for every value)
+CHUNK_RUNS = 64  # mode bit: runs of chunks with identical streams store the stream once (flags bit 3)
+MAX_RUNS = 4096  # chunk-run records hold at most this many runs
 
 R = 512
 NSYM = 1024
@@ -327,6 +329,19 @@ def chunk_offsets(rec: bytes) -> np.ndarray:
     h = parse_header(rec)
     o = 64 + ((2 * h["n_used"] + 3) & ~3)
     return np.frombuffer(rec[o:o + 4 * (h["n_chunks"] + 1)], dtype="<u4").astype(np.int64) & 0x7FFFFFFF
+
+
+def chunk_runs(rec: bytes):
+    """A chunk-run record's runs as (ends, word offsets with their marks), or
+    None for a record with a plain offsets table."""
+    h = parse_header(rec)
+    if not h["flags"] & 8:
+        return None
+    o = 64 + ((2 * h["n_used"] + 3) & ~3)
+    R = int(np.frombuffer(rec[o:o + 4], dtype="<u4")[0])
+    ends = np.frombuffer(rec[o + 4:o + 4 + 4 * R], dtype="<u4").astype(np.int64)
+    woff = np.frombuffer(rec[o + 4 + 4 * R:o + 8 + 8 * R], dtype="<u4").astype(np.int64)
+    return ends, woff
 
 
 def constant_chunks(rec: bytes) -> np.ndarray:

@@ -108,6 +108,20 @@ static void cmac(double ur, double ui, double ar, double ai, double *cr, double 
 #define ORC_PWREL 32u
 #define ORC_PW_MAXBITS 20
 
+/* Chunk runs (mode bit ORC_CHUNK_RUNS; an extension: the run-length stage
+ * over the Huffman output that ratios far beyond one bit per value need, one
+ * of the codec variants Section IV leaves to future work): consecutive chunks
+ * whose stored streams are identical (the same words and the same constant
+ * mark) form a run, whose stream is stored once.  Where that makes the record
+ * smaller and the slice has at most ORC_MAX_RUNS runs, the table of chunk
+ * offsets is replaced by: u32 R; R u32 run ends (cumulative chunk counts,
+ * strictly increasing, the last equal to n_chunks); R + 1 u32 word offsets of
+ * the runs' streams (non-decreasing; bit 31 of all but the last is the
+ * constant mark; the last equals n_words).  Header word 14 bit 3 marks such
+ * records.  Codes, amplitudes and norms are those of the mode without it. */
+#define ORC_CHUNK_RUNS 64u
+#define ORC_MAX_RUNS 4096u
+
 /* b for a pointwise-relative bound eb, or -1 when eb is out of range. */
 static int pw_bits(double eb) {
   if (!(eb > 0.0) || !(eb < 0.5)) return -1;
@@ -616,46 +630,9 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
   }
   uint64_t n_words = coff[nchunks];
   uint64_t symtab_bytes = ((2 * (uint64_t)n_used) + 3) & ~(uint64_t)3;
-  uint64_t total = ORC_HDR + symtab_bytes + 4 * (nchunks + 1) + 4 * n_words;
-  if (total > 0xFFFFFFFFull) {
-    free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
-    return ORC_EINVAL;
-  }
-  uint8_t *rec = (uint8_t *)calloc(total, 1);
-  if (!rec) {
-    free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
-    return ORC_ENOMEM;
-  }
-  wr32(rec + 0, ORC_MAGIC);
-  wr32(rec + 4, (uint32_t)slice_log2);
-  wr32(rec + 8, (uint32_t)chunk_log2);
-  wr32(rec + 12, n_used);
-  wr32(rec + 16, (uint32_t)nchunks);
-  wr32(rec + 20, (uint32_t)n_words);
-  wr32(rec + 24, (uint32_t)nesc);
-  wr32(rec + 28, (uint32_t)total);
-  wrf64(rec + 32, step);
-  wr64(rec + 40, (uint64_t)sumsq);
-  wr64(rec + 48, (uint64_t)(sumsq >> 64));
-  wr32(rec + 56, (zc ? 1u : 0u) | (cc ? 2u : 0u) | (pw ? 4u : 0u));
-  wr32(rec + 60, pw ? (uint32_t)pw_bits(eb) : 0u);
-  /* symbol table in canonical order: by code length, then by symbol */
-  uint8_t *tab = rec + ORC_HDR;
-  uint32_t k = 0;
-  for (int l = 0; l <= ORC_LMAX; l++) {
-    for (int s = 0; s < ORC_NSYM; s++) {
-      if (!hist[s] || lens[s] != l) continue;
-      uint16_t e = (uint16_t)((unsigned)s | ((unsigned)lens[s] << 10));
-      memcpy(tab + 2 * k, &e, 2);
-      k++;
-    }
-  }
-  uint8_t *offs = tab + symtab_bytes;
-  for (uint64_t c = 0; c <= nchunks; c++)
-    wr32(offs + 4 * c, (uint32_t)coff[c] | (c < nchunks && cconst[c] ? ORC_CONST_MARK : 0u));
   uint32_t *words = (uint32_t *)calloc(n_words ? n_words : 1, sizeof(uint32_t));
   if (!words) {
-    free(rec); free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
+    free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
     return ORC_ENOMEM;
   }
   for (uint64_t c = 0; c < nchunks; c++) {
@@ -674,8 +651,86 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
       }
     }
   }
-  memcpy(offs + 4 * (nchunks + 1), words, 4 * n_words);
+  /* chunk runs: a chunk starts a run unless its stream (words and constant
+   * mark) equals its predecessor's */
+  uint64_t nruns = 0, run_words = 0;
+  uint32_t *run_src = NULL;
+  if (mode & ORC_CHUNK_RUNS) {
+    run_src = (uint32_t *)malloc(sizeof(uint32_t) * (ORC_MAX_RUNS + 1));
+    if (!run_src) {
+      free(words); free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
+      return ORC_ENOMEM;
+    }
+    for (uint64_t c = 0; c < nchunks; c++) {
+      uint64_t nw = coff[c + 1] - coff[c];
+      int same = c > 0 && cconst[c] == cconst[c - 1] && nw == coff[c] - coff[c - 1] &&
+                 memcmp(words + coff[c], words + coff[c - 1], 4 * nw) == 0;
+      if (same) continue;
+      if (nruns < ORC_MAX_RUNS) {
+        run_src[nruns] = (uint32_t)c;
+        run_words += nw;
+      }
+      nruns++;
+    }
+  }
+  const int use_runs = (mode & ORC_CHUNK_RUNS) && nruns <= ORC_MAX_RUNS &&
+                       8 * nruns + 8 + 4 * run_words < 4 * (nchunks + 1) + 4 * n_words;
+  uint64_t table_bytes = use_runs ? 8 * nruns + 8 : 4 * (nchunks + 1);
+  uint64_t stored_words = use_runs ? run_words : n_words;
+  uint64_t total = ORC_HDR + symtab_bytes + table_bytes + 4 * stored_words;
+  if (total > 0xFFFFFFFFull) {
+    free(words); free(run_src); free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
+    return ORC_EINVAL;
+  }
+  uint8_t *rec = (uint8_t *)calloc(total, 1);
+  if (!rec) {
+    free(words); free(run_src); free(v); free(p); free(d); free(sym); free(cbits); free(coff); free(cconst);
+    return ORC_ENOMEM;
+  }
+  wr32(rec + 0, ORC_MAGIC);
+  wr32(rec + 4, (uint32_t)slice_log2);
+  wr32(rec + 8, (uint32_t)chunk_log2);
+  wr32(rec + 12, n_used);
+  wr32(rec + 16, (uint32_t)nchunks);
+  wr32(rec + 20, (uint32_t)stored_words);
+  wr32(rec + 24, (uint32_t)nesc);
+  wr32(rec + 28, (uint32_t)total);
+  wrf64(rec + 32, step);
+  wr64(rec + 40, (uint64_t)sumsq);
+  wr64(rec + 48, (uint64_t)(sumsq >> 64));
+  wr32(rec + 56, (zc ? 1u : 0u) | (cc ? 2u : 0u) | (pw ? 4u : 0u) | (use_runs ? 8u : 0u));
+  wr32(rec + 60, pw ? (uint32_t)pw_bits(eb) : 0u);
+  /* symbol table in canonical order: by code length, then by symbol */
+  uint8_t *tab = rec + ORC_HDR;
+  uint32_t k = 0;
+  for (int l = 0; l <= ORC_LMAX; l++) {
+    for (int s = 0; s < ORC_NSYM; s++) {
+      if (!hist[s] || lens[s] != l) continue;
+      uint16_t e = (uint16_t)((unsigned)s | ((unsigned)lens[s] << 10));
+      memcpy(tab + 2 * k, &e, 2);
+      k++;
+    }
+  }
+  uint8_t *offs = tab + symtab_bytes;
+  if (use_runs) {
+    uint8_t *ends = offs + 4, *woff = ends + 4 * nruns, *stream = woff + 4 * (nruns + 1);
+    wr32(offs, (uint32_t)nruns);
+    uint64_t w = 0;
+    for (uint64_t r = 0; r < nruns; r++) {
+      uint64_t c = run_src[r], nw = coff[c + 1] - coff[c];
+      wr32(ends + 4 * r, r + 1 < nruns ? run_src[r + 1] : (uint32_t)nchunks);
+      wr32(woff + 4 * r, (uint32_t)w | (cconst[c] ? ORC_CONST_MARK : 0u));
+      memcpy(stream + 4 * w, words + coff[c], 4 * nw);
+      w += nw;
+    }
+    wr32(woff + 4 * nruns, (uint32_t)w);
+  } else {
+    for (uint64_t c = 0; c <= nchunks; c++)
+      wr32(offs + 4 * c, (uint32_t)coff[c] | (c < nchunks && cconst[c] ? ORC_CONST_MARK : 0u));
+    memcpy(offs + 4 * (nchunks + 1), words, 4 * n_words);
+  }
   free(words);
+  free(run_src);
   if (st) {
     st->max_err = max_err;
     st->n_escapes = nesc;
@@ -693,10 +748,12 @@ int orc_compress_slice(const double *re, const double *im, int slice_log2, int c
 
 typedef struct {
   uint32_t slice_log2, chunk_log2, n_used, n_chunks, n_words, n_escapes, total, flags, pw_bits;
+  uint32_t nruns;  /* chunk-run records: the number of runs (0 otherwise) */
   double step;
   uint64_t sumsq_lo, sumsq_hi;
   const uint8_t *symtab;
-  const uint8_t *offs;
+  const uint8_t *offs;  /* chunk offsets, or (chunk-run records) the run ends */
+  const uint8_t *woff;  /* chunk-run records: the runs' word offsets */
   const uint8_t *words;
 } orc_rec;
 
@@ -714,18 +771,43 @@ int orc_parse(const uint8_t *rec, uint64_t len, orc_rec *h) {
   h->sumsq_hi = rd64(rec + 48);
   h->flags = rd32(rec + 56);
   h->pw_bits = rd32(rec + 60);
-  if (h->flags > 7) return ORC_ECORRUPT;
+  if (h->flags > 15) return ORC_ECORRUPT;
   if (h->flags & 4 ? (h->pw_bits > ORC_PW_MAXBITS || h->step != 1.0 || h->sumsq_hi != 0) : h->pw_bits != 0)
     return ORC_ECORRUPT;
   if (h->slice_log2 > 26 || h->chunk_log2 > h->slice_log2) return ORC_ECORRUPT;
   if (h->n_chunks != (uint32_t)((2ull << h->slice_log2) >> h->chunk_log2)) return ORC_ECORRUPT;
   if (h->n_used < 1 || h->n_used > ORC_NSYM) return ORC_ECORRUPT;
   uint64_t symtab_bytes = ((2 * (uint64_t)h->n_used) + 3) & ~(uint64_t)3;
-  uint64_t total = ORC_HDR + symtab_bytes + 4 * ((uint64_t)h->n_chunks + 1) + 4 * (uint64_t)h->n_words;
-  if (total != h->total || total > len) return ORC_ECORRUPT;
   h->symtab = rec + ORC_HDR;
-  h->offs = h->symtab + symtab_bytes;
-  h->words = h->offs + 4 * ((uint64_t)h->n_chunks + 1);
+  uint64_t table_bytes = 4 * ((uint64_t)h->n_chunks + 1);
+  h->nruns = 0;
+  h->woff = NULL;
+  if (h->flags & 8) {
+    if (len < ORC_HDR + symtab_bytes + 4) return ORC_ECORRUPT;
+    h->nruns = rd32(h->symtab + symtab_bytes);
+    if (h->nruns < 1 || h->nruns > h->n_chunks || h->nruns > ORC_MAX_RUNS) return ORC_ECORRUPT;
+    table_bytes = 8 * (uint64_t)h->nruns + 8;
+  }
+  uint64_t total = ORC_HDR + symtab_bytes + table_bytes + 4 * (uint64_t)h->n_words;
+  if (total != h->total || total > len) return ORC_ECORRUPT;
+  if (h->flags & 8) {
+    h->offs = h->symtab + symtab_bytes + 4;
+    h->woff = h->offs + 4 * (uint64_t)h->nruns;
+    /* run ends strictly increasing up to n_chunks; word offsets non-decreasing
+     * up to n_words, the last without a mark */
+    uint32_t prev_end = 0, prev_w = 0;
+    for (uint32_t r = 0; r < h->nruns; r++) {
+      uint32_t e = rd32(h->offs + 4 * (uint64_t)r), w = rd32(h->woff + 4 * (uint64_t)r) & ~ORC_CONST_MARK;
+      if (e <= prev_end || w < prev_w) return ORC_ECORRUPT;
+      prev_end = e;
+      prev_w = w;
+    }
+    uint32_t wl = rd32(h->woff + 4 * (uint64_t)h->nruns);
+    if (prev_end != h->n_chunks || wl != h->n_words || wl < prev_w) return ORC_ECORRUPT;
+  } else {
+    h->offs = h->symtab + symtab_bytes;
+  }
+  h->words = h->symtab + symtab_bytes + table_bytes;
   return ORC_OK;
 }
 
@@ -802,11 +884,29 @@ int orc_decode_p(const uint8_t *rec, uint64_t len, int64_t *p) {
     }
   }
   uint64_t B = (uint64_t)1 << h.chunk_log2;
+  uint32_t run = 0, run_begin = 0; /* chunk-run records: the run holding chunk c */
   for (uint64_t c = 0; c < h.n_chunks; c++) {
-    uint32_t o0 = rd32(h.offs + 4 * c), o1 = rd32(h.offs + 4 * (c + 1));
+    uint32_t o0, o1;
+    if (h.flags & 8) {
+      uint32_t end = rd32(h.offs + 4 * run);
+      while (end <= c) { /* the next run: its end must lie beyond the previous one */
+        run_begin = end;
+        if (++run >= h.nruns) return ORC_ECORRUPT;
+        end = rd32(h.offs + 4 * run);
+        if (end <= run_begin) return ORC_ECORRUPT;
+      }
+      if (run + 1 == h.nruns && end != h.n_chunks) return ORC_ECORRUPT;
+      o0 = rd32(h.woff + 4 * run);
+      o1 = rd32(h.woff + 4 * (run + 1));
+      if (run + 1 == h.nruns && (o1 & ~ORC_CONST_MARK) != h.n_words) return ORC_ECORRUPT;
+      if (run + 1 == h.nruns && (o1 & ORC_CONST_MARK)) return ORC_ECORRUPT;
+    } else {
+      o0 = rd32(h.offs + 4 * c);
+      o1 = rd32(h.offs + 4 * (c + 1));
+      if (c + 1 == h.n_chunks && (o1 & ORC_CONST_MARK)) return ORC_ECORRUPT;
+    }
     const int cconst = (o0 & ORC_CONST_MARK) != 0;
     if (cconst && !(h.flags & 2)) return ORC_ECORRUPT;
-    if (c + 1 == h.n_chunks && (o1 & ORC_CONST_MARK)) return ORC_ECORRUPT;
     uint32_t w0 = o0 & ~ORC_CONST_MARK, w1 = o1 & ~ORC_CONST_MARK;
     if (w1 < w0 || w1 > h.n_words) return ORC_ECORRUPT;
     if (!cconst && w1 == w0 && h.n_used > 1) { /* an empty chunk under a real code: all zero */
