@@ -75,6 +75,15 @@ extern "C" {
                                squared norm as an FP64 value (a pairwise tree over its 2L values).
                                Excludes SIM_EB_REL */
 
+#define SIM_CHUNK_RUNS 0x40u /* chunk runs (an extension: a run-length stage over the Huffman output, one
+                                of the compression variants Section IV leaves to future work):
+                                consecutive chunks whose stored streams are identical (the same words and
+                                constant mark) form a run whose stream is stored once.  Where that makes
+                                a record smaller and the slice has at most 4096 runs, the chunk offsets
+                                are replaced by u32 R, R run ends (cumulative chunk counts) and R + 1 word
+                                offsets of the runs' streams; header word 14 bit 3 marks such records.
+                                Codes, amplitudes and norms are unchanged; only record sizes shrink */
+
 #define SIM_FUSE_MAX 5   /* widest fused block, in qubits */
 
 /* ---- gate kinds (Section II: the circuit is a sequence of gates applied one

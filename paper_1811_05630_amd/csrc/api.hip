@@ -30,6 +30,7 @@ using cq::f64::launch_begin_pass;
 using cq::f64::launch_codebook;
 using cq::f64::launch_encode;
 using cq::f64::launch_finish;
+using cq::f64::launch_runs;
 using cq::f64::launch_rel_step;
 using cq::f64::launch_reset_slots;
 
@@ -65,9 +66,10 @@ namespace {
   } while (0)
 
 enum KClass { K_BEGIN, K_RESET, K_INIT, K_DECODE, K_MINMAX, K_RELSTEP, K_GATEQ, K_CODEBOOK, K_ENCODE, K_FINISH,
-              K_READOUT, K_DENSE, K_COUNT };
+              K_READOUT, K_DENSE, K_RUNS, K_COUNT };
 const char *kClassNames =
-    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,encode,finish,readout,dense_mfma";
+    "begin_pass,reset_slots,init,decode,gate_minmax,rel_step,gate_quant,codebook,encode,finish,readout,dense_mfma,"
+    "runs";
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -238,6 +240,10 @@ int alloc_slots(sim_t *s) {
   sl.stage_words = stage_words_for(s->geo.chunk_log2);
   if ((rc = s->dalloc((void **)&sl.stage, 4ull * W * s->geo.nchunks * sl.stage_words))) return rc;
   if ((rc = s->dalloc((void **)&sl.csum, 8ull * W * s->geo.nchunks))) return rc;
+  if ((rc = s->dalloc((void **)&sl.run_src, 4ull * W * kMaxRuns))) return rc;
+  if ((rc = s->dalloc((void **)&sl.run_woff, 4ull * W * (kMaxRuns + 1)))) return rc;
+  if ((rc = s->dalloc((void **)&sl.nruns, 4 * W))) return rc;
+  if ((rc = s->dalloc((void **)&sl.run_words, 4 * W))) return rc;
   return SIM_OK;
 }
 
@@ -272,12 +278,16 @@ uint64_t carve_slots(const Geo &g, uint64_t W, uint8_t *base, Slots *sl) {
   o.stage_words = stage_words_for(g.chunk_log2);
   take(&o.stage, 4ull * W * g.nchunks * o.stage_words);
   take(&o.csum, 8ull * W * g.nchunks);
+  take(&o.run_src, 4ull * W * kMaxRuns);
+  take(&o.run_woff, 4ull * W * (kMaxRuns + 1));
+  take(&o.nruns, 4 * W);
+  take(&o.run_words, 4 * W);
   return off;
 }
 
 uint64_t per_slot_bytes(const Geo &g) {
   return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 2) + 4ull * kGqParts * (kNSym + 8) + 12ull * g.nchunks +
-         4ull * g.nchunks * stage_words_for(g.chunk_log2) + 4ull * kMaxEncBlocks + 128;
+         4ull * g.nchunks * stage_words_for(g.chunk_log2) + 4ull * kMaxEncBlocks + 8ull * kMaxRuns + 140;
 }
 
 // Slot order of every slice for gates whose slice-index targets form `gm`:
@@ -674,6 +684,11 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
     s->kt_begin(K_ENCODE);
     launch_encode(st, slots, s->geo, ns, s->ctl);
     s->kt_end();
+    if (s->geo.chunk_runs) {
+      s->kt_begin(K_RUNS);
+      launch_runs(st, slots, s->geo, ns, s->ctl);
+      s->kt_end();
+    }
     s->kt_begin(K_FINISH);
     launch_finish(st, slots, s->geo, ss, ns, qp, s->arena[1 - c], s->arena_cap[1 - c], nxt, s->ctl, pass);
     s->kt_end();
@@ -838,7 +853,8 @@ int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   if (sl2 < 1 || sl2 > n || sl2 > 26) return set_err(SIM_EINVAL, "slice_log2 %d outside 1..min(26, n)", sl2);
   if (!(cfg->error_bound > 0.0) || !std::isfinite(cfg->error_bound))
     return set_err(SIM_EINVAL, "error bound must be positive and finite");
-  if (cfg->mode & ~(SIM_EB_REL | SIM_FP32 | SIM_FUSED | SIM_ZERO_CHUNKS | SIM_CONST_CHUNKS | SIM_EB_PWREL))
+  if (cfg->mode & ~(SIM_EB_REL | SIM_FP32 | SIM_FUSED | SIM_ZERO_CHUNKS | SIM_CONST_CHUNKS | SIM_EB_PWREL |
+                    SIM_CHUNK_RUNS))
     return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
   if ((cfg->mode & SIM_EB_REL) && (cfg->mode & SIM_EB_PWREL))
     return set_err(SIM_EINVAL, "SIM_EB_REL and SIM_EB_PWREL exclude each other");
@@ -861,6 +877,7 @@ int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   s->geo.const_chunks = (cfg->mode & SIM_CONST_CHUNKS) ? 1u : 0u;
   s->geo.fmt_in = s->geo.zero_chunks | (s->geo.const_chunks << 1);
   s->geo.pw_bits = pwb;
+  s->geo.chunk_runs = (cfg->mode & SIM_CHUNK_RUNS) ? 1u : 0u;
   s->eb = cfg->error_bound;
   s->mode = cfg->mode;
   s->fp32 = (cfg->mode & SIM_FP32) != 0;
@@ -1586,7 +1603,18 @@ static int check_record(const sim_t *s, const uint8_t *r, uint64_t len, double *
   if ((int)sl2 != s->geo.slice_log2 || (int)cl2 != s->geo.chunk_log2 || nch != s->geo.nchunks)
     return set_err(SIM_ECORRUPT, "record geometry does not match the simulator");
   if (n_used < 1 || n_used > (uint32_t)kNSym) return set_err(SIM_ECORRUPT, "bad symbol count");
-  if (rec_bytes_host(n_used, nch, nw) != tot || tot != len) return set_err(SIM_ECORRUPT, "inconsistent size");
+  const uint32_t flags = rd32(56);
+  if (flags > 15) return set_err(SIM_ECORRUPT, "unknown header flags");
+  const uint64_t ooff = kHdr + ((2ull * n_used + 3) & ~3ull);
+  uint32_t nruns = 0;  // chunk runs (flags bit 3)
+  if (flags & 8) {
+    if (len < ooff + 4) return set_err(SIM_ECORRUPT, "short record");
+    nruns = rd32(ooff);
+    if (nruns < 1 || nruns > nch || nruns > kMaxRuns) return set_err(SIM_ECORRUPT, "bad run count");
+    if (ooff + 8ull * nruns + 8 + 4ull * nw != tot || tot != len) return set_err(SIM_ECORRUPT, "inconsistent size");
+  } else if (rec_bytes_host(n_used, nch, nw) != tot || tot != len) {
+    return set_err(SIM_ECORRUPT, "inconsistent size");
+  }
   uint64_t kraft = 0;
   int prev = -1;
   for (uint32_t k = 0; k < n_used; k++) {
@@ -1599,24 +1627,31 @@ static int check_record(const sim_t *s, const uint8_t *r, uint64_t len, double *
     kraft += 1ull << (kLMax - l);
   }
   if (kraft != (1ull << kLMax)) return set_err(SIM_ECORRUPT, "symbol table is not a complete prefix code");
-  const uint32_t flags = rd32(56);
-  if (flags > 7) return set_err(SIM_ECORRUPT, "unknown header flags");
   // pointwise-relative records (flags bit 2, word 15 their mantissa bits) only in that mode, with its bits
   const bool pw = (flags & 4) != 0;
   if (pw != (s->geo.pw_bits >= 0) || rd32(60) != (pw ? (uint32_t)s->geo.pw_bits : 0u))
     return set_err(SIM_ECORRUPT, "record's bound kind does not match the simulator");
-  const uint64_t ooff = kHdr + ((2ull * n_used + 3) & ~3ull);
-  uint32_t prevw = 0;
+  // the streams' word offsets (per chunk, or per run after the run ends):
+  // non-decreasing from 0 to n_words, constant marks only where allowed, an
+  // empty stream only with zero chunks (or as a constant chunk)
+  const uint32_t nent = nruns ? nruns : nch;
+  const uint64_t woff = nruns ? ooff + 4 + 4ull * nruns : ooff;
+  uint32_t prevw = 0, prev_end = 0;
   bool prev_const = false;
-  for (uint32_t c = 0; c <= nch; c++) {
-    const uint32_t x = rd32(ooff + 4ull * c);
+  for (uint32_t c = 0; c <= nent; c++) {
+    const uint32_t x = rd32(woff + 4ull * c);
     const bool cst = (x >> 31) != 0;
     const uint32_t w = x & 0x7FFFFFFFu;
-    if (cst && (!(flags & 2) || c == nch)) return set_err(SIM_ECORRUPT, "bad constant-chunk mark");
-    if (w < prevw || w > nw || (c == 0 && w != 0) || (c == nch && w != nw))
+    if (cst && (!(flags & 2) || c == nent)) return set_err(SIM_ECORRUPT, "bad constant-chunk mark");
+    if (w < prevw || w > nw || (c == 0 && w != 0) || (c == nent && w != nw))
       return set_err(SIM_ECORRUPT, "bad chunk offsets");
     if (c > 0 && w == prevw && n_used > 1 && !prev_const && !(flags & 1))
       return set_err(SIM_ECORRUPT, "empty chunk in a record without zero chunks");
+    if (nruns && c < nent) {  // run ends: strictly increasing, the last n_chunks
+      const uint32_t e = rd32(ooff + 4 + 4ull * c);
+      if (e <= prev_end || (c + 1 == nent && e != nch)) return set_err(SIM_ECORRUPT, "bad chunk runs");
+      prev_end = e;
+    }
     prevw = w;
     prev_const = cst;
   }

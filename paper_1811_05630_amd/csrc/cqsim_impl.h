@@ -18,7 +18,7 @@ namespace cq {
 //   8  u32 chunk_log2                48 u64 sum p^2, high 64 bits
 //  12  u32 n_used (coded symbols)    56 u32 flags: bit 0 zero chunks, bit 1 constant chunks,
 //                                       bit 2 pointwise-relative codes (step 1, the sum field
-//                                       an FP64 squared norm)
+//                                       an FP64 squared norm), bit 3 chunk runs
 //                                    60 u32 pointwise-relative mantissa bits, else 0
 //  16  u32 n_chunks = 2L/B
 //  20  u32 n_words (bit stream)
@@ -27,6 +27,11 @@ namespace cq {
 //  64  n_used x u16 (symbol | length << 10) ordered by (length, symbol), padded to 4 bytes
 //      (n_chunks + 1) x u32 word offset of each chunk in the bit stream
 //      n_words x u32 bit stream, most significant bit first, chunks word-aligned
+// With chunk runs (flags bit 3), consecutive chunks with identical streams
+// share one stored stream, and the offsets table is instead: u32 R (at most
+// kMaxRuns), R x u32 run ends (cumulative chunk counts, the last n_chunks),
+// (R + 1) x u32 word offsets of the runs' streams (the last n_words).  A
+// chunk's word offset (or its run's) carries the constant mark in bit 31.
 constexpr uint32_t kMagic = 0x31535143u;
 constexpr int kHdr = 64;
 constexpr int kR = 512;       // quantisation radius: symbol d + R for |d| < R
@@ -107,6 +112,7 @@ struct Geo {
                           // the modes, or imported records
   int pw_bits;            // -1, or pointwise-relative records: a code is a value's bit pattern without
                           // the sign, rounded to pw_bits mantissa bits and shifted right by 52 - pw_bits
+  uint32_t chunk_runs;    // SIM_CHUNK_RUNS: runs of chunks with identical streams store the stream once
 };
 
 // Per-slot scratch of one batch of decompressed slices.
@@ -137,6 +143,11 @@ struct Slots {
   uint64_t *part;         // [W][kGqParts][4] sum p^2 lo, hi, escapes, max error bits
   double *csum;           // [W][nchunks] pointwise-relative mode: each chunk's sum of squared stored
                           // values as a pairwise tree in index order (the codebook sums the slice)
+  // chunk runs (SIM_CHUNK_RUNS), written by the runs kernel after encode
+  uint32_t *run_src;      // [W][kMaxRuns] first chunk of each run
+  uint32_t *run_woff;     // [W][kMaxRuns + 1] word offset of each run's stream in the record | mark
+  uint32_t *nruns;        // [W] number of runs (may exceed kMaxRuns: then the plain layout)
+  uint32_t *run_words;    // [W] words of the runs' streams
 };
 
 // Per-slice stored-state metadata (one copy per arena).
@@ -204,6 +215,8 @@ void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, co
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
                      uint32_t nparts, Ctl *ctl, uint32_t pw_nchunks = 0);
 void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
+// chunk runs of each slot of the batch (SIM_CHUNK_RUNS), between encode and finish
+void launch_runs(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
 // records of the batch: offsets in the output arena, headers, symbol tables,
 // chunk offsets, bit streams, per-slice metadata
 void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,
@@ -220,6 +233,7 @@ CQ_AMPLITUDE_LAUNCHERS
 inline uint64_t gq_tile(uint64_t L) { return L < 1024 ? L : 1024; }
 constexpr uint32_t kGqWgs = 16;
 constexpr uint32_t kMaxEncBlocks = 1024;  // encode (and finish) workgroups per slot, at most
+constexpr uint32_t kMaxRuns = 4096;       // chunk runs of a record, at most
 constexpr uint32_t kGqParts = 2 * kGqWgs;
 
 // words of one chunk's staging slot

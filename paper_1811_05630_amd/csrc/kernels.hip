@@ -436,8 +436,9 @@ __device__ __forceinline__ typename DecFmt<C32>::T dec_val(typename DecFmt<C32>:
 template <bool FULL, bool C32, int FMT>
 __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, const StateMeta &cur, uint64_t slice,
                                               uint32_t u, const uint32_t *offs, uint32_t nchunks, uint32_t n_words,
-                                              uint32_t n_used, double k, uint32_t *dtab, uint8_t *stg,
-                                              uint32_t (*pf)[64 * kDecWaves], Ctl *ctl, uint32_t pass) {
+                                              uint32_t n_used, uint32_t nruns, double k, uint32_t *dtab,
+                                              uint8_t *stg, uint32_t (*pf)[64 * kDecWaves], Ctl *ctl,
+                                              uint32_t pass) {
   using F = DecFmt<C32>;
   using T = typename F::T;
   constexpr int PF = F::PF, RMAX = F::R, PITCH = F::PITCH;
@@ -450,9 +451,26 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   br.nw = 0;
   constexpr bool ZC = (FMT & 1) != 0, CC = (FMT & 2) != 0;
   bool cconst = false;  // a constant chunk: its head, then the zero difference
+  const uint32_t *stream = offs + (nchunks + 1);  // the bit stream
   if (active) {
-    w0 = offs[c];
-    uint32_t w1 = offs[c + 1];
+    uint32_t w1;
+    if (nruns) {  // chunk runs: the run holding chunk c, by binary search over the run ends
+      const uint32_t *ends = offs + 1, *wo = offs + 1 + nruns;
+      uint32_t lo = 0, hi = nruns - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ends[mid] > c)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      w0 = wo[lo];
+      w1 = wo[lo + 1];
+      stream = wo + nruns + 1;
+    } else {
+      w0 = offs[c];
+      w1 = offs[c + 1];
+    }
     if (CC) {
       cconst = (w0 >> 31) != 0;
       w0 &= 0x7FFFFFFFu;
@@ -469,7 +487,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   // one-symbol code has no bits: its chunks are empty and decode normally)
   const bool zero = ZC && active && !cconst && br.nw == 0 && n_used > 1;
   constexpr uint32_t kZeroPair = (uint32_t)kR | ((uint32_t)kR << 14) | (1u << 28);  // dtab_entry(R, 0, R, 0, true)
-  br.w = offs + (nchunks + 1) + w0;
+  br.w = stream + w0;
   br.wi = 0;
   br.buf = 0;
   br.nbits = 0;
@@ -603,12 +621,18 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
   for (uint32_t k = 0; k < kN; k++) ((uint4 *)dtab)[tid + k * kT] = dt[k];
   const uint32_t sym_bytes = (2 * n_used + 3) & ~3u;
   const uint32_t *offs = (const uint32_t *)(rec + kHdr + sym_bytes);
+  // chunk runs (flags bit 3): the table starts with the number of runs
+  const uint32_t nruns = (ld32(rec + 56) & 8u) ? offs[0] : 0u;
+  if ((ld32(rec + 56) & 8u) && (nruns < 1 || nruns > nchunks || nruns > kMaxRuns)) {
+    if (tid == 0) fail(ctl, kFlagCorrupt, pass);
+    return;
+  }
   if (c32)
-    decode_chunks<FULL, true, FMT>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, 0.0, dtab, stg, pf, ctl,
-                                   pass);
+    decode_chunks<FULL, true, FMT>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns, 0.0, dtab, stg, pf,
+                                   ctl, pass);
   else
-    decode_chunks<FULL, false, FMT>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, kscale[slice], dtab, stg,
-                                    pf, ctl, pass);
+    decode_chunks<FULL, false, FMT>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns, kscale[slice],
+                                    dtab, stg, pf, ctl, pass);
 }
 
 // ------------------------------------------------------------ gate + quantise
@@ -2889,6 +2913,81 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
   }
 }
 
+// ------------------------------------------------------------------ chunk runs
+// One workgroup per slot (SIM_CHUNK_RUNS): chunk c starts a run unless its
+// staged stream -- word count, constant mark and words -- equals chunk
+// c - 1's.  Tiles of one chunk per thread; block scans number the runs and
+// sum their words.  The first kMaxRuns runs get their first chunk and the
+// word offset of their stream (with the mark); nruns and run_words hold the
+// totals, from which finish chooses the record layout.
+__global__ void __launch_bounds__(1024) k_runs(Slots sl, Geo g, uint32_t cpb, const Ctl *ctl) {
+  if (ctl->flags) return;
+  __shared__ uint32_t scan[17];
+  const uint32_t u = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
+  const uint32_t nch = g.nchunks, W = sl.stage_words;
+  const uint32_t *cw = sl.chunk_words + (uint64_t)u * nch;
+  const uint32_t *bw = sl.blk_words + (uint64_t)u * kMaxEncBlocks;
+  const uint32_t *stage = sl.stage + (uint64_t)u * nch * W;
+  uint32_t *src = sl.run_src + (uint64_t)u * kMaxRuns;
+  uint32_t *woff = sl.run_woff + (uint64_t)u * (kMaxRuns + 1);
+  // chunk c's words: staged at block b's region (b * cpb chunks in) plus its
+  // packed offset; they end at the next chunk's offset or the block's total
+  auto span = [&](uint32_t c, uint64_t &w0, uint32_t &n, uint32_t &mark) {
+    const uint32_t b = c / cpb, x = cw[c], off = x & 0x7FFFFFFFu;
+    const uint32_t end = (c + 1 < nch && (c + 1) / cpb == b) ? (cw[c + 1] & 0x7FFFFFFFu) : bw[b];
+    w0 = (uint64_t)b * cpb * W + off;
+    n = end - off;
+    mark = x & 0x80000000u;
+  };
+  uint32_t runs = 0, words = 0;  // over the tiles so far (uniform)
+  for (uint32_t t0 = 0; t0 < nch; t0 += T) {
+    const uint32_t c = t0 + tid;
+    uint32_t start = 0, nw = 0, mark = 0;
+    if (c < nch) {
+      uint64_t w0;
+      span(c, w0, nw, mark);
+      start = 1;
+      if (c > 0) {
+        uint64_t p0;
+        uint32_t pn, pm;
+        span(c - 1, p0, pn, pm);
+        if (pn == nw && pm == mark) {
+          uint32_t i = 0;
+          while (i < nw && stage[w0 + i] == stage[p0 + i]) i++;
+          start = i == nw ? 0u : 1u;
+        }
+      }
+    }
+    uint32_t tile_runs, tile_words;
+    const uint32_t r = runs + block_excl_scan(start, scan, &tile_runs);
+    const uint32_t w = words + block_excl_scan(start ? nw : 0u, scan, &tile_words);
+    if (start && r < kMaxRuns) {
+      src[r] = c;
+      woff[r] = w | mark;
+    }
+    runs += tile_runs;
+    words += tile_words;
+  }
+  if (tid == 0) {
+    sl.nruns[u] = runs;
+    sl.run_words[u] = words;
+    if (runs <= kMaxRuns) woff[runs] = words;
+  }
+}
+
+// The layout of slot v's record: chunk runs when the mode is on, the slot
+// has at most kMaxRuns runs and that layout is the smaller; its bytes.
+__device__ __forceinline__ uint64_t slot_rec_bytes(const Slots &sl, const Geo &g, uint32_t v, uint32_t n_used,
+                                                   uint32_t words, bool &runs) {
+  const uint64_t nch = g.nchunks, plain = rec_bytes(n_used, g.nchunks, words);
+  runs = false;
+  if (!g.chunk_runs) return plain;
+  const uint64_t R = sl.nruns[v], Wr = sl.run_words[v];
+  if (R > kMaxRuns || 8 * R + 8 + 4 * Wr >= 4 * (nch + 1) + 4ull * words) return plain;
+  runs = true;
+  return plain - 4 * (nch + 1) - 4ull * words + 8 * R + 8 + 4 * Wr;
+}
+
 // ------------------------------------------------------------------ finish
 // Workgroup (b, u) takes encode block b of slot u.  Every workgroup sizes all
 // records of the batch (slot order), so it knows its record's offset and the
@@ -2946,7 +3045,9 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
   // record sizes of the batch (slot order) and this slot's offset among them
   uint64_t pre = 0, tot = 0, ex = 0;
   for (uint32_t v = tid; v < (uint32_t)nslots; v += T) {
-    const uint64_t bytes = v == tid ? rec_bytes(nu0, nch, wd0) : rec_bytes(sl.nused[v], nch, sl.words[v]);
+    bool rv;
+    const uint64_t bytes = v == tid ? slot_rec_bytes(sl, g, v, nu0, wd0, rv)
+                                    : slot_rec_bytes(sl, g, v, sl.nused[v], sl.words[v], rv);
     const uint64_t ba = (bytes + kRecAlign - 1) & ~(kRecAlign - 1);
     tot += ba;
     ex += bytes;
@@ -2982,31 +3083,54 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
   }
   const uint64_t off = base + pre;
   uint8_t *rec = arena + off;
+  bool ru;  // chunk-run layout
+  const uint64_t rbytes = slot_rec_bytes(sl, g, u, n_used, words, ru);
   uint32_t *offs = (uint32_t *)(rec + kHdr + ((2 * n_used + 3) & ~3u));
-  uint32_t *stream = offs + nch + 1;
-  for (uint32_t c = cb + tid; c < ce; c += T) {  // a constant chunk's mark (bit 31) travels with its offset
-    const uint32_t x = c == cb + tid ? cw0 : cw[c];
-    offs[c] = ((uint32_t)bp + (x & 0x7FFFFFFFu)) | (x & 0x80000000u);
-  }
-#pragma unroll
-  for (uint32_t k = 0; k < kU; k++) {
-    const uint32_t i = k * T + tid;
-    if (i < nw) stream[bp + i] = sw[k];
-  }
-  // the rest in steps of kB words per thread: every load of a step is issued
-  // before its stores, so a step waits for memory once, not once per word
-  constexpr uint32_t kB = 32;
-  for (uint32_t i0 = kU * T; i0 < nw; i0 += kB * T) {
-    uint32_t v[kB];
-#pragma unroll
-    for (uint32_t k = 0; k < kB; k++) {
-      const uint32_t i = i0 + k * T + tid;
-      v[k] = i < nw ? src[i] : 0u;
+  const uint32_t R = ru ? sl.nruns[u] : 0u;
+  const uint32_t *rsrc = sl.run_src + (uint64_t)u * kMaxRuns;
+  const uint32_t *rwoff = sl.run_woff + (uint64_t)u * (kMaxRuns + 1);
+  if (ru) {  // the streams of the runs that start in this block, a wavefront per run
+    uint32_t *rstream = offs + 2 * R + 2;
+    uint32_t lo = 0, hi = R;  // the first run starting at or after cb
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (rsrc[mid] < cb)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    const uint32_t wave = tid >> 6, nwv = T >> 6, lane = lane_id();
+    for (uint32_t r = lo + wave; r < R && rsrc[r] < ce; r += nwv) {
+      const uint32_t from = cw[rsrc[r]] & 0x7FFFFFFFu;  // in this block's packed words
+      const uint32_t to = rwoff[r] & 0x7FFFFFFFu, n = (rwoff[r + 1] & 0x7FFFFFFFu) - to;
+      for (uint32_t i = lane; i < n; i += 64) rstream[to + i] = src[from + i];
+    }
+  } else {
+    uint32_t *stream = offs + nch + 1;
+    for (uint32_t c = cb + tid; c < ce; c += T) {  // a constant chunk's mark (bit 31) travels with its offset
+      const uint32_t x = c == cb + tid ? cw0 : cw[c];
+      offs[c] = ((uint32_t)bp + (x & 0x7FFFFFFFu)) | (x & 0x80000000u);
     }
 #pragma unroll
-    for (uint32_t k = 0; k < kB; k++) {
-      const uint32_t i = i0 + k * T + tid;
-      if (i < nw) stream[bp + i] = v[k];
+    for (uint32_t k = 0; k < kU; k++) {
+      const uint32_t i = k * T + tid;
+      if (i < nw) stream[bp + i] = sw[k];
+    }
+    // the rest in steps of kB words per thread: every load of a step is issued
+    // before its stores, so a step waits for memory once, not once per word
+    constexpr uint32_t kB = 32;
+    for (uint32_t i0 = kU * T; i0 < nw; i0 += kB * T) {
+      uint32_t v[kB];
+#pragma unroll
+      for (uint32_t k = 0; k < kB; k++) {
+        const uint32_t i = i0 + k * T + tid;
+        v[k] = i < nw ? src[i] : 0u;
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kB; k++) {
+        const uint32_t i = i0 + k * T + tid;
+        if (i < nw) stream[bp + i] = v[k];
+      }
     }
   }
   if (b != 0) return;
@@ -3018,21 +3142,32 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
     h32[2] = (uint32_t)g.chunk_log2;
     h32[3] = n_used;
     h32[4] = nch;
-    h32[5] = words;
+    h32[5] = ru ? sl.run_words[u] : words;
     h32[6] = nesc;
-    h32[7] = (uint32_t)rec_bytes(n_used, nch, words);
+    h32[7] = (uint32_t)rbytes;
     *(double *)(rec + 32) = step;
     *(uint64_t *)(rec + 40) = sq_lo;
     *(uint64_t *)(rec + 48) = sq_hi;
-    // zero chunks; constant chunks; pointwise-relative codes and their mantissa bits
-    h32[14] = (g.zero_chunks ? 1u : 0u) | (g.const_chunks ? 2u : 0u) | (qp.pw ? 4u : 0u);
+    // zero chunks; constant chunks; pointwise-relative codes and their mantissa bits; chunk runs
+    h32[14] = (g.zero_chunks ? 1u : 0u) | (g.const_chunks ? 2u : 0u) | (qp.pw ? 4u : 0u) | (ru ? 8u : 0u);
     h32[15] = qp.pw ? (uint32_t)qp.pw_bits : 0u;
     nxt.rec_off[slice] = off;
     nxt.rec_len[slice] = h32[7];
     nxt.step[slice] = step;
     nxt.sq[2 * slice] = sq_lo;
     nxt.sq[2 * slice + 1] = sq_hi;
-    offs[nch] = words;
+    if (ru) {
+      offs[0] = R;
+      offs[1 + 2 * R] = rwoff[R];
+    } else {
+      offs[nch] = words;
+    }
+  }
+  if (ru) {  // run ends and the runs' word offsets
+    for (uint32_t r = tid; r < R; r += T) {
+      offs[1 + r] = r + 1 < R ? rsrc[r + 1] : nch;
+      offs[1 + R + r] = rwoff[r];
+    }
   }
   // the symbol table, padded with a zero entry to 4 bytes
   uint16_t *tab = (uint16_t *)(rec + kHdr);
@@ -3425,6 +3560,11 @@ void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, co
     case 2: launch_encode_fmt<2>(st, sl, g, nslots, ctl); break;
     default: launch_encode_fmt<3>(st, sl, g, nslots, ctl); break;
   }
+}
+
+void launch_runs(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
+  const uint32_t cpb = enc_chunks_per_block(g, nslots);
+  CQ_LAUNCH(k_runs, dim3((unsigned)nslots), dim3(1024), 0, st, sl, g, cpb, ctl);
 }
 
 void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,

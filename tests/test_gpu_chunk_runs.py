@@ -1,0 +1,124 @@
+"""GPU parity of chunk-run records (SIM_CHUNK_RUNS): byte-equal records to
+the oracle's after every checked pass, with zero and constant chunks, both
+precisions, the relative and pointwise-relative bounds, several workspace
+batches and encode blocks per slot; the record checks on import; captured
+graphs and the allocation-free entry point.  Each case prints its name before
+it touches the GPU."""
+import struct
+
+import numpy as np
+import pytest
+
+import oracle
+import qcircuits as qc
+from test_gpu_parity import run_both, say
+
+pytestmark = pytest.mark.gpu
+
+cq = pytest.importorskip("paper_1811_05630_amd")
+
+
+def runs_used(sim):
+    return sum(bool(oracle.parse_header(r)["flags"] & 8) for r in sim.records())
+
+
+@pytest.mark.parametrize("cl", [3, 5, 8, 10])
+@pytest.mark.parametrize("extra", [{}, dict(zero_chunks=True, const_chunks=True)])
+def test_grover_chunk_runs_match_the_oracle(cl, extra):
+    n, sl, eb = 12, 10, 1e-6
+    gates = qc.grover(n, 1234, 1)
+    say(f"chunk runs: grover n={n} sl={sl} cl={cl} {extra}")
+    sim, orc = run_both(n, sl, cl, eb, gates, check_every=5, chunk_runs=True, **extra)
+    assert np.array_equal(sim.amplitudes().view(np.float64), orc.amplitudes().view(np.float64))
+    st = sim.stats()
+    assert st["compressed_bytes"] == orc.total_bytes() and st["peak_compressed"] == orc.peak_bytes()
+
+
+def test_chunk_runs_are_used_and_save_bytes():
+    n, sl, cl, eb = 16, 13, 6, 1e-7
+    gates = qc.grover(n, 77, 1)
+    say("chunk runs: bytes saved on a Grover iteration")
+    sim, orc = run_both(n, sl, cl, eb, gates, check_every=9, chunk_runs=True)
+    plain = cq.Sim(n, sl, eb, chunk_log2=cl)
+    plain.apply(gates)
+    assert runs_used(sim) > 0
+    assert sim.stats()["compressed_bytes"] < plain.stats()["compressed_bytes"]
+    assert np.array_equal(sim.amplitudes().view(np.float64), plain.amplitudes().view(np.float64))
+
+
+def test_chunk_runs_other_modes():
+    n, sl, cl = 11, 8, 5
+    gates = qc.grover(n, 300, 1)
+    say("chunk runs: FP32")
+    run_both(n, sl, cl, 1e-6, gates, check_every=7, fp32=True, chunk_runs=True)
+    say("chunk runs: relative bound (FP64 workspace)")
+    run_both(n, sl, cl, 1e-4, gates, rel=True, check_every=7, chunk_runs=True, zero_chunks=True)
+    say("chunk runs: pointwise-relative bound")
+    run_both(n, sl, cl, 0.002, gates, check_every=7, pointwise=True, chunk_runs=True)
+    say("chunk runs: QFT of a basis state")
+    run_both(10, 7, 4, 1e-6, qc.qft(10), init=("basis", 3), check_every=11, chunk_runs=True)
+
+
+def test_chunk_runs_many_blocks_and_batches():
+    # 2048 chunks per slot: several encode blocks per slot, runs crossing
+    # block boundaries; a small workspace (several batches) and a small arena
+    n, sl, cl, eb = 18, 16, 6, 1e-7
+    gates = qc.grover(n, 1000, 1)
+    g = gates[:n + 3] + gates[-4:]
+    say("chunk runs: blocks, batches and arena growth")
+    run_both(n, sl, cl, eb, g, check_every=3, chunk_runs=True, workspace_bytes=9 << 20, arena_bytes=8192)
+
+
+def test_chunk_runs_benchmark_geometry():
+    w = qc.grover_workload(seed=0)
+    n, sl, eb = w.n_qubits, w.slice_log2, w.error_bound
+    g = w.gates[:n] + w.gates[n:n + 3] + w.gates[n + 90:n + 93]
+    say("chunk runs: 24 qubits, 64 slices of 2^18, the H layer, oracle and diffusion gates")
+    sim, orc = run_both(n, sl, 8, eb, g, check_every=len(g), chunk_runs=True)
+    assert runs_used(sim) > 0
+
+
+def test_chunk_run_records_import_and_checks():
+    n, sl, cl, eb = 12, 9, 5, 1e-6
+    gates = qc.grover(n, 5, 1)[:n + 1]
+    say("chunk runs: export / import")
+    src = cq.Sim(n, sl, eb, chunk_log2=cl, chunk_runs=True)
+    src.apply(gates)
+    recs = src.records()
+    runs = [j for j, r in enumerate(recs) if oracle.parse_header(r)["flags"] & 8]
+    assert runs
+    dst = cq.Sim(n, sl, eb, chunk_log2=cl)  # a handle without the mode reads such records too
+    for j, r in enumerate(recs):
+        dst.import_record(j, r)
+    assert np.array_equal(dst.amplitudes().view(np.float64), src.amplitudes().view(np.float64))
+    g = gates[:3]
+    dst.apply(g)
+    src.apply(g)
+    assert np.array_equal(dst.amplitudes().view(np.float64), src.amplitudes().view(np.float64))
+    r = recs[runs[0]]
+    h = oracle.parse_header(r)
+    o = 64 + ((2 * h["n_used"] + 3) & ~3)
+    R = struct.unpack_from("<I", r, o)[0]
+    after = cq.Sim(n, sl, eb, chunk_log2=cl)
+    for bad_at, val in [(o, 0), (o, h["n_chunks"] + 1), (o + 4 * R, h["n_chunks"] - 1), (56, 0)]:
+        bad = bytearray(r)
+        struct.pack_into("<I", bad, bad_at, val)
+        with pytest.raises(cq.SimError) as e:
+            after.import_record(runs[0], bytes(bad))
+        assert e.value.rc == -4, (bad_at, val)
+
+
+def test_chunk_runs_graph_and_noalloc():
+    n, sl, cl, eb = 12, 9, 5, 1e-6
+    gates = qc.grover(n, 99, 1)
+    say("chunk runs: captured graph")
+    a = cq.Sim(n, sl, eb, chunk_log2=cl, chunk_runs=True)
+    b = cq.Sim(n, sl, eb, chunk_log2=cl, chunk_runs=True)
+    prog = cq.Graph(a, gates)
+    prog.launch()
+    b.apply(gates)
+    assert a.records() == b.records()
+    say("chunk runs: allocation-free entry point")
+    c = cq.Sim(n, sl, eb, chunk_log2=cl, chunk_runs=True, arena_bytes=1 << 20)
+    assert c.apply_noalloc(gates) == (0, len(gates))
+    assert c.records() == b.records()

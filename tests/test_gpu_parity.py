@@ -38,13 +38,14 @@ def assert_same_records(sim, orc, label, which=None):
 
 
 def run_both(n, sl, cl, eb, gates, rel=False, init=None, check_every=1, workspace_bytes=0, arena_bytes=0,
-             use_torch=None, fp32=False, zero_chunks=False, const_chunks=False):
-    mode = ((oracle.REL if rel else oracle.ABS) | (oracle.FP32 if fp32 else 0) |
-            (oracle.ZERO_CHUNKS if zero_chunks else 0) | (oracle.CONST_CHUNKS if const_chunks else 0))
+             use_torch=None, fp32=False, zero_chunks=False, const_chunks=False, chunk_runs=False, pointwise=False):
+    mode = ((oracle.REL if rel else oracle.PWREL if pointwise else oracle.ABS) | (oracle.FP32 if fp32 else 0) |
+            (oracle.ZERO_CHUNKS if zero_chunks else 0) | (oracle.CONST_CHUNKS if const_chunks else 0) |
+            (oracle.CHUNK_RUNS if chunk_runs else 0))
     orc = oracle.OracleSim(n, sl, cl, eb, mode)
     sim = cq.Sim(n, sl, eb, relative=rel, chunk_log2=cl, workspace_bytes=workspace_bytes,
                  arena_bytes=arena_bytes, use_torch=use_torch, fp32=fp32, zero_chunks=zero_chunks,
-                 const_chunks=const_chunks)
+                 const_chunks=const_chunks, chunk_runs=chunk_runs, pointwise=pointwise)
     if init is not None:
         kind, arg = init
         if kind == "basis":
@@ -144,7 +145,8 @@ def test_workspace_batches_and_arena_growth():
     say("batches+growth", n, sl, cl, eb)
     nch = (2 << sl) >> cl
     stage_words = ((1 << cl) * 68 + 31) // 32 + 1
-    per_slot = 2 * (1 << sl) * 18 + 1024 * 6 + 4 * 32 * (1024 + 8) + 12 * nch + 4 * nch * stage_words + 4 * 1024 + 128
+    per_slot = (2 * (1 << sl) * 18 + 1024 * 6 + 4 * 32 * (1024 + 8) + 12 * nch + 4 * nch * stage_words + 4 * 1024 +
+                8 * 4096 + 140)  # ... encode block totals, chunk-run tables
     gates = qc.random_layered(n, 2, seed=5) + [qc.U([13, 12, 3], np.eye(8)[::-1]), qc.H(13)]
     sim, orc = run_both(n, sl, cl, eb, gates, check_every=7, workspace_bytes=8 * per_slot, arena_bytes=8192)
     st = sim.stats()
