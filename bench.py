@@ -86,9 +86,11 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="grover24: also report the chunk-length autotuner's table (sim_tune_chunk) on the circuit")
     ap.add_argument("--zero-chunks", action="store_true",
-                    help="grover24: zero-chunk records (all-zero chunks stored with no words)")
+                    help="grover24, grover34: zero-chunk records (all-zero chunks stored with no words)")
     ap.add_argument("--const-chunks", action="store_true",
-                    help="grover24: constant-chunk records (a chunk of equal values keeps its first only)")
+                    help="grover24, grover34: constant-chunk records (a chunk of equal values keeps its first only)")
+    ap.add_argument("--chunk-runs", action="store_true",
+                    help="grover24, grover34: chunk-run records (runs of chunks with identical streams stored once)")
     ap.add_argument("--workload", choices=("grover34", "grover24", "qft30", "qft12", "serve"), default="grover34",
                     help="grover34 (default, the headline line: 34-qubit Grover search, FP64 and FP32); "
                          "grover24: 24-qubit Grover search; qft30: 30-qubit QFT of a product state in fused "
@@ -269,7 +271,7 @@ def run_grover24(args):
     # stays above 6), so that no reallocation falls inside a timed batch
     sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, arena_bytes=(16 << n) // 4,
                  fp32=args.fp32, zero_chunks=args.zero_chunks,
-                 const_chunks=args.const_chunks)
+                 const_chunks=args.const_chunks, chunk_runs=args.chunk_runs)
     # initial H layer (untimed), then warm-up passes
     # the circuit is marshalled once, outside every timed region
     gates = cq.Circuit(w.gates)
@@ -307,10 +309,11 @@ def run_grover24(args):
                           "amplitudes, absolute bound 1e-7, plain mode (one pass per gate)" +
                           (", FP32 mode" if args.fp32 else "") +
                           (", zero-chunk records" if args.zero_chunks else "") +
-                          (", constant-chunk records" if args.const_chunks else ""),
+                          (", constant-chunk records" if args.const_chunks else "") +
+                          (", chunk-run records" if args.chunk_runs else ""),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
               "error_bound": w.error_bound, "passes_timed": K, "first_timed_gate": n + Wm, "fp32": args.fp32,
-              "zero_chunks": args.zero_chunks, "const_chunks": args.const_chunks}
+              "zero_chunks": args.zero_chunks, "const_chunks": args.const_chunks, "chunk_runs": args.chunk_runs}
     line = report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config,
                   plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16)
     if args.tune:  # the H layer and 300 Grover gates on fresh handles, chunks of 2^5 .. 2^10
@@ -461,7 +464,8 @@ def run_grover34_leg(args, w, fp32, K, Wm):
     # about 6.6, in its first diffusion passes), so that no arena grows, and
     # no pass is run again, inside the timed region
     sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, workspace_bytes=96 << 30,
-                 arena_bytes=(16 << n) // 4, fp32=fp32)
+                 arena_bytes=(16 << n) // 4, fp32=fp32, zero_chunks=args.zero_chunks,
+                 const_chunks=args.const_chunks, chunk_runs=args.chunk_runs)
     g = cq.Circuit(w.gates)  # marshalled once, outside the timed region
     assert len(g) >= start + K + args.latency_passes
 
@@ -525,7 +529,10 @@ def run_grover34(args):
                           "amplitudes (raw FP64 state 256 GiB, held compressed), absolute bound 1e-8, plain mode, "
                           "FP64; passes %d..%d timed (the first oracle, then H on qubits 0..%d of its diffusion; "
                           "every slice holds nonzero amplitudes), after the initial H layer"
-                          % (args.seed, start, start + K - 1, K - 2),
+                          % (args.seed, start, start + K - 1, K - 2) +
+                          (", zero-chunk records" if args.zero_chunks else "") +
+                          (", constant-chunk records" if args.const_chunks else "") +
+                          (", chunk-run records" if args.chunk_runs else ""),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
               "error_bound": w.error_bound, "passes_timed": K, "first_timed_pass": start,
               "workspace_slots": r64["st2"]["workspace_slots"], "fp32": False}
