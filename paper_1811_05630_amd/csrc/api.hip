@@ -240,6 +240,9 @@ int alloc_slots(sim_t *s) {
   sl.stage_words = stage_words_for(s->geo.chunk_log2);
   if ((rc = s->dalloc((void **)&sl.stage, 4ull * W * s->geo.nchunks * sl.stage_words))) return rc;
   if ((rc = s->dalloc((void **)&sl.csum, 8ull * W * s->geo.nchunks))) return rc;
+  if ((rc = s->dalloc((void **)&sl.run_start, 1ull * W * s->geo.nchunks))) return rc;
+  if ((rc = s->dalloc((void **)&sl.run_tile, 8ull * W * s->geo.run_tiles))) return rc;
+  if ((rc = s->dalloc((void **)&sl.blk_run, 4ull * W * kMaxEncBlocks))) return rc;
   if ((rc = s->dalloc((void **)&sl.run_src, 4ull * W * kMaxRuns))) return rc;
   if ((rc = s->dalloc((void **)&sl.run_woff, 4ull * W * (kMaxRuns + 1)))) return rc;
   if ((rc = s->dalloc((void **)&sl.nruns, 4 * W))) return rc;
@@ -278,6 +281,9 @@ uint64_t carve_slots(const Geo &g, uint64_t W, uint8_t *base, Slots *sl) {
   o.stage_words = stage_words_for(g.chunk_log2);
   take(&o.stage, 4ull * W * g.nchunks * o.stage_words);
   take(&o.csum, 8ull * W * g.nchunks);
+  take(&o.run_start, 1ull * W * g.nchunks);
+  take(&o.run_tile, 8ull * W * g.run_tiles);
+  take(&o.blk_run, 4ull * W * kMaxEncBlocks);
   take(&o.run_src, 4ull * W * kMaxRuns);
   take(&o.run_woff, 4ull * W * (kMaxRuns + 1));
   take(&o.nruns, 4 * W);
@@ -287,7 +293,8 @@ uint64_t carve_slots(const Geo &g, uint64_t W, uint8_t *base, Slots *sl) {
 
 uint64_t per_slot_bytes(const Geo &g) {
   return 2 * g.L * (8 + 2 + 8) + (uint64_t)kNSym * (4 + 2) + 4ull * kGqParts * (kNSym + 8) + 12ull * g.nchunks +
-         4ull * g.nchunks * stage_words_for(g.chunk_log2) + 4ull * kMaxEncBlocks + 8ull * kMaxRuns + 140;
+         4ull * g.nchunks * stage_words_for(g.chunk_log2) + 4ull * kMaxEncBlocks + 8ull * kMaxRuns + 140 +
+         g.nchunks + 8ull * g.run_tiles + 4ull * kMaxEncBlocks;
 }
 
 // Slot order of every slice for gates whose slice-index targets form `gm`:
@@ -878,6 +885,7 @@ int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   s->geo.fmt_in = s->geo.zero_chunks | (s->geo.const_chunks << 1);
   s->geo.pw_bits = pwb;
   s->geo.chunk_runs = (cfg->mode & SIM_CHUNK_RUNS) ? 1u : 0u;
+  s->geo.run_tiles = (s->geo.nchunks + kRunTile - 1) / kRunTile;
   s->eb = cfg->error_bound;
   s->mode = cfg->mode;
   s->fp32 = (cfg->mode & SIM_FP32) != 0;

@@ -113,6 +113,7 @@ struct Geo {
   int pw_bits;            // -1, or pointwise-relative records: a code is a value's bit pattern without
                           // the sign, rounded to pw_bits mantissa bits and shifted right by 52 - pw_bits
   uint32_t chunk_runs;    // SIM_CHUNK_RUNS: runs of chunks with identical streams store the stream once
+  uint32_t run_tiles;     // tiles of kRunTile chunks per slice (the runs kernels' grid)
 };
 
 // Per-slot scratch of one batch of decompressed slices.
@@ -144,6 +145,9 @@ struct Slots {
   double *csum;           // [W][nchunks] pointwise-relative mode: each chunk's sum of squared stored
                           // values as a pairwise tree in index order (the codebook sums the slice)
   // chunk runs (SIM_CHUNK_RUNS), written by the runs kernel after encode
+  uint8_t *run_start;     // [W][nchunks] 1 where a chunk starts a run
+  uint32_t *run_tile;     // [W][run_tiles][2] runs starting in each tile of kRunTile chunks, their words
+  uint32_t *blk_run;      // [W][kMaxEncBlocks] index of the first run starting in each encode block
   uint32_t *run_src;      // [W][kMaxRuns] first chunk of each run
   uint32_t *run_woff;     // [W][kMaxRuns + 1] word offset of each run's stream in the record | mark
   uint32_t *nruns;        // [W] number of runs (may exceed kMaxRuns: then the plain layout)
@@ -234,6 +238,7 @@ inline uint64_t gq_tile(uint64_t L) { return L < 1024 ? L : 1024; }
 constexpr uint32_t kGqWgs = 16;
 constexpr uint32_t kMaxEncBlocks = 1024;  // encode (and finish) workgroups per slot, at most
 constexpr uint32_t kMaxRuns = 4096;       // chunk runs of a record, at most
+constexpr uint32_t kRunTile = 1024;       // chunks per workgroup of the runs kernels
 constexpr uint32_t kGqParts = 2 * kGqWgs;
 
 // words of one chunk's staging slot

@@ -2914,64 +2914,111 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
 }
 
 // ------------------------------------------------------------------ chunk runs
-// One workgroup per slot (SIM_CHUNK_RUNS): chunk c starts a run unless its
-// staged stream -- word count, constant mark and words -- equals chunk
-// c - 1's.  Tiles of one chunk per thread; block scans number the runs and
-// sum their words.  The first kMaxRuns runs get their first chunk and the
-// word offset of their stream (with the mark); nruns and run_words hold the
-// totals, from which finish chooses the record layout.
-__global__ void __launch_bounds__(1024) k_runs(Slots sl, Geo g, uint32_t cpb, const Ctl *ctl) {
+// SIM_CHUNK_RUNS: chunk c starts a run unless its staged stream -- word
+// count, constant mark and words -- equals chunk c - 1's.  Two launches over
+// tiles of kRunTile chunks (grid: tiles x slots): the first marks the run
+// starts and counts each tile's runs and their words; the second adds the
+// counts of the tiles before its own and numbers its runs with block scans.
+// The first kMaxRuns runs get their first chunk and the word offset of their
+// stream (with the mark); nruns and run_words hold the slot's totals, from
+// which finish chooses the record layout.
+struct ChunkSpan {  // a chunk's staged words (offset from the slot's staging region), count and mark
+  uint64_t w0;
+  uint32_t n, mark;
+};
+// chunk c's words: staged at block b's region (b * cpb chunks in) plus its
+// packed offset; they end at the next chunk's offset or the block's total
+__device__ __forceinline__ ChunkSpan chunk_span(const uint32_t *cw, const uint32_t *bw, uint32_t nch, uint32_t cpb,
+                                                uint32_t W, uint32_t c) {
+  const uint32_t b = c / cpb, x = cw[c], off = x & 0x7FFFFFFFu;
+  const uint32_t end = (c + 1 < nch && (c + 1) / cpb == b) ? (cw[c + 1] & 0x7FFFFFFFu) : bw[b];
+  return ChunkSpan{(uint64_t)b * cpb * W + off, end - off, x & 0x80000000u};
+}
+
+__global__ void __launch_bounds__(kRunTile) k_runs_mark(Slots sl, Geo g, uint32_t cpb, const Ctl *ctl) {
   if (ctl->flags) return;
   __shared__ uint32_t scan[17];
-  const uint32_t u = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
-  const uint32_t nch = g.nchunks, W = sl.stage_words;
+  const uint32_t t = blockIdx.x, u = blockIdx.y, tid = threadIdx.x;
+  const uint32_t nch = g.nchunks, W = sl.stage_words, c = t * kRunTile + tid;
   const uint32_t *cw = sl.chunk_words + (uint64_t)u * nch;
   const uint32_t *bw = sl.blk_words + (uint64_t)u * kMaxEncBlocks;
   const uint32_t *stage = sl.stage + (uint64_t)u * nch * W;
-  uint32_t *src = sl.run_src + (uint64_t)u * kMaxRuns;
-  uint32_t *woff = sl.run_woff + (uint64_t)u * (kMaxRuns + 1);
-  // chunk c's words: staged at block b's region (b * cpb chunks in) plus its
-  // packed offset; they end at the next chunk's offset or the block's total
-  auto span = [&](uint32_t c, uint64_t &w0, uint32_t &n, uint32_t &mark) {
-    const uint32_t b = c / cpb, x = cw[c], off = x & 0x7FFFFFFFu;
-    const uint32_t end = (c + 1 < nch && (c + 1) / cpb == b) ? (cw[c + 1] & 0x7FFFFFFFu) : bw[b];
-    w0 = (uint64_t)b * cpb * W + off;
-    n = end - off;
-    mark = x & 0x80000000u;
-  };
-  uint32_t runs = 0, words = 0;  // over the tiles so far (uniform)
-  for (uint32_t t0 = 0; t0 < nch; t0 += T) {
-    const uint32_t c = t0 + tid;
-    uint32_t start = 0, nw = 0, mark = 0;
-    if (c < nch) {
-      uint64_t w0;
-      span(c, w0, nw, mark);
-      start = 1;
-      if (c > 0) {
-        uint64_t p0;
-        uint32_t pn, pm;
-        span(c - 1, p0, pn, pm);
-        if (pn == nw && pm == mark) {
-          uint32_t i = 0;
-          while (i < nw && stage[w0 + i] == stage[p0 + i]) i++;
-          start = i == nw ? 0u : 1u;
-        }
+  uint32_t start = 0, nw = 0;
+  if (c < nch) {
+    const ChunkSpan a = chunk_span(cw, bw, nch, cpb, W, c);
+    nw = a.n;
+    start = 1;
+    if (c > 0) {
+      const ChunkSpan p = chunk_span(cw, bw, nch, cpb, W, c - 1);
+      if (p.n == a.n && p.mark == a.mark) {
+        uint32_t i = 0;
+        while (i < a.n && stage[a.w0 + i] == stage[p.w0 + i]) i++;
+        start = i == a.n ? 0u : 1u;
       }
     }
-    uint32_t tile_runs, tile_words;
-    const uint32_t r = runs + block_excl_scan(start, scan, &tile_runs);
-    const uint32_t w = words + block_excl_scan(start ? nw : 0u, scan, &tile_words);
-    if (start && r < kMaxRuns) {
-      src[r] = c;
-      woff[r] = w | mark;
-    }
-    runs += tile_runs;
-    words += tile_words;
+    sl.run_start[(uint64_t)u * nch + c] = (uint8_t)start;
   }
+  uint32_t runs, words;
+  block_excl_scan(start, scan, &runs);
+  block_excl_scan(start ? nw : 0u, scan, &words);
   if (tid == 0) {
-    sl.nruns[u] = runs;
-    sl.run_words[u] = words;
-    if (runs <= kMaxRuns) woff[runs] = words;
+    const uint64_t k = (uint64_t)u * g.run_tiles + t;
+    sl.run_tile[2 * k] = runs;
+    sl.run_tile[2 * k + 1] = words;
+  }
+}
+
+__global__ void __launch_bounds__(kRunTile) k_runs_number(Slots sl, Geo g, uint32_t cpb, const Ctl *ctl) {
+  if (ctl->flags) return;
+  __shared__ uint32_t scan[17];
+  const uint32_t t = blockIdx.x, u = blockIdx.y, tid = threadIdx.x;
+  const uint32_t nch = g.nchunks, c = t * kRunTile + tid;
+  const uint32_t *tiles = sl.run_tile + 2ull * u * g.run_tiles;
+  // runs and words of the tiles before this one (and, for the last tile, of all)
+  const uint32_t upto = t + 1 == g.run_tiles ? g.run_tiles : t;
+  uint32_t r0 = 0, w0 = 0, rall = 0, wall = 0;
+  for (uint32_t i = tid; i < upto; i += kRunTile) {
+    if (i < t) {
+      r0 += tiles[2 * i];
+      w0 += tiles[2 * i + 1];
+    }
+    rall += tiles[2 * i];
+    wall += tiles[2 * i + 1];
+  }
+  uint32_t x;
+  block_excl_scan(r0, scan, &x);
+  r0 = x;
+  block_excl_scan(w0, scan, &x);
+  w0 = x;
+  block_excl_scan(rall, scan, &x);
+  rall = x;
+  block_excl_scan(wall, scan, &x);
+  wall = x;
+  uint32_t *src = sl.run_src + (uint64_t)u * kMaxRuns;
+  uint32_t *woff = sl.run_woff + (uint64_t)u * (kMaxRuns + 1);
+  // every tile, also past kMaxRuns runs: a slot of exactly kMaxRuns runs
+  // still takes the run layout, and finish reads every block's first run
+  uint32_t start = 0, nw = 0, mark = 0;
+  if (c < nch) {
+    start = sl.run_start[(uint64_t)u * nch + c];
+    const ChunkSpan a = chunk_span(sl.chunk_words + (uint64_t)u * nch, sl.blk_words + (uint64_t)u * kMaxEncBlocks,
+                                   nch, cpb, sl.stage_words, c);
+    nw = a.n;
+    mark = a.mark;
+  }
+  uint32_t tr, tw;
+  const uint32_t r = r0 + block_excl_scan(start, scan, &tr);
+  const uint32_t w = w0 + block_excl_scan(start ? nw : 0u, scan, &tw);
+  if (start && r < kMaxRuns) {
+    src[r] = c;
+    woff[r] = w | mark;
+  }
+  // the first run of each encode block: the runs starting before its first chunk
+  if (c < nch && c % cpb == 0) sl.blk_run[(uint64_t)u * kMaxEncBlocks + c / cpb] = r;
+  if (t + 1 == g.run_tiles && tid == 0) {
+    sl.nruns[u] = rall;
+    sl.run_words[u] = wall;
+    if (rall <= kMaxRuns) woff[rall] = wall;
   }
 }
 
@@ -3089,21 +3136,21 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
   const uint32_t R = ru ? sl.nruns[u] : 0u;
   const uint32_t *rsrc = sl.run_src + (uint64_t)u * kMaxRuns;
   const uint32_t *rwoff = sl.run_woff + (uint64_t)u * (kMaxRuns + 1);
-  if (ru) {  // the streams of the runs that start in this block, a wavefront per run
+  if (ru) {  // the streams of the runs that start in this block
     uint32_t *rstream = offs + 2 * R + 2;
-    uint32_t lo = 0, hi = R;  // the first run starting at or after cb
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (rsrc[mid] < cb)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    const uint32_t wave = tid >> 6, nwv = T >> 6, lane = lane_id();
-    for (uint32_t r = lo + wave; r < R && rsrc[r] < ce; r += nwv) {
+    const uint32_t lo = sl.blk_run[(uint64_t)u * kMaxEncBlocks + b];  // the first run starting at or after cb
+    for (uint32_t r = lo + tid; r < R && rsrc[r] < ce; r += T) {  // a thread per run
       const uint32_t from = cw[rsrc[r]] & 0x7FFFFFFFu;  // in this block's packed words
       const uint32_t to = rwoff[r] & 0x7FFFFFFFu, n = (rwoff[r + 1] & 0x7FFFFFFFu) - to;
-      for (uint32_t i = lane; i < n; i += 64) rstream[to + i] = src[from + i];
+      uint32_t i = 0;
+      for (; i + 8 <= n; i += 8) {  // eight loads in flight, then their stores
+        uint32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) v[k] = src[from + i + k];
+#pragma unroll
+        for (int k = 0; k < 8; k++) rstream[to + i + k] = v[k];
+      }
+      for (; i < n; i++) rstream[to + i] = src[from + i];
     }
   } else {
     uint32_t *stream = offs + nch + 1;
@@ -3564,7 +3611,9 @@ void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, co
 
 void launch_runs(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {
   const uint32_t cpb = enc_chunks_per_block(g, nslots);
-  CQ_LAUNCH(k_runs, dim3((unsigned)nslots), dim3(1024), 0, st, sl, g, cpb, ctl);
+  const dim3 grid(g.run_tiles, (unsigned)nslots);
+  CQ_LAUNCH(k_runs_mark, grid, dim3(kRunTile), 0, st, sl, g, cpb, ctl);
+  CQ_LAUNCH(k_runs_number, grid, dim3(kRunTile), 0, st, sl, g, cpb, ctl);
 }
 
 void launch_finish(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t *slot_slice, int nslots,

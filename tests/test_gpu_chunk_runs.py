@@ -122,3 +122,18 @@ def test_chunk_runs_graph_and_noalloc():
     c = cq.Sim(n, sl, eb, chunk_log2=cl, chunk_runs=True, arena_bytes=1 << 20)
     assert c.apply_noalloc(gates) == (0, len(gates))
     assert c.records() == b.records()
+
+
+def test_exactly_max_runs_with_quiet_tiles():
+    """A record of exactly 4096 runs whose last run starts halfway through
+    the slice (16 qubits, slices of 2^15, chunks of 4: after the diffusion's
+    H on qubit 3, slice 1 has 4096 runs, the last from chunk 8189 of 16384):
+    the tiles after it start no run, and the record still takes the run
+    layout, so every encode block must find its first run."""
+    n, sl, cl, eb = 16, 15, 2, 1e-7
+    gates = qc.grover(n, 12345, 1)[:21]
+    say("chunk runs: exactly 4096 runs")
+    sim, orc = run_both(n, sl, cl, eb, gates, check_every=1, chunk_runs=True)
+    recs = orc.records()
+    assert any(oracle.parse_header(r)["flags"] & 8 and len(oracle.chunk_runs(r)[0]) == oracle.MAX_RUNS
+               for r in recs)

@@ -146,7 +146,7 @@ def test_workspace_batches_and_arena_growth():
     nch = (2 << sl) >> cl
     stage_words = ((1 << cl) * 68 + 31) // 32 + 1
     per_slot = (2 * (1 << sl) * 18 + 1024 * 6 + 4 * 32 * (1024 + 8) + 12 * nch + 4 * nch * stage_words + 4 * 1024 +
-                8 * 4096 + 140)  # ... encode block totals, chunk-run tables
+                8 * 4096 + 140 + nch + 8 * ((nch + 1023) // 1024) + 4 * 1024)  # ... chunk-run tables
     gates = qc.random_layered(n, 2, seed=5) + [qc.U([13, 12, 3], np.eye(8)[::-1]), qc.H(13)]
     sim, orc = run_both(n, sl, cl, eb, gates, check_every=7, workspace_bytes=8 * per_slot, arena_bytes=8192)
     st = sim.stats()
