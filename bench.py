@@ -10,7 +10,8 @@ are not available).  The initial H layer runs untimed; the timed passes start
 at the first Grover iteration's oracle and run into its diffusion layer, where
 every slice holds nonzero amplitudes.  The same window is then run in FP32
 mode, and both read-outs are compared on sampled amplitudes (with the exact
-state beside them).
+state beside them), and once more with zero-chunk, constant-chunk and
+chunk-run records (the same amplitudes, smaller records).
 
 Prints one JSON line: throughput in state amplitudes per second (amplitude-
 passes: 2^34 per step), the compression ratio, per-pass latency percentiles,
@@ -83,6 +84,8 @@ def parse():
                     help="grover24: FP32 mode (FP32 working values and gate arithmetic); grover34 runs both "
                          "precisions")
     ap.add_argument("--no-fp32", action="store_true", help="grover34: skip the FP32 leg")
+    ap.add_argument("--no-codec-leg", action="store_true",
+                    help="grover34: skip the leg with zero-chunk, constant-chunk and chunk-run records")
     ap.add_argument("--tune", action="store_true",
                     help="grover24: also report the chunk-length autotuner's table (sim_tune_chunk) on the circuit")
     ap.add_argument("--zero-chunks", action="store_true",
@@ -449,7 +452,7 @@ def grover34_sample_ranges(n, sl, marked, seed=11):
     return [(b, 4096) for b in starts]
 
 
-def run_grover34_leg(args, w, fp32, K, Wm):
+def run_grover34_leg(args, w, fp32, K, Wm, codec=None):
     """One precision of the headline: the prelude untimed, Wm warm-up passes
     (the end of the initial H layer), K timed passes from the first oracle on;
     then the same window again from |0...0> with per-kernel event timing, and
@@ -463,9 +466,10 @@ def run_grover34_leg(args, w, fp32, K, Wm):
     # record arenas sized up front for a ratio of 4 (the window's smallest is
     # about 6.6, in its first diffusion passes), so that no arena grows, and
     # no pass is run again, inside the timed region
+    if codec is None:
+        codec = dict(zero_chunks=args.zero_chunks, const_chunks=args.const_chunks, chunk_runs=args.chunk_runs)
     sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, workspace_bytes=96 << 30,
-                 arena_bytes=(16 << n) // 4, fp32=fp32, zero_chunks=args.zero_chunks,
-                 const_chunks=args.const_chunks, chunk_runs=args.chunk_runs)
+                 arena_bytes=(16 << n) // 4, fp32=fp32, **codec)
     g = cq.Circuit(w.gates)  # marshalled once, outside the timed region
     assert len(g) >= start + K + args.latency_passes
 
@@ -506,7 +510,8 @@ def run_grover34_leg(args, w, fp32, K, Wm):
 def run_grover34(args):
     """The headline: 34-qubit Grover search (1024 slices of 2^24, absolute
     bound 1e-8), FP64, timed from the first oracle into its diffusion layer;
-    the FP32 leg beside it."""
+    the FP32 leg and a leg with the record variants (zero chunks, constant
+    chunks, chunk runs) beside it."""
     import numpy as np
     import qcircuits as qc
 
@@ -559,6 +564,18 @@ def run_grover34(args):
                                                 "p99": float(np.percentile(r32["lat"], 99))}
                         if r32["lat"] else None}
     line["accuracy"] = acc
+    if not args.no_codec_leg and not (args.chunk_runs or args.zero_chunks or args.const_chunks):
+        # the same window with the record variants past the Huffman stage
+        # (zero chunks, constant chunks, chunk runs): the same codes and
+        # amplitudes, smaller records
+        print("[bench] grover34 chunk-run leg", file=sys.stderr, flush=True)
+        rr = run_grover34_leg(args, w, False, K, Wm,
+                              codec=dict(zero_chunks=True, const_chunks=True, chunk_runs=True))
+        line["chunk_runs"] = {"value": K * N / rr["dt"], "unit": "amps/s", "ms_per_step": rr["dt"] / K * 1e3,
+                              "ratio": rr["st3"]["raw_bytes"] / rr["st3"]["compressed_bytes"],
+                              "min_ratio": rr["st3"]["min_ratio"],
+                              "records": "zero-chunk, constant-chunk and chunk-run records",
+                              "same_readout_as_plain": bool(np.array_equal(rr["read"], r64["read"]))}
     if not args.no_cpu:
         print("[bench] grover34 CPU oracle sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_grover34(w, args.cpu_seconds, args.chunk_log2, K)
