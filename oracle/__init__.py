@@ -25,6 +25,7 @@ CONST_CHUNKS = 16  # mode bit: a chunk whose values all equal its head keeps onl
 PWREL = 32  # mode bit: pointwise-relative bound (|v - v'| <= eb |v| for every value)
 CHUNK_RUNS = 64  # mode bit: runs of chunks with identical streams store the stream once (flags bit 3)
 MAX_RUNS = 4096  # chunk-run records hold at most this many runs
+OPT = 128  # mode bit: passes skip slice groups where a gate's slice-index controls fail, relabel index SWAPs
 
 R = 512
 NSYM = 1024

@@ -122,6 +122,16 @@ static void cmac(double ur, double ui, double ar, double ai, double *cr, double 
 #define ORC_CHUNK_RUNS 64u
 #define ORC_MAX_RUNS 4096u
 
+/* Optimised passes (mode bit ORC_OPT; an extension, off for Algorithm 1 as
+ * written, plain mode only): a pass whose gate is controlled on slice-index
+ * qubits leaves the slice groups whose index bits fail those controls as
+ * they are (their records are not decoded, renormalised or re-encoded), and
+ * a SWAP of two slice-index qubits without controls relabels the slices
+ * (record j becomes record sigma(j), sigma exchanging the two index bits)
+ * without touching a value.  The norm of the next pass is that of all stored
+ * records, as always. */
+#define ORC_OPT 128u
+
 /* b for a pointwise-relative bound eb, or -1 when eb is out of range. */
 static int pw_bits(double eb) {
   if (!(eb > 0.0) || !(eb < 0.5)) return -1;
@@ -1128,6 +1138,7 @@ int orc_sim_init(orc_sim *s, int kind, uint64_t x, const double *f) {
   }
   if (rc_all == ORC_OK) {
     for (uint64_t j = 0; j < s->nslices; j++) {
+      if (!nrec[j]) continue; /* a group left as it was (ORC_OPT) */
       free(s->rec[j]);
       s->rec[j] = nrec[j];
       s->rec_len[j] = nlen[j];
@@ -1217,14 +1228,66 @@ static int process_group(const orc_sim *s, const orc_gate *g, double scale, int 
   return rc;
 }
 
+/* ORC_OPT: whether g is a SWAP of two slice-index qubits without controls
+ * (a two-target dense gate whose matrix is exactly the exchange); *a, *b get
+ * the two index bits. */
+static int slice_swap(const orc_sim *s, const orc_gate *g, int *a, int *b) {
+  if (g->kind != ORC_DENSE || g->n_targets != 2 || g->ctrl_mask) return 0;
+  if ((int)g->targets[0] < s->slice_log2 || (int)g->targets[1] < s->slice_log2) return 0;
+  for (int r = 0; r < 4; r++)
+    for (int c = 0; c < 4; c++) {
+      int one = (r == 0 && c == 0) || (r == 1 && c == 2) || (r == 2 && c == 1) || (r == 3 && c == 3);
+      if (g->matrix[2 * (4 * r + c)] != (one ? 1.0 : 0.0) || g->matrix[2 * (4 * r + c) + 1] != 0.0) return 0;
+    }
+  *a = (int)g->targets[0] - s->slice_log2;
+  *b = (int)g->targets[1] - s->slice_log2;
+  return 1;
+}
+
 /* Apply gates one by one (one pass each).  A pass that fails leaves the state
  * as it was before that pass; *applied counts the completed passes. */
 int orc_sim_apply(orc_sim *s, const orc_gate *gates, uint64_t ngates, uint64_t *applied) {
   *applied = 0;
+  const int opt = (s->mode & ORC_OPT) != 0;
   for (uint64_t gi = 0; gi < ngates; gi++) {
     const orc_gate *g = &gates[gi];
     int rc = check_gate(s, g);
     if (rc) return rc;
+    int sa, sb;
+    if (opt && slice_swap(s, g, &sa, &sb)) { /* relabel: record j moves to sigma(j) */
+      uint8_t **nrec = (uint8_t **)malloc(sizeof(uint8_t *) * s->nslices);
+      uint64_t *nlen = (uint64_t *)malloc(sizeof(uint64_t) * s->nslices);
+      double *nstep = (double *)malloc(sizeof(double) * s->nslices);
+      uint64_t *nlo = (uint64_t *)malloc(sizeof(uint64_t) * s->nslices);
+      uint64_t *nhi = (uint64_t *)malloc(sizeof(uint64_t) * s->nslices);
+      if (!nrec || !nlen || !nstep || !nlo || !nhi) {
+        free(nrec); free(nlen); free(nstep); free(nlo); free(nhi);
+        return ORC_ENOMEM;
+      }
+      for (uint64_t j = 0; j < s->nslices; j++) {
+        uint64_t ba = (j >> sa) & 1, bb = (j >> sb) & 1;
+        uint64_t t = ba == bb ? j : j ^ (((uint64_t)1 << sa) | ((uint64_t)1 << sb));
+        nrec[t] = s->rec[j];
+        nlen[t] = s->rec_len[j];
+        nstep[t] = s->step[j];
+        nlo[t] = s->sq_lo[j];
+        nhi[t] = s->sq_hi[j];
+      }
+      memcpy(s->rec, nrec, sizeof(uint8_t *) * s->nslices);
+      memcpy(s->rec_len, nlen, sizeof(uint64_t) * s->nslices);
+      memcpy(s->step, nstep, sizeof(double) * s->nslices);
+      memcpy(s->sq_lo, nlo, sizeof(uint64_t) * s->nslices);
+      memcpy(s->sq_hi, nhi, sizeof(uint64_t) * s->nslices);
+      free(nrec); free(nlen); free(nstep); free(nlo); free(nhi);
+      s->passes++;
+      note_total(s);
+      *applied = gi + 1;
+      continue;
+    }
+    /* controls on slice-index qubits: the slice bits a group must have */
+    const uint64_t lo_bits = ((uint64_t)1 << s->slice_log2) - 1;
+    const uint64_t smask = opt ? (g->ctrl_mask & ~lo_bits) >> s->slice_log2 : 0;
+    const uint64_t svals = opt ? (g->ctrl_vals & ~lo_bits) >> s->slice_log2 : 0;
     double scale = orc_sim_scale(s);
     uint64_t gm = group_mask(s, g);
     uint8_t **nrec = (uint8_t **)calloc(s->nslices, sizeof(uint8_t *));
@@ -1234,6 +1297,7 @@ int orc_sim_apply(orc_sim *s, const orc_gate *gates, uint64_t ngates, uint64_t *
 #pragma omp parallel for schedule(dynamic)
     for (int64_t j0 = 0; j0 < (int64_t)s->nslices; j0++) {
       if ((uint64_t)j0 & gm) continue; /* not a group leader */
+      if (((uint64_t)j0 & smask) != svals) continue; /* ORC_OPT: the gate is the identity here */
       uint64_t mem[32];
       uint8_t *orec[32];
       uint64_t olen[32];
@@ -1259,6 +1323,7 @@ int orc_sim_apply(orc_sim *s, const orc_gate *gates, uint64_t ngates, uint64_t *
       return rc_all;
     }
     for (uint64_t j = 0; j < s->nslices; j++) {
+      if (!nrec[j]) continue; /* a group left as it was (ORC_OPT) */
       free(s->rec[j]);
       s->rec[j] = nrec[j];
       s->rec_len[j] = nlen[j];
@@ -1418,6 +1483,7 @@ int orc_block_matrix(const orc_gate *gates, const orc_pass *p, double *U) {
  * passes. */
 int orc_sim_apply_fused(orc_sim *s, const orc_gate *gates, uint64_t ngates, uint64_t *applied) {
   *applied = 0;
+  if (s->mode & ORC_OPT) return ORC_EINVAL; /* optimised passes are a plain-mode option */
   uint64_t np = 0;
   orc_plan(gates, ngates, NULL, 0, &np);
   orc_pass *plan = (orc_pass *)calloc(np ? np : 1, sizeof(orc_pass));
@@ -1695,6 +1761,7 @@ void orc_vsim_destroy(orc_vsim *s);
 orc_vsim *orc_vsim_create(int n, int slice_log2, double eb, uint32_t mode) {
   if (n < 1 || n > 40 || slice_log2 < 1 || slice_log2 > n || slice_log2 > 26) return NULL;
   if (mode & ORC_PWREL) return NULL; /* codes only: the pointwise-relative norm needs the values */
+  if (mode & ORC_OPT) return NULL;   /* Algorithm 1 as written only */
   orc_vsim *s = (orc_vsim *)calloc(1, sizeof(orc_vsim));
   if (!s) return NULL;
   s->n = n;
