@@ -84,6 +84,13 @@ extern "C" {
                                 offsets of the runs' streams; header word 14 bit 3 marks such records.
                                 Codes, amplitudes and norms are unchanged; only record sizes shrink */
 
+#define SIM_OPT 0x80u    /* optimised passes (an extension, off for Algorithm 1 as written; not with
+                            SIM_FUSED, not through sim_apply_noalloc): a gate controlled on slice-index
+                            qubits leaves the slice groups whose index bits fail those controls as they
+                            are (records not decoded, renormalised or re-encoded), and a SWAP of two
+                            slice-index qubits without controls relabels the slices (record j becomes
+                            the record of j with the two index bits exchanged) without touching a value */
+
 #define SIM_FUSE_MAX 5   /* widest fused block, in qubits */
 
 /* ---- gate kinds (Section II: the circuit is a sequence of gates applied one

@@ -30,6 +30,7 @@ SIM_ZERO_CHUNKS = 0x8
 SIM_CONST_CHUNKS = 0x10
 SIM_EB_PWREL = 0x20
 SIM_CHUNK_RUNS = 0x40
+SIM_OPT = 0x80
 GATE_DENSE = 1
 GATE_PHASE = 2
 # named kinds (include/cqsim.h): matrices and phases made by the library from params
@@ -306,7 +307,8 @@ class Sim:
     def __init__(self, n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False,
                  chunk_log2: int = 0, workspace_bytes: int = 0, use_torch: Optional[bool] = None,
                  arena_bytes: int = 0, fused: bool = False, fp32: bool = False, zero_chunks: bool = False,
-                 const_chunks: bool = False, allocator=None, pointwise: bool = False, chunk_runs: bool = False):
+                 const_chunks: bool = False, allocator=None, pointwise: bool = False, chunk_runs: bool = False,
+                 opt: bool = False):
         """allocator: optional (ALLOC_FN, FREE_FN) pair of device-memory hooks
         (sim_config.alloc / free_fn); the caller keeps them alive as long as
         the Sim.  Otherwise torch's caching allocator (when torch sees a
@@ -315,7 +317,7 @@ class Sim:
         cfg = _config(n_qubits, slice_log2, error_bound, relative=relative, chunk_log2=chunk_log2,
                       workspace_bytes=workspace_bytes, arena_bytes=arena_bytes, fused=fused, fp32=fp32,
                       zero_chunks=zero_chunks, const_chunks=const_chunks, pointwise=pointwise,
-                      chunk_runs=chunk_runs)
+                      chunk_runs=chunk_runs, opt=opt)
         self._mem = None
         if use_torch is None:
             use_torch = _torch_ready()
@@ -338,6 +340,7 @@ class Sim:
         self.const_chunks = const_chunks
         self.pointwise = pointwise
         self.chunk_runs = chunk_runs
+        self.opt = opt
         self.chunk_log2 = min(chunk_log2 or 10, slice_log2)
 
     def close(self):
@@ -494,7 +497,7 @@ class Graph:
 def _config(n_qubits: int, slice_log2: int, error_bound: float, relative: bool = False, chunk_log2: int = 0,
             workspace_bytes: int = 0, arena_bytes: int = 0, fused: bool = False, fp32: bool = False,
             zero_chunks: bool = False, const_chunks: bool = False, pointwise: bool = False,
-            chunk_runs: bool = False) -> ConfigStruct:
+            chunk_runs: bool = False, opt: bool = False) -> ConfigStruct:
     cfg = ConfigStruct()
     cfg.n_qubits = n_qubits
     cfg.slice_log2 = slice_log2
@@ -502,7 +505,7 @@ def _config(n_qubits: int, slice_log2: int, error_bound: float, relative: bool =
     cfg.error_bound = error_bound
     cfg.mode = ((SIM_EB_REL if relative else SIM_EB_ABS) | (SIM_FUSED if fused else 0) | (SIM_FP32 if fp32 else 0) |
                 (SIM_ZERO_CHUNKS if zero_chunks else 0) | (SIM_CONST_CHUNKS if const_chunks else 0) |
-                (SIM_EB_PWREL if pointwise else 0) | (SIM_CHUNK_RUNS if chunk_runs else 0))
+                (SIM_EB_PWREL if pointwise else 0) | (SIM_CHUNK_RUNS if chunk_runs else 0) | (SIM_OPT if opt else 0))
     cfg.workspace_bytes = workspace_bytes
     cfg.arena_bytes = arena_bytes
     return cfg

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -31,6 +32,7 @@ using cq::f64::launch_codebook;
 using cq::f64::launch_encode;
 using cq::f64::launch_finish;
 using cq::f64::launch_runs;
+using cq::f64::launch_carry;
 using cq::f64::launch_rel_step;
 using cq::f64::launch_reset_slots;
 
@@ -109,6 +111,15 @@ struct sim_s {
   Slots slots{};
   int W = 0;
   std::map<uint64_t, uint64_t *> tables;  // group mask -> slot order of all slices
+  // SIM_OPT: slices a pass processes and those it carries over unchanged, per
+  // (group mask, slice-index control mask, values), or, for a relabelling
+  // SWAP, per (all ones, bit a, bit b); and the carried records' offsets
+  struct OptLists {
+    uint64_t *active = nullptr, n_active = 0;
+    uint64_t *src = nullptr, *dst = nullptr, n_carry = 0;
+  };
+  std::map<std::array<uint64_t, 3>, OptLists> opt_lists;
+  uint64_t *carry_off = nullptr;
   // The workspace that passes run on: the handle's own (slots, W, tables),
   // or, during sim_apply_noalloc, one carved from the scratch array, with
   // every slot table present and no device allocation allowed.
@@ -637,7 +648,63 @@ QuantParams quant_params(const sim_t *s) {
 
 // Enqueue one pass.  init_kind >= 0: build that initial state instead of
 // decompressing (no normalisation, identity gate).
-int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint64_t x) {
+// SIM_OPT decisions of one pass: a SWAP of slice-index bits sa and sb (a
+// relabelling), or controls on slice-index bits (smask, svals in slice-index
+// bits) that leave the other groups untouched; neither: an ordinary pass.
+struct PassOpt {
+  int sa = -1, sb = -1;
+  uint64_t smask = 0, svals = 0;
+};
+
+// SIM_OPT lists of a pass (built on the host and copied to the device once,
+// before any graph capture that uses them).
+int opt_lists(sim_t *s, uint64_t gm, const PassOpt &po, const sim_t::OptLists **out) {
+  const std::array<uint64_t, 3> key = po.sa >= 0 ? std::array<uint64_t, 3>{~0ull, (uint64_t)po.sa, (uint64_t)po.sb}
+                                                 : std::array<uint64_t, 3>{gm, po.smask, po.svals};
+  auto it = s->opt_lists.find(key);
+  if (it != s->opt_lists.end()) {
+    *out = &it->second;
+    return SIM_OK;
+  }
+  if (s->no_alloc) return set_err(SIM_EINVAL, "SIM_OPT passes are not available without allocation");
+  int rc;
+  if (!s->carry_off && (rc = s->dalloc((void **)&s->carry_off, 8 * s->nslices))) return rc;
+  std::vector<uint64_t> act, src, dst;
+  if (po.sa >= 0) {  // relabel: slice j becomes the slice with index bits sa and sb exchanged
+    for (uint64_t j = 0; j < s->nslices; j++) {
+      const uint64_t ba = (j >> po.sa) & 1, bb = (j >> po.sb) & 1;
+      src.push_back(j);
+      dst.push_back(ba == bb ? j : j ^ ((1ull << po.sa) | (1ull << po.sb)));
+    }
+  } else {  // whole groups (slot order of gm) whose index bits meet the controls; the rest carried
+    const uint64_t *table;
+    if ((rc = slot_table(s, gm, &table))) return rc;
+    std::vector<uint64_t> order(s->nslices);
+    HIP_TRY(hipMemcpy(order.data(), table, 8 * s->nslices, hipMemcpyDeviceToHost));
+    for (uint64_t j : order) {
+      if ((j & po.smask) == po.svals)
+        act.push_back(j);
+      else
+        src.push_back(j);
+    }
+    dst = src;
+  }
+  sim_t::OptLists L;
+  auto put = [&](const std::vector<uint64_t> &h, uint64_t **d) -> int {
+    if (h.empty()) return SIM_OK;
+    int r = s->dalloc((void **)d, 8 * h.size());
+    if (r) return r;
+    HIP_TRY(hipMemcpy(*d, h.data(), 8 * h.size(), hipMemcpyHostToDevice));
+    return SIM_OK;
+  };
+  if ((rc = put(act, &L.active)) || (rc = put(src, &L.src)) || (rc = put(dst, &L.dst))) return rc;
+  L.n_active = act.size();
+  L.n_carry = src.size();
+  *out = &(s->opt_lists[key] = L);
+  return SIM_OK;
+}
+
+int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint64_t x, const PassOpt *po = nullptr) {
   const int c = s->cur;
   const StateMeta &cur = s->meta[c];
   const StateMeta &nxt = s->meta[1 - c];
@@ -647,9 +714,28 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
   const uint64_t *table;
   int rc = slot_table(s, init_kind >= 0 ? 0 : gm, &table);
   if (rc) return rc;
+  uint64_t count = s->nslices;  // slices the batches process
+  const sim_t::OptLists *ol = nullptr;
+  if (init_kind < 0 && po && (po->sa >= 0 || po->smask)) {
+    if ((rc = opt_lists(s, gm, *po, &ol))) return rc;
+    if (po->sa >= 0) {  // a relabelling SWAP: every record carried to its new slice, nothing decoded
+      s->kt_begin(K_BEGIN);
+      launch_begin_pass(st, s->ctl, cur, s->nslices, s->kscale, 0, s->geo.pw_bits >= 0);
+      s->kt_end();
+      launch_carry(st, s->ctl, cur, nxt, s->arena[c], s->arena[1 - c], s->arena_cap[1 - c], ol->src, ol->dst,
+                   ol->n_carry, s->carry_off, pass);
+      s->cur = 1 - c;
+      return check_launch("relabel");
+    }
+    table = ol->active;
+    count = ol->n_active;
+  }
   s->kt_begin(K_BEGIN);
   launch_begin_pass(st, s->ctl, cur, s->nslices, s->kscale, init_kind >= 0 ? 0 : 1, s->geo.pw_bits >= 0);
   s->kt_end();
+  if (ol && ol->n_carry)  // groups where the gate is the identity keep their records
+    launch_carry(st, s->ctl, cur, nxt, s->arena[c], s->arena[1 - c], s->arena_cap[1 - c], ol->src, ol->dst,
+                 ol->n_carry, s->carry_off, pass);
   const GateDesc &gq = gd.kind == 4 ? s->ident : gd;
   // compact workspace (int32 codes) when decode feeds the quantising kernel
   // directly and that kernel reads it; the device still falls back to FP64
@@ -657,8 +743,8 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
   const bool compact = init_kind < 0 && !qp.rel && !qp.pw && gd.kind != 4 && AMP(s, gq_compact)(s->geo, gq);
   const Slots &slots = s->run_slots();
   const uint64_t W = (uint64_t)s->run_W();
-  for (uint64_t b0 = 0; b0 < s->nslices; b0 += W) {
-    const int ns = (int)std::min<uint64_t>(W, s->nslices - b0);
+  for (uint64_t b0 = 0; b0 < count; b0 += W) {
+    const int ns = (int)std::min<uint64_t>(W, count - b0);
     const uint64_t *ss = table + b0;
     if (init_kind >= 0) {
       s->kt_begin(K_INIT);
@@ -765,7 +851,7 @@ int ensure_arenas(sim_t *s) {
 
 // Run gates (or an init pass when gates == nullptr) with failure handling.
 int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, int init_kind, uint64_t x,
-               size_t *applied_out) {
+               size_t *applied_out, const PassOpt *opts = nullptr) {
   size_t applied = 0;
   int rc = SIM_OK;
   size_t total = descs ? n : 1;
@@ -780,9 +866,9 @@ int run_passes(sim_t *s, const GateDesc *descs, const uint64_t *gms, size_t n, i
     const int cur_start = s->cur;
     for (size_t i = applied; i < total; i++) {
       if (descs)
-        rc = enqueue_pass(s, descs[i], gms[i], -1, 0);
+        rc = enqueue_pass(s, descs[i], gms[i], -1, 0, opts ? opts + i : nullptr);
       else
-        rc = enqueue_pass(s, GateDesc{}, 0, init_kind, x);
+        rc = enqueue_pass(s, GateDesc{}, 0, init_kind, x, nullptr);
       if (rc) return rc;
     }
     // count the records of the last batch (settle only)
@@ -861,8 +947,10 @@ int configure(const sim_config *cfg, sim_t *s, uint64_t *arena_cap) {
   if (!(cfg->error_bound > 0.0) || !std::isfinite(cfg->error_bound))
     return set_err(SIM_EINVAL, "error bound must be positive and finite");
   if (cfg->mode & ~(SIM_EB_REL | SIM_FP32 | SIM_FUSED | SIM_ZERO_CHUNKS | SIM_CONST_CHUNKS | SIM_EB_PWREL |
-                    SIM_CHUNK_RUNS))
+                    SIM_CHUNK_RUNS | SIM_OPT))
     return set_err(SIM_EINVAL, "unsupported mode bits 0x%x", cfg->mode);
+  if ((cfg->mode & SIM_OPT) && (cfg->mode & SIM_FUSED))
+    return set_err(SIM_EINVAL, "SIM_OPT is a plain-mode option (not with SIM_FUSED)");
   if ((cfg->mode & SIM_EB_REL) && (cfg->mode & SIM_EB_PWREL))
     return set_err(SIM_EINVAL, "SIM_EB_REL and SIM_EB_PWREL exclude each other");
   int pwb = -1;
@@ -1065,6 +1153,7 @@ struct PassSet {
   std::vector<size_t> moff;
   std::vector<sim_gate> pg;
   std::vector<int> kind4;
+  std::vector<PassOpt> opts;  // SIM_OPT: per pass (empty otherwise)
   size_t n_pass = 0;
 };
 
@@ -1166,6 +1255,29 @@ static void pass_descs(const sim_t *s, PassSet &P, double *dev, std::vector<Gate
     descs[i] = make_desc(s, P.pg[i], dense ? dev + P.moff[i] : nullptr, &gms[i]);
     if (P.kind4[i]) descs[i].kind = 4;
   }
+  P.opts.clear();
+  if (!(s->mode & SIM_OPT)) return;
+  P.opts.resize(P.n_pass);
+  const int sl2 = s->geo.slice_log2;
+  const uint64_t lo = (1ull << sl2) - 1;
+  for (size_t i = 0; i < P.n_pass; i++) {
+    const sim_gate &g = P.pg[i];
+    PassOpt &o = P.opts[i];
+    bool swap = g.kind == SIM_GATE_DENSE && g.n_targets == 2 && g.ctrl_mask == 0 && (int)g.targets[0] >= sl2 &&
+                (int)g.targets[1] >= sl2;
+    for (int r = 0; swap && r < 4; r++)  // exactly the exchange of the two targets
+      for (int c = 0; c < 4; c++) {
+        const bool one = (r == 0 && c == 0) || (r == 1 && c == 2) || (r == 2 && c == 1) || (r == 3 && c == 3);
+        if (g.matrix[2 * (4 * r + c)] != (one ? 1.0 : 0.0) || g.matrix[2 * (4 * r + c) + 1] != 0.0) swap = false;
+      }
+    if (swap) {
+      o.sa = (int)g.targets[0] - sl2;
+      o.sb = (int)g.targets[1] - sl2;
+    } else {
+      o.smask = (g.ctrl_mask & ~lo) >> sl2;
+      o.svals = (g.ctrl_vals & ~lo) >> sl2;
+    }
+  }
 }
 
 int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
@@ -1193,7 +1305,9 @@ int sim_apply(sim_t *s, const sim_gate *gates, size_t n, size_t *n_applied) {
   if (!hm.empty()) HIP_TRY(hipMemcpy(s->dmat, hm.data(), 8 * hm.size(), hipMemcpyHostToDevice));
   size_t applied = 0;
   HIP_TRY(hipEventRecord(s->ev0, s->stream));
-  int rc = n_pass ? run_passes(s, descs.data(), gms.data(), n_pass, -1, 0, &applied) : SIM_OK;
+  int rc = n_pass ? run_passes(s, descs.data(), gms.data(), n_pass, -1, 0, &applied,
+                               P.opts.empty() ? nullptr : P.opts.data())
+                  : SIM_OK;
   HIP_TRY(hipEventRecord(s->ev1, s->stream));
   HIP_TRY(hipEventSynchronize(s->ev1));
   float ms = 0;
@@ -1244,9 +1358,12 @@ static int graph_capture(sim_graph_t *G) {
     G->exec = nullptr;
   }
   int rc;
+  const PassOpt *opts = G->P.opts.empty() ? nullptr : G->P.opts.data();
   for (size_t i = 0; i < G->P.n_pass; i++) {  // slot tables exist before the capture (they copy to the device)
     const uint64_t *t;
     if ((rc = slot_table(s, G->gms[i], &t))) return rc;
+    const sim_t::OptLists *ol;
+    if (opts && (opts[i].sa >= 0 || opts[i].smask) && (rc = opt_lists(s, G->gms[i], opts[i], &ol))) return rc;
   }
   if (!s->cap_stream && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return set_err(SIM_EDEVICE, "capture stream creation failed");
@@ -1262,7 +1379,8 @@ static int graph_capture(sim_graph_t *G) {
   if (e != hipSuccess) {
     rc = set_err(SIM_EDEVICE, "graph capture could not start: %s", hipGetErrorString(e));
   } else {
-    for (size_t i = 0; i < G->P.n_pass && rc == SIM_OK; i++) rc = enqueue_pass(s, G->descs[i], G->gms[i], -1, 0);
+    for (size_t i = 0; i < G->P.n_pass && rc == SIM_OK; i++)
+      rc = enqueue_pass(s, G->descs[i], G->gms[i], -1, 0, opts ? opts + i : nullptr);
     e = hipStreamEndCapture(s->cap_stream, &graph);
     if (rc == SIM_OK && e != hipSuccess) rc = set_err(SIM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
   }
@@ -1372,7 +1490,8 @@ int sim_graph_launch(sim_t *s, sim_graph_t *G, size_t *n_applied) {
   if ((rc = ensure_arenas(s))) return rc;
   HIP_TRY(hipEventRecord(s->ev0, s->stream));
   if (s->cur != G->start_cur) {  // the other parity: ordinary launches of the same passes
-    rc = run_passes(s, G->descs.data(), G->gms.data(), n, -1, 0, &applied);
+    rc = run_passes(s, G->descs.data(), G->gms.data(), n, -1, 0, &applied,
+                    G->P.opts.empty() ? nullptr : G->P.opts.data());
   } else {
     if (!graph_current(G)) rc = graph_capture(G);  // an arena has been reallocated since
     if (rc == SIM_OK) {
@@ -1396,7 +1515,8 @@ int sim_graph_launch(sim_t *s, sim_graph_t *G, size_t *n_applied) {
             if (flags & kFlagOverflow) {  // the rest through ordinary launches, into a larger arena
               if ((rc = grow_arena(s, 1 - s->cur, 0)) == SIM_OK) {
                 size_t more = 0;
-                rc = run_passes(s, G->descs.data() + done, G->gms.data() + done, n - done, -1, 0, &more);
+                rc = run_passes(s, G->descs.data() + done, G->gms.data() + done, n - done, -1, 0, &more,
+                                G->P.opts.empty() ? nullptr : G->P.opts.data() + done);
                 applied += more;
               }
             } else if (flags & kFlagCorrupt) {
@@ -1797,6 +1917,7 @@ int sim_apply_noalloc(sim_t *s, const sim_gate *gates, size_t n, size_t *n_appli
   if (n_applied) *n_applied = 0;
   if (!s) return set_err(SIM_EINVAL, "null handle");
   if (n && !gates) return set_err(SIM_EINVAL, "null gate array");
+  if (s->mode & SIM_OPT) return set_err(SIM_EINVAL, "SIM_OPT handles apply through sim_apply");
   uint8_t *base = nullptr;
   int rc = scratch_address(&base);
   if (rc) return rc;

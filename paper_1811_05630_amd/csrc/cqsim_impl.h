@@ -219,6 +219,11 @@ void launch_rel_step(hipStream_t st, const Slots &sl, int nslots, double rel, co
 void launch_codebook(hipStream_t st, const Slots &sl, const uint64_t *slot_slice, int nslots, const StateMeta &nxt,
                      uint32_t nparts, Ctl *ctl, uint32_t pw_nchunks = 0);
 void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
+// SIM_OPT: the records of slices src[0..count) copied unchanged into the output
+// arena as slices dst[...] (after the arena position), with their metadata
+void launch_carry(hipStream_t st, Ctl *ctl, const StateMeta &cur, const StateMeta &nxt, const uint8_t *in,
+                  uint8_t *out, uint64_t cap, const uint64_t *src, const uint64_t *dst, uint64_t count, uint64_t *off,
+                  uint32_t pass);
 // chunk runs of each slot of the batch (SIM_CHUNK_RUNS), between encode and finish
 void launch_runs(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl);
 // records of the batch: offsets in the output arena, headers, symbol tables,

@@ -2913,6 +2913,83 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
   }
 }
 
+// ------------------------------------------------------------------ carried records
+// SIM_OPT passes that leave slices as they are: record j of the input arena
+// becomes record dst[i] = src[i] (groups where the gate is the identity) or a
+// relabelled slice of the output arena, copied byte for byte with its
+// metadata and decoder table.  A plan launch (one workgroup) places the
+// records after the arena position begin_pass left, as one batch whose size
+// the next batch's codebook (or the next pass) settles; a copy launch moves
+// them.  Carried records keep the input's code width.
+__global__ void __launch_bounds__(1024) k_carry_plan(Ctl *ctl, StateMeta cur, const uint64_t *src, uint64_t count,
+                                                     uint64_t cap, uint64_t *off, uint32_t pass) {
+  if (ctl->flags) return;
+  __shared__ uint64_t wsum[16][2];
+  const uint32_t tid = threadIdx.x, T = blockDim.x, lane = lane_id(), wave = tid >> 6;
+  const uint64_t base = ctl->bump;
+  uint64_t run = 0, exact = 0;  // bytes placed by earlier rounds (uniform)
+  for (uint64_t i0 = 0; i0 < count; i0 += T) {
+    const uint64_t i = i0 + tid;
+    const uint64_t len = i < count ? cur.rec_len[src[i]] : 0u;
+    const uint64_t ba = (len + kRecAlign - 1) & ~(kRecAlign - 1);
+    // 64-bit exclusive scan of the aligned sizes (and sum of the exact ones) over the block
+    uint64_t inc = ba, le = len;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t y = __shfl_up(inc, d, 64);
+      if (lane >= (uint32_t)d) inc += y;
+    }
+    for (int d = 32; d > 0; d >>= 1) le += __shfl_xor(le, d, 64);
+    if (lane == 63) wsum[wave][0] = inc;
+    if (lane == 0) wsum[wave][1] = le;
+    __syncthreads();
+    uint64_t before = 0, tot = 0, tlen = 0;
+    for (uint32_t w = 0; w < T / 64; w++) {
+      if (w < wave) before += wsum[w][0];
+      tot += wsum[w][0];
+      tlen += wsum[w][1];
+    }
+    __syncthreads();
+    if (i < count) off[i] = base + run + before + inc - ba;
+    run += tot;
+    exact += tlen;
+  }
+  if (tid == 0) {
+    if (base + run > cap) {
+      fail(ctl, kFlagOverflow, pass);
+      return;
+    }
+    ctl->pending_bump = run;
+    ctl->pending_bytes = exact;
+    if (ctl->wide) ctl->wide_next = 1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_carry_copy(const Ctl *ctl, StateMeta cur, StateMeta nxt, const uint8_t *in,
+                                                    uint8_t *out, const uint64_t *src, const uint64_t *dst,
+                                                    uint64_t count, const uint64_t *off) {
+  if (ctl->flags) return;
+  const uint32_t tid = threadIdx.x, T = blockDim.x;
+  for (uint64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const uint64_t j = src[i], t = dst[i];
+    const uint32_t len = cur.rec_len[j];
+    const uint8_t *a = in + cur.rec_off[j];
+    uint8_t *b = out + off[i];
+    // records start on 256-byte boundaries and hold whole 4-byte words
+    for (uint32_t k = tid; k < len / 16; k += T) ((uint4 *)b)[k] = ((const uint4 *)a)[k];
+    for (uint32_t k = (len / 16) * 4 + tid; k < len / 4; k += T) ((uint32_t *)b)[k] = ((const uint32_t *)a)[k];
+    const uint4 *dt = (const uint4 *)(cur.dtab + j * (1u << kLMax));
+    uint4 *dn = (uint4 *)(nxt.dtab + t * (1u << kLMax));
+    for (uint32_t k = tid; k < (1u << kLMax) / 4; k += T) dn[k] = dt[k];
+    if (tid == 0) {
+      nxt.rec_off[t] = off[i];
+      nxt.rec_len[t] = len;
+      nxt.step[t] = cur.step[j];
+      nxt.sq[2 * t] = cur.sq[2 * j];
+      nxt.sq[2 * t + 1] = cur.sq[2 * j + 1];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ chunk runs
 // SIM_CHUNK_RUNS: chunk c starts a run unless its staged stream -- word
 // count, constant mark and words -- equals chunk c - 1's.  Two launches over
@@ -3607,6 +3684,14 @@ void launch_encode(hipStream_t st, const Slots &sl, const Geo &g, int nslots, co
     case 2: launch_encode_fmt<2>(st, sl, g, nslots, ctl); break;
     default: launch_encode_fmt<3>(st, sl, g, nslots, ctl); break;
   }
+}
+
+void launch_carry(hipStream_t st, Ctl *ctl, const StateMeta &cur, const StateMeta &nxt, const uint8_t *in,
+                  uint8_t *out, uint64_t cap, const uint64_t *src, const uint64_t *dst, uint64_t count, uint64_t *off,
+                  uint32_t pass) {
+  CQ_LAUNCH(k_carry_plan, dim3(1), dim3(1024), 0, st, ctl, cur, src, count, cap, off, pass);
+  const uint32_t wgs = (uint32_t)(count < 2048 ? count : 2048);
+  CQ_LAUNCH(k_carry_copy, dim3(wgs), dim3(256), 0, st, ctl, cur, nxt, in, out, src, dst, count, off);
 }
 
 void launch_runs(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const Ctl *ctl) {

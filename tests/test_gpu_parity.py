@@ -38,14 +38,15 @@ def assert_same_records(sim, orc, label, which=None):
 
 
 def run_both(n, sl, cl, eb, gates, rel=False, init=None, check_every=1, workspace_bytes=0, arena_bytes=0,
-             use_torch=None, fp32=False, zero_chunks=False, const_chunks=False, chunk_runs=False, pointwise=False):
+             use_torch=None, fp32=False, zero_chunks=False, const_chunks=False, chunk_runs=False, pointwise=False,
+             opt=False):
     mode = ((oracle.REL if rel else oracle.PWREL if pointwise else oracle.ABS) | (oracle.FP32 if fp32 else 0) |
             (oracle.ZERO_CHUNKS if zero_chunks else 0) | (oracle.CONST_CHUNKS if const_chunks else 0) |
-            (oracle.CHUNK_RUNS if chunk_runs else 0))
+            (oracle.CHUNK_RUNS if chunk_runs else 0) | (oracle.OPT if opt else 0))
     orc = oracle.OracleSim(n, sl, cl, eb, mode)
     sim = cq.Sim(n, sl, eb, relative=rel, chunk_log2=cl, workspace_bytes=workspace_bytes,
                  arena_bytes=arena_bytes, use_torch=use_torch, fp32=fp32, zero_chunks=zero_chunks,
-                 const_chunks=const_chunks, chunk_runs=chunk_runs, pointwise=pointwise)
+                 const_chunks=const_chunks, chunk_runs=chunk_runs, pointwise=pointwise, opt=opt)
     if init is not None:
         kind, arg = init
         if kind == "basis":
