@@ -92,6 +92,9 @@ def parse():
                     help="grover24, grover34: zero-chunk records (all-zero chunks stored with no words)")
     ap.add_argument("--const-chunks", action="store_true",
                     help="grover24, grover34: constant-chunk records (a chunk of equal values keeps its first only)")
+    ap.add_argument("--opt", action="store_true",
+                    help="grover24, grover34: optimised passes (SIM_OPT: groups where a gate's slice-index controls "
+                         "fail are carried over unchanged)")
     ap.add_argument("--chunk-runs", action="store_true",
                     help="grover24, grover34: chunk-run records (runs of chunks with identical streams stored once)")
     ap.add_argument("--workload", choices=("grover34", "grover24", "qft30", "qft12", "serve"), default="grover34",
@@ -274,7 +277,7 @@ def run_grover24(args):
     # stays above 6), so that no reallocation falls inside a timed batch
     sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, arena_bytes=(16 << n) // 4,
                  fp32=args.fp32, zero_chunks=args.zero_chunks,
-                 const_chunks=args.const_chunks, chunk_runs=args.chunk_runs)
+                 const_chunks=args.const_chunks, chunk_runs=args.chunk_runs, opt=args.opt)
     # initial H layer (untimed), then warm-up passes
     # the circuit is marshalled once, outside every timed region
     gates = cq.Circuit(w.gates)
@@ -313,7 +316,8 @@ def run_grover24(args):
                           (", FP32 mode" if args.fp32 else "") +
                           (", zero-chunk records" if args.zero_chunks else "") +
                           (", constant-chunk records" if args.const_chunks else "") +
-                          (", chunk-run records" if args.chunk_runs else ""),
+                          (", chunk-run records" if args.chunk_runs else "") +
+                          (", optimised passes" if args.opt else ""),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
               "error_bound": w.error_bound, "passes_timed": K, "first_timed_gate": n + Wm, "fp32": args.fp32,
               "zero_chunks": args.zero_chunks, "const_chunks": args.const_chunks, "chunk_runs": args.chunk_runs}
@@ -467,7 +471,8 @@ def run_grover34_leg(args, w, fp32, K, Wm, codec=None):
     # about 6.6, in its first diffusion passes), so that no arena grows, and
     # no pass is run again, inside the timed region
     if codec is None:
-        codec = dict(zero_chunks=args.zero_chunks, const_chunks=args.const_chunks, chunk_runs=args.chunk_runs)
+        codec = dict(zero_chunks=args.zero_chunks, const_chunks=args.const_chunks, chunk_runs=args.chunk_runs,
+                     opt=args.opt)
     sim = cq.Sim(n, w.slice_log2, w.error_bound, chunk_log2=args.chunk_log2, workspace_bytes=96 << 30,
                  arena_bytes=(16 << n) // 4, fp32=fp32, **codec)
     g = cq.Circuit(w.gates)  # marshalled once, outside the timed region
@@ -537,7 +542,8 @@ def run_grover34(args):
                           % (args.seed, start, start + K - 1, K - 2) +
                           (", zero-chunk records" if args.zero_chunks else "") +
                           (", constant-chunk records" if args.const_chunks else "") +
-                          (", chunk-run records" if args.chunk_runs else ""),
+                          (", chunk-run records" if args.chunk_runs else "") +
+                          (", optimised passes" if args.opt else ""),
               "n_qubits": n, "slice_log2": w.slice_log2, "chunk_log2": args.chunk_log2,
               "error_bound": w.error_bound, "passes_timed": K, "first_timed_pass": start,
               "workspace_slots": r64["st2"]["workspace_slots"], "fp32": False}
@@ -564,7 +570,7 @@ def run_grover34(args):
                                                 "p99": float(np.percentile(r32["lat"], 99))}
                         if r32["lat"] else None}
     line["accuracy"] = acc
-    if not args.no_codec_leg and not (args.chunk_runs or args.zero_chunks or args.const_chunks):
+    if not args.no_codec_leg and not (args.chunk_runs or args.zero_chunks or args.const_chunks or args.opt):
         # the same window with the record variants past the Huffman stage
         # (zero chunks, constant chunks, chunk runs): the same codes and
         # amplitudes, smaller records
