@@ -330,33 +330,50 @@ __global__ void k_init(Slots sl, Geo g, const uint64_t *slot_slice, uint64_t tot
 // more words than the slot holds reads them from global memory.
 
 constexpr int kDecWaves = 4;       // wavefronts per workgroup
-constexpr int kDecPfMax = 12;      // largest slot (words per lane)
-constexpr int kDecStage = 64 * 17 * 8;  // tile bytes per wavefront: 64 rows of 16 FP64 or 32 int32 values, padded
+
+// Two decoder configurations.  The wide one, for passes that decode FP64
+// values (relative and pointwise-relative bounds, fused blocks), stages 16
+// FP64 values per lane and round and prefetches up to 12 words; its 63.5 KB
+// of LDS per workgroup allow two workgroups per CU.  The narrow one, for
+// passes that decode int32 codes, stages 32 codes per round and prefetches 4
+// words (53 KB): three workgroups per CU, more chains to hide the table
+// lookups' latency.  Its FP64 fallback (a pass whose codes may not fit int32)
+// stages 8 values per round.
+template <bool SMALL>
+struct DecCfg {
+  static constexpr int kPfMax = SMALL ? 4 : 12;                    // largest slot (words per lane)
+  static constexpr int kStage = SMALL ? 64 * 33 * 4 : 64 * 17 * 8;  // tile bytes per wavefront, rows padded
+};
 
 // The running sum p: FP64 (exact below 2^53) for the FP64 workspace; for
 // the compact one, whose codes all lie below 2^31 in magnitude, uint32
 // arithmetic modulo 2^32, which is exact for every partial sum as each of
 // them is such a code (an escaped difference may be larger, its sum is not).
-template <bool C32>
+template <bool C32, bool SMALL = false>
 struct DecFmt {  // FP64 workspace
   using T = double;
   using P = double;
-  static constexpr int R = 16, PITCH = 17, PF = 8;
+  static constexpr int R = SMALL ? 8 : 16, PITCH = R + 1, PF = SMALL ? 4 : 8;
   static __device__ __forceinline__ double add(double p, int d) { return p + (double)d; }
   static __device__ __forceinline__ double add_esc(double p, int64_t d) { return p + (double)d; }
   static __device__ __forceinline__ double val(double p, double k) { return rw(p * k); }
 };
-template <>
-struct DecFmt<true> {  // compact workspace: the code itself
+template <bool SMALL>
+struct DecFmt<true, SMALL> {  // compact workspace: the code itself
   using T = int32_t;
   using P = uint32_t;
-  static constexpr int R = 32, PITCH = 33, PF = 12;
+  static constexpr int R = 32, PITCH = 33, PF = SMALL ? 4 : 12;
   static __device__ __forceinline__ uint32_t add(uint32_t p, int d) { return p + (uint32_t)d; }
   static __device__ __forceinline__ uint32_t add_esc(uint32_t p, int64_t d) { return p + (uint32_t)(uint64_t)d; }
   static __device__ __forceinline__ int32_t val(uint32_t p, double) { return (int32_t)p; }
 };
-static_assert(64 * DecFmt<true>::PITCH * 4 <= kDecStage && 64 * DecFmt<false>::PITCH * 8 <= kDecStage, "tile");
-static_assert(DecFmt<true>::PF <= kDecPfMax && DecFmt<false>::PF <= kDecPfMax, "slot");
+template <bool SMALL>
+constexpr bool dec_fits() {
+  return 64 * DecFmt<true, SMALL>::PITCH * 4 <= DecCfg<SMALL>::kStage &&
+         64 * DecFmt<false, SMALL>::PITCH * 8 <= DecCfg<SMALL>::kStage &&
+         DecFmt<true, SMALL>::PF <= DecCfg<SMALL>::kPfMax && DecFmt<false, SMALL>::PF <= DecCfg<SMALL>::kPfMax;
+}
+static_assert(dec_fits<false>() && dec_fits<true>(), "tile and slot sizes");
 
 template <int PF>
 struct BitReader {
@@ -433,13 +450,13 @@ __device__ __forceinline__ typename DecFmt<C32>::T dec_val(typename DecFmt<C32>:
   }
 }
 
-template <bool FULL, bool C32, int FMT>
+template <bool FULL, bool C32, int FMT, bool SMALL>
 __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, const StateMeta &cur, uint64_t slice,
                                               uint32_t u, const uint32_t *offs, uint32_t nchunks, uint32_t n_words,
                                               uint32_t n_used, uint32_t nruns, double k, uint32_t *dtab,
                                               uint8_t *stg, uint32_t (*pf)[64 * kDecWaves], Ctl *ctl,
                                               uint32_t pass) {
-  using F = DecFmt<C32>;
+  using F = DecFmt<C32, SMALL>;
   using T = typename F::T;
   constexpr int PF = F::PF, RMAX = F::R, PITCH = F::PITCH;
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
@@ -509,7 +526,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   const uint64_t B = 1ull << g.chunk_log2;
   const uint32_t R = FULL ? (uint32_t)RMAX : (B < (uint64_t)RMAX ? (uint32_t)B : (uint32_t)RMAX);
   T *out = (T *)(sl.ws + (uint64_t)u * 2 * g.L);
-  T *st = (T *)(stg + wave * kDecStage);
+  T *st = (T *)(stg + wave * DecCfg<SMALL>::kStage);
   typename F::P p = 0;  // running sum
   // nothing is in flight when the rounds start, so no load issued here is
   // waited for inside them (where a wait would also wait for the stores)
@@ -585,17 +602,19 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   }
 }
 
-template <bool FULL, int FMT>
-__global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
-                                                           const uint8_t *arena, StateMeta cur, const double *kscale,
-                                                           Ctl *ctl, uint32_t pass, int compact_ok) {
+// SMALL: the narrow configuration (launched for passes that may decode int32 codes)
+template <bool FULL, int FMT, bool SMALL>
+__global__ void __launch_bounds__(64 * kDecWaves, SMALL ? 3 : 1) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
+                                                                       const uint8_t *arena, StateMeta cur,
+                                                                       const double *kscale, Ctl *ctl, uint32_t pass,
+                                                                       int compact_ok) {
   if (ctl->flags) return;
   // compact workspace: the int32 codes q themselves (every |q| < 2^31), the
   // gate kernel multiplies by the slice's scale; else the FP64 values q * k
   const bool c32 = compact_ok && !ctl->wide;
   __shared__ __align__(16) uint32_t dtab[1 << kLMax];
-  __shared__ __align__(16) uint8_t stg[kDecWaves * kDecStage];
-  __shared__ uint32_t pf[kDecPfMax][64 * kDecWaves];
+  __shared__ __align__(16) uint8_t stg[kDecWaves * DecCfg<SMALL>::kStage];
+  __shared__ uint32_t pf[DecCfg<SMALL>::kPfMax][64 * kDecWaves];
   const uint32_t u = blockIdx.y, tid = threadIdx.x;
   const uint64_t slice = slot_slice[u];
   // the slice's decoder table (16 KiB, its own buffer): its loads go out
@@ -628,11 +647,11 @@ __global__ void __launch_bounds__(64 * kDecWaves) k_decode(Slots sl, Geo g, cons
     return;
   }
   if (c32)
-    decode_chunks<FULL, true, FMT>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns, 0.0, dtab, stg, pf,
-                                   ctl, pass);
+    decode_chunks<FULL, true, FMT, SMALL>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns, 0.0, dtab,
+                                          stg, pf, ctl, pass);
   else
-    decode_chunks<FULL, false, FMT>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns, kscale[slice],
-                                    dtab, stg, pf, ctl, pass);
+    decode_chunks<FULL, false, FMT, SMALL>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns,
+                                           kscale[slice], dtab, stg, pf, ctl, pass);
 }
 
 // ------------------------------------------------------------ gate + quantise
@@ -3437,8 +3456,16 @@ void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
   dim3 grid(grid1(g.nchunks, per_wg), (unsigned)nslots);
   const bool full = (1ull << g.chunk_log2) >= (uint64_t)DecFmt<true>::R && g.nchunks % per_wg == 0;
   const int c = compact ? 1 : 0;
-#define CQ_DEC(FULL_, FMT_) \
-  CQ_LAUNCH((k_decode<FULL_, FMT_>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, ctl, pass, c)
+#define CQ_DEC1(FULL_, FMT_, SMALL_)                                                                        \
+  CQ_LAUNCH((k_decode<FULL_, FMT_, SMALL_>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, \
+            ctl, pass, c)
+#define CQ_DEC(FULL_, FMT_)                 \
+  do {                                      \
+    if (compact)                            \
+      CQ_DEC1(FULL_, FMT_, true);           \
+    else                                    \
+      CQ_DEC1(FULL_, FMT_, false);          \
+  } while (0)
   switch (g.fmt_in & 3u) {
     case 0: if (full) CQ_DEC(true, 0); else CQ_DEC(false, 0); break;
     case 1: if (full) CQ_DEC(true, 1); else CQ_DEC(false, 1); break;
@@ -3446,6 +3473,7 @@ void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
     default: if (full) CQ_DEC(true, 3); else CQ_DEC(false, 3); break;
   }
 #undef CQ_DEC
+#undef CQ_DEC1
 }
 
 static int gate_kind(const GateDesc &gd) {
