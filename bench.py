@@ -43,28 +43,28 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
     "grover34": {
-        "decode": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 9191657220},
-        "gate_quant": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 14189855149},
-        "codebook": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 5839575},
-        "encode": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 6980882713},
-        "finish": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 1074944972},
+        "decode": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 9196986788},
+        "gate_quant": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 14189994131},
+        "codebook": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 5872105},
+        "encode": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 6980871163},
+        "finish": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 1075017400},
     },
     "grover24": {
-        "decode": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 149626206},
-        "gate_quant": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 221611842},
-        "codebook": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 5862115},
-        "encode": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 82770950},
-        "finish": {"kernels_sha256": "e06315e073e410828409e198044e5782795314d7d316e1af841109a28682e93e",
-                 "bytes_per_launch": 16511362},
+        "decode": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 149685211},
+        "gate_quant": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 221593340},
+        "codebook": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 5879825},
+        "encode": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 82771417},
+        "finish": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
+                 "bytes_per_launch": 16587877},
     },
 }
 
