@@ -2697,6 +2697,41 @@ __device__ __forceinline__ uint2 enc_syms(const uint16_t *sym, uint64_t j, uint6
   return make_uint2(t[0] | (t[1] << 16), t[2] | (t[3] << 16));
 }
 
+// The store wavefront's work for one round: the round's NCH chunks (those
+// below ce) are packed after the block's earlier words.  Lane k < NCH holds
+// chunk k's word count, a prefix over those lanes places the chunks, and one
+// flat loop copies every word and clears it for the round after next, so
+// the chunks do not form a chain of LDS round trips.
+template <uint32_t NCH, bool CC>
+__device__ __forceinline__ void enc_store_round(const Slots &sl, const Geo &g, uint32_t u, uint32_t c0, uint32_t ce,
+                                                uint32_t *lw_round, const uint32_t *cnw_round, uint32_t W,
+                                                uint32_t *blk, uint32_t &packed) {
+  static_assert(NCH >= 1 && NCH <= 8, "one row of lanes");
+  const uint32_t lane = lane_id();
+  const uint32_t nch = c0 < ce ? (ce - c0 < NCH ? ce - c0 : NCH) : 0u;
+  const uint32_t v = lane < nch ? cnw_round[lane] : 0u;
+  const uint32_t nw = CC ? v & 0x7FFFFFFFu : v;
+  uint32_t inc = nw;  // inclusive prefix over lanes 0..7 (row 0)
+  inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x111 /* row_shr:1 */, 0xF, 0xF, true);
+  inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x112 /* row_shr:2 */, 0xF, 0xF, true);
+  inc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)inc, 0x114 /* row_shr:4 */, 0xF, 0xF, true);
+  const uint32_t pre = inc - nw;
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)inc, (int)NCH - 1);
+  if (lane < nch) sl.chunk_words[(uint64_t)u * g.nchunks + c0 + lane] = (packed + pre) | (CC ? v & 0x80000000u : 0u);
+  uint32_t pk[NCH];
+#pragma unroll
+  for (uint32_t k = 0; k < NCH; k++) pk[k] = (uint32_t)__builtin_amdgcn_readlane((int)pre, (int)k);
+  for (uint32_t i = lane; i < total; i += 64) {
+    uint32_t off = i;  // word i of the round lies in the last chunk whose prefix is at most i
+#pragma unroll
+    for (uint32_t k = 1; k < NCH; k++)
+      if (i >= pk[k]) off = k * W + (i - pk[k]);
+    blk[packed + i] = lw_round[off];
+    lw_round[off] = 0;
+  }
+  packed += total;
+}
+
 // Chunks [cb, ce) of slot blockIdx.y; coding wavefront w takes chunks cb + w,
 // cb + w + 4, ...; every wavefront runs the same number of rounds so that
 // barriers line up.  STEPS = ceil(B / 256) steps of 256 symbols per chunk.
@@ -2910,19 +2945,8 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
       }
     } else if (wave == kEncWaves && r > 0) {  // store the previous round's chunks, packed
       const uint32_t pb = buf ^ 1u;
-      for (uint32_t w = 0; w < (uint32_t)kEncWaves; w++) {
-        const uint32_t c = cb + (r - 1) * kEncWaves + w;
-        if (c >= ce) break;
-        const uint32_t v = cnw[pb][w];
-        const uint32_t nw = CC ? v & 0x7FFFFFFFu : v;
-        uint32_t *src = lw_all + (uint64_t)(pb * kEncWaves + w) * W;
-        for (uint32_t i = lane; i < nw; i += 64) {  // copied out, then cleared for the round after next
-          blk[packed + i] = src[i];
-          src[i] = 0;
-        }
-        if (lane == 0) sl.chunk_words[(uint64_t)u * g.nchunks + c] = packed | (CC ? v & 0x80000000u : 0u);
-        packed += nw;
-      }
+      enc_store_round<kEncWaves, CC>(sl, g, u, cb + (r - 1) * kEncWaves, ce, lw_all + (uint64_t)pb * kEncWaves * W,
+                                     cnw[pb], W, blk, packed);
     }
     lds_sync();  // round r coded; round r - 1 read out of LDS
   }
