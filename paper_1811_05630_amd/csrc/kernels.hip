@@ -884,6 +884,98 @@ __device__ __forceinline__ SlotOut slot_out(const Slots &sl, const Geo &g, uint3
   return t;
 }
 
+// ------------------------------------------------ buffer memory operations
+// The gate kernels address slot memory through buffer resources: a
+// descriptor in scalar registers plus a 32-bit offset per lane, so that no
+// 64-bit address arithmetic runs per lane, and an access past the
+// descriptor's size is dropped by the hardware (reads return zero).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufWord3 = 0x00020000;  // descriptor word 3 for untyped 32-bit access on gfx9-family chips
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufWord3);
+}
+__device__ __forceinline__ double buf_ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __longlong_as_double((long long)(((uint64_t)x.y << 32) | x.x));
+}
+__device__ __forceinline__ void buf_st_u16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_i64(__amdgpu_buffer_rsrc_t r, uint32_t off, int64_t v) {
+  u32x2 x;
+  x.x = (uint32_t)(uint64_t)v;
+  x.y = (uint32_t)((uint64_t)v >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
+}
+
+// Escape buffer layout.  gate_quant writes each escaped difference to the
+// escape buffer and encode reads it back.  Within every aligned group of
+// G = min(B, 256) positions of a plane (B the chunk length) the group's
+// escapes fill its first entries, in position order, so that sparse escapes
+// touch few cache lines (a scattered 8-byte store makes the memory read and
+// rewrite its whole line).
+__device__ __forceinline__ uint32_t esc_group(const Geo &g) { return g.chunk_log2 < 8 ? 1u << g.chunk_log2 : 256u; }
+
+// set bits of m in the lanes below this one
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+// set bits of m in the lanes below this one inside its aligned segment of G < 64 lanes
+__device__ __forceinline__ uint32_t seg_below(uint64_t m, uint32_t G) {
+  const uint32_t lane = lane_id();
+  const uint64_t before_seg = (1ull << (lane & ~(G - 1))) - 1;
+  return (uint32_t)__popcll(m & ((1ull << lane) - 1) & ~before_seg);
+}
+
+// Escapes of a tile whose element e = v * T + tid sits at position ob + e
+// (T = 64 nwv threads, ob a multiple of G): the escape's rank in its group
+// counts the group's escapes in earlier rows and wavefronts (through cnt in
+// LDS, written before a workgroup barrier and read after it) and in lower
+// lanes.  Step 1, before the barrier: each wavefront's counts per row.
+template <int V>
+__device__ __forceinline__ void esc_count_tile(const bool (&er)[V], const bool (&ei)[V], uint32_t G, uint32_t *cnt) {
+  const uint32_t wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+#pragma unroll
+  for (int v = 0; v < V; v++) {
+    const uint64_t mr = __ballot(er[v]), mi = __ballot(ei[v]);
+    if (G >= 64 && lane_id() == 0) {
+      cnt[2 * (v * nwv + wave)] = (uint32_t)__popcll(mr);
+      cnt[2 * (v * nwv + wave) + 1] = (uint32_t)__popcll(mi);
+    }
+  }
+}
+// Step 2, after the barrier: ranks and stores, through a buffer resource
+// over the slot's escape buffer (re plane, then im plane of L entries each).
+template <int V>
+__device__ __forceinline__ void esc_store_tile(const bool (&er)[V], const bool (&ei)[V], const int64_t (&dr)[V],
+                                               const int64_t (&di)[V], uint32_t G, const uint32_t *cnt, uint32_t ob,
+                                               __amdgpu_buffer_rsrc_t esc, uint32_t L) {
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, nwv = blockDim.x >> 6, T = blockDim.x;
+#pragma unroll
+  for (int v = 0; v < V; v++) {
+    const uint64_t mr = __ballot(er[v]), mi = __ballot(ei[v]);
+    if ((mr | mi) == 0) continue;
+    uint32_t rr, ri;
+    if (G >= 64) {
+      const uint32_t f = v * nwv + wave, f0 = f & ~((G >> 6) - 1);
+      uint32_t br = 0, bi = 0;
+      for (uint32_t x = f0; x < f; x++) {
+        br += cnt[2 * x];
+        bi += cnt[2 * x + 1];
+      }
+      rr = br + lanes_below(mr);
+      ri = bi + lanes_below(mi);
+    } else {
+      rr = seg_below(mr, G);
+      ri = seg_below(mi, G);
+    }
+    const uint32_t gb = (ob + v * T + tid) & ~(G - 1);
+    if (er[v]) buf_st_i64(esc, 8 * (gb + rr), dr[v]);
+    if (ei[v]) buf_st_i64(esc, 8 * (L + gb + ri), di[v]);
+  }
+}
+
 // Running sums of one thread over the tiles it handles.
 struct Acc {
   uint64_t lo, hi;  // sum p^2
@@ -938,11 +1030,15 @@ __device__ __forceinline__ void tile_symbols(const double (&qr)[V], const double
   uint32_t sr[V], si[V];
   uint32_t nval = 0;
   bool uni = true;
+  bool esr[V], esi[V];
+  int64_t edr[V], edi[V];
 #pragma unroll
   for (int v = 0; v < V; v++) {
     const uint32_t e = v * T + tid;
     const double up_r = __shfl_up(qr[v], 1, 64), up_i = __shfl_up(qi[v], 1, 64);
     sr[v] = si[v] = 0;
+    esr[v] = esi[v] = false;
+    edr[v] = edi[v] = 0;
     if (!FULL && e >= C) continue;
     const uint32_t o = ob + e;
     double pr = 0.0, pi = 0.0;  // predecessor in the chunk (0 at a chunk head)
@@ -962,8 +1058,10 @@ __device__ __forceinline__ void tile_symbols(const double (&qr)[V], const double
     const bool er = !(fabs(dr) < (double)kR), ei = !(fabs(di) < (double)kR);
     sr[v] = er ? 0u : (uint32_t)((int)dr + kR);
     si[v] = ei ? 0u : (uint32_t)((int)di + kR);
-    if (er) so.escr[o] = (int64_t)dr;
-    if (ei) so.esci[o] = (int64_t)di;
+    esr[v] = er;
+    esi[v] = ei;
+    edr[v] = (int64_t)dr;
+    edi[v] = (int64_t)di;
     acc.nesc += (uint32_t)er + (uint32_t)ei;
     so.symr[o] = (uint16_t)sr[v];
     so.symi[o] = (uint16_t)si[v];
@@ -998,7 +1096,11 @@ __device__ __forceinline__ void tile_symbols(const double (&qr)[V], const double
     }
     atomicAdd(&h[cs], cn);
   }
-  lds_sync();  // bnd is reused by the next tile
+  __shared__ uint32_t ecnt[2 * V * 4];
+  const uint32_t G = esc_group(g);
+  esc_count_tile<V>(esr, esi, G, ecnt);
+  lds_sync();  // bnd is reused by the next tile; ecnt is read below and rewritten after the next tile's barrier
+  esc_store_tile<V>(esr, esi, edr, edi, G, ecnt, ob, buf_rsrc(so.escr, (uint32_t)(16 * g.L)), (uint32_t)g.L);
 }
 
 // LDS histogram update of one thread's 2V symbols of a whole tile.  The
@@ -1032,31 +1134,6 @@ template <int V>
 __device__ __forceinline__ void hist_full(const uint32_t (&sr)[V], const uint32_t (&si)[V], uint32_t *h) {
   hist_part<V>(sr, h);
   hist_part<V>(si, h);
-}
-
-// ------------------------------------------------ buffer memory operations
-// The whole-tile kernels address slot memory through buffer resources: a
-// descriptor in scalar registers plus a 32-bit offset per lane, so that no
-// 64-bit address arithmetic runs per lane, and an access past the
-// descriptor's size is dropped by the hardware (reads return zero).
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-constexpr int kBufWord3 = 0x00020000;  // descriptor word 3 for untyped 32-bit access on gfx9-family chips
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufWord3);
-}
-__device__ __forceinline__ double buf_ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-  return __longlong_as_double((long long)(((uint64_t)x.y << 32) | x.x));
-}
-__device__ __forceinline__ void buf_st_u16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t v) {
-  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, off, 0, 0);
-}
-__device__ __forceinline__ void buf_st_i64(__amdgpu_buffer_rsrc_t r, uint32_t off, int64_t v) {
-  u32x2 x;
-  x.x = (uint32_t)(uint64_t)v;
-  x.y = (uint32_t)((uint64_t)v >> 32);
-  __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
 }
 
 // the value of the lane below (0 in lane 0): a DPP shift of the wavefront
@@ -1108,6 +1185,7 @@ __device__ __forceinline__ void tile_symbols_full(const double (&qr)[V], const d
   lds_sync();
   const bool big = (bigw[0] | bigw[1] | bigw[2] | bigw[3]) != 0;
   uint32_t sr[V], si[V];
+  int64_t edr[V], edi[V];  // escaped differences, stored after the barrier below
   if (big) {
     bool any_esc = false;
     double dr[V], di[V];
@@ -1142,9 +1220,8 @@ __device__ __forceinline__ void tile_symbols_full(const double (&qr)[V], const d
     if (__ballot(any_esc)) {
 #pragma unroll
       for (int v = 0; v < V; v++) {
-        const uint32_t o = ob + v * T + tid;
-        if (sr[v] == 0) buf_st_i64(sb.esc, 8 * o, (int64_t)dr[v]);
-        if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + o), (int64_t)di[v]);
+        edr[v] = (int64_t)dr[v];
+        edi[v] = (int64_t)di[v];
       }
     }
     add_squares<V>(qr, qi, acc.lo, acc.hi);
@@ -1185,9 +1262,8 @@ __device__ __forceinline__ void tile_symbols_full(const double (&qr)[V], const d
     if (__ballot(any_esc)) {
 #pragma unroll
       for (int v = 0; v < V; v++) {
-        const uint32_t o = ob + v * T + tid;
-        if (sr[v] == 0) buf_st_i64(sb.esc, 8 * o, (int64_t)dr[v]);
-        if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + o), (int64_t)di[v]);
+        edr[v] = (int64_t)dr[v];
+        edi[v] = (int64_t)di[v];
       }
     }
     const uint64_t x = acc.lo + (uint64_t)t;
@@ -1195,7 +1271,17 @@ __device__ __forceinline__ void tile_symbols_full(const double (&qr)[V], const d
     acc.lo = x;
   }
   hist_full<V>(sr, si, h);
-  lds_sync();  // bnd and bigw are reused by the next tile
+  __shared__ uint32_t ecnt[2 * V * 4];
+  const uint32_t G = esc_group(g);
+  bool esr[V], esi[V];
+#pragma unroll
+  for (int v = 0; v < V; v++) {
+    esr[v] = sr[v] == 0;
+    esi[v] = si[v] == 0;
+  }
+  esc_count_tile<V>(esr, esi, G, ecnt);
+  lds_sync();  // bnd and bigw are reused by the next tile; ecnt is read below and rewritten after the next tile's barrier
+  esc_store_tile<V>(esr, esi, edr, edi, G, ecnt, ob, sb.esc, sb.L);
 }
 
 // Reduce the workgroup's sums and write them, with the LDS histogram h (then
@@ -1710,6 +1796,35 @@ __device__ __forceinline__ double lane63(double x) {  // the value of lane 63, i
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// Escapes of a wavefront range (position ob + v * 64 + lane, ob a multiple
+// of 256): each one's rank in its group counts the group's escapes in earlier
+// rows and lower lanes.
+template <typename D>
+__device__ __forceinline__ void wr_store_escs(const SlotBuf &sb, uint32_t ob, uint32_t G, const uint32_t (&sr)[4],
+                                              const uint32_t (&si)[4], const D (&dr)[4], const D (&di)[4]) {
+  const uint32_t lane = lane_id();
+  const uint32_t rows = G >= 64 ? G >> 6 : 1u;  // rows per group
+  uint32_t br = 0, bi = 0;                       // the group's escapes in earlier rows
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    const uint64_t mr = __ballot(sr[v] == 0), mi = __ballot(si[v] == 0);
+    if (((uint32_t)v & (rows - 1)) == 0) br = bi = 0;
+    uint32_t rr, ri;
+    if (G >= 64) {
+      rr = br + lanes_below(mr);
+      ri = bi + lanes_below(mi);
+    } else {
+      rr = seg_below(mr, G);
+      ri = seg_below(mi, G);
+    }
+    br += (uint32_t)__popcll(mr);
+    bi += (uint32_t)__popcll(mi);
+    const uint32_t gb = (ob + v * 64 + lane) & ~(G - 1);
+    if (sr[v] == 0) buf_st_i64(sb.esc, 8 * (gb + rr), (int64_t)dr[v]);
+    if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + gb + ri), (int64_t)di[v]);
+  }
+}
+
 // Symbols, escapes, squares and histogram of one range at offset ob (a
 // chunk head).  Integer path when every |q| of the wavefront is below 2^24
 // (the choice only changes the arithmetic, not the result).
@@ -1747,14 +1862,7 @@ __device__ __forceinline__ void wr_symbols(const double (&qr)[4], const double (
       buf_st_u16(sb.sym, 2 * o, sr[v]);
       buf_st_u16(sb.sym, 2 * (sb.L + o), si[v]);
     }
-    if (__ballot(any_esc)) {
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const uint32_t o = ob + v * 64 + lane;
-        if (sr[v] == 0) buf_st_i64(sb.esc, 8 * o, (int64_t)dr[v]);
-        if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + o), (int64_t)di[v]);
-      }
-    }
+    if (__ballot(any_esc)) wr_store_escs(sb, ob, esc_group(g), sr, si, dr, di);
     add_squares<4>(qr, qi, acc.lo, acc.hi);
     note_wide<4>(qr, qi, acc);
   } else {
@@ -1790,14 +1898,7 @@ __device__ __forceinline__ void wr_symbols(const double (&qr)[4], const double (
       t += (int64_t)ir[v] * ir[v];
       t += (int64_t)ii[v] * ii[v];
     }
-    if (__ballot(any_esc)) {
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const uint32_t o = ob + v * 64 + lane;
-        if (sr[v] == 0) buf_st_i64(sb.esc, 8 * o, (int64_t)dr[v]);
-        if (si[v] == 0) buf_st_i64(sb.esc, 8 * (sb.L + o), (int64_t)di[v]);
-      }
-    }
+    if (__ballot(any_esc)) wr_store_escs(sb, ob, esc_group(g), sr, si, dr, di);
     const uint64_t x = acc.lo + (uint64_t)t;
     acc.hi += x < acc.lo;
     acc.lo = x;
@@ -2797,11 +2898,18 @@ __global__ void __launch_bounds__(64 * (kEncWaves + 1), STEPS > 2 ? 2 : 4) k_enc
 #pragma unroll
     for (int i = 0; i < STEPS; i++) {
       const uint32_t sv[4] = {d[i].x & 0xffffu, d[i].x >> 16, d[i].y & 0xffffu, d[i].y >> 16};
+      bool is_esc[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) is_esc[k] = (uint64_t)i * 256 + 4 * (uint64_t)lane + k < B && sv[k] == 0;
+      // the group is step i's 256 positions (or the chunk, below 256): escapes
+      // of lower lanes come first, then this lane's in order
+      uint32_t r = lanes_below(__ballot(is_esc[0])) + lanes_below(__ballot(is_esc[1])) +
+                   lanes_below(__ballot(is_esc[2])) + lanes_below(__ballot(is_esc[3]));
+      const uint64_t gb = (uint64_t)c * Bc + (uint64_t)i * 256;
 #pragma unroll
       for (int k = 0; k < 4; k++) {
-        const uint64_t j = (uint64_t)i * 256 + 4 * (uint64_t)lane + k;
-        const bool is_esc = j < B && sv[k] == 0;
-        const uint32_t off = is_esc ? (uint32_t)(8 * ((uint64_t)c * Bc + j)) : 0xFFFFFFF0u;
+        const uint32_t off = is_esc[k] ? (uint32_t)(8 * (gb + r)) : 0xFFFFFFF0u;
+        r += is_esc[k] ? 1u : 0u;
         const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(escb, off, 0, 0);
         e[i][k] = (int64_t)(((uint64_t)x.y << 32) | x.x);
       }
