@@ -43,28 +43,28 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
     "grover34": {
-        "decode": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 9196986788},
-        "gate_quant": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 14189994131},
-        "codebook": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 5872105},
-        "encode": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 6980871163},
-        "finish": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 1075017400},
+        "decode": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 9196770148},
+        "gate_quant": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 13767374702},
+        "codebook": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 5868173},
+        "encode": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 5773241207},
+        "finish": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 1075048103},
     },
     "grover24": {
-        "decode": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 149685211},
-        "gate_quant": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 221593340},
-        "codebook": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 5879825},
-        "encode": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 82771417},
-        "finish": {"kernels_sha256": "b28fcf690fe125368a73873251f4b7cda68a6ea408726ccf31c37072ba860564",
-                 "bytes_per_launch": 16587877},
+        "decode": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 149677459},
+        "gate_quant": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 220371716},
+        "codebook": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 5869925},
+        "encode": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 79001659},
+        "finish": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
+                 "bytes_per_launch": 16583478},
     },
 }
 
