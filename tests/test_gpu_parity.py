@@ -92,6 +92,32 @@ def gate_zoo(n, seed):
 
 # ------------------------------------------------------------------ cases
 
+@pytest.mark.parametrize("cl", [1, 2, 4, 5, 6, 7, 8, 9, 10])
+def test_sparse_periodic_escapes_every_group_size(cl):
+    """The escape buffer keeps each group of min(chunk, 256) positions'
+    escapes at the group's start (ranks from ballots, across the wavefronts
+    of a tile through LDS).  A Grover state after its oracle, then H on the
+    low qubits, has escapes every 2^t positions in its real plane (differences
+    of about 780 and more steps against R = 512), and the dense two-qubit gates
+    take the tile kernels: records byte-equal to the oracle after every pass."""
+    n, sl, eb = 13, 11, 1e-5
+    say("sparse escapes", n, sl, cl, eb)
+    rng = np.random.default_rng(cl)
+
+    def ru2(s):
+        r = np.random.default_rng(s)
+        a = r.standard_normal((4, 4)) + 1j * r.standard_normal((4, 4))
+        q, rr = np.linalg.qr(a)
+        return q * (np.diag(rr) / abs(np.diag(rr)))
+
+    marked = int(rng.integers(0, 1 << n))
+    gates = [qc.H(t) for t in range(n)] + [qc.MCPHASE((1 << n) - 1, marked, -1.0)]
+    gates += [qc.H(t) for t in range(8)] + [qc.U([0, 1], ru2(cl)), qc.U([3, 6], ru2(cl + 50)), qc.H(9)]
+    sim, orc = run_both(n, sl, cl, eb, gates)
+    assert np.array_equal(sim.amplitudes(), orc.amplitudes())
+    assert sim.stats()["max_abs_codec_err"] <= eb
+
+
 def test_qft12_basis_every_pass_identical():
     w = qc.qft_basis_workload()
     say("qft12 basis", w.n_qubits, w.slice_log2, w.error_bound)
