@@ -283,7 +283,7 @@ def run_grover24(args):
     gates = cq.Circuit(w.gates)
     sim.apply(gates[:n])
     pos = n
-    assert len(gates) >= pos + Wm + 2 * K + args.latency_passes
+    assert len(gates) >= pos + Wm + 3 * K + args.latency_passes
     sim.apply(gates[pos:pos + Wm])
     pos += Wm
     torch.cuda.synchronize()
@@ -304,6 +304,18 @@ def run_grover24(args):
     pos += K
     st2 = sim.stats()
 
+    # the next K passes as one captured HIP graph (sim_graph_*), captured
+    # outside the timed region: the same kernels without the gaps between
+    # launches
+    graph = sim.graph(gates[pos:pos + K])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    assert graph.launch() == K
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    graph.close()
+    pos += K
+
     # per-pass latency: one sim_apply call per pass, host clock
     lat = []
     for i in range(args.latency_passes):
@@ -323,6 +335,9 @@ def run_grover24(args):
               "zero_chunks": args.zero_chunks, "const_chunks": args.const_chunks, "chunk_runs": args.chunk_runs}
     line = report(args, w, sim, value, K, Wm, dt, kt, st1, st2, lat, config,
                   plane_bytes=8 if compact_workspace(w, False, args.chunk_log2) else 16)
+    line["graph"] = {"value": K * N / t_graph, "unit": "amps/s", "ms_per_step": t_graph / K * 1e3,
+                     "speedup_vs_launches": dt / t_graph,
+                     "passes": "the %d passes after the timed window and its repeat, as one captured graph" % K}
     if args.tune:  # the H layer and 300 Grover gates on fresh handles, chunks of 2^5 .. 2^10
         best, table = cq.tune_chunk(n, w.slice_log2, w.error_bound, gates[:n + 300], lo=5, hi=10,
                                     fp32=args.fp32, zero_chunks=args.zero_chunks,
