@@ -439,18 +439,20 @@ __device__ __forceinline__ double pw_value(double q, int b) {
   return q < 0.0 ? -x : x;
 }
 
-// A decoded value: the code itself (compact workspace), else p k, or the
-// pointwise-relative value of p times k.
-template <bool C32>
+// A decoded value: the code itself (compact workspace), else p k, or (PW:
+// records of pointwise-relative codes) the pointwise-relative value of p
+// times k.  PW is a template parameter of the decode kernels, so that the
+// other FP64 loops carry no trace of it.
+template <bool C32, bool PW>
 __device__ __forceinline__ typename DecFmt<C32>::T dec_val(typename DecFmt<C32>::P p, double k, int pwb) {
-  if constexpr (C32) {
+  if constexpr (C32 || !PW) {
     return DecFmt<C32>::val(p, k);
   } else {
-    return pwb >= 0 ? rw(pw_value(p, pwb) * k) : DecFmt<C32>::val(p, k);
+    return rw(pw_value(p, pwb) * k);
   }
 }
 
-template <bool FULL, bool C32, int FMT, bool SMALL>
+template <bool FULL, bool C32, int FMT, bool SMALL, bool PW>
 __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, const StateMeta &cur, uint64_t slice,
                                               uint32_t u, const uint32_t *offs, uint32_t nchunks, uint32_t n_words,
                                               uint32_t n_used, uint32_t nruns, double k, uint32_t *dtab,
@@ -557,7 +559,7 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
             z = br.take(nb);
           }
           p = F::add_esc(p, unzigzag(z));
-          st[lane * PITCH + q] = dec_val<C32>(p, k, g.pw_bits);
+          st[lane * PITCH + q] = dec_val<C32, PW>(p, k, g.pw_bits);
           q++;
           continue;
         }
@@ -569,9 +571,9 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
         br.buf <<= len;
         br.nbits -= (int)len;
         p = F::add(p, (int)sym - kR);
-        st[lane * PITCH + q] = dec_val<C32>(p, k, g.pw_bits);
+        st[lane * PITCH + q] = dec_val<C32, PW>(p, k, g.pw_bits);
         const typename F::P p2 = F::add(p, (int)((e >> 14) & 1023u) - kR);
-        st[lane * PITCH + q + 1] = dec_val<C32>(p2, k, g.pw_bits);
+        st[lane * PITCH + q + 1] = dec_val<C32, PW>(p2, k, g.pw_bits);
         p = two ? p2 : p;
         q += two ? 2u : 1u;
       }
@@ -602,8 +604,9 @@ __device__ __forceinline__ void decode_chunks(const Slots &sl, const Geo &g, con
   }
 }
 
-// SMALL: the narrow configuration (launched for passes that may decode int32 codes)
-template <bool FULL, int FMT, bool SMALL>
+// SMALL: the narrow configuration (launched for passes that may decode int32
+// codes); PW: records of pointwise-relative codes
+template <bool FULL, int FMT, bool SMALL, bool PW>
 __global__ void __launch_bounds__(64 * kDecWaves, SMALL ? 3 : 1) k_decode(Slots sl, Geo g, const uint64_t *slot_slice,
                                                                        const uint8_t *arena, StateMeta cur,
                                                                        const double *kscale, Ctl *ctl, uint32_t pass,
@@ -647,10 +650,10 @@ __global__ void __launch_bounds__(64 * kDecWaves, SMALL ? 3 : 1) k_decode(Slots 
     return;
   }
   if (c32)
-    decode_chunks<FULL, true, FMT, SMALL>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns, 0.0, dtab,
+    decode_chunks<FULL, true, FMT, SMALL, false>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns, 0.0, dtab,
                                           stg, pf, ctl, pass);
   else
-    decode_chunks<FULL, false, FMT, SMALL>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns,
+    decode_chunks<FULL, false, FMT, SMALL, PW>(sl, g, cur, slice, u, offs, nchunks, n_words, n_used, nruns,
                                            kscale[slice], dtab, stg, pf, ctl, pass);
 }
 
@@ -3588,9 +3591,16 @@ void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
   dim3 grid(grid1(g.nchunks, per_wg), (unsigned)nslots);
   const bool full = (1ull << g.chunk_log2) >= (uint64_t)DecFmt<true>::R && g.nchunks % per_wg == 0;
   const int c = compact ? 1 : 0;
-#define CQ_DEC1(FULL_, FMT_, SMALL_)                                                                        \
-  CQ_LAUNCH((k_decode<FULL_, FMT_, SMALL_>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, \
+#define CQ_DEC2(FULL_, FMT_, SMALL_, PW_)                                                                       \
+  CQ_LAUNCH((k_decode<FULL_, FMT_, SMALL_, PW_>), grid, dim3(per_wg), 0, st, sl, g, slot_slice, arena, cur, kscale, \
             ctl, pass, c)
+#define CQ_DEC1(FULL_, FMT_, SMALL_)         \
+  do {                                       \
+    if (g.pw_bits >= 0)                      \
+      CQ_DEC2(FULL_, FMT_, SMALL_, true);    \
+    else                                     \
+      CQ_DEC2(FULL_, FMT_, SMALL_, false);   \
+  } while (0)
 #define CQ_DEC(FULL_, FMT_)                 \
   do {                                      \
     if (compact)                            \
@@ -3606,6 +3616,7 @@ void launch_decode(hipStream_t st, const Slots &sl, const Geo &g, const uint64_t
   }
 #undef CQ_DEC
 #undef CQ_DEC1
+#undef CQ_DEC2
 }
 
 static int gate_kind(const GateDesc &gd) {
