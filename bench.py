@@ -43,28 +43,28 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
     "grover34": {
-        "decode": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 9196770148},
-        "gate_quant": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 13767374702},
-        "codebook": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 5868173},
-        "encode": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 5773241207},
-        "finish": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 1075048103},
+        "decode": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 9196490623},
+        "gate_quant": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 13767151265},
+        "codebook": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 5832275},
+        "encode": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 5773218484},
+        "finish": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 1075015932},
     },
     "grover24": {
-        "decode": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 149677459},
-        "gate_quant": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 220371716},
-        "codebook": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 5869925},
-        "encode": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 79001659},
-        "finish": {"kernels_sha256": "721bdebb7a6b9c74510c1f00f1355c0715cd20bb1f805bb655560a723097858f",
-                 "bytes_per_launch": 16583478},
+        "decode": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 149670035},
+        "gate_quant": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 220364500},
+        "codebook": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 5840384},
+        "encode": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 79001373},
+        "finish": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
+                 "bytes_per_launch": 16594976},
     },
 }
 
