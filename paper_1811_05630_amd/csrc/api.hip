@@ -755,15 +755,20 @@ int enqueue_pass(sim_t *s, const GateDesc &gd, uint64_t gm, int init_kind, uint6
       AMP(s, launch_decode)(st, slots, s->geo, ss, ns, s->arena[c], cur, s->kscale, s->ctl, pass, compact);
       s->kt_end();
     }
-    if (gd.kind == 4) {  // fused block on matrix cores, in place; then quantised as the identity
+    // fused block on matrix cores, in place; then quantised as the identity.
+    // With the relative bound the block kernel can take the min/max itself.
+    const bool mm_fused = gd.kind == 4 && qp.rel && AMP(s, dense_minmax_ok)(s->geo, gd);
+    if (gd.kind == 4) {
       s->kt_begin(K_DENSE);
-      AMP(s, launch_dense_mfma)(st, slots, s->geo, ns, gd, s->ctl);
+      AMP(s, launch_dense_mfma)(st, slots, s->geo, ns, gd, s->ctl, mm_fused);
       s->kt_end();
     }
-    if (qp.rel) {
+    if (qp.rel && !mm_fused) {
       s->kt_begin(K_MINMAX);
       AMP(s, launch_gate_minmax)(st, slots, s->geo, ss, ns, gd.kind == 4 ? s->ident : gd, s->ctl);
       s->kt_end();
+    }
+    if (qp.rel) {
       s->kt_begin(K_RELSTEP);
       launch_rel_step(st, slots, ns, qp.eb, s->ctl);
       s->kt_end();

@@ -197,9 +197,11 @@ LaunchTimer &launch_timer();
                              bool compact, const double *kscale);                                              \
   /* whether the gate_quant kernel chosen for gd can read a compact workspace */                               \
   bool gq_compact(const Geo &g, const GateDesc &gd);                                                           \
-  /* fused block (kind 4) applied in place to the decompressed slots */                                        \
+  /* fused block (kind 4) applied in place to the decompressed slots; minmax: also each slot's min/max   */ \
+  /* of the outputs (relative bound; only where dense_minmax_ok)                                         */ \
   void launch_dense_mfma(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const GateDesc &gd,        \
-                         const Ctl *ctl);                                                                      \
+                         const Ctl *ctl, bool minmax);                                                         \
+  bool dense_minmax_ok(const Geo &g, const GateDesc &gd);                                                      \
   void launch_readout(hipStream_t st, const Slots &sl, const Geo &g, uint64_t first_amp, uint64_t count,       \
                       int probabilities, double *out);
 

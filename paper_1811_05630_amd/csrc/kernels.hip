@@ -3474,9 +3474,15 @@ __global__ void __launch_bounds__(256) k_finish(Slots sl, Geo g, const uint64_t 
 // where f_b is the base counter with a zero inserted at every target bit.
 // A wavefront reads all inputs of its 16 bases before it writes their
 // outputs, and no two wavefronts share a base, so updating in place is safe.
+// MM (relative bound, every target inside the slice, whole groups of 16
+// bases per slot): the block also takes each slot's min/max of its outputs,
+// as the min/max kernel would from the workspace afterwards.  Then every
+// wavefront walks one contiguous range of bases, whose 16-base groups each
+// lie in one slot, keeps the keys of the slot it is in, and folds them into
+// the slot's with one atomic pair per slot it leaves.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-template <int K>
+template <int K, bool MM>
 __global__ void __launch_bounds__(256) k_dense_mfma(Slots sl, Geo g, GateDesc gd, uint64_t nbases, const Ctl *ctl) {
   if (ctl->flags) return;
   constexpr int NM = 1 << K, D = 2 * NM, RB = D / 16, KS = D / 4;
@@ -3489,7 +3495,25 @@ __global__ void __launch_bounds__(256) k_dense_mfma(Slots sl, Geo g, GateDesc gd
   const uint64_t L = g.L;
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwv = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t jb = wave * 16; jb < nbases; jb += nwv * 16) {
+  // MM: bases [wave * per, (wave + 1) * per) in steps of 16; otherwise every nwv-th group of 16
+  const uint64_t per = MM ? ((nbases + nwv - 1) / nwv + 15) & ~15ull : 16;
+  const uint64_t j0 = MM ? wave * per : wave * 16, jend = MM ? (j0 + per < nbases ? j0 + per : nbases) : nbases;
+  const uint64_t jstep = MM ? 16 : nwv * 16;
+  uint64_t kmin = ~0ull, kmax = 0ull, mslot = ~0ull;  // MM: this lane's keys for slot mslot
+  auto flush = [&]() {  // wavefront-uniform: the keys of every lane into slot mslot's
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t x = __shfl_xor(kmin, off, 64), y = __shfl_xor(kmax, off, 64);
+      kmin = x < kmin ? x : kmin;
+      kmax = y > kmax ? y : kmax;
+    }
+    if (lane == 0 && kmin <= kmax) {
+      atomicMin((unsigned long long *)&sl.minmax[2 * mslot], (unsigned long long)kmin);
+      atomicMax((unsigned long long *)&sl.minmax[2 * mslot + 1], (unsigned long long)kmax);
+    }
+    kmin = ~0ull;
+    kmax = 0ull;
+  };
+  for (uint64_t jb = j0; jb < jend; jb += jstep) {
     const uint64_t j = jb + col;
     const bool valid = j < nbases;
     uint64_t f = valid ? j : jb;  // lanes past the last base read base jb and store nothing
@@ -3512,6 +3536,13 @@ __global__ void __launch_bounds__(256) k_dense_mfma(Slots sl, Geo g, GateDesc gd
     for (int s = 0; s < KS; s++)
 #pragma unroll
       for (int R = 0; R < RB; R++) acc[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[R][s], x[s], acc[R], 0, 0, 0);
+    if (MM) {  // the group's slot (uniform: 16 bases of one slot)
+      const uint64_t slot = (uint64_t)__builtin_amdgcn_readfirstlane((int)(f >> g.slice_log2));
+      if (slot != mslot) {
+        if (mslot != ~0ull) flush();
+        mslot = slot;
+      }
+    }
     if (valid) {
 #pragma unroll
       for (int R = 0; R < RB; R++)
@@ -3519,25 +3550,46 @@ __global__ void __launch_bounds__(256) k_dense_mfma(Slots sl, Geo g, GateDesc gd
         for (int i = 0; i < 4; i++) {
           const uint32_t r = 16 * R + 4 * i + quad;
           const uint64_t fm = f | gd.dep[r & (NM - 1)];
-          sl.ws[(fm >> g.slice_log2) * 2 * L + (r >= (uint32_t)NM ? L : 0) + (fm & (L - 1))] = rw(acc[R][i]);
+          const double y = rw(acc[R][i]);
+          sl.ws[(fm >> g.slice_log2) * 2 * L + (r >= (uint32_t)NM ? L : 0) + (fm & (L - 1))] = y;
+          if (MM) {
+            const uint64_t key = dkey(y);
+            kmin = key < kmin ? key : kmin;
+            kmax = key > kmax ? key : kmax;
+          }
         }
     }
   }
+  if (MM && mslot != ~0ull) flush();
+}
+
+bool dense_minmax_ok(const Geo &g, const GateDesc &gd) {
+  for (int t = 0; t < gd.k; t++)
+    if (gd.tloc[t] >= g.slice_log2) return false;
+  return ((g.L >> gd.k) & 15) == 0;  // whole groups of 16 bases per slot
 }
 
 void launch_dense_mfma(hipStream_t st, const Slots &sl, const Geo &g, int nslots, const GateDesc &gd,
-                       const Ctl *ctl) {
+                       const Ctl *ctl, bool minmax) {
   const uint64_t nbases = ((uint64_t)nslots * g.L) >> gd.k;
   const uint64_t waves = (nbases + 15) / 16;
   uint64_t blocks = (waves + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   const dim3 grid((unsigned)blocks), block(256);
+#define CQ_DM(K_)                                                                     \
+  do {                                                                                \
+    if (minmax)                                                                       \
+      CQ_LAUNCH((k_dense_mfma<K_, true>), grid, block, 0, st, sl, g, gd, nbases, ctl); \
+    else                                                                              \
+      CQ_LAUNCH((k_dense_mfma<K_, false>), grid, block, 0, st, sl, g, gd, nbases, ctl); \
+  } while (0)
   switch (gd.k) {
-    case 3: CQ_LAUNCH(k_dense_mfma<3>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
-    case 4: CQ_LAUNCH(k_dense_mfma<4>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
-    default: CQ_LAUNCH(k_dense_mfma<5>, grid, block, 0, st, sl, g, gd, nbases, ctl); break;
+    case 3: CQ_DM(3); break;
+    case 4: CQ_DM(4); break;
+    default: CQ_DM(5); break;
   }
+#undef CQ_DM
 }
 
 // ----------------------------------------------------------------- readout
