@@ -43,28 +43,28 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1811_05630_amd", "csrc", "kernels.hip")
 # source they were taken on (sha256 of kernels.hip).
 MEASURED_TRAFFIC = {
     "grover34": {
-        "decode": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 9196490623},
-        "gate_quant": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 13767151265},
-        "codebook": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 5832275},
-        "encode": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 5773218484},
-        "finish": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 1075015932},
+        "decode": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 9196552035},
+        "gate_quant": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 13767265397},
+        "codebook": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 5864041},
+        "encode": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 5773226182},
+        "finish": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 1075019555},
     },
     "grover24": {
-        "decode": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 149670035},
-        "gate_quant": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 220364500},
-        "codebook": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 5840384},
-        "encode": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 79001373},
-        "finish": {"kernels_sha256": "9075985c1eb79a942414d84b5b9854f848cf0cc844b687be0cc6a9b900b439a1",
-                 "bytes_per_launch": 16594976},
+        "decode": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 149670621},
+        "gate_quant": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 220343282},
+        "codebook": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 5870640},
+        "encode": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 78993272},
+        "finish": {"kernels_sha256": "19bc40c8b65ed4589a884b0d0d9c1317bc7ee10729a95950a57a7f394cc5bf2a",
+                 "bytes_per_launch": 16579607},
     },
 }
 
