@@ -106,6 +106,39 @@ def test_qft_of_product_state_relative_bound():
     assert np.array_equal(decoded_state(sim), a)
 
 
+def test_relative_bound_blocks_take_their_slot_min_max():
+    """Slices of 2^10: 5-qubit blocks inside the slice take each slot's min/max
+    of their outputs in the block kernel (the relative bound's step), blocks
+    with slice-index targets leave it to the min/max kernel.  Every pass's
+    records carry the same power-of-two step as the oracle's, and the state
+    stays within the bound of the oracle's and of the exact one."""
+    n, sl, cl, rel = 13, 10, 6, 1e-4
+    say("fused relative min/max", n, sl, cl, rel)
+    theta, phi = qc.product_angles(n, 5)
+    f = qc.product_factors(theta, phi)
+    gates = qc.qft(n)
+    plan = oracle.plan(gates)
+    inside = [p for p in plan if p[2] and max(p[3]) < sl and len(p[3]) == 5]
+    assert inside, "the plan has 5-qubit blocks inside the slice"
+    orc = oracle.OracleSim(n, sl, cl, rel, oracle.REL)
+    sim = cq.Sim(n, sl, rel, relative=True, chunk_log2=cl, fused=True)
+    orc.init_product(f)
+    sim.init_product(f)
+    for i, p in enumerate(plan):
+        g = gates[p[0]:p[0] + p[1]]
+        orc.apply(g, fused=True)
+        assert sim.apply(g) == len(g)
+        for j in range(orc.nslices):
+            hs, ho = oracle.parse_header(sim.record(j)), oracle.parse_header(orc.record(j))
+            assert hs["step"] == ho["step"], f"pass {i}, slice {j}: step {hs['step']} against {ho['step']}"
+    a, b = sim.amplitudes(), orc.amplitudes()
+    exact = math.sqrt(1 << n) * np.fft.ifft(oracle.product_state(f))
+    amax = np.max(np.abs(exact))
+    assert np.max(np.abs(a - b)) <= 4 * 2 * rel * amax
+    assert np.linalg.norm(a - exact) < len(plan) * math.sqrt(2 << n) * 2 * rel * amax
+    assert np.array_equal(decoded_state(sim), a)
+
+
 def test_grover_with_cross_slice_blocks():
     n, sl, cl, eb = 11, 5, 4, 1e-7
     say("fused grover", n, sl, cl, eb)
